@@ -1,0 +1,185 @@
+"""The unrolled COSMO iteration and its reverse mode, in float64
+(test infrastructure; see package doc).
+
+An instance is any object with attributes P (n x n sparse, symmetric), q [n],
+A (m x n sparse), b [m] and cones (see cones.py).
+
+Forward step k (Sec. "Conic Operator Splitting Method", reduced form
+eq:cosmo_linear_system_reduced; penalties rectified per App. D):
+    rho_hat = rectify(rho^k)
+    M       = P + sigma I + A' D(rho_hat) A
+    xi      = sigma x - q + A'(y + rho_hat o (b - s))
+    x~      = M^{-1} xi
+    s~      = b - A x~            (equal to s - (y + nu~)/rho of the full system)
+    x+      = alpha x~ + (1 - alpha) x
+    s^      = alpha s~ + (1 - alpha) s
+    s+      = Pi_K(s^ + y / rho_hat)
+    y+      = y + rho_hat o (s^ - s+)
+"""
+from dataclasses import dataclass
+from typing import List, Optional
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .cones import proj_cone, proj_cone_vjp, rectify, rectify_adjoint
+
+
+@dataclass
+class Hyper:
+    sigma: float = 1e-6          # fixed, Sec. "Conic Operator Splitting Method"
+
+
+def reduced_matrix(inst, rho_hat: np.ndarray, sigma: float) -> sp.csc_matrix:
+    """M(rho) = P + sigma I + A' D(rho) A  (eq:cosmo_linear_system_reduced)."""
+    n = inst.A.shape[1]
+    M = inst.P + sigma * sp.identity(n) + inst.A.T @ sp.diags(rho_hat) @ inst.A
+    return sp.csc_matrix(M)
+
+
+def solve_reduced(inst, rho_hat: np.ndarray, sigma: float):
+    """Exact factorisation of M; returns an object with .solve(rhs)."""
+    return spla.splu(reduced_matrix(inst, rho_hat, sigma))
+
+
+def step_forward(inst, x, s, y, rho, alpha, sigma=1e-6, lu=None) -> dict:
+    """One COSMO step z^k -> z^{k+1}; returns every intermediate."""
+    A, b, q = inst.A, inst.b, inst.q
+    rho_hat = rectify(rho, inst.cones)
+    if lu is None:
+        lu = solve_reduced(inst, rho_hat, sigma)
+    xi = sigma * x - q + A.T @ (y + rho_hat * (b - s))
+    xt = lu.solve(xi)
+    st = b - A @ xt
+    xn = alpha * xt + (1.0 - alpha) * x
+    sh = alpha * st + (1.0 - alpha) * s
+    v = sh + y / rho_hat
+    sn, aux = proj_cone(v, inst.cones)
+    yn = y + rho_hat * (sh - sn)
+    return dict(x=x, s=s, y=y, rho=rho, rho_hat=rho_hat, alpha=alpha, xi=xi, xt=xt,
+                st=st, sh=sh, v=v, aux=aux, lu=lu, xn=xn, sn=sn, yn=yn)
+
+
+def unroll_forward(inst, rho: np.ndarray, alpha: np.ndarray, x0=None, s0=None, y0=None,
+                   sigma: float = 1e-6):
+    """K steps with per-iteration (rho^k, alpha^k); z^0 = 0 unless given
+    (App. D: zero default initialisation).  Returns (tape, (xK, sK, yK))."""
+    n, m = inst.A.shape[1], inst.A.shape[0]
+    x = np.zeros(n) if x0 is None else np.asarray(x0, np.float64).copy()
+    s = np.zeros(m) if s0 is None else np.asarray(s0, np.float64).copy()
+    y = np.zeros(m) if y0 is None else np.asarray(y0, np.float64).copy()
+    tape = []
+    for k in range(rho.shape[0]):
+        st = step_forward(inst, x, s, y, rho[k], float(alpha[k]), sigma)
+        tape.append(st)
+        x, s, y = st["xn"], st["sn"], st["yn"]
+    return tape, (x, s, y)
+
+
+def step_backward(inst, st: dict, gxn, gsn, gyn, sigma=1e-6):
+    """Reverse of one step: cotangents of (x+, s+, y+) -> cotangents of
+    (x, s, y) and of (rho^k, alpha^k).
+
+    Linear solve: with the adjoint lam~ solving M lam~ = -grad_{x~}
+    (eq:grad_rho), the matrix part of the penalty gradient is
+    (A lam~) o (A x~) (stacked form after eq:grad_rho).  The right-hand side
+    xi also depends on (x, s, y, rho); that part (left to autograd in the
+    paper) is written out by hand with xibar = M^{-1} xbar~ = -lam~.
+    """
+    A, b, cones = inst.A, inst.b, inst.cones
+    rho_hat, alpha = st["rho_hat"], st["alpha"]
+    x, s, y, xt, stl, sh, v, sn = (st[k] for k in ("x", "s", "y", "xt", "st", "sh", "v", "sn"))
+    # y+ = y + rho_hat (s^ - s+)
+    gy = gyn.copy()
+    gsh = rho_hat * gyn
+    grh = gyn * (sh - sn)
+    gsn_tot = gsn - rho_hat * gyn
+    # s+ = Pi_K(v)
+    gv = proj_cone_vjp(v, st["aux"], cones, gsn_tot)
+    # v = s^ + y / rho_hat
+    gsh = gsh + gv
+    gy = gy + gv / rho_hat
+    grh = grh - gv * y / rho_hat ** 2
+    # s^ = alpha s~ + (1 - alpha) s ;  x+ = alpha x~ + (1 - alpha) x
+    gst = alpha * gsh
+    gs = (1.0 - alpha) * gsh
+    galpha = float(gsh @ (stl - s) + gxn @ (xt - x))
+    gx = (1.0 - alpha) * gxn
+    # s~ = b - A x~
+    gxt = alpha * gxn - A.T @ gst
+    # x~ = M(rho)^{-1} xi
+    xibar, g_mat = implicit_solve_vjp(st["lu"], A, xt, gxt)
+    grh = grh + g_mat
+    Axb = A @ xibar                               # xi = sigma x - q + A'(y + rho_hat (b - s))
+    gx = gx + sigma * xibar
+    gy = gy + Axb
+    grh = grh + Axb * (b - s)
+    gs = gs - rho_hat * Axb
+    grho = rectify_adjoint(grh, cones)
+    return gx, gs, gy, grho, galpha
+
+
+def implicit_solve_vjp(lu, A, xt, gxt):
+    """Matrix-free implicit differentiation of x~ = M(rho)^{-1} xi
+    (Sec. "Matrix-Free Implicit Differentiation").
+
+    The adjoint lam~ solves M lam~ = -grad_{x~} L with the same operator
+    (eq:grad_rho); since dM/drho_i = a_i a_i', the penalty gradient through
+    M is (A lam~) o (A x~).  The cotangent of the right-hand side is
+    xibar = M^{-1} grad_{x~} L = -lam~.  Returns (xibar, grad_rho_matrix)."""
+    lam = lu.solve(-gxt)                          # M symmetric
+    return -lam, (A @ lam) * (A @ xt)
+
+
+def unroll_backward(inst, tape: List[dict], gxK, gsK, gyK, sigma=1e-6):
+    """Backpropagation through the K unrolled steps (eq:du-objective)."""
+    K = len(tape)
+    m = inst.A.shape[0]
+    grho = np.zeros((K, m))
+    galpha = np.zeros(K)
+    gx, gs, gy = (np.asarray(g, np.float64).copy() for g in (gxK, gsK, gyK))
+    for k in range(K - 1, -1, -1):
+        gx, gs, gy, grho[k], galpha[k] = step_backward(inst, tape[k], gx, gs, gy, sigma)
+    return grho, galpha, gx, gs, gy
+
+
+def kkt_residuals(inst, x, s, y):
+    """Primal r_p = Ax + s - b and dual r_d = Px + q - A'y.
+
+    The paper prints the dual residual with +A'y (loss, App. D); with the
+    iteration as written the fixed point satisfies Px + q - A'y = 0
+    (y lies in the polar cone), so the minus sign is the reading used."""
+    rp = inst.A @ x + s - inst.b
+    rd = inst.P @ x + inst.q - inst.A.T @ y
+    return rp, rd
+
+
+def residual_loss(inst, x, s, y) -> float:
+    """Final-residual loss ||r_p||^2 + ||r_d||^2 of one instance."""
+    rp, rd = kkt_residuals(inst, x, s, y)
+    return float(rp @ rp + rd @ rd)
+
+
+def residual_loss_grad(inst, x, s, y):
+    rp, rd = kkt_residuals(inst, x, s, y)
+    gx = 2.0 * (inst.A.T @ rp) + 2.0 * (inst.P.T @ rd)
+    gs = 2.0 * rp
+    gy = -2.0 * (inst.A @ rd)
+    return gx, gs, gy
+
+
+def run_fixed(inst, rho_row: np.ndarray, alpha: float, iters: int, sigma: float = 1e-6,
+              z0: Optional[tuple] = None):
+    """Plain COSMO with constant (rho, alpha) for `iters` steps, reusing one
+    factorisation; used to reach converged values for closed-form checks."""
+    n, m = inst.A.shape[1], inst.A.shape[0]
+    if z0 is None:
+        x, s, y = np.zeros(n), np.zeros(m), np.zeros(m)
+    else:
+        x, s, y = (np.asarray(z, np.float64).copy() for z in z0)
+    lu = solve_reduced(inst, rectify(rho_row, inst.cones), sigma)
+    for _ in range(iters):
+        st = step_forward(inst, x, s, y, rho_row, alpha, sigma, lu=lu)
+        x, s, y = st["xn"], st["sn"], st["yn"]
+    return x, s, y
