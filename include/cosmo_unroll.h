@@ -1,0 +1,226 @@
+/*
+ * cosmo_unroll.h -- C ABI of the batched, unrolled COSMO hot path on MI355X.
+ *
+ * Problem (eq:conic-standard):  minimize 1/2 x'Px + q'x  s.t.  Ax + s = b, s in K,
+ * K a product of zero, nonnegative, second-order (SOC) and PSD cones.
+ *
+ * One forward step k (Sec. "Conic Operator Splitting Method", indirect mode
+ * eq:cosmo_linear_system_reduced; per-block penalty rectification of App. D,
+ * "Hyperparameter policy"):
+ *   rho_hat = rectify(rho^k)                       (mean over each SOC/PSD block)
+ *   x~  solves (P + sigma I + A' D(rho_hat) A) x~ = sigma x - q + A'(y + rho_hat o (b - s))
+ *        by Jacobi-preconditioned CG (Table 2, "Linear solve"), matrix-free
+ *   s~  = b - A x~
+ *   x+  = alpha x~ + (1 - alpha) x,   s^ = alpha s~ + (1 - alpha) s
+ *   s+  = Pi_K(s^ + y / rho_hat)                  (PSD: eigendecompose, clip; eq:psd-proj)
+ *   y+  = y + rho_hat o (s^ - s+)
+ * The backward pass is the matrix-free implicit rule of Sec. "Matrix-Free
+ * Implicit Differentiation" (adjoint CG with the same operator, eq:grad_rho)
+ * and the Daleckii-Krein rule for the PSD projection (eq:psd-cotangent-dk,
+ * eq:lowner).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Super-batch (App. C, "super-batches"): B independent instances are stacked;
+ *   instance i owns columns [n_off[i], n_off[i+1]) and rows [m_off[i], m_off[i+1]).
+ *   A and P are block diagonal by instance.
+ * - Real arrays hold `dtype` elements (float or double).  Index arrays are
+ *   int64 row pointers and int32 column indices.
+ * - PSD blocks use the svec encoding: a p x p symmetric block occupies
+ *   p(p+1)/2 consecutive rows, column-major over the upper triangle (column j
+ *   holds rows i = 0..j), off-diagonal entries scaled by sqrt(2).
+ * - "device" pointers are HIP device memory owned by the caller; "host"
+ *   pointers are read during the call only (unless stated otherwise).
+ * - `stream` is a hipStream_t (NULL = default stream).  Unroll, loss and
+ *   projection launches are asynchronous on it.  After cosmo_plan_create the
+ *   unroll and loss calls allocate nothing; every O(n + m) buffer (workspace,
+ *   tape) is caller-owned, sized by cosmo_workspace_size.
+ * - Errors: host-checkable misuse returns COSMO_EINVAL before anything is
+ *   launched; a HIP runtime failure returns COSMO_EHIP.  Numerical conditions
+ *   detected on the device (CG not converged, eigen-sweeps exhausted,
+ *   non-finite values) never abort a call: they are counted in cosmo_stats.
+ *   cosmo_last_error() returns a message for the last failure on this thread.
+ * - A plan is not safe for concurrent calls; distinct plans are independent.
+ */
+#ifndef COSMO_UNROLL_H
+#define COSMO_UNROLL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  COSMO_OK = 0,
+  COSMO_EINVAL = -1,        /* invalid argument or descriptor */
+  COSMO_ENOMEM = -2,        /* a plan-owned allocation failed */
+  COSMO_EHIP = -3,          /* HIP runtime error (launch, copy, device) */
+  COSMO_EUNSUPPORTED = -4   /* valid request outside the implemented envelope */
+} cosmo_status;
+
+typedef enum { COSMO_F32 = 0, COSMO_F64 = 1 } cosmo_dtype;
+
+typedef enum {
+  COSMO_CONE_ZERO = 0,      /* s = 0            (equality rows)          */
+  COSMO_CONE_NONNEG = 1,    /* s >= 0                                     */
+  COSMO_CONE_SOC = 2,       /* (t, w): ||w||_2 <= t, size = rows (>= 1)   */
+  COSMO_CONE_PSD = 3        /* svec(S), S psd, size = matrix order p      */
+} cosmo_cone_kind;
+
+/* Largest PSD order handled: the one-sided Jacobi eigensolver keeps one
+ * p x p block in the 160 KiB LDS of a workgroup. */
+#define COSMO_MAX_PSD_ORDER_F32 200
+#define COSMO_MAX_PSD_ORDER_F64 140
+
+typedef struct cosmo_plan cosmo_plan;
+
+/* Problem data of a super-batch.  Arrays marked (d) are device pointers that
+ * must stay valid and unchanged until cosmo_plan_destroy; (h) are host arrays
+ * read during cosmo_plan_create only. */
+typedef struct {
+  int32_t B;                   /* number of instances, >= 1                           */
+  const int64_t *n_off;        /* (h) [B+1], n_off[0] = 0, non-decreasing, n_tot = n_off[B] */
+  const int64_t *m_off;        /* (h) [B+1], m_off[0] = 0, strictly increasing         */
+  const int64_t *A_rowptr;     /* (d) [m_tot+1] CSR of A (m_tot x n_tot)               */
+  const int32_t *A_col;        /* (d) [nnz(A)], columns inside the row's instance       */
+  const void *A_val;           /* (d) [nnz(A)] dtype                                    */
+  int64_t A_nnz;
+  const int64_t *P_rowptr;     /* (d) [n_tot+1] CSR of P, symmetric, full storage;
+                                  may be NULL when P_nnz == 0                            */
+  const int32_t *P_col;        /* (d) [nnz(P)]                                          */
+  const void *P_val;           /* (d) [nnz(P)] dtype                                    */
+  int64_t P_nnz;
+  const void *q;               /* (d) [n_tot] dtype                                     */
+  const void *b;               /* (d) [m_tot] dtype                                     */
+  int32_t n_cones;             /* cone blocks, laid out contiguously in list order,
+                                  covering rows 0..m_tot, none straddling instances     */
+  const int32_t *cone_kind;    /* (h) [n_cones] cosmo_cone_kind                         */
+  const int32_t *cone_size;    /* (h) [n_cones] rows (zero/nonneg/soc) or order p (psd) */
+} cosmo_problem;
+
+typedef struct {
+  cosmo_dtype dtype;           /* arithmetic and storage type of all real arrays        */
+  int32_t K;                   /* unrolled steps, >= 1                                  */
+  double sigma;                /* > 0; the paper fixes 1e-6                             */
+  double cg_tol;               /* PCG stops when ||xi - M x~||_2 <= cg_tol ||xi||_2      */
+  int32_t cg_max_iter;         /* >= 1                                                   */
+  int32_t eig_max_sweeps;      /* Jacobi sweep cap, >= 1                                 */
+  double eig_tol;              /* Jacobi column-orthogonality threshold; 0 = dtype default */
+  int32_t eig_refine;          /* float64 refinement steps applied to the float32
+                                  eigenpairs of every PSD block (Ogita-Aishima); the
+                                  projection is then formed in float64.  Ignored for
+                                  COSMO_F64, whose sweeps already run in float64.       */
+} cosmo_options;
+
+/* Per-instance device counters, updated with atomics (max / or); the caller
+ * zeroes them before a call if it wants per-call values. */
+typedef struct {
+  int32_t cg_iters_max;        /* largest PCG iteration count of any solve             */
+  int32_t cg_not_converged;    /* number of solves that hit cg_max_iter                */
+  int32_t eig_sweeps_max;      /* largest Jacobi sweep count of any PSD block          */
+  int32_t eig_not_converged;   /* PSD eigensolves that hit eig_max_sweeps              */
+  int32_t nonfinite;           /* 1 if a non-finite value reached the iterate          */
+  int32_t reserved[3];
+} cosmo_stats;
+
+const char *cosmo_status_string(cosmo_status s);
+const char *cosmo_last_error(void);
+int32_t cosmo_abi_version(void);
+
+/* Validate the problem, copy its structure to the host, build the transposed
+ * CSR of A, cone tables and work lists, and upload them (plan-owned device
+ * memory, freed by cosmo_plan_destroy).  Synchronous.  *plan is NULL on error. */
+cosmo_status cosmo_plan_create(cosmo_plan **plan, const cosmo_problem *prob, const cosmo_options *opt);
+cosmo_status cosmo_plan_destroy(cosmo_plan *plan);
+
+/* Bytes of caller-owned device memory: forward workspace, tape (K steps of
+ * checkpoints: iterates z^0..z^K, x~ and s~ of every step, eigenvalues and
+ * eigenvectors of every PSD block -- O(n + m + sum p^2) per step), backward
+ * workspace.  Any pointer may be NULL. */
+cosmo_status cosmo_workspace_size(const cosmo_plan *plan, size_t *fwd_ws_bytes, size_t *tape_bytes,
+                                  size_t *bwd_ws_bytes);
+
+/* Byte offsets, inside the tape, of iterate k (0 <= k <= K) and of x~, s~ of
+ * step k (0 <= k < K; pass NULL for those when k == K). */
+cosmo_status cosmo_tape_offsets(const cosmo_plan *plan, int32_t k, size_t *x_off, size_t *s_off,
+                                size_t *y_off, size_t *xt_off, size_t *st_off);
+
+/* K forward steps.
+ *   rho   (d) [K][m_tot] > 0, per row; rectified per SOC/PSD block inside.
+ *   alpha (d) [K][B] in (0, 2), one relaxation per instance and step.
+ *   x0 (d) [n_tot], s0, y0 (d) [m_tot]; NULL = zeros (App. D default start).
+ *   xK, sK, yK (d) outputs (may be NULL).
+ *   tape  (d) [tape_bytes] or NULL for a forward-only run (then the backward
+ *         pass is unavailable and only the final iterate is kept).
+ *   ws    (d) [fwd_ws_bytes].   stats (d) [B] cosmo_stats or NULL. */
+cosmo_status cosmo_unroll_forward(cosmo_plan *plan, const void *rho, const void *alpha, const void *x0,
+                                  const void *s0, const void *y0, void *xK, void *sK, void *yK, void *tape,
+                                  void *ws, void *stats, void *stream);
+
+/* Reverse pass over the K steps recorded in `tape` by cosmo_unroll_forward
+ * with the same rho / alpha.  Incoming cotangents gxK, gsK, gyK (d) of the
+ * final iterate (NULL = 0).  Outputs (d), each may be NULL:
+ *   grho [K][m_tot] w.r.t. the raw per-row rho (rectification included),
+ *   galpha [K][B], gx0 [n_tot], gs0, gy0 [m_tot].
+ *   ws (d) [bwd_ws_bytes].  Deterministic: no floating-point atomics. */
+cosmo_status cosmo_unroll_backward(cosmo_plan *plan, const void *rho, const void *alpha, const void *tape,
+                                   const void *gxK, const void *gsK, const void *gyK, void *grho,
+                                   void *galpha, void *gx0, void *gs0, void *gy0, void *ws, void *stats,
+                                   void *stream);
+
+/* Final-residual loss per instance, L_i = ||A x + s - b||^2 + ||P x + q - A'y||^2
+ * (the dual residual sign follows the fixed point of the iteration above,
+ * at which P x + q - A'y = 0), and its gradient when gx, gs, gy are non-NULL:
+ *   gx = 2A'r_p + 2P r_d,  gs = 2 r_p,  gy = -2 A r_d.
+ * loss (d) [B].  ws (d) [fwd_ws_bytes] of the same plan. */
+cosmo_status cosmo_residual_loss(cosmo_plan *plan, const void *x, const void *s, const void *y, void *loss,
+                                 void *gx, void *gs, void *gy, void *ws, void *stream);
+
+/* Standalone projections (the same kernels as the unroll).  Block layouts are
+ * host arrays; they are copied into the caller's workspace `ws` with a
+ * blocking copy before the asynchronous launch.  `offset` is the first row of
+ * each block inside `in` / `out`.  Block rows must not overlap. */
+
+/* Bytes of device workspace for psd_proj / psd_proj_vjp / socp_proj(_vjp):
+ * block descriptors plus 3 p^2 float64 of refinement scratch per PSD block. */
+size_t cosmo_proj_workspace_size(int32_t nblk, const int32_t *order_or_dim);
+
+/* eq:psd-proj per block: out = svec(U max(L, 0) U') of S = smat(in).
+ * eigvals (d, nullable) [sum p], in no particular order inside a block;
+ * eigvecs (d, nullable) [sum p^2], block b column-major p x p at offset
+ * sum_{b'<b} p_{b'}^2, column i paired with eigvals i.  `refine` as in
+ * cosmo_options.eig_refine. */
+cosmo_status psd_proj(int32_t nblk, const int32_t *order, const int64_t *offset, cosmo_dtype dtype,
+                      const void *in, void *out, void *eigvals, void *eigvecs, int32_t max_sweeps,
+                      double eig_tol, int32_t refine, void *ws, void *stream);
+
+/* eq:psd-cotangent-dk per block, reusing the decomposition of psd_proj:
+ * gin = svec(U (L o (U' smat(gout) U)) U'), L the Loewner matrix of max(., 0)
+ * (eq:lowner; f'(0) taken as 0). */
+cosmo_status psd_proj_vjp(int32_t nblk, const int32_t *order, const int64_t *offset, cosmo_dtype dtype,
+                          const void *eigvals, const void *eigvecs, const void *gout, void *gin, void *ws,
+                          void *stream);
+
+/* Projection onto SOC blocks (t, w) of `dim` rows (closed form), and its VJP
+ * (J is symmetric: identity inside the cone, zero inside its polar, else
+ * 1/2 [[1, u'], [u, (1 + t/|w|) I - (t/|w|) u u']] with u = w/|w|). */
+cosmo_status socp_proj(int32_t ncones, const int32_t *dim, const int64_t *offset, cosmo_dtype dtype,
+                       const void *in, void *out, void *ws, void *stream);
+cosmo_status socp_proj_vjp(int32_t ncones, const int32_t *dim, const int64_t *offset, cosmo_dtype dtype,
+                           const void *in, const void *gout, void *gin, void *ws, void *stream);
+
+/* Measurement support (not needed on the hot path).  With profiling on, the
+ * library records a pair of HIP events on the call's stream around every
+ * launch of a kernel family: 0 = PSD eigensolve + reconstruction, 1 = DK VJP,
+ * 2 = PCG solves, 3 = row/column SpMV passes.  profile_read waits for the
+ * recorded events and returns the number of launches and their summed
+ * duration since profiling was (re)enabled. */
+cosmo_status cosmo_plan_set_profiling(cosmo_plan *plan, int32_t enable);
+cosmo_status cosmo_plan_profile_read(cosmo_plan *plan, int32_t kind, int64_t *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COSMO_UNROLL_H */

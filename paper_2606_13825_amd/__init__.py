@@ -1,0 +1,14 @@
+"""MI355X-native batched, unrolled COSMO for conic programs.
+
+Forward: matrix-free Jacobi-PCG on the reduced system, projections onto the
+zero, nonnegative, second-order and PSD cones.  Backward: adjoint PCG
+(matrix-free implicit differentiation) and the Daleckii-Krein VJP of the PSD
+projection.  All of it runs in the HIP library libcosmo_unroll.so behind the
+C ABI of include/cosmo_unroll.h; this package only marshals arguments.
+"""
+from .binding import (CosmoBatch, CosmoUnroll, ResidualLoss, psd_proj, psd_proj_vjp, socp_proj,
+                      socp_proj_vjp, ForwardResult, BackwardResult)
+from ._lib import CosmoError, lib, LIB_PATH
+
+__all__ = ["CosmoBatch", "CosmoUnroll", "ResidualLoss", "psd_proj", "psd_proj_vjp", "socp_proj",
+           "socp_proj_vjp", "ForwardResult", "BackwardResult", "CosmoError", "lib", "LIB_PATH"]

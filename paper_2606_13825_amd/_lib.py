@@ -1,0 +1,135 @@
+"""ctypes loader for libcosmo_unroll.so (the C ABI in include/cosmo_unroll.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+library.  Importing this module does not touch the GPU; loading fails loudly
+when the library has not been built.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcosmo_unroll.so")
+
+COSMO_OK, COSMO_EINVAL, COSMO_ENOMEM, COSMO_EHIP, COSMO_EUNSUPPORTED = 0, -1, -2, -3, -4
+COSMO_F32, COSMO_F64 = 0, 1
+CONE_CODES = {"zero": 0, "nonneg": 1, "soc": 2, "psd": 3}
+
+# Every symbol the header declares (checked by the CPU test-suite).
+EXPORTED = [
+    "cosmo_status_string", "cosmo_last_error", "cosmo_abi_version",
+    "cosmo_plan_create", "cosmo_plan_destroy", "cosmo_workspace_size", "cosmo_tape_offsets",
+    "cosmo_unroll_forward", "cosmo_unroll_backward", "cosmo_residual_loss",
+    "cosmo_proj_workspace_size", "psd_proj", "psd_proj_vjp", "socp_proj", "socp_proj_vjp",
+    "cosmo_plan_set_profiling", "cosmo_plan_profile_read",
+]
+
+
+class CosmoProblem(ctypes.Structure):
+    _fields_ = [
+        ("B", ctypes.c_int32),
+        ("n_off", ctypes.POINTER(ctypes.c_int64)),
+        ("m_off", ctypes.POINTER(ctypes.c_int64)),
+        ("A_rowptr", ctypes.c_void_p),
+        ("A_col", ctypes.c_void_p),
+        ("A_val", ctypes.c_void_p),
+        ("A_nnz", ctypes.c_int64),
+        ("P_rowptr", ctypes.c_void_p),
+        ("P_col", ctypes.c_void_p),
+        ("P_val", ctypes.c_void_p),
+        ("P_nnz", ctypes.c_int64),
+        ("q", ctypes.c_void_p),
+        ("b", ctypes.c_void_p),
+        ("n_cones", ctypes.c_int32),
+        ("cone_kind", ctypes.POINTER(ctypes.c_int32)),
+        ("cone_size", ctypes.POINTER(ctypes.c_int32)),
+    ]
+
+
+class CosmoOptions(ctypes.Structure):
+    _fields_ = [
+        ("dtype", ctypes.c_int32),
+        ("K", ctypes.c_int32),
+        ("sigma", ctypes.c_double),
+        ("cg_tol", ctypes.c_double),
+        ("cg_max_iter", ctypes.c_int32),
+        ("eig_max_sweeps", ctypes.c_int32),
+        ("eig_tol", ctypes.c_double),
+        ("eig_refine", ctypes.c_int32),
+    ]
+
+
+class CosmoStats(ctypes.Structure):
+    _fields_ = [("cg_iters_max", ctypes.c_int32), ("cg_not_converged", ctypes.c_int32),
+                ("eig_sweeps_max", ctypes.c_int32), ("eig_not_converged", ctypes.c_int32),
+                ("nonfinite", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+STATS_FIELDS = ["cg_iters_max", "cg_not_converged", "eig_sweeps_max", "eig_not_converged", "nonfinite"]
+STATS_INTS = 8
+
+_lib = None
+
+
+class CosmoError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: status {status}: {msg}")
+        self.status = status
+
+
+def _sig(lib):
+    vp, i32, i64, dbl, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    P32 = ctypes.POINTER(ctypes.c_int32)
+    P64 = ctypes.POINTER(ctypes.c_int64)
+    lib.cosmo_status_string.restype = ctypes.c_char_p
+    lib.cosmo_status_string.argtypes = [ctypes.c_int]
+    lib.cosmo_last_error.restype = ctypes.c_char_p
+    lib.cosmo_last_error.argtypes = []
+    lib.cosmo_abi_version.restype = i32
+    lib.cosmo_plan_create.restype = ctypes.c_int
+    lib.cosmo_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(CosmoProblem), ctypes.POINTER(CosmoOptions)]
+    lib.cosmo_plan_destroy.restype = ctypes.c_int
+    lib.cosmo_plan_destroy.argtypes = [vp]
+    lib.cosmo_workspace_size.restype = ctypes.c_int
+    lib.cosmo_workspace_size.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(sz)]
+    lib.cosmo_tape_offsets.restype = ctypes.c_int
+    lib.cosmo_tape_offsets.argtypes = [vp, i32] + [ctypes.POINTER(sz)] * 5
+    lib.cosmo_unroll_forward.restype = ctypes.c_int
+    lib.cosmo_unroll_forward.argtypes = [vp] * 13
+    lib.cosmo_unroll_backward.restype = ctypes.c_int
+    lib.cosmo_unroll_backward.argtypes = [vp] * 15
+    lib.cosmo_residual_loss.restype = ctypes.c_int
+    lib.cosmo_residual_loss.argtypes = [vp] * 10
+    lib.cosmo_proj_workspace_size.restype = sz
+    lib.cosmo_proj_workspace_size.argtypes = [i32, P32]
+    lib.psd_proj.restype = ctypes.c_int
+    lib.psd_proj.argtypes = [i32, P32, P64, ctypes.c_int, vp, vp, vp, vp, i32, dbl, i32, vp, vp]
+    lib.psd_proj_vjp.restype = ctypes.c_int
+    lib.psd_proj_vjp.argtypes = [i32, P32, P64, ctypes.c_int, vp, vp, vp, vp, vp, vp]
+    lib.socp_proj.restype = ctypes.c_int
+    lib.socp_proj.argtypes = [i32, P32, P64, ctypes.c_int, vp, vp, vp, vp]
+    lib.socp_proj_vjp.restype = ctypes.c_int
+    lib.socp_proj_vjp.argtypes = [i32, P32, P64, ctypes.c_int, vp, vp, vp, vp, vp]
+    lib.cosmo_plan_set_profiling.restype = ctypes.c_int
+    lib.cosmo_plan_set_profiling.argtypes = [vp, i32]
+    lib.cosmo_plan_profile_read.restype = ctypes.c_int
+    lib.cosmo_plan_profile_read.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(dbl)]
+
+
+def lib():
+    """The loaded library; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2606_13825_amd.build.build() "
+                               "(the HIP library is required; there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        _sig(L)
+        _lib = L
+    return _lib
+
+
+def check(status: int, where: str) -> None:
+    if status != COSMO_OK:
+        L = lib()
+        msg = L.cosmo_last_error().decode(errors="replace")
+        raise CosmoError(status, where, msg or L.cosmo_status_string(status).decode())

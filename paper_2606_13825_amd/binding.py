@@ -1,0 +1,391 @@
+"""Python binding of the C ABI: stacks a list of conic instances into one
+super-batch (device tensors owned by PyTorch), creates the plan, and exposes
+the forward / backward / loss / projection calls plus a
+torch.autograd.Function wrapper.  Marshalling only: no step of the method is
+computed here.
+
+An instance is any object with attributes P (n x n scipy sparse, symmetric),
+q [n], A (m x n scipy sparse), b [m] and cones (objects with .kind in
+{"zero", "nonneg", "soc", "psd"} and .size = rows, or matrix order for psd).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_TORCH_DT = {L.COSMO_F32: torch.float32, L.COSMO_F64: torch.float64}
+_NP_DT = {L.COSMO_F32: np.float32, L.COSMO_F64: np.float64}
+
+
+def _dt_code(dtype) -> int:
+    if dtype in (torch.float32, np.float32, "f32", "float32"):
+        return L.COSMO_F32
+    if dtype in (torch.float64, np.float64, "f64", "float64"):
+        return L.COSMO_F64
+    raise ValueError(f"unsupported dtype {dtype}")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _psd_rows(p: int) -> int:
+    return p * (p + 1) // 2
+
+
+@dataclass
+class ForwardResult:
+    x: torch.Tensor
+    s: torch.Tensor
+    y: torch.Tensor
+    tape: Optional[torch.Tensor]
+
+
+@dataclass
+class BackwardResult:
+    grho: torch.Tensor
+    galpha: torch.Tensor
+    gx0: torch.Tensor
+    gs0: torch.Tensor
+    gy0: torch.Tensor
+
+
+class CosmoBatch:
+    """A super-batch of B instances on one GPU and its plan (App. C,
+    "super-batches").  Hyperparameters: rho [K, m_tot] per row, alpha [K, B]."""
+
+    def __init__(self, instances: Sequence, *, K: int, dtype=torch.float32, sigma: float = 1e-6,
+                 cg_tol: Optional[float] = None, cg_max_iter: int = 500, eig_max_sweeps: int = 60,
+                 eig_tol: float = 0.0, eig_refine: int = 1, device="cuda:0"):
+        self.device = torch.device(device)
+        self.code = _dt_code(dtype)
+        self.dtype = _TORCH_DT[self.code]
+        npdt = _NP_DT[self.code]
+        self.K, self.B = int(K), len(instances)
+        if cg_tol is None:
+            cg_tol = 1e-6 if self.code == L.COSMO_F32 else 1e-12
+        ns = [int(inst.A.shape[1]) for inst in instances]
+        ms = [int(inst.A.shape[0]) for inst in instances]
+        self.n_off = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+        self.m_off = np.concatenate([[0], np.cumsum(ms)]).astype(np.int64)
+        self.n_tot, self.m_tot = int(self.n_off[-1]), int(self.m_off[-1])
+        # stacked CSR of A and P (block diagonal), built per instance
+        arp, acol, aval, prp, pcol, pval = [np.zeros(1, np.int64)], [], [], [np.zeros(1, np.int64)], [], []
+        annz = pnnz = 0
+        kinds, sizes = [], []
+        for i, inst in enumerate(instances):
+            A = inst.A.tocsr()
+            A.sort_indices()
+            arp.append(A.indptr[1:].astype(np.int64) + annz)
+            acol.append(A.indices.astype(np.int32) + np.int32(self.n_off[i]))
+            aval.append(A.data.astype(npdt))
+            annz += A.nnz
+            Pm = inst.P.tocsr()
+            Pm.sort_indices()
+            prp.append(Pm.indptr[1:].astype(np.int64) + pnnz)
+            pcol.append(Pm.indices.astype(np.int32) + np.int32(self.n_off[i]))
+            pval.append(Pm.data.astype(npdt))
+            pnnz += Pm.nnz
+            for c in inst.cones:
+                kinds.append(L.CONE_CODES[c.kind])
+                sizes.append(int(c.size))
+        dev = self.device
+        self.A_rowptr = torch.from_numpy(np.concatenate(arp)).to(dev)
+        self.A_col = torch.from_numpy(np.concatenate(acol) if acol else np.zeros(0, np.int32)).to(dev)
+        self.A_val = torch.from_numpy(np.concatenate(aval)).to(dev)
+        self.A_nnz = annz
+        self.P_nnz = pnnz
+        if pnnz:
+            self.P_rowptr = torch.from_numpy(np.concatenate(prp)).to(dev)
+            self.P_col = torch.from_numpy(np.concatenate(pcol)).to(dev)
+            self.P_val = torch.from_numpy(np.concatenate(pval)).to(dev)
+        else:
+            self.P_rowptr = self.P_col = self.P_val = None
+        self.q = torch.from_numpy(np.concatenate([np.asarray(inst.q, np.float64) for inst in instances]).astype(npdt)).to(dev)
+        self.b = torch.from_numpy(np.concatenate([np.asarray(inst.b, np.float64) for inst in instances]).astype(npdt)).to(dev)
+        self.cone_kind = np.asarray(kinds, np.int32)
+        self.cone_size = np.asarray(sizes, np.int32)
+        self.instances_meta = [(ns[i], ms[i]) for i in range(self.B)]
+        prob = L.CosmoProblem()
+        prob.B = self.B
+        prob.n_off = self.n_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        prob.m_off = self.m_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        prob.A_rowptr = self.A_rowptr.data_ptr()
+        prob.A_col = self.A_col.data_ptr()
+        prob.A_val = self.A_val.data_ptr()
+        prob.A_nnz = annz
+        prob.P_rowptr = self.P_rowptr.data_ptr() if pnnz else None
+        prob.P_col = self.P_col.data_ptr() if pnnz else None
+        prob.P_val = self.P_val.data_ptr() if pnnz else None
+        prob.P_nnz = pnnz
+        prob.q = self.q.data_ptr()
+        prob.b = self.b.data_ptr()
+        prob.n_cones = len(kinds)
+        prob.cone_kind = self.cone_kind.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        prob.cone_size = self.cone_size.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        opt = L.CosmoOptions()
+        opt.dtype = self.code
+        opt.K = self.K
+        opt.sigma = float(sigma)
+        opt.cg_tol = float(cg_tol)
+        opt.cg_max_iter = int(cg_max_iter)
+        opt.eig_max_sweeps = int(eig_max_sweeps)
+        opt.eig_tol = float(eig_tol)
+        opt.eig_refine = int(eig_refine)
+        self.opt = opt
+        lib = L.lib()
+        torch.cuda.synchronize(dev)
+        h = ctypes.c_void_p()
+        L.check(lib.cosmo_plan_create(ctypes.byref(h), ctypes.byref(prob), ctypes.byref(opt)), "cosmo_plan_create")
+        self._plan = h
+        f, t, b = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        L.check(lib.cosmo_workspace_size(h, ctypes.byref(f), ctypes.byref(t), ctypes.byref(b)), "cosmo_workspace_size")
+        self.fwd_ws_bytes, self.tape_bytes, self.bwd_ws_bytes = f.value, t.value, b.value
+        self.esz = 4 if self.code == L.COSMO_F32 else 8
+
+    # -- lifetime ------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_plan", None):
+            L.lib().cosmo_plan_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- buffers ---------------------------------------------------------------
+    def _buf(self, nbytes: int) -> torch.Tensor:
+        return torch.empty((max(nbytes, self.esz) + self.esz - 1) // self.esz, dtype=self.dtype, device=self.device)
+
+    def new_tape(self) -> torch.Tensor:
+        return self._buf(self.tape_bytes)
+
+    def new_fwd_ws(self) -> torch.Tensor:
+        return self._buf(self.fwd_ws_bytes)
+
+    def new_bwd_ws(self) -> torch.Tensor:
+        return self._buf(self.bwd_ws_bytes)
+
+    def new_stats(self) -> torch.Tensor:
+        return torch.zeros((self.B, L.STATS_INTS), dtype=torch.int32, device=self.device)
+
+    @staticmethod
+    def stats_dict(stats: torch.Tensor):
+        s = stats.cpu().numpy()
+        return {k: s[:, i].copy() for i, k in enumerate(L.STATS_FIELDS)}
+
+    def _check_vec(self, t, n, name):
+        if t is None:
+            return None
+        if t.dtype != self.dtype or t.device != self.device or not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"{name}: need a contiguous {self.dtype} tensor of {n} elements on {self.device}")
+        return t
+
+    # -- calls ---------------------------------------------------------------
+    def forward(self, rho: torch.Tensor, alpha: torch.Tensor, x0=None, s0=None, y0=None, *, tape=True,
+                stats: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
+                out: Optional[tuple] = None) -> ForwardResult:
+        self._check_vec(rho, self.K * self.m_tot, "rho")
+        self._check_vec(alpha, self.K * self.B, "alpha")
+        for t, n, nm in ((x0, self.n_tot, "x0"), (s0, self.m_tot, "s0"), (y0, self.m_tot, "y0")):
+            self._check_vec(t, n, nm)
+        if isinstance(tape, torch.Tensor):
+            tp = tape
+        else:
+            tp = self.new_tape() if tape else None
+        ws = ws if ws is not None else self.new_fwd_ws()
+        if out is None:
+            out = (torch.empty(self.n_tot, dtype=self.dtype, device=self.device),
+                   torch.empty(self.m_tot, dtype=self.dtype, device=self.device),
+                   torch.empty(self.m_tot, dtype=self.dtype, device=self.device))
+        x, s, y = out
+        st = L.lib().cosmo_unroll_forward(self._plan, _ptr(rho), _ptr(alpha), _ptr(x0), _ptr(s0), _ptr(y0),
+                                          _ptr(x), _ptr(s), _ptr(y), _ptr(tp), _ptr(ws), _ptr(stats),
+                                          _stream(self.device))
+        L.check(st, "cosmo_unroll_forward")
+        return ForwardResult(x, s, y, tp)
+
+    def backward(self, rho, alpha, tape, gx=None, gs=None, gy=None, *, stats=None, ws=None,
+                 out: Optional[tuple] = None) -> BackwardResult:
+        if tape is None:
+            raise ValueError("backward needs the tape of a forward call")
+        for t, n, nm in ((gx, self.n_tot, "gx"), (gs, self.m_tot, "gs"), (gy, self.m_tot, "gy")):
+            self._check_vec(t, n, nm)
+        ws = ws if ws is not None else self.new_bwd_ws()
+        if out is None:
+            out = (torch.empty((self.K, self.m_tot), dtype=self.dtype, device=self.device),
+                   torch.empty((self.K, self.B), dtype=self.dtype, device=self.device),
+                   torch.empty(self.n_tot, dtype=self.dtype, device=self.device),
+                   torch.empty(self.m_tot, dtype=self.dtype, device=self.device),
+                   torch.empty(self.m_tot, dtype=self.dtype, device=self.device))
+        grho, galpha, gx0, gs0, gy0 = out
+        st = L.lib().cosmo_unroll_backward(self._plan, _ptr(rho), _ptr(alpha), _ptr(tape), _ptr(gx), _ptr(gs),
+                                           _ptr(gy), _ptr(grho), _ptr(galpha), _ptr(gx0), _ptr(gs0), _ptr(gy0),
+                                           _ptr(ws), _ptr(stats), _stream(self.device))
+        L.check(st, "cosmo_unroll_backward")
+        return BackwardResult(grho, galpha, gx0, gs0, gy0)
+
+    def residual_loss(self, x, s, y, *, grad=True, ws=None):
+        ws = ws if ws is not None else self.new_fwd_ws()
+        loss = torch.empty(self.B, dtype=self.dtype, device=self.device)
+        g = (torch.empty(self.n_tot, dtype=self.dtype, device=self.device),
+             torch.empty(self.m_tot, dtype=self.dtype, device=self.device),
+             torch.empty(self.m_tot, dtype=self.dtype, device=self.device)) if grad else (None, None, None)
+        st = L.lib().cosmo_residual_loss(self._plan, _ptr(x), _ptr(s), _ptr(y), _ptr(loss), _ptr(g[0]),
+                                         _ptr(g[1]), _ptr(g[2]), _ptr(ws), _stream(self.device))
+        L.check(st, "cosmo_residual_loss")
+        return loss, g
+
+    def tape_iterate(self, tape: torch.Tensor, k: int):
+        """Views of (x^k, s^k, y^k) and, for k < K, (x~, s~) of step k."""
+        offs = [ctypes.c_size_t() for _ in range(5)]
+        want_step = k < self.K
+        args = [ctypes.byref(o) for o in offs[:3]] + ([ctypes.byref(o) for o in offs[3:]] if want_step else [None, None])
+        L.check(L.lib().cosmo_tape_offsets(self._plan, int(k), *args), "cosmo_tape_offsets")
+        e = self.esz
+        n, m = self.n_tot, self.m_tot
+        x = tape[offs[0].value // e: offs[0].value // e + n]
+        s = tape[offs[1].value // e: offs[1].value // e + m]
+        y = tape[offs[2].value // e: offs[2].value // e + m]
+        if not want_step:
+            return x, s, y, None, None
+        return (x, s, y, tape[offs[3].value // e: offs[3].value // e + n],
+                tape[offs[4].value // e: offs[4].value // e + m])
+
+    def split_n(self, v):
+        return [v[self.n_off[i]:self.n_off[i + 1]] for i in range(self.B)]
+
+    def split_m(self, v):
+        return [v[..., self.m_off[i]:self.m_off[i + 1]] for i in range(self.B)]
+
+    # -- measurement -------------------------------------------------------------
+    def set_profiling(self, on: bool):
+        L.check(L.lib().cosmo_plan_set_profiling(self._plan, int(on)), "cosmo_plan_set_profiling")
+
+    def profile_read(self, kind: int):
+        n, ms = ctypes.c_int64(), ctypes.c_double()
+        L.check(L.lib().cosmo_plan_profile_read(self._plan, int(kind), ctypes.byref(n), ctypes.byref(ms)),
+                "cosmo_plan_profile_read")
+        return n.value, ms.value
+
+
+class CosmoUnroll(torch.autograd.Function):
+    """(x^K, s^K, y^K) = K unrolled COSMO steps from (x^0, s^0, y^0) with
+    per-step (rho^k, alpha^k); backward by the library's reverse pass."""
+
+    @staticmethod
+    def forward(ctx, batch: CosmoBatch, rho, alpha, x0=None, s0=None, y0=None):
+        r = batch.forward(rho.contiguous(), alpha.contiguous(), x0, s0, y0, tape=True)
+        ctx.batch = batch
+        ctx.has0 = (x0 is not None, s0 is not None, y0 is not None)
+        ctx.save_for_backward(rho, alpha, r.tape)
+        return r.x, r.s, r.y
+
+    @staticmethod
+    def backward(ctx, gx, gs, gy):
+        rho, alpha, tape = ctx.saved_tensors
+        b: CosmoBatch = ctx.batch
+        g = [None if t is None else t.contiguous() for t in (gx, gs, gy)]
+        r = b.backward(rho.contiguous(), alpha.contiguous(), tape, *g)
+        return (None, r.grho.view_as(rho), r.galpha.view_as(alpha),
+                r.gx0 if ctx.has0[0] else None, r.gs0 if ctx.has0[1] else None, r.gy0 if ctx.has0[2] else None)
+
+
+class ResidualLoss(torch.autograd.Function):
+    """Sum over instances of ||Ax + s - b||^2 + ||Px + q - A'y||^2."""
+
+    @staticmethod
+    def forward(ctx, batch: CosmoBatch, x, s, y):
+        loss, g = batch.residual_loss(x.contiguous(), s.contiguous(), y.contiguous(), grad=True)
+        ctx.save_for_backward(*g)
+        return loss.sum()
+
+    @staticmethod
+    def backward(ctx, go):
+        gx, gs, gy = ctx.saved_tensors
+        return None, gx * go, gs * go, gy * go
+
+
+# ---- standalone projections --------------------------------------------------
+
+def _proj_ws(nblk: int, sizes: np.ndarray, device) -> torch.Tensor:
+    nb = L.lib().cosmo_proj_workspace_size(int(nblk), sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return torch.empty(int(nb), dtype=torch.uint8, device=device)
+
+
+def psd_proj(x: torch.Tensor, orders: Sequence[int], offsets: Optional[Sequence[int]] = None, *,
+             max_sweeps: int = 60, eig_tol: float = 0.0, refine: int = 1, want_eig: bool = True):
+    """Project each svec block of x onto the PSD cone (eq:psd-proj).
+    Returns (out, eigvals [sum p], eigvecs [sum p^2]) ."""
+    orders = np.asarray(orders, np.int32)
+    if offsets is None:
+        offsets = np.concatenate([[0], np.cumsum([_psd_rows(int(p)) for p in orders])[:-1]])
+    offsets = np.asarray(offsets, np.int64)
+    code = _dt_code(x.dtype)
+    out = torch.empty_like(x)
+    lam = torch.empty(int(orders.sum()), dtype=x.dtype, device=x.device) if want_eig else None
+    U = torch.empty(int((orders.astype(np.int64) ** 2).sum()), dtype=x.dtype, device=x.device) if want_eig else None
+    ws = _proj_ws(len(orders), orders, x.device)
+    st = L.lib().psd_proj(len(orders), orders.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                          offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), code, _ptr(x.contiguous()),
+                          _ptr(out), _ptr(lam), _ptr(U), int(max_sweeps), float(eig_tol), int(refine), _ptr(ws),
+                          _stream(x.device))
+    L.check(st, "psd_proj")
+    return out, lam, U
+
+
+def psd_proj_vjp(eigvals, eigvecs, gout: torch.Tensor, orders, offsets=None):
+    """Daleckii-Krein VJP of psd_proj (eq:psd-cotangent-dk)."""
+    orders = np.asarray(orders, np.int32)
+    if offsets is None:
+        offsets = np.concatenate([[0], np.cumsum([_psd_rows(int(p)) for p in orders])[:-1]])
+    offsets = np.asarray(offsets, np.int64)
+    gin = torch.empty_like(gout)
+    ws = _proj_ws(len(orders), orders, gout.device)
+    st = L.lib().psd_proj_vjp(len(orders), orders.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                              offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dt_code(gout.dtype),
+                              _ptr(eigvals), _ptr(eigvecs), _ptr(gout.contiguous()), _ptr(gin), _ptr(ws),
+                              _stream(gout.device))
+    L.check(st, "psd_proj_vjp")
+    return gin
+
+
+def socp_proj(x: torch.Tensor, dims: Sequence[int], offsets=None):
+    dims = np.asarray(dims, np.int32)
+    if offsets is None:
+        offsets = np.concatenate([[0], np.cumsum(dims)[:-1]])
+    offsets = np.asarray(offsets, np.int64)
+    out = torch.empty_like(x)
+    ws = _proj_ws(len(dims), dims, x.device)
+    st = L.lib().socp_proj(len(dims), dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                           offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dt_code(x.dtype),
+                           _ptr(x.contiguous()), _ptr(out), _ptr(ws), _stream(x.device))
+    L.check(st, "socp_proj")
+    return out
+
+
+def socp_proj_vjp(x: torch.Tensor, gout: torch.Tensor, dims, offsets=None):
+    dims = np.asarray(dims, np.int32)
+    if offsets is None:
+        offsets = np.concatenate([[0], np.cumsum(dims)[:-1]])
+    offsets = np.asarray(offsets, np.int64)
+    gin = torch.empty_like(gout)
+    ws = _proj_ws(len(dims), dims, x.device)
+    st = L.lib().socp_proj_vjp(len(dims), dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                               offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dt_code(x.dtype),
+                               _ptr(x.contiguous()), _ptr(gout.contiguous()), _ptr(gin), _ptr(ws),
+                               _stream(x.device))
+    L.check(st, "socp_proj_vjp")
+    return gin

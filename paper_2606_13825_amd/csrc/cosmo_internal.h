@@ -1,0 +1,147 @@
+// Internal declarations shared by the host library and the kernel files.
+// Not part of the public ABI (see include/cosmo_unroll.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "cosmo_unroll.h"
+
+namespace cosmo {
+
+// ---- device-side descriptors --------------------------------------------
+
+enum RowKind : uint8_t { ROW_ZERO = 0, ROW_NONNEG = 1, ROW_SOC = 2, ROW_PSD = 3 };
+
+struct SocDesc {      // one second-order cone block
+  int64_t row0;       // first row
+  int32_t dim;        // rows (t first, then w)
+  int32_t inst;       // owning instance
+};
+
+struct PsdDesc {      // one PSD block in svec form
+  int64_t row0;       // first row of its svec
+  int64_t uoff;       // element offset of its p x p eigenvector block (column-major)
+  int64_t loff;       // element offset of its p eigenvalues
+  int32_t p;          // matrix order
+  int32_t inst;       // owning instance
+};
+
+struct RectDesc {     // a block whose penalty is averaged (SOC or PSD)
+  int64_t row0;
+  int32_t rows;
+  int32_t pad;
+};
+
+// Rows (or columns) of a CSR matrix grouped into three length classes so a
+// sub-wave of L lanes serves one row with coalesced loads.
+struct RowBuckets {
+  int32_t *d_rows = nullptr;   // concatenated row ids of the three classes
+  int64_t begin[4] = {0, 0, 0, 0};
+  int32_t lanes[3] = {1, 8, 64};
+};
+
+// ---- dtype traits ------------------------------------------------------------
+
+template <typename T> struct Eps;
+template <> struct Eps<float> { static constexpr double jacobi_tol = 2.0e-7; };
+template <> struct Eps<double> { static constexpr double jacobi_tol = 1.0e-14; };
+
+// ---- launch wrappers (defined in the .hip files) ----------------------------
+
+struct ProblemDev;   // device-side view of a plan, passed by value to kernels
+
+template <typename T> struct View {
+  // problem (caller-owned)
+  const int64_t *A_rowptr; const int32_t *A_col; const T *A_val;
+  const int64_t *P_rowptr; const int32_t *P_col; const T *P_val;
+  const T *q; const T *b;
+  // plan-owned
+  const int64_t *At_rowptr; const int32_t *At_col; const T *At_val;
+  const T *Pdiag;
+  const uint8_t *row_kind; const int32_t *row_inst; const int32_t *col_inst;
+  const int64_t *n_off; const int64_t *m_off;
+  const int32_t *inst_LA; const int32_t *inst_LAt;
+  int32_t B; int64_t n_tot, m_tot;
+  T sigma;
+};
+
+struct Launch {
+  hipStream_t stream;
+};
+
+// vector / row-wise kernels (k_vec.hip)
+template <typename T> void launch_rectify(const View<T> &v, const RectDesc *rect, int32_t nrect, const T *rho,
+                                          T *rho_hat, int32_t K, hipStream_t st);
+template <typename T> void launch_cols_pre(const View<T> &v, const RowBuckets &bk, const T *rho_hat, const T *x,
+                                           const T *s, const T *y, T *dg, T *xi, hipStream_t st);
+template <typename T> void launch_rows_post(const View<T> &v, const RowBuckets &bk, const T *rho_hat,
+                                            const T *alpha_k, const T *xt, const T *s, const T *y, T *st_out,
+                                            T *sh, T *vv, T *s_new, T *y_new, hipStream_t st);
+template <typename T> void launch_bwd_rows_a(const View<T> &v, const T *rho_hat, const T *alpha_k, const T *stl,
+                                             const T *s, const T *y, const T *s_new, const T *gs_in,
+                                             const T *gy_in, T *gsn, T *gv, hipStream_t st);
+template <typename T> void launch_rows_v(const View<T> &v, const T *rho_hat, const T *alpha_k, const T *stl,
+                                         const T *s, const T *y, T *vv, hipStream_t st);
+template <typename T> void launch_bwd_rows_b(const View<T> &v, const T *rho_hat, const T *alpha_k, const T *stl,
+                                             const T *s, const T *y, const T *s_new, const T *gy_in, const T *gv,
+                                             T *gsh, T *gst, T *gs_out, T *gy_out, T *grh, hipStream_t st);
+template <typename T> void launch_bwd_cols(const View<T> &v, const RowBuckets &bk, const T *rho_hat,
+                                           const T *alpha_k, const T *gst, const T *gx_in, T *gxt, T *dg,
+                                           hipStream_t st);
+template <typename T> void launch_bwd_rows_c(const View<T> &v, const RowBuckets &bk, const T *rho_hat,
+                                             const T *w, const T *stl, const T *s, T *grh, T *gs_out,
+                                             T *gy_out, hipStream_t st);
+template <typename T> void launch_rect_adjoint(const View<T> &v, const RectDesc *rect, int32_t nrect,
+                                               const T *grh, T *grho_k, hipStream_t st);
+template <typename T> void launch_alpha_reduce(const View<T> &v, const T *gsh, const T *stl, const T *s,
+                                               const T *gx_in, const T *xt, const T *x, T *galpha_k,
+                                               hipStream_t st);
+template <typename T> void launch_loss(const View<T> &v, const RowBuckets &bkA, const RowBuckets &bkAt,
+                                       const T *x, const T *s, const T *y, T *rp, T *rd, T *loss, T *gx,
+                                       T *gs, T *gy, hipStream_t st);
+template <typename T> void launch_copy(T *dst, const T *src, int64_t n, hipStream_t st);
+template <typename T> void launch_fill(T *dst, T val, int64_t n, hipStream_t st);
+template <typename T> void launch_nonfinite_check(const View<T> &v, const T *x, const T *s, const T *y,
+                                                  cosmo_stats *stats, hipStream_t st);
+
+// PCG (k_pcg.hip): one workgroup per instance.
+//   mode 0 (forward): solves M x = rhs, warm start from x (in/out), writes
+//     xt_out (may alias x) and, if xnew != nullptr, x+ = alpha x~ + (1 - alpha) xold.
+//   mode 1 (adjoint): solves M w = rhs; writes w and gx_out = (1 - alpha) gx_in + sigma w.
+template <typename T> void launch_pcg(const View<T> &v, const T *rho_hat, const T *dg, const T *rhs, T *x,
+                                      T *r, T *z, T *p, T *Mp, T *t, double tol, int32_t max_iter,
+                                      const T *alpha_k, const T *xold, T *xnew, const T *gx_in, T *gx_out,
+                                      int32_t mode, cosmo_stats *stats, hipStream_t st);
+
+// SOC (k_soc.hip)
+template <typename T> void launch_soc_step(const SocDesc *d, int32_t n, const T *rho_hat, const T *vv,
+                                           const T *sh, const T *y, T *s_new, T *y_new, hipStream_t st);
+template <typename T> void launch_soc_vjp(const SocDesc *d, int32_t n, const T *vv, const T *g, T *out,
+                                          hipStream_t st);
+template <typename T> void launch_soc_proj(const SocDesc *d, int32_t n, const T *in, T *out, hipStream_t st);
+
+// PSD (k_psd.hip).  Blocks are processed by order class; `d` lists blocks
+// [0, n).  Forward step: eig of smat(vv_blk), Pi, s+ and y+ rows, eigenpairs
+// to (U, lam).  Standalone: the same with no y update.
+struct PsdLaunchCfg {
+  int32_t max_sweeps;
+  double tol;
+  int32_t refine;          // float64 refinement steps after the Jacobi sweeps
+  int32_t max_p;           // largest order in the list
+};
+template <typename T> void launch_psd_step(const PsdDesc *d, int32_t n, const PsdLaunchCfg &cfg,
+                                           const T *rho_hat, const T *vv, const T *sh, const T *y, T *s_new,
+                                           T *y_new, T *U, T *lam, double *rscratch, cosmo_stats *stats,
+                                           hipStream_t st);
+template <typename T> void launch_psd_vjp(const PsdDesc *d, int32_t n, int32_t max_p, const T *U, const T *lam,
+                                          const T *g, T *out, T *scratch, hipStream_t st);
+
+// bookkeeping for profiling: kernel-family events
+void set_last_error(const std::string &msg);
+
+}  // namespace cosmo

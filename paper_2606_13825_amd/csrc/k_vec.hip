@@ -1,0 +1,521 @@
+// Row- and column-wise kernels of the unrolled COSMO step: the right-hand
+// side and Jacobi diagonal of the reduced system, the slack / relaxation /
+// projection-onto-separable-cones pass, the reverse of those passes, penalty
+// rectification and its adjoint, per-instance reductions and the residual
+// loss.  All sparse products use coalesced sub-wave CSR: L consecutive lanes
+// serve one row and combine their partial sums with a fixed butterfly, so
+// every result is bitwise reproducible.
+#include "cosmo_internal.h"
+
+namespace cosmo {
+namespace {
+
+constexpr int NT = 256;
+
+template <typename T> __device__ inline T subwave_sum(T v, int L) {
+  for (int off = L >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Position of this thread inside the bucketed row list: returns false when
+// the sub-wave has no row.  All lanes of a sub-wave agree.
+struct BucketPos {
+  int64_t row;
+  int lane;
+  int L;
+};
+
+__device__ inline bool bucket_pos(const int32_t *rows, const int64_t *begin, const int32_t *lanes,
+                                  const int32_t *blk_start, BucketPos &bp) {
+  const int b = blockIdx.x;
+  const int c = (b < blk_start[1]) ? 0 : ((b < blk_start[2]) ? 1 : 2);
+  const int L = lanes[c];
+  const int per_block = NT / L;
+  const int64_t idx = begin[c] + (int64_t)(b - blk_start[c]) * per_block + threadIdx.x / L;
+  bp.lane = threadIdx.x % L;
+  bp.L = L;
+  if (idx >= begin[c + 1]) return false;
+  bp.row = rows[idx];
+  return true;
+}
+
+struct BucketArgs {
+  const int32_t *rows;
+  int64_t begin[4];
+  int32_t lanes[3];
+  int32_t blk_start[4];
+};
+
+BucketArgs make_bucket_args(const RowBuckets &bk) {
+  BucketArgs a;
+  a.rows = bk.d_rows;
+  int64_t nb = 0;
+  for (int c = 0; c < 3; ++c) {
+    a.begin[c] = bk.begin[c];
+    a.lanes[c] = bk.lanes[c];
+    a.blk_start[c] = (int32_t)nb;
+    const int64_t cnt = bk.begin[c + 1] - bk.begin[c];
+    const int per = NT / bk.lanes[c];
+    nb += (cnt + per - 1) / per;
+  }
+  a.begin[3] = bk.begin[3];
+  a.blk_start[3] = (int32_t)nb;
+  return a;
+}
+
+#define BUCKET_PREAMBLE                                                                        \
+  BucketPos bp;                                                                                \
+  if (!bucket_pos(ba.rows, ba.begin, ba.lanes, ba.blk_start, bp)) return;
+
+// ---- rectification -----------------------------------------------------------
+
+template <typename T>
+__global__ void k_copy(T *__restrict__ dst, const T *__restrict__ src, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) dst[i] = src[i];
+}
+
+template <typename T> __global__ void k_fill(T *__restrict__ dst, T val, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) dst[i] = val;
+}
+
+// One wave per (step, block): the block mean of `src` written to every row
+// of the block in `dst` (rectification and its adjoint are the same map).
+template <typename T>
+__global__ void k_block_mean(const RectDesc *__restrict__ rect, int32_t nrect, const T *__restrict__ src,
+                             T *__restrict__ dst, int64_t stride, int32_t K) {
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int64_t job = (int64_t)blockIdx.x * (NT / 64) + wave;
+  if (job >= (int64_t)nrect * K) return;
+  const int k = (int)(job / nrect);
+  const RectDesc d = rect[job % nrect];
+  const T *s = src + k * stride + d.row0;
+  T acc = 0;
+  for (int i = lane; i < d.rows; i += 64) acc += s[i];
+  acc = subwave_sum(acc, 64);
+  const T mean = acc / (T)d.rows;
+  T *o = dst + k * stride + d.row0;
+  for (int i = lane; i < d.rows; i += 64) o[i] = mean;
+}
+
+// ---- forward ----------------------------------------------------------------
+
+// Per column j of A (row j of A'):
+//   dg[j] = P_jj + sigma + sum_i rho_hat_i A_ij^2        (Jacobi preconditioner)
+//   xi[j] = sigma x_j - q_j + sum_i A_ij (y_i + rho_hat_i (b_i - s_i))
+template <typename T>
+__global__ __launch_bounds__(NT) void k_cols_pre(View<T> v, BucketArgs ba, const T *__restrict__ rho_hat,
+                                                 const T *__restrict__ x, const T *__restrict__ s,
+                                                 const T *__restrict__ y, T *__restrict__ dg,
+                                                 T *__restrict__ xi) {
+  BUCKET_PREAMBLE
+  const int64_t j = bp.row;
+  T a_xi = 0, a_d = 0;
+  for (int64_t k = v.At_rowptr[j] + bp.lane; k < v.At_rowptr[j + 1]; k += bp.L) {
+    const int32_t i = v.At_col[k];
+    const T a = v.At_val[k];
+    const T r = rho_hat[i];
+    a_xi += a * (y[i] + r * (v.b[i] - s[i]));
+    a_d += r * a * a;
+  }
+  a_xi = subwave_sum(a_xi, bp.L);
+  a_d = subwave_sum(a_d, bp.L);
+  if (bp.lane == 0) {
+    dg[j] = v.Pdiag[j] + v.sigma + a_d;
+    xi[j] = v.sigma * x[j] - v.q[j] + a_xi;
+  }
+}
+
+// Per row i: s~ = b - A x~;  s^ = alpha s~ + (1 - alpha) s;  v = s^ + y / rho_hat.
+// Zero rows: s+ = 0.  Nonneg rows: s+ = max(v, 0).  Both: y+ = y + rho_hat (s^ - s+).
+// SOC / PSD rows leave s^ and v for the cone kernels.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_rows_post(View<T> v, BucketArgs ba, const T *__restrict__ rho_hat,
+                                                  const T *__restrict__ alpha_k, const T *__restrict__ xt,
+                                                  const T *__restrict__ s, const T *__restrict__ y,
+                                                  T *__restrict__ st_out, T *__restrict__ sh_out,
+                                                  T *__restrict__ vv_out, T *__restrict__ s_new,
+                                                  T *__restrict__ y_new) {
+  BUCKET_PREAMBLE
+  const int64_t i = bp.row;
+  T ax = 0;
+  for (int64_t k = v.A_rowptr[i] + bp.lane; k < v.A_rowptr[i + 1]; k += bp.L) ax += v.A_val[k] * xt[v.A_col[k]];
+  ax = subwave_sum(ax, bp.L);
+  if (bp.lane != 0) return;
+  const T al = alpha_k[v.row_inst[i]];
+  const T r = rho_hat[i];
+  const T stl = v.b[i] - ax;
+  const T shat = al * stl + ((T)1 - al) * s[i];
+  const T vi = shat + y[i] / r;
+  st_out[i] = stl;
+  const uint8_t kind = v.row_kind[i];
+  if (kind == ROW_ZERO || kind == ROW_NONNEG) {
+    const T sp = (kind == ROW_ZERO) ? (T)0 : (vi > (T)0 ? vi : (T)0);
+    s_new[i] = sp;
+    y_new[i] = y[i] + r * (shat - sp);
+  } else {
+    sh_out[i] = shat;
+    vv_out[i] = vi;
+  }
+}
+
+// ---- backward ---------------------------------------------------------------
+
+// Per row: the cotangent reaching s+ after the y-update, gsn = gs+ - rho_hat gy+;
+// separable cones apply their Jacobian (zero: 0, nonneg: mask v > 0).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_bwd_rows_a(View<T> v, const T *__restrict__ rho_hat,
+                                                   const T *__restrict__ alpha_k, const T *__restrict__ stl,
+                                                   const T *__restrict__ s, const T *__restrict__ y,
+                                                   const T *__restrict__ gs_in, const T *__restrict__ gy_in,
+                                                   T *__restrict__ gsn, T *__restrict__ gv) {
+  const int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x;
+  if (i >= v.m_tot) return;
+  const T r = rho_hat[i];
+  const T g = gs_in[i] - r * gy_in[i];
+  const uint8_t kind = v.row_kind[i];
+  if (kind == ROW_ZERO) {
+    gv[i] = 0;
+  } else if (kind == ROW_NONNEG) {
+    const T al = alpha_k[v.row_inst[i]];
+    const T vi = al * stl[i] + ((T)1 - al) * s[i] + y[i] / r;
+    gv[i] = vi > (T)0 ? g : (T)0;
+  } else {
+    gsn[i] = g;
+  }
+}
+
+// v = s^ + y / rho_hat on every row (recomputed from the tape in the reverse pass).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_rows_v(View<T> v, const T *__restrict__ rho_hat,
+                                               const T *__restrict__ alpha_k, const T *__restrict__ stl,
+                                               const T *__restrict__ s, const T *__restrict__ y,
+                                               T *__restrict__ vv) {
+  const int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x;
+  if (i >= v.m_tot) return;
+  const T al = alpha_k[v.row_inst[i]];
+  vv[i] = al * stl[i] + ((T)1 - al) * s[i] + y[i] / rho_hat[i];
+}
+
+// Per row, once every cone has produced v-bar:
+//   gs^ = rho_hat gy+ + gv;  gy = gy+ + gv / rho_hat;
+//   grh = gy+ (s^ - s+) - gv y / rho_hat^2;  gs~ = alpha gs^;  gs = (1 - alpha) gs^.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_bwd_rows_b(View<T> v, const T *__restrict__ rho_hat,
+                                                   const T *__restrict__ alpha_k, const T *__restrict__ stl,
+                                                   const T *__restrict__ s, const T *__restrict__ y,
+                                                   const T *__restrict__ s_new, const T *__restrict__ gy_in,
+                                                   const T *__restrict__ gv, T *__restrict__ gsh,
+                                                   T *__restrict__ gst, T *__restrict__ gs_out,
+                                                   T *__restrict__ gy_out, T *__restrict__ grh) {
+  const int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x;
+  if (i >= v.m_tot) return;
+  const T r = rho_hat[i];
+  const T al = alpha_k[v.row_inst[i]];
+  const T shat = al * stl[i] + ((T)1 - al) * s[i];
+  const T gyp = gy_in[i];
+  const T g_v = gv[i];
+  const T g_sh = r * gyp + g_v;
+  gsh[i] = g_sh;
+  gy_out[i] = gyp + g_v / r;
+  grh[i] = gyp * (shat - s_new[i]) - g_v * y[i] / (r * r);
+  gst[i] = al * g_sh;
+  gs_out[i] = ((T)1 - al) * g_sh;
+}
+
+// Per column j: xt-bar = alpha gx+ - (A' gs~)_j ; also the Jacobi diagonal.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_bwd_cols(View<T> v, BucketArgs ba, const T *__restrict__ rho_hat,
+                                                 const T *__restrict__ alpha_k, const T *__restrict__ gst,
+                                                 const T *__restrict__ gx_in, T *__restrict__ gxt,
+                                                 T *__restrict__ dg) {
+  BUCKET_PREAMBLE
+  const int64_t j = bp.row;
+  T acc = 0, a_d = 0;
+  for (int64_t k = v.At_rowptr[j] + bp.lane; k < v.At_rowptr[j + 1]; k += bp.L) {
+    const int32_t i = v.At_col[k];
+    const T a = v.At_val[k];
+    acc += a * gst[i];
+    a_d += rho_hat[i] * a * a;
+  }
+  acc = subwave_sum(acc, bp.L);
+  a_d = subwave_sum(a_d, bp.L);
+  if (bp.lane == 0) {
+    const T al = alpha_k[v.col_inst[j]];
+    gxt[j] = al * gx_in[j] - acc;
+    dg[j] = v.Pdiag[j] + v.sigma + a_d;
+  }
+}
+
+// Per row, with w solving M w = xt-bar and g = A w:
+//   grh += g (s~ - s)   [matrix term -(A w)(A x~) plus right-hand-side term g (b - s)]
+//   gy += g ;  gs -= rho_hat g
+template <typename T>
+__global__ __launch_bounds__(NT) void k_bwd_rows_c(View<T> v, BucketArgs ba, const T *__restrict__ rho_hat,
+                                                   const T *__restrict__ w, const T *__restrict__ stl,
+                                                   const T *__restrict__ s, T *__restrict__ grh,
+                                                   T *__restrict__ gs_out, T *__restrict__ gy_out) {
+  BUCKET_PREAMBLE
+  const int64_t i = bp.row;
+  T g = 0;
+  for (int64_t k = v.A_rowptr[i] + bp.lane; k < v.A_rowptr[i + 1]; k += bp.L) g += v.A_val[k] * w[v.A_col[k]];
+  g = subwave_sum(g, bp.L);
+  if (bp.lane != 0) return;
+  grh[i] += g * (stl[i] - s[i]);
+  gy_out[i] += g;
+  gs_out[i] -= rho_hat[i] * g;
+}
+
+// Workgroup reduction with a fixed tree: deterministic.
+template <typename T> __device__ inline T block_sum(T v, T *red) {
+  v = subwave_sum(v, 64);
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  T tot = 0;
+  for (int w = 0; w < NT / 64; ++w) tot += red[w];
+  return tot;
+}
+
+// One workgroup per instance: alpha-bar = gs^'(s~ - s) + gx+'(x~ - x).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_alpha_reduce(View<T> v, const T *__restrict__ gsh,
+                                                     const T *__restrict__ stl, const T *__restrict__ s,
+                                                     const T *__restrict__ gx_in, const T *__restrict__ xt,
+                                                     const T *__restrict__ x, T *__restrict__ galpha_k) {
+  __shared__ T red[NT / 64];
+  const int b = blockIdx.x;
+  T acc = 0;
+  for (int64_t i = v.m_off[b] + threadIdx.x; i < v.m_off[b + 1]; i += NT) acc += gsh[i] * (stl[i] - s[i]);
+  for (int64_t j = v.n_off[b] + threadIdx.x; j < v.n_off[b + 1]; j += NT) acc += gx_in[j] * (xt[j] - x[j]);
+  const T tot = block_sum(acc, red);
+  if (threadIdx.x == 0) galpha_k[b] = tot;
+}
+
+// ---- residual loss ------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_loss_rp(View<T> v, BucketArgs ba, const T *__restrict__ x,
+                                                const T *__restrict__ s, T *__restrict__ rp) {
+  BUCKET_PREAMBLE
+  const int64_t i = bp.row;
+  T ax = 0;
+  for (int64_t k = v.A_rowptr[i] + bp.lane; k < v.A_rowptr[i + 1]; k += bp.L) ax += v.A_val[k] * x[v.A_col[k]];
+  ax = subwave_sum(ax, bp.L);
+  if (bp.lane == 0) rp[i] = ax + s[i] - v.b[i];
+}
+
+// rd_j = (P x)_j + q_j - (A' y)_j
+template <typename T>
+__global__ __launch_bounds__(NT) void k_loss_rd(View<T> v, BucketArgs ba, const T *__restrict__ x,
+                                                const T *__restrict__ y, T *__restrict__ rd) {
+  BUCKET_PREAMBLE
+  const int64_t j = bp.row;
+  T acc = 0;
+  for (int64_t k = v.At_rowptr[j] + bp.lane; k < v.At_rowptr[j + 1]; k += bp.L) acc -= v.At_val[k] * y[v.At_col[k]];
+  if (v.P_rowptr)
+    for (int64_t k = v.P_rowptr[j] + bp.lane; k < v.P_rowptr[j + 1]; k += bp.L) acc += v.P_val[k] * x[v.P_col[k]];
+  acc = subwave_sum(acc, bp.L);
+  if (bp.lane == 0) rd[j] = acc + v.q[j];
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_loss_reduce(View<T> v, const T *__restrict__ rp, const T *__restrict__ rd,
+                                                    T *__restrict__ loss) {
+  __shared__ T red[NT / 64];
+  const int b = blockIdx.x;
+  T acc = 0;
+  for (int64_t i = v.m_off[b] + threadIdx.x; i < v.m_off[b + 1]; i += NT) acc += rp[i] * rp[i];
+  for (int64_t j = v.n_off[b] + threadIdx.x; j < v.n_off[b + 1]; j += NT) acc += rd[j] * rd[j];
+  const T tot = block_sum(acc, red);
+  if (threadIdx.x == 0) loss[b] = tot;
+}
+
+// gx_j = 2 (A' rp)_j + 2 (P rd)_j
+template <typename T>
+__global__ __launch_bounds__(NT) void k_loss_gx(View<T> v, BucketArgs ba, const T *__restrict__ rp,
+                                                const T *__restrict__ rd, T *__restrict__ gx) {
+  BUCKET_PREAMBLE
+  const int64_t j = bp.row;
+  T acc = 0;
+  for (int64_t k = v.At_rowptr[j] + bp.lane; k < v.At_rowptr[j + 1]; k += bp.L) acc += v.At_val[k] * rp[v.At_col[k]];
+  if (v.P_rowptr)
+    for (int64_t k = v.P_rowptr[j] + bp.lane; k < v.P_rowptr[j + 1]; k += bp.L) acc += v.P_val[k] * rd[v.P_col[k]];
+  acc = subwave_sum(acc, bp.L);
+  if (bp.lane == 0) gx[j] = (T)2 * acc;
+}
+
+// gs_i = 2 rp_i ; gy_i = -2 (A rd)_i
+template <typename T>
+__global__ __launch_bounds__(NT) void k_loss_gsy(View<T> v, BucketArgs ba, const T *__restrict__ rp,
+                                                 const T *__restrict__ rd, T *__restrict__ gs,
+                                                 T *__restrict__ gy) {
+  BUCKET_PREAMBLE
+  const int64_t i = bp.row;
+  T acc = 0;
+  for (int64_t k = v.A_rowptr[i] + bp.lane; k < v.A_rowptr[i + 1]; k += bp.L) acc += v.A_val[k] * rd[v.A_col[k]];
+  acc = subwave_sum(acc, bp.L);
+  if (bp.lane == 0) {
+    if (gs) gs[i] = (T)2 * rp[i];
+    if (gy) gy[i] = (T)-2 * acc;
+  }
+}
+
+// ---- health check ---------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_nonfinite(View<T> v, const T *__restrict__ x, const T *__restrict__ s,
+                                                  const T *__restrict__ y, cosmo_stats *stats) {
+  const int b = blockIdx.x;
+  int bad = 0;
+  for (int64_t i = v.m_off[b] + threadIdx.x; i < v.m_off[b + 1]; i += NT)
+    bad |= !(isfinite(s[i]) && isfinite(y[i]));
+  for (int64_t j = v.n_off[b] + threadIdx.x; j < v.n_off[b + 1]; j += NT) bad |= !isfinite(x[j]);
+  bad = __syncthreads_or(bad);
+  if (threadIdx.x == 0 && bad) atomicOr(&stats[b].nonfinite, 1);
+}
+
+int64_t nblocks_bucket(const BucketArgs &a) { return a.blk_start[3]; }
+
+inline int grid_for(int64_t n) {
+  int64_t g = (n + NT - 1) / NT;
+  if (g < 1) g = 1;
+  if (g > 65535 * 16) g = 65535 * 16;
+  return (int)g;
+}
+
+}  // namespace
+
+template <typename T>
+void launch_rectify(const View<T> &v, const RectDesc *rect, int32_t nrect, const T *rho, T *rho_hat, int32_t K,
+                    hipStream_t st) {
+  const int64_t tot = (int64_t)K * v.m_tot;
+  k_copy<T><<<grid_for(tot), NT, 0, st>>>(rho_hat, rho, tot);
+  if (nrect > 0) {
+    const int64_t jobs = (int64_t)nrect * K;
+    k_block_mean<T><<<(int)((jobs + 3) / 4), NT, 0, st>>>(rect, nrect, rho, rho_hat, v.m_tot, K);
+  }
+}
+
+template <typename T>
+void launch_rect_adjoint(const View<T> &v, const RectDesc *rect, int32_t nrect, const T *grh, T *grho_k,
+                         hipStream_t st) {
+  k_copy<T><<<grid_for(v.m_tot), NT, 0, st>>>(grho_k, grh, v.m_tot);
+  if (nrect > 0) k_block_mean<T><<<(nrect + 3) / 4, NT, 0, st>>>(rect, nrect, grh, grho_k, v.m_tot, 1);
+}
+
+template <typename T>
+void launch_cols_pre(const View<T> &v, const RowBuckets &bk, const T *rho_hat, const T *x, const T *s, const T *y,
+                     T *dg, T *xi, hipStream_t st) {
+  BucketArgs a = make_bucket_args(bk);
+  if (nblocks_bucket(a) > 0) k_cols_pre<T><<<(int)nblocks_bucket(a), NT, 0, st>>>(v, a, rho_hat, x, s, y, dg, xi);
+}
+
+template <typename T>
+void launch_rows_post(const View<T> &v, const RowBuckets &bk, const T *rho_hat, const T *alpha_k, const T *xt,
+                      const T *s, const T *y, T *st_out, T *sh, T *vv, T *s_new, T *y_new, hipStream_t st) {
+  BucketArgs a = make_bucket_args(bk);
+  if (nblocks_bucket(a) > 0)
+    k_rows_post<T><<<(int)nblocks_bucket(a), NT, 0, st>>>(v, a, rho_hat, alpha_k, xt, s, y, st_out, sh, vv, s_new,
+                                                          y_new);
+}
+
+template <typename T>
+void launch_bwd_rows_a(const View<T> &v, const T *rho_hat, const T *alpha_k, const T *stl, const T *s, const T *y,
+                       const T *s_new, const T *gs_in, const T *gy_in, T *gsn, T *gv, hipStream_t st) {
+  (void)s_new;
+  k_bwd_rows_a<T><<<grid_for(v.m_tot), NT, 0, st>>>(v, rho_hat, alpha_k, stl, s, y, gs_in, gy_in, gsn, gv);
+}
+
+template <typename T>
+void launch_rows_v(const View<T> &v, const T *rho_hat, const T *alpha_k, const T *stl, const T *s, const T *y, T *vv,
+                   hipStream_t st) {
+  k_rows_v<T><<<grid_for(v.m_tot), NT, 0, st>>>(v, rho_hat, alpha_k, stl, s, y, vv);
+}
+
+template <typename T>
+void launch_bwd_rows_b(const View<T> &v, const T *rho_hat, const T *alpha_k, const T *stl, const T *s, const T *y,
+                       const T *s_new, const T *gy_in, const T *gv, T *gsh, T *gst, T *gs_out, T *gy_out, T *grh,
+                       hipStream_t st) {
+  k_bwd_rows_b<T><<<grid_for(v.m_tot), NT, 0, st>>>(v, rho_hat, alpha_k, stl, s, y, s_new, gy_in, gv, gsh, gst,
+                                                    gs_out, gy_out, grh);
+}
+
+template <typename T>
+void launch_bwd_cols(const View<T> &v, const RowBuckets &bk, const T *rho_hat, const T *alpha_k, const T *gst,
+                     const T *gx_in, T *gxt, T *dg, hipStream_t st) {
+  BucketArgs a = make_bucket_args(bk);
+  if (nblocks_bucket(a) > 0)
+    k_bwd_cols<T><<<(int)nblocks_bucket(a), NT, 0, st>>>(v, a, rho_hat, alpha_k, gst, gx_in, gxt, dg);
+}
+
+template <typename T>
+void launch_bwd_rows_c(const View<T> &v, const RowBuckets &bk, const T *rho_hat, const T *w, const T *stl,
+                       const T *s, T *grh, T *gs_out, T *gy_out, hipStream_t st) {
+  BucketArgs a = make_bucket_args(bk);
+  if (nblocks_bucket(a) > 0)
+    k_bwd_rows_c<T><<<(int)nblocks_bucket(a), NT, 0, st>>>(v, a, rho_hat, w, stl, s, grh, gs_out, gy_out);
+}
+
+template <typename T>
+void launch_alpha_reduce(const View<T> &v, const T *gsh, const T *stl, const T *s, const T *gx_in, const T *xt,
+                         const T *x, T *galpha_k, hipStream_t st) {
+  k_alpha_reduce<T><<<v.B, NT, 0, st>>>(v, gsh, stl, s, gx_in, xt, x, galpha_k);
+}
+
+template <typename T>
+void launch_loss(const View<T> &v, const RowBuckets &bkA, const RowBuckets &bkAt, const T *x, const T *s, const T *y,
+                 T *rp, T *rd, T *loss, T *gx, T *gs, T *gy, hipStream_t st) {
+  BucketArgs a = make_bucket_args(bkA), at = make_bucket_args(bkAt);
+  if (nblocks_bucket(a) > 0) k_loss_rp<T><<<(int)nblocks_bucket(a), NT, 0, st>>>(v, a, x, s, rp);
+  if (nblocks_bucket(at) > 0) k_loss_rd<T><<<(int)nblocks_bucket(at), NT, 0, st>>>(v, at, x, y, rd);
+  k_loss_reduce<T><<<v.B, NT, 0, st>>>(v, rp, rd, loss);
+  if (gx && nblocks_bucket(at) > 0) k_loss_gx<T><<<(int)nblocks_bucket(at), NT, 0, st>>>(v, at, rp, rd, gx);
+  if ((gs || gy) && nblocks_bucket(a) > 0) k_loss_gsy<T><<<(int)nblocks_bucket(a), NT, 0, st>>>(v, a, rp, rd, gs, gy);
+}
+
+template <typename T> void launch_copy(T *dst, const T *src, int64_t n, hipStream_t st) {
+  if (n > 0) k_copy<T><<<grid_for(n), NT, 0, st>>>(dst, src, n);
+}
+
+template <typename T> void launch_fill(T *dst, T val, int64_t n, hipStream_t st) {
+  if (n > 0) k_fill<T><<<grid_for(n), NT, 0, st>>>(dst, val, n);
+}
+
+template <typename T>
+void launch_nonfinite_check(const View<T> &v, const T *x, const T *s, const T *y, cosmo_stats *stats,
+                            hipStream_t st) {
+  if (stats) k_nonfinite<T><<<v.B, NT, 0, st>>>(v, x, s, y, stats);
+}
+
+#define INST(T)                                                                                                   \
+  template void launch_rectify<T>(const View<T> &, const RectDesc *, int32_t, const T *, T *, int32_t,          \
+                                  hipStream_t);                                                                 \
+  template void launch_rect_adjoint<T>(const View<T> &, const RectDesc *, int32_t, const T *, T *, hipStream_t); \
+  template void launch_cols_pre<T>(const View<T> &, const RowBuckets &, const T *, const T *, const T *,        \
+                                   const T *, T *, T *, hipStream_t);                                           \
+  template void launch_rows_post<T>(const View<T> &, const RowBuckets &, const T *, const T *, const T *,       \
+                                    const T *, const T *, T *, T *, T *, T *, T *, hipStream_t);                \
+  template void launch_bwd_rows_a<T>(const View<T> &, const T *, const T *, const T *, const T *, const T *,    \
+                                     const T *, const T *, const T *, T *, T *, hipStream_t);                   \
+  template void launch_rows_v<T>(const View<T> &, const T *, const T *, const T *, const T *, const T *, T *,  \
+                                 hipStream_t);                                                                \
+  template void launch_bwd_rows_b<T>(const View<T> &, const T *, const T *, const T *, const T *, const T *,    \
+                                     const T *, const T *, const T *, T *, T *, T *, T *, T *, hipStream_t);    \
+  template void launch_bwd_cols<T>(const View<T> &, const RowBuckets &, const T *, const T *, const T *,        \
+                                   const T *, T *, T *, hipStream_t);                                           \
+  template void launch_bwd_rows_c<T>(const View<T> &, const RowBuckets &, const T *, const T *, const T *,      \
+                                     const T *, T *, T *, T *, hipStream_t);                                    \
+  template void launch_alpha_reduce<T>(const View<T> &, const T *, const T *, const T *, const T *, const T *,  \
+                                       const T *, T *, hipStream_t);                                            \
+  template void launch_loss<T>(const View<T> &, const RowBuckets &, const RowBuckets &, const T *, const T *,   \
+                               const T *, T *, T *, T *, T *, T *, T *, hipStream_t);                           \
+  template void launch_copy<T>(T *, const T *, int64_t, hipStream_t);                                           \
+  template void launch_fill<T>(T *, T, int64_t, hipStream_t);                                                   \
+  template void launch_nonfinite_check<T>(const View<T> &, const T *, const T *, const T *, cosmo_stats *,      \
+                                          hipStream_t);
+
+INST(float)
+INST(double)
+
+}  // namespace cosmo

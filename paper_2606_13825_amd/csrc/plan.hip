@@ -1,0 +1,979 @@
+// Host side of the C ABI: argument validation, plan construction (transposed
+// CSR of A, cone tables, length-bucketed row lists, PSD blocks grouped by
+// order class), caller-owned workspace / tape layout, and the launch
+// sequences of the K-step forward and reverse passes.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "cosmo_internal.h"
+
+namespace cosmo {
+
+static thread_local std::string g_last_error;
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+
+}  // namespace cosmo
+
+using namespace cosmo;
+
+namespace {
+
+constexpr int32_t ABI_VERSION = 1;
+
+#define FAIL(code, msg)            \
+  do {                             \
+    set_last_error(msg);           \
+    return code;                   \
+  } while (0)
+
+#define HIPCHK(expr)                                                                              \
+  do {                                                                                            \
+    hipError_t e_ = (expr);                                                                       \
+    if (e_ != hipSuccess) {                                                                       \
+      set_last_error(std::string(#expr) + ": " + hipGetErrorString(e_));                          \
+      return COSMO_EHIP;                                                                          \
+    }                                                                                             \
+  } while (0)
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Order classes of the eigensolver launch configurations.
+inline int psd_class(int p) { return p <= 32 ? 0 : (p <= 64 ? 1 : (p <= 128 ? 2 : 3)); }
+
+struct DevBuf {
+  void *ptr = nullptr;
+  ~DevBuf() {
+    if (ptr) (void)hipFree(ptr);
+  }
+};
+
+struct ProfileSlot {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  size_t used = 0;
+};
+
+}  // namespace
+
+struct cosmo_plan {
+  cosmo_options opt{};
+  int32_t B = 0;
+  int64_t n_tot = 0, m_tot = 0;
+  std::vector<int64_t> n_off, m_off;
+  size_t esz = 4;
+  // caller-owned problem arrays
+  const int64_t *A_rowptr = nullptr;
+  const int32_t *A_col = nullptr;
+  const void *A_val = nullptr;
+  int64_t A_nnz = 0;
+  const int64_t *P_rowptr = nullptr;
+  const int32_t *P_col = nullptr;
+  const void *P_val = nullptr;
+  int64_t P_nnz = 0;
+  const void *q = nullptr, *b = nullptr;
+  // plan-owned device memory (one allocation, carved)
+  DevBuf mem;
+  int64_t *d_n_off = nullptr, *d_m_off = nullptr;
+  int64_t *d_At_rowptr = nullptr;
+  int32_t *d_At_col = nullptr;
+  void *d_At_val = nullptr;
+  void *d_Pdiag = nullptr;
+  uint8_t *d_row_kind = nullptr;
+  int32_t *d_row_inst = nullptr, *d_col_inst = nullptr;
+  int32_t *d_inst_LA = nullptr, *d_inst_LAt = nullptr;
+  SocDesc *d_soc = nullptr;
+  int32_t n_soc = 0;
+  PsdDesc *d_psd = nullptr;
+  int32_t n_psd = 0;
+  int32_t psd_cls_begin[5] = {0, 0, 0, 0, 0};
+  int32_t psd_cls_maxp[4] = {0, 0, 0, 0};
+  RectDesc *d_rect = nullptr;
+  int32_t n_rect = 0;
+  RowBuckets bkA, bkAt;
+  int64_t sum_p = 0, sum_p2 = 0, sum_p2_large = 0;
+  // layouts (element offsets of T)
+  struct {
+    size_t rho_hat, dg, xi, r, z, p, Mp, t, sh, vv, itA, itB, xt, st, U, lam, rp, rd, rs, total;
+  } fw{};
+  struct {
+    size_t slot, step, xt, st, lam, U, total;  // per-slot / per-step sizes and offsets inside a step
+  } tp{};
+  struct {
+    size_t rho_hat, gA, gB, gsn, gv, gsh, gst, grh, gxt, w, dg, r, z, p, Mp, t, vv, dk, zero, total;
+  } bw{};
+  bool profiling = false;
+  ProfileSlot prof[4];
+  ~cosmo_plan() {
+    for (auto &s : prof)
+      for (auto &e : s.ev) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+      }
+  }
+};
+
+namespace {
+
+template <typename T> View<T> make_view(const cosmo_plan *pl) {
+  View<T> v;
+  v.A_rowptr = pl->A_rowptr;
+  v.A_col = pl->A_col;
+  v.A_val = static_cast<const T *>(pl->A_val);
+  v.P_rowptr = pl->P_nnz > 0 ? pl->P_rowptr : nullptr;
+  v.P_col = pl->P_col;
+  v.P_val = static_cast<const T *>(pl->P_val);
+  v.q = static_cast<const T *>(pl->q);
+  v.b = static_cast<const T *>(pl->b);
+  v.At_rowptr = pl->d_At_rowptr;
+  v.At_col = pl->d_At_col;
+  v.At_val = static_cast<const T *>(pl->d_At_val);
+  v.Pdiag = static_cast<const T *>(pl->d_Pdiag);
+  v.row_kind = pl->d_row_kind;
+  v.row_inst = pl->d_row_inst;
+  v.col_inst = pl->d_col_inst;
+  v.n_off = pl->d_n_off;
+  v.m_off = pl->d_m_off;
+  v.inst_LA = pl->d_inst_LA;
+  v.inst_LAt = pl->d_inst_LAt;
+  v.B = pl->B;
+  v.n_tot = pl->n_tot;
+  v.m_tot = pl->m_tot;
+  v.sigma = (T)pl->opt.sigma;
+  return v;
+}
+
+// Profiling: events around launches of one kernel family.
+struct ProfScope {
+  cosmo_plan *pl;
+  int kind;
+  hipStream_t st;
+  hipEvent_t e1 = nullptr;
+  ProfScope(cosmo_plan *p, int k, hipStream_t s) : pl(p), kind(k), st(s) {
+    if (!pl->profiling) return;
+    ProfileSlot &sl = pl->prof[kind];
+    if (sl.used == sl.ev.size()) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+      sl.ev.emplace_back(a, b);
+    }
+    auto &pr = sl.ev[sl.used++];
+    (void)hipEventRecord(pr.first, st);
+    e1 = pr.second;
+  }
+  ~ProfScope() {
+    if (e1) (void)hipEventRecord(e1, st);
+  }
+};
+
+cosmo_status validate_options(const cosmo_options *o) {
+  if (!o) FAIL(COSMO_EINVAL, "options is NULL");
+  if (o->dtype != COSMO_F32 && o->dtype != COSMO_F64) FAIL(COSMO_EINVAL, "dtype must be COSMO_F32 or COSMO_F64");
+  if (o->K < 1) FAIL(COSMO_EINVAL, "K must be >= 1");
+  if (!(o->sigma > 0.0) || !std::isfinite(o->sigma)) FAIL(COSMO_EINVAL, "sigma must be finite and > 0");
+  if (!(o->cg_tol >= 0.0) || !std::isfinite(o->cg_tol)) FAIL(COSMO_EINVAL, "cg_tol must be finite and >= 0");
+  if (o->cg_max_iter < 1) FAIL(COSMO_EINVAL, "cg_max_iter must be >= 1");
+  if (o->eig_max_sweeps < 1) FAIL(COSMO_EINVAL, "eig_max_sweeps must be >= 1");
+  if (!(o->eig_tol >= 0.0) || !std::isfinite(o->eig_tol)) FAIL(COSMO_EINVAL, "eig_tol must be finite and >= 0");
+  if (o->eig_refine < 0 || o->eig_refine > 4) FAIL(COSMO_EINVAL, "eig_refine must be in [0, 4]");
+  return COSMO_OK;
+}
+
+// Host-only checks (no device access).
+cosmo_status validate_problem_host(const cosmo_problem *p, const cosmo_options *o) {
+  if (!p) FAIL(COSMO_EINVAL, "problem is NULL");
+  if (p->B < 1) FAIL(COSMO_EINVAL, "B must be >= 1");
+  if (!p->n_off || !p->m_off) FAIL(COSMO_EINVAL, "n_off / m_off must be non-NULL host arrays");
+  if (p->n_off[0] != 0 || p->m_off[0] != 0) FAIL(COSMO_EINVAL, "n_off[0] and m_off[0] must be 0");
+  for (int i = 0; i < p->B; ++i) {
+    if (p->n_off[i + 1] < p->n_off[i]) FAIL(COSMO_EINVAL, "n_off must be non-decreasing");
+    if (p->m_off[i + 1] <= p->m_off[i]) FAIL(COSMO_EINVAL, "every instance needs at least one row");
+  }
+  const int64_t n_tot = p->n_off[p->B], m_tot = p->m_off[p->B];
+  if (n_tot < 1) FAIL(COSMO_EINVAL, "no variables");
+  if (n_tot > INT32_MAX || m_tot > INT32_MAX) FAIL(COSMO_EUNSUPPORTED, "n_tot and m_tot must fit in int32");
+  if (!p->A_rowptr || !p->A_col || !p->A_val) FAIL(COSMO_EINVAL, "A arrays must be non-NULL");
+  if (p->A_nnz < 0) FAIL(COSMO_EINVAL, "A_nnz < 0");
+  if (p->P_nnz < 0) FAIL(COSMO_EINVAL, "P_nnz < 0");
+  if (p->P_nnz > 0 && (!p->P_rowptr || !p->P_col || !p->P_val)) FAIL(COSMO_EINVAL, "P arrays must be non-NULL");
+  if (!p->q || !p->b) FAIL(COSMO_EINVAL, "q and b must be non-NULL");
+  if (p->n_cones < 1 || !p->cone_kind || !p->cone_size) FAIL(COSMO_EINVAL, "cone list is empty or NULL");
+  // cones tile the rows, none straddles an instance
+  int64_t row = 0;
+  int inst = 0;
+  const int maxp = (o->dtype == COSMO_F32) ? COSMO_MAX_PSD_ORDER_F32 : COSMO_MAX_PSD_ORDER_F64;
+  for (int c = 0; c < p->n_cones; ++c) {
+    const int k = p->cone_kind[c], sz = p->cone_size[c];
+    if (k < COSMO_CONE_ZERO || k > COSMO_CONE_PSD) FAIL(COSMO_EINVAL, "unknown cone kind at index " + std::to_string(c));
+    if (sz < 1) FAIL(COSMO_EINVAL, "cone size must be >= 1 at index " + std::to_string(c));
+    if (k == COSMO_CONE_PSD && sz > maxp)
+      FAIL(COSMO_EUNSUPPORTED, "PSD order " + std::to_string(sz) + " exceeds the supported maximum " + std::to_string(maxp));
+    const int64_t rows = (k == COSMO_CONE_PSD) ? (int64_t)sz * (sz + 1) / 2 : sz;
+    while (inst < p->B && row >= p->m_off[inst + 1]) ++inst;
+    if (row + rows > p->m_off[inst + 1]) FAIL(COSMO_EINVAL, "cone " + std::to_string(c) + " straddles an instance boundary");
+    row += rows;
+  }
+  if (row != m_tot) FAIL(COSMO_EINVAL, "cone rows sum to " + std::to_string(row) + " but m_tot is " + std::to_string(m_tot));
+  return COSMO_OK;
+}
+
+int pow2_lanes(double avg) {
+  int L = 1;
+  while (L < 64 && L < avg) L <<= 1;
+  return L;
+}
+
+void build_buckets(const std::vector<int64_t> &rowptr, int64_t nrows, std::vector<int32_t> &rows_out,
+                   RowBuckets &bk) {
+  std::vector<int32_t> cls[3];
+  for (int64_t r = 0; r < nrows; ++r) {
+    const int64_t len = rowptr[r + 1] - rowptr[r];
+    cls[len <= 4 ? 0 : (len <= 48 ? 1 : 2)].push_back((int32_t)r);
+  }
+  rows_out.clear();
+  for (int c = 0; c < 3; ++c) {
+    bk.begin[c] = (int64_t)rows_out.size();
+    rows_out.insert(rows_out.end(), cls[c].begin(), cls[c].end());
+  }
+  bk.begin[3] = (int64_t)rows_out.size();
+  bk.lanes[0] = 1;
+  bk.lanes[1] = 8;
+  bk.lanes[2] = 64;
+}
+
+template <typename T>
+cosmo_status build_plan(cosmo_plan *pl, const cosmo_problem *p) {
+  const int64_t n = pl->n_tot, m = pl->m_tot, nnz = p->A_nnz;
+  // --- copy A (and P) to the host
+  std::vector<int64_t> rp(m + 1);
+  HIPCHK(hipMemcpy(rp.data(), p->A_rowptr, (m + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+  if (rp[0] != 0 || rp[m] != nnz) FAIL(COSMO_EINVAL, "A_rowptr[0] must be 0 and A_rowptr[m_tot] must equal A_nnz");
+  for (int64_t i = 0; i < m; ++i)
+    if (rp[i + 1] < rp[i]) FAIL(COSMO_EINVAL, "A_rowptr must be non-decreasing");
+  std::vector<int32_t> col(nnz);
+  std::vector<T> val(nnz);
+  if (nnz > 0) {
+    HIPCHK(hipMemcpy(col.data(), p->A_col, nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(val.data(), p->A_val, nnz * sizeof(T), hipMemcpyDeviceToHost));
+  }
+  for (int b = 0; b < pl->B; ++b)
+    for (int64_t i = pl->m_off[b]; i < pl->m_off[b + 1]; ++i)
+      for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+        if (col[k] < pl->n_off[b] || col[k] >= pl->n_off[b + 1])
+          FAIL(COSMO_EINVAL, "A has an entry outside its instance's column block (row " + std::to_string(i) + ")");
+  std::vector<T> pdiag(n, (T)0);
+  std::vector<int64_t> prp;
+  if (p->P_nnz > 0) {
+    prp.resize(n + 1);
+    std::vector<int32_t> pc(p->P_nnz);
+    std::vector<T> pv(p->P_nnz);
+    HIPCHK(hipMemcpy(prp.data(), p->P_rowptr, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+    if (prp[0] != 0 || prp[n] != p->P_nnz) FAIL(COSMO_EINVAL, "P_rowptr[0] must be 0 and P_rowptr[n_tot] must equal P_nnz");
+    HIPCHK(hipMemcpy(pc.data(), p->P_col, p->P_nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(pv.data(), p->P_val, p->P_nnz * sizeof(T), hipMemcpyDeviceToHost));
+    for (int b = 0; b < pl->B; ++b)
+      for (int64_t j = pl->n_off[b]; j < pl->n_off[b + 1]; ++j) {
+        if (prp[j + 1] < prp[j]) FAIL(COSMO_EINVAL, "P_rowptr must be non-decreasing");
+        for (int64_t k = prp[j]; k < prp[j + 1]; ++k) {
+          if (pc[k] < pl->n_off[b] || pc[k] >= pl->n_off[b + 1])
+            FAIL(COSMO_EINVAL, "P has an entry outside its instance's block");
+          if (pc[k] == j) pdiag[j] += pv[k];
+        }
+      }
+  } else {
+    prp.assign(n + 1, 0);
+  }
+  // --- transpose of A (counting sort by column; rows stay increasing)
+  std::vector<int64_t> trp(n + 1, 0);
+  for (int64_t k = 0; k < nnz; ++k) trp[col[k] + 1]++;
+  for (int64_t j = 0; j < n; ++j) trp[j + 1] += trp[j];
+  std::vector<int64_t> fill(trp.begin(), trp.end() - 1);
+  std::vector<int32_t> tcol(nnz);
+  std::vector<T> tval(nnz);
+  for (int64_t i = 0; i < m; ++i)
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+      const int64_t dst = fill[col[k]]++;
+      tcol[dst] = (int32_t)i;
+      tval[dst] = val[k];
+    }
+  // --- row / column metadata
+  std::vector<uint8_t> rkind(m);
+  std::vector<int32_t> rinst(m), cinst(n);
+  for (int b = 0; b < pl->B; ++b) {
+    for (int64_t i = pl->m_off[b]; i < pl->m_off[b + 1]; ++i) rinst[i] = b;
+    for (int64_t j = pl->n_off[b]; j < pl->n_off[b + 1]; ++j) cinst[j] = b;
+  }
+  std::vector<SocDesc> socs;
+  std::vector<PsdDesc> psds;
+  std::vector<RectDesc> rects;
+  int64_t row = 0;
+  for (int c = 0; c < p->n_cones; ++c) {
+    const int k = p->cone_kind[c], sz = p->cone_size[c];
+    const int64_t rows = (k == COSMO_CONE_PSD) ? (int64_t)sz * (sz + 1) / 2 : sz;
+    for (int64_t i = row; i < row + rows; ++i) rkind[i] = (uint8_t)k;
+    if (k == COSMO_CONE_SOC) {
+      socs.push_back({row, sz, rinst[row]});
+      rects.push_back({row, (int32_t)rows, 0});
+    } else if (k == COSMO_CONE_PSD) {
+      psds.push_back({row, 0, 0, sz, rinst[row]});
+      rects.push_back({row, (int32_t)rows, 0});
+    }
+    row += rows;
+  }
+  // PSD blocks: eigen storage offsets in list order, then grouped by order
+  // class with the largest blocks first inside each class.
+  int64_t uo = 0, lo = 0, large = 0;
+  for (auto &d : psds) {
+    d.uoff = uo;
+    d.loff = lo;
+    uo += (int64_t)d.p * d.p;
+    lo += d.p;
+    if ((size_t)3 * d.p * d.p * sizeof(T) > 163840 - 4096) large += (int64_t)d.p * d.p;
+  }
+  pl->sum_p2 = uo;
+  pl->sum_p = lo;
+  pl->sum_p2_large = uo;   // DK scratch indexed by uoff
+  (void)large;
+  std::stable_sort(psds.begin(), psds.end(), [](const PsdDesc &a, const PsdDesc &b) {
+    const int ca = psd_class(a.p), cb = psd_class(b.p);
+    if (ca != cb) return ca < cb;
+    return a.p > b.p;
+  });
+  for (int c = 0; c < 5; ++c) pl->psd_cls_begin[c] = 0;
+  for (int c = 0; c < 4; ++c) pl->psd_cls_maxp[c] = 0;
+  {
+    int idx = 0;
+    for (int c = 0; c < 4; ++c) {
+      pl->psd_cls_begin[c] = idx;
+      while (idx < (int)psds.size() && psd_class(psds[idx].p) == c) {
+        pl->psd_cls_maxp[c] = std::max(pl->psd_cls_maxp[c], psds[idx].p);
+        ++idx;
+      }
+    }
+    pl->psd_cls_begin[4] = idx;
+  }
+  pl->n_soc = (int32_t)socs.size();
+  pl->n_psd = (int32_t)psds.size();
+  pl->n_rect = (int32_t)rects.size();
+  // row buckets and per-instance lane widths
+  std::vector<int32_t> rowsA, rowsAt;
+  build_buckets(rp, m, rowsA, pl->bkA);
+  build_buckets(trp, n, rowsAt, pl->bkAt);
+  std::vector<int32_t> LA(pl->B), LAt(pl->B);
+  for (int b = 0; b < pl->B; ++b) {
+    const int64_t r0 = pl->m_off[b], r1 = pl->m_off[b + 1], c0 = pl->n_off[b], c1 = pl->n_off[b + 1];
+    const double annz = (double)(rp[r1] - rp[r0]) / std::max<int64_t>(1, r1 - r0);
+    const double tnnz = (double)(trp[c1] - trp[c0] + prp[c1] - prp[c0]) / std::max<int64_t>(1, c1 - c0);
+    LA[b] = pow2_lanes(annz);
+    LAt[b] = pow2_lanes(tnnz);
+  }
+  // --- one device allocation for everything the plan owns
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  const size_t o_noff = take((pl->B + 1) * sizeof(int64_t)), o_moff = take((pl->B + 1) * sizeof(int64_t));
+  const size_t o_trp = take((n + 1) * sizeof(int64_t)), o_tcol = take(std::max<int64_t>(nnz, 1) * sizeof(int32_t));
+  const size_t o_tval = take(std::max<int64_t>(nnz, 1) * sizeof(T)), o_pdiag = take(n * sizeof(T));
+  const size_t o_rkind = take(m), o_rinst = take(m * sizeof(int32_t)), o_cinst = take(n * sizeof(int32_t));
+  const size_t o_LA = take(pl->B * sizeof(int32_t)), o_LAt = take(pl->B * sizeof(int32_t));
+  const size_t o_soc = take(std::max<size_t>(socs.size(), 1) * sizeof(SocDesc));
+  const size_t o_psd = take(std::max<size_t>(psds.size(), 1) * sizeof(PsdDesc));
+  const size_t o_rect = take(std::max<size_t>(rects.size(), 1) * sizeof(RectDesc));
+  const size_t o_bA = take(std::max<size_t>(rowsA.size(), 1) * sizeof(int32_t));
+  const size_t o_bAt = take(std::max<size_t>(rowsAt.size(), 1) * sizeof(int32_t));
+  if (hipMalloc(&pl->mem.ptr, off) != hipSuccess) {
+    pl->mem.ptr = nullptr;
+    FAIL(COSMO_ENOMEM, "plan allocation of " + std::to_string(off) + " bytes failed");
+  }
+  char *base = static_cast<char *>(pl->mem.ptr);
+  auto up = [&](size_t o, const void *src, size_t bytes) -> hipError_t {
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpy(base + o, src, bytes, hipMemcpyHostToDevice);
+  };
+  HIPCHK(up(o_noff, pl->n_off.data(), (pl->B + 1) * sizeof(int64_t)));
+  HIPCHK(up(o_moff, pl->m_off.data(), (pl->B + 1) * sizeof(int64_t)));
+  HIPCHK(up(o_trp, trp.data(), (n + 1) * sizeof(int64_t)));
+  HIPCHK(up(o_tcol, tcol.data(), nnz * sizeof(int32_t)));
+  HIPCHK(up(o_tval, tval.data(), nnz * sizeof(T)));
+  HIPCHK(up(o_pdiag, pdiag.data(), n * sizeof(T)));
+  HIPCHK(up(o_rkind, rkind.data(), m));
+  HIPCHK(up(o_rinst, rinst.data(), m * sizeof(int32_t)));
+  HIPCHK(up(o_cinst, cinst.data(), n * sizeof(int32_t)));
+  HIPCHK(up(o_LA, LA.data(), pl->B * sizeof(int32_t)));
+  HIPCHK(up(o_LAt, LAt.data(), pl->B * sizeof(int32_t)));
+  HIPCHK(up(o_soc, socs.data(), socs.size() * sizeof(SocDesc)));
+  HIPCHK(up(o_psd, psds.data(), psds.size() * sizeof(PsdDesc)));
+  HIPCHK(up(o_rect, rects.data(), rects.size() * sizeof(RectDesc)));
+  HIPCHK(up(o_bA, rowsA.data(), rowsA.size() * sizeof(int32_t)));
+  HIPCHK(up(o_bAt, rowsAt.data(), rowsAt.size() * sizeof(int32_t)));
+  pl->d_n_off = reinterpret_cast<int64_t *>(base + o_noff);
+  pl->d_m_off = reinterpret_cast<int64_t *>(base + o_moff);
+  pl->d_At_rowptr = reinterpret_cast<int64_t *>(base + o_trp);
+  pl->d_At_col = reinterpret_cast<int32_t *>(base + o_tcol);
+  pl->d_At_val = base + o_tval;
+  pl->d_Pdiag = base + o_pdiag;
+  pl->d_row_kind = reinterpret_cast<uint8_t *>(base + o_rkind);
+  pl->d_row_inst = reinterpret_cast<int32_t *>(base + o_rinst);
+  pl->d_col_inst = reinterpret_cast<int32_t *>(base + o_cinst);
+  pl->d_inst_LA = reinterpret_cast<int32_t *>(base + o_LA);
+  pl->d_inst_LAt = reinterpret_cast<int32_t *>(base + o_LAt);
+  pl->d_soc = reinterpret_cast<SocDesc *>(base + o_soc);
+  pl->d_psd = reinterpret_cast<PsdDesc *>(base + o_psd);
+  pl->d_rect = reinterpret_cast<RectDesc *>(base + o_rect);
+  pl->bkA.d_rows = reinterpret_cast<int32_t *>(base + o_bA);
+  pl->bkAt.d_rows = reinterpret_cast<int32_t *>(base + o_bAt);
+  return COSMO_OK;
+}
+
+// Element-offset layouts of the caller-owned buffers.
+void build_layouts(cosmo_plan *pl) {
+  const size_t n = pl->n_tot, m = pl->m_tot, K = pl->opt.K;
+  const size_t A = 64;   // 256-byte alignment for float, 512 for double
+  size_t o = 0;
+  auto take = [&](size_t elems) {
+    const size_t r = o;
+    o = align_up(o + std::max<size_t>(elems, 1), A);
+    return r;
+  };
+  auto &f = pl->fw;
+  f.rho_hat = take(K * m);
+  f.dg = take(n);
+  f.xi = take(n);
+  f.r = take(n);
+  f.z = take(n);
+  f.p = take(n);
+  f.Mp = take(n);
+  f.t = take(m);
+  f.sh = take(m);
+  f.vv = take(m);
+  f.itA = take(n + 2 * m);
+  f.itB = take(n + 2 * m);
+  f.xt = take(n);
+  f.st = take(m);
+  f.U = take(pl->sum_p2);
+  f.lam = take(pl->sum_p);
+  f.rp = take(m);
+  f.rd = take(n);
+  f.rs = take(3 * (size_t)pl->sum_p2 * 8 / pl->esz);   // float64 eigen-refinement scratch
+  f.total = o;
+  // tape: slot k (x, s, y) for k = 0..K, then per step (x~, s~, lam, U)
+  auto &t = pl->tp;
+  t.slot = align_up(n, A) + 2 * align_up(m, A);
+  t.xt = 0;
+  t.st = align_up(n, A);
+  t.lam = t.st + align_up(m, A);
+  t.U = t.lam + align_up(std::max<int64_t>(pl->sum_p, 1), A);
+  t.step = t.U + align_up(std::max<int64_t>(pl->sum_p2, 1), A);
+  t.total = (K + 1) * t.slot + K * t.step;
+  auto &w = pl->bw;
+  o = 0;
+  w.rho_hat = take(K * m);
+  w.gA = take(n + 2 * m);
+  w.gB = take(n + 2 * m);
+  w.gsn = take(m);
+  w.gv = take(m);
+  w.gsh = take(m);
+  w.gst = take(m);
+  w.grh = take(m);
+  w.gxt = take(n);
+  w.w = take(n);
+  w.dg = take(n);
+  w.r = take(n);
+  w.z = take(n);
+  w.p = take(n);
+  w.Mp = take(n);
+  w.t = take(m);
+  w.vv = take(m);
+  w.dk = take(pl->sum_p2_large);
+  w.total = o;
+}
+
+size_t slot_x(const cosmo_plan *pl, size_t k) { return k * pl->tp.slot; }
+size_t slot_s(const cosmo_plan *pl, size_t k) { return k * pl->tp.slot + align_up(pl->n_tot, 64); }
+size_t slot_y(const cosmo_plan *pl, size_t k) {
+  return k * pl->tp.slot + align_up(pl->n_tot, 64) + align_up(pl->m_tot, 64);
+}
+size_t step_base(const cosmo_plan *pl, size_t k) { return (pl->opt.K + 1) * pl->tp.slot + k * pl->tp.step; }
+
+template <typename T>
+void launch_psd_classes(cosmo_plan *pl, const T *rho_hat, const T *vv, const T *sh, const T *y, T *s_new, T *y_new,
+                        T *U, T *lam, double *rscratch, cosmo_stats *stats, hipStream_t st) {
+  ProfScope ps(pl, 0, st);
+  const bool refine = pl->opt.dtype == COSMO_F32 && pl->opt.eig_refine > 0;
+  for (int c = 0; c < 4; ++c) {
+    const int n = pl->psd_cls_begin[c + 1] - pl->psd_cls_begin[c];
+    if (n == 0) continue;
+    PsdLaunchCfg cfg{pl->opt.eig_max_sweeps, pl->opt.eig_tol, refine ? pl->opt.eig_refine : 0, pl->psd_cls_maxp[c]};
+    launch_psd_step<T>(pl->d_psd + pl->psd_cls_begin[c], n, cfg, rho_hat, vv, sh, y, s_new, y_new, U, lam,
+                       refine ? rscratch : nullptr, stats, st);
+  }
+}
+
+template <typename T>
+void launch_dk_classes(cosmo_plan *pl, const T *U, const T *lam, const T *g, T *out, T *scratch, hipStream_t st) {
+  ProfScope ps(pl, 1, st);
+  for (int c = 0; c < 4; ++c) {
+    const int n = pl->psd_cls_begin[c + 1] - pl->psd_cls_begin[c];
+    if (n == 0) continue;
+    launch_psd_vjp<T>(pl->d_psd + pl->psd_cls_begin[c], n, pl->psd_cls_maxp[c], U, lam, g, out, scratch, st);
+  }
+}
+
+template <typename T>
+cosmo_status forward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T *x0, const T *s0, const T *y0, T *xK,
+                          T *sK, T *yK, T *tape, T *ws, cosmo_stats *stats, hipStream_t st) {
+  const View<T> v = make_view<T>(pl);
+  const int64_t n = pl->n_tot, m = pl->m_tot;
+  const int K = pl->opt.K;
+  auto &f = pl->fw;
+  T *rho_hat = ws + f.rho_hat;
+  launch_rectify<T>(v, pl->d_rect, pl->n_rect, rho, rho_hat, K, st);
+  auto X = [&](int k) -> T * { return tape ? tape + slot_x(pl, k) : ws + ((k & 1) ? f.itB : f.itA); };
+  auto S = [&](int k) -> T * {
+    return tape ? tape + slot_s(pl, k) : ws + ((k & 1) ? f.itB : f.itA) + align_up(n, 64);
+  };
+  auto Y = [&](int k) -> T * {
+    return tape ? tape + slot_y(pl, k) : ws + ((k & 1) ? f.itB : f.itA) + align_up(n, 64) + align_up(m, 64);
+  };
+  auto XT = [&](int k) -> T * { return tape ? tape + step_base(pl, k) + pl->tp.xt : ws + f.xt; };
+  auto ST = [&](int k) -> T * { return tape ? tape + step_base(pl, k) + pl->tp.st : ws + f.st; };
+  auto LAM = [&](int k) -> T * { return tape ? tape + step_base(pl, k) + pl->tp.lam : ws + f.lam; };
+  auto UU = [&](int k) -> T * { return tape ? tape + step_base(pl, k) + pl->tp.U : ws + f.U; };
+  if (x0) launch_copy<T>(X(0), x0, n, st); else launch_fill<T>(X(0), (T)0, n, st);
+  if (s0) launch_copy<T>(S(0), s0, m, st); else launch_fill<T>(S(0), (T)0, m, st);
+  if (y0) launch_copy<T>(Y(0), y0, m, st); else launch_fill<T>(Y(0), (T)0, m, st);
+  for (int k = 0; k < K; ++k) {
+    const T *rh = rho_hat + (size_t)k * m;
+    const T *al = alpha + (size_t)k * pl->B;
+    T *x = X(k), *s = S(k), *y = Y(k), *xn = X(k + 1), *sn = S(k + 1), *yn = Y(k + 1);
+    T *xt = XT(k);
+    // warm start of the CG: previous x~ (first step: x^0)
+    if (tape) launch_copy<T>(xt, k == 0 ? x : XT(k - 1), n, st);
+    else if (k == 0) launch_copy<T>(xt, x, n, st);
+    {
+      ProfScope ps(pl, 3, st);
+      launch_cols_pre<T>(v, pl->bkAt, rh, x, s, y, ws + f.dg, ws + f.xi, st);
+    }
+    {
+      ProfScope ps(pl, 2, st);
+      launch_pcg<T>(v, rh, ws + f.dg, ws + f.xi, xt, ws + f.r, ws + f.z, ws + f.p, ws + f.Mp, ws + f.t,
+                    pl->opt.cg_tol, pl->opt.cg_max_iter, al, x, xn, nullptr, nullptr, 0, stats, st);
+    }
+    {
+      ProfScope ps(pl, 3, st);
+      launch_rows_post<T>(v, pl->bkA, rh, al, xt, s, y, ST(k), ws + f.sh, ws + f.vv, sn, yn, st);
+    }
+    launch_soc_step<T>(pl->d_soc, pl->n_soc, rh, ws + f.vv, ws + f.sh, y, sn, yn, st);
+    launch_psd_classes<T>(pl, rh, ws + f.vv, ws + f.sh, y, sn, yn, UU(k), LAM(k),
+                          reinterpret_cast<double *>(ws + f.rs), stats, st);
+  }
+  launch_nonfinite_check<T>(v, X(K), S(K), Y(K), stats, st);
+  if (xK) launch_copy<T>(xK, X(K), n, st);
+  if (sK) launch_copy<T>(sK, S(K), m, st);
+  if (yK) launch_copy<T>(yK, Y(K), m, st);
+  HIPCHK(hipGetLastError());
+  return COSMO_OK;
+}
+
+template <typename T>
+cosmo_status backward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T *tape, const T *gxK, const T *gsK,
+                           const T *gyK, T *grho, T *galpha, T *gx0, T *gs0, T *gy0, T *ws, cosmo_stats *stats,
+                           hipStream_t st) {
+  const View<T> v = make_view<T>(pl);
+  const int64_t n = pl->n_tot, m = pl->m_tot;
+  const int K = pl->opt.K;
+  auto &w = pl->bw;
+  T *rho_hat = ws + w.rho_hat;
+  launch_rectify<T>(v, pl->d_rect, pl->n_rect, rho, rho_hat, K, st);
+  const size_t on = 0, os = align_up(n, 64), oy = align_up(n, 64) + align_up(m, 64);
+  T *gA = ws + w.gA, *gB = ws + w.gB;
+  if (gxK) launch_copy<T>(gA + on, gxK, n, st); else launch_fill<T>(gA + on, (T)0, n, st);
+  if (gsK) launch_copy<T>(gA + os, gsK, m, st); else launch_fill<T>(gA + os, (T)0, m, st);
+  if (gyK) launch_copy<T>(gA + oy, gyK, m, st); else launch_fill<T>(gA + oy, (T)0, m, st);
+  launch_fill<T>(ws + w.w, (T)0, n, st);
+  launch_fill<T>(ws + w.gsn, (T)0, m, st);
+  T *scratch = ws + w.dk;
+  for (int k = K - 1; k >= 0; --k) {
+    const T *rh = rho_hat + (size_t)k * m;
+    const T *al = alpha + (size_t)k * pl->B;
+    const T *x = tape + slot_x(pl, k), *s = tape + slot_s(pl, k), *y = tape + slot_y(pl, k);
+    const T *sn = tape + slot_s(pl, k + 1);
+    const T *xt = tape + step_base(pl, k) + pl->tp.xt, *stl = tape + step_base(pl, k) + pl->tp.st;
+    const T *lam = tape + step_base(pl, k) + pl->tp.lam, *U = tape + step_base(pl, k) + pl->tp.U;
+    T *gx_in = gA + on, *gs_in = gA + os, *gy_in = gA + oy;
+    T *gx_out = gB + on, *gs_out = gB + os, *gy_out = gB + oy;
+    {
+      ProfScope ps(pl, 3, st);
+      launch_bwd_rows_a<T>(v, rh, al, stl, s, y, sn, gs_in, gy_in, ws + w.gsn, ws + w.gv, st);
+    }
+    if (pl->n_soc > 0 || pl->n_psd > 0) {
+      // v = s^ + y / rho_hat on cone rows, recomputed from the tape
+      launch_rows_v<T>(v, rh, al, stl, s, y, ws + w.vv, st);
+    }
+    launch_soc_vjp<T>(pl->d_soc, pl->n_soc, ws + w.vv, ws + w.gsn, ws + w.gv, st);
+    launch_dk_classes<T>(pl, U, lam, ws + w.gsn, ws + w.gv, scratch, st);
+    {
+      ProfScope ps(pl, 3, st);
+      launch_bwd_rows_b<T>(v, rh, al, stl, s, y, sn, gy_in, ws + w.gv, ws + w.gsh, ws + w.gst, gs_out, gy_out,
+                           ws + w.grh, st);
+      launch_bwd_cols<T>(v, pl->bkAt, rh, al, ws + w.gst, gx_in, ws + w.gxt, ws + w.dg, st);
+    }
+    {
+      ProfScope ps(pl, 2, st);
+      launch_pcg<T>(v, rh, ws + w.dg, ws + w.gxt, ws + w.w, ws + w.r, ws + w.z, ws + w.p, ws + w.Mp, ws + w.t,
+                    pl->opt.cg_tol, pl->opt.cg_max_iter, al, nullptr, nullptr, gx_in, gx_out, 1, stats, st);
+    }
+    {
+      ProfScope ps(pl, 3, st);
+      launch_bwd_rows_c<T>(v, pl->bkA, rh, ws + w.w, stl, s, ws + w.grh, gs_out, gy_out, st);
+    }
+    if (grho) launch_rect_adjoint<T>(v, pl->d_rect, pl->n_rect, ws + w.grh, grho + (size_t)k * m, st);
+    if (galpha) launch_alpha_reduce<T>(v, ws + w.gsh, stl, s, gx_in, xt, x, galpha + (size_t)k * pl->B, st);
+    std::swap(gA, gB);
+  }
+  if (gx0) launch_copy<T>(gx0, gA + on, n, st);
+  if (gs0) launch_copy<T>(gs0, gA + os, m, st);
+  if (gy0) launch_copy<T>(gy0, gA + oy, m, st);
+  HIPCHK(hipGetLastError());
+  return COSMO_OK;
+}
+
+cosmo_status check_plan(const cosmo_plan *pl) {
+  if (!pl) FAIL(COSMO_EINVAL, "plan is NULL");
+  return COSMO_OK;
+}
+
+}  // namespace
+
+// ============================ C ABI ============================================
+
+extern "C" {
+
+const char *cosmo_status_string(cosmo_status s) {
+  switch (s) {
+    case COSMO_OK: return "COSMO_OK";
+    case COSMO_EINVAL: return "COSMO_EINVAL: invalid argument";
+    case COSMO_ENOMEM: return "COSMO_ENOMEM: allocation failed";
+    case COSMO_EHIP: return "COSMO_EHIP: HIP runtime error";
+    case COSMO_EUNSUPPORTED: return "COSMO_EUNSUPPORTED: outside the implemented envelope";
+  }
+  return "unknown cosmo_status";
+}
+
+const char *cosmo_last_error(void) { return cosmo::g_last_error.c_str(); }
+
+int32_t cosmo_abi_version(void) { return ABI_VERSION; }
+
+cosmo_status cosmo_plan_create(cosmo_plan **plan, const cosmo_problem *prob, const cosmo_options *opt) {
+  if (!plan) FAIL(COSMO_EINVAL, "plan out-pointer is NULL");
+  *plan = nullptr;
+  cosmo_status s = validate_options(opt);
+  if (s != COSMO_OK) return s;
+  s = validate_problem_host(prob, opt);
+  if (s != COSMO_OK) return s;
+  cosmo_plan *pl = new (std::nothrow) cosmo_plan();
+  if (!pl) FAIL(COSMO_ENOMEM, "host allocation failed");
+  pl->opt = *opt;
+  pl->B = prob->B;
+  pl->n_off.assign(prob->n_off, prob->n_off + prob->B + 1);
+  pl->m_off.assign(prob->m_off, prob->m_off + prob->B + 1);
+  pl->n_tot = pl->n_off.back();
+  pl->m_tot = pl->m_off.back();
+  pl->esz = opt->dtype == COSMO_F32 ? 4 : 8;
+  pl->A_rowptr = prob->A_rowptr;
+  pl->A_col = prob->A_col;
+  pl->A_val = prob->A_val;
+  pl->A_nnz = prob->A_nnz;
+  pl->P_rowptr = prob->P_rowptr;
+  pl->P_col = prob->P_col;
+  pl->P_val = prob->P_val;
+  pl->P_nnz = prob->P_nnz;
+  pl->q = prob->q;
+  pl->b = prob->b;
+  s = (opt->dtype == COSMO_F32) ? build_plan<float>(pl, prob) : build_plan<double>(pl, prob);
+  if (s != COSMO_OK) {
+    delete pl;
+    return s;
+  }
+  build_layouts(pl);
+  *plan = pl;
+  return COSMO_OK;
+}
+
+cosmo_status cosmo_plan_destroy(cosmo_plan *plan) {
+  if (!plan) return COSMO_OK;
+  (void)hipDeviceSynchronize();
+  delete plan;
+  return COSMO_OK;
+}
+
+cosmo_status cosmo_workspace_size(const cosmo_plan *plan, size_t *fwd, size_t *tape, size_t *bwd) {
+  cosmo_status s = check_plan(plan);
+  if (s != COSMO_OK) return s;
+  if (fwd) *fwd = plan->fw.total * plan->esz;
+  if (tape) *tape = plan->tp.total * plan->esz;
+  if (bwd) *bwd = plan->bw.total * plan->esz;
+  return COSMO_OK;
+}
+
+cosmo_status cosmo_tape_offsets(const cosmo_plan *plan, int32_t k, size_t *x_off, size_t *s_off, size_t *y_off,
+                                size_t *xt_off, size_t *st_off) {
+  cosmo_status s = check_plan(plan);
+  if (s != COSMO_OK) return s;
+  if (k < 0 || k > plan->opt.K) FAIL(COSMO_EINVAL, "k out of range [0, K]");
+  if (k == plan->opt.K && (xt_off || st_off)) FAIL(COSMO_EINVAL, "x~ and s~ exist for steps 0..K-1 only");
+  const size_t e = plan->esz;
+  if (x_off) *x_off = slot_x(plan, k) * e;
+  if (s_off) *s_off = slot_s(plan, k) * e;
+  if (y_off) *y_off = slot_y(plan, k) * e;
+  if (xt_off) *xt_off = (step_base(plan, k) + plan->tp.xt) * e;
+  if (st_off) *st_off = (step_base(plan, k) + plan->tp.st) * e;
+  return COSMO_OK;
+}
+
+cosmo_status cosmo_unroll_forward(cosmo_plan *plan, const void *rho, const void *alpha, const void *x0,
+                                  const void *s0, const void *y0, void *xK, void *sK, void *yK, void *tape, void *ws,
+                                  void *stats, void *stream) {
+  cosmo_status s = check_plan(plan);
+  if (s != COSMO_OK) return s;
+  if (!rho || !alpha) FAIL(COSMO_EINVAL, "rho and alpha are required");
+  if (!ws) FAIL(COSMO_EINVAL, "workspace is required");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto *stp = static_cast<cosmo_stats *>(stats);
+  if (plan->opt.dtype == COSMO_F32)
+    return forward_impl<float>(plan, (const float *)rho, (const float *)alpha, (const float *)x0, (const float *)s0,
+                               (const float *)y0, (float *)xK, (float *)sK, (float *)yK, (float *)tape, (float *)ws,
+                               stp, st);
+  return forward_impl<double>(plan, (const double *)rho, (const double *)alpha, (const double *)x0,
+                              (const double *)s0, (const double *)y0, (double *)xK, (double *)sK, (double *)yK,
+                              (double *)tape, (double *)ws, stp, st);
+}
+
+cosmo_status cosmo_unroll_backward(cosmo_plan *plan, const void *rho, const void *alpha, const void *tape,
+                                   const void *gxK, const void *gsK, const void *gyK, void *grho, void *galpha,
+                                   void *gx0, void *gs0, void *gy0, void *ws, void *stats, void *stream) {
+  cosmo_status s = check_plan(plan);
+  if (s != COSMO_OK) return s;
+  if (!rho || !alpha) FAIL(COSMO_EINVAL, "rho and alpha are required");
+  if (!tape) FAIL(COSMO_EINVAL, "the backward pass needs the tape written by cosmo_unroll_forward");
+  if (!ws) FAIL(COSMO_EINVAL, "workspace is required");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto *stp = static_cast<cosmo_stats *>(stats);
+  if (plan->opt.dtype == COSMO_F32)
+    return backward_impl<float>(plan, (const float *)rho, (const float *)alpha, (const float *)tape,
+                                (const float *)gxK, (const float *)gsK, (const float *)gyK, (float *)grho,
+                                (float *)galpha, (float *)gx0, (float *)gs0, (float *)gy0, (float *)ws, stp, st);
+  return backward_impl<double>(plan, (const double *)rho, (const double *)alpha, (const double *)tape,
+                               (const double *)gxK, (const double *)gsK, (const double *)gyK, (double *)grho,
+                               (double *)galpha, (double *)gx0, (double *)gs0, (double *)gy0, (double *)ws, stp, st);
+}
+
+cosmo_status cosmo_residual_loss(cosmo_plan *plan, const void *x, const void *s, const void *y, void *loss, void *gx,
+                                 void *gs, void *gy, void *ws, void *stream) {
+  cosmo_status st0 = check_plan(plan);
+  if (st0 != COSMO_OK) return st0;
+  if (!x || !s || !y || !loss || !ws) FAIL(COSMO_EINVAL, "x, s, y, loss and ws are required");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (plan->opt.dtype == COSMO_F32) {
+    const View<float> v = make_view<float>(plan);
+    float *w = (float *)ws;
+    launch_loss<float>(v, plan->bkA, plan->bkAt, (const float *)x, (const float *)s, (const float *)y, w + plan->fw.rp,
+                       w + plan->fw.rd, (float *)loss, (float *)gx, (float *)gs, (float *)gy, st);
+  } else {
+    const View<double> v = make_view<double>(plan);
+    double *w = (double *)ws;
+    launch_loss<double>(v, plan->bkA, plan->bkAt, (const double *)x, (const double *)s, (const double *)y,
+                        w + plan->fw.rp, w + plan->fw.rd, (double *)loss, (double *)gx, (double *)gs, (double *)gy, st);
+  }
+  HIPCHK(hipGetLastError());
+  return COSMO_OK;
+}
+
+// ---- profiling (not part of the hot path) -------------------------------------
+
+cosmo_status cosmo_plan_set_profiling(cosmo_plan *plan, int32_t enable) {
+  cosmo_status s = check_plan(plan);
+  if (s != COSMO_OK) return s;
+  plan->profiling = enable != 0;
+  for (auto &sl : plan->prof) sl.used = 0;
+  return COSMO_OK;
+}
+
+cosmo_status cosmo_plan_profile_read(cosmo_plan *plan, int32_t kind, int64_t *launches, double *total_ms) {
+  cosmo_status s = check_plan(plan);
+  if (s != COSMO_OK) return s;
+  if (kind < 0 || kind > 3) FAIL(COSMO_EINVAL, "kind must be 0..3");
+  ProfileSlot &sl = plan->prof[kind];
+  double tot = 0;
+  for (size_t i = 0; i < sl.used; ++i) {
+    HIPCHK(hipEventSynchronize(sl.ev[i].second));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, sl.ev[i].first, sl.ev[i].second));
+    tot += ms;
+  }
+  if (launches) *launches = (int64_t)sl.used;
+  if (total_ms) *total_ms = tot;
+  return COSMO_OK;
+}
+
+// ---- standalone projections ------------------------------------------------------
+
+size_t cosmo_proj_workspace_size(int32_t nblk, const int32_t *order_or_dim) {
+  if (nblk < 0) return 0;
+  size_t p2 = 0;
+  if (order_or_dim)
+    for (int b = 0; b < nblk; ++b) p2 += (size_t)std::max(order_or_dim[b], 0) * std::max(order_or_dim[b], 0);
+  return align_up((size_t)std::max(nblk, 1) * std::max(sizeof(PsdDesc), sizeof(SocDesc)), 256) + 3 * p2 * 8;
+}
+
+}  // extern "C"
+
+namespace {
+
+cosmo_status psd_common(int32_t nblk, const int32_t *order, const int64_t *offset, cosmo_dtype dt, void *ws,
+                        hipStream_t st, std::vector<PsdDesc> &descs, int32_t cls_begin[5], int32_t cls_maxp[4]) {
+  if (nblk < 1 || !order || !offset) FAIL(COSMO_EINVAL, "need nblk >= 1 and host order / offset arrays");
+  if (dt != COSMO_F32 && dt != COSMO_F64) FAIL(COSMO_EINVAL, "bad dtype");
+  if (!ws) FAIL(COSMO_EINVAL, "workspace is required");
+  const int maxp = dt == COSMO_F32 ? COSMO_MAX_PSD_ORDER_F32 : COSMO_MAX_PSD_ORDER_F64;
+  descs.resize(nblk);
+  int64_t uo = 0, lo = 0;
+  std::vector<std::pair<int64_t, int64_t>> ranges;
+  for (int b = 0; b < nblk; ++b) {
+    if (order[b] < 1 || order[b] > maxp) FAIL(order[b] < 1 ? COSMO_EINVAL : COSMO_EUNSUPPORTED, "PSD order out of range");
+    if (offset[b] < 0) FAIL(COSMO_EINVAL, "negative offset");
+    descs[b] = {offset[b], uo, lo, order[b], 0};
+    uo += (int64_t)order[b] * order[b];
+    lo += order[b];
+    ranges.push_back({offset[b], offset[b] + (int64_t)order[b] * (order[b] + 1) / 2});
+  }
+  std::sort(ranges.begin(), ranges.end());
+  for (size_t i = 1; i < ranges.size(); ++i)
+    if (ranges[i].first < ranges[i - 1].second) FAIL(COSMO_EINVAL, "PSD blocks overlap");
+  std::stable_sort(descs.begin(), descs.end(), [](const PsdDesc &a, const PsdDesc &b) {
+    const int ca = psd_class(a.p), cb = psd_class(b.p);
+    if (ca != cb) return ca < cb;
+    return a.p > b.p;
+  });
+  int idx = 0;
+  for (int c = 0; c < 4; ++c) {
+    cls_begin[c] = idx;
+    cls_maxp[c] = 0;
+    while (idx < nblk && psd_class(descs[idx].p) == c) cls_maxp[c] = std::max(cls_maxp[c], descs[idx++].p);
+  }
+  cls_begin[4] = idx;
+  HIPCHK(hipMemcpyAsync(ws, descs.data(), nblk * sizeof(PsdDesc), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return COSMO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cosmo_status psd_proj(int32_t nblk, const int32_t *order, const int64_t *offset, cosmo_dtype dtype, const void *in,
+                      void *out, void *eigvals, void *eigvecs, int32_t max_sweeps, double eig_tol, int32_t refine,
+                      void *ws, void *stream) {
+  if (!in || !out) FAIL(COSMO_EINVAL, "in and out are required");
+  if (max_sweeps < 1) FAIL(COSMO_EINVAL, "max_sweeps must be >= 1");
+  if (refine < 0 || refine > 4) FAIL(COSMO_EINVAL, "refine must be in [0, 4]");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<PsdDesc> descs;
+  int32_t cb[5], cm[4];
+  cosmo_status s = psd_common(nblk, order, offset, dtype, ws, st, descs, cb, cm);
+  if (s != COSMO_OK) return s;
+  const PsdDesc *d = static_cast<const PsdDesc *>(ws);
+  double *rs = reinterpret_cast<double *>(static_cast<char *>(ws) +
+                                          align_up((size_t)nblk * std::max(sizeof(PsdDesc), sizeof(SocDesc)), 256));
+  const int rf = dtype == COSMO_F32 ? refine : 0;
+  for (int c = 0; c < 4; ++c) {
+    const int n = cb[c + 1] - cb[c];
+    if (!n) continue;
+    PsdLaunchCfg cfg{max_sweeps, eig_tol, rf, cm[c]};
+    if (dtype == COSMO_F32)
+      launch_psd_step<float>(d + cb[c], n, cfg, nullptr, (const float *)in, nullptr, nullptr, (float *)out, nullptr,
+                             (float *)eigvecs, (float *)eigvals, rf ? rs : nullptr, nullptr, st);
+    else
+      launch_psd_step<double>(d + cb[c], n, cfg, nullptr, (const double *)in, nullptr, nullptr, (double *)out,
+                              nullptr, (double *)eigvecs, (double *)eigvals, nullptr, nullptr, st);
+  }
+  HIPCHK(hipGetLastError());
+  return COSMO_OK;
+}
+
+cosmo_status psd_proj_vjp(int32_t nblk, const int32_t *order, const int64_t *offset, cosmo_dtype dtype,
+                          const void *eigvals, const void *eigvecs, const void *gout, void *gin, void *ws,
+                          void *stream) {
+  if (!eigvals || !eigvecs || !gout || !gin) FAIL(COSMO_EINVAL, "eigvals, eigvecs, gout and gin are required");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<PsdDesc> descs;
+  int32_t cb[5], cm[4];
+  cosmo_status s = psd_common(nblk, order, offset, dtype, ws, st, descs, cb, cm);
+  if (s != COSMO_OK) return s;
+  const PsdDesc *d = static_cast<const PsdDesc *>(ws);
+  // a p x p buffer that does not fit next to the first one in LDS lives in the
+  // workspace's scratch area (sum p^2 elements, indexed like the eigenvectors)
+  void *scratch = static_cast<char *>(ws) + align_up((size_t)nblk * std::max(sizeof(PsdDesc), sizeof(SocDesc)), 256);
+  for (int c = 0; c < 4; ++c) {
+    const int n = cb[c + 1] - cb[c];
+    if (!n) continue;
+    if (dtype == COSMO_F32)
+      launch_psd_vjp<float>(d + cb[c], n, cm[c], (const float *)eigvecs, (const float *)eigvals, (const float *)gout,
+                            (float *)gin, (float *)scratch, st);
+    else
+      launch_psd_vjp<double>(d + cb[c], n, cm[c], (const double *)eigvecs, (const double *)eigvals,
+                             (const double *)gout, (double *)gin, (double *)scratch, st);
+  }
+  HIPCHK(hipGetLastError());
+  return COSMO_OK;
+}
+
+static cosmo_status soc_common(int32_t ncones, const int32_t *dim, const int64_t *offset, cosmo_dtype dt, void *ws,
+                               hipStream_t st) {
+  if (ncones < 1 || !dim || !offset) FAIL(COSMO_EINVAL, "need ncones >= 1 and host dim / offset arrays");
+  if (dt != COSMO_F32 && dt != COSMO_F64) FAIL(COSMO_EINVAL, "bad dtype");
+  if (!ws) FAIL(COSMO_EINVAL, "workspace is required");
+  std::vector<SocDesc> d(ncones);
+  for (int c = 0; c < ncones; ++c) {
+    if (dim[c] < 1 || offset[c] < 0) FAIL(COSMO_EINVAL, "bad SOC dim / offset");
+    d[c] = {offset[c], dim[c], 0};
+  }
+  HIPCHK(hipMemcpyAsync(ws, d.data(), ncones * sizeof(SocDesc), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return COSMO_OK;
+}
+
+cosmo_status socp_proj(int32_t ncones, const int32_t *dim, const int64_t *offset, cosmo_dtype dtype, const void *in,
+                       void *out, void *ws, void *stream) {
+  if (!in || !out) FAIL(COSMO_EINVAL, "in and out are required");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  cosmo_status s = soc_common(ncones, dim, offset, dtype, ws, st);
+  if (s != COSMO_OK) return s;
+  const SocDesc *d = static_cast<const SocDesc *>(ws);
+  if (dtype == COSMO_F32) launch_soc_proj<float>(d, ncones, (const float *)in, (float *)out, st);
+  else launch_soc_proj<double>(d, ncones, (const double *)in, (double *)out, st);
+  HIPCHK(hipGetLastError());
+  return COSMO_OK;
+}
+
+cosmo_status socp_proj_vjp(int32_t ncones, const int32_t *dim, const int64_t *offset, cosmo_dtype dtype,
+                           const void *in, const void *gout, void *gin, void *ws, void *stream) {
+  if (!in || !gout || !gin) FAIL(COSMO_EINVAL, "in, gout and gin are required");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  cosmo_status s = soc_common(ncones, dim, offset, dtype, ws, st);
+  if (s != COSMO_OK) return s;
+  const SocDesc *d = static_cast<const SocDesc *>(ws);
+  if (dtype == COSMO_F32) launch_soc_vjp<float>(d, ncones, (const float *)in, (const float *)gout, (float *)gin, st);
+  else launch_soc_vjp<double>(d, ncones, (const double *)in, (const double *)gout, (double *)gin, st);
+  HIPCHK(hipGetLastError());
+  return COSMO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,55 @@
+"""Shared pieces of the GPU parity tests: running the float64 oracle on the
+same (rounded) data and hyperparameters, and the norm-wise tolerance test.
+
+Tolerance (per instance and per array): ||gpu - ref||_2 <= tol * max(||ref||_2, floor)
+with floor = 1e-6 max(1, ||b||, ||q||), so arrays whose reference is ~0 are
+compared against the data scale.
+"""
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+
+
+def say(msg: str) -> None:
+    print(msg, flush=True)
+
+
+def ensure_lib():
+    from paper_2606_13825_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        raise RuntimeError("libcosmo_unroll.so is not built; run __graft_entry__.build() first")
+
+
+def floor_of(inst) -> float:
+    return 1e-6 * max(1.0, float(np.linalg.norm(inst.b)), float(np.linalg.norm(inst.q)))
+
+
+def rel_err(gpu, ref, floor=0.0) -> float:
+    gpu = np.asarray(gpu, np.float64)
+    ref = np.asarray(ref, np.float64)
+    return float(np.linalg.norm(gpu - ref) / max(np.linalg.norm(ref), floor, 1e-300))
+
+
+def assert_close(gpu, ref, tol, floor, what):
+    e = rel_err(gpu, ref, floor)
+    assert np.all(np.isfinite(np.asarray(gpu))), f"{what}: non-finite values"
+    assert e <= tol, f"{what}: relative error {e:.3e} > {tol:.1e}"
+    return e
+
+
+def oracle_run(inst, rho_k_m, alpha_k, with_grad=True, x0=None, s0=None, y0=None):
+    """Forward (and loss-gradient backward) of one instance in float64."""
+    tape, (x, s, y) = oracle.unroll_forward(inst, rho_k_m, alpha_k, x0, s0, y0)
+    out = dict(tape=tape, x=x, s=s, y=y, loss=oracle.residual_loss(inst, x, s, y))
+    if with_grad:
+        g = oracle.residual_loss_grad(inst, x, s, y)
+        grho, galpha, gx0, gs0, gy0 = oracle.unroll_backward(inst, tape, *g)
+        out.update(grho=grho, galpha=galpha, gx0=gx0, gs0=gs0, gy0=gy0)
+    return out

@@ -1,0 +1,129 @@
+"""The C-ABI library loads, exports every symbol its header declares, and
+rejects malformed descriptors on the host before touching any device
+(CPU only: no compute call is made)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cosmo_unroll.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2606_13825_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2606_13825_amd import build
+        build.build()
+    return _lib
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\**\s*([a-z_0-9]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported(L):
+    lib = L.lib()
+    declared = _declared_functions()
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(L.EXPORTED) == declared
+
+
+def test_status_strings_and_version(L):
+    lib = L.lib()
+    assert lib.cosmo_abi_version() == 1
+    assert b"EINVAL" in lib.cosmo_status_string(L.COSMO_EINVAL)
+
+
+def _problem(L, B=1, n_off=(0, 3), m_off=(0, 4), kinds=(0, 1), sizes=(1, 3)):
+    n_off = np.asarray(n_off, np.int64)
+    m_off = np.asarray(m_off, np.int64)
+    kinds = np.asarray(kinds, np.int32)
+    sizes = np.asarray(sizes, np.int32)
+    p = L.CosmoProblem()
+    p.B = B
+    p.n_off = n_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    p.m_off = m_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    # non-NULL stand-ins: validation rejects the layout before any device access
+    p.A_rowptr = p.A_col = p.A_val = p.q = p.b = 16
+    p.A_nnz = 4
+    p.P_nnz = 0
+    p.n_cones = len(kinds)
+    p.cone_kind = kinds.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    p.cone_size = sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    return p, (n_off, m_off, kinds, sizes)
+
+
+def _options(L, **kw):
+    o = L.CosmoOptions()
+    o.dtype, o.K, o.sigma, o.cg_tol, o.cg_max_iter, o.eig_max_sweeps, o.eig_tol = 0, 5, 1e-6, 1e-6, 100, 30, 0.0
+    o.eig_refine = 1
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+@pytest.mark.parametrize("case", [
+    dict(B=0),
+    dict(n_off=(1, 3)),
+    dict(m_off=(0, 0)),
+    dict(kinds=(0, 1), sizes=(1, 2)),            # cone rows do not cover m
+    dict(kinds=(0, 7), sizes=(1, 3)),            # unknown cone kind
+    dict(kinds=(0, 3), sizes=(1, 0)),            # empty cone
+    dict(B=2, n_off=(0, 2, 3), m_off=(0, 2, 4), kinds=(0, 1), sizes=(3, 1)),   # straddles instances
+])
+def test_invalid_problem_rejected_on_host(L, case):
+    p, keep = _problem(L, **case)
+    h = ctypes.c_void_p()
+    st = L.lib().cosmo_plan_create(ctypes.byref(h), ctypes.byref(p), ctypes.byref(_options(L)))
+    assert st == L.COSMO_EINVAL
+    assert h.value is None
+    assert L.lib().cosmo_last_error()
+
+
+@pytest.mark.parametrize("kw", [dict(K=0), dict(sigma=0.0), dict(cg_max_iter=0), dict(dtype=5),
+                                dict(eig_max_sweeps=0), dict(cg_tol=-1.0), dict(eig_refine=-1)])
+def test_invalid_options_rejected(L, kw):
+    p, keep = _problem(L)
+    h = ctypes.c_void_p()
+    st = L.lib().cosmo_plan_create(ctypes.byref(h), ctypes.byref(p), ctypes.byref(_options(L, **kw)))
+    assert st == L.COSMO_EINVAL
+
+
+def test_psd_order_beyond_envelope_is_unsupported(L):
+    p, keep = _problem(L, n_off=(0, 3), m_off=(0, 201 * 202 // 2), kinds=(3,), sizes=(201,))
+    p.n_cones = 1
+    h = ctypes.c_void_p()
+    st = L.lib().cosmo_plan_create(ctypes.byref(h), ctypes.byref(p), ctypes.byref(_options(L)))
+    assert st == L.COSMO_EUNSUPPORTED
+
+
+def test_null_arguments_rejected(L):
+    lib = L.lib()
+    assert lib.cosmo_plan_create(None, None, None) == L.COSMO_EINVAL
+    h = ctypes.c_void_p()
+    assert lib.cosmo_plan_create(ctypes.byref(h), None, ctypes.byref(_options(L))) == L.COSMO_EINVAL
+    assert lib.cosmo_workspace_size(None, None, None, None) == L.COSMO_EINVAL
+    assert lib.cosmo_unroll_forward(*([None] * 13)) == L.COSMO_EINVAL
+    assert lib.cosmo_unroll_backward(*([None] * 15)) == L.COSMO_EINVAL
+    orders = np.array([3], np.int32)
+    offs = np.array([0], np.int64)
+    P32 = orders.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    P64 = offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    assert lib.psd_proj(1, P32, P64, 0, None, None, None, None, 10, 0.0, 1, None, None) == L.COSMO_EINVAL
+    assert lib.socp_proj(0, P32, P64, 0, None, None, None, None) == L.COSMO_EINVAL
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, L):
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", "/nonexistent/libcosmo_unroll.so")
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        L.lib()

@@ -1,0 +1,115 @@
+"""End-to-end parity of the batched unrolled COSMO on the GPU against the
+float64 oracle: every iterate of the tape, the final-residual loss, and the
+gradients w.r.t. (rho^k, alpha^k, x0, s0, y0)."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_common import assert_close, ensure_lib, floor_of, oracle_run, say
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _stack_hyper(insts, K, rng, perturb=True, dtype=np.float32):
+    rhos, alphas = [], []
+    for inst in insts:
+        if perturb:
+            r, a = synth.perturbed_hyper(inst, K, rng)
+        else:
+            r, a = synth.default_rho(inst, K), np.full(K, 1.6)
+        rhos.append(r.astype(dtype))
+        alphas.append(a.astype(dtype))
+    return rhos, alphas
+
+
+def _run(insts, K, dtype, rhos, alphas, z0=None, cg_tol=None, grad=True, **kw):
+    from paper_2606_13825_amd import CosmoBatch
+    tdt = torch.float32 if dtype == np.float32 else torch.float64
+    batch = CosmoBatch(insts, K=K, dtype=tdt, device=DEV, cg_tol=cg_tol, **kw)
+    rho = torch.from_numpy(np.concatenate(rhos, axis=1)).to(DEV)
+    alpha = torch.from_numpy(np.stack(alphas, axis=1)).to(DEV)
+    args = [None, None, None]
+    if z0 is not None:
+        args = [torch.from_numpy(np.concatenate(v).astype(dtype)).to(DEV) for v in z0]
+    stats = batch.new_stats()
+    fw = batch.forward(rho, alpha, *args, stats=stats)
+    loss, g = batch.residual_loss(fw.x, fw.s, fw.y)
+    bw = batch.backward(rho, alpha, fw.tape, *g, stats=stats) if grad else None
+    torch.cuda.synchronize()
+    return batch, fw, loss, bw, batch.stats_dict(stats)
+
+
+def _check(batch, fw, loss, bw, insts, rhos, alphas, tol_it, tol_g, every_k=False, z0=None, grad=True):
+    for i, inst in enumerate(insts):
+        zi = None if z0 is None else [z0[0][i], z0[1][i], z0[2][i]]
+        ref = oracle_run(inst, rhos[i].astype(np.float64), alphas[i].astype(np.float64), grad,
+                         *(zi if zi else (None, None, None)))
+        fl = floor_of(inst)
+        sl_n = slice(batch.n_off[i], batch.n_off[i + 1])
+        sl_m = slice(batch.m_off[i], batch.m_off[i + 1])
+        if every_k:
+            for k in range(1, batch.K + 1):
+                x, s, y, _, _ = batch.tape_iterate(fw.tape, k)
+                st = ref["tape"][k - 1]
+                for nm, g_, r_ in (("x", x[sl_n], st["xn"]), ("s", s[sl_m], st["sn"]), ("y", y[sl_m], st["yn"])):
+                    assert_close(g_.double().cpu().numpy(), r_, tol_it, fl, f"inst {i} iterate {nm}^{k}")
+        for nm, g_, r_ in (("x", fw.x[sl_n], ref["x"]), ("s", fw.s[sl_m], ref["s"]), ("y", fw.y[sl_m], ref["y"])):
+            assert_close(g_.double().cpu().numpy(), r_, tol_it, fl, f"inst {i} final {nm}")
+        assert abs(float(loss[i]) - ref["loss"]) <= tol_g * max(abs(ref["loss"]), 1e-6), (i, float(loss[i]), ref["loss"])
+        if grad:
+            assert_close(bw.grho[:, sl_m].double().cpu().numpy(), ref["grho"], tol_g, 0.0, f"inst {i} grad rho")
+            assert_close(bw.galpha[:, i].double().cpu().numpy(), ref["galpha"], tol_g, 0.0, f"inst {i} grad alpha")
+            for nm, g_, r_ in (("x0", bw.gx0[sl_n], ref["gx0"]), ("s0", bw.gs0[sl_m], ref["gs0"]),
+                               ("y0", bw.gy0[sl_m], ref["gy0"])):
+                assert_close(g_.double().cpu().numpy(), r_, tol_g, 1e-6 * max(1.0, np.linalg.norm(ref["grho"])),
+                             f"inst {i} grad {nm}")
+
+
+# Random dense A and P give M condition numbers near 1e4, so a float32 solve carries
+# ~1e-4 relative error by itself; the float32 bar here follows that, while the
+# workload tests (diagonal or near-diagonal M) keep 1e-5 / 1e-4.
+@pytest.mark.parametrize("dtype,tol_it,tol_g", [(np.float64, 1e-10, 1e-8), (np.float32, 2e-4, 1e-3)])
+def test_mixed_cones_every_iterate_and_gradients(dtype, tol_it, tol_g):
+    ensure_lib()
+    rng = np.random.default_rng(10)
+    insts = [synth.random_mixed(rng, n=8, soc_dims=(3, 4), psd_orders=(3, 2)),
+             synth.random_mixed(rng, n=12, n_zero=0, soc_dims=(5,), psd_orders=(4,)),
+             synth.random_mixed(rng, n=6, n_nonneg=0, soc_dims=(), psd_orders=(5, 1))]
+    insts = [x.astype(dtype) for x in insts]
+    K = 8
+    rhos, alphas = _stack_hyper(insts, K, rng, dtype=dtype)
+    z0 = [[(0.3 * rng.standard_normal(d)).astype(dtype) for d in (x.n for x in insts)],
+          [(0.3 * rng.standard_normal(d)).astype(dtype) for d in (x.m for x in insts)],
+          [(0.3 * rng.standard_normal(d)).astype(dtype) for d in (x.m for x in insts)]]
+    z0d = [[v.astype(np.float64) for v in grp] for grp in z0]
+    say(f"mixed cones dtype={np.dtype(dtype).name} K={K}")
+    cg = 1e-13 if dtype == np.float64 else 1e-7
+    batch, fw, loss, bw, st = _run(insts, K, dtype, rhos, alphas, z0=z0, cg_tol=cg)
+    assert st["nonfinite"].max() == 0 and st["eig_not_converged"].max() == 0
+    _check(batch, fw, loss, bw, insts, rhos, alphas, tol_it, tol_g, every_k=True, z0=z0d)
+
+
+def test_c1_maxcut_fp64_every_iterate():
+    ensure_lib()
+    inst = synth.c1_instance()
+    K = 100
+    rho = synth.default_rho(inst, K)
+    alpha = np.full(K, 1.6)
+    say("C1 max-cut n=20 fp64 K=100 forward")
+    batch, fw, loss, bw, st = _run([inst], K, np.float64, [rho], [alpha], cg_tol=1e-10, grad=False)
+    assert st["cg_iters_max"][0] <= 2
+    _check(batch, fw, loss, bw, [inst], [rho], [alpha], 1e-9, 1e-8, every_k=True, grad=False)
+
+
+def test_c2_small_batch_fp32_forward_backward():
+    ensure_lib()
+    rng = np.random.default_rng(20)
+    insts = [x.astype(np.float32) for x in synth.c2_batch(B=4, p_lo=20, p_hi=45, seed=22)]
+    K = 20
+    rhos, alphas = _stack_hyper(insts, K, rng)
+    say(f"C2-like B=4 p={[i.meta['order'] for i in insts]} fp32 K={K}")
+    batch, fw, loss, bw, st = _run(insts, K, np.float32, rhos, alphas)
+    assert st["nonfinite"].max() == 0
+    _check(batch, fw, loss, bw, insts, rhos, alphas, 1e-5, 1e-4, every_k=True)
