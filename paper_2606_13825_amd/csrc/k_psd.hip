@@ -306,10 +306,16 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
               } else {
                 const double li = lamd[row], lj = lamd[col];
                 const double num = as[e] + lj * rij, gap = lj - li;
-                // first-order correction only where it is small (|E_ij| <= 1e-3):
-                // a pair whose coupling is not small against its gap stays as it
-                // is, which moves the projection by at most |num| (the residual)
-                bE[row + col * p] = (fabs(gap) > delta && fabs(num) <= 1e-3 * fabs(gap)) ? num / gap : 0.5 * rij;
+                // The projection and the Loewner-weighted VJP depend only on
+                // the split between positive and non-positive eigenvalues, so
+                // only pairs across that split are rotated, and only when the
+                // correction is small (|E_ij| <= 1e-3); every other pair is
+                // re-orthogonalised.  The test is symmetric in (i, j), so
+                // E + E' = R entry by entry and X stays orthonormal to second
+                // order.
+                const double cpl = fabs(as[e]) + fmax(fabs(li), fabs(lj)) * fabs(rij);
+                const bool rotate = (li * lj < 0.0) && fabs(gap) > delta && cpl <= 1e-3 * fabs(gap);
+                bE[row + col * p] = rotate ? num / gap : 0.5 * rij;
               }
             }
           }
