@@ -112,6 +112,9 @@ typedef struct {
                                   eigenpairs of every PSD block (Ogita-Aishima); the
                                   projection is then formed in float64.  Ignored for
                                   COSMO_F64, whose sweeps already run in float64.       */
+  int32_t eig_warm_start;      /* 1: start every step's Jacobi sweeps from the same
+                                  block's eigenvectors of the previous step (same
+                                  decomposition, fewer sweeps); 0: start from S.        */
 } cosmo_options;
 
 /* Per-instance device counters, updated with atomics (max / or); the caller

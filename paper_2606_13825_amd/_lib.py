@@ -55,6 +55,7 @@ class CosmoOptions(ctypes.Structure):
         ("eig_max_sweeps", ctypes.c_int32),
         ("eig_tol", ctypes.c_double),
         ("eig_refine", ctypes.c_int32),
+        ("eig_warm_start", ctypes.c_int32),
     ]
 
 

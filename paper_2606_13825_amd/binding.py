@@ -66,7 +66,7 @@ class CosmoBatch:
 
     def __init__(self, instances: Sequence, *, K: int, dtype=torch.float32, sigma: float = 1e-6,
                  cg_tol: Optional[float] = None, cg_max_iter: int = 500, eig_max_sweeps: int = 60,
-                 eig_tol: float = 0.0, eig_refine: int = 1, device="cuda:0"):
+                 eig_tol: float = 0.0, eig_refine: int = 1, eig_warm_start: bool = True, device="cuda:0"):
         self.device = torch.device(device)
         self.code = _dt_code(dtype)
         self.dtype = _TORCH_DT[self.code]
@@ -142,6 +142,7 @@ class CosmoBatch:
         opt.eig_max_sweeps = int(eig_max_sweeps)
         opt.eig_tol = float(eig_tol)
         opt.eig_refine = int(eig_refine)
+        opt.eig_warm_start = int(bool(eig_warm_start))
         self.opt = opt
         lib = L.lib()
         torch.cuda.synchronize(dev)

@@ -136,8 +136,8 @@ struct PsdLaunchCfg {
 };
 template <typename T> void launch_psd_step(const PsdDesc *d, int32_t n, const PsdLaunchCfg &cfg,
                                            const T *rho_hat, const T *vv, const T *sh, const T *y, T *s_new,
-                                           T *y_new, T *U, T *lam, double *rscratch, cosmo_stats *stats,
-                                           hipStream_t st);
+                                           T *y_new, T *U, T *lam, double *rscratch, const T *Uprev,
+                                           cosmo_stats *stats, hipStream_t st);
 template <typename T> void launch_psd_vjp(const PsdDesc *d, int32_t n, int32_t max_p, const T *U, const T *lam,
                                           const T *g, T *out, T *scratch, hipStream_t st);
 

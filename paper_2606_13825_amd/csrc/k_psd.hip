@@ -103,14 +103,14 @@ template <typename T, int NT> __device__ inline T wg_max(T v, T *red) {
 }
 
 // mode 0: COSMO step on the block (s+ and y+ rows); mode 1: projection only.
-template <typename T, int NT, int G>
+template <typename T, int NT, int G, int PMAX>
 __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ descs, int32_t max_sweeps, T tol_base,
                                                 int32_t mode, const T *__restrict__ rho_hat,
                                                 const T *__restrict__ vin, const T *__restrict__ sh,
                                                 const T *__restrict__ y, T *__restrict__ s_new,
                                                 T *__restrict__ y_new, T *__restrict__ Uout,
                                                 T *__restrict__ lamout, cosmo_stats *stats, int32_t refine,
-                                                double *__restrict__ rscratch) {
+                                                double *__restrict__ rscratch, const T *__restrict__ Uprev) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *W = reinterpret_cast<T *>(smem_raw);
   __shared__ T red[NT / 64];
@@ -148,7 +148,35 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
   const T inf = wg_max<T, NT>(rowmax, red);
   T c = (T)1.1 * fmin(sqrt(fro2), inf);
   if (!(c > (T)0)) c = (T)1;
-  for (int i = tid; i < p; i += NT) W[i + i * p] += c;
+  if (Uprev) {
+    // Warm start: W = (S + c I) U_prev, with U_prev the eigenvectors of the same
+    // block at the previous unrolled step.  One-sided Jacobi on W computes the
+    // same decomposition (W = G V with V orthogonal, W'W diagonal at the end);
+    // a nearly diagonalising start only shortens the sweeps.
+    const T *Up = Uprev + d.uoff;
+    const int nt0 = (p + 15) / 16;
+    const int wave0 = tid >> 6, lane0 = tid & 63;
+    for (int t = wave0; t < nt0 * nt0; t += NT / 64) {
+      const int I = t / nt0, J = t % nt0;
+      const typename Mma<T>::v4 acc = tile_mma<T>(
+          I * 16, J * 16, p,
+          [&](int i, int k) -> T {
+            if (i >= p || k >= p) return (T)0;
+            const int a = i < k ? i : k, b = i < k ? k : i;
+            const T val = v[b * (b + 1) / 2 + a];
+            return a == b ? val : val * (T)RSQRT2;
+          },
+          [&](int k, int j) -> T { return (k < p && j < p) ? Up[k + j * p] : (T)0; });
+      const int col = J * 16 + (lane0 & 15);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = I * 16 + Mma<T>::row(lane0, e);
+        if (row < p && col < p) W[row + col * p] = acc[e] + c * Up[row + col * p];
+      }
+    }
+  } else {
+    for (int i = tid; i < p; i += NT) W[i + i * p] += c;
+  }
   __syncthreads();
 
   const T tol = tol_base > (T)0 ? tol_base : (T)4 * Unit<T>::eps * sqrt((T)p);
@@ -156,6 +184,7 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
   const int npairs = P / 2;
   const int ngroups = NT / G;
   const int grp = tid / G, gl = tid % G;
+  constexpr int MAXE = (PMAX + G - 1) / G;   // column elements held per lane
   int sweep = 0;
   bool converged = (p == 1);
   for (; sweep < max_sweeps && !converged; ++sweep) {
@@ -178,12 +207,16 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
         }
         T *wa = W + a * p;
         T *wb = W + b * p;
+        T xa[MAXE], xb[MAXE];
         T al = 0, be = 0, ga = 0;
-        for (int i = gl; i < p; i += G) {
-          const T x = wa[i], yv = wb[i];
-          al += x * x;
-          be += yv * yv;
-          ga += x * yv;
+#pragma unroll
+        for (int e = 0; e < MAXE; ++e) {
+          const int i = gl + e * G;
+          xa[e] = (i < p) ? wa[i] : (T)0;
+          xb[e] = (i < p) ? wb[i] : (T)0;
+          al += xa[e] * xa[e];
+          be += xb[e] * xb[e];
+          ga += xa[e] * xb[e];
         }
         for (int off = G >> 1; off > 0; off >>= 1) {
           al += __shfl_xor(al, off, 64);
@@ -195,10 +228,13 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
           const T tt = (zeta >= (T)0 ? (T)1 : (T)-1) / (fabs(zeta) + sqrt((T)1 + zeta * zeta));
           const T cs = (T)1 / sqrt((T)1 + tt * tt);
           const T sn = cs * tt;
-          for (int i = gl; i < p; i += G) {
-            const T x = wa[i], yv = wb[i];
-            wa[i] = cs * x - sn * yv;
-            wb[i] = sn * x + cs * yv;
+#pragma unroll
+          for (int e = 0; e < MAXE; ++e) {
+            const int i = gl + e * G;
+            if (i < p) {
+              wa[i] = cs * xa[e] - sn * xb[e];
+              wb[i] = sn * xa[e] + cs * xb[e];
+            }
           }
           if (gl == 0) flags[fslot] = 1;
         }
@@ -599,18 +635,18 @@ void set_dyn_lds_cap(const void *fn) {
   (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(LDS_LIMIT - stat));
 }
 
-template <typename T, int NT, int G>
+template <typename T, int NT, int G, int PMAX>
 void run_eig(const PsdDesc *d, int32_t n, int32_t max_p, const PsdLaunchCfg &cfg, int32_t mode, const T *rho_hat,
              const T *vv, const T *sh, const T *y, T *s_new, T *y_new, T *U, T *lam, cosmo_stats *stats,
-             double *rscratch, hipStream_t st) {
+             double *rscratch, const T *Uprev, hipStream_t st) {
   const size_t dyn = (size_t)max_p * max_p * sizeof(T);
   static bool attr_set = false;
   if (!attr_set) {
-    set_dyn_lds_cap(reinterpret_cast<const void *>(&k_psd_eig<T, NT, G>));
+    set_dyn_lds_cap(reinterpret_cast<const void *>(&k_psd_eig<T, NT, G, PMAX>));
     attr_set = true;
   }
-  k_psd_eig<T, NT, G><<<n, NT, dyn, st>>>(d, cfg.max_sweeps, (T)cfg.tol, mode, rho_hat, vv, sh, y, s_new, y_new, U,
-                                          lam, stats, rscratch ? cfg.refine : 0, rscratch);
+  k_psd_eig<T, NT, G, PMAX><<<n, NT, dyn, st>>>(d, cfg.max_sweeps, (T)cfg.tol, mode, rho_hat, vv, sh, y, s_new,
+                                                y_new, U, lam, stats, rscratch ? cfg.refine : 0, rscratch, Uprev);
 }
 
 }  // namespace
@@ -620,14 +656,14 @@ void run_eig(const PsdDesc *d, int32_t n, int32_t max_p, const PsdLaunchCfg &cfg
 template <typename T>
 void launch_psd_step(const PsdDesc *d, int32_t n, const PsdLaunchCfg &cfg, const T *rho_hat, const T *vv,
                      const T *sh, const T *y, T *s_new, T *y_new, T *U, T *lam, double *rscratch,
-                     cosmo_stats *stats, hipStream_t st) {
+                     const T *Uprev, cosmo_stats *stats, hipStream_t st) {
   if (n <= 0) return;
   const int mode = (y_new != nullptr) ? 0 : 1;
   const int mp = cfg.max_p;
-  if (mp <= 32) run_eig<T, 64, 4>(d, n, mp, cfg, mode, rho_hat, vv, sh, y, s_new, y_new, U, lam, stats, rscratch, st);
-  else if (mp <= 64) run_eig<T, 256, 8>(d, n, mp, cfg, mode, rho_hat, vv, sh, y, s_new, y_new, U, lam, stats, rscratch, st);
-  else if (mp <= 128) run_eig<T, 512, 8>(d, n, mp, cfg, mode, rho_hat, vv, sh, y, s_new, y_new, U, lam, stats, rscratch, st);
-  else run_eig<T, 1024, 8>(d, n, mp, cfg, mode, rho_hat, vv, sh, y, s_new, y_new, U, lam, stats, rscratch, st);
+  if (mp <= 32) run_eig<T, 64, 4, 32>(d, n, mp, cfg, mode, rho_hat, vv, sh, y, s_new, y_new, U, lam, stats, rscratch, Uprev, st);
+  else if (mp <= 64) run_eig<T, 256, 8, 64>(d, n, mp, cfg, mode, rho_hat, vv, sh, y, s_new, y_new, U, lam, stats, rscratch, Uprev, st);
+  else if (mp <= 128) run_eig<T, 512, 8, 128>(d, n, mp, cfg, mode, rho_hat, vv, sh, y, s_new, y_new, U, lam, stats, rscratch, Uprev, st);
+  else run_eig<T, 1024, 8, 200>(d, n, mp, cfg, mode, rho_hat, vv, sh, y, s_new, y_new, U, lam, stats, rscratch, Uprev, st);
 }
 
 template <typename T>
@@ -649,10 +685,10 @@ void launch_psd_vjp(const PsdDesc *d, int32_t n, int32_t max_p, const T *U, cons
 
 template void launch_psd_step<float>(const PsdDesc *, int32_t, const PsdLaunchCfg &, const float *, const float *,
                                      const float *, const float *, float *, float *, float *, float *, double *,
-                                     cosmo_stats *, hipStream_t);
+                                     const float *, cosmo_stats *, hipStream_t);
 template void launch_psd_step<double>(const PsdDesc *, int32_t, const PsdLaunchCfg &, const double *,
                                       const double *, const double *, const double *, double *, double *, double *,
-                                      double *, double *, cosmo_stats *, hipStream_t);
+                                      double *, double *, const double *, cosmo_stats *, hipStream_t);
 template void launch_psd_vjp<float>(const PsdDesc *, int32_t, int32_t, const float *, const float *, const float *,
                                     float *, float *, hipStream_t);
 template void launch_psd_vjp<double>(const PsdDesc *, int32_t, int32_t, const double *, const double *,

@@ -108,12 +108,21 @@ struct cosmo_plan {
   } bw{};
   bool profiling = false;
   ProfileSlot prof[4];
+  // auxiliary streams (default priority) and events for concurrent order classes
+  hipStream_t aux[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[3] = {nullptr, nullptr, nullptr};
   ~cosmo_plan() {
     for (auto &s : prof)
       for (auto &e : s.ev) {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
       }
+    for (int i = 0; i < 3; ++i) {
+      if (aux[i]) (void)hipStreamDestroy(aux[i]);
+      if (ev_join[i]) (void)hipEventDestroy(ev_join[i]);
+    }
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
   }
 };
 
@@ -180,6 +189,7 @@ cosmo_status validate_options(const cosmo_options *o) {
   if (o->eig_max_sweeps < 1) FAIL(COSMO_EINVAL, "eig_max_sweeps must be >= 1");
   if (!(o->eig_tol >= 0.0) || !std::isfinite(o->eig_tol)) FAIL(COSMO_EINVAL, "eig_tol must be finite and >= 0");
   if (o->eig_refine < 0 || o->eig_refine > 4) FAIL(COSMO_EINVAL, "eig_refine must be in [0, 4]");
+  if (o->eig_warm_start != 0 && o->eig_warm_start != 1) FAIL(COSMO_EINVAL, "eig_warm_start must be 0 or 1");
   return COSMO_OK;
 }
 
@@ -453,8 +463,10 @@ void build_layouts(cosmo_plan *pl) {
   f.t = take(m);
   f.sh = take(m);
   f.vv = take(m);
-  f.itA = take(n + 2 * m);
-  f.itB = take(n + 2 * m);
+  // (x, s, y) triples laid out like a tape slot: each part starts 64-element aligned
+  const size_t triple = align_up(n, A) + 2 * align_up(m, A);
+  f.itA = take(triple);
+  f.itB = take(triple);
   f.xt = take(n);
   f.st = take(m);
   f.U = take(pl->sum_p2);
@@ -475,8 +487,8 @@ void build_layouts(cosmo_plan *pl) {
   auto &w = pl->bw;
   o = 0;
   w.rho_hat = take(K * m);
-  w.gA = take(n + 2 * m);
-  w.gB = take(n + 2 * m);
+  w.gA = take(triple);
+  w.gB = take(triple);
   w.gsn = take(m);
   w.gv = take(m);
   w.gsh = take(m);
@@ -502,28 +514,45 @@ size_t slot_y(const cosmo_plan *pl, size_t k) {
 }
 size_t step_base(const cosmo_plan *pl, size_t k) { return (pl->opt.K + 1) * pl->tp.slot + k * pl->tp.step; }
 
+// The PSD order classes are independent launches over disjoint blocks: the
+// first non-empty class runs on the caller's stream, the others on the plan's
+// auxiliary streams, forked from and joined back into the caller's stream by
+// events (a pattern stream capture also accepts).
+template <typename F> void fork_classes(cosmo_plan *pl, hipStream_t st, F &&launch_class) {
+  int cls[4], nc = 0;
+  for (int c = 0; c < 4; ++c)
+    if (pl->psd_cls_begin[c + 1] > pl->psd_cls_begin[c]) cls[nc++] = c;
+  if (nc == 0) return;
+  if (nc > 1) (void)hipEventRecord(pl->ev_fork, st);
+  for (int i = 1; i < nc; ++i) {
+    (void)hipStreamWaitEvent(pl->aux[i - 1], pl->ev_fork, 0);
+    launch_class(cls[i], pl->aux[i - 1]);
+    (void)hipEventRecord(pl->ev_join[i - 1], pl->aux[i - 1]);
+  }
+  launch_class(cls[0], st);
+  for (int i = 1; i < nc; ++i) (void)hipStreamWaitEvent(st, pl->ev_join[i - 1], 0);
+}
+
 template <typename T>
 void launch_psd_classes(cosmo_plan *pl, const T *rho_hat, const T *vv, const T *sh, const T *y, T *s_new, T *y_new,
-                        T *U, T *lam, double *rscratch, cosmo_stats *stats, hipStream_t st) {
+                        T *U, T *lam, double *rscratch, const T *Uprev, cosmo_stats *stats, hipStream_t st) {
   ProfScope ps(pl, 0, st);
   const bool refine = pl->opt.dtype == COSMO_F32 && pl->opt.eig_refine > 0;
-  for (int c = 0; c < 4; ++c) {
+  fork_classes(pl, st, [&](int c, hipStream_t s) {
     const int n = pl->psd_cls_begin[c + 1] - pl->psd_cls_begin[c];
-    if (n == 0) continue;
     PsdLaunchCfg cfg{pl->opt.eig_max_sweeps, pl->opt.eig_tol, refine ? pl->opt.eig_refine : 0, pl->psd_cls_maxp[c]};
     launch_psd_step<T>(pl->d_psd + pl->psd_cls_begin[c], n, cfg, rho_hat, vv, sh, y, s_new, y_new, U, lam,
-                       refine ? rscratch : nullptr, stats, st);
-  }
+                       refine ? rscratch : nullptr, Uprev, stats, s);
+  });
 }
 
 template <typename T>
 void launch_dk_classes(cosmo_plan *pl, const T *U, const T *lam, const T *g, T *out, T *scratch, hipStream_t st) {
   ProfScope ps(pl, 1, st);
-  for (int c = 0; c < 4; ++c) {
+  fork_classes(pl, st, [&](int c, hipStream_t s) {
     const int n = pl->psd_cls_begin[c + 1] - pl->psd_cls_begin[c];
-    if (n == 0) continue;
-    launch_psd_vjp<T>(pl->d_psd + pl->psd_cls_begin[c], n, pl->psd_cls_maxp[c], U, lam, g, out, scratch, st);
-  }
+    launch_psd_vjp<T>(pl->d_psd + pl->psd_cls_begin[c], n, pl->psd_cls_maxp[c], U, lam, g, out, scratch, s);
+  });
 }
 
 template <typename T>
@@ -571,8 +600,12 @@ cosmo_status forward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T 
       launch_rows_post<T>(v, pl->bkA, rh, al, xt, s, y, ST(k), ws + f.sh, ws + f.vv, sn, yn, st);
     }
     launch_soc_step<T>(pl->d_soc, pl->n_soc, rh, ws + f.vv, ws + f.sh, y, sn, yn, st);
+    // warm start from the previous step's eigenvectors of the same blocks (the
+    // tape keeps them; without a tape the single buffer is updated in place,
+    // each block reading its own slot before overwriting it)
+    const T *Uprev = (pl->opt.eig_warm_start && k > 0) ? (tape ? UU(k - 1) : UU(k)) : nullptr;
     launch_psd_classes<T>(pl, rh, ws + f.vv, ws + f.sh, y, sn, yn, UU(k), LAM(k),
-                          reinterpret_cast<double *>(ws + f.rs), stats, st);
+                          reinterpret_cast<double *>(ws + f.rs), Uprev, stats, st);
   }
   launch_nonfinite_check<T>(v, X(K), S(K), Y(K), stats, st);
   if (xK) launch_copy<T>(xK, X(K), n, st);
@@ -703,6 +736,17 @@ cosmo_status cosmo_plan_create(cosmo_plan **plan, const cosmo_problem *prob, con
     return s;
   }
   build_layouts(pl);
+  for (int i = 0; i < 3; ++i) {
+    if (hipStreamCreateWithFlags(&pl->aux[i], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&pl->ev_join[i], hipEventDisableTiming) != hipSuccess) {
+      delete pl;
+      FAIL(COSMO_EHIP, "creating auxiliary streams failed");
+    }
+  }
+  if (hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) != hipSuccess) {
+    delete pl;
+    FAIL(COSMO_EHIP, "creating events failed");
+  }
   *plan = pl;
   return COSMO_OK;
 }
@@ -899,10 +943,10 @@ cosmo_status psd_proj(int32_t nblk, const int32_t *order, const int64_t *offset,
     PsdLaunchCfg cfg{max_sweeps, eig_tol, rf, cm[c]};
     if (dtype == COSMO_F32)
       launch_psd_step<float>(d + cb[c], n, cfg, nullptr, (const float *)in, nullptr, nullptr, (float *)out, nullptr,
-                             (float *)eigvecs, (float *)eigvals, rf ? rs : nullptr, nullptr, st);
+                             (float *)eigvecs, (float *)eigvals, rf ? rs : nullptr, nullptr, nullptr, st);
     else
       launch_psd_step<double>(d + cb[c], n, cfg, nullptr, (const double *)in, nullptr, nullptr, (double *)out,
-                              nullptr, (double *)eigvecs, (double *)eigvals, nullptr, nullptr, st);
+                              nullptr, (double *)eigvecs, (double *)eigvals, nullptr, nullptr, nullptr, st);
   }
   HIPCHK(hipGetLastError());
   return COSMO_OK;

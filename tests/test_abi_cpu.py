@@ -66,6 +66,7 @@ def _options(L, **kw):
     o = L.CosmoOptions()
     o.dtype, o.K, o.sigma, o.cg_tol, o.cg_max_iter, o.eig_max_sweeps, o.eig_tol = 0, 5, 1e-6, 1e-6, 100, 30, 0.0
     o.eig_refine = 1
+    o.eig_warm_start = 1
     for k, v in kw.items():
         setattr(o, k, v)
     return o
@@ -90,7 +91,8 @@ def test_invalid_problem_rejected_on_host(L, case):
 
 
 @pytest.mark.parametrize("kw", [dict(K=0), dict(sigma=0.0), dict(cg_max_iter=0), dict(dtype=5),
-                                dict(eig_max_sweeps=0), dict(cg_tol=-1.0), dict(eig_refine=-1)])
+                                dict(eig_max_sweeps=0), dict(cg_tol=-1.0), dict(eig_refine=-1),
+                                dict(eig_warm_start=2)])
 def test_invalid_options_rejected(L, kw):
     p, keep = _problem(L)
     h = ctypes.c_void_p()

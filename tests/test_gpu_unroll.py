@@ -120,3 +120,25 @@ def test_c2_small_batch_fp32_forward_backward():
     batch, fw, loss, bw, st = _run(insts, K, np.float32, rhos, alphas)
     assert st["nonfinite"].max() == 0
     _check(batch, fw, loss, bw, insts, rhos, alphas, 1e-5, 1e-4, every_k=True)
+
+
+def test_first_instance_and_forward_only_path_fp64():
+    """Regression: the (x, s, y) ping-pong buffers of the reverse pass (and of
+    the forward-only path) hold 64-element-aligned parts; with n, m not
+    multiples of 64 the first instance of a batch is the one that would see
+    an undersized buffer."""
+    ensure_lib()
+    from paper_2606_13825_amd import CosmoBatch
+    rng = np.random.default_rng(61)
+    inst = synth.c2_batch(B=1, p_lo=39, p_hi=39, seed=61)[0]
+    K = 3
+    rhos, alphas = _stack_hyper([inst], K, rng, dtype=np.float64)
+    say(f"first-instance gradients fp64 n={inst.n} m={inst.m} K={K}")
+    batch, fw, loss, bw, st = _run([inst], K, np.float64, rhos, alphas, cg_tol=1e-13)
+    _check(batch, fw, loss, bw, [inst], rhos, alphas, 1e-10, 1e-9, every_k=True)
+    rho = torch.from_numpy(rhos[0]).to(DEV)
+    alpha = torch.from_numpy(alphas[0].reshape(K, 1)).to(DEV)
+    plain = batch.forward(rho, alpha, tape=False)
+    torch.cuda.synchronize()
+    for a, b in ((plain.x, fw.x), (plain.s, fw.s), (plain.y, fw.y)):
+        assert torch.equal(a, b)

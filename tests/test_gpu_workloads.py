@@ -1,0 +1,94 @@
+"""Parity of the remaining workload families on the GPU against the float64
+oracle: Lovasz theta on circulant graphs (repeated eigenvalues, PSD orders
+up to 200), Huber-regression SOCPs (nonnegative + SOC cones, dense block,
+genuine CG), covariance-steering SDPs (many small PSD blocks, sparse A,
+genuine CG).  Reduced batches are compared instance by instance; the full
+batch of each workload is run in the launch configuration the benchmark uses
+and checked on a sample of instances."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_common import assert_close, ensure_lib, floor_of, oracle_run, say
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _hyper(insts, K, seed, spread=0.5):
+    rng = np.random.default_rng(seed)
+    rhos, alphas = [], []
+    for inst in insts:
+        r, a = synth.perturbed_hyper(inst, K, rng, spread=spread)
+        rhos.append(r.astype(np.float32))
+        alphas.append(a.astype(np.float32))
+    return rhos, alphas
+
+
+def _run_and_check(insts, K, rhos, alphas, check_idx, tol_it, tol_g, **kw):
+    from paper_2606_13825_amd import CosmoBatch
+    batch = CosmoBatch(insts, K=K, dtype=torch.float32, device=DEV, **kw)
+    rho = torch.from_numpy(np.concatenate(rhos, axis=1)).to(DEV)
+    alpha = torch.from_numpy(np.stack(alphas, axis=1)).to(DEV)
+    stats = batch.new_stats()
+    fw = batch.forward(rho, alpha, stats=stats)
+    loss, g = batch.residual_loss(fw.x, fw.s, fw.y)
+    bw = batch.backward(rho, alpha, fw.tape, *g, stats=stats)
+    torch.cuda.synchronize()
+    st = batch.stats_dict(stats)
+    say(f"  stats: cg_iters_max={st['cg_iters_max'].max()} cg_not_conv={st['cg_not_converged'].sum()} "
+        f"eig_sweeps_max={st['eig_sweeps_max'].max()} eig_not_conv={st['eig_not_converged'].sum()}")
+    assert st["nonfinite"].max() == 0
+    errs = []
+    for i in check_idx:
+        inst = insts[i]
+        ref = oracle_run(inst, rhos[i].astype(np.float64), alphas[i].astype(np.float64))
+        fl = floor_of(inst)
+        sl_n = slice(batch.n_off[i], batch.n_off[i + 1])
+        sl_m = slice(batch.m_off[i], batch.m_off[i + 1])
+        e = []
+        for nm, g_, r_ in (("x", fw.x[sl_n], ref["x"]), ("s", fw.s[sl_m], ref["s"]), ("y", fw.y[sl_m], ref["y"])):
+            e.append(assert_close(g_.double().cpu().numpy(), r_, tol_it, fl, f"inst {i} final {nm}"))
+        e.append(assert_close(bw.grho[:, sl_m].double().cpu().numpy(), ref["grho"], tol_g, 0.0, f"inst {i} grad rho"))
+        e.append(assert_close(bw.galpha[:, i].double().cpu().numpy(), ref["galpha"], tol_g, 0.0,
+                              f"inst {i} grad alpha"))
+        errs.append(max(e))
+    say(f"  max rel err over checked instances: {max(errs):.2e}")
+    return batch
+
+
+def test_lovasz_circulant_reduced():
+    ensure_lib()
+    insts = [x.astype(np.float32) for x in synth.c3_batch(B=4, n_lo=16, n_hi=40, seed=31)]
+    K = 20
+    rhos, alphas = _hyper(insts, K, 32)
+    say(f"Lovasz circulant B=4 orders={[i.meta['order'] for i in insts]} K={K}")
+    _run_and_check(insts, K, rhos, alphas, range(4), 1e-5, 1e-4)
+
+
+def test_lovasz_circulant_large_orders():
+    ensure_lib()
+    insts = [x.astype(np.float32) for x in synth.c3_batch(B=2, n_lo=150, n_hi=200, seed=33)]
+    K = 6
+    rhos, alphas = _hyper(insts, K, 34)
+    say(f"Lovasz circulant B=2 orders={[i.meta['order'] for i in insts]} K={K}")
+    _run_and_check(insts, K, rhos, alphas, range(2), 2e-5, 2e-4)
+
+
+def test_huber_socp_reduced():
+    ensure_lib()
+    insts = [x.astype(np.float32) for x in synth.c4_batch(B=3, seed=41, n_obs=200, n_coef=50, n_soc=20)]
+    K = 10
+    rhos, alphas = _hyper(insts, K, 42)
+    say(f"Huber SOCP B=3 n={insts[0].n} m={insts[0].m} K={K}")
+    _run_and_check(insts, K, rhos, alphas, range(3), 1e-4, 1e-3, cg_tol=1e-7, cg_max_iter=1000)
+
+
+def test_covsteer_reduced():
+    ensure_lib()
+    insts = [x.astype(np.float32) for x in synth.c5_batch(B=3, seed=51, nx_choices=(4, 6), T_lo=5, T_hi=8)]
+    K = 8
+    rhos, alphas = _hyper(insts, K, 52)
+    say(f"covariance steering B=3 n={[i.n for i in insts]} m={[i.m for i in insts]} K={K}")
+    _run_and_check(insts, K, rhos, alphas, range(3), 1e-4, 1e-3, cg_tol=1e-7, cg_max_iter=2000)
