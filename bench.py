@@ -82,7 +82,12 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick", action="store_true",
+                    help="counter-collection run: the timed steps only (no plain-forward comparison, "
+                         "no event-timed step, no CPU leg)")
     args = ap.parse_args()
+    if args.quick:
+        args.no_cpu_baseline = True
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU: the batch shards over instances with no "
                                    "exchange inside the unroll, but runs on more than one GPU are not part of it"}))
@@ -138,6 +143,11 @@ def main():
     dt = (time.perf_counter() - t0) / args.steps
     peak_fb = torch.cuda.max_memory_allocated(dev) - base_mem
     print(f"[bench] fwd+bwd {dt * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+
+    if args.quick:
+        print(json.dumps({"metric": "fwd+bwd unrolled COSMO iters/s (counter-collection run)",
+                          "value": B * K / dt, "unit": "instance-iterations/s", "ms_per_step": dt * 1e3}))
+        return
 
     # dominant kernel families, timed with HIP events on the call's stream
     batch.set_profiling(True)

@@ -108,10 +108,12 @@ typedef struct {
   int32_t cg_max_iter;         /* >= 1                                                   */
   int32_t eig_max_sweeps;      /* Jacobi sweep cap, >= 1                                 */
   double eig_tol;              /* Jacobi column-orthogonality threshold; 0 = dtype default */
-  int32_t eig_refine;          /* float64 refinement steps applied to the float32
-                                  eigenpairs of every PSD block (Ogita-Aishima); the
-                                  projection is then formed in float64.  Ignored for
-                                  COSMO_F64, whose sweeps already run in float64.       */
+  int32_t eig_refine;          /* 1: refine the float32 eigenpairs of every PSD block
+                                  once (Ogita-Aishima step with float64-accumulated
+                                  residual products) and form the projection by
+                                  Rayleigh-Ritz on the positive subspace; 0: use
+                                  the Jacobi eigenpairs as they are.  Must be 0 or 1;
+                                  ignored for COSMO_F64, whose sweeps run in float64. */
   int32_t eig_warm_start;      /* 1: start every step's Jacobi sweeps from the same
                                   block's eigenvectors of the previous step (same
                                   decomposition, fewer sweeps); 0: start from S.        */
@@ -187,7 +189,7 @@ cosmo_status cosmo_residual_loss(cosmo_plan *plan, const void *x, const void *s,
  * each block inside `in` / `out`.  Block rows must not overlap. */
 
 /* Bytes of device workspace for psd_proj / psd_proj_vjp / socp_proj(_vjp):
- * block descriptors plus 3 p^2 float64 of refinement scratch per PSD block. */
+ * block descriptors plus 3 p^2 float64 of eigensolver scratch per PSD block. */
 size_t cosmo_proj_workspace_size(int32_t nblk, const int32_t *order_or_dim);
 
 /* eq:psd-proj per block: out = svec(U max(L, 0) U') of S = smat(in).

@@ -70,15 +70,20 @@ template <typename T> struct View {
   T sigma;
 };
 
-struct Launch {
-  hipStream_t stream;
+// Outputs of the in-kernel diagonal solve (all null: the PCG kernel solves).
+// Forward: xt = x~, xn = x+, alpha_k per instance.  Adjoint: xt = w,
+// xn = the cotangent of x.
+template <typename T> struct DiagSolve {
+  T *xt = nullptr;
+  T *xn = nullptr;
+  const T *alpha_k = nullptr;
 };
 
 // vector / row-wise kernels (k_vec.hip)
 template <typename T> void launch_rectify(const View<T> &v, const RectDesc *rect, int32_t nrect, const T *rho,
                                           T *rho_hat, int32_t K, hipStream_t st);
 template <typename T> void launch_cols_pre(const View<T> &v, const RowBuckets &bk, const T *rho_hat, const T *x,
-                                           const T *s, const T *y, T *dg, T *xi, hipStream_t st);
+                                           const T *s, const T *y, T *dg, T *xi, DiagSolve<T> ds, hipStream_t st);
 template <typename T> void launch_rows_post(const View<T> &v, const RowBuckets &bk, const T *rho_hat,
                                             const T *alpha_k, const T *xt, const T *s, const T *y, T *st_out,
                                             T *sh, T *vv, T *s_new, T *y_new, hipStream_t st);
@@ -92,7 +97,7 @@ template <typename T> void launch_bwd_rows_b(const View<T> &v, const T *rho_hat,
                                              T *gsh, T *gst, T *gs_out, T *gy_out, T *grh, hipStream_t st);
 template <typename T> void launch_bwd_cols(const View<T> &v, const RowBuckets &bk, const T *rho_hat,
                                            const T *alpha_k, const T *gst, const T *gx_in, T *gxt, T *dg,
-                                           hipStream_t st);
+                                           DiagSolve<T> ds, hipStream_t st);
 template <typename T> void launch_bwd_rows_c(const View<T> &v, const RowBuckets &bk, const T *rho_hat,
                                              const T *w, const T *stl, const T *s, T *grh, T *gs_out,
                                              T *gy_out, hipStream_t st);

@@ -118,11 +118,17 @@ __global__ __launch_bounds__(PT) void k_pcg(View<T> v, const T *__restrict__ rho
   block_sum2(rz, rr, red);
   block_sum2(bb, dummy, red);
   const T thr = tol * tol * bb;
+  // A non-finite right-hand side, operator or iterate ends the solve and
+  // marks its solution non-finite (rather than leaving the finite warm start).
+  bool fail = !(isfinite(rr) && isfinite(bb));
   int it = 0;
-  while (rr > thr && it < max_iter) {
+  while (!fail && rr > thr && it < max_iter) {
     __syncthreads();   // p complete before the operator reads it
     const T pMp = apply_M(v, rho_hat, p, t, Mp, n0, n1, m0, m1, LA, LAt, red);
-    if (!(pMp > (T)0)) break;   // breakdown (or NaN): keep the current x
+    if (!(pMp > (T)0)) {   // breakdown at round-off level: keep the current x
+      fail = !isfinite(pMp);
+      break;
+    }
     const T a = rz / pMp;
     T rz_new = 0, rr_new = 0;
     for (int64_t j = n0 + threadIdx.x; j < n1; j += PT) {
@@ -138,9 +144,12 @@ __global__ __launch_bounds__(PT) void k_pcg(View<T> v, const T *__restrict__ rho
     const T beta = rz_new / rz;
     rz = rz_new;
     rr = rr_new;
+    fail = !isfinite(rr);
     for (int64_t j = n0 + threadIdx.x; j < n1; j += PT) p[j] = z[j] + beta * p[j];
     ++it;
   }
+  if (fail)
+    for (int64_t j = n0 + threadIdx.x; j < n1; j += PT) x[j] = (T)NAN;
   // epilogue (each thread touches only the columns it owns below)
   const T al = alpha_k ? alpha_k[b] : (T)1;
   if (mode == 0) {
@@ -151,7 +160,7 @@ __global__ __launch_bounds__(PT) void k_pcg(View<T> v, const T *__restrict__ rho
   }
   if (stats && threadIdx.x == 0) {
     atomicMax(&stats[b].cg_iters_max, it);
-    if (rr > thr) atomicAdd(&stats[b].cg_not_converged, 1);
+    if (!(rr <= thr)) atomicAdd(&stats[b].cg_not_converged, 1);
   }
 }
 

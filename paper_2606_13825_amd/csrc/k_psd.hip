@@ -20,6 +20,8 @@
 // Reconstruction Pi = U diag(max(lam, 0)) U' and the four products of the DK
 // rule U (L o (U' T U)) U' run on the matrix cores (v_mfma 16x16x4, FP32 or
 // FP64), on 16 x 16 output tiles, one wave per tile.
+#include <type_traits>
+
 #include "cosmo_internal.h"
 
 namespace cosmo {
@@ -102,6 +104,103 @@ template <typename T, int NT> __device__ inline T wg_max(T v, T *red) {
   return t;
 }
 
+// Leading dimension of a p x p block held in LDS.  In order classes up to
+// 128 the G lanes of a Jacobi pair read rows gl, gl + G, ... of a column
+// without masks: columns are padded with zero rows to a multiple of G and
+// then to an odd multiple of 8 words, so the groups of a wave, which work on
+// consecutive columns in the circle schedule, read disjoint LDS banks.  In the
+// largest class a block alone nearly fills the LDS: even orders pad to the
+// next odd one and reads past row p are clamped.  p * eig_ld(p) does not
+// decrease with p.
+template <int G, int PMAX> __host__ __device__ constexpr int eig_ld(int p) {
+  return PMAX <= 128 ? 8 * ((G * ((p + G - 1) / G) + 7) / 8 | 1) : (p | 1);
+}
+
+// Cross-lane moves inside rows of 16 lanes (DPP): quad_perm [1,0,3,2] and
+// [2,3,0,1], row_half_mirror, row_mirror.
+template <int CTRL> __device__ inline float dpp_mov(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL> __device__ inline double dpp_mov(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// Sum over aligned groups of G = 4, 8 or 16 lanes, in every lane of the group.
+template <int G, typename T> __device__ inline T group_sum(T x) {
+  static_assert(G == 4 || G == 8 || G == 16, "group of 4, 8 or 16 lanes");
+  x += dpp_mov<0xB1>(x);
+  x += dpp_mov<0x4E>(x);
+  if constexpr (G >= 8) x += dpp_mov<0x141>(x);
+  if constexpr (G >= 16) x += dpp_mov<0x140>(x);
+  return x;
+}
+
+// Jacobi rotation (cs, sn) that makes columns with squared norms al, be and
+// inner product ga orthogonal (smaller angle, |tan| <= 1).  Float32 uses the
+// hardware reciprocal and reciprocal square root: any rotation with
+// cs^2 + sn^2 = 1 to working precision is valid, a slightly inexact angle only
+// leaves a little more for the next sweep.
+__device__ inline void jacobi_rot(float al, float be, float ga, float &cs, float &sn) {
+  const float zeta = (be - al) * __builtin_amdgcn_rcpf(2.f * ga);
+  const float tt = __builtin_amdgcn_rcpf(fabsf(zeta) + __builtin_amdgcn_sqrtf(1.f + zeta * zeta));
+  cs = __builtin_amdgcn_rsqf(1.f + tt * tt);
+  sn = copysignf(cs * tt, zeta);
+}
+__device__ inline void jacobi_rot(double al, double be, double ga, double &cs, double &sn) {
+  const double zeta = (be - al) / (2.0 * ga);
+  const double tt = 1.0 / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  cs = 1.0 / sqrt(1.0 + tt * tt);
+  sn = copysign(cs * tt, zeta);
+}
+
+// Two 16 x 16 tiles C1 = A B1, C2 = A B2 sharing the A operand.
+template <typename T, typename FA, typename FB1, typename FB2>
+__device__ inline void tile_mma2(int I0, int J0, int kdim, FA fa, FB1 fb1, FB2 fb2, typename Mma<T>::v4 &c1,
+                                 typename Mma<T>::v4 &c2) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, kk = lane >> 4;
+  c1 = typename Mma<T>::v4{0, 0, 0, 0};
+  c2 = typename Mma<T>::v4{0, 0, 0, 0};
+  for (int k0 = 0; k0 < kdim; k0 += 4) {
+    const int k = k0 + kk;
+    const T a = fa(I0 + r, k);
+    c1 = Mma<T>::op(a, fb1(k, J0 + r), c1);
+    c2 = Mma<T>::op(a, fb2(k, J0 + r), c2);
+  }
+}
+
+// Runs comp(t) for the tiles t = wave, wave + nw, ... below ntiles and stores
+// each result with wr(t, result).  INPL: the wave keeps all its results in
+// registers until every wave has finished computing (one barrier), so wr may
+// overwrite what comp reads; HOLD must cover the tiles of one wave.  Ends
+// with a barrier.
+template <int HOLD, bool INPL, typename Fc, typename Fw>
+__device__ inline void tile_pass(int ntiles, int wave, int nw, Fc comp, Fw wr) {
+  if constexpr (INPL) {
+    decltype(comp(0)) hold[HOLD];
+#pragma unroll
+    for (int h = 0; h < HOLD; ++h) {
+      const int t = wave + h * nw;
+      if (t < ntiles) hold[h] = comp(t);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < HOLD; ++h) {
+      const int t = wave + h * nw;
+      if (t < ntiles) wr(t, hold[h]);
+    }
+  } else {
+    for (int t = wave; t < ntiles; t += nw) wr(t, comp(t));
+  }
+  __syncthreads();
+}
+
+struct Acc2d {
+  Mma<double>::v4 g, h;
+};
+
 // mode 0: COSMO step on the block (s+ and y+ rows); mode 1: projection only.
 template <typename T, int NT, int G, int PMAX>
 __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ descs, int32_t max_sweeps, T tol_base,
@@ -115,13 +214,15 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
   T *W = reinterpret_cast<T *>(smem_raw);
   __shared__ T red[NT / 64];
   __shared__ double redd[2 * (NT / 64)];
-  __shared__ double lamd[MAXP];
-  __shared__ int pos_idx[MAXP];
+  __shared__ double lamd[PMAX];
+  __shared__ short pos_idx[PMAX];
+  __shared__ signed char cls[PMAX];
   __shared__ int flags[3];
   __shared__ int npos_s;
 
   const PsdDesc d = descs[blockIdx.x];
   const int p = d.p;
+  const int ld = eig_ld<G, PMAX>(p);
   const int nrows = p * (p + 1) / 2;
   const T *v = vin + d.row0;
   const int tid = threadIdx.x;
@@ -134,15 +235,36 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
     T val = v[idx];
     fro2 += val * val;
     if (i != j) val *= (T)RSQRT2;
-    W[i + j * p] = val;
-    W[j + i * p] = val;
+    W[i + j * ld] = val;
+    W[j + i * ld] = val;
+  }
+  constexpr bool PADDED = PMAX <= 128;   // zero rows up to a multiple of G (see eig_ld)
+  const int ne = (p + G - 1) / G;         // column rows per Jacobi lane
+  if constexpr (PADDED) {
+    const int npad = G * ne - p;
+    for (int e = tid; e < npad * p; e += NT) {
+      const int j = e / npad;
+      W[p + (e - j * npad) + j * ld] = (T)0;
+    }
   }
   if (tid < 3) flags[tid] = 0;
   fro2 = wg_sum<T, NT>(fro2, red);   // contains barriers: W complete after this
+  if (!isfinite(fro2)) {
+    // a non-finite block yields a non-finite projection (never a clipped one)
+    for (int idx = tid; idx < nrows; idx += NT) {
+      s_new[d.row0 + idx] = (T)NAN;
+      if (mode == 0) y_new[d.row0 + idx] = (T)NAN;
+    }
+    if (lamout)
+      for (int i = tid; i < p; i += NT) lamout[d.loff + i] = (T)NAN;
+    if (Uout)
+      for (int e = tid; e < p * p; e += NT) Uout[d.uoff + e] = (T)NAN;
+    return;   // fro2 is the same in every thread: the whole workgroup leaves
+  }
   T rowmax = 0;
   for (int i = tid; i < p; i += NT) {
     T a = 0;
-    for (int j = 0; j < p; ++j) a += fabs(W[i + j * p]);
+    for (int j = 0; j < p; ++j) a += fabs(W[i + j * ld]);
     rowmax = fmax(rowmax, a);
   }
   const T inf = wg_max<T, NT>(rowmax, red);
@@ -171,11 +293,11 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int row = I * 16 + Mma<T>::row(lane0, e);
-        if (row < p && col < p) W[row + col * p] = acc[e] + c * Up[row + col * p];
+        if (row < p && col < p) W[row + col * ld] = acc[e] + c * Up[row + col * p];
       }
     }
   } else {
-    for (int i = tid; i < p; i += NT) W[i + i * p] += c;
+    for (int i = tid; i < p; i += NT) W[i + i * ld] += c;
   }
   __syncthreads();
 
@@ -187,54 +309,57 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
   constexpr int MAXE = (PMAX + G - 1) / G;   // column elements held per lane
   int sweep = 0;
   bool converged = (p == 1);
+  const T tol2 = tol * tol;
   for (; sweep < max_sweeps && !converged; ++sweep) {
     const int fslot = sweep % 3;
     for (int r = 0; r < P - 1; ++r) {
       for (int k = grp; k < npairs; k += ngroups) {
+        // circle schedule: column P-1 stays, the others rotate by one per round
         int a, b;
         if (k == 0) {
           a = r;
           b = P - 1;
         } else {
-          a = (r + k) % (P - 1);
-          b = (r - k + P - 1) % (P - 1);
+          a = r + k;
+          if (a >= P - 1) a -= P - 1;
+          b = r - k;
+          if (b < 0) b += P - 1;
         }
-        if (a >= p || b >= p) continue;   // dummy column of an odd order
-        if (a > b) {
-          const int tmp = a;
-          a = b;
-          b = tmp;
-        }
-        T *wa = W + a * p;
-        T *wb = W + b * p;
+        const bool live = a < p && b < p;   // else the dummy column of an odd order
+        T *wa = W + (live ? a : 0) * ld;
+        T *wb = W + (live ? b : 0) * ld;
+        // Rows past the lane's last one (e >= ne) re-read that row (or row
+        // p - 1 in the unpadded class) and are masked out of the sums; their
+        // stores repeat the value stored for that row, so no branch is needed.
         T xa[MAXE], xb[MAXE];
+        int row[MAXE];
+#pragma unroll
+        for (int e = 0; e < MAXE; ++e) {
+          int rw = gl + (e < ne ? e : ne - 1) * G;
+          if constexpr (!PADDED) rw = rw < p ? rw : p - 1;
+          row[e] = rw;
+          xa[e] = wa[rw];
+          xb[e] = wb[rw];
+        }
         T al = 0, be = 0, ga = 0;
 #pragma unroll
         for (int e = 0; e < MAXE; ++e) {
-          const int i = gl + e * G;
-          xa[e] = (i < p) ? wa[i] : (T)0;
-          xb[e] = (i < p) ? wb[i] : (T)0;
-          al += xa[e] * xa[e];
-          be += xb[e] * xb[e];
-          ga += xa[e] * xb[e];
+          const bool in = e < ne && (PADDED || gl + e * G < p);
+          const T u = in ? xa[e] : (T)0, w = in ? xb[e] : (T)0;
+          al += u * u;
+          be += w * w;
+          ga += u * w;
         }
-        for (int off = G >> 1; off > 0; off >>= 1) {
-          al += __shfl_xor(al, off, 64);
-          be += __shfl_xor(be, off, 64);
-          ga += __shfl_xor(ga, off, 64);
-        }
-        if (fabs(ga) > tol * sqrt(al * be)) {
-          const T zeta = (be - al) / ((T)2 * ga);
-          const T tt = (zeta >= (T)0 ? (T)1 : (T)-1) / (fabs(zeta) + sqrt((T)1 + zeta * zeta));
-          const T cs = (T)1 / sqrt((T)1 + tt * tt);
-          const T sn = cs * tt;
+        al = group_sum<G>(al);
+        be = group_sum<G>(be);
+        ga = group_sum<G>(ga);
+        if (live && ga * ga > tol2 * al * be) {
+          T cs, sn;
+          jacobi_rot(al, be, ga, cs, sn);
 #pragma unroll
           for (int e = 0; e < MAXE; ++e) {
-            const int i = gl + e * G;
-            if (i < p) {
-              wa[i] = cs * xa[e] - sn * xb[e];
-              wb[i] = sn * xa[e] + cs * xb[e];
-            }
+            wa[row[e]] = cs * xa[e] - sn * xb[e];
+            wb[row[e]] = sn * xa[e] + cs * xb[e];
           }
           if (gl == 0) flags[fslot] = 1;
         }
@@ -248,15 +373,16 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
 
   // eigenpairs: lam_i = ||w_i|| - c, u_i = w_i / ||w_i||
   for (int i = tid; i < p; i += NT) {
-    const T *wi = W + i * p;
+    const T *wi = W + i * ld;
     double ss = 0;
     for (int r = 0; r < p; ++r) ss += (double)wi[r] * (double)wi[r];
     lamd[i] = sqrt(ss);
   }
   __syncthreads();
   for (int e = tid; e < p * p; e += NT) {
-    const double sg = lamd[e / p];
-    W[e] = sg > 0.0 ? (T)((double)W[e] / sg) : (T)0;
+    const int j = e / p, i = e - j * p;
+    const double sg = lamd[j];
+    W[i + j * ld] = sg > 0.0 ? (T)((double)W[i + j * ld] / sg) : (T)0;
   }
   __syncthreads();
   for (int i = tid; i < p; i += NT) lamd[i] -= (double)c;
@@ -265,256 +391,288 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
   const int nt = (p + 15) / 16;
   const int wave = tid >> 6, lane = tid & 63;
   constexpr int NWv = NT / 64;
-  const int pp = p * p;
-
-  // Optional float64 refinement of the float32 eigenpairs (Ogita & Aishima,
-  // "Iterative refinement for symmetric eigenvalue decomposition", 2018):
-  //   R = I - X'X,  S~ = X' S X,  lam_i = S~_ii / (1 - R_ii),
-  //   delta = 2 (||S~ - diag(lam)|| + ||S|| ||R||)   (Frobenius bounds),
-  //   E_ij = (S~_ij + lam_j R_ij) / (lam_j - lam_i) if |lam_j - lam_i| > delta, else R_ij / 2,
-  //   X <- X + X E.
-  // Every product is accumulated in float64 on the matrix cores.  Pairs
-  // closer than delta (and pairs whose correction would not be small) are
-  // only re-orthogonalised; the projection is then formed by Rayleigh-Ritz on
-  // the positive subspace, Pi = X+ (X+' S X+) X+', which depends on the split
-  // between positive and non-positive eigenvalues only, not on how the
-  // eigenvectors are chosen inside a cluster.
-  const double *Xg = nullptr;   // refined eigenvectors in global float64 scratch
-  double *bA = nullptr, *bE = nullptr, *bX = nullptr;
-  if (refine > 0) {
-    bA = rscratch + 3 * d.uoff;
-    bE = bA + pp;
-    bX = bE + pp;
-    double *xdst = bX;
-    const double sfro = sqrt((double)fro2);
-    for (int step = 0; step < refine; ++step) {
-      const double *xs = Xg;
-      auto X = [&](int i, int j) -> double { return xs ? xs[i + j * p] : (double)W[i + j * p]; };
-      auto Sv = [&](int i, int k) -> double {
-        const int a = i < k ? i : k, b = i < k ? k : i;
-        const double val = (double)v[b * (b + 1) / 2 + a];
-        return a == b ? val : val * RSQRT2;
-      };
-      // A1 = S X
-      for (int t = wave; t < nt * nt; t += NWv) {
-        const int I = t / nt, J = t % nt;
-        const typename Mma<double>::v4 acc = tile_mma<double>(
-            I * 16, J * 16, p, [&](int i, int k) -> double { return (i < p && k < p) ? Sv(i, k) : 0.0; },
-            [&](int k, int j) -> double { return (k < p && j < p) ? X(k, j) : 0.0; });
-        const int col = J * 16 + (lane & 15);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int row = I * 16 + Mma<double>::row(lane, e);
-          if (row < p && col < p) bA[row + col * p] = acc[e];
-        }
-      }
-      __syncthreads();
-      for (int i = tid; i < p; i += NT) {
-        double si = 0, gi = 0;
-        for (int r = 0; r < p; ++r) {
-          const double xr = X(r, i);
-          si += xr * bA[r + i * p];
-          gi += xr * xr;
-        }
-        lamd[i] = si / gi;
-      }
-      __syncthreads();
-      // pass 1: Frobenius norms of S~ - diag(lam) and R; pass 2: E
-      double nS = 0, nR = 0, delta = 0;
-      for (int pass = 0; pass < 2; ++pass) {
-        for (int t = wave; t < nt * nt; t += NWv) {
-          const int I = t / nt, J = t % nt;
-          auto fxt = [&](int i, int k) -> double { return (i < p && k < p) ? X(k, i) : 0.0; };
-          const typename Mma<double>::v4 as = tile_mma<double>(
-              I * 16, J * 16, p, fxt, [&](int k, int j) -> double { return (k < p && j < p) ? bA[k + j * p] : 0.0; });
-          const typename Mma<double>::v4 ag = tile_mma<double>(
-              I * 16, J * 16, p, fxt, [&](int k, int j) -> double { return (k < p && j < p) ? X(k, j) : 0.0; });
-          const int col = J * 16 + (lane & 15);
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int row = I * 16 + Mma<double>::row(lane, e);
-            if (row < p && col < p) {
-              const double rij = (row == col ? 1.0 : 0.0) - ag[e];
-              if (pass == 0) {
-                const double dv = (row == col) ? as[e] - lamd[row] : as[e];
-                nS += dv * dv;
-                nR += rij * rij;
-              } else {
-                const double li = lamd[row], lj = lamd[col];
-                const double num = as[e] + lj * rij, gap = lj - li;
-                // The projection and the Loewner-weighted VJP depend only on
-                // the split between positive and non-positive eigenvalues, so
-                // only pairs across that split are rotated, and only when the
-                // correction is small (|E_ij| <= 1e-3); every other pair is
-                // re-orthogonalised.  The test is symmetric in (i, j), so
-                // E + E' = R entry by entry and X stays orthonormal to second
-                // order.
-                const double cpl = fabs(as[e]) + fmax(fabs(li), fabs(lj)) * fabs(rij);
-                const bool rotate = (li * lj < 0.0) && fabs(gap) > delta && cpl <= 1e-3 * fabs(gap);
-                bE[row + col * p] = rotate ? num / gap : 0.5 * rij;
-              }
-            }
-          }
-        }
-        if (pass == 0) {
-          for (int off = 32; off > 0; off >>= 1) {
-            nS += __shfl_xor(nS, off, 64);
-            nR += __shfl_xor(nR, off, 64);
-          }
-          __syncthreads();
-          if (lane == 0) {
-            redd[wave] = nS;
-            redd[NWv + wave] = nR;
-          }
-          __syncthreads();
-          double ts = 0, tr = 0;
-          for (int w = 0; w < NWv; ++w) {
-            ts += redd[w];
-            tr += redd[NWv + w];
-          }
-          delta = 2.0 * (sqrt(ts) + sfro * sqrt(tr));
-        }
-      }
-      __syncthreads();
-      // X <- X + X E  (into the buffer not being read)
-      for (int t = wave; t < nt * nt; t += NWv) {
-        const int I = t / nt, J = t % nt;
-        const typename Mma<double>::v4 acc = tile_mma<double>(
-            I * 16, J * 16, p, [&](int i, int k) -> double { return (i < p && k < p) ? X(i, k) : 0.0; },
-            [&](int k, int j) -> double { return (k < p && j < p) ? bE[k + j * p] : 0.0; });
-        const int col = J * 16 + (lane & 15);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int row = I * 16 + Mma<double>::row(lane, e);
-          if (row < p && col < p) xdst[row + col * p] = X(row, col) + acc[e];
-        }
-      }
-      __syncthreads();
-      Xg = xdst;
-      xdst = (xdst == bX) ? bA : bX;
-    }
-  }
-
-  if (lamout)
-    for (int i = tid; i < p; i += NT) lamout[d.loff + i] = (T)lamd[i];
-  if (Uout)
-    for (int e = tid; e < pp; e += NT) Uout[d.uoff + e] = Xg ? (T)Xg[e] : W[e];
-  if (tid == 0) {
-    int np = 0;
-    for (int i = 0; i < p; ++i)
-      if (lamd[i] > 0.0) pos_idx[np++] = i;
-    npos_s = np;
-    if (stats) {
-      atomicMax(&stats[d.inst].eig_sweeps_max, sweep);
-      if (!converged) atomicAdd(&stats[d.inst].eig_not_converged, 1);
-    }
-  }
-  __syncthreads();
-  const int npos = npos_s;
-
+  constexpr int NTMAX = (PMAX + 15) / 16;
+  constexpr int HOLD = (NTMAX * NTMAX + NWv - 1) / NWv;
+  constexpr int HOLDU = (NTMAX * (NTMAX + 1) / 2 + NWv - 1) / NWv;
   const int ntiles = nt * (nt + 1) / 2;
   const T *yb = y + d.row0;
   const T *shb = sh + d.row0;
   const T rh = (mode == 0) ? rho_hat[d.row0] : (T)0;
-  const int ntp = (npos + 15) / 16;
-  double *Mrr = nullptr;   // X+' S X+  (npos x npos) for the Rayleigh-Ritz form
-  double *Crr = nullptr;   // X+ (X+' S X+)  (p x npos)
-  if (Xg && npos > 0) {
-    double *free1 = (Xg == bA) ? bX : bA;
-    double *free2 = bE;
-    auto Sv = [&](int i, int k) -> double {
-      const int a = i < k ? i : k, b = i < k ? k : i;
-      const double val = (double)v[b * (b + 1) / 2 + a];
-      return a == b ? val : val * RSQRT2;
-    };
-    // T1 = S X+  (p x npos) -> free1
-    for (int t = wave; t < nt * ntp; t += NWv) {
-      const int I = t / ntp, J = t % ntp;
-      const typename Mma<double>::v4 acc = tile_mma<double>(
-          I * 16, J * 16, p, [&](int i, int k) -> double { return (i < p && k < p) ? Sv(i, k) : 0.0; },
-          [&](int k, int j) -> double { return (k < p && j < npos) ? Xg[k + pos_idx[j] * p] : 0.0; });
-      const int col = J * 16 + (lane & 15);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int row = I * 16 + Mma<double>::row(lane, e);
-        if (row < p && col < npos) free1[row + col * p] = acc[e];
-      }
+  // svec entry (row, col), row <= col, of the projection, and the y+ row
+  auto put = [&](int row, int col, double val) {
+    const int idx = col * (col + 1) / 2 + row;
+    const T o = (T)((row == col) ? val : val * SQRT2);
+    s_new[d.row0 + idx] = o;
+    if (mode == 0) y_new[d.row0 + idx] = yb[idx] + rh * (shb[idx] - o);
+  };
+  auto count = [&]() {
+    if (stats) {
+      atomicMax(&stats[d.inst].eig_sweeps_max, sweep);
+      if (!converged) atomicAdd(&stats[d.inst].eig_not_converged, 1);
     }
-    __syncthreads();
-    // M = X+' T1  (npos x npos) -> free2
-    for (int t = wave; t < ntp * ntp; t += NWv) {
-      const int I = t / ntp, J = t % ntp;
-      const typename Mma<double>::v4 acc = tile_mma<double>(
-          I * 16, J * 16, p, [&](int i, int k) -> double { return (i < npos && k < p) ? Xg[k + pos_idx[i] * p] : 0.0; },
-          [&](int k, int j) -> double { return (k < p && j < npos) ? free1[k + j * p] : 0.0; });
-      const int col = J * 16 + (lane & 15);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int row = I * 16 + Mma<double>::row(lane, e);
-        if (row < npos && col < npos) free2[row + col * npos] = acc[e];
-      }
-    }
-    __syncthreads();
-    // C = X+ M  (p x npos) -> free1
-    for (int t = wave; t < nt * ntp; t += NWv) {
-      const int I = t / ntp, J = t % ntp;
-      const typename Mma<double>::v4 acc = tile_mma<double>(
-          I * 16, J * 16, npos,
-          [&](int i, int k) -> double { return (i < p && k < npos) ? Xg[i + pos_idx[k] * p] : 0.0; },
-          [&](int k, int j) -> double { return (k < npos && j < npos) ? free2[k + j * npos] : 0.0; });
-      const int col = J * 16 + (lane & 15);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int row = I * 16 + Mma<double>::row(lane, e);
-        if (row < p && col < npos) free1[row + col * p] = acc[e];
-      }
-    }
-    __syncthreads();
-    Mrr = free2;
-    Crr = free1;
-  }
-  (void)Mrr;
+  };
 
-  // Pi: Rayleigh-Ritz C X+' when refined, else sum_{lam_k > 0} lam_k u_k u_k'
-  // (upper-triangle tiles only)
+  if constexpr (std::is_same<T, float>::value) {
+    if (refine > 0) {
+      // One refinement step of the float32 eigenpairs (after Ogita & Aishima,
+      // "Iterative refinement for symmetric eigenvalue decomposition", 2018)
+      // with float64-accumulated residual products, then the projection by
+      // Rayleigh-Ritz on the positive subspace.  With X the Jacobi
+      // eigenvectors and lam~ the Jacobi eigenvalues:
+      //   D = S X - X diag(lam~)                       (small; stored in float32)
+      //   R = I - X'X,  S~ = X'S X = (X'X) diag(lam~) + X'D,  lam_i = S~_ii / (1 - R_ii)
+      //   E_ij = (S~_ij + lam_j R_ij) / (lam_j - lam_i)  for pairs across the split
+      //          between positive and non-positive eigenvalues whose gap exceeds
+      //          delta = 2 (||S~ - diag(lam)||_F + ||S||_F ||R||_F) and whose
+      //          coupling is small (<= 1e-3 of the gap);  E_ij = R_ij / 2 otherwise
+      //   X <- X + X E
+      //   Pi = X+ M X+',  M = X+' S X+ to first order in E:
+      //          M_ii = lam_i,  M_ij = S~_ij + (lam_i + lam_j) R_ij / 2.
+      // The projection depends only on the positive subspace, so pairs on the
+      // same side of the split are only re-orthogonalised, and M absorbs
+      // their remaining coupling; E + E' = R entry by entry keeps X
+      // orthonormal to second order.  Only D and the products building S~ and
+      // R need float64 accumulation; the correction X E is small and runs in
+      // float32.
+      constexpr bool INPL = PMAX <= 128;   // second p x p buffer in LDS, else global scratch
+      float *Db = INPL ? W + p * ld : reinterpret_cast<float *>(rscratch + 3 * (size_t)d.uoff);
+      float *SR = INPL ? Db : Db + p * ld;   // S~ (upper) and R (lower), then E and M
+      float *Cb = Db;                        // X+ M
+      if constexpr (INPL) {
+        for (int idx = tid; idx < nrows; idx += NT) {
+          const int j = svec_col(idx);
+          const int i = idx - j * (j + 1) / 2;
+          float val = v[idx];
+          if (i != j) val *= (float)RSQRT2;
+          Db[i + j * ld] = val;
+          Db[j + i * ld] = val;
+        }
+        __syncthreads();
+      }
+      auto Sget = [&](int i, int k) -> double {
+        if constexpr (INPL) {
+          return (double)Db[i + k * ld];
+        } else {
+          const int a = i < k ? i : k, b = i < k ? k : i;
+          const double val = (double)v[b * (b + 1) / 2 + a];
+          return a == b ? val : val * RSQRT2;
+        }
+      };
+      // D = S X - X diag(lam~)
+      tile_pass<HOLD, INPL>(
+          nt * nt, wave, NWv,
+          [&](int t) {
+            const int I = t / nt, J = t % nt;
+            return tile_mma<double>(
+                I * 16, J * 16, p, [&](int i, int k) -> double { return (i < p && k < p) ? Sget(i, k) : 0.0; },
+                [&](int k, int j) -> double { return (k < p && j < p) ? (double)W[k + j * ld] : 0.0; });
+          },
+          [&](int t, const Mma<double>::v4 &acc) {
+            const int I = t / nt, J = t % nt;
+            const int col = J * 16 + (lane & 15);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int row = I * 16 + Mma<double>::row(lane, e);
+              if (row < p && col < p) Db[row + col * ld] = (float)(acc[e] - (double)W[row + col * ld] * lamd[col]);
+            }
+          });
+      // S~ into the upper triangle, R into the lower, lam_i on the diagonal
+      double nS = 0, nR = 0;
+      tile_pass<HOLDU, INPL>(
+          ntiles, wave, NWv,
+          [&](int t) {
+            int I, J;
+            upper_tile(t, I, J);
+            Acc2d a;
+            tile_mma2<double>(
+                I * 16, J * 16, p, [&](int i, int k) -> double { return (i < p && k < p) ? (double)W[k + i * ld] : 0.0; },
+                [&](int k, int j) -> double { return (k < p && j < p) ? (double)W[k + j * ld] : 0.0; },
+                [&](int k, int j) -> double { return (k < p && j < p) ? (double)Db[k + j * ld] : 0.0; }, a.g, a.h);
+            return a;
+          },
+          [&](int t, const Acc2d &a) {
+            int I, J;
+            upper_tile(t, I, J);
+            const int col = J * 16 + (lane & 15);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int row = I * 16 + Mma<double>::row(lane, e);
+              if (row <= col && col < p) {
+                const double st = a.h[e] + a.g[e] * lamd[col];
+                if (row < col) {
+                  const double r = -a.g[e];
+                  SR[row + col * ld] = (float)st;
+                  SR[col + row * ld] = (float)r;
+                  nS += 2.0 * st * st;
+                  nR += 2.0 * r * r;
+                } else {
+                  const double lam = a.g[e] > 0.0 ? st / a.g[e] : 0.0;
+                  const double r = 1.0 - a.g[e];
+                  SR[row + row * ld] = (float)lam;
+                  nS += (st - lam) * (st - lam);
+                  nR += r * r;
+                }
+              }
+            }
+          });
+      for (int off = 32; off > 0; off >>= 1) {
+        nS += __shfl_xor(nS, off, 64);
+        nR += __shfl_xor(nR, off, 64);
+      }
+      if (lane == 0) {
+        redd[wave] = nS;
+        redd[NWv + wave] = nR;
+      }
+      // refined eigenvalues, their signs, and E_ii = R_ii / 2 on the diagonal
+      for (int i = tid; i < p; i += NT) {
+        const double lam = (double)SR[i + i * ld];
+        double g = 0;
+        for (int k = 0; k < p; ++k) {
+          const double x = (double)W[k + i * ld];
+          g += x * x;
+        }
+        lamd[i] = lam;
+        cls[i] = lam > 0.0 ? 1 : (lam < 0.0 ? -1 : 0);
+        SR[i + i * ld] = (float)(0.5 * (1.0 - g));
+      }
+      __syncthreads();
+      double ts = 0, tr = 0;
+      for (int w = 0; w < NWv; ++w) {
+        ts += redd[w];
+        tr += redd[NWv + w];
+      }
+      const double delta = 2.0 * (sqrt(ts) + sqrt((double)fro2) * sqrt(tr));
+      // off-diagonal pairs i < j: across the split, E_ij into (i, j) and E_ji
+      // into (j, i); on one side, M_ij into (i, j) and E_ij = E_ji into (j, i)
+      for (int e = tid; e < p * p; e += NT) {
+        const int j = e / p, i = e - j * p;
+        if (i >= j) continue;
+        const double s = (double)SR[i + j * ld], r = (double)SR[j + i * ld];
+        const double li = lamd[i], lj = lamd[j];
+        if (li * lj < 0.0) {
+          const double gap = lj - li;
+          const double cpl = fabs(s) + fmax(fabs(li), fabs(lj)) * fabs(r);
+          const bool rot = fabs(gap) > delta && cpl <= 1e-3 * fabs(gap);
+          SR[i + j * ld] = (float)(rot ? (s + lj * r) / gap : 0.5 * r);
+          SR[j + i * ld] = (float)(rot ? (s + li * r) / (-gap) : 0.5 * r);
+        } else {
+          SR[i + j * ld] = (float)(s + 0.5 * (li + lj) * r);
+          SR[j + i * ld] = (float)(0.5 * r);
+        }
+      }
+      __syncthreads();
+      // X <- X + X E, in place in W
+      auto Eget = [&](int k, int j) -> float {
+        return (k >= j || cls[k] * cls[j] < 0) ? SR[k + j * ld] : SR[j + k * ld];
+      };
+      tile_pass<HOLD, true>(
+          nt * nt, wave, NWv,
+          [&](int t) {
+            const int I = t / nt, J = t % nt;
+            return tile_mma<float>(
+                I * 16, J * 16, p, [&](int i, int k) -> float { return (i < p && k < p) ? W[i + k * ld] : 0.f; },
+                [&](int k, int j) -> float { return (k < p && j < p) ? Eget(k, j) : 0.f; });
+          },
+          [&](int t, const Mma<float>::v4 &acc) {
+            const int I = t / nt, J = t % nt;
+            const int col = J * 16 + (lane & 15);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int row = I * 16 + Mma<float>::row(lane, e);
+              if (row < p && col < p) W[row + col * ld] += acc[e];
+            }
+          });
+      if (lamout)
+        for (int i = tid; i < p; i += NT) lamout[d.loff + i] = (float)lamd[i];
+      if (Uout)
+        for (int e = tid; e < p * p; e += NT) {
+          const int j = e / p, i = e - j * p;
+          Uout[d.uoff + e] = W[i + j * ld];
+        }
+      if (tid == 0) {
+        int np = 0;
+        for (int i = 0; i < p; ++i)
+          if (cls[i] > 0) pos_idx[np++] = (short)i;
+        npos_s = np;
+        count();
+      }
+      __syncthreads();
+      const int npos = npos_s;
+      const int ntp = (npos + 15) / 16;
+      // C = X+ M  (p x npos)
+      auto Mget = [&](int a, int b) -> float {
+        if (a == b) return (float)lamd[a];
+        return a < b ? SR[a + b * ld] : SR[b + a * ld];
+      };
+      tile_pass<HOLD, INPL>(
+          nt * ntp, wave, NWv,
+          [&](int t) {
+            const int I = t / ntp, J = t % ntp;
+            return tile_mma<float>(
+                I * 16, J * 16, npos,
+                [&](int i, int k) -> float { return (i < p && k < npos) ? W[i + pos_idx[k] * ld] : 0.f; },
+                [&](int k, int j) -> float { return (k < npos && j < npos) ? Mget(pos_idx[k], pos_idx[j]) : 0.f; });
+          },
+          [&](int t, const Mma<float>::v4 &acc) {
+            const int I = t / ntp, J = t % ntp;
+            const int col = J * 16 + (lane & 15);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int row = I * 16 + Mma<float>::row(lane, e);
+              if (row < p && col < npos) Cb[row + col * ld] = acc[e];
+            }
+          });
+      // Pi = C X+', upper-triangle tiles
+      for (int t = wave; t < ntiles; t += NWv) {
+        int I, J;
+        upper_tile(t, I, J);
+        const Mma<float>::v4 acc = tile_mma<float>(
+            I * 16, J * 16, npos, [&](int i, int k) -> float { return (i < p && k < npos) ? Cb[i + k * ld] : 0.f; },
+            [&](int k, int j) -> float { return (j < p && k < npos) ? W[j + pos_idx[k] * ld] : 0.f; });
+        const int col = J * 16 + (lane & 15);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = I * 16 + Mma<float>::row(lane, e);
+          if (row <= col && col < p) put(row, col, (double)acc[e]);
+        }
+      }
+      return;
+    }
+  }
+
+  // Unrefined: Pi = sum_{lam_k > 0} lam_k u_k u_k' (upper-triangle tiles)
+  if (lamout)
+    for (int i = tid; i < p; i += NT) lamout[d.loff + i] = (T)lamd[i];
+  if (Uout)
+    for (int e = tid; e < p * p; e += NT) {
+      const int j = e / p, i = e - j * p;
+      Uout[d.uoff + e] = W[i + j * ld];
+    }
+  if (tid == 0) {
+    int np = 0;
+    for (int i = 0; i < p; ++i)
+      if (lamd[i] > 0.0) pos_idx[np++] = (short)i;
+    npos_s = np;
+    count();
+  }
+  __syncthreads();
+  const int npos = npos_s;
   for (int t = wave; t < ntiles; t += NWv) {
     int I, J;
     upper_tile(t, I, J);
-    double accv[4];
-    int rowv[4];
-    if (Xg) {
-      const typename Mma<double>::v4 acc = tile_mma<double>(
-          I * 16, J * 16, npos,
-          [&](int i, int k) -> double { return (i >= p || k >= npos) ? 0.0 : Crr[i + k * p]; },
-          [&](int k, int j) -> double { return (j >= p || k >= npos) ? 0.0 : Xg[j + pos_idx[k] * p]; });
-      for (int e = 0; e < 4; ++e) {
-        accv[e] = acc[e];
-        rowv[e] = Mma<double>::row(lane, e);
-      }
-    } else {
-      const typename Mma<T>::v4 acc = tile_mma<T>(
-          I * 16, J * 16, npos,
-          [&](int i, int k) -> T {
-            if (i >= p || k >= npos) return (T)0;
-            const int c2 = pos_idx[k];
-            return W[i + c2 * p] * (T)lamd[c2];
-          },
-          [&](int k, int j) -> T { return (j >= p || k >= npos) ? (T)0 : W[j + pos_idx[k] * p]; });
-      for (int e = 0; e < 4; ++e) {
-        accv[e] = (double)acc[e];
-        rowv[e] = Mma<T>::row(lane, e);
-      }
-    }
+    const typename Mma<T>::v4 acc = tile_mma<T>(
+        I * 16, J * 16, npos,
+        [&](int i, int k) -> T {
+          if (i >= p || k >= npos) return (T)0;
+          const int c2 = pos_idx[k];
+          return W[i + c2 * ld] * (T)lamd[c2];
+        },
+        [&](int k, int j) -> T { return (j >= p || k >= npos) ? (T)0 : W[j + pos_idx[k] * ld]; });
     const int col = J * 16 + (lane & 15);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int row = I * 16 + rowv[e];
-      if (row <= col && col < p) {
-        const int idx = col * (col + 1) / 2 + row;
-        const T val = (T)((row == col) ? accv[e] : accv[e] * SQRT2);
-        s_new[d.row0 + idx] = val;
-        if (mode == 0) y_new[d.row0 + idx] = yb[idx] + rh * (shb[idx] - val);
-      }
+      const int row = I * 16 + Mma<T>::row(lane, e);
+      if (row <= col && col < p) put(row, col, (double)acc[e]);
     }
   }
 }
@@ -639,14 +797,18 @@ template <typename T, int NT, int G, int PMAX>
 void run_eig(const PsdDesc *d, int32_t n, int32_t max_p, const PsdLaunchCfg &cfg, int32_t mode, const T *rho_hat,
              const T *vv, const T *sh, const T *y, T *s_new, T *y_new, T *U, T *lam, cosmo_stats *stats,
              double *rscratch, const T *Uprev, hipStream_t st) {
-  const size_t dyn = (size_t)max_p * max_p * sizeof(T);
+  // The float32 refinement keeps a second p x ld buffer in LDS for classes up
+  // to order 128, in the global scratch above.
+  const int refine = (std::is_same<T, float>::value && rscratch) ? cfg.refine : 0;
+  const size_t nbuf = (refine > 0 && PMAX <= 128) ? 2 : 1;
+  const size_t dyn = nbuf * (size_t)max_p * (size_t)eig_ld<G, PMAX>(max_p) * sizeof(T);
   static bool attr_set = false;
   if (!attr_set) {
     set_dyn_lds_cap(reinterpret_cast<const void *>(&k_psd_eig<T, NT, G, PMAX>));
     attr_set = true;
   }
   k_psd_eig<T, NT, G, PMAX><<<n, NT, dyn, st>>>(d, cfg.max_sweeps, (T)cfg.tol, mode, rho_hat, vv, sh, y, s_new,
-                                                y_new, U, lam, stats, rscratch ? cfg.refine : 0, rscratch, Uprev);
+                                                y_new, U, lam, stats, refine, rscratch, Uprev);
 }
 
 }  // namespace

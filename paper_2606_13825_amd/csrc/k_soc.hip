@@ -13,7 +13,10 @@ constexpr int ST = 256;
 // Norm of w with one rescaling pass to avoid overflow/underflow.
 template <typename T> __device__ inline T wnorm(const T *w, int d) {
   T mx = 0;
-  for (int i = 0; i < d; ++i) mx = fmax(mx, fabs(w[i]));
+  for (int i = 0; i < d; ++i) {
+    const T a = fabs(w[i]);
+    mx = (a > mx || a != a) ? a : mx;   // a NaN entry sticks (fmax would drop it)
+  }
   if (mx == (T)0) return 0;
   T acc = 0;
   for (int i = 0; i < d; ++i) {

@@ -102,11 +102,14 @@ __global__ void k_block_mean(const RectDesc *__restrict__ rect, int32_t nrect, c
 // Per column j of A (row j of A'):
 //   dg[j] = P_jj + sigma + sum_i rho_hat_i A_ij^2        (Jacobi preconditioner)
 //   xi[j] = sigma x_j - q_j + sum_i A_ij (y_i + rho_hat_i (b_i - s_i))
+// With a diagonal M (every row of A has at most one nonzero and P is
+// diagonal) the Jacobi-PCG solution is x~ = xi / dg exactly; `ds` then
+// carries the outputs and the solve is finished here.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_cols_pre(View<T> v, BucketArgs ba, const T *__restrict__ rho_hat,
                                                  const T *__restrict__ x, const T *__restrict__ s,
                                                  const T *__restrict__ y, T *__restrict__ dg,
-                                                 T *__restrict__ xi) {
+                                                 T *__restrict__ xi, DiagSolve<T> ds) {
   BUCKET_PREAMBLE
   const int64_t j = bp.row;
   T a_xi = 0, a_d = 0;
@@ -120,8 +123,16 @@ __global__ __launch_bounds__(NT) void k_cols_pre(View<T> v, BucketArgs ba, const
   a_xi = subwave_sum(a_xi, bp.L);
   a_d = subwave_sum(a_d, bp.L);
   if (bp.lane == 0) {
-    dg[j] = v.Pdiag[j] + v.sigma + a_d;
-    xi[j] = v.sigma * x[j] - v.q[j] + a_xi;
+    const T d = v.Pdiag[j] + v.sigma + a_d;
+    const T r = v.sigma * x[j] - v.q[j] + a_xi;
+    dg[j] = d;
+    xi[j] = r;
+    if (ds.xt) {
+      const T xt = r / d;
+      const T al = ds.alpha_k[v.col_inst[j]];
+      ds.xt[j] = xt;
+      ds.xn[j] = al * xt + ((T)1 - al) * x[j];
+    }
   }
 }
 
@@ -149,7 +160,7 @@ __global__ __launch_bounds__(NT) void k_rows_post(View<T> v, BucketArgs ba, cons
   st_out[i] = stl;
   const uint8_t kind = v.row_kind[i];
   if (kind == ROW_ZERO || kind == ROW_NONNEG) {
-    const T sp = (kind == ROW_ZERO) ? (T)0 : (vi > (T)0 ? vi : (T)0);
+    const T sp = (kind == ROW_ZERO) ? (T)0 : (vi < (T)0 ? (T)0 : vi);   // NaN passes through
     s_new[i] = sp;
     y_new[i] = y[i] + r * (shat - sp);
   } else {
@@ -223,11 +234,13 @@ __global__ __launch_bounds__(NT) void k_bwd_rows_b(View<T> v, const T *__restric
 }
 
 // Per column j: xt-bar = alpha gx+ - (A' gs~)_j ; also the Jacobi diagonal.
+// With a diagonal M the adjoint solve is w = xt-bar / dg (see k_cols_pre);
+// then w and gx = (1 - alpha) gx+ + sigma w are written here.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_bwd_cols(View<T> v, BucketArgs ba, const T *__restrict__ rho_hat,
                                                  const T *__restrict__ alpha_k, const T *__restrict__ gst,
                                                  const T *__restrict__ gx_in, T *__restrict__ gxt,
-                                                 T *__restrict__ dg) {
+                                                 T *__restrict__ dg, DiagSolve<T> ds) {
   BUCKET_PREAMBLE
   const int64_t j = bp.row;
   T acc = 0, a_d = 0;
@@ -241,8 +254,15 @@ __global__ __launch_bounds__(NT) void k_bwd_cols(View<T> v, BucketArgs ba, const
   a_d = subwave_sum(a_d, bp.L);
   if (bp.lane == 0) {
     const T al = alpha_k[v.col_inst[j]];
-    gxt[j] = al * gx_in[j] - acc;
-    dg[j] = v.Pdiag[j] + v.sigma + a_d;
+    const T r = al * gx_in[j] - acc;
+    const T d = v.Pdiag[j] + v.sigma + a_d;
+    gxt[j] = r;
+    dg[j] = d;
+    if (ds.xt) {
+      const T w = r / d;
+      ds.xt[j] = w;
+      ds.xn[j] = ((T)1 - al) * gx_in[j] + v.sigma * w;
+    }
   }
 }
 
@@ -406,9 +426,10 @@ void launch_rect_adjoint(const View<T> &v, const RectDesc *rect, int32_t nrect, 
 
 template <typename T>
 void launch_cols_pre(const View<T> &v, const RowBuckets &bk, const T *rho_hat, const T *x, const T *s, const T *y,
-                     T *dg, T *xi, hipStream_t st) {
+                     T *dg, T *xi, DiagSolve<T> ds, hipStream_t st) {
   BucketArgs a = make_bucket_args(bk);
-  if (nblocks_bucket(a) > 0) k_cols_pre<T><<<(int)nblocks_bucket(a), NT, 0, st>>>(v, a, rho_hat, x, s, y, dg, xi);
+  if (nblocks_bucket(a) > 0)
+    k_cols_pre<T><<<(int)nblocks_bucket(a), NT, 0, st>>>(v, a, rho_hat, x, s, y, dg, xi, ds);
 }
 
 template <typename T>
@@ -443,10 +464,10 @@ void launch_bwd_rows_b(const View<T> &v, const T *rho_hat, const T *alpha_k, con
 
 template <typename T>
 void launch_bwd_cols(const View<T> &v, const RowBuckets &bk, const T *rho_hat, const T *alpha_k, const T *gst,
-                     const T *gx_in, T *gxt, T *dg, hipStream_t st) {
+                     const T *gx_in, T *gxt, T *dg, DiagSolve<T> ds, hipStream_t st) {
   BucketArgs a = make_bucket_args(bk);
   if (nblocks_bucket(a) > 0)
-    k_bwd_cols<T><<<(int)nblocks_bucket(a), NT, 0, st>>>(v, a, rho_hat, alpha_k, gst, gx_in, gxt, dg);
+    k_bwd_cols<T><<<(int)nblocks_bucket(a), NT, 0, st>>>(v, a, rho_hat, alpha_k, gst, gx_in, gxt, dg, ds);
 }
 
 template <typename T>
@@ -493,7 +514,7 @@ void launch_nonfinite_check(const View<T> &v, const T *x, const T *s, const T *y
                                   hipStream_t);                                                                 \
   template void launch_rect_adjoint<T>(const View<T> &, const RectDesc *, int32_t, const T *, T *, hipStream_t); \
   template void launch_cols_pre<T>(const View<T> &, const RowBuckets &, const T *, const T *, const T *,        \
-                                   const T *, T *, T *, hipStream_t);                                           \
+                                   const T *, T *, T *, DiagSolve<T>, hipStream_t);                             \
   template void launch_rows_post<T>(const View<T> &, const RowBuckets &, const T *, const T *, const T *,       \
                                     const T *, const T *, T *, T *, T *, T *, T *, hipStream_t);                \
   template void launch_bwd_rows_a<T>(const View<T> &, const T *, const T *, const T *, const T *, const T *,    \
@@ -503,7 +524,7 @@ void launch_nonfinite_check(const View<T> &v, const T *x, const T *s, const T *y
   template void launch_bwd_rows_b<T>(const View<T> &, const T *, const T *, const T *, const T *, const T *,    \
                                      const T *, const T *, const T *, T *, T *, T *, T *, T *, hipStream_t);    \
   template void launch_bwd_cols<T>(const View<T> &, const RowBuckets &, const T *, const T *, const T *,        \
-                                   const T *, T *, T *, hipStream_t);                                           \
+                                   const T *, T *, T *, DiagSolve<T>, hipStream_t);                             \
   template void launch_bwd_rows_c<T>(const View<T> &, const RowBuckets &, const T *, const T *, const T *,      \
                                      const T *, T *, T *, T *, hipStream_t);                                    \
   template void launch_alpha_reduce<T>(const View<T> &, const T *, const T *, const T *, const T *, const T *,  \

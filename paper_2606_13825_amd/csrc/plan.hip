@@ -96,6 +96,10 @@ struct cosmo_plan {
   int32_t n_rect = 0;
   RowBuckets bkA, bkAt;
   int64_t sum_p = 0, sum_p2 = 0, sum_p2_large = 0;
+  // M = P + sigma I + A' D A is diagonal when every row of A has at most one
+  // nonzero and P is diagonal; the linear solves are then done in the
+  // column kernels (x~ = xi / diag M) and the PCG kernel is not launched.
+  bool diag_M = false;
   // layouts (element offsets of T)
   struct {
     size_t rho_hat, dg, xi, r, z, p, Mp, t, sh, vv, itA, itB, xt, st, U, lam, rp, rd, rs, total;
@@ -188,7 +192,7 @@ cosmo_status validate_options(const cosmo_options *o) {
   if (o->cg_max_iter < 1) FAIL(COSMO_EINVAL, "cg_max_iter must be >= 1");
   if (o->eig_max_sweeps < 1) FAIL(COSMO_EINVAL, "eig_max_sweeps must be >= 1");
   if (!(o->eig_tol >= 0.0) || !std::isfinite(o->eig_tol)) FAIL(COSMO_EINVAL, "eig_tol must be finite and >= 0");
-  if (o->eig_refine < 0 || o->eig_refine > 4) FAIL(COSMO_EINVAL, "eig_refine must be in [0, 4]");
+  if (o->eig_refine < 0 || o->eig_refine > 1) FAIL(COSMO_EINVAL, "eig_refine must be 0 or 1");
   if (o->eig_warm_start != 0 && o->eig_warm_start != 1) FAIL(COSMO_EINVAL, "eig_warm_start must be 0 or 1");
   return COSMO_OK;
 }
@@ -366,6 +370,17 @@ cosmo_status build_plan(cosmo_plan *pl, const cosmo_problem *p) {
     }
     pl->psd_cls_begin[4] = idx;
   }
+  {
+    bool dm = true;
+    for (int64_t i = 0; i < m && dm; ++i) dm = (rp[i + 1] - rp[i]) <= 1;
+    if (dm && p->P_nnz > 0) {
+      std::vector<int32_t> pc(p->P_nnz);
+      HIPCHK(hipMemcpy(pc.data(), p->P_col, p->P_nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+      for (int64_t j = 0; j < n && dm; ++j)
+        for (int64_t k = prp[j]; k < prp[j + 1] && dm; ++k) dm = (pc[k] == j);
+    }
+    pl->diag_M = dm;
+  }
   pl->n_soc = (int32_t)socs.size();
   pl->n_psd = (int32_t)psds.size();
   pl->n_rect = (int32_t)rects.size();
@@ -473,7 +488,7 @@ void build_layouts(cosmo_plan *pl) {
   f.lam = take(pl->sum_p);
   f.rp = take(m);
   f.rd = take(n);
-  f.rs = take(3 * (size_t)pl->sum_p2 * 8 / pl->esz);   // float64 eigen-refinement scratch
+  f.rs = take(3 * (size_t)pl->sum_p2 * 8 / pl->esz);   // eigensolver refinement scratch
   f.total = o;
   // tape: slot k (x, s, y) for k = 0..K, then per step (x~, s~, lam, U)
   auto &t = pl->tp;
@@ -583,14 +598,21 @@ cosmo_status forward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T 
     const T *al = alpha + (size_t)k * pl->B;
     T *x = X(k), *s = S(k), *y = Y(k), *xn = X(k + 1), *sn = S(k + 1), *yn = Y(k + 1);
     T *xt = XT(k);
-    // warm start of the CG: previous x~ (first step: x^0)
-    if (tape) launch_copy<T>(xt, k == 0 ? x : XT(k - 1), n, st);
-    else if (k == 0) launch_copy<T>(xt, x, n, st);
-    {
-      ProfScope ps(pl, 3, st);
-      launch_cols_pre<T>(v, pl->bkAt, rh, x, s, y, ws + f.dg, ws + f.xi, st);
+    DiagSolve<T> ds;
+    if (pl->diag_M) {
+      ds.xt = xt;
+      ds.xn = xn;
+      ds.alpha_k = al;
+    } else {
+      // warm start of the CG: previous x~ (first step: x^0)
+      if (tape) launch_copy<T>(xt, k == 0 ? x : XT(k - 1), n, st);
+      else if (k == 0) launch_copy<T>(xt, x, n, st);
     }
     {
+      ProfScope ps(pl, 3, st);
+      launch_cols_pre<T>(v, pl->bkAt, rh, x, s, y, ws + f.dg, ws + f.xi, ds, st);
+    }
+    if (!pl->diag_M) {
       ProfScope ps(pl, 2, st);
       launch_pcg<T>(v, rh, ws + f.dg, ws + f.xi, xt, ws + f.r, ws + f.z, ws + f.p, ws + f.Mp, ws + f.t,
                     pl->opt.cg_tol, pl->opt.cg_max_iter, al, x, xn, nullptr, nullptr, 0, stats, st);
@@ -656,9 +678,15 @@ cosmo_status backward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T
       ProfScope ps(pl, 3, st);
       launch_bwd_rows_b<T>(v, rh, al, stl, s, y, sn, gy_in, ws + w.gv, ws + w.gsh, ws + w.gst, gs_out, gy_out,
                            ws + w.grh, st);
-      launch_bwd_cols<T>(v, pl->bkAt, rh, al, ws + w.gst, gx_in, ws + w.gxt, ws + w.dg, st);
+      DiagSolve<T> ds;
+      if (pl->diag_M) {
+        ds.xt = ws + w.w;
+        ds.xn = gx_out;
+        ds.alpha_k = al;
+      }
+      launch_bwd_cols<T>(v, pl->bkAt, rh, al, ws + w.gst, gx_in, ws + w.gxt, ws + w.dg, ds, st);
     }
-    {
+    if (!pl->diag_M) {
       ProfScope ps(pl, 2, st);
       launch_pcg<T>(v, rh, ws + w.dg, ws + w.gxt, ws + w.w, ws + w.r, ws + w.z, ws + w.p, ws + w.Mp, ws + w.t,
                     pl->opt.cg_tol, pl->opt.cg_max_iter, al, nullptr, nullptr, gx_in, gx_out, 1, stats, st);
@@ -927,7 +955,7 @@ cosmo_status psd_proj(int32_t nblk, const int32_t *order, const int64_t *offset,
                       void *ws, void *stream) {
   if (!in || !out) FAIL(COSMO_EINVAL, "in and out are required");
   if (max_sweeps < 1) FAIL(COSMO_EINVAL, "max_sweeps must be >= 1");
-  if (refine < 0 || refine > 4) FAIL(COSMO_EINVAL, "refine must be in [0, 4]");
+  if (refine < 0 || refine > 1) FAIL(COSMO_EINVAL, "refine must be 0 or 1");
   hipStream_t st = static_cast<hipStream_t>(stream);
   std::vector<PsdDesc> descs;
   int32_t cb[5], cm[4];

@@ -91,7 +91,7 @@ def test_invalid_problem_rejected_on_host(L, case):
 
 
 @pytest.mark.parametrize("kw", [dict(K=0), dict(sigma=0.0), dict(cg_max_iter=0), dict(dtype=5),
-                                dict(eig_max_sweeps=0), dict(cg_tol=-1.0), dict(eig_refine=-1),
+                                dict(eig_max_sweeps=0), dict(cg_tol=-1.0), dict(eig_refine=-1), dict(eig_refine=2),
                                 dict(eig_warm_start=2)])
 def test_invalid_options_rejected(L, kw):
     p, keep = _problem(L)
