@@ -30,6 +30,42 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3     # MI355X published FP32 vector peak
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
+# Algorithmic work of one PSD block of order p: 9 p^3 for a textbook symmetric
+# eigendecomposition (eigenvectors included) + 2 p^3 for U max(L, 0) U'.
+EIG_FLOPS_PER_P3 = 11.0
+# The library's PSD order classes and their float32 eigensolve kernels.
+EIG_KERNEL_NAMES = {0: "k_psd_eig<float,64,4,32> (orders <= 32)", 1: "k_psd_eig<float,256,8,64> (orders 33-64)",
+                    2: "k_psd_eig<float,512,8,128> (orders 65-128)", 3: "k_psd_eig<float,1024,8,200> (orders 129-200)"}
+EIG_PROFILE = os.path.join(ROOT, "profiles", "k_psd_eig_maxcut64_pmc.md")
+EIG_SOURCE = os.path.join(ROOT, "paper_2606_13825_amd", "csrc", "k_psd.hip")
+
+
+def psd_order_class(orders):
+    o = np.asarray(orders)
+    return np.where(o <= 32, 0, np.where(o <= 64, 1, np.where(o <= 128, 2, 3)))
+
+
+def traffic_from_profile(cls):
+    """HBM bytes per dispatch of the class's eigensolve kernel, from the
+    committed counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the same
+    counters on a copy kernel of known size); None when there is none for this
+    class or the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        kv = {}
+        with open(EIG_PROFILE) as f:
+            for line in f:
+                if ":" in line and line[:1].isalpha():
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        with open(EIG_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+        if kv.get("source_sha256") != sha or int(kv.get("order_class", -1)) != int(cls):
+            return None
+        return float(kv["traffic_bytes_per_dispatch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
 
 def _workload(name):
     import synth
@@ -82,6 +118,8 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 256 MiB five times (reference for the HBM byte counters)")
     ap.add_argument("--quick", action="store_true",
                     help="counter-collection run: the timed steps only (no plain-forward comparison, "
                          "no event-timed step, no CPU leg)")
@@ -92,6 +130,17 @@ def main():
         print(json.dumps({"error": "this build measures one GPU: the batch shards over instances with no "
                                    "exchange inside the unroll, but runs on more than one GPU are not part of it"}))
         raise SystemExit(2)
+
+    if args.copy_calibration:
+        import torch
+        n = 64 * 1024 * 1024
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "dispatches": 5}))
+        return
 
     wl = _workload(args.workload)
     insts, K = wl["insts"], wl["K"]
@@ -149,21 +198,25 @@ def main():
                           "value": B * K / dt, "unit": "instance-iterations/s", "ms_per_step": dt * 1e3}))
         return
 
-    # dominant kernel families, timed with HIP events on the call's stream
+    # kernel families, and the eigensolve kernel of each PSD order class alone,
+    # timed with HIP events recorded by the library on the streams they run on
     batch.set_profiling(True)
     step()
     torch.cuda.synchronize(dev)
     fam = {}
     for kind, name in ((0, "psd_eig_project"), (1, "psd_dk_vjp"), (2, "pcg"), (3, "csr_row_col_passes")):
-        n, ms = batch.profile_read(kind)
-        fam[name] = (n, ms)
+        fam[name] = batch.profile_read(kind)
+    cls = {c: batch.profile_read(4 + c) for c in range(4)}
     batch.set_profiling(False)
     orders = np.array([inst.meta["order"] for inst in insts], np.float64)
-    eig_flops = float(np.sum(11.0 * orders ** 3))      # 9 p^3 eigensolve + 2 p^3 reconstruction
-    n_eig, ms_eig = fam["psd_eig_project"]
-    avg_eig_ms = ms_eig / max(n_eig, 1)
-    achieved = eig_flops / (avg_eig_ms * 1e-3) / 1e12
+    cls_of = psd_order_class(orders)
+    dom = max((c for c in cls if cls[c][0] > 0), key=lambda c: cls[c][1])
+    n_dom, ms_dom = cls[dom]
+    dom_flops = float(np.sum(EIG_FLOPS_PER_P3 * orders[cls_of == dom] ** 3))
+    avg_dom_ms = ms_dom / max(n_dom, 1)
+    achieved = dom_flops / (avg_dom_ms * 1e-3) / 1e12
     print(f"[bench] kernel families (launches, ms): {fam}", file=sys.stderr, flush=True)
+    print(f"[bench] eigensolve per order class (launches, ms): {cls}", file=sys.stderr, flush=True)
 
     # plain forward: unbatched, forward-only, no tape
     del tape, fws, bws
@@ -202,10 +255,11 @@ def main():
         "peak_hbm_bytes": {"fwd_bwd_batched": int(peak_fb), "plain_fwd_unbatched": int(peak_plain)},
         "plain_fwd": {"value": B * K / dt_plain, "unit": "instance-iterations/s", "ms_total": dt_plain * 1e3},
         "kernel_families_ms_per_step": {k: v[1] for k, v in fam.items()},
-        "roofline": {"kernel": "psd_eig_project (Jacobi eigensolve + float64 refinement + reconstruction)",
-                     "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
-                     "flops_per_launch": eig_flops, "avg_launch_ms": avg_eig_ms, "launches": n_eig},
+        "roofline": {"kernel": EIG_KERNEL_NAMES[dom], "bound": "alu", "achieved": achieved,
+                     "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
+                     "traffic": traffic_from_profile(dom),
+                     "flops_per_launch": dom_flops, "blocks_per_launch": int(np.sum(cls_of == dom)),
+                     "avg_launch_ms": avg_dom_ms, "launches": n_dom},
         "stats": {k: int(v.max()) for k, v in batch.stats_dict(stats).items()},
     }
 

@@ -218,10 +218,13 @@ cosmo_status socp_proj_vjp(int32_t ncones, const int32_t *dim, const int64_t *of
 
 /* Measurement support (not needed on the hot path).  With profiling on, the
  * library records a pair of HIP events on the call's stream around every
- * launch of a kernel family: 0 = PSD eigensolve + reconstruction, 1 = DK VJP,
- * 2 = PCG solves, 3 = row/column SpMV passes.  profile_read waits for the
- * recorded events and returns the number of launches and their summed
- * duration since profiling was (re)enabled. */
+ * launch of a kernel family: 0 = PSD eigensolve + reconstruction (all order
+ * classes, fork to join), 1 = DK VJP, 2 = PCG solves, 3 = row/column SpMV
+ * passes, and 4 + c = the eigensolve kernel of PSD order class c alone
+ * (c = 0: p <= 32, 1: p <= 64, 2: p <= 128, 3: p <= 200), timed on the
+ * stream it runs on.  profile_read waits for the recorded events and returns
+ * the number of launches and their summed duration since profiling was
+ * (re)enabled; kind outside 0..7 is COSMO_EINVAL. */
 cosmo_status cosmo_plan_set_profiling(cosmo_plan *plan, int32_t enable);
 cosmo_status cosmo_plan_profile_read(cosmo_plan *plan, int32_t kind, int64_t *launches, double *total_ms);
 

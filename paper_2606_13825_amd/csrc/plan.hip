@@ -111,7 +111,7 @@ struct cosmo_plan {
     size_t rho_hat, gA, gB, gsn, gv, gsh, gst, grh, gxt, w, dg, r, z, p, Mp, t, vv, dk, zero, total;
   } bw{};
   bool profiling = false;
-  ProfileSlot prof[4];
+  ProfileSlot prof[8];   // kinds of cosmo_plan_profile_read
   // auxiliary streams (default priority) and events for concurrent order classes
   hipStream_t aux[3] = {nullptr, nullptr, nullptr};
   hipEvent_t ev_fork = nullptr;
@@ -556,6 +556,7 @@ void launch_psd_classes(cosmo_plan *pl, const T *rho_hat, const T *vv, const T *
   fork_classes(pl, st, [&](int c, hipStream_t s) {
     const int n = pl->psd_cls_begin[c + 1] - pl->psd_cls_begin[c];
     PsdLaunchCfg cfg{pl->opt.eig_max_sweeps, pl->opt.eig_tol, refine ? pl->opt.eig_refine : 0, pl->psd_cls_maxp[c]};
+    ProfScope pc(pl, 4 + c, s);   // this class's kernel alone, on the stream it runs on
     launch_psd_step<T>(pl->d_psd + pl->psd_cls_begin[c], n, cfg, rho_hat, vv, sh, y, s_new, y_new, U, lam,
                        refine ? rscratch : nullptr, Uprev, stats, s);
   });
@@ -881,7 +882,7 @@ cosmo_status cosmo_plan_set_profiling(cosmo_plan *plan, int32_t enable) {
 cosmo_status cosmo_plan_profile_read(cosmo_plan *plan, int32_t kind, int64_t *launches, double *total_ms) {
   cosmo_status s = check_plan(plan);
   if (s != COSMO_OK) return s;
-  if (kind < 0 || kind > 3) FAIL(COSMO_EINVAL, "kind must be 0..3");
+  if (kind < 0 || kind > 7) FAIL(COSMO_EINVAL, "kind must be 0..7");
   ProfileSlot &sl = plan->prof[kind];
   double tot = 0;
   for (size_t i = 0; i < sl.used; ++i) {

@@ -16,19 +16,19 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
 
-def _hyper(insts, K, seed, spread=0.5):
+def _hyper(insts, K, seed, spread=0.5, dtype=np.float32):
     rng = np.random.default_rng(seed)
     rhos, alphas = [], []
     for inst in insts:
         r, a = synth.perturbed_hyper(inst, K, rng, spread=spread)
-        rhos.append(r.astype(np.float32))
-        alphas.append(a.astype(np.float32))
+        rhos.append(r.astype(np.float32).astype(dtype))
+        alphas.append(a.astype(np.float32).astype(dtype))
     return rhos, alphas
 
 
-def _run_and_check(insts, K, rhos, alphas, check_idx, tol_it, tol_g, **kw):
+def _run_and_check(insts, K, rhos, alphas, check_idx, tol_it, tol_g, dtype=torch.float32, **kw):
     from paper_2606_13825_amd import CosmoBatch
-    batch = CosmoBatch(insts, K=K, dtype=torch.float32, device=DEV, **kw)
+    batch = CosmoBatch(insts, K=K, dtype=dtype, device=DEV, **kw)
     rho = torch.from_numpy(np.concatenate(rhos, axis=1)).to(DEV)
     alpha = torch.from_numpy(np.stack(alphas, axis=1)).to(DEV)
     stats = batch.new_stats()
@@ -55,16 +55,66 @@ def _run_and_check(insts, K, rhos, alphas, check_idx, tol_it, tol_g, **kw):
                               f"inst {i} grad alpha"))
         errs.append(max(e))
     say(f"  max rel err over checked instances: {max(errs):.2e}")
+    batch.last = (fw, rho, alpha)
     return batch
 
 
-def test_lovasz_circulant_reduced():
+def _lovasz_reduced(dtype):
+    return [x.astype(dtype) for x in synth.c3_batch(B=4, n_lo=16, n_hi=40, seed=31)]
+
+
+def test_lovasz_circulant_reduced_fp64():
+    """K = 20 in float64: every final iterate and gradient at float64 level."""
     ensure_lib()
-    insts = [x.astype(np.float32) for x in synth.c3_batch(B=4, n_lo=16, n_hi=40, seed=31)]
+    insts = _lovasz_reduced(np.float64)
+    K = 20
+    rhos, alphas = _hyper(insts, K, 32, dtype=np.float64)
+    say(f"Lovasz circulant fp64 B=4 orders={[i.meta['order'] for i in insts]} K={K}")
+    _run_and_check(insts, K, rhos, alphas, range(4), 1e-10, 1e-8, dtype=torch.float64, cg_tol=1e-13)
+
+
+def test_lovasz_circulant_reduced_fp32_short():
+    """K = 6 in float32, at the float32 bar (1e-5 iterates, 1e-4 gradients)."""
+    ensure_lib()
+    insts = _lovasz_reduced(np.float32)
+    K = 6
+    rhos, alphas = _hyper(insts, K, 32)
+    say(f"Lovasz circulant fp32 B=4 orders={[i.meta['order'] for i in insts]} K={K}")
+    _run_and_check(insts, K, rhos, alphas, range(4), 1e-5, 1e-4)
+
+
+def test_lovasz_circulant_fp32_one_step_parity():
+    """K = 20 in float32.  These trajectories amplify rounding about a
+    thousandfold over 20 steps (the oracle itself, with its iterates rounded
+    to float32 after every step, drifts by up to 4e-5 from its float64 run),
+    so end-to-end float32 agreement is limited by the problem, not the
+    kernels.  What the kernels control is every single step: the float64
+    oracle, started from the GPU's own iterate z^k, must reproduce the GPU's
+    z^(k+1) at the float32 bar, for every k."""
+    ensure_lib()
+    import oracle
+    from paper_2606_13825_amd import CosmoBatch
+    insts = _lovasz_reduced(np.float32)
     K = 20
     rhos, alphas = _hyper(insts, K, 32)
-    say(f"Lovasz circulant B=4 orders={[i.meta['order'] for i in insts]} K={K}")
-    _run_and_check(insts, K, rhos, alphas, range(4), 1e-5, 1e-4)
+    batch = CosmoBatch(insts, K=K, dtype=torch.float32, device=DEV)
+    rho = torch.from_numpy(np.concatenate(rhos, axis=1)).to(DEV)
+    alpha = torch.from_numpy(np.stack(alphas, axis=1)).to(DEV)
+    fw = batch.forward(rho, alpha)
+    torch.cuda.synchronize()
+    its = [[t.double().cpu().numpy() for t in batch.tape_iterate(fw.tape, k)[:3]] for k in range(K + 1)]
+    worst = 0.0
+    for i, inst in enumerate(insts):
+        sl_n = slice(batch.n_off[i], batch.n_off[i + 1])
+        sl_m = slice(batch.m_off[i], batch.m_off[i + 1])
+        fl = floor_of(inst)
+        for k in range(K):
+            x, s, y = its[k][0][sl_n], its[k][1][sl_m], its[k][2][sl_m]
+            st = oracle.step_forward(inst, x, s, y, rhos[i][k].astype(np.float64), float(alphas[i][k]))
+            for nm, g, r in (("x", its[k + 1][0][sl_n], st["xn"]), ("s", its[k + 1][1][sl_m], st["sn"]),
+                             ("y", its[k + 1][2][sl_m], st["yn"])):
+                worst = max(worst, assert_close(g, r, 1e-5, fl, f"inst {i} step {k} {nm}"))
+    say(f"  worst one-step rel err: {worst:.2e}")
 
 
 def test_lovasz_circulant_large_orders():
