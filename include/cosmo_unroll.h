@@ -120,14 +120,18 @@ typedef struct {
 } cosmo_options;
 
 /* Per-instance device counters, updated with atomics (max / or); the caller
- * zeroes them before a call if it wants per-call values. */
+ * zeroes them before a call if it wants per-call values (the sums wrap past
+ * 2^31). */
 typedef struct {
   int32_t cg_iters_max;        /* largest PCG iteration count of any solve             */
   int32_t cg_not_converged;    /* number of solves that hit cg_max_iter                */
   int32_t eig_sweeps_max;      /* largest Jacobi sweep count of any PSD block          */
   int32_t eig_not_converged;   /* PSD eigensolves that hit eig_max_sweeps              */
   int32_t nonfinite;           /* 1 if a non-finite value reached the iterate          */
-  int32_t reserved[3];
+  int32_t eig_sweeps_total;    /* Jacobi sweeps summed over the PSD block solves       */
+  int32_t eig_solves;          /* PSD block eigensolves (eig_sweeps_total / eig_solves
+                                  is the mean sweep count)                              */
+  int32_t reserved;
 } cosmo_stats;
 
 const char *cosmo_status_string(cosmo_status s);

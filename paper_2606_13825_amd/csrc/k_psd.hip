@@ -408,6 +408,8 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
   auto count = [&]() {
     if (stats) {
       atomicMax(&stats[d.inst].eig_sweeps_max, sweep);
+      atomicAdd(&stats[d.inst].eig_sweeps_total, sweep);
+      atomicAdd(&stats[d.inst].eig_solves, 1);
       if (!converged) atomicAdd(&stats[d.inst].eig_not_converged, 1);
     }
   };
