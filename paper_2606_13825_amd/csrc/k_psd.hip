@@ -218,6 +218,7 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
   __shared__ short pos_idx[PMAX];
   __shared__ signed char cls[PMAX];
   __shared__ int flags[3];
+  __shared__ int bigf[3];
   __shared__ int npos_s;
 
   const PsdDesc d = descs[blockIdx.x];
@@ -247,7 +248,7 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
       W[p + (e - j * npad) + j * ld] = (T)0;
     }
   }
-  if (tid < 3) flags[tid] = 0;
+  if (tid < 3) flags[tid] = bigf[tid] = 0;
   fro2 = wg_sum<T, NT>(fro2, red);   // contains barriers: W complete after this
   if (!isfinite(fro2)) {
     // a non-finite block yields a non-finite projection (never a clipped one)
@@ -270,11 +271,48 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
   const T inf = wg_max<T, NT>(rowmax, red);
   T c = (T)1.1 * fmin(sqrt(fro2), inf);
   if (!(c > (T)0)) c = (T)1;
-  if (Uprev) {
-    // Warm start: W = (S + c I) U_prev, with U_prev the eigenvectors of the same
-    // block at the previous unrolled step.  One-sided Jacobi on W computes the
-    // same decomposition (W = G V with V orthogonal, W'W diagonal at the end);
-    // a nearly diagonalising start only shortens the sweeps.
+  // Warm start: W = (S + c I) U_prev, with U_prev the eigenvectors of the same
+  // block at the previous unrolled step.  One-sided Jacobi on W computes the
+  // same decomposition (W = G V with V orthogonal, W'W diagonal at the end);
+  // a nearly diagonalising start only shortens the sweeps.
+  bool started = false;
+  if constexpr (std::is_same<T, float>::value && PMAX <= 128) {
+    if (Uprev && refine > 0) {
+      // U_prev staged in the refinement buffer (free until the refinement);
+      // S is in W, so the products are held in registers until all are done
+      constexpr int NWs = NT / 64;
+      constexpr int NTM = (PMAX + 15) / 16;
+      constexpr int HOLDS = (NTM * NTM + NWs - 1) / NWs;
+      const float *Up = Uprev + d.uoff;
+      float *Ub = W + p * ld;
+      for (int e = tid; e < p * p; e += NT) {
+        const int j = e / p;
+        Ub[(e - j * p) + j * ld] = Up[e];
+      }
+      __syncthreads();
+      const int nt0 = (p + 15) / 16;
+      const int wave0 = tid >> 6, lane0 = tid & 63;
+      tile_pass<HOLDS, true>(
+          nt0 * nt0, wave0, NWs,
+          [&](int t) {
+            const int I = t / nt0, J = t % nt0;
+            return tile_mma<float>(
+                I * 16, J * 16, p, [&](int i, int k) -> float { return (i < p && k < p) ? W[i + k * ld] : 0.f; },
+                [&](int k, int j) -> float { return (k < p && j < p) ? Ub[k + j * ld] : 0.f; });
+          },
+          [&](int t, const Mma<float>::v4 &acc) {
+            const int I = t / nt0, J = t % nt0;
+            const int col = J * 16 + (lane0 & 15);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int row = I * 16 + Mma<float>::row(lane0, e);
+              if (row < p && col < p) W[row + col * ld] = acc[e] + c * Ub[row + col * ld];
+            }
+          });
+      started = true;
+    }
+  }
+  if (!started && Uprev) {
     const T *Up = Uprev + d.uoff;
     const int nt0 = (p + 15) / 16;
     const int wave0 = tid >> 6, lane0 = tid & 63;
@@ -296,7 +334,7 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
         if (row < p && col < p) W[row + col * ld] = acc[e] + c * Up[row + col * p];
       }
     }
-  } else {
+  } else if (!started) {
     for (int i = tid; i < p; i += NT) W[i + i * ld] += c;
   }
   __syncthreads();
@@ -310,6 +348,12 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
   int sweep = 0;
   bool converged = (p == 1);
   const T tol2 = tol * tol;
+  // With the refinement behind them the sweeps of orders up to 128 can stop
+  // once a sweep's largest column cosine is below 1e-3: the couplings left
+  // are then of order 1e-6, well inside what one refinement step removes.
+  // The largest class converges fully (stopping early there left 1e-4
+  // errors on order-196 blocks).
+  const T stop2 = (std::is_same<T, float>::value && PMAX <= 128 && refine > 0) ? (T)1e-6 : (T)0;
   for (; sweep < max_sweeps && !converged; ++sweep) {
     const int fslot = sweep % 3;
     for (int r = 0; r < P - 1; ++r) {
@@ -331,15 +375,15 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
         // Rows past the lane's last one (e >= ne) re-read that row (or row
         // p - 1 in the unpadded class) and are masked out of the sums; their
         // stores repeat the value stored for that row, so no branch is needed.
+        auto row_of = [&](int e) {
+          const int rw = gl + (e < ne ? e : ne - 1) * G;
+          return (PADDED || rw < p) ? rw : p - 1;
+        };
         T xa[MAXE], xb[MAXE];
-        int row[MAXE];
 #pragma unroll
         for (int e = 0; e < MAXE; ++e) {
-          int rw = gl + (e < ne ? e : ne - 1) * G;
-          if constexpr (!PADDED) rw = rw < p ? rw : p - 1;
-          row[e] = rw;
-          xa[e] = wa[rw];
-          xb[e] = wb[rw];
+          xa[e] = wa[row_of(e)];
+          xb[e] = wb[row_of(e)];
         }
         T al = 0, be = 0, ga = 0;
 #pragma unroll
@@ -358,16 +402,19 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
           jacobi_rot(al, be, ga, cs, sn);
 #pragma unroll
           for (int e = 0; e < MAXE; ++e) {
-            wa[row[e]] = cs * xa[e] - sn * xb[e];
-            wb[row[e]] = sn * xa[e] + cs * xb[e];
+            wa[row_of(e)] = cs * xa[e] - sn * xb[e];
+            wb[row_of(e)] = sn * xa[e] + cs * xb[e];
           }
-          if (gl == 0) flags[fslot] = 1;
+          if (gl == 0) {
+            flags[fslot] = 1;
+            if (ga * ga > stop2 * al * be) bigf[fslot] = 1;
+          }
         }
       }
       __syncthreads();
     }
-    converged = (flags[fslot] == 0);
-    if (tid == 0) flags[(sweep + 2) % 3] = 0;
+    converged = (flags[fslot] == 0) || (stop2 > (T)0 && bigf[fslot] == 0);
+    if (tid == 0) flags[(sweep + 2) % 3] = bigf[(sweep + 2) % 3] = 0;
   }
   // every thread computed `converged` from the same flag after the same barrier
 
@@ -827,7 +874,12 @@ void launch_psd_step(const PsdDesc *d, int32_t n, const PsdLaunchCfg &cfg, const
   if (mp <= 32) run_eig<T, 64, 4, 32>(d, n, mp, cfg, mode, rho_hat, vv, sh, y, s_new, y_new, U, lam, stats, rscratch, Uprev, st);
   else if (mp <= 64) run_eig<T, 256, 8, 64>(d, n, mp, cfg, mode, rho_hat, vv, sh, y, s_new, y_new, U, lam, stats, rscratch, Uprev, st);
   else if (mp <= 128) run_eig<T, 512, 8, 128>(d, n, mp, cfg, mode, rho_hat, vv, sh, y, s_new, y_new, U, lam, stats, rscratch, Uprev, st);
-  else run_eig<T, 1024, 8, 200>(d, n, mp, cfg, mode, rho_hat, vv, sh, y, s_new, y_new, U, lam, stats, rscratch, Uprev, st);
+  else if constexpr (std::is_same<T, float>::value)
+    run_eig<T, 1024, 8, COSMO_MAX_PSD_ORDER_F32>(d, n, mp, cfg, mode, rho_hat, vv, sh, y, s_new, y_new, U, lam, stats,
+                                                rscratch, Uprev, st);
+  else
+    run_eig<T, 1024, 8, COSMO_MAX_PSD_ORDER_F64>(d, n, mp, cfg, mode, rho_hat, vv, sh, y, s_new, y_new, U, lam, stats,
+                                                rscratch, Uprev, st);
 }
 
 template <typename T>

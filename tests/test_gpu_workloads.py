@@ -90,7 +90,12 @@ def test_lovasz_circulant_fp32_one_step_parity():
     so end-to-end float32 agreement is limited by the problem, not the
     kernels.  What the kernels control is every single step: the float64
     oracle, started from the GPU's own iterate z^k, must reproduce the GPU's
-    z^(k+1) at the float32 bar, for every k."""
+    z^(k+1) at the float32 bar, for every k.  The bar has one floor that no
+    float32 pipeline avoids: the right-hand side xi is a float32 vector, and
+    rounding it once moves the exact solve by M^-1 (fl32(xi) - xi), which the
+    ill-conditioned M of these instances (cond ~ 1e3 p) can amplify past
+    1e-5; the step is allowed 8 such roundings, carried through to s and y
+    (the projection is nonexpansive, y+ adds rho (s^ - s+))."""
     ensure_lib()
     import oracle
     from paper_2606_13825_amd import CosmoBatch
@@ -103,18 +108,24 @@ def test_lovasz_circulant_fp32_one_step_parity():
     fw = batch.forward(rho, alpha)
     torch.cuda.synchronize()
     its = [[t.double().cpu().numpy() for t in batch.tape_iterate(fw.tape, k)[:3]] for k in range(K + 1)]
-    worst = 0.0
+    worst, n_floor = 0.0, 0
     for i, inst in enumerate(insts):
         sl_n = slice(batch.n_off[i], batch.n_off[i + 1])
         sl_m = slice(batch.m_off[i], batch.m_off[i + 1])
         fl = floor_of(inst)
         for k in range(K):
             x, s, y = its[k][0][sl_n], its[k][1][sl_m], its[k][2][sl_m]
-            st = oracle.step_forward(inst, x, s, y, rhos[i][k].astype(np.float64), float(alphas[i][k]))
+            a = float(alphas[i][k])
+            st = oracle.step_forward(inst, x, s, y, rhos[i][k].astype(np.float64), a)
+            dxt = st["lu"].solve(st["xi"].astype(np.float32).astype(np.float64) - st["xi"])
+            dsh = a * np.linalg.norm(inst.A @ dxt)
+            floors = {"x": 8 * a * np.linalg.norm(dxt), "s": 8 * dsh, "y": 16 * float(st["rho_hat"].max()) * dsh}
             for nm, g, r in (("x", its[k + 1][0][sl_n], st["xn"]), ("s", its[k + 1][1][sl_m], st["sn"]),
                              ("y", its[k + 1][2][sl_m], st["yn"])):
-                worst = max(worst, assert_close(g, r, 1e-5, fl, f"inst {i} step {k} {nm}"))
-    say(f"  worst one-step rel err: {worst:.2e}")
+                f = max(fl, floors[nm] / 1e-5)
+                n_floor += f > np.linalg.norm(r)
+                worst = max(worst, assert_close(g, r, 1e-5, f, f"inst {i} step {k} {nm}"))
+    say(f"  worst one-step rel err: {worst:.2e} (rounding floor active in {n_floor} of {3 * K * len(insts)} checks)")
 
 
 def test_lovasz_circulant_large_orders():
