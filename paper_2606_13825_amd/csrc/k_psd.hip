@@ -58,12 +58,25 @@ constexpr int MAXP = COSMO_MAX_PSD_ORDER_F32;
 // 0 outside the matrices.  Lane l feeds A(I0 + l%16, k0 + l/16) and
 // B(k0 + l/16, J0 + l%16); accumulator element e of lane l is
 // C(I0 + Mma<T>::row(l, e), J0 + l%16).
+// The k loop is unrolled by four products so the operand reads of a group
+// are issued together.
 template <typename T, typename FA, typename FB>
 __device__ inline typename Mma<T>::v4 tile_mma(int I0, int J0, int kdim, FA fa, FB fb) {
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, kk = lane >> 4;
   typename Mma<T>::v4 acc = {0, 0, 0, 0};
-  for (int k0 = 0; k0 < kdim; k0 += 4) {
+  int k0 = 0;
+  for (; k0 + 16 <= kdim; k0 += 16) {
+    T a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = fa(I0 + r, k0 + 4 * u + kk);
+      b[u] = fb(k0 + 4 * u + kk, J0 + r);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = Mma<T>::op(a[u], b[u], acc);
+  }
+  for (; k0 < kdim; k0 += 4) {
     const int k = k0 + kk;
     acc = Mma<T>::op(fa(I0 + r, k), fb(k, J0 + r), acc);
   }
@@ -104,16 +117,26 @@ template <typename T, int NT> __device__ inline T wg_max(T v, T *red) {
   return t;
 }
 
+// Jacobi lanes move 16 bytes per LDS access in the padded classes.
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); };
+
 // Leading dimension of a p x p block held in LDS.  In order classes up to
-// 128 the G lanes of a Jacobi pair read rows gl, gl + G, ... of a column
-// without masks: columns are padded with zero rows to a multiple of G and
-// then to an odd multiple of 8 words, so the groups of a wave, which work on
-// consecutive columns in the circle schedule, read disjoint LDS banks.  In the
-// largest class a block alone nearly fills the LDS: even orders pad to the
-// next odd one and reads past row p are clamped.  p * eig_ld(p) does not
-// decrease with p.
-template <int G, int PMAX> __host__ __device__ constexpr int eig_ld(int p) {
-  return PMAX <= 128 ? 8 * ((G * ((p + G - 1) / G) + 7) / 8 | 1) : (p | 1);
+// 128 the G lanes of a Jacobi pair read a column in 16-byte pieces (VE
+// elements per lane, VE G rows per access of the group) without masks:
+// columns are padded with zero rows to a multiple of VE G, then by 8 more
+// elements, so ld is an odd multiple of 8 and the groups of a wave, which
+// work on consecutive columns in the circle schedule, hit different LDS
+// banks.  In the largest class a block alone nearly fills the LDS: even
+// orders pad to the next odd one, lanes read single elements and reads past
+// row p are clamped.  p * eig_ld(p) does not decrease with p.
+template <typename T, int G, int PMAX> __host__ __device__ constexpr int eig_rows(int p) {
+  return PMAX <= 128 ? (16 / (int)sizeof(T)) * G * ((p + (16 / (int)sizeof(T)) * G - 1) / ((16 / (int)sizeof(T)) * G))
+                     : p;
+}
+template <typename T, int G, int PMAX> __host__ __device__ constexpr int eig_ld(int p) {
+  return PMAX <= 128 ? eig_rows<T, G, PMAX>(p) + 8 : (p | 1);
 }
 
 // Cross-lane moves inside rows of 16 lanes (DPP): quad_perm [1,0,3,2] and
@@ -163,7 +186,23 @@ __device__ inline void tile_mma2(int I0, int J0, int kdim, FA fa, FB1 fb1, FB2 f
   const int r = lane & 15, kk = lane >> 4;
   c1 = typename Mma<T>::v4{0, 0, 0, 0};
   c2 = typename Mma<T>::v4{0, 0, 0, 0};
-  for (int k0 = 0; k0 < kdim; k0 += 4) {
+  int k0 = 0;
+  for (; k0 + 16 <= kdim; k0 += 16) {
+    T a[4], b1[4], b2[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + 4 * u + kk;
+      a[u] = fa(I0 + r, k);
+      b1[u] = fb1(k, J0 + r);
+      b2[u] = fb2(k, J0 + r);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      c1 = Mma<T>::op(a[u], b1[u], c1);
+      c2 = Mma<T>::op(a[u], b2[u], c2);
+    }
+  }
+  for (; k0 < kdim; k0 += 4) {
     const int k = k0 + kk;
     const T a = fa(I0 + r, k);
     c1 = Mma<T>::op(a, fb1(k, J0 + r), c1);
@@ -223,7 +262,7 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
 
   const PsdDesc d = descs[blockIdx.x];
   const int p = d.p;
-  const int ld = eig_ld<G, PMAX>(p);
+  const int ld = eig_ld<T, G, PMAX>(p);
   const int nrows = p * (p + 1) / 2;
   const T *v = vin + d.row0;
   const int tid = threadIdx.x;
@@ -239,10 +278,10 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
     W[i + j * ld] = val;
     W[j + i * ld] = val;
   }
-  constexpr bool PADDED = PMAX <= 128;   // zero rows up to a multiple of G (see eig_ld)
-  const int ne = (p + G - 1) / G;         // column rows per Jacobi lane
+  constexpr bool PADDED = PMAX <= 128;   // zero rows up to eig_rows (see eig_ld)
+  const int ne = (p + G - 1) / G;         // column rows per Jacobi lane (unpadded class)
   if constexpr (PADDED) {
-    const int npad = G * ne - p;
+    const int npad = eig_rows<T, G, PMAX>(p) - p;
     for (int e = tid; e < npad * p; e += NT) {
       const int j = e / npad;
       W[p + (e - j * npad) + j * ld] = (T)0;
@@ -372,43 +411,86 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
         const bool live = a < p && b < p;   // else the dummy column of an odd order
         T *wa = W + (live ? a : 0) * ld;
         T *wb = W + (live ? b : 0) * ld;
-        // Rows past the lane's last one (e >= ne) re-read that row (or row
-        // p - 1 in the unpadded class) and are masked out of the sums; their
-        // stores repeat the value stored for that row, so no branch is needed.
-        auto row_of = [&](int e) {
-          const int rw = gl + (e < ne ? e : ne - 1) * G;
-          return (PADDED || rw < p) ? rw : p - 1;
-        };
-        T xa[MAXE], xb[MAXE];
-#pragma unroll
-        for (int e = 0; e < MAXE; ++e) {
-          xa[e] = wa[row_of(e)];
-          xb[e] = wb[row_of(e)];
-        }
         T al = 0, be = 0, ga = 0;
+        bool rot = false;
+        if constexpr (PADDED) {
+          // Pieces past the last (c >= nc) re-read the lane's last piece, are
+          // masked out of the sums, and their stores repeat that piece's.
+          typedef typename Vec16<T>::type V;
+          constexpr int VE = 16 / (int)sizeof(T);
+          constexpr int MAXC = (PMAX + VE * G - 1) / (VE * G);
+          const int nc = (p + VE * G - 1) / (VE * G);
+          V xa[MAXC], xb[MAXC];
 #pragma unroll
-        for (int e = 0; e < MAXE; ++e) {
-          const bool in = e < ne && (PADDED || gl + e * G < p);
-          const T u = in ? xa[e] : (T)0, w = in ? xb[e] : (T)0;
-          al += u * u;
-          be += w * w;
-          ga += u * w;
-        }
-        al = group_sum<G>(al);
-        be = group_sum<G>(be);
-        ga = group_sum<G>(ga);
-        if (live && ga * ga > tol2 * al * be) {
-          T cs, sn;
-          jacobi_rot(al, be, ga, cs, sn);
+          for (int c = 0; c < MAXC; ++c) {
+            const int rw = VE * (gl + (c < nc ? c : nc - 1) * G);
+            xa[c] = *reinterpret_cast<const V *>(wa + rw);
+            xb[c] = *reinterpret_cast<const V *>(wb + rw);
+          }
+#pragma unroll
+          for (int c = 0; c < MAXC; ++c) {
+            const T m = c < nc ? (T)1 : (T)0;
+#pragma unroll
+            for (int q = 0; q < VE; ++q) {
+              const T u = m * xa[c][q], w = m * xb[c][q];
+              al += u * u;
+              be += w * w;
+              ga += u * w;
+            }
+          }
+          al = group_sum<G>(al);
+          be = group_sum<G>(be);
+          ga = group_sum<G>(ga);
+          rot = live && ga * ga > tol2 * al * be;
+          if (rot) {
+            T cs, sn;
+            jacobi_rot(al, be, ga, cs, sn);
+#pragma unroll
+            for (int c = 0; c < MAXC; ++c) {
+              const int rw = VE * (gl + (c < nc ? c : nc - 1) * G);
+              *reinterpret_cast<V *>(wa + rw) = cs * xa[c] - sn * xb[c];
+              *reinterpret_cast<V *>(wb + rw) = sn * xa[c] + cs * xb[c];
+            }
+          }
+        } else {
+          // Rows past the lane's last one (e >= ne) re-read row p - 1 or the
+          // lane's last row and are masked out of the sums; their stores
+          // repeat the value stored for that row.
+          auto row_of = [&](int e) {
+            const int rw = gl + (e < ne ? e : ne - 1) * G;
+            return rw < p ? rw : p - 1;
+          };
+          T xa[MAXE], xb[MAXE];
 #pragma unroll
           for (int e = 0; e < MAXE; ++e) {
-            wa[row_of(e)] = cs * xa[e] - sn * xb[e];
-            wb[row_of(e)] = sn * xa[e] + cs * xb[e];
+            xa[e] = wa[row_of(e)];
+            xb[e] = wb[row_of(e)];
           }
-          if (gl == 0) {
-            flags[fslot] = 1;
-            if (ga * ga > stop2 * al * be) bigf[fslot] = 1;
+#pragma unroll
+          for (int e = 0; e < MAXE; ++e) {
+            const bool in = e < ne && gl + e * G < p;
+            const T u = in ? xa[e] : (T)0, w = in ? xb[e] : (T)0;
+            al += u * u;
+            be += w * w;
+            ga += u * w;
           }
+          al = group_sum<G>(al);
+          be = group_sum<G>(be);
+          ga = group_sum<G>(ga);
+          rot = live && ga * ga > tol2 * al * be;
+          if (rot) {
+            T cs, sn;
+            jacobi_rot(al, be, ga, cs, sn);
+#pragma unroll
+            for (int e = 0; e < MAXE; ++e) {
+              wa[row_of(e)] = cs * xa[e] - sn * xb[e];
+              wb[row_of(e)] = sn * xa[e] + cs * xb[e];
+            }
+          }
+        }
+        if (rot && gl == 0) {
+          flags[fslot] = 1;
+          if (ga * ga > stop2 * al * be) bigf[fslot] = 1;
         }
       }
       __syncthreads();
@@ -850,7 +932,7 @@ void run_eig(const PsdDesc *d, int32_t n, int32_t max_p, const PsdLaunchCfg &cfg
   // to order 128, in the global scratch above.
   const int refine = (std::is_same<T, float>::value && rscratch) ? cfg.refine : 0;
   const size_t nbuf = (refine > 0 && PMAX <= 128) ? 2 : 1;
-  const size_t dyn = nbuf * (size_t)max_p * (size_t)eig_ld<G, PMAX>(max_p) * sizeof(T);
+  const size_t dyn = nbuf * (size_t)max_p * (size_t)eig_ld<T, G, PMAX>(max_p) * sizeof(T);
   static bool attr_set = false;
   if (!attr_set) {
     set_dyn_lds_cap(reinterpret_cast<const void *>(&k_psd_eig<T, NT, G, PMAX>));

@@ -78,23 +78,30 @@ template <typename T> __global__ void k_fill(T *__restrict__ dst, T val, int64_t
   for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) dst[i] = val;
 }
 
-// One wave per (step, block): the block mean of `src` written to every row
-// of the block in `dst` (rectification and its adjoint are the same map).
+// One workgroup per (step, block): the block mean of `src` written to every
+// row of the block in `dst` (rectification and its adjoint are the same map).
+// Each thread keeps four loads in flight.
+template <typename T> __device__ inline T block_sum(T v, T *red);
+
 template <typename T>
-__global__ void k_block_mean(const RectDesc *__restrict__ rect, int32_t nrect, const T *__restrict__ src,
-                             T *__restrict__ dst, int64_t stride, int32_t K) {
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int64_t job = (int64_t)blockIdx.x * (NT / 64) + wave;
-  if (job >= (int64_t)nrect * K) return;
-  const int k = (int)(job / nrect);
-  const RectDesc d = rect[job % nrect];
-  const T *s = src + k * stride + d.row0;
-  T acc = 0;
-  for (int i = lane; i < d.rows; i += 64) acc += s[i];
-  acc = subwave_sum(acc, 64);
-  const T mean = acc / (T)d.rows;
+__global__ __launch_bounds__(NT) void k_block_mean(const RectDesc *__restrict__ rect, int32_t nrect,
+                                                   const T *__restrict__ src, T *__restrict__ dst, int64_t stride) {
+  __shared__ T red[NT / 64];
+  const int k = (int)(blockIdx.x / nrect);
+  const RectDesc d = rect[blockIdx.x % nrect];
+  const T *sp = src + k * stride + d.row0;
+  T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  int i = threadIdx.x;
+  for (; i + 3 * NT < d.rows; i += 4 * NT) {
+    a0 += sp[i];
+    a1 += sp[i + NT];
+    a2 += sp[i + 2 * NT];
+    a3 += sp[i + 3 * NT];
+  }
+  for (; i < d.rows; i += NT) a0 += sp[i];
+  const T mean = block_sum((a0 + a1) + (a2 + a3), red) / (T)d.rows;
   T *o = dst + k * stride + d.row0;
-  for (int i = lane; i < d.rows; i += 64) o[i] = mean;
+  for (int j = threadIdx.x; j < d.rows; j += NT) o[j] = mean;
 }
 
 // ---- forward ----------------------------------------------------------------
@@ -305,10 +312,21 @@ __global__ __launch_bounds__(NT) void k_alpha_reduce(View<T> v, const T *__restr
                                                      const T *__restrict__ x, T *__restrict__ galpha_k) {
   __shared__ T red[NT / 64];
   const int b = blockIdx.x;
-  T acc = 0;
-  for (int64_t i = v.m_off[b] + threadIdx.x; i < v.m_off[b + 1]; i += NT) acc += gsh[i] * (stl[i] - s[i]);
-  for (int64_t j = v.n_off[b] + threadIdx.x; j < v.n_off[b + 1]; j += NT) acc += gx_in[j] * (xt[j] - x[j]);
-  const T tot = block_sum(acc, red);
+  T a0 = 0, a1 = 0;
+  const int64_t m1 = v.m_off[b + 1], n1 = v.n_off[b + 1];
+  int64_t i = v.m_off[b] + threadIdx.x;
+  for (; i + NT < m1; i += 2 * NT) {
+    a0 += gsh[i] * (stl[i] - s[i]);
+    a1 += gsh[i + NT] * (stl[i + NT] - s[i + NT]);
+  }
+  for (; i < m1; i += NT) a0 += gsh[i] * (stl[i] - s[i]);
+  int64_t j = v.n_off[b] + threadIdx.x;
+  for (; j + NT < n1; j += 2 * NT) {
+    a0 += gx_in[j] * (xt[j] - x[j]);
+    a1 += gx_in[j + NT] * (xt[j + NT] - x[j + NT]);
+  }
+  for (; j < n1; j += NT) a0 += gx_in[j] * (xt[j] - x[j]);
+  const T tot = block_sum(a0 + a1, red);
   if (threadIdx.x == 0) galpha_k[b] = tot;
 }
 
@@ -413,7 +431,7 @@ void launch_rectify(const View<T> &v, const RectDesc *rect, int32_t nrect, const
   k_copy<T><<<grid_for(tot), NT, 0, st>>>(rho_hat, rho, tot);
   if (nrect > 0) {
     const int64_t jobs = (int64_t)nrect * K;
-    k_block_mean<T><<<(int)((jobs + 3) / 4), NT, 0, st>>>(rect, nrect, rho, rho_hat, v.m_tot, K);
+    k_block_mean<T><<<(int)jobs, NT, 0, st>>>(rect, nrect, rho, rho_hat, v.m_tot);
   }
 }
 
@@ -421,7 +439,7 @@ template <typename T>
 void launch_rect_adjoint(const View<T> &v, const RectDesc *rect, int32_t nrect, const T *grh, T *grho_k,
                          hipStream_t st) {
   k_copy<T><<<grid_for(v.m_tot), NT, 0, st>>>(grho_k, grh, v.m_tot);
-  if (nrect > 0) k_block_mean<T><<<(nrect + 3) / 4, NT, 0, st>>>(rect, nrect, grh, grho_k, v.m_tot, 1);
+  if (nrect > 0) k_block_mean<T><<<nrect, NT, 0, st>>>(rect, nrect, grh, grho_k, v.m_tot);
 }
 
 template <typename T>
