@@ -1,20 +1,31 @@
 """Benchmark: batched forward + backward unrolled COSMO on one MI355X.
 
-Workload (default): a batch of 64 max-cut SDPs, orders p ~ U{30..100}, edge
-probability ~ U(0.1, 0.5), float32, K = 50 unrolled steps with per-step
-penalties rho^k (per row) and relaxations alpha^k (per instance), loss =
-final primal residual^2 + dual residual^2, backward to every rho^k, alpha^k.
-One timed step = forward (K steps) + loss + backward (K steps) over the
-whole batch, inputs resident in HBM.
+Workloads (synthetic stand-ins with the shapes of the paper's App. F
+classes; `--workload`, default c2):
 
-Prints one JSON line: instance-iterations per second (B K / time per step),
-peak HBM of the batched forward + backward against the plain forward
-(unbatched, forward-only, no tape), the roofline of the dominant kernel
-family measured with HIP events inside the library, the error against the
-float64 oracle on a sample of instances, and the oracle's own throughput on
-the host cores (cpu_baseline).
+  c1  one max-cut SDP on G(20, 0.3), float64, K = 100, forward only,
+      CG tolerance 1e-10
+  c2  64 max-cut SDPs, orders p ~ U{30..100}, edge probability U(0.1, 0.5),
+      float32, K = 50 with per-step, per-row rho^k and per-instance alpha^k,
+      forward + loss + backward (the headline configuration)
+  c3  32 Lovasz theta SDPs on random circulant graphs, n ~ U{64..200},
+      float32, K = 50, forward + loss + backward
+  c4  256 Huber-regression SOCPs (2000 x 500 Gaussian design, Student-t
+      noise, 200 second-order cones of dimension 3-10), float32, K = 40,
+      forward + loss + backward
+  c5  128 covariance-steering SDPs (nx in {4..12}, nu = nx/2, T ~ U{30..100}),
+      float32, K = 30, forward + loss + backward
+
+One timed step = one pass of the whole unroll over the whole batch with
+inputs resident in HBM.  Prints one JSON line: instance-iterations per
+second (B K / time per step), peak HBM of the batched pass against the plain
+forward (B sequential single-instance forward-only calls, no tape), the
+roofline of the dominant kernel measured with HIP events recorded by the
+library on the stream the kernel runs on, and the float64 oracle's own
+throughput on the host cores over a bounded sample (cpu_baseline).
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,6 +37,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+METRIC = "fwd+bwd unrolled COSMO iters/s & peak HBM vs plain fwd, at 1e-5 rel err"
 PEAK_FP32_VECTOR_TFLOPS = 157.3     # MI355X published FP32 vector peak
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
@@ -35,7 +47,8 @@ PEAK_HBM_GBS = 8000.0
 EIG_FLOPS_PER_P3 = 11.0
 # The library's PSD order classes and their float32 eigensolve kernels.
 EIG_KERNEL_NAMES = {0: "k_psd_eig<float,64,4,32> (orders <= 32)", 1: "k_psd_eig<float,256,8,64> (orders 33-64)",
-                    2: "k_psd_eig<float,512,8,128> (orders 65-128)", 3: "k_psd_eig<float,1024,8,200> (orders 129-200)"}
+                    2: "k_psd_eig<float,512,8,128> (orders 65-128)",
+                    3: "k_psd_eig<float,1024,8,200> (orders 129-200)"}
 EIG_PROFILE = os.path.join(ROOT, "profiles", "k_psd_eig_maxcut64_pmc.md")
 EIG_SOURCE = os.path.join(ROOT, "paper_2606_13825_amd", "csrc", "k_psd.hip")
 
@@ -50,7 +63,6 @@ def traffic_from_profile(cls):
     committed counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the same
     counters on a copy kernel of known size); None when there is none for this
     class or the kernel source has changed since the counters were taken."""
-    import hashlib
     try:
         kv = {}
         with open(EIG_PROFILE) as f:
@@ -67,47 +79,92 @@ def traffic_from_profile(cls):
         return None
 
 
+def pcg_bytes_per_iteration(inst, esz):
+    """Algorithmic HBM bytes of one PCG iteration on one instance: the values
+    and column indices of A and A' (one pass each) and of P, plus the vectors
+    the iteration streams (p, t = rho A p, M p, x, r, z)."""
+    nnz_a = inst.A.nnz
+    nnz_p = inst.P.nnz if inst.P is not None else 0
+    return 2 * nnz_a * (esz + 4) + nnz_p * (esz + 4) + esz * (6 * inst.n + 2 * inst.m)
+
+
 def _workload(name):
     import synth
+    f32 = lambda xs: [x.astype(np.float32) for x in xs]
+    if name == "c1":
+        return dict(name="maxcut_sdp_G20p0.3_fp64_K100_forward", insts=[synth.c1_instance()], K=100, dtype="f64",
+                    backward=False, cg_tol=1e-10, hyper="default", cpu_sample=1, cpu_steps=100, roofline="eig")
     if name == "c2":
-        insts = [x.astype(np.float32) for x in synth.c2_batch()]
-        return dict(name="maxcut_sdp_batch64_p30-100_fp32_K50", insts=insts, K=50, dtype="f32", seed=2)
+        return dict(name="maxcut_sdp_batch64_p30-100_fp32_K50", insts=f32(synth.c2_batch()), K=50, dtype="f32",
+                    backward=True, hyper="perturbed", seed=2, cpu_sample=16, cpu_steps=50, roofline="eig")
+    if name == "c3":
+        return dict(name="lovasz_circulant_batch32_n64-200_fp32_K50", insts=f32(synth.c3_batch()), K=50,
+                    dtype="f32", backward=True, hyper="default", cpu_sample=16, cpu_steps=10, roofline="eig")
+    if name == "c4":
+        return dict(name="huber_socp_batch256_2000x500_200soc_fp32_K40", insts=f32(synth.c4_batch()), K=40,
+                    dtype="f32", backward=True, hyper="default", cpu_sample=16, cpu_steps=2, roofline="pcg",
+                    cg_max_iter=1000)
+    if name == "c5":
+        return dict(name="covsteer_sdp_batch128_nx4-12_T30-100_fp32_K30", insts=f32(synth.c5_batch()), K=30,
+                    dtype="f32", backward=True, hyper="default", cpu_sample=16, cpu_steps=30, roofline="eig",
+                    cg_max_iter=2000)
     raise SystemExit(f"unknown workload {name}")
 
 
-def _hyper(insts, K, seed):
+def _hyper(wl):
+    """rho [K, m] and alpha [K] per instance: the R1 defaults with alpha = 1.6,
+    or (c2, per-iteration learnable hyperparameters) a seeded log-uniform
+    perturbation of them with alpha^k ~ U(1.4, 1.8)."""
     import synth
-    rng = np.random.default_rng(1000 + seed)
+    npdt = np.float32 if wl["dtype"] == "f32" else np.float64
     rhos, alphas = [], []
-    for inst in insts:
-        r, a = synth.perturbed_hyper(inst, K, rng)
-        rhos.append(r.astype(np.float32))
-        alphas.append(a.astype(np.float32))
+    rng = np.random.default_rng(1000 + wl.get("seed", 0))
+    for inst in wl["insts"]:
+        if wl["hyper"] == "perturbed":
+            r, a = synth.perturbed_hyper(inst, wl["K"], rng)
+        else:
+            r, a = synth.default_rho(inst, wl["K"]), np.full(wl["K"], 1.6)
+        rhos.append(r.astype(np.float32).astype(npdt))
+        alphas.append(a.astype(np.float32).astype(npdt))
     return rhos, alphas
 
 
 def _oracle_job(args):
-    inst, rho, alpha = args
+    inst, rho, alpha, backward = args
     import oracle
     t0 = time.perf_counter()
     tape, (x, s, y) = oracle.unroll_forward(inst, rho, alpha)
-    g = oracle.residual_loss_grad(inst, x, s, y)
-    grho, galpha, *_ = oracle.unroll_backward(inst, tape, *g)
+    grho = galpha = None
+    if backward:
+        g = oracle.residual_loss_grad(inst, x, s, y)
+        grho, galpha, *_ = oracle.unroll_backward(inst, tape, *g)
     return time.perf_counter() - t0, x, s, y, grho, galpha
 
 
-def cpu_baseline(insts, rhos, alphas, K, n_sample, workers):
-    """The float64 oracle, as it stands, on the first n_sample instances,
-    instance-parallel over `workers` single-threaded processes."""
+def cpu_baseline(wl, rhos, alphas, n_sample, steps, workers):
+    """The float64 oracle, as it stands, on the first n_sample instances and
+    the first `steps` unrolled steps, instance-parallel over `workers`
+    single-threaded processes."""
     import multiprocessing as mp
-    jobs = [(insts[i], rhos[i].astype(np.float64), alphas[i].astype(np.float64)) for i in range(n_sample)]
+    jobs = [(wl["insts"][i], rhos[i][:steps].astype(np.float64), alphas[i][:steps].astype(np.float64),
+             wl["backward"]) for i in range(n_sample)]
     # runs before this process touches the GPU, so forked workers are plain CPU processes
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(workers) as pool:
         res = pool.map(_oracle_job, jobs)
-    wall = time.perf_counter() - t0
-    return wall, res
+    return time.perf_counter() - t0, res
+
+
+def _copy_calibration():
+    import torch
+    n = 64 * 1024 * 1024
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "dispatches": 5}))
 
 
 def main():
@@ -115,9 +172,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2")
-    ap.add_argument("--cpu-sample", type=int, default=16)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--cpu-sample", type=int, default=None, help="instances in the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain (unbatched forward-only) comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB five times (reference for the HBM byte counters)")
     ap.add_argument("--quick", action="store_true",
@@ -126,26 +184,19 @@ def main():
     args = ap.parse_args()
     if args.quick:
         args.no_cpu_baseline = True
+        args.no_plain = True
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU: the batch shards over instances with no "
                                    "exchange inside the unroll, but runs on more than one GPU are not part of it"}))
         raise SystemExit(2)
-
     if args.copy_calibration:
-        import torch
-        n = 64 * 1024 * 1024
-        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
-        dst = torch.empty_like(src)
-        for _ in range(5):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "dispatches": 5}))
+        _copy_calibration()
         return
 
     wl = _workload(args.workload)
-    insts, K = wl["insts"], wl["K"]
+    insts, K, backward = wl["insts"], wl["K"], wl["backward"]
     B = len(insts)
-    rhos, alphas = _hyper(insts, K, wl["seed"])
+    rhos, alphas = _hyper(wl)
     print(f"[bench] workload {wl['name']}: B={B} K={K}", file=sys.stderr, flush=True)
 
     cpu = None
@@ -154,29 +205,38 @@ def main():
             aff = len(os.sched_getaffinity(0))
         except AttributeError:
             aff = os.cpu_count() or 1
-        workers = max(1, min(16, aff, args.cpu_sample))
-        n_s = min(args.cpu_sample, B)
-        wall, res = cpu_baseline(insts, rhos, alphas, K, n_s, workers)
-        cpu = (wall, res, workers, n_s)
-        print(f"[bench] cpu baseline: {n_s} instances in {wall:.1f} s on {workers} processes", file=sys.stderr,
-              flush=True)
+        n_s = min(args.cpu_sample or wl["cpu_sample"], B)
+        workers = max(1, min(16, aff, n_s))
+        steps = min(wl["cpu_steps"], K)
+        wall, res = cpu_baseline(wl, rhos, alphas, n_s, steps, workers)
+        cpu = (wall, res, workers, n_s, steps)
+        print(f"[bench] cpu baseline: {n_s} instances x {steps} steps in {wall:.1f} s on {workers} processes",
+              file=sys.stderr, flush=True)
 
     import torch
     from paper_2606_13825_amd import CosmoBatch
 
     dev = torch.device("cuda:0")
     torch.zeros(1, device=dev)          # initialise the device before the memory counters
+    tdt = torch.float32 if wl["dtype"] == "f32" else torch.float64
+    kw = {}
+    for key in ("cg_tol", "cg_max_iter"):
+        if key in wl:
+            kw[key] = wl[key]
 
     torch.cuda.reset_peak_memory_stats(dev)
     base_mem = torch.cuda.memory_allocated(dev)
-    batch = CosmoBatch(insts, K=K, dtype=torch.float32, device=dev)
+    batch = CosmoBatch(insts, K=K, dtype=tdt, device=dev, **kw)
     rho = torch.from_numpy(np.concatenate(rhos, axis=1)).to(dev)
     alpha = torch.from_numpy(np.stack(alphas, axis=1)).to(dev)
-    tape = batch.new_tape()
-    fws, bws = batch.new_fwd_ws(), batch.new_bwd_ws()
+    tape = batch.new_tape() if backward else None
+    fws = batch.new_fwd_ws()
+    bws = batch.new_bwd_ws() if backward else None
     stats = batch.new_stats()
 
     def step():
+        if not backward:
+            return batch.forward(rho, alpha, tape=False, ws=fws, stats=stats), None, None
         fw = batch.forward(rho, alpha, tape=tape, ws=fws, stats=stats)
         loss, g = batch.residual_loss(fw.x, fw.s, fw.y, ws=fws)
         bw = batch.backward(rho, alpha, fw.tape, *g, ws=bws, stats=stats)
@@ -191,54 +251,89 @@ def main():
     torch.cuda.synchronize(dev)
     dt = (time.perf_counter() - t0) / args.steps
     peak_fb = torch.cuda.max_memory_allocated(dev) - base_mem
-    print(f"[bench] fwd+bwd {dt * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+    print(f"[bench] {'fwd+bwd' if backward else 'fwd'} {dt * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
 
     if args.quick:
-        print(json.dumps({"metric": "fwd+bwd unrolled COSMO iters/s (counter-collection run)",
-                          "value": B * K / dt, "unit": "instance-iterations/s", "ms_per_step": dt * 1e3}))
+        print(json.dumps({"metric": METRIC + " (counter-collection run)", "value": B * K / dt,
+                          "unit": "instance-iterations/s", "ms_per_step": dt * 1e3,
+                          "config": {"workload": wl["name"]}}))
         return
 
     # kernel families, and the eigensolve kernel of each PSD order class alone,
     # timed with HIP events recorded by the library on the streams they run on
+    st_prof = batch.new_stats()
     batch.set_profiling(True)
-    step()
+    if backward:
+        fw2 = batch.forward(rho, alpha, tape=tape, ws=fws, stats=st_prof)
+        _, g2 = batch.residual_loss(fw2.x, fw2.s, fw2.y, ws=fws)
+        batch.backward(rho, alpha, fw2.tape, *g2, ws=bws, stats=st_prof)
+    else:
+        batch.forward(rho, alpha, tape=False, ws=fws, stats=st_prof)
     torch.cuda.synchronize(dev)
     fam = {}
     for kind, name in ((0, "psd_eig_project"), (1, "psd_dk_vjp"), (2, "pcg"), (3, "csr_row_col_passes")):
         fam[name] = batch.profile_read(kind)
     cls = {c: batch.profile_read(4 + c) for c in range(4)}
     batch.set_profiling(False)
-    orders = np.array([inst.meta["order"] for inst in insts], np.float64)
-    cls_of = psd_order_class(orders)
-    dom = max((c for c in cls if cls[c][0] > 0), key=lambda c: cls[c][1])
-    n_dom, ms_dom = cls[dom]
-    dom_flops = float(np.sum(EIG_FLOPS_PER_P3 * orders[cls_of == dom] ** 3))
-    avg_dom_ms = ms_dom / max(n_dom, 1)
-    achieved = dom_flops / (avg_dom_ms * 1e-3) / 1e12
+    sprof = batch.stats_dict(st_prof)
     print(f"[bench] kernel families (launches, ms): {fam}", file=sys.stderr, flush=True)
     print(f"[bench] eigensolve per order class (launches, ms): {cls}", file=sys.stderr, flush=True)
 
-    # plain forward: unbatched, forward-only, no tape
-    del tape, fws, bws
-    torch.cuda.empty_cache()
-    torch.cuda.reset_peak_memory_stats(dev)
-    base_mem2 = torch.cuda.memory_allocated(dev)
-    singles = [CosmoBatch([inst], K=K, dtype=torch.float32, device=dev) for inst in insts]
-    srho = [torch.from_numpy(r).to(dev) for r in rhos]
-    salpha = [torch.from_numpy(a.reshape(K, 1)).to(dev) for a in alphas]
-    for i in range(min(2, B)):
-        singles[i].forward(srho[i], salpha[i], tape=False)
-    torch.cuda.synchronize(dev)
-    t1 = time.perf_counter()
-    for i in range(B):
-        singles[i].forward(srho[i], salpha[i], tape=False)
-    torch.cuda.synchronize(dev)
-    dt_plain = time.perf_counter() - t1
-    peak_plain = torch.cuda.max_memory_allocated(dev) - base_mem2
-    print(f"[bench] plain forward {dt_plain * 1e3:.2f} ms for B={B}", file=sys.stderr, flush=True)
+    rooflines = {}
+    orders = np.array([c.size for inst in insts for c in inst.cones if c.kind == "psd"], np.float64)
+    if len(orders) and any(cls[c][0] > 0 for c in cls):
+        cls_of = psd_order_class(orders)
+        dom = max((c for c in cls if cls[c][0] > 0), key=lambda c: cls[c][1])
+        n_dom, ms_dom = cls[dom]
+        flops = float(np.sum(EIG_FLOPS_PER_P3 * orders[cls_of == dom] ** 3))
+        avg_ms = ms_dom / max(n_dom, 1)
+        ach = flops / (avg_ms * 1e-3) / 1e12
+        peak = PEAK_FP32_VECTOR_TFLOPS if wl["dtype"] == "f32" else PEAK_FP64_TFLOPS
+        name = EIG_KERNEL_NAMES[dom] if wl["dtype"] == "f32" else EIG_KERNEL_NAMES[dom].replace("float", "double")
+        rooflines["eig"] = {"kernel": name, "bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                            "frac": ach / peak,
+                            "traffic": traffic_from_profile(dom) if args.workload == "c2" else None,
+                            "flops_per_launch": flops, "blocks_per_launch": int(np.sum(cls_of == dom)),
+                            "avg_launch_ms": avg_ms, "launches": n_dom}
+    n_pcg, ms_pcg = fam["pcg"]
+    if n_pcg > 0:
+        esz = 4 if wl["dtype"] == "f32" else 8
+        iters = sprof["cg_iters_total"].astype(np.float64)
+        # each launch solves every instance once: (iterations + 1) operator applications
+        total = sum((iters[i] + n_pcg) * pcg_bytes_per_iteration(inst, esz) for i, inst in enumerate(insts))
+        avg_ms = ms_pcg / n_pcg
+        ach = total / n_pcg / (avg_ms * 1e-3) / 1e9
+        rooflines["pcg"] = {"kernel": "k_pcg<%s> (one workgroup per instance)" % ("float" if esz == 4 else "double"),
+                            "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                            "frac": ach / PEAK_HBM_GBS, "traffic": None, "bytes_per_launch": total / n_pcg,
+                            "avg_launch_ms": avg_ms, "launches": n_pcg,
+                            "mean_cg_iterations": float(iters.sum() / (n_pcg * B))}
+    primary = wl["roofline"] if wl["roofline"] in rooflines else next(iter(rooflines), None)
+
+    plain = None
+    peak_plain = None
+    if not args.no_plain:
+        del tape, fws, bws
+        torch.cuda.empty_cache()
+        torch.cuda.reset_peak_memory_stats(dev)
+        base_mem2 = torch.cuda.memory_allocated(dev)
+        singles = [CosmoBatch([inst], K=K, dtype=tdt, device=dev, **kw) for inst in insts]
+        srho = [torch.from_numpy(r).to(dev) for r in rhos]
+        salpha = [torch.from_numpy(a.reshape(K, 1)).to(dev) for a in alphas]
+        for i in range(min(2, B)):
+            singles[i].forward(srho[i], salpha[i], tape=False)
+        torch.cuda.synchronize(dev)
+        t1 = time.perf_counter()
+        for i in range(B):
+            singles[i].forward(srho[i], salpha[i], tape=False)
+        torch.cuda.synchronize(dev)
+        dt_plain = time.perf_counter() - t1
+        peak_plain = torch.cuda.max_memory_allocated(dev) - base_mem2
+        plain = {"value": B * K / dt_plain, "unit": "instance-iterations/s", "ms_total": dt_plain * 1e3}
+        print(f"[bench] plain forward {dt_plain * 1e3:.2f} ms for B={B}", file=sys.stderr, flush=True)
 
     out = {
-        "metric": "fwd+bwd unrolled COSMO iters/s & peak HBM vs plain fwd, at 1e-5 rel err",
+        "metric": METRIC,
         "value": B * K / dt,
         "unit": "instance-iterations/s",
         "n_gpus": 1,
@@ -248,38 +343,41 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": wl["dtype"],
         "data": "synthetic",
-        "config": {"workload": wl["name"], "instances": B, "unroll_K": K, "pass": "forward+loss+backward",
-                   "psd_orders": [int(o) for o in orders]},
-        "peak_hbm_bytes": {"fwd_bwd_batched": int(peak_fb), "plain_fwd_unbatched": int(peak_plain)},
-        "plain_fwd": {"value": B * K / dt_plain, "unit": "instance-iterations/s", "ms_total": dt_plain * 1e3},
+        "config": {"workload": wl["name"], "instances": B, "unroll_K": K,
+                   "pass": "forward+loss+backward" if backward else "forward"},
+        "peak_hbm_bytes": {"batched": int(peak_fb), "plain_fwd_unbatched": None if peak_plain is None
+                           else int(peak_plain)},
+        "plain_fwd": plain,
         "kernel_families_ms_per_step": {k: v[1] for k, v in fam.items()},
-        "roofline": {"kernel": EIG_KERNEL_NAMES[dom], "bound": "alu", "achieved": achieved,
-                     "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
-                     "traffic": traffic_from_profile(dom),
-                     "flops_per_launch": dom_flops, "blocks_per_launch": int(np.sum(cls_of == dom)),
-                     "avg_launch_ms": avg_dom_ms, "launches": n_dom},
+        "roofline": rooflines.get(primary),
+        "roofline_other": {k: v for k, v in rooflines.items() if k != primary} or None,
         "stats": {k: int(v.max()) for k, v in batch.stats_dict(stats).items()},
     }
 
     if cpu is not None:
-        wall, res, workers, n_s = cpu
-        out["cpu_baseline"] = {"value": n_s * K / wall, "unit": "instance-iterations/s", "cores": workers,
+        wall, res, workers, n_s, steps = cpu
+        out["cpu_baseline"] = {"value": n_s * steps / wall, "unit": "instance-iterations/s", "cores": workers,
                                "kind": "oracle",
-                               "sample": f"first {n_s} instances of the batch, forward+loss+backward, K={K}, "
-                                         f"float64, {workers} single-threaded processes"}
-        # error of the timed GPU run against the oracle on the same sample
-        e_it, e_g = 0.0, 0.0
-        xs, ss, ys = batch.split_n(fw.x), batch.split_m(fw.s), batch.split_m(fw.y)
-        for i, (_, x, s, y, grho, galpha) in enumerate(res):
-            for gpu, ref in ((xs[i], x), (ss[i], s), (ys[i], y)):
-                e_it = max(e_it, np.linalg.norm(gpu.double().cpu().numpy() - ref) / max(np.linalg.norm(ref), 1e-12))
-            gr = bw.grho[:, batch.m_off[i]:batch.m_off[i + 1]].double().cpu().numpy()
-            e_g = max(e_g, np.linalg.norm(gr - grho) / max(np.linalg.norm(grho), 1e-12))
-            ga = bw.galpha[:, i].double().cpu().numpy()
-            e_g = max(e_g, np.linalg.norm(ga - galpha) / max(np.linalg.norm(galpha), 1e-12))
-        out["rel_err_vs_oracle"] = {"final_iterates_max": e_it, "gradients_max": e_g, "instances": n_s}
+                               "sample": f"first {n_s} instances of the batch, first {steps} of {K} steps, "
+                                         f"{'forward+loss+backward' if backward else 'forward'}, float64, "
+                                         f"{workers} single-threaded processes"}
+        if steps == K:
+            # error of the timed GPU run against the oracle on the same sample
+            e_it, e_g = 0.0, 0.0
+            xs, ss, ys = batch.split_n(fw.x), batch.split_m(fw.s), batch.split_m(fw.y)
+            for i, (_, x, s, y, grho, galpha) in enumerate(res):
+                for gpu, ref in ((xs[i], x), (ss[i], s), (ys[i], y)):
+                    e_it = max(e_it, np.linalg.norm(gpu.double().cpu().numpy() - ref) /
+                               max(np.linalg.norm(ref), 1e-12))
+                if backward:
+                    gr = bw.grho[:, batch.m_off[i]:batch.m_off[i + 1]].double().cpu().numpy()
+                    e_g = max(e_g, np.linalg.norm(gr - grho) / max(np.linalg.norm(grho), 1e-12))
+                    ga = bw.galpha[:, i].double().cpu().numpy()
+                    e_g = max(e_g, np.linalg.norm(ga - galpha) / max(np.linalg.norm(galpha), 1e-12))
+            out["rel_err_vs_oracle"] = {"final_iterates_max": e_it, "gradients_max": e_g if backward else None,
+                                        "instances": n_s}
     print(json.dumps(out))
 
 

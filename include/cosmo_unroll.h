@@ -131,7 +131,7 @@ typedef struct {
   int32_t eig_sweeps_total;    /* Jacobi sweeps summed over the PSD block solves       */
   int32_t eig_solves;          /* PSD block eigensolves (eig_sweeps_total / eig_solves
                                   is the mean sweep count)                              */
-  int32_t reserved;
+  int32_t cg_iters_total;      /* PCG iterations summed over the solves                */
 } cosmo_stats;
 
 const char *cosmo_status_string(cosmo_status s);

@@ -65,7 +65,10 @@ template <typename T> struct View {
   const T *Pdiag;
   const uint8_t *row_kind; const int32_t *row_inst; const int32_t *col_inst;
   const int64_t *n_off; const int64_t *m_off;
-  const int32_t *inst_LA; const int32_t *inst_LAt;
+  // per instance b and row-length class c (1, 8, 64 lanes per row): its rows
+  // of A (columns of A for At) are rowsA[instA[c (B+1) + b] .. instA[c (B+1) + b + 1])
+  const int32_t *rowsA; const int32_t *rowsAt;
+  const int64_t *instA; const int64_t *instAt;
   int32_t B; int64_t n_tot, m_tot;
   T sigma;
 };

@@ -45,45 +45,59 @@ template <typename T> __device__ inline void block_sum2(T &a, T &b, T *red) {
   b = tb;
 }
 
-// out = M p over the instance; returns (in every thread) p'Mp.
+// One pass of CSR row products over the rows rows[r0..r1) of one length
+// class, L lanes per row (each lane keeps two products in flight), handing
+// each row's sum to emit(row, sum) on its first lane.
+template <typename T, int L, typename F>
+__device__ inline void csr_pass(const int32_t *__restrict__ rows, int64_t r0, int64_t r1,
+                                const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                const T *__restrict__ val, const T *__restrict__ vin, F emit) {
+  constexpr int per = PT / L;
+  const int sub = threadIdx.x / L, lane = threadIdx.x % L;
+  for (int64_t base = r0; base < r1; base += per) {
+    const int64_t ri = base + sub;
+    int32_t row = 0;
+    T a0 = 0, a1 = 0;
+    if (ri < r1) {
+      row = rows[ri];
+      const int64_t k1 = rowptr[row + 1];
+      int64_t k = rowptr[row] + lane;
+      for (; k + L < k1; k += 2 * L) {
+        a0 += val[k] * vin[col[k]];
+        a1 += val[k + L] * vin[col[k + L]];
+      }
+      if (k < k1) a0 += val[k] * vin[col[k]];
+    }
+    const T acc = sub_sum(a0 + a1, L);   // every lane of the row group takes part
+    if (ri < r1 && lane == 0) emit(row, acc);
+  }
+}
+
+// out = M p over the instance; returns (in every thread) p'Mp.  Rows of A and
+// of A' are taken by length class (1, 8 or 64 lanes per row).
 template <typename T>
 __device__ T apply_M(const View<T> &v, const T *__restrict__ rho_hat, const T *__restrict__ p, T *__restrict__ t,
-                     T *__restrict__ out, int64_t n0, int64_t n1, int64_t m0, int64_t m1, int LA, int LAt,
-                     T *red) {
+                     T *__restrict__ out, int b, T *red) {
+  const int64_t B1 = v.B + 1;
   // t_i = rho_hat_i (A p)_i
-  {
-    const int per = PT / LA;
-    const int sub = threadIdx.x / LA, lane = threadIdx.x % LA;
-    for (int64_t base = m0; base < m1; base += per) {
-      const int64_t i = base + sub;
-      T acc = 0;
-      if (i < m1)
-        for (int64_t k = v.A_rowptr[i] + lane; k < v.A_rowptr[i + 1]; k += LA) acc += v.A_val[k] * p[v.A_col[k]];
-      acc = sub_sum(acc, LA);
-      if (i < m1 && lane == 0) t[i] = rho_hat[i] * acc;
-    }
-  }
+  auto emit_t = [&](int32_t i, T acc) { t[i] = rho_hat[i] * acc; };
+  csr_pass<T, 1>(v.rowsA, v.instA[b], v.instA[b + 1], v.A_rowptr, v.A_col, v.A_val, p, emit_t);
+  csr_pass<T, 8>(v.rowsA, v.instA[B1 + b], v.instA[B1 + b + 1], v.A_rowptr, v.A_col, v.A_val, p, emit_t);
+  csr_pass<T, 64>(v.rowsA, v.instA[2 * B1 + b], v.instA[2 * B1 + b + 1], v.A_rowptr, v.A_col, v.A_val, p, emit_t);
   __syncthreads();
+  // (M p)_j = (A' t)_j + (P p)_j + sigma p_j
   T pMp = 0, dummy = 0;
-  {
-    const int per = PT / LAt;
-    const int sub = threadIdx.x / LAt, lane = threadIdx.x % LAt;
-    for (int64_t base = n0; base < n1; base += per) {
-      const int64_t j = base + sub;
-      T acc = 0;
-      if (j < n1) {
-        for (int64_t k = v.At_rowptr[j] + lane; k < v.At_rowptr[j + 1]; k += LAt) acc += v.At_val[k] * t[v.At_col[k]];
-        if (v.P_rowptr)
-          for (int64_t k = v.P_rowptr[j] + lane; k < v.P_rowptr[j + 1]; k += LAt) acc += v.P_val[k] * p[v.P_col[k]];
-      }
-      acc = sub_sum(acc, LAt);
-      if (j < n1 && lane == 0) {
-        const T mp = acc + v.sigma * p[j];
-        out[j] = mp;
-        pMp += p[j] * mp;
-      }
-    }
-  }
+  auto emit_m = [&](int32_t j, T acc) {
+    if (v.P_rowptr)
+      for (int64_t k = v.P_rowptr[j]; k < v.P_rowptr[j + 1]; ++k) acc += v.P_val[k] * p[v.P_col[k]];
+    const T mp = acc + v.sigma * p[j];
+    out[j] = mp;
+    pMp += p[j] * mp;
+  };
+  csr_pass<T, 1>(v.rowsAt, v.instAt[b], v.instAt[b + 1], v.At_rowptr, v.At_col, v.At_val, t, emit_m);
+  csr_pass<T, 8>(v.rowsAt, v.instAt[B1 + b], v.instAt[B1 + b + 1], v.At_rowptr, v.At_col, v.At_val, t, emit_m);
+  csr_pass<T, 64>(v.rowsAt, v.instAt[2 * B1 + b], v.instAt[2 * B1 + b + 1], v.At_rowptr, v.At_col, v.At_val, t,
+                  emit_m);
   block_sum2(pMp, dummy, red);
   return pMp;
 }
@@ -98,11 +112,10 @@ __global__ __launch_bounds__(PT) void k_pcg(View<T> v, const T *__restrict__ rho
                                             T *__restrict__ gx_out, int32_t mode, cosmo_stats *stats) {
   __shared__ T red[2 * NW];
   const int b = blockIdx.x;
-  const int64_t n0 = v.n_off[b], n1 = v.n_off[b + 1], m0 = v.m_off[b], m1 = v.m_off[b + 1];
-  const int LA = v.inst_LA[b], LAt = v.inst_LAt[b];
+  const int64_t n0 = v.n_off[b], n1 = v.n_off[b + 1];
 
   // r = rhs - M x (warm start)
-  apply_M(v, rho_hat, x, t, Mp, n0, n1, m0, m1, LA, LAt, red);
+  apply_M(v, rho_hat, x, t, Mp, b, red);
   __syncthreads();
   T rz = 0, rr = 0, bb = 0, dummy = 0;
   for (int64_t j = n0 + threadIdx.x; j < n1; j += PT) {
@@ -124,7 +137,7 @@ __global__ __launch_bounds__(PT) void k_pcg(View<T> v, const T *__restrict__ rho
   int it = 0;
   while (!fail && rr > thr && it < max_iter) {
     __syncthreads();   // p complete before the operator reads it
-    const T pMp = apply_M(v, rho_hat, p, t, Mp, n0, n1, m0, m1, LA, LAt, red);
+    const T pMp = apply_M(v, rho_hat, p, t, Mp, b, red);
     if (!(pMp > (T)0)) {   // breakdown at round-off level: keep the current x
       fail = !isfinite(pMp);
       break;
@@ -160,6 +173,7 @@ __global__ __launch_bounds__(PT) void k_pcg(View<T> v, const T *__restrict__ rho
   }
   if (stats && threadIdx.x == 0) {
     atomicMax(&stats[b].cg_iters_max, it);
+    atomicAdd(&stats[b].cg_iters_total, it);
     if (!(rr <= thr)) atomicAdd(&stats[b].cg_not_converged, 1);
   }
 }

@@ -85,7 +85,7 @@ struct cosmo_plan {
   void *d_Pdiag = nullptr;
   uint8_t *d_row_kind = nullptr;
   int32_t *d_row_inst = nullptr, *d_col_inst = nullptr;
-  int32_t *d_inst_LA = nullptr, *d_inst_LAt = nullptr;
+  int64_t *d_instA = nullptr, *d_instAt = nullptr;   // per-instance ranges of the row classes
   SocDesc *d_soc = nullptr;
   int32_t n_soc = 0;
   PsdDesc *d_psd = nullptr;
@@ -151,8 +151,10 @@ template <typename T> View<T> make_view(const cosmo_plan *pl) {
   v.col_inst = pl->d_col_inst;
   v.n_off = pl->d_n_off;
   v.m_off = pl->d_m_off;
-  v.inst_LA = pl->d_inst_LA;
-  v.inst_LAt = pl->d_inst_LAt;
+  v.rowsA = pl->bkA.d_rows;
+  v.rowsAt = pl->bkAt.d_rows;
+  v.instA = pl->d_instA;
+  v.instAt = pl->d_instAt;
   v.B = pl->B;
   v.n_tot = pl->n_tot;
   v.m_tot = pl->m_tot;
@@ -233,12 +235,6 @@ cosmo_status validate_problem_host(const cosmo_problem *p, const cosmo_options *
   }
   if (row != m_tot) FAIL(COSMO_EINVAL, "cone rows sum to " + std::to_string(row) + " but m_tot is " + std::to_string(m_tot));
   return COSMO_OK;
-}
-
-int pow2_lanes(double avg) {
-  int L = 1;
-  while (L < 64 && L < avg) L <<= 1;
-  return L;
 }
 
 void build_buckets(const std::vector<int64_t> &rowptr, int64_t nrows, std::vector<int32_t> &rows_out,
@@ -388,14 +384,19 @@ cosmo_status build_plan(cosmo_plan *pl, const cosmo_problem *p) {
   std::vector<int32_t> rowsA, rowsAt;
   build_buckets(rp, m, rowsA, pl->bkA);
   build_buckets(trp, n, rowsAt, pl->bkAt);
-  std::vector<int32_t> LA(pl->B), LAt(pl->B);
-  for (int b = 0; b < pl->B; ++b) {
-    const int64_t r0 = pl->m_off[b], r1 = pl->m_off[b + 1], c0 = pl->n_off[b], c1 = pl->n_off[b + 1];
-    const double annz = (double)(rp[r1] - rp[r0]) / std::max<int64_t>(1, r1 - r0);
-    const double tnnz = (double)(trp[c1] - trp[c0] + prp[c1] - prp[c0]) / std::max<int64_t>(1, c1 - c0);
-    LA[b] = pow2_lanes(annz);
-    LAt[b] = pow2_lanes(tnnz);
-  }
+  // rows of each class are listed in increasing order, so an instance's rows
+  // of a class are one contiguous range of the list
+  auto inst_ranges = [&](const std::vector<int32_t> &rows, const RowBuckets &bk, const std::vector<int64_t> &off) {
+    std::vector<int64_t> rng(3 * (size_t)(pl->B + 1));
+    for (int c = 0; c < 3; ++c) {
+      auto first = rows.begin() + bk.begin[c], last = rows.begin() + bk.begin[c + 1];
+      for (int b = 0; b <= pl->B; ++b)
+        rng[c * (size_t)(pl->B + 1) + b] = std::lower_bound(first, last, off[b]) - rows.begin();
+    }
+    return rng;
+  };
+  const std::vector<int64_t> instA = inst_ranges(rowsA, pl->bkA, pl->m_off);
+  const std::vector<int64_t> instAt = inst_ranges(rowsAt, pl->bkAt, pl->n_off);
   // --- one device allocation for everything the plan owns
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -407,7 +408,7 @@ cosmo_status build_plan(cosmo_plan *pl, const cosmo_problem *p) {
   const size_t o_trp = take((n + 1) * sizeof(int64_t)), o_tcol = take(std::max<int64_t>(nnz, 1) * sizeof(int32_t));
   const size_t o_tval = take(std::max<int64_t>(nnz, 1) * sizeof(T)), o_pdiag = take(n * sizeof(T));
   const size_t o_rkind = take(m), o_rinst = take(m * sizeof(int32_t)), o_cinst = take(n * sizeof(int32_t));
-  const size_t o_LA = take(pl->B * sizeof(int32_t)), o_LAt = take(pl->B * sizeof(int32_t));
+  const size_t o_iA = take(instA.size() * sizeof(int64_t)), o_iAt = take(instAt.size() * sizeof(int64_t));
   const size_t o_soc = take(std::max<size_t>(socs.size(), 1) * sizeof(SocDesc));
   const size_t o_psd = take(std::max<size_t>(psds.size(), 1) * sizeof(PsdDesc));
   const size_t o_rect = take(std::max<size_t>(rects.size(), 1) * sizeof(RectDesc));
@@ -431,8 +432,8 @@ cosmo_status build_plan(cosmo_plan *pl, const cosmo_problem *p) {
   HIPCHK(up(o_rkind, rkind.data(), m));
   HIPCHK(up(o_rinst, rinst.data(), m * sizeof(int32_t)));
   HIPCHK(up(o_cinst, cinst.data(), n * sizeof(int32_t)));
-  HIPCHK(up(o_LA, LA.data(), pl->B * sizeof(int32_t)));
-  HIPCHK(up(o_LAt, LAt.data(), pl->B * sizeof(int32_t)));
+  HIPCHK(up(o_iA, instA.data(), instA.size() * sizeof(int64_t)));
+  HIPCHK(up(o_iAt, instAt.data(), instAt.size() * sizeof(int64_t)));
   HIPCHK(up(o_soc, socs.data(), socs.size() * sizeof(SocDesc)));
   HIPCHK(up(o_psd, psds.data(), psds.size() * sizeof(PsdDesc)));
   HIPCHK(up(o_rect, rects.data(), rects.size() * sizeof(RectDesc)));
@@ -447,8 +448,8 @@ cosmo_status build_plan(cosmo_plan *pl, const cosmo_problem *p) {
   pl->d_row_kind = reinterpret_cast<uint8_t *>(base + o_rkind);
   pl->d_row_inst = reinterpret_cast<int32_t *>(base + o_rinst);
   pl->d_col_inst = reinterpret_cast<int32_t *>(base + o_cinst);
-  pl->d_inst_LA = reinterpret_cast<int32_t *>(base + o_LA);
-  pl->d_inst_LAt = reinterpret_cast<int32_t *>(base + o_LAt);
+  pl->d_instA = reinterpret_cast<int64_t *>(base + o_iA);
+  pl->d_instAt = reinterpret_cast<int64_t *>(base + o_iAt);
   pl->d_soc = reinterpret_cast<SocDesc *>(base + o_soc);
   pl->d_psd = reinterpret_cast<PsdDesc *>(base + o_psd);
   pl->d_rect = reinterpret_cast<RectDesc *>(base + o_rect);
