@@ -220,6 +220,28 @@ cosmo_status socp_proj(int32_t ncones, const int32_t *dim, const int64_t *offset
 cosmo_status socp_proj_vjp(int32_t ncones, const int32_t *dim, const int64_t *offset, cosmo_dtype dtype,
                            const void *in, const void *gout, void *gin, void *ws, void *stream);
 
+/* Schedules of the CG solves (Table 2; Sec. "Matrix-Free Implicit
+ * Differentiation"): form 0 = one workgroup per instance iterating to its own
+ * tolerance (the default); form f = 1 or 2 = one cooperative launch over the
+ * whole device with at most f workgroups per compute unit, the operator
+ * passes of all instances spread over every workgroup and grid barriers
+ * between phases (falls back to form 0 where cooperative launch is not
+ * available).  Both forms compute the same iteration with the same stopping
+ * rule; their sums are taken in different orders, each deterministic.
+ * set_pcg_form: form outside 0..2 is COSMO_EINVAL. */
+cosmo_status cosmo_plan_set_pcg_form(cosmo_plan *plan, int32_t form);
+cosmo_status cosmo_plan_get_pcg_form(const cosmo_plan *plan, int32_t *form);
+
+/* Autotuner: runs the forward unroll (no tape) once per CG schedule on the
+ * given rho, alpha and forward workspace, times the second of two runs with
+ * events on `stream`, and keeps the fastest schedule in the plan.  A setup
+ * call, not for the hot path: it allocates a scratch output buffer and waits
+ * for the stream.  ms (host, nullable) [3] receives the timings (-1 for
+ * forms not run); problems whose reduced matrix is diagonal have no CG and
+ * keep their form. */
+cosmo_status cosmo_plan_autotune(cosmo_plan *plan, const void *rho, const void *alpha, void *ws, void *stream,
+                                 double *ms);
+
 /* Measurement support (not needed on the hot path).  With profiling on, the
  * library records a pair of HIP events on the call's stream around every
  * launch of a kernel family: 0 = PSD eigensolve + reconstruction (all order

@@ -21,6 +21,7 @@ EXPORTED = [
     "cosmo_unroll_forward", "cosmo_unroll_backward", "cosmo_residual_loss",
     "cosmo_proj_workspace_size", "psd_proj", "psd_proj_vjp", "socp_proj", "socp_proj_vjp",
     "cosmo_plan_set_profiling", "cosmo_plan_profile_read",
+    "cosmo_plan_set_pcg_form", "cosmo_plan_get_pcg_form", "cosmo_plan_autotune",
 ]
 
 
@@ -116,6 +117,12 @@ def _sig(lib):
     lib.cosmo_plan_set_profiling.argtypes = [vp, i32]
     lib.cosmo_plan_profile_read.restype = ctypes.c_int
     lib.cosmo_plan_profile_read.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(dbl)]
+    lib.cosmo_plan_set_pcg_form.restype = ctypes.c_int
+    lib.cosmo_plan_set_pcg_form.argtypes = [vp, i32]
+    lib.cosmo_plan_get_pcg_form.restype = ctypes.c_int
+    lib.cosmo_plan_get_pcg_form.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.cosmo_plan_autotune.restype = ctypes.c_int
+    lib.cosmo_plan_autotune.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(dbl)]
 
 
 def lib():

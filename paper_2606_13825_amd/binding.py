@@ -277,6 +277,28 @@ class CosmoBatch:
     def set_profiling(self, on: bool):
         L.check(L.lib().cosmo_plan_set_profiling(self._plan, int(on)), "cosmo_plan_set_profiling")
 
+    # -- schedules ----------------------------------------------------------------
+    def set_pcg_form(self, form: int):
+        """CG schedule: 0 one workgroup per instance, 1 or 2 cooperative (that
+        many workgroups per compute unit at most)."""
+        L.check(L.lib().cosmo_plan_set_pcg_form(self._plan, int(form)), "cosmo_plan_set_pcg_form")
+
+    def pcg_form(self) -> int:
+        f = ctypes.c_int32()
+        L.check(L.lib().cosmo_plan_get_pcg_form(self._plan, ctypes.byref(f)), "cosmo_plan_get_pcg_form")
+        return f.value
+
+    def autotune(self, rho: torch.Tensor, alpha: torch.Tensor, ws: Optional[torch.Tensor] = None):
+        """Time every CG schedule on a forward unroll and keep the fastest;
+        returns (chosen form, [ms per form], -1 where not run)."""
+        rho = self._check_vec(rho.contiguous(), self.K * self.m_tot, "rho")
+        alpha = self._check_vec(alpha.contiguous(), self.K * self.B, "alpha")
+        ws = ws if ws is not None else self.new_fwd_ws()
+        ms = (ctypes.c_double * 3)()
+        L.check(L.lib().cosmo_plan_autotune(self._plan, _ptr(rho), _ptr(alpha), _ptr(ws), _stream(self.device), ms),
+                "cosmo_plan_autotune")
+        return self.pcg_form(), [float(x) for x in ms]
+
     def profile_read(self, kind: int):
         n, ms = ctypes.c_int64(), ctypes.c_double()
         L.check(L.lib().cosmo_plan_profile_read(self._plan, int(kind), ctypes.byref(n), ctypes.byref(ms)),

@@ -124,7 +124,8 @@ template <typename T> void launch_nonfinite_check(const View<T> &v, const T *x, 
 template <typename T> void launch_pcg(const View<T> &v, const T *rho_hat, const T *dg, const T *rhs, T *x,
                                       T *r, T *z, T *p, T *Mp, T *t, double tol, int32_t max_iter,
                                       const T *alpha_k, const T *xold, T *xnew, const T *gx_in, T *gx_out,
-                                      int32_t mode, cosmo_stats *stats, hipStream_t st);
+                                      int32_t mode, cosmo_stats *stats, void *state, int32_t form,
+                                      hipStream_t st);
 
 // SOC (k_soc.hip)
 template <typename T> void launch_soc_step(const SocDesc *d, int32_t n, const T *rho_hat, const T *vv,

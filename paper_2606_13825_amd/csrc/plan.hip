@@ -62,6 +62,7 @@ struct ProfileSlot {
 
 struct cosmo_plan {
   cosmo_options opt{};
+  int32_t pcg_form = 0;   // CG schedule: 0 one workgroup per instance, f > 0 cooperative (f per CU)
   int32_t B = 0;
   int64_t n_tot = 0, m_tot = 0;
   std::vector<int64_t> n_off, m_off;
@@ -102,13 +103,13 @@ struct cosmo_plan {
   bool diag_M = false;
   // layouts (element offsets of T)
   struct {
-    size_t rho_hat, dg, xi, r, z, p, Mp, t, sh, vv, itA, itB, xt, st, U, lam, rp, rd, rs, total;
+    size_t rho_hat, dg, xi, r, z, p, Mp, t, cg, sh, vv, itA, itB, xt, st, U, lam, rp, rd, rs, total;
   } fw{};
   struct {
     size_t slot, step, xt, st, lam, U, total;  // per-slot / per-step sizes and offsets inside a step
   } tp{};
   struct {
-    size_t rho_hat, gA, gB, gsn, gv, gsh, gst, grh, gxt, w, dg, r, z, p, Mp, t, vv, dk, zero, total;
+    size_t rho_hat, gA, gB, gsn, gv, gsh, gst, grh, gxt, w, dg, r, z, p, Mp, t, cg, vv, dk, zero, total;
   } bw{};
   bool profiling = false;
   ProfileSlot prof[8];   // kinds of cosmo_plan_profile_read
@@ -477,6 +478,7 @@ void build_layouts(cosmo_plan *pl) {
   f.p = take(n);
   f.Mp = take(n);
   f.t = take(m);
+  f.cg = take(8 * ((size_t)pl->B + 1));   // per-instance state of the cooperative CG
   f.sh = take(m);
   f.vv = take(m);
   // (x, s, y) triples laid out like a tape slot: each part starts 64-element aligned
@@ -518,6 +520,7 @@ void build_layouts(cosmo_plan *pl) {
   w.p = take(n);
   w.Mp = take(n);
   w.t = take(m);
+  w.cg = take(8 * ((size_t)pl->B + 1));
   w.vv = take(m);
   w.dk = take(pl->sum_p2_large);
   w.total = o;
@@ -617,7 +620,7 @@ cosmo_status forward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T 
     if (!pl->diag_M) {
       ProfScope ps(pl, 2, st);
       launch_pcg<T>(v, rh, ws + f.dg, ws + f.xi, xt, ws + f.r, ws + f.z, ws + f.p, ws + f.Mp, ws + f.t,
-                    pl->opt.cg_tol, pl->opt.cg_max_iter, al, x, xn, nullptr, nullptr, 0, stats, st);
+                    pl->opt.cg_tol, pl->opt.cg_max_iter, al, x, xn, nullptr, nullptr, 0, stats, ws + f.cg, pl->pcg_form, st);
     }
     {
       ProfScope ps(pl, 3, st);
@@ -691,7 +694,8 @@ cosmo_status backward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T
     if (!pl->diag_M) {
       ProfScope ps(pl, 2, st);
       launch_pcg<T>(v, rh, ws + w.dg, ws + w.gxt, ws + w.w, ws + w.r, ws + w.z, ws + w.p, ws + w.Mp, ws + w.t,
-                    pl->opt.cg_tol, pl->opt.cg_max_iter, al, nullptr, nullptr, gx_in, gx_out, 1, stats, st);
+                    pl->opt.cg_tol, pl->opt.cg_max_iter, al, nullptr, nullptr, gx_in, gx_out, 1, stats, ws + w.cg,
+                    pl->pcg_form, st);
     }
     {
       ProfScope ps(pl, 3, st);
@@ -868,6 +872,73 @@ cosmo_status cosmo_residual_loss(cosmo_plan *plan, const void *x, const void *s,
   }
   HIPCHK(hipGetLastError());
   return COSMO_OK;
+}
+
+// ---- schedules -------------------------------------------------------------------
+
+cosmo_status cosmo_plan_set_pcg_form(cosmo_plan *plan, int32_t form) {
+  cosmo_status s = check_plan(plan);
+  if (s != COSMO_OK) return s;
+  if (form < 0 || form > 2) FAIL(COSMO_EINVAL, "form must be 0, 1 or 2");
+  plan->pcg_form = form;
+  return COSMO_OK;
+}
+
+cosmo_status cosmo_plan_get_pcg_form(const cosmo_plan *plan, int32_t *form) {
+  cosmo_status s = check_plan(plan);
+  if (s != COSMO_OK) return s;
+  if (!form) FAIL(COSMO_EINVAL, "form is NULL");
+  *form = plan->pcg_form;
+  return COSMO_OK;
+}
+
+cosmo_status cosmo_plan_autotune(cosmo_plan *plan, const void *rho, const void *alpha, void *ws, void *stream,
+                                 double *ms_out) {
+  cosmo_status s = check_plan(plan);
+  if (s != COSMO_OK) return s;
+  if (!rho || !alpha || !ws) FAIL(COSMO_EINVAL, "rho, alpha and the workspace are required");
+  if (ms_out)
+    for (int f = 0; f < 3; ++f) ms_out[f] = -1.0;
+  if (plan->diag_M) return COSMO_OK;   // no CG to schedule
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  DevBuf out;
+  HIPCHK(hipMalloc(&out.ptr, (2 * plan->m_tot + plan->n_tot) * plan->esz));
+  char *o = static_cast<char *>(out.ptr);
+  void *xK = o, *sK = o + plan->n_tot * plan->esz, *yK = o + (plan->n_tot + plan->m_tot) * plan->esz;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    FAIL(COSMO_EHIP, "hipEventCreate failed");
+  }
+  const int32_t keep = plan->pcg_form;
+  double best = -1.0;
+  int32_t best_form = keep;
+  for (int32_t f = 0; f < 3 && s == COSMO_OK; ++f) {
+    plan->pcg_form = f;
+    for (int rep = 0; rep < 2 && s == COSMO_OK; ++rep) {   // the first run warms caches and code objects
+      (void)hipEventRecord(e0, st);
+      s = cosmo_unroll_forward(plan, rho, alpha, nullptr, nullptr, nullptr, xK, sK, yK, nullptr, ws, nullptr, stream);
+      (void)hipEventRecord(e1, st);
+    }
+    if (s != COSMO_OK) break;
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      s = COSMO_EHIP;
+      break;
+    }
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms_out) ms_out[f] = ms;
+    if (best < 0 || ms < best) {
+      best = ms;
+      best_form = f;
+    }
+  }
+  (void)hipStreamSynchronize(st);   // nothing in flight reads the scratch outputs when they are freed
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  plan->pcg_form = (s == COSMO_OK) ? best_form : keep;
+  return s;
 }
 
 // ---- profiling (not part of the hot path) -------------------------------------

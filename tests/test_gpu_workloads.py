@@ -26,11 +26,18 @@ def _hyper(insts, K, seed, spread=0.5, dtype=np.float32):
     return rhos, alphas
 
 
-def _run_and_check(insts, K, rhos, alphas, check_idx, tol_it, tol_g, dtype=torch.float32, **kw):
+def _run_and_check(insts, K, rhos, alphas, check_idx, tol_it, tol_g, dtype=torch.float32, form=None,
+                   autotune=False, **kw):
     from paper_2606_13825_amd import CosmoBatch
     batch = CosmoBatch(insts, K=K, dtype=dtype, device=DEV, **kw)
     rho = torch.from_numpy(np.concatenate(rhos, axis=1)).to(DEV)
     alpha = torch.from_numpy(np.stack(alphas, axis=1)).to(DEV)
+    if form is not None:
+        batch.set_pcg_form(form)
+    if autotune:
+        chosen, ms = batch.autotune(rho, alpha)
+        say(f"  autotune: CG schedule {chosen}, forward ms per schedule {['%.2f' % m for m in ms]}")
+        assert chosen in (0, 1, 2) and ms[chosen] == min(m for m in ms if m >= 0)
     stats = batch.new_stats()
     fw = batch.forward(rho, alpha, stats=stats)
     loss, g = batch.residual_loss(fw.x, fw.s, fw.y)
@@ -142,19 +149,32 @@ def test_lovasz_circulant_large_orders():
     _run_and_check(insts, K, rhos, alphas, range(2), 2e-5, 2e-4)
 
 
-def test_huber_socp_reduced():
+@pytest.mark.parametrize("form", [0, 1, 2])
+def test_huber_socp_reduced(form):
+    """Both CG schedules (one workgroup per instance; cooperative)."""
     ensure_lib()
     insts = [x.astype(np.float32) for x in synth.c4_batch(B=3, seed=41, n_obs=200, n_coef=50, n_soc=20)]
     K = 10
     rhos, alphas = _hyper(insts, K, 42)
-    say(f"Huber SOCP B=3 n={insts[0].n} m={insts[0].m} K={K}")
-    _run_and_check(insts, K, rhos, alphas, range(3), 1e-4, 1e-3, cg_tol=1e-7, cg_max_iter=1000)
+    say(f"Huber SOCP B=3 n={insts[0].n} m={insts[0].m} K={K} CG schedule {form}")
+    _run_and_check(insts, K, rhos, alphas, range(3), 1e-4, 1e-3, form=form, cg_tol=1e-7, cg_max_iter=1000)
 
 
-def test_covsteer_reduced():
+@pytest.mark.parametrize("form", [0, 1])
+def test_covsteer_reduced(form):
     ensure_lib()
     insts = [x.astype(np.float32) for x in synth.c5_batch(B=3, seed=51, nx_choices=(4, 6), T_lo=5, T_hi=8)]
     K = 8
     rhos, alphas = _hyper(insts, K, 52)
-    say(f"covariance steering B=3 n={[i.n for i in insts]} m={[i.m for i in insts]} K={K}")
-    _run_and_check(insts, K, rhos, alphas, range(3), 1e-4, 1e-3, cg_tol=1e-7, cg_max_iter=2000)
+    say(f"covariance steering B=3 n={[i.n for i in insts]} m={[i.m for i in insts]} K={K} CG schedule {form}")
+    _run_and_check(insts, K, rhos, alphas, range(3), 1e-4, 1e-3, form=form, cg_tol=1e-7, cg_max_iter=2000)
+
+
+def test_covsteer_autotuned_schedule():
+    """The autotuner picks the fastest CG schedule it timed, and the run that
+    follows stays at the oracle."""
+    ensure_lib()
+    insts = [x.astype(np.float32) for x in synth.c5_batch(B=4, seed=53, nx_choices=(4, 6), T_lo=5, T_hi=8)]
+    K = 6
+    rhos, alphas = _hyper(insts, K, 54)
+    _run_and_check(insts, K, rhos, alphas, range(4), 1e-4, 1e-3, autotune=True, cg_tol=1e-7, cg_max_iter=2000)
