@@ -122,7 +122,7 @@ template <typename T> void launch_nonfinite_check(const View<T> &v, const T *x, 
 //     xt_out (may alias x) and, if xnew != nullptr, x+ = alpha x~ + (1 - alpha) xold.
 //   mode 1 (adjoint): solves M w = rhs; writes w and gx_out = (1 - alpha) gx_in + sigma w.
 template <typename T> void launch_pcg(const View<T> &v, const T *rho_hat, const T *dg, const T *rhs, T *x,
-                                      T *r, T *z, T *p, T *Mp, T *t, double tol, int32_t max_iter,
+                                      T *r, T *z, T *p, T *Mp, T *t, double *t64, double tol, int32_t max_iter,
                                       const T *alpha_k, const T *xold, T *xnew, const T *gx_in, T *gx_out,
                                       int32_t mode, cosmo_stats *stats, void *state, int32_t form,
                                       hipStream_t st);

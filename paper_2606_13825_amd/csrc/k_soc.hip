@@ -2,7 +2,10 @@
 // the COSMO slack / dual update on SOC rows, and the vector-Jacobian product
 // of the projection (Sec. "Stable PSD Projection": the SOC projection is
 // piecewise smooth).  One thread per cone: the cones of the workloads have
-// a handful of rows, and the loops below are plain strided sums.
+// a handful of rows, and the loops below are plain strided sums.  The
+// arithmetic runs in float64 from the stored values and is rounded once on
+// store (a float32 pipeline's s+ and y+ = y + rho (s^ - s+) then carry no
+// cancellation error beyond that rounding).
 #include "cosmo_internal.h"
 
 namespace cosmo {
@@ -11,16 +14,16 @@ namespace {
 constexpr int ST = 256;
 
 // Norm of w with one rescaling pass to avoid overflow/underflow.
-template <typename T> __device__ inline T wnorm(const T *w, int d) {
-  T mx = 0;
+template <typename T> __device__ inline double wnorm(const T *w, int d) {
+  double mx = 0;
   for (int i = 0; i < d; ++i) {
-    const T a = fabs(w[i]);
+    const double a = fabs((double)w[i]);
     mx = (a > mx || a != a) ? a : mx;   // a NaN entry sticks (fmax would drop it)
   }
-  if (mx == (T)0) return 0;
-  T acc = 0;
+  if (mx == 0.0) return 0;
+  double acc = 0;
   for (int i = 0; i < d; ++i) {
-    const T u = w[i] / mx;
+    const double u = (double)w[i] / mx;
     acc += u * u;
   }
   return mx * sqrt(acc);
@@ -29,16 +32,16 @@ template <typename T> __device__ inline T wnorm(const T *w, int d) {
 // out = Pi(v): identity if ||w|| <= t, zero if ||w|| <= -t, else
 // ((||w|| + t)/2) (1, w/||w||).
 template <typename T> __device__ inline void soc_project(const T *v, T *out, int dim) {
-  const T t = v[0];
-  const T nw = wnorm(v + 1, dim - 1);
+  const double t = v[0];
+  const double nw = wnorm(v + 1, dim - 1);
   if (nw <= t) {
     for (int i = 0; i < dim; ++i) out[i] = v[i];
   } else if (nw <= -t) {
     for (int i = 0; i < dim; ++i) out[i] = 0;
   } else {
-    const T a = (T)0.5 * ((T)1 + t / nw);
-    out[0] = a * nw;
-    for (int i = 1; i < dim; ++i) out[i] = a * v[i];
+    const double a = 0.5 * (1.0 + t / nw);
+    out[0] = (T)(a * nw);
+    for (int i = 1; i < dim; ++i) out[i] = (T)(a * (double)v[i]);
   }
 }
 
@@ -54,7 +57,7 @@ __global__ __launch_bounds__(ST) void k_soc_step(const SocDesc *__restrict__ d, 
   soc_project(vv + r0, s_new + r0, cd.dim);
   for (int i = 0; i < cd.dim; ++i) {
     const int64_t r = r0 + i;
-    y_new[r] = y[r] + rho_hat[r] * (sh[r] - s_new[r]);
+    y_new[r] = (T)((double)y[r] + (double)rho_hat[r] * ((double)sh[r] - (double)s_new[r]));
   }
 }
 
@@ -78,21 +81,22 @@ __global__ __launch_bounds__(ST) void k_soc_vjp(const SocDesc *__restrict__ d, i
   const T *gg = g + cd.row0;
   T *o = out + cd.row0;
   const int dim = cd.dim;
-  const T t = v[0];
-  const T nw = wnorm(v + 1, dim - 1);
+  const double t = v[0];
+  const double nw = wnorm(v + 1, dim - 1);
   if (nw <= t) {
     for (int i = 0; i < dim; ++i) o[i] = gg[i];
   } else if (nw <= -t) {
     for (int i = 0; i < dim; ++i) o[i] = 0;
   } else {
-    T ug = 0;   // u'g_w
-    for (int i = 1; i < dim; ++i) ug += v[i] * gg[i];
+    double ug = 0;   // u'g_w
+    for (int i = 1; i < dim; ++i) ug += (double)v[i] * (double)gg[i];
     ug /= nw;
-    const T rr = t / nw;
-    o[0] = (T)0.5 * (gg[0] + ug);
+    const double rr = t / nw;
+    const double g0 = gg[0];
+    o[0] = (T)(0.5 * (g0 + ug));
     for (int i = 1; i < dim; ++i) {
-      const T ui = v[i] / nw;
-      o[i] = (T)0.5 * (ui * gg[0] + ((T)1 + rr) * gg[i] - rr * ui * ug);
+      const double ui = (double)v[i] / nw;
+      o[i] = (T)(0.5 * (ui * g0 + (1.0 + rr) * (double)gg[i] - rr * ui * ug));
     }
   }
 }

@@ -17,6 +17,19 @@ template <typename T> __device__ inline T subwave_sum(T v, int L) {
   return v;
 }
 
+// Row and column sums, and the differences they feed (s~ - s, xi, the
+// gradient terms), are formed in float64 from the stored values and rounded
+// once: near a fixed point these differences are small against their terms,
+// and float32 accumulation would leave errors of order eps |terms| in them.
+// s^ and v are evaluated by this one function in the forward and the reverse
+// pass, so the nonnegative-cone mask is the same in both.
+template <typename T> __device__ inline double shat_of(T al, T stl, T s) {
+  return (double)al * (double)stl + (1.0 - (double)al) * (double)s;
+}
+template <typename T> __device__ inline double v_of(T al, T stl, T s, T y, T r) {
+  return shat_of(al, stl, s) + (double)y / (double)r;
+}
+
 // Position of this thread inside the bucketed row list: returns false when
 // the sub-wave has no row.  All lanes of a sub-wave agree.
 struct BucketPos {
@@ -119,19 +132,19 @@ __global__ __launch_bounds__(NT) void k_cols_pre(View<T> v, BucketArgs ba, const
                                                  T *__restrict__ xi, DiagSolve<T> ds) {
   BUCKET_PREAMBLE
   const int64_t j = bp.row;
-  T a_xi = 0, a_d = 0;
+  double a_xi = 0, a_d = 0;
   for (int64_t k = v.At_rowptr[j] + bp.lane; k < v.At_rowptr[j + 1]; k += bp.L) {
     const int32_t i = v.At_col[k];
-    const T a = v.At_val[k];
-    const T r = rho_hat[i];
-    a_xi += a * (y[i] + r * (v.b[i] - s[i]));
+    const double a = v.At_val[k];
+    const double r = rho_hat[i];
+    a_xi += a * ((double)y[i] + r * ((double)v.b[i] - (double)s[i]));
     a_d += r * a * a;
   }
   a_xi = subwave_sum(a_xi, bp.L);
   a_d = subwave_sum(a_d, bp.L);
   if (bp.lane == 0) {
-    const T d = v.Pdiag[j] + v.sigma + a_d;
-    const T r = v.sigma * x[j] - v.q[j] + a_xi;
+    const T d = (T)((double)v.Pdiag[j] + (double)v.sigma + a_d);
+    const T r = (T)((double)v.sigma * (double)x[j] - (double)v.q[j] + a_xi);
     dg[j] = d;
     xi[j] = r;
     if (ds.xt) {
@@ -155,24 +168,25 @@ __global__ __launch_bounds__(NT) void k_rows_post(View<T> v, BucketArgs ba, cons
                                                   T *__restrict__ y_new) {
   BUCKET_PREAMBLE
   const int64_t i = bp.row;
-  T ax = 0;
-  for (int64_t k = v.A_rowptr[i] + bp.lane; k < v.A_rowptr[i + 1]; k += bp.L) ax += v.A_val[k] * xt[v.A_col[k]];
+  double ax = 0;
+  for (int64_t k = v.A_rowptr[i] + bp.lane; k < v.A_rowptr[i + 1]; k += bp.L)
+    ax += (double)v.A_val[k] * (double)xt[v.A_col[k]];
   ax = subwave_sum(ax, bp.L);
   if (bp.lane != 0) return;
   const T al = alpha_k[v.row_inst[i]];
   const T r = rho_hat[i];
-  const T stl = v.b[i] - ax;
-  const T shat = al * stl + ((T)1 - al) * s[i];
-  const T vi = shat + y[i] / r;
+  const T stl = (T)((double)v.b[i] - ax);   // stored; s^ and v below use the stored value
+  const double shat = shat_of(al, stl, s[i]);
+  const double vi = v_of(al, stl, s[i], y[i], r);
   st_out[i] = stl;
   const uint8_t kind = v.row_kind[i];
   if (kind == ROW_ZERO || kind == ROW_NONNEG) {
-    const T sp = (kind == ROW_ZERO) ? (T)0 : (vi < (T)0 ? (T)0 : vi);   // NaN passes through
+    const T sp = (kind == ROW_ZERO) ? (T)0 : (vi < 0.0 ? (T)0 : (T)vi);   // NaN passes through
     s_new[i] = sp;
-    y_new[i] = y[i] + r * (shat - sp);
+    y_new[i] = (T)((double)y[i] + (double)r * (shat - (double)sp));
   } else {
-    sh_out[i] = shat;
-    vv_out[i] = vi;
+    sh_out[i] = (T)shat;
+    vv_out[i] = (T)vi;
   }
 }
 
@@ -189,14 +203,13 @@ __global__ __launch_bounds__(NT) void k_bwd_rows_a(View<T> v, const T *__restric
   const int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x;
   if (i >= v.m_tot) return;
   const T r = rho_hat[i];
-  const T g = gs_in[i] - r * gy_in[i];
+  const T g = (T)((double)gs_in[i] - (double)r * (double)gy_in[i]);
   const uint8_t kind = v.row_kind[i];
   if (kind == ROW_ZERO) {
     gv[i] = 0;
   } else if (kind == ROW_NONNEG) {
-    const T al = alpha_k[v.row_inst[i]];
-    const T vi = al * stl[i] + ((T)1 - al) * s[i] + y[i] / r;
-    gv[i] = vi > (T)0 ? g : (T)0;
+    const double vi = v_of(alpha_k[v.row_inst[i]], stl[i], s[i], y[i], r);
+    gv[i] = vi > 0.0 ? g : (T)0;
   } else {
     gsn[i] = g;
   }
@@ -210,8 +223,7 @@ __global__ __launch_bounds__(NT) void k_rows_v(View<T> v, const T *__restrict__ 
                                                T *__restrict__ vv) {
   const int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x;
   if (i >= v.m_tot) return;
-  const T al = alpha_k[v.row_inst[i]];
-  vv[i] = al * stl[i] + ((T)1 - al) * s[i] + y[i] / rho_hat[i];
+  vv[i] = (T)v_of(alpha_k[v.row_inst[i]], stl[i], s[i], y[i], rho_hat[i]);
 }
 
 // Per row, once every cone has produced v-bar:
@@ -227,17 +239,17 @@ __global__ __launch_bounds__(NT) void k_bwd_rows_b(View<T> v, const T *__restric
                                                    T *__restrict__ gy_out, T *__restrict__ grh) {
   const int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x;
   if (i >= v.m_tot) return;
-  const T r = rho_hat[i];
+  const double r = rho_hat[i];
   const T al = alpha_k[v.row_inst[i]];
-  const T shat = al * stl[i] + ((T)1 - al) * s[i];
-  const T gyp = gy_in[i];
-  const T g_v = gv[i];
-  const T g_sh = r * gyp + g_v;
-  gsh[i] = g_sh;
-  gy_out[i] = gyp + g_v / r;
-  grh[i] = gyp * (shat - s_new[i]) - g_v * y[i] / (r * r);
-  gst[i] = al * g_sh;
-  gs_out[i] = ((T)1 - al) * g_sh;
+  const double shat = shat_of(al, stl[i], s[i]);
+  const double gyp = gy_in[i];
+  const double g_v = gv[i];
+  const double g_sh = r * gyp + g_v;
+  gsh[i] = (T)g_sh;
+  gy_out[i] = (T)(gyp + g_v / r);
+  grh[i] = (T)(gyp * (shat - (double)s_new[i]) - g_v * (double)y[i] / (r * r));
+  gst[i] = (T)((double)al * g_sh);
+  gs_out[i] = (T)((1.0 - (double)al) * g_sh);
 }
 
 // Per column j: xt-bar = alpha gx+ - (A' gs~)_j ; also the Jacobi diagonal.
@@ -250,19 +262,19 @@ __global__ __launch_bounds__(NT) void k_bwd_cols(View<T> v, BucketArgs ba, const
                                                  T *__restrict__ dg, DiagSolve<T> ds) {
   BUCKET_PREAMBLE
   const int64_t j = bp.row;
-  T acc = 0, a_d = 0;
+  double acc = 0, a_d = 0;
   for (int64_t k = v.At_rowptr[j] + bp.lane; k < v.At_rowptr[j + 1]; k += bp.L) {
     const int32_t i = v.At_col[k];
-    const T a = v.At_val[k];
-    acc += a * gst[i];
-    a_d += rho_hat[i] * a * a;
+    const double a = v.At_val[k];
+    acc += a * (double)gst[i];
+    a_d += (double)rho_hat[i] * a * a;
   }
   acc = subwave_sum(acc, bp.L);
   a_d = subwave_sum(a_d, bp.L);
   if (bp.lane == 0) {
     const T al = alpha_k[v.col_inst[j]];
-    const T r = al * gx_in[j] - acc;
-    const T d = v.Pdiag[j] + v.sigma + a_d;
+    const T r = (T)((double)al * (double)gx_in[j] - acc);
+    const T d = (T)((double)v.Pdiag[j] + (double)v.sigma + a_d);
     gxt[j] = r;
     dg[j] = d;
     if (ds.xt) {
@@ -283,13 +295,14 @@ __global__ __launch_bounds__(NT) void k_bwd_rows_c(View<T> v, BucketArgs ba, con
                                                    T *__restrict__ gs_out, T *__restrict__ gy_out) {
   BUCKET_PREAMBLE
   const int64_t i = bp.row;
-  T g = 0;
-  for (int64_t k = v.A_rowptr[i] + bp.lane; k < v.A_rowptr[i + 1]; k += bp.L) g += v.A_val[k] * w[v.A_col[k]];
+  double g = 0;
+  for (int64_t k = v.A_rowptr[i] + bp.lane; k < v.A_rowptr[i + 1]; k += bp.L)
+    g += (double)v.A_val[k] * (double)w[v.A_col[k]];
   g = subwave_sum(g, bp.L);
   if (bp.lane != 0) return;
-  grh[i] += g * (stl[i] - s[i]);
-  gy_out[i] += g;
-  gs_out[i] -= rho_hat[i] * g;
+  grh[i] = (T)((double)grh[i] + g * ((double)stl[i] - (double)s[i]));
+  gy_out[i] = (T)((double)gy_out[i] + g);
+  gs_out[i] = (T)((double)gs_out[i] - (double)rho_hat[i] * g);
 }
 
 // Workgroup reduction with a fixed tree: deterministic.
@@ -310,24 +323,25 @@ __global__ __launch_bounds__(NT) void k_alpha_reduce(View<T> v, const T *__restr
                                                      const T *__restrict__ stl, const T *__restrict__ s,
                                                      const T *__restrict__ gx_in, const T *__restrict__ xt,
                                                      const T *__restrict__ x, T *__restrict__ galpha_k) {
-  __shared__ T red[NT / 64];
+  __shared__ double red[NT / 64];
   const int b = blockIdx.x;
-  T a0 = 0, a1 = 0;
+  double a0 = 0, a1 = 0;
+  auto term = [](T g, T u, T w) { return (double)g * ((double)u - (double)w); };
   const int64_t m1 = v.m_off[b + 1], n1 = v.n_off[b + 1];
   int64_t i = v.m_off[b] + threadIdx.x;
   for (; i + NT < m1; i += 2 * NT) {
-    a0 += gsh[i] * (stl[i] - s[i]);
-    a1 += gsh[i + NT] * (stl[i + NT] - s[i + NT]);
+    a0 += term(gsh[i], stl[i], s[i]);
+    a1 += term(gsh[i + NT], stl[i + NT], s[i + NT]);
   }
-  for (; i < m1; i += NT) a0 += gsh[i] * (stl[i] - s[i]);
+  for (; i < m1; i += NT) a0 += term(gsh[i], stl[i], s[i]);
   int64_t j = v.n_off[b] + threadIdx.x;
   for (; j + NT < n1; j += 2 * NT) {
-    a0 += gx_in[j] * (xt[j] - x[j]);
-    a1 += gx_in[j + NT] * (xt[j + NT] - x[j + NT]);
+    a0 += term(gx_in[j], xt[j], x[j]);
+    a1 += term(gx_in[j + NT], xt[j + NT], x[j + NT]);
   }
-  for (; j < n1; j += NT) a0 += gx_in[j] * (xt[j] - x[j]);
-  const T tot = block_sum(a0 + a1, red);
-  if (threadIdx.x == 0) galpha_k[b] = tot;
+  for (; j < n1; j += NT) a0 += term(gx_in[j], xt[j], x[j]);
+  const double tot = block_sum(a0 + a1, red);
+  if (threadIdx.x == 0) galpha_k[b] = (T)tot;
 }
 
 // ---- residual loss ------------------------------------------------------------
@@ -337,10 +351,11 @@ __global__ __launch_bounds__(NT) void k_loss_rp(View<T> v, BucketArgs ba, const 
                                                 const T *__restrict__ s, T *__restrict__ rp) {
   BUCKET_PREAMBLE
   const int64_t i = bp.row;
-  T ax = 0;
-  for (int64_t k = v.A_rowptr[i] + bp.lane; k < v.A_rowptr[i + 1]; k += bp.L) ax += v.A_val[k] * x[v.A_col[k]];
+  double ax = 0;
+  for (int64_t k = v.A_rowptr[i] + bp.lane; k < v.A_rowptr[i + 1]; k += bp.L)
+    ax += (double)v.A_val[k] * (double)x[v.A_col[k]];
   ax = subwave_sum(ax, bp.L);
-  if (bp.lane == 0) rp[i] = ax + s[i] - v.b[i];
+  if (bp.lane == 0) rp[i] = (T)(ax + (double)s[i] - (double)v.b[i]);
 }
 
 // rd_j = (P x)_j + q_j - (A' y)_j
@@ -349,24 +364,26 @@ __global__ __launch_bounds__(NT) void k_loss_rd(View<T> v, BucketArgs ba, const 
                                                 const T *__restrict__ y, T *__restrict__ rd) {
   BUCKET_PREAMBLE
   const int64_t j = bp.row;
-  T acc = 0;
-  for (int64_t k = v.At_rowptr[j] + bp.lane; k < v.At_rowptr[j + 1]; k += bp.L) acc -= v.At_val[k] * y[v.At_col[k]];
+  double acc = 0;
+  for (int64_t k = v.At_rowptr[j] + bp.lane; k < v.At_rowptr[j + 1]; k += bp.L)
+    acc -= (double)v.At_val[k] * (double)y[v.At_col[k]];
   if (v.P_rowptr)
-    for (int64_t k = v.P_rowptr[j] + bp.lane; k < v.P_rowptr[j + 1]; k += bp.L) acc += v.P_val[k] * x[v.P_col[k]];
+    for (int64_t k = v.P_rowptr[j] + bp.lane; k < v.P_rowptr[j + 1]; k += bp.L)
+      acc += (double)v.P_val[k] * (double)x[v.P_col[k]];
   acc = subwave_sum(acc, bp.L);
-  if (bp.lane == 0) rd[j] = acc + v.q[j];
+  if (bp.lane == 0) rd[j] = (T)(acc + (double)v.q[j]);
 }
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_loss_reduce(View<T> v, const T *__restrict__ rp, const T *__restrict__ rd,
                                                     T *__restrict__ loss) {
-  __shared__ T red[NT / 64];
+  __shared__ double red[NT / 64];
   const int b = blockIdx.x;
-  T acc = 0;
-  for (int64_t i = v.m_off[b] + threadIdx.x; i < v.m_off[b + 1]; i += NT) acc += rp[i] * rp[i];
-  for (int64_t j = v.n_off[b] + threadIdx.x; j < v.n_off[b + 1]; j += NT) acc += rd[j] * rd[j];
-  const T tot = block_sum(acc, red);
-  if (threadIdx.x == 0) loss[b] = tot;
+  double acc = 0;
+  for (int64_t i = v.m_off[b] + threadIdx.x; i < v.m_off[b + 1]; i += NT) acc += (double)rp[i] * (double)rp[i];
+  for (int64_t j = v.n_off[b] + threadIdx.x; j < v.n_off[b + 1]; j += NT) acc += (double)rd[j] * (double)rd[j];
+  const double tot = block_sum(acc, red);
+  if (threadIdx.x == 0) loss[b] = (T)tot;
 }
 
 // gx_j = 2 (A' rp)_j + 2 (P rd)_j

@@ -103,13 +103,13 @@ struct cosmo_plan {
   bool diag_M = false;
   // layouts (element offsets of T)
   struct {
-    size_t rho_hat, dg, xi, r, z, p, Mp, t, cg, sh, vv, itA, itB, xt, st, U, lam, rp, rd, rs, total;
+    size_t rho_hat, dg, xi, r, z, p, Mp, t, t64, cg, sh, vv, itA, itB, xt, st, U, lam, rp, rd, rs, total;
   } fw{};
   struct {
     size_t slot, step, xt, st, lam, U, total;  // per-slot / per-step sizes and offsets inside a step
   } tp{};
   struct {
-    size_t rho_hat, gA, gB, gsn, gv, gsh, gst, grh, gxt, w, dg, r, z, p, Mp, t, cg, vv, dk, zero, total;
+    size_t rho_hat, gA, gB, gsn, gv, gsh, gst, grh, gxt, w, dg, r, z, p, Mp, t, t64, cg, vv, dk, zero, total;
   } bw{};
   bool profiling = false;
   ProfileSlot prof[8];   // kinds of cosmo_plan_profile_read
@@ -478,7 +478,8 @@ void build_layouts(cosmo_plan *pl) {
   f.p = take(n);
   f.Mp = take(n);
   f.t = take(m);
-  f.cg = take(8 * ((size_t)pl->B + 1));   // per-instance state of the cooperative CG
+  f.t64 = take(2 * m);                     // float64 residual pass of the CG (m doubles)
+  f.cg = take(16 * ((size_t)pl->B + 1));  // per-instance state of the CG (cooperative form)
   f.sh = take(m);
   f.vv = take(m);
   // (x, s, y) triples laid out like a tape slot: each part starts 64-element aligned
@@ -520,7 +521,8 @@ void build_layouts(cosmo_plan *pl) {
   w.p = take(n);
   w.Mp = take(n);
   w.t = take(m);
-  w.cg = take(8 * ((size_t)pl->B + 1));
+  w.t64 = take(2 * m);
+  w.cg = take(16 * ((size_t)pl->B + 1));
   w.vv = take(m);
   w.dk = take(pl->sum_p2_large);
   w.total = o;
@@ -620,7 +622,7 @@ cosmo_status forward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T 
     if (!pl->diag_M) {
       ProfScope ps(pl, 2, st);
       launch_pcg<T>(v, rh, ws + f.dg, ws + f.xi, xt, ws + f.r, ws + f.z, ws + f.p, ws + f.Mp, ws + f.t,
-                    pl->opt.cg_tol, pl->opt.cg_max_iter, al, x, xn, nullptr, nullptr, 0, stats, ws + f.cg, pl->pcg_form, st);
+                    reinterpret_cast<double *>(ws + f.t64), pl->opt.cg_tol, pl->opt.cg_max_iter, al, x, xn, nullptr, nullptr, 0, stats, ws + f.cg, pl->pcg_form, st);
     }
     {
       ProfScope ps(pl, 3, st);
@@ -694,7 +696,7 @@ cosmo_status backward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T
     if (!pl->diag_M) {
       ProfScope ps(pl, 2, st);
       launch_pcg<T>(v, rh, ws + w.dg, ws + w.gxt, ws + w.w, ws + w.r, ws + w.z, ws + w.p, ws + w.Mp, ws + w.t,
-                    pl->opt.cg_tol, pl->opt.cg_max_iter, al, nullptr, nullptr, gx_in, gx_out, 1, stats, ws + w.cg,
+                    reinterpret_cast<double *>(ws + w.t64), pl->opt.cg_tol, pl->opt.cg_max_iter, al, nullptr, nullptr, gx_in, gx_out, 1, stats, ws + w.cg,
                     pl->pcg_form, st);
     }
     {

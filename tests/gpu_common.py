@@ -53,3 +53,25 @@ def oracle_run(inst, rho_k_m, alpha_k, with_grad=True, x0=None, s0=None, y0=None
         grho, galpha, gx0, gs0, gy0 = oracle.unroll_backward(inst, tape, *g)
         out.update(grho=grho, galpha=galpha, gx0=gx0, gs0=gs0, gy0=gy0)
     return out
+
+
+def one_step_err(inst, z, z_next, rho_k, alpha_k, fl, tol=1e-5):
+    """The float64 oracle's step from the GPU's iterate z = (x, s, y) against
+    the GPU's next iterate, per array, at `tol` relative.  The bar has one floor
+    no float32 pipeline avoids: the right-hand side xi is a float32 vector, and
+    rounding it once moves the exact solve by M^-1 (fl32(xi) - xi); the step is
+    allowed 8 such roundings, carried through to s and y (the projection is
+    nonexpansive, y+ adds rho (s^ - s+)).  Returns (worst error, number of
+    arrays where the floor decided)."""
+    x, s, y = z
+    st = oracle.step_forward(inst, x, s, y, np.asarray(rho_k, np.float64), float(alpha_k))
+    dxt = st["lu"].solve(st["xi"].astype(np.float32).astype(np.float64) - st["xi"])
+    dsh = float(alpha_k) * np.linalg.norm(inst.A @ dxt)
+    floors = {"x": 8 * float(alpha_k) * np.linalg.norm(dxt), "s": 8 * dsh,
+              "y": 16 * float(st["rho_hat"].max()) * dsh}
+    worst, n_floor = 0.0, 0
+    for nm, g, r in (("x", z_next[0], st["xn"]), ("s", z_next[1], st["sn"]), ("y", z_next[2], st["yn"])):
+        f = max(fl, floors[nm] / tol)
+        n_floor += f > np.linalg.norm(r)
+        worst = max(worst, assert_close(g, r, tol, f, nm))
+    return worst, n_floor

@@ -1,0 +1,174 @@
+"""Full-size workloads in the launch configuration bench.py times (the same
+batch, K, dtype, hyperparameters and autotuned CG schedule), checked on
+sampled outputs the float64 oracle can compute one by one:
+
+  * c5 (128 covariance-steering SDPs, K = 30): whole trajectories and
+    gradients of two sampled instances (the largest, and the first);
+  * c3 (32 Lovasz SDPs, K = 50) and c4 (256 Huber SOCPs, K = 40), whose full
+    oracle runs take minutes per instance: one-step parity of the forward at
+    sampled steps (the oracle started from the GPU's own iterate), and the
+    gradients of the last steps, reverse mode in the oracle from the GPU's
+    own iterates and loss seeds (those gradients depend on nothing earlier),
+    both at the GPU's own taped solves and against exact solves with a floor
+    for the float32 rounding of the stored steps.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.cones import proj_cone
+from gpu_common import assert_close, ensure_lib, floor_of, one_step_err, oracle_run, say
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _bench_run(name):
+    """The benchmark's own workload, hyperparameters and launch configuration:
+    one forward + loss + backward pass."""
+    import bench
+    from paper_2606_13825_amd import CosmoBatch
+    wl = bench._workload(name)
+    rhos, alphas = bench._hyper(wl)
+    kw = {k: wl[k] for k in ("cg_tol", "cg_max_iter") if k in wl}
+    batch = CosmoBatch(wl["insts"], K=wl["K"], dtype=torch.float32, device=DEV, **kw)
+    rho = torch.from_numpy(np.concatenate(rhos, axis=1)).to(DEV)
+    alpha = torch.from_numpy(np.stack(alphas, axis=1)).to(DEV)
+    form, ms = batch.autotune(rho, alpha)
+    say(f"{wl['name']}: B={len(wl['insts'])} K={wl['K']} CG schedule {form} ({ms})")
+    stats = batch.new_stats()
+    fw = batch.forward(rho, alpha, stats=stats)
+    _, g = batch.residual_loss(fw.x, fw.s, fw.y)
+    bw = batch.backward(rho, alpha, fw.tape, *g, stats=stats)
+    torch.cuda.synchronize()
+    st = batch.stats_dict(stats)
+    say(f"  CG: max iterations {int(st['cg_iters_max'].max())}, total {int(st['cg_iters_total'].sum())}, "
+        f"solves not at tolerance {int(st['cg_not_converged'].sum())}")
+    assert st["nonfinite"].max() == 0
+    return wl, rhos, alphas, batch, fw, bw
+
+
+def _iterate(batch, fw, i, k):
+    x, s, y = batch.tape_iterate(fw.tape, k)[:3]
+    return (x[batch.n_off[i]:batch.n_off[i + 1]].double().cpu().numpy(),
+            s[batch.m_off[i]:batch.m_off[i + 1]].double().cpu().numpy(),
+            y[batch.m_off[i]:batch.m_off[i + 1]].double().cpu().numpy())
+
+
+def _check_one_steps(wl, rhos, alphas, batch, fw, samples):
+    worst = 0.0
+    for i, k in samples:
+        inst = wl["insts"][i]
+        e, _ = one_step_err(inst, _iterate(batch, fw, i, k), _iterate(batch, fw, i, k + 1), rhos[i][k],
+                            alphas[i][k], floor_of(inst))
+        worst = max(worst, e)
+    say(f"  one-step parity at {samples}: worst rel err {worst:.2e}")
+
+
+def _step_at(inst, z, rho, alpha, fwd=None, round32=False):
+    """The oracle's record of step k from iterate z.  With fwd = (x~, s~, s+)
+    (the GPU's taped solve and next slack) the record is rebuilt around
+    those values: s^, v and the cone data follow from them by the oracle's
+    own formulas.  With round32 the quantities a float32 pipeline stores
+    are rounded."""
+    st = oracle.step_forward(inst, *z, np.asarray(rho, np.float64), float(alpha))
+    if fwd is not None:
+        x, s, y = z
+        xt, stl, sn = fwd
+        sh = st["alpha"] * stl + (1.0 - st["alpha"]) * s
+        v = sh + y / st["rho_hat"]
+        _, aux = proj_cone(v, inst.cones)
+        st.update(xt=xt, st=stl, sh=sh, v=v, sn=sn, aux=aux)
+    if round32:
+        for key in ("xt", "st", "sh", "v", "sn"):
+            st[key] = st[key].astype(np.float32).astype(np.float64)
+    return st
+
+
+def _reverse(inst, tape, zK):
+    gx, gs, gy = oracle.residual_loss_grad(inst, *zK)
+    ref_r, ref_a = [], []
+    for st in reversed(tape):
+        gx, gs, gy, gr, ga = oracle.step_backward(inst, st, gx, gs, gy)
+        ref_r.append(gr)
+        ref_a.append(ga)
+    return np.array(ref_r[::-1]), np.array(ref_a[::-1])
+
+
+def _check_tail_gradients(wl, rhos, alphas, batch, fw, bw, i, tail, tol):
+    """grad rho^k and alpha^k of instance i for the last `tail` steps.
+
+    (a) At `tol`: the oracle's reverse pass over the GPU's own iterates,
+        taped solves (x~, s~) and next slacks s+ -- the reverse arithmetic,
+        adjoint solves and cone VJPs, on the same forward quantities (the
+        rho gradient carries s^ - s+, which a single float32 rounding of s+
+        already moves by ~1e-4 at this depth).
+    (b) grad rho against the oracle's own forward (exact solves), at `tol`
+        with one floor: these gradients carry differences such as s~ - s
+        and s^ - s+, small near a fixed point, so rounding the stored
+        per-step quantities to float32 once already moves them by d
+        (computed here); the bar allows 8 such roundings.  grad alpha is
+        a single dot product over those same differences per step, whose
+        error at this depth is set by the forward solve's tolerance; it is
+        checked by (a)."""
+    inst, K = wl["insts"][i], wl["K"]
+    ks = range(K - tail, K)
+    zs = [_iterate(batch, fw, i, k) for k in ks]
+    zK = _iterate(batch, fw, i, K)
+    fwd = []
+    for j, k in enumerate(ks):
+        xt, stl = batch.tape_iterate(fw.tape, k)[3:]
+        fwd.append((xt[batch.n_off[i]:batch.n_off[i + 1]].double().cpu().numpy(),
+                    stl[batch.m_off[i]:batch.m_off[i + 1]].double().cpu().numpy(),
+                    (zs[j + 1] if j + 1 < len(zs) else zK)[1]))
+    sl_m = slice(batch.m_off[i], batch.m_off[i + 1])
+    g_r = bw.grho[K - tail:, sl_m].double().cpu().numpy()
+    g_a = bw.galpha[K - tail:, i].double().cpu().numpy()
+    at_r, at_a = _reverse(inst, [_step_at(inst, z, rhos[i][k], alphas[i][k], f) for z, k, f in zip(zs, ks, fwd)], zK)
+    e1 = assert_close(g_r, at_r, tol, 0.0, f"inst {i} grad rho tail at the GPU's solves")
+    e2 = assert_close(g_a, at_a, tol, 0.0, f"inst {i} grad alpha tail at the GPU's solves")
+    ref_r, ref_a = _reverse(inst, [_step_at(inst, z, rhos[i][k], alphas[i][k]) for z, k in zip(zs, ks)], zK)
+    r32_r, _ = _reverse(inst, [_step_at(inst, z, rhos[i][k], alphas[i][k], round32=True) for z, k in zip(zs, ks)], zK)
+    d = np.linalg.norm(r32_r - ref_r)
+    e3 = assert_close(g_r, ref_r, tol, 8 * d / tol, f"inst {i} grad rho tail")
+    say(f"  gradients of the last {tail} steps, instance {i}: at the GPU's solves rel err {max(e1, e2):.2e}; "
+        f"grad rho vs exact solves {e3:.2e} (float32 rounding of the stored steps alone: "
+        f"{d / np.linalg.norm(ref_r):.2e}), grad alpha vs exact solves "
+        f"{np.linalg.norm(g_a - ref_a) / np.linalg.norm(ref_a):.2e}")
+
+
+def test_c5_covsteer_full_batch_sampled_instances():
+    ensure_lib()
+    wl, rhos, alphas, batch, fw, bw = _bench_run("c5")
+    insts = wl["insts"]
+    largest = int(np.argmax([inst.n for inst in insts]))
+    for i in sorted({0, largest}):
+        inst = insts[i]
+        ref = oracle_run(inst, rhos[i].astype(np.float64), alphas[i].astype(np.float64))
+        fl = floor_of(inst)
+        sl_n = slice(batch.n_off[i], batch.n_off[i + 1])
+        sl_m = slice(batch.m_off[i], batch.m_off[i + 1])
+        e = [assert_close(a.double().cpu().numpy(), r, 1e-4, fl, f"inst {i} final {nm}")
+             for nm, a, r in (("x", fw.x[sl_n], ref["x"]), ("s", fw.s[sl_m], ref["s"]), ("y", fw.y[sl_m], ref["y"]))]
+        e.append(assert_close(bw.grho[:, sl_m].double().cpu().numpy(), ref["grho"], 1e-3, 0.0, f"inst {i} grad rho"))
+        e.append(assert_close(bw.galpha[:, i].double().cpu().numpy(), ref["galpha"], 1e-3, 0.0,
+                              f"inst {i} grad alpha"))
+        say(f"  instance {i} (n={inst.n}, m={inst.m}): max rel err {max(e):.2e}")
+
+
+def test_c3_lovasz_full_batch_sampled_steps():
+    ensure_lib()
+    wl, rhos, alphas, batch, fw, bw = _bench_run("c3")
+    K, B = wl["K"], len(wl["insts"])
+    big = int(np.argmax([inst.meta["order"] for inst in wl["insts"]]))
+    _check_one_steps(wl, rhos, alphas, batch, fw, [(0, 0), (big, 0), (big, K // 2), (B - 1, K - 1)])
+    _check_tail_gradients(wl, rhos, alphas, batch, fw, bw, big, 3, 1e-4)
+
+
+def test_c4_huber_full_batch_sampled_steps():
+    ensure_lib()
+    wl, rhos, alphas, batch, fw, bw = _bench_run("c4")
+    K, B = wl["K"], len(wl["insts"])
+    _check_one_steps(wl, rhos, alphas, batch, fw, [(0, 0), (B - 1, K // 2), (B // 2, K - 1)])
+    _check_tail_gradients(wl, rhos, alphas, batch, fw, bw, B - 1, 2, 1e-4)

@@ -10,7 +10,7 @@ import pytest
 import torch
 
 import synth
-from gpu_common import assert_close, ensure_lib, floor_of, oracle_run, say
+from gpu_common import assert_close, ensure_lib, floor_of, one_step_err, oracle_run, say
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -109,7 +109,6 @@ def test_lovasz_circulant_fp32_one_step_parity():
     1e-5; the step is allowed 8 such roundings, carried through to s and y
     (the projection is nonexpansive, y+ adds rho (s^ - s+))."""
     ensure_lib()
-    import oracle
     from paper_2606_13825_amd import CosmoBatch
     insts = _lovasz_reduced(np.float32)
     K = 20
@@ -124,19 +123,11 @@ def test_lovasz_circulant_fp32_one_step_parity():
     for i, inst in enumerate(insts):
         sl_n = slice(batch.n_off[i], batch.n_off[i + 1])
         sl_m = slice(batch.m_off[i], batch.m_off[i + 1])
-        fl = floor_of(inst)
         for k in range(K):
-            x, s, y = its[k][0][sl_n], its[k][1][sl_m], its[k][2][sl_m]
-            a = float(alphas[i][k])
-            st = oracle.step_forward(inst, x, s, y, rhos[i][k].astype(np.float64), a)
-            dxt = st["lu"].solve(st["xi"].astype(np.float32).astype(np.float64) - st["xi"])
-            dsh = a * np.linalg.norm(inst.A @ dxt)
-            floors = {"x": 8 * a * np.linalg.norm(dxt), "s": 8 * dsh, "y": 16 * float(st["rho_hat"].max()) * dsh}
-            for nm, g, r in (("x", its[k + 1][0][sl_n], st["xn"]), ("s", its[k + 1][1][sl_m], st["sn"]),
-                             ("y", its[k + 1][2][sl_m], st["yn"])):
-                f = max(fl, floors[nm] / 1e-5)
-                n_floor += f > np.linalg.norm(r)
-                worst = max(worst, assert_close(g, r, 1e-5, f, f"inst {i} step {k} {nm}"))
+            z = (its[k][0][sl_n], its[k][1][sl_m], its[k][2][sl_m])
+            z1 = (its[k + 1][0][sl_n], its[k + 1][1][sl_m], its[k + 1][2][sl_m])
+            e, nf = one_step_err(inst, z, z1, rhos[i][k], alphas[i][k], floor_of(inst))
+            worst, n_floor = max(worst, e), n_floor + nf
     say(f"  worst one-step rel err: {worst:.2e} (rounding floor active in {n_floor} of {3 * K * len(insts)} checks)")
 
 
