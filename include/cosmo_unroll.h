@@ -228,17 +228,36 @@ cosmo_status socp_proj_vjp(int32_t ncones, const int32_t *dim, const int64_t *of
  * between phases (falls back to form 0 where cooperative launch is not
  * available).  Both forms compute the same iteration with the same stopping
  * rule; their sums are taken in different orders, each deterministic.
- * set_pcg_form: form outside 0..2 is COSMO_EINVAL. */
+ * set_pcg_form: form outside 0..2 is COSMO_EINVAL; a cooperative form while
+ * graph mode is on is COSMO_EUNSUPPORTED. */
 cosmo_status cosmo_plan_set_pcg_form(cosmo_plan *plan, int32_t form);
 cosmo_status cosmo_plan_get_pcg_form(const cosmo_plan *plan, int32_t *form);
 
-/* Autotuner: runs the forward unroll (no tape) once per CG schedule on the
+/* Graph mode (enable = 0 or 1, default 0).  When on, cosmo_unroll_forward and
+ * cosmo_unroll_backward record their whole launch sequence (all K steps, the
+ * order-class streams included) into a HIP graph on the first call with a
+ * given set of pointer arguments, and on every call replay it on `stream`
+ * with one graph launch: one host call per unroll instead of several
+ * launches per step.  The data behind the pointers may change between calls
+ * (new rho, alpha, initial iterates); a call with any other pointer set
+ * records anew (and frees the previous recording), so callers that replay
+ * keep their buffers.  Recording happens on a stream the plan owns, so the
+ * caller's stream may be the default stream.  While profiling is enabled the
+ * calls launch eagerly.  Results are bitwise the same as eager launches.
+ * Enabling it with a cooperative CG form selected is COSMO_EUNSUPPORTED
+ * (cooperative launches are not recorded).  Set-up calls. */
+cosmo_status cosmo_plan_set_graph(cosmo_plan *plan, int32_t enable);
+cosmo_status cosmo_plan_get_graph(const cosmo_plan *plan, int32_t *enabled);
+
+/* Autotuner: runs the forward unroll (no tape) under each schedule -- CG
+ * forms 0, 1, 2 launched eagerly, and form 0 replayed from a graph -- on the
  * given rho, alpha and forward workspace, times the second of two runs with
- * events on `stream`, and keeps the fastest schedule in the plan.  A setup
- * call, not for the hot path: it allocates a scratch output buffer and waits
- * for the stream.  ms (host, nullable) [3] receives the timings (-1 for
- * forms not run); problems whose reduced matrix is diagonal have no CG and
- * keep their form. */
+ * events on `stream`, and keeps the fastest (CG form and graph mode) in the
+ * plan.  A setup call, not for the hot path: it allocates a scratch output
+ * buffer and waits for the stream.  ms (host, nullable) [4] receives the
+ * timings in that order (-1 for schedules not run: problems whose reduced
+ * matrix is diagonal have no CG, and only the eager and graph runs of form
+ * 0 are timed for them). */
 cosmo_status cosmo_plan_autotune(cosmo_plan *plan, const void *rho, const void *alpha, void *ws, void *stream,
                                  double *ms);
 

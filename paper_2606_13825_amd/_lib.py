@@ -22,6 +22,7 @@ EXPORTED = [
     "cosmo_proj_workspace_size", "psd_proj", "psd_proj_vjp", "socp_proj", "socp_proj_vjp",
     "cosmo_plan_set_profiling", "cosmo_plan_profile_read",
     "cosmo_plan_set_pcg_form", "cosmo_plan_get_pcg_form", "cosmo_plan_autotune",
+    "cosmo_plan_set_graph", "cosmo_plan_get_graph",
 ]
 
 
@@ -121,6 +122,10 @@ def _sig(lib):
     lib.cosmo_plan_set_pcg_form.argtypes = [vp, i32]
     lib.cosmo_plan_get_pcg_form.restype = ctypes.c_int
     lib.cosmo_plan_get_pcg_form.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.cosmo_plan_set_graph.restype = ctypes.c_int
+    lib.cosmo_plan_set_graph.argtypes = [vp, i32]
+    lib.cosmo_plan_get_graph.restype = ctypes.c_int
+    lib.cosmo_plan_get_graph.argtypes = [vp, ctypes.POINTER(i32)]
     lib.cosmo_plan_autotune.restype = ctypes.c_int
     lib.cosmo_plan_autotune.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(dbl)]
 

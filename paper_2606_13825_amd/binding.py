@@ -288,13 +288,25 @@ class CosmoBatch:
         L.check(L.lib().cosmo_plan_get_pcg_form(self._plan, ctypes.byref(f)), "cosmo_plan_get_pcg_form")
         return f.value
 
+    def set_graph(self, enable: bool):
+        """Graph mode: forward and backward calls record their launch
+        sequence once per set of buffers and replay it afterwards."""
+        L.check(L.lib().cosmo_plan_set_graph(self._plan, int(bool(enable))), "cosmo_plan_set_graph")
+
+    def graph(self) -> bool:
+        f = ctypes.c_int32()
+        L.check(L.lib().cosmo_plan_get_graph(self._plan, ctypes.byref(f)), "cosmo_plan_get_graph")
+        return bool(f.value)
+
     def autotune(self, rho: torch.Tensor, alpha: torch.Tensor, ws: Optional[torch.Tensor] = None):
-        """Time every CG schedule on a forward unroll and keep the fastest;
-        returns (chosen form, [ms per form], -1 where not run)."""
+        """Time the schedules (CG forms 0, 1, 2 eager; form 0 from a graph) on
+        a forward unroll and keep the fastest; returns (chosen CG form,
+        [ms per schedule], -1 where not run).  graph() tells whether graph
+        mode was chosen."""
         rho = self._check_vec(rho.contiguous(), self.K * self.m_tot, "rho")
         alpha = self._check_vec(alpha.contiguous(), self.K * self.B, "alpha")
         ws = ws if ws is not None else self.new_fwd_ws()
-        ms = (ctypes.c_double * 3)()
+        ms = (ctypes.c_double * 4)()
         L.check(L.lib().cosmo_plan_autotune(self._plan, _ptr(rho), _ptr(alpha), _ptr(ws), _stream(self.device), ms),
                 "cosmo_plan_autotune")
         return self.pcg_form(), [float(x) for x in ms]

@@ -117,7 +117,26 @@ struct cosmo_plan {
   hipStream_t aux[3] = {nullptr, nullptr, nullptr};
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_join[3] = {nullptr, nullptr, nullptr};
+  // Graph mode: each direction's launch sequence is recorded once per set of
+  // pointer arguments (on the plan's own capture stream, so the caller may
+  // pass the legacy default stream) and replayed on the caller's stream.
+  struct Recorded {
+    hipGraphExec_t exec = nullptr;
+    std::vector<const void *> key;
+  };
+  bool graph = false;
+  hipStream_t cap = nullptr;
+  Recorded rec_fwd, rec_bwd;
+  void drop_graphs() {
+    for (Recorded *r : {&rec_fwd, &rec_bwd}) {
+      if (r->exec) (void)hipGraphExecDestroy(r->exec);
+      r->exec = nullptr;
+      r->key.clear();
+    }
+  }
   ~cosmo_plan() {
+    drop_graphs();
+    if (cap) (void)hipStreamDestroy(cap);
     for (auto &s : prof)
       for (auto &e : s.ev) {
         (void)hipEventDestroy(e.first);
@@ -714,6 +733,38 @@ cosmo_status backward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T
   return COSMO_OK;
 }
 
+// Runs `body(stream)` eagerly on `st`, or in graph mode replays the recorded
+// sequence for this argument set (recording it first if the set is new).
+// Profiling runs are always eager (their events are read back by the host).
+template <typename F>
+cosmo_status run_recorded(cosmo_plan *pl, cosmo_plan::Recorded &rec, std::vector<const void *> key, hipStream_t st,
+                          F &&body) {
+  if (!pl->graph || pl->profiling) return body(st);
+  if (!rec.exec || rec.key != key) {
+    if (rec.exec) (void)hipGraphExecDestroy(rec.exec);
+    rec.exec = nullptr;
+    rec.key.clear();
+    HIPCHK(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeRelaxed));
+    const cosmo_status s = body(pl->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(pl->cap, &g);
+    if (s != COSMO_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess || !g) FAIL(COSMO_EHIP, std::string("recording the unroll failed: ") + hipGetErrorString(e));
+    const hipError_t ei = hipGraphInstantiate(&rec.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      rec.exec = nullptr;
+      FAIL(COSMO_EHIP, std::string("instantiating the recorded unroll failed: ") + hipGetErrorString(ei));
+    }
+    rec.key = std::move(key);
+  }
+  HIPCHK(hipGraphLaunch(rec.exec, st));
+  return COSMO_OK;
+}
+
 cosmo_status check_plan(const cosmo_plan *pl) {
   if (!pl) FAIL(COSMO_EINVAL, "plan is NULL");
   return COSMO_OK;
@@ -779,7 +830,8 @@ cosmo_status cosmo_plan_create(cosmo_plan **plan, const cosmo_problem *prob, con
       FAIL(COSMO_EHIP, "creating auxiliary streams failed");
     }
   }
-  if (hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) != hipSuccess) {
+  if (hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking) != hipSuccess) {
     delete pl;
     FAIL(COSMO_EHIP, "creating events failed");
   }
@@ -825,15 +877,17 @@ cosmo_status cosmo_unroll_forward(cosmo_plan *plan, const void *rho, const void 
   if (s != COSMO_OK) return s;
   if (!rho || !alpha) FAIL(COSMO_EINVAL, "rho and alpha are required");
   if (!ws) FAIL(COSMO_EINVAL, "workspace is required");
-  hipStream_t st = static_cast<hipStream_t>(stream);
   auto *stp = static_cast<cosmo_stats *>(stats);
-  if (plan->opt.dtype == COSMO_F32)
-    return forward_impl<float>(plan, (const float *)rho, (const float *)alpha, (const float *)x0, (const float *)s0,
-                               (const float *)y0, (float *)xK, (float *)sK, (float *)yK, (float *)tape, (float *)ws,
-                               stp, st);
-  return forward_impl<double>(plan, (const double *)rho, (const double *)alpha, (const double *)x0,
-                              (const double *)s0, (const double *)y0, (double *)xK, (double *)sK, (double *)yK,
-                              (double *)tape, (double *)ws, stp, st);
+  return run_recorded(plan, plan->rec_fwd, {rho, alpha, x0, s0, y0, xK, sK, yK, tape, ws, stats},
+                      static_cast<hipStream_t>(stream), [&](hipStream_t st) {
+    if (plan->opt.dtype == COSMO_F32)
+      return forward_impl<float>(plan, (const float *)rho, (const float *)alpha, (const float *)x0,
+                                 (const float *)s0, (const float *)y0, (float *)xK, (float *)sK, (float *)yK,
+                                 (float *)tape, (float *)ws, stp, st);
+    return forward_impl<double>(plan, (const double *)rho, (const double *)alpha, (const double *)x0,
+                                (const double *)s0, (const double *)y0, (double *)xK, (double *)sK, (double *)yK,
+                                (double *)tape, (double *)ws, stp, st);
+  });
 }
 
 cosmo_status cosmo_unroll_backward(cosmo_plan *plan, const void *rho, const void *alpha, const void *tape,
@@ -844,15 +898,17 @@ cosmo_status cosmo_unroll_backward(cosmo_plan *plan, const void *rho, const void
   if (!rho || !alpha) FAIL(COSMO_EINVAL, "rho and alpha are required");
   if (!tape) FAIL(COSMO_EINVAL, "the backward pass needs the tape written by cosmo_unroll_forward");
   if (!ws) FAIL(COSMO_EINVAL, "workspace is required");
-  hipStream_t st = static_cast<hipStream_t>(stream);
   auto *stp = static_cast<cosmo_stats *>(stats);
-  if (plan->opt.dtype == COSMO_F32)
-    return backward_impl<float>(plan, (const float *)rho, (const float *)alpha, (const float *)tape,
-                                (const float *)gxK, (const float *)gsK, (const float *)gyK, (float *)grho,
-                                (float *)galpha, (float *)gx0, (float *)gs0, (float *)gy0, (float *)ws, stp, st);
-  return backward_impl<double>(plan, (const double *)rho, (const double *)alpha, (const double *)tape,
-                               (const double *)gxK, (const double *)gsK, (const double *)gyK, (double *)grho,
-                               (double *)galpha, (double *)gx0, (double *)gs0, (double *)gy0, (double *)ws, stp, st);
+  return run_recorded(plan, plan->rec_bwd, {rho, alpha, tape, gxK, gsK, gyK, grho, galpha, gx0, gs0, gy0, ws, stats},
+                      static_cast<hipStream_t>(stream), [&](hipStream_t st) {
+    if (plan->opt.dtype == COSMO_F32)
+      return backward_impl<float>(plan, (const float *)rho, (const float *)alpha, (const float *)tape,
+                                  (const float *)gxK, (const float *)gsK, (const float *)gyK, (float *)grho,
+                                  (float *)galpha, (float *)gx0, (float *)gs0, (float *)gy0, (float *)ws, stp, st);
+    return backward_impl<double>(plan, (const double *)rho, (const double *)alpha, (const double *)tape,
+                                 (const double *)gxK, (const double *)gsK, (const double *)gyK, (double *)grho,
+                                 (double *)galpha, (double *)gx0, (double *)gs0, (double *)gy0, (double *)ws, stp, st);
+  });
 }
 
 cosmo_status cosmo_residual_loss(cosmo_plan *plan, const void *x, const void *s, const void *y, void *loss, void *gx,
@@ -882,7 +938,27 @@ cosmo_status cosmo_plan_set_pcg_form(cosmo_plan *plan, int32_t form) {
   cosmo_status s = check_plan(plan);
   if (s != COSMO_OK) return s;
   if (form < 0 || form > 2) FAIL(COSMO_EINVAL, "form must be 0, 1 or 2");
+  if (form != 0 && plan->graph) FAIL(COSMO_EUNSUPPORTED, "the cooperative CG forms are not recorded into graphs");
   plan->pcg_form = form;
+  return COSMO_OK;
+}
+
+cosmo_status cosmo_plan_set_graph(cosmo_plan *plan, int32_t enable) {
+  cosmo_status s = check_plan(plan);
+  if (s != COSMO_OK) return s;
+  if (enable != 0 && enable != 1) FAIL(COSMO_EINVAL, "enable must be 0 or 1");
+  if (enable && plan->pcg_form != 0 && !plan->diag_M)
+    FAIL(COSMO_EUNSUPPORTED, "the cooperative CG forms are not recorded into graphs");
+  plan->drop_graphs();
+  plan->graph = enable != 0;
+  return COSMO_OK;
+}
+
+cosmo_status cosmo_plan_get_graph(const cosmo_plan *plan, int32_t *enabled) {
+  cosmo_status s = check_plan(plan);
+  if (s != COSMO_OK) return s;
+  if (!enabled) FAIL(COSMO_EINVAL, "enabled is NULL");
+  *enabled = plan->graph ? 1 : 0;
   return COSMO_OK;
 }
 
@@ -900,8 +976,7 @@ cosmo_status cosmo_plan_autotune(cosmo_plan *plan, const void *rho, const void *
   if (s != COSMO_OK) return s;
   if (!rho || !alpha || !ws) FAIL(COSMO_EINVAL, "rho, alpha and the workspace are required");
   if (ms_out)
-    for (int f = 0; f < 3; ++f) ms_out[f] = -1.0;
-  if (plan->diag_M) return COSMO_OK;   // no CG to schedule
+    for (int c = 0; c < 4; ++c) ms_out[c] = -1.0;
   hipStream_t st = static_cast<hipStream_t>(stream);
   DevBuf out;
   HIPCHK(hipMalloc(&out.ptr, (2 * plan->m_tot + plan->n_tot) * plan->esz));
@@ -913,12 +988,20 @@ cosmo_status cosmo_plan_autotune(cosmo_plan *plan, const void *rho, const void *
     (void)hipEventDestroy(e0);
     FAIL(COSMO_EHIP, "hipEventCreate failed");
   }
-  const int32_t keep = plan->pcg_form;
+  // candidates: CG forms 0, 1, 2 launched eagerly, then form 0 replayed from a graph
+  const int32_t cand_form[4] = {0, 1, 2, 0};
+  const bool cand_graph[4] = {false, false, false, true};
+  const int32_t keep_form = plan->pcg_form;
+  const bool keep_graph = plan->graph, keep_prof = plan->profiling;
+  plan->profiling = false;
   double best = -1.0;
-  int32_t best_form = keep;
-  for (int32_t f = 0; f < 3 && s == COSMO_OK; ++f) {
-    plan->pcg_form = f;
-    for (int rep = 0; rep < 2 && s == COSMO_OK; ++rep) {   // the first run warms caches and code objects
+  int best_c = -1;
+  for (int c = 0; c < 4 && s == COSMO_OK; ++c) {
+    if (plan->diag_M && cand_form[c] != 0) continue;   // no CG to schedule
+    plan->drop_graphs();
+    plan->pcg_form = cand_form[c];
+    plan->graph = cand_graph[c];
+    for (int rep = 0; rep < 2 && s == COSMO_OK; ++rep) {   // the first run warms caches, code objects, records
       (void)hipEventRecord(e0, st);
       s = cosmo_unroll_forward(plan, rho, alpha, nullptr, nullptr, nullptr, xK, sK, yK, nullptr, ws, nullptr, stream);
       (void)hipEventRecord(e1, st);
@@ -930,16 +1013,19 @@ cosmo_status cosmo_plan_autotune(cosmo_plan *plan, const void *rho, const void *
     }
     float ms = 0;
     (void)hipEventElapsedTime(&ms, e0, e1);
-    if (ms_out) ms_out[f] = ms;
+    if (ms_out) ms_out[c] = ms;
     if (best < 0 || ms < best) {
       best = ms;
-      best_form = f;
+      best_c = c;
     }
   }
   (void)hipStreamSynchronize(st);   // nothing in flight reads the scratch outputs when they are freed
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  plan->pcg_form = (s == COSMO_OK) ? best_form : keep;
+  plan->drop_graphs();   // the recorded sequences point at the scratch outputs
+  plan->profiling = keep_prof;
+  plan->pcg_form = (s == COSMO_OK && best_c >= 0) ? cand_form[best_c] : keep_form;
+  plan->graph = (s == COSMO_OK && best_c >= 0) ? cand_graph[best_c] : keep_graph;
   return s;
 }
 
