@@ -27,8 +27,15 @@
 //    barriers, and instances that are done drop out of the passes.  Every
 //    workgroup leaves each loop at the same barrier, when no instance is
 //    left active (bounded by max_iter and the restart count).
-#include <hip/hip_cooperative_groups.h>
-
+//
+// The grid barrier is written here rather than taken from the runtime: an
+// arrival counter and a generation word, with an agent-scope release fence
+// before arriving and an acquire fence after leaving, costs about a quarter
+// of the runtime's grid synchronisation at 256-512 workgroups.  The launch
+// is cooperative, so every workgroup is resident and every wait ends; each
+// wait is still bounded in time, and a wait that runs out raises an abort
+// word that releases every workgroup: the solve then ends at once and marks
+// its solutions non-finite instead of hanging.
 #include <algorithm>
 
 #include "cosmo_internal.h"
@@ -321,18 +328,64 @@ __global__ __launch_bounds__(PT) void k_pcg(View<T> v, const T *__restrict__ rho
 
 // ---- cooperative form ------------------------------------------------------------
 
+constexpr uint64_t BAR_TIMEOUT_TICKS = 200000000ull;   // 2 s of the 100 MHz real-time counter
+
+// Barrier words of one cooperative solve, each in its own 256-byte line,
+// zeroed on the stream before the launch.
+struct GridBar {
+  uint32_t *count, *gen, *abort;
+  uint32_t nblk;
+};
+
+// Returns true once any wait of this solve has run out of time.
+__device__ inline bool grid_barrier(const GridBar &gb, uint32_t &gen, int32_t *shared_flag) {
+  __syncthreads();   // the workgroup's stores are complete (workgroup-scope release in every wave)
+  const uint32_t target = gen + 1;
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (__hip_atomic_fetch_add(gb.count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gb.nblk - 1) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __hip_atomic_store(gb.count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(gb.gen, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+      while (__hip_atomic_load(gb.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != target) {
+        if (__hip_atomic_load(gb.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+        if (__builtin_amdgcn_s_memrealtime() - t0 > BAR_TIMEOUT_TICKS) {
+          __hip_atomic_store(gb.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    *shared_flag = __hip_atomic_load(gb.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+  }
+  gen = target;
+  __syncthreads();
+  return *shared_flag != 0;
+}
+
+// Zeroes the barrier words before a cooperative solve.
+__global__ void k_bar_reset(uint32_t *words) {
+  if (threadIdx.x < 3) words[64 * threadIdx.x] = 0;
+}
+
 // Per-instance state of the cooperative solve (caller workspace, 16 (B + 1)
-// elements of T): rz, rr [B] in T, thr, rrt [B] in float64, then int32 it,
-// act, done, fail [B] and two counters.
+// + 256 elements of T): the three barrier words (768 bytes), then rz, rr [B]
+// in T, thr, rrt [B] in float64, then int32 it, act, done, fail [B] and two
+// counters.
 template <typename T> struct CoopState {
   T *rz, *rr;
   double *thr, *rrt;
   int32_t *it, *act, *done, *fail, *cnt;
 };
 
+constexpr size_t BAR_BYTES = 768;
+
 template <typename T> __device__ inline CoopState<T> coop_state(void *ws, int B) {
   CoopState<T> c;
-  char *base = static_cast<char *>(ws);
+  char *base = static_cast<char *>(ws) + BAR_BYTES;
   c.rz = reinterpret_cast<T *>(base);
   c.rr = c.rz + B;
   const size_t dbl = (2 * (size_t)B * sizeof(T) + 7) / 8 * 8;   // 8-byte aligned (the workspace is 256-aligned)
@@ -356,11 +409,15 @@ __global__ __launch_bounds__(CT) void k_pcg_coop(View<T> v, const T *__restrict_
                                                  const T *__restrict__ xold, T *__restrict__ xnew,
                                                  const T *__restrict__ gx_in, T *__restrict__ gx_out, int32_t mode,
                                                  cosmo_stats *stats, void *state) {
-  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
   __shared__ T red[2 * (CT / 64)];
   __shared__ double redd[2 * (CT / 64)];
+  __shared__ int32_t bar_flag;
   const CoopState<T> cs = coop_state<T>(state, v.B);
-  auto gsync = [&]() { grid.sync(); };
+  uint32_t *words = static_cast<uint32_t *>(state);
+  const GridBar gb{words, words + 64, words + 128, gridDim.x};
+  uint32_t gen = 0;
+  bool aborted = false;
+  auto gsync = [&]() { aborted = grid_barrier(gb, gen, &bar_flag) || aborted; };
   auto row_open = [&](int32_t i) { return cs.done[v.row_inst[i]] == 0; };
   auto col_open = [&](int32_t j) { return cs.done[v.col_inst[j]] == 0; };
   auto row_act = [&](int32_t i) { return cs.act[v.row_inst[i]] != 0; };
@@ -391,10 +448,11 @@ __global__ __launch_bounds__(CT) void k_pcg_coop(View<T> v, const T *__restrict_
       cs.fail[b] = !isfinite(bb);
     }
   }
-  grid.sync();
-  for (int restart = 0;; ++restart) {
+  gsync();
+  for (int restart = 0; !aborted; ++restart) {
     // true residual of the instances not done; z, p; which go on
     op_residual64<CT, true>(v, rho_hat, rhs, x, t64, r, 0, v.B, row_open, col_open, gsync);
+    if (aborted) break;
     for (int b = blockIdx.x; b < v.B; b += gridDim.x) {
       if (cs.done[b]) continue;
       const int64_t n0 = v.n_off[b], n1 = v.n_off[b + 1];
@@ -423,11 +481,12 @@ __global__ __launch_bounds__(CT) void k_pcg_coop(View<T> v, const T *__restrict_
         if (!done) atomicAdd(&cs.cnt[cur], 1);
       }
     }
-    grid.sync();
-    if (decide() == 0) break;
+    gsync();
+    if (aborted || decide() == 0) break;
     // CG on the recursive residual until no instance is active
     for (;;) {
       op_apply<CT, true>(v, rho_hat, p, t, Mp, 0, v.B, row_act, col_act, gsync);
+      if (aborted) break;
       for (int b = blockIdx.x; b < v.B; b += gridDim.x) {
         if (!cs.act[b]) continue;
         const int64_t n0 = v.n_off[b], n1 = v.n_off[b + 1];
@@ -471,13 +530,15 @@ __global__ __launch_bounds__(CT) void k_pcg_coop(View<T> v, const T *__restrict_
           if (act) atomicAdd(&cs.cnt[cur], 1);
         }
       }
-      grid.sync();
-      if (decide() == 0) break;
+      gsync();
+      if (aborted || decide() == 0) break;
     }
   }
+  // after an abort the solutions are marked non-finite (the state of the
+  // instances is not trusted)
   for (int b = blockIdx.x; b < v.B; b += gridDim.x)
-    finish<CT>(v, b, cs.fail[b] != 0, cs.it[b], cs.rrt[b], cs.thr[b], x, alpha_k, xold, xnew, gx_in, gx_out, mode,
-               stats);
+    finish<CT>(v, b, aborted || cs.fail[b] != 0, cs.it[b], cs.rrt[b], cs.thr[b], x, alpha_k, xold, xnew, gx_in,
+               gx_out, mode, stats);
 }
 
 }  // namespace
@@ -515,6 +576,7 @@ void launch_pcg(const View<T> &v, const T *rho_hat, const T *dg, const T *rhs, T
     int32_t mi = max_iter, md = mode;
     void *args[] = {&va, &rho_hat, &dg,   &rhs,  &x,     &r,      &z,  &p,     &Mp,    &t,   &t64,
                     &tl, &mi,      &alpha_k, &xold, &xnew, &gx_in, &gx_out, &md, &stats, &state};
+    k_bar_reset<<<1, 64, 0, st>>>(static_cast<uint32_t *>(state));
     if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_pcg_coop<T>), dim3(grid), dim3(CT), args, 0,
                                    st) == hipSuccess)
       return;

@@ -498,7 +498,7 @@ void build_layouts(cosmo_plan *pl) {
   f.Mp = take(n);
   f.t = take(m);
   f.t64 = take(2 * m);                     // float64 residual pass of the CG (m doubles)
-  f.cg = take(16 * ((size_t)pl->B + 1));  // per-instance state of the CG (cooperative form)
+  f.cg = take(16 * ((size_t)pl->B + 1) + 256);  // per-instance state of the CG (cooperative form)
   f.sh = take(m);
   f.vv = take(m);
   // (x, s, y) triples laid out like a tape slot: each part starts 64-element aligned
@@ -541,7 +541,7 @@ void build_layouts(cosmo_plan *pl) {
   w.Mp = take(n);
   w.t = take(m);
   w.t64 = take(2 * m);
-  w.cg = take(16 * ((size_t)pl->B + 1));
+  w.cg = take(16 * ((size_t)pl->B + 1) + 256);
   w.vv = take(m);
   w.dk = take(pl->sum_p2_large);
   w.total = o;
