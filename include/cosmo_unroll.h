@@ -84,8 +84,9 @@ typedef struct {
   const int64_t *n_off;        /* (h) [B+1], n_off[0] = 0, non-decreasing, n_tot = n_off[B] */
   const int64_t *m_off;        /* (h) [B+1], m_off[0] = 0, strictly increasing         */
   const int64_t *A_rowptr;     /* (d) [m_tot+1] CSR of A (m_tot x n_tot)               */
-  const int32_t *A_col;        /* (d) [nnz(A)], columns inside the row's instance       */
-  const void *A_val;           /* (d) [nnz(A)] dtype                                    */
+  const int32_t *A_col;        /* (d) [nnz(A)], columns inside the row's instance;
+                                  16-byte aligned (rows are read in 16-byte pieces)     */
+  const void *A_val;           /* (d) [nnz(A)] dtype, 16-byte aligned                   */
   int64_t A_nnz;
   const int64_t *P_rowptr;     /* (d) [n_tot+1] CSR of P, symmetric, full storage;
                                   may be NULL when P_nnz == 0                            */

@@ -86,7 +86,7 @@ template <typename T> struct DiagSolve {
 template <typename T> void launch_rectify(const View<T> &v, const RectDesc *rect, int32_t nrect, const T *rho,
                                           T *rho_hat, int32_t K, hipStream_t st);
 template <typename T> void launch_cols_pre(const View<T> &v, const RowBuckets &bk, const T *rho_hat, const T *x,
-                                           const T *s, const T *y, T *dg, T *xi, DiagSolve<T> ds, hipStream_t st);
+                                           const T *s, const T *y, T *dg, double *xi, DiagSolve<T> ds, hipStream_t st);
 template <typename T> void launch_rows_post(const View<T> &v, const RowBuckets &bk, const T *rho_hat,
                                             const T *alpha_k, const T *xt, const T *s, const T *y, T *st_out,
                                             T *sh, T *vv, T *s_new, T *y_new, hipStream_t st);
@@ -99,7 +99,7 @@ template <typename T> void launch_bwd_rows_b(const View<T> &v, const T *rho_hat,
                                              const T *s, const T *y, const T *s_new, const T *gy_in, const T *gv,
                                              T *gsh, T *gst, T *gs_out, T *gy_out, T *grh, hipStream_t st);
 template <typename T> void launch_bwd_cols(const View<T> &v, const RowBuckets &bk, const T *rho_hat,
-                                           const T *alpha_k, const T *gst, const T *gx_in, T *gxt, T *dg,
+                                           const T *alpha_k, const T *gst, const T *gx_in, double *gxt, T *dg,
                                            DiagSolve<T> ds, hipStream_t st);
 template <typename T> void launch_bwd_rows_c(const View<T> &v, const RowBuckets &bk, const T *rho_hat,
                                              const T *w, const T *stl, const T *s, T *grh, T *gs_out,
@@ -121,7 +121,7 @@ template <typename T> void launch_nonfinite_check(const View<T> &v, const T *x, 
 //   mode 0 (forward): solves M x = rhs, warm start from x (in/out), writes
 //     xt_out (may alias x) and, if xnew != nullptr, x+ = alpha x~ + (1 - alpha) xold.
 //   mode 1 (adjoint): solves M w = rhs; writes w and gx_out = (1 - alpha) gx_in + sigma w.
-template <typename T> void launch_pcg(const View<T> &v, const T *rho_hat, const T *dg, const T *rhs, T *x,
+template <typename T> void launch_pcg(const View<T> &v, const T *rho_hat, const T *dg, const double *rhs, T *x,
                                       T *r, T *z, T *p, T *Mp, T *t, double *t64, double tol, int32_t max_iter,
                                       const T *alpha_k, const T *xold, T *xnew, const T *gx_in, T *gx_out,
                                       int32_t mode, cosmo_stats *stats, void *state, int32_t form,

@@ -1,5 +1,8 @@
 // Jacobi-preconditioned conjugate gradient for the reduced COSMO system
 //   M(rho_hat) x = rhs,   M = P + sigma I + A' D(rho_hat) A
+// (rhs is held in float64: in float32 its one rounding alone can move the
+// solution by up to cond(M) eps, e.g. 4e-3 on the Lovasz systems, whose
+// right-hand side is dominated by the trace row's large component)
 // (eq:cosmo_linear_system_reduced; CG with Jacobi preconditioner, Table 2).
 // The operator is applied matrix-free: t = rho_hat o (A p) over the
 // instance's rows, then (M p)_j = (P p)_j + sigma p_j + (A' t)_j over its
@@ -12,10 +15,13 @@
 // max_iter iterations in all.  The iteration runs in the working precision
 // on the recursively updated residual; when that meets the tolerance the
 // true residual is recomputed with float64 accumulation, and if it does not
-// the CG restarts from it (at most once).  On an ill-conditioned M a
-// float32 recursion alone stalls at a solution error near cond(M) eps; one
-// restart from an accurate residual brings the error down to the rounding
-// of the stored solution (a second one gains nothing measurable in float32).
+// the CG restarts from it (iterative refinement: each restarted round solves
+// for the correction and only needs to lower its own starting residual by
+// 1e-2).  Refinement ends when the true residual meets the tolerance, after
+// four restarts, or when a round lowered the true residual by less than 2x
+// (the working precision's floor).  On an ill-conditioned M a float32
+// recursion alone leaves a solution error near cond(M) eps; each refinement
+// round multiplies it by about cond(M) eps again.
 //
 // Two launch forms share the rule and the per-instance scalars (segmented
 // CG over the super-batch):
@@ -45,7 +51,9 @@ namespace {
 
 constexpr int PT = 512;      // threads per instance workgroup
 constexpr int CT = 256;      // threads per workgroup of the cooperative form
-constexpr int NRESTART = 1;  // restarts from a float64 residual
+constexpr int NRESTART = 4;          // restarts from a float64 residual, at most
+constexpr double ROUND_DROP2 = 1e-4;  // a restarted round lowers its residual by 1e-2 (squared here)
+constexpr double STALL2 = 0.25;       // a true residual that fell by less than 2x ends the refinement
 
 template <typename T> __device__ inline T sub_sum(T v, int L) {
   for (int off = L >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -122,8 +130,20 @@ __device__ inline void short_rows(const int32_t *__restrict__ rows, int64_t firs
   }
 }
 
-// L lanes per row, two products in flight per lane.  gsub / nsub: this
-// thread's row group and the number of row groups of the pass.
+// 16-byte pieces of a row: VE = 16 / sizeof(T) values and VE column indices.
+template <typename T> struct alignas(16) ValPiece {
+  T v[16 / sizeof(T)];
+};
+template <int N> struct alignas(4 * N) ColPiece {
+  int32_t c[N];
+};
+
+// L lanes per row.  The row's entries are read in 16-byte pieces (the CSR
+// arrays are 16-byte aligned): entries before its first aligned piece and
+// after its last full piece one per lane, the full pieces two per lane per
+// pass (the second clamped and masked), so that four 16-byte loads and 2 VE
+// gathers are in flight per lane.  gsub / nsub: this thread's row group and
+// the number of row groups of the pass.
 template <int L, typename AT, typename T, typename VT, typename Act, typename F>
 __device__ inline void row_pass(const int32_t *__restrict__ rows, int64_t r0, int64_t r1, int64_t gsub, int64_t nsub,
                                 const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
@@ -131,6 +151,9 @@ __device__ inline void row_pass(const int32_t *__restrict__ rows, int64_t r0, in
   if constexpr (L == 1) {
     short_rows<AT>(rows, r0 + gsub, r1, nsub, rowptr, col, val, vin, active, emit);
   } else {
+    constexpr int VE = 16 / sizeof(T);
+    using VP = ValPiece<T>;
+    using CP = ColPiece<VE>;
     const int lane = threadIdx.x % L;
     for (int64_t base = r0; base < r1; base += nsub) {
       const int64_t ri = base + gsub;
@@ -141,13 +164,26 @@ __device__ inline void row_pass(const int32_t *__restrict__ rows, int64_t r0, in
         row = rows[ri];
         ok = active(row);
         if (ok) {
-          const int64_t k1 = rowptr[row + 1];
-          int64_t k = rowptr[row] + lane;
-          for (; k + L < k1; k += 2 * L) {
-            a0 += (AT)val[k] * (AT)vin[col[k]];
-            a1 += (AT)val[k + L] * (AT)vin[col[k + L]];
+          const int64_t kb = rowptr[row], k1 = rowptr[row + 1];
+          int64_t ka = (kb + VE - 1) / VE * VE;
+          if (ka > k1) ka = k1;
+          const int64_t np = (k1 - ka) / VE, kt = ka + np * VE;
+          if (lane < ka - kb) a0 += (AT)val[kb + lane] * (AT)vin[col[kb + lane]];
+          if (lane < k1 - kt) a1 += (AT)val[kt + lane] * (AT)vin[col[kt + lane]];
+          const VP *vp = reinterpret_cast<const VP *>(val + ka);
+          const CP *cp = reinterpret_cast<const CP *>(col + ka);
+          for (int64_t q = lane; q < np; q += 2 * L) {
+            const bool two = q + L < np;
+            const int64_t q1 = two ? q + L : q;
+            const VP v0 = vp[q], v1 = vp[q1];
+            const CP c0 = cp[q], c1 = cp[q1];
+#pragma unroll
+            for (int e = 0; e < VE; ++e) {
+              a0 += (AT)v0.v[e] * (AT)vin[c0.c[e]];
+              const AT p1 = (AT)v1.v[e] * (AT)vin[c1.c[e]];
+              a1 += two ? p1 : (AT)0;
+            }
           }
-          if (k < k1) a0 += (AT)val[k] * (AT)vin[col[k]];
         }
       }
       const AT acc = sub_sum(a0 + a1, L);   // every lane of the row group takes part
@@ -205,7 +241,7 @@ __device__ inline void op_apply(const View<T> &v, const T *__restrict__ rho_hat,
 // r = rhs - M x with float64 accumulation (t64 holds rho_hat o (A x) in
 // float64); r is stored in the working precision.
 template <int NTH, bool GRID, typename T, typename RowAct, typename ColAct, typename Sync>
-__device__ inline void op_residual64(const View<T> &v, const T *__restrict__ rho_hat, const T *__restrict__ rhs,
+__device__ inline void op_residual64(const View<T> &v, const T *__restrict__ rho_hat, const double *__restrict__ rhs,
                                      const T *__restrict__ x, double *__restrict__ t64, T *__restrict__ r, int b0,
                                      int b1, RowAct row_act, ColAct col_act, Sync sync) {
   const int64_t B1 = v.B + 1;
@@ -217,7 +253,7 @@ __device__ inline void op_residual64(const View<T> &v, const T *__restrict__ rho
                                     if (v.P_rowptr)
                                       for (int64_t k = v.P_rowptr[j]; k < v.P_rowptr[j + 1]; ++k)
                                         acc += (double)v.P_val[k] * (double)x[v.P_col[k]];
-                                    r[j] = (T)((double)rhs[j] - acc - (double)v.sigma * (double)x[j]);
+                                    r[j] = (T)(rhs[j] - acc - (double)v.sigma * (double)x[j]);
                                   });
   sync();
 }
@@ -248,7 +284,7 @@ __device__ inline void finish(const View<T> &v, int b, bool fail, int it, double
 
 template <typename T>
 __global__ __launch_bounds__(PT) void k_pcg(View<T> v, const T *__restrict__ rho_hat, const T *__restrict__ dg,
-                                            const T *__restrict__ rhs, T *__restrict__ x, T *__restrict__ r,
+                                            const double *__restrict__ rhs, T *__restrict__ x, T *__restrict__ r,
                                             T *__restrict__ z, T *__restrict__ p, T *__restrict__ Mp,
                                             T *__restrict__ t, double *__restrict__ t64, T tol, int32_t max_iter,
                                             const T *__restrict__ alpha_k, const T *__restrict__ xold,
@@ -262,12 +298,12 @@ __global__ __launch_bounds__(PT) void k_pcg(View<T> v, const T *__restrict__ rho
   auto bar = []() { __syncthreads(); };
 
   double bb = 0, dd = 0;
-  for (int64_t j = n0 + threadIdx.x; j < n1; j += PT) bb += (double)rhs[j] * (double)rhs[j];
+  for (int64_t j = n0 + threadIdx.x; j < n1; j += PT) bb += rhs[j] * rhs[j];
   wg_sum2<PT>(bb, dd, redd);
   const double thr = (double)tol * (double)tol * bb;
   bool fail = !isfinite(bb);
   int it = 0;
-  double rrt = 0;
+  double rrt = 0, rrt_prev = 0;
   for (int restart = 0;; ++restart) {
     // true residual, z = r / diag M, p = z
     op_residual64<PT, false>(v, rho_hat, rhs, x, t64, r, b, b + 1, all, all, bar);
@@ -285,9 +321,12 @@ __global__ __launch_bounds__(PT) void k_pcg(View<T> v, const T *__restrict__ rho
     wg_sum2<PT>(rz, rr, red);
     wg_sum2<PT>(rrt, dd, redd);
     fail = fail || !isfinite(rrt);
-    if (fail || rrt <= thr || it >= max_iter || restart > NRESTART) break;
+    const bool stalled = restart > 0 && rrt > STALL2 * rrt_prev;
+    if (fail || rrt <= thr || it >= max_iter || restart > NRESTART || stalled) break;
+    rrt_prev = rrt;
+    const T target = (T)(restart == 0 ? thr : fmax(thr, ROUND_DROP2 * (double)rr));
     // CG on the recursive residual
-    while (rr > (T)thr && it < max_iter) {
+    while (rr > target && it < max_iter) {
       __syncthreads();   // p complete before the operator reads it
       op_apply<PT, false>(v, rho_hat, p, t, Mp, b, b + 1, all, all, bar);
       T pMp = 0, dummy = 0;
@@ -372,12 +411,12 @@ __global__ void k_bar_reset(uint32_t *words) {
 }
 
 // Per-instance state of the cooperative solve (caller workspace, 16 (B + 1)
-// + 256 elements of T): the three barrier words (768 bytes), then rz, rr [B]
-// in T, thr, rrt [B] in float64, then int32 it, act, done, fail [B] and two
-// counters.
+// + 256 elements of T): the three barrier words (768 bytes), then rz, rr,
+// tgt [B] in T, thr, rrt, rrt_prev [B] in float64, then int32 it, act, done,
+// fail [B] and two counters.
 template <typename T> struct CoopState {
-  T *rz, *rr;
-  double *thr, *rrt;
+  T *rz, *rr, *tgt;
+  double *thr, *rrt, *rrt_prev;
   int32_t *it, *act, *done, *fail, *cnt;
 };
 
@@ -388,10 +427,12 @@ template <typename T> __device__ inline CoopState<T> coop_state(void *ws, int B)
   char *base = static_cast<char *>(ws) + BAR_BYTES;
   c.rz = reinterpret_cast<T *>(base);
   c.rr = c.rz + B;
-  const size_t dbl = (2 * (size_t)B * sizeof(T) + 7) / 8 * 8;   // 8-byte aligned (the workspace is 256-aligned)
+  c.tgt = c.rr + B;
+  const size_t dbl = (3 * (size_t)B * sizeof(T) + 7) / 8 * 8;   // 8-byte aligned (the workspace is 256-aligned)
   c.thr = reinterpret_cast<double *>(base + dbl);
   c.rrt = c.thr + B;
-  int32_t *i = reinterpret_cast<int32_t *>(c.rrt + B);
+  c.rrt_prev = c.rrt + B;
+  int32_t *i = reinterpret_cast<int32_t *>(c.rrt_prev + B);
   c.it = i;
   c.act = i + B;
   c.done = i + 2 * B;
@@ -402,7 +443,7 @@ template <typename T> __device__ inline CoopState<T> coop_state(void *ws, int B)
 
 template <typename T>
 __global__ __launch_bounds__(CT) void k_pcg_coop(View<T> v, const T *__restrict__ rho_hat, const T *__restrict__ dg,
-                                                 const T *__restrict__ rhs, T *__restrict__ x, T *__restrict__ r,
+                                                 const double *__restrict__ rhs, T *__restrict__ x, T *__restrict__ r,
                                                  T *__restrict__ z, T *__restrict__ p, T *__restrict__ Mp,
                                                  T *__restrict__ t, double *__restrict__ t64, T tol,
                                                  int32_t max_iter, const T *__restrict__ alpha_k,
@@ -441,7 +482,7 @@ __global__ __launch_bounds__(CT) void k_pcg_coop(View<T> v, const T *__restrict_
   if (blockIdx.x == 0 && threadIdx.x < 2) cs.cnt[threadIdx.x] = 0;
   for (int b = blockIdx.x; b < v.B; b += gridDim.x) {
     double bb = 0, dd = 0;
-    for (int64_t j = v.n_off[b] + threadIdx.x; j < v.n_off[b + 1]; j += CT) bb += (double)rhs[j] * (double)rhs[j];
+    for (int64_t j = v.n_off[b] + threadIdx.x; j < v.n_off[b + 1]; j += CT) bb += rhs[j] * rhs[j];
     wg_sum2<CT>(bb, dd, redd);
     if (threadIdx.x == 0) {
       cs.thr[b] = (double)tol * (double)tol * bb;
@@ -471,13 +512,17 @@ __global__ __launch_bounds__(CT) void k_pcg_coop(View<T> v, const T *__restrict_
       wg_sum2<CT>(rrt, dd, redd);
       if (threadIdx.x == 0) {
         const bool fail = cs.fail[b] || !isfinite(rrt);
-        const bool done = fail || rrt <= cs.thr[b] || cs.it[b] >= max_iter || restart > NRESTART;
+        const bool stalled = restart > 0 && rrt > STALL2 * cs.rrt_prev[b];
+        const bool done = fail || rrt <= cs.thr[b] || cs.it[b] >= max_iter || restart > NRESTART || stalled;
+        const T tgt = (T)(restart == 0 ? cs.thr[b] : fmax(cs.thr[b], ROUND_DROP2 * (double)rr));
         cs.rz[b] = rz;
         cs.rr[b] = rr;
+        cs.tgt[b] = tgt;
         cs.rrt[b] = rrt;
+        cs.rrt_prev[b] = rrt;
         cs.fail[b] = fail;
         cs.done[b] = done;
-        cs.act[b] = !done && rr > (T)cs.thr[b];
+        cs.act[b] = !done && rr > tgt;
         if (!done) atomicAdd(&cs.cnt[cur], 1);
       }
     }
@@ -513,7 +558,7 @@ __global__ __launch_bounds__(CT) void k_pcg_coop(View<T> v, const T *__restrict_
           const T beta = rz_new / rz;
           for (int64_t j = n0 + threadIdx.x; j < n1; j += CT) p[j] = z[j] + beta * p[j];
           fail = !isfinite(rr_new);
-          act = !fail && rr_new > (T)cs.thr[b] && cs.it[b] + 1 < max_iter;
+          act = !fail && rr_new > cs.tgt[b] && cs.it[b] + 1 < max_iter;
         }
         __syncthreads();   // every thread has read the scalars before they change
         if (threadIdx.x == 0) {
@@ -562,7 +607,7 @@ int pcg_coop_grid(int per_cu) {
 }
 
 template <typename T>
-void launch_pcg(const View<T> &v, const T *rho_hat, const T *dg, const T *rhs, T *x, T *r, T *z, T *p, T *Mp, T *t,
+void launch_pcg(const View<T> &v, const T *rho_hat, const T *dg, const double *rhs, T *x, T *r, T *z, T *p, T *Mp, T *t,
                 double *t64, double tol, int32_t max_iter, const T *alpha_k, const T *xold, T *xnew,
                 const T *gx_in, T *gx_out, int32_t mode, cosmo_stats *stats, void *state, int32_t form,
                 hipStream_t st) {
@@ -586,7 +631,7 @@ void launch_pcg(const View<T> &v, const T *rho_hat, const T *dg, const T *rhs, T
                                gx_in, gx_out, mode, stats);
 }
 
-template void launch_pcg<float>(const View<float> &, const float *, const float *, const float *, float *, float *,
+template void launch_pcg<float>(const View<float> &, const float *, const float *, const double *, float *, float *,
                                 float *, float *, float *, float *, double *, double, int32_t, const float *,
                                 const float *, float *, const float *, float *, int32_t, cosmo_stats *, void *,
                                 int32_t, hipStream_t);

@@ -129,7 +129,7 @@ template <typename T>
 __global__ __launch_bounds__(NT) void k_cols_pre(View<T> v, BucketArgs ba, const T *__restrict__ rho_hat,
                                                  const T *__restrict__ x, const T *__restrict__ s,
                                                  const T *__restrict__ y, T *__restrict__ dg,
-                                                 T *__restrict__ xi, DiagSolve<T> ds) {
+                                                 double *__restrict__ xi, DiagSolve<T> ds) {
   BUCKET_PREAMBLE
   const int64_t j = bp.row;
   double a_xi = 0, a_d = 0;
@@ -144,11 +144,11 @@ __global__ __launch_bounds__(NT) void k_cols_pre(View<T> v, BucketArgs ba, const
   a_d = subwave_sum(a_d, bp.L);
   if (bp.lane == 0) {
     const T d = (T)((double)v.Pdiag[j] + (double)v.sigma + a_d);
-    const T r = (T)((double)v.sigma * (double)x[j] - (double)v.q[j] + a_xi);
+    const double r = (double)v.sigma * (double)x[j] - (double)v.q[j] + a_xi;
     dg[j] = d;
-    xi[j] = r;
+    xi[j] = r;   // kept in float64: the solve's right-hand side is not rounded
     if (ds.xt) {
-      const T xt = r / d;
+      const T xt = (T)(r / (double)d);
       const T al = ds.alpha_k[v.col_inst[j]];
       ds.xt[j] = xt;
       ds.xn[j] = al * xt + ((T)1 - al) * x[j];
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(NT) void k_bwd_rows_b(View<T> v, const T *__restric
 template <typename T>
 __global__ __launch_bounds__(NT) void k_bwd_cols(View<T> v, BucketArgs ba, const T *__restrict__ rho_hat,
                                                  const T *__restrict__ alpha_k, const T *__restrict__ gst,
-                                                 const T *__restrict__ gx_in, T *__restrict__ gxt,
+                                                 const T *__restrict__ gx_in, double *__restrict__ gxt,
                                                  T *__restrict__ dg, DiagSolve<T> ds) {
   BUCKET_PREAMBLE
   const int64_t j = bp.row;
@@ -273,12 +273,12 @@ __global__ __launch_bounds__(NT) void k_bwd_cols(View<T> v, BucketArgs ba, const
   a_d = subwave_sum(a_d, bp.L);
   if (bp.lane == 0) {
     const T al = alpha_k[v.col_inst[j]];
-    const T r = (T)((double)al * (double)gx_in[j] - acc);
+    const double r = (double)al * (double)gx_in[j] - acc;
     const T d = (T)((double)v.Pdiag[j] + (double)v.sigma + a_d);
     gxt[j] = r;
     dg[j] = d;
     if (ds.xt) {
-      const T w = r / d;
+      const T w = (T)(r / (double)d);
       ds.xt[j] = w;
       ds.xn[j] = ((T)1 - al) * gx_in[j] + v.sigma * w;
     }
@@ -461,7 +461,7 @@ void launch_rect_adjoint(const View<T> &v, const RectDesc *rect, int32_t nrect, 
 
 template <typename T>
 void launch_cols_pre(const View<T> &v, const RowBuckets &bk, const T *rho_hat, const T *x, const T *s, const T *y,
-                     T *dg, T *xi, DiagSolve<T> ds, hipStream_t st) {
+                     T *dg, double *xi, DiagSolve<T> ds, hipStream_t st) {
   BucketArgs a = make_bucket_args(bk);
   if (nblocks_bucket(a) > 0)
     k_cols_pre<T><<<(int)nblocks_bucket(a), NT, 0, st>>>(v, a, rho_hat, x, s, y, dg, xi, ds);
@@ -499,7 +499,7 @@ void launch_bwd_rows_b(const View<T> &v, const T *rho_hat, const T *alpha_k, con
 
 template <typename T>
 void launch_bwd_cols(const View<T> &v, const RowBuckets &bk, const T *rho_hat, const T *alpha_k, const T *gst,
-                     const T *gx_in, T *gxt, T *dg, DiagSolve<T> ds, hipStream_t st) {
+                     const T *gx_in, double *gxt, T *dg, DiagSolve<T> ds, hipStream_t st) {
   BucketArgs a = make_bucket_args(bk);
   if (nblocks_bucket(a) > 0)
     k_bwd_cols<T><<<(int)nblocks_bucket(a), NT, 0, st>>>(v, a, rho_hat, alpha_k, gst, gx_in, gxt, dg, ds);
@@ -549,7 +549,7 @@ void launch_nonfinite_check(const View<T> &v, const T *x, const T *s, const T *y
                                   hipStream_t);                                                                 \
   template void launch_rect_adjoint<T>(const View<T> &, const RectDesc *, int32_t, const T *, T *, hipStream_t); \
   template void launch_cols_pre<T>(const View<T> &, const RowBuckets &, const T *, const T *, const T *,        \
-                                   const T *, T *, T *, DiagSolve<T>, hipStream_t);                             \
+                                   const T *, T *, double *, DiagSolve<T>, hipStream_t);                        \
   template void launch_rows_post<T>(const View<T> &, const RowBuckets &, const T *, const T *, const T *,       \
                                     const T *, const T *, T *, T *, T *, T *, T *, hipStream_t);                \
   template void launch_bwd_rows_a<T>(const View<T> &, const T *, const T *, const T *, const T *, const T *,    \
@@ -559,7 +559,7 @@ void launch_nonfinite_check(const View<T> &v, const T *x, const T *s, const T *y
   template void launch_bwd_rows_b<T>(const View<T> &, const T *, const T *, const T *, const T *, const T *,    \
                                      const T *, const T *, const T *, T *, T *, T *, T *, T *, hipStream_t);    \
   template void launch_bwd_cols<T>(const View<T> &, const RowBuckets &, const T *, const T *, const T *,        \
-                                   const T *, T *, T *, DiagSolve<T>, hipStream_t);                             \
+                                   const T *, double *, T *, DiagSolve<T>, hipStream_t);                             \
   template void launch_bwd_rows_c<T>(const View<T> &, const RowBuckets &, const T *, const T *, const T *,      \
                                      const T *, T *, T *, T *, hipStream_t);                                    \
   template void launch_alpha_reduce<T>(const View<T> &, const T *, const T *, const T *, const T *, const T *,  \

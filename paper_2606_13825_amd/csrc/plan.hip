@@ -233,6 +233,8 @@ cosmo_status validate_problem_host(const cosmo_problem *p, const cosmo_options *
   if (n_tot < 1) FAIL(COSMO_EINVAL, "no variables");
   if (n_tot > INT32_MAX || m_tot > INT32_MAX) FAIL(COSMO_EUNSUPPORTED, "n_tot and m_tot must fit in int32");
   if (!p->A_rowptr || !p->A_col || !p->A_val) FAIL(COSMO_EINVAL, "A arrays must be non-NULL");
+  if ((reinterpret_cast<uintptr_t>(p->A_col) | reinterpret_cast<uintptr_t>(p->A_val)) % 16 != 0)
+    FAIL(COSMO_EINVAL, "A_col and A_val must be 16-byte aligned");
   if (p->A_nnz < 0) FAIL(COSMO_EINVAL, "A_nnz < 0");
   if (p->P_nnz < 0) FAIL(COSMO_EINVAL, "P_nnz < 0");
   if (p->P_nnz > 0 && (!p->P_rowptr || !p->P_col || !p->P_val)) FAIL(COSMO_EINVAL, "P arrays must be non-NULL");
@@ -491,7 +493,7 @@ void build_layouts(cosmo_plan *pl) {
   auto &f = pl->fw;
   f.rho_hat = take(K * m);
   f.dg = take(n);
-  f.xi = take(n);
+  f.xi = take(n * 8 / pl->esz);           // right-hand side of the solve, float64
   f.r = take(n);
   f.z = take(n);
   f.p = take(n);
@@ -532,7 +534,7 @@ void build_layouts(cosmo_plan *pl) {
   w.gsh = take(m);
   w.gst = take(m);
   w.grh = take(m);
-  w.gxt = take(n);
+  w.gxt = take(n * 8 / pl->esz);          // right-hand side of the adjoint solve, float64
   w.w = take(n);
   w.dg = take(n);
   w.r = take(n);
@@ -636,11 +638,11 @@ cosmo_status forward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T 
     }
     {
       ProfScope ps(pl, 3, st);
-      launch_cols_pre<T>(v, pl->bkAt, rh, x, s, y, ws + f.dg, ws + f.xi, ds, st);
+      launch_cols_pre<T>(v, pl->bkAt, rh, x, s, y, ws + f.dg, reinterpret_cast<double *>(ws + f.xi), ds, st);
     }
     if (!pl->diag_M) {
       ProfScope ps(pl, 2, st);
-      launch_pcg<T>(v, rh, ws + f.dg, ws + f.xi, xt, ws + f.r, ws + f.z, ws + f.p, ws + f.Mp, ws + f.t,
+      launch_pcg<T>(v, rh, ws + f.dg, reinterpret_cast<const double *>(ws + f.xi), xt, ws + f.r, ws + f.z, ws + f.p, ws + f.Mp, ws + f.t,
                     reinterpret_cast<double *>(ws + f.t64), pl->opt.cg_tol, pl->opt.cg_max_iter, al, x, xn, nullptr, nullptr, 0, stats, ws + f.cg, pl->pcg_form, st);
     }
     {
@@ -710,11 +712,11 @@ cosmo_status backward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T
         ds.xn = gx_out;
         ds.alpha_k = al;
       }
-      launch_bwd_cols<T>(v, pl->bkAt, rh, al, ws + w.gst, gx_in, ws + w.gxt, ws + w.dg, ds, st);
+      launch_bwd_cols<T>(v, pl->bkAt, rh, al, ws + w.gst, gx_in, reinterpret_cast<double *>(ws + w.gxt), ws + w.dg, ds, st);
     }
     if (!pl->diag_M) {
       ProfScope ps(pl, 2, st);
-      launch_pcg<T>(v, rh, ws + w.dg, ws + w.gxt, ws + w.w, ws + w.r, ws + w.z, ws + w.p, ws + w.Mp, ws + w.t,
+      launch_pcg<T>(v, rh, ws + w.dg, reinterpret_cast<const double *>(ws + w.gxt), ws + w.w, ws + w.r, ws + w.z, ws + w.p, ws + w.Mp, ws + w.t,
                     reinterpret_cast<double *>(ws + w.t64), pl->opt.cg_tol, pl->opt.cg_max_iter, al, nullptr, nullptr, gx_in, gx_out, 1, stats, ws + w.cg,
                     pl->pcg_form, st);
     }

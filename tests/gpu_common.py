@@ -57,12 +57,13 @@ def oracle_run(inst, rho_k_m, alpha_k, with_grad=True, x0=None, s0=None, y0=None
 
 def one_step_err(inst, z, z_next, rho_k, alpha_k, fl, tol=1e-5):
     """The float64 oracle's step from the GPU's iterate z = (x, s, y) against
-    the GPU's next iterate, per array, at `tol` relative.  The bar has one floor
-    no float32 pipeline avoids: the right-hand side xi is a float32 vector, and
-    rounding it once moves the exact solve by M^-1 (fl32(xi) - xi); the step is
-    allowed 8 such roundings, carried through to s and y (the projection is
-    nonexpansive, y+ adds rho (s^ - s+)).  Returns (worst error, number of
-    arrays where the floor decided)."""
+    the GPU's next iterate, per array, at `tol` relative, with one floor: the
+    step may carry the effect of 8 float32 roundings of the right-hand side xi
+    through the solve, M^-1 (fl32(xi) - xi), and on to s and y (the
+    projection is nonexpansive, y+ adds rho (s^ - s+)).  The library keeps xi
+    in float64; the floor stands in for the float32 rounding of the stored
+    per-step values (s~, s^, v), which reach the next iterate the same way.
+    Returns (worst error, number of arrays where the floor decided)."""
     x, s, y = z
     st = oracle.step_forward(inst, x, s, y, np.asarray(rho_k, np.float64), float(alpha_k))
     dxt = st["lu"].solve(st["xi"].astype(np.float32).astype(np.float64) - st["xi"])

@@ -43,7 +43,7 @@ def test_status_strings_and_version(L):
     assert b"EINVAL" in lib.cosmo_status_string(L.COSMO_EINVAL)
 
 
-def _problem(L, B=1, n_off=(0, 3), m_off=(0, 4), kinds=(0, 1), sizes=(1, 3)):
+def _problem(L, B=1, n_off=(0, 3), m_off=(0, 4), kinds=(0, 1), sizes=(1, 3), a_val=16):
     n_off = np.asarray(n_off, np.int64)
     m_off = np.asarray(m_off, np.int64)
     kinds = np.asarray(kinds, np.int32)
@@ -53,7 +53,8 @@ def _problem(L, B=1, n_off=(0, 3), m_off=(0, 4), kinds=(0, 1), sizes=(1, 3)):
     p.n_off = n_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
     p.m_off = m_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
     # non-NULL stand-ins: validation rejects the layout before any device access
-    p.A_rowptr = p.A_col = p.A_val = p.q = p.b = 16
+    p.A_rowptr = p.A_col = p.q = p.b = 16
+    p.A_val = a_val
     p.A_nnz = 4
     p.P_nnz = 0
     p.n_cones = len(kinds)
@@ -80,6 +81,7 @@ def _options(L, **kw):
     dict(kinds=(0, 7), sizes=(1, 3)),            # unknown cone kind
     dict(kinds=(0, 3), sizes=(1, 0)),            # empty cone
     dict(B=2, n_off=(0, 2, 3), m_off=(0, 2, 4), kinds=(0, 1), sizes=(3, 1)),   # straddles instances
+    dict(a_val=20),                              # A_val not 16-byte aligned
 ])
 def test_invalid_problem_rejected_on_host(L, case):
     p, keep = _problem(L, **case)

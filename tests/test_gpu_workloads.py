@@ -14,6 +14,11 @@ from gpu_common import assert_close, ensure_lib, floor_of, one_step_err, oracle_
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
+# The Lovasz systems have cond(M) ~ 1e3 p (the trace row), so a relative
+# residual of 1e-8 admits solve errors near 1e-3 against the exact solve;
+# float32 runs of this family solve to 1e-10 (the CG then stops at the
+# float32 floor of the true residual), as the benchmark's Lovasz workload does.
+LOVASZ_CG_TOL = 1e-10
 
 
 def _hyper(insts, K, seed, spread=0.5, dtype=np.float32):
@@ -94,7 +99,7 @@ def test_lovasz_circulant_reduced_fp32_short():
     K = 4
     rhos, alphas = _hyper(insts, K, 32)
     say(f"Lovasz circulant fp32 B=4 orders={[i.meta['order'] for i in insts]} K={K}")
-    _run_and_check(insts, K, rhos, alphas, range(4), 5e-5, 1e-4)
+    _run_and_check(insts, K, rhos, alphas, range(4), 5e-5, 1e-4, cg_tol=LOVASZ_CG_TOL)
 
 
 def test_lovasz_circulant_fp32_one_step_parity():
@@ -104,18 +109,16 @@ def test_lovasz_circulant_fp32_one_step_parity():
     so end-to-end float32 agreement is limited by the problem, not the
     kernels.  What the kernels control is every single step: the float64
     oracle, started from the GPU's own iterate z^k, must reproduce the GPU's
-    z^(k+1) at the float32 bar, for every k.  The bar has one floor that no
-    float32 pipeline avoids: the right-hand side xi is a float32 vector, and
-    rounding it once moves the exact solve by M^-1 (fl32(xi) - xi), which the
-    ill-conditioned M of these instances (cond ~ 1e3 p) can amplify past
-    1e-5; the step is allowed 8 such roundings, carried through to s and y
-    (the projection is nonexpansive, y+ adds rho (s^ - s+))."""
+    z^(k+1) at the float32 bar, for every k, with the floor of one_step_err
+    (8 float32 roundings of xi carried through the solve; the library keeps
+    xi in float64, so the floor only stands in for the float32 rounding of
+    the stored per-step values)."""
     ensure_lib()
     from paper_2606_13825_amd import CosmoBatch
     insts = _lovasz_reduced(np.float32)
     K = 20
     rhos, alphas = _hyper(insts, K, 32)
-    batch = CosmoBatch(insts, K=K, dtype=torch.float32, device=DEV)
+    batch = CosmoBatch(insts, K=K, dtype=torch.float32, device=DEV, cg_tol=LOVASZ_CG_TOL)
     rho = torch.from_numpy(np.concatenate(rhos, axis=1)).to(DEV)
     alpha = torch.from_numpy(np.stack(alphas, axis=1)).to(DEV)
     fw = batch.forward(rho, alpha)
@@ -139,7 +142,7 @@ def test_lovasz_circulant_large_orders():
     K = 6
     rhos, alphas = _hyper(insts, K, 34)
     say(f"Lovasz circulant B=2 orders={[i.meta['order'] for i in insts]} K={K}")
-    _run_and_check(insts, K, rhos, alphas, range(2), 2e-5, 2e-4)
+    _run_and_check(insts, K, rhos, alphas, range(2), 2e-5, 2e-4, cg_tol=LOVASZ_CG_TOL)
 
 
 @pytest.mark.parametrize("form", [0, 1, 2])
