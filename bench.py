@@ -51,6 +51,8 @@ EIG_KERNEL_NAMES = {0: "k_psd_eig<float,64,4,32> (orders <= 32)", 1: "k_psd_eig<
                     3: "k_psd_eig<float,1024,8,200> (orders 129-200)"}
 EIG_PROFILE = os.path.join(ROOT, "profiles", "k_psd_eig_maxcut64_pmc.md")
 EIG_SOURCE = os.path.join(ROOT, "paper_2606_13825_amd", "csrc", "k_psd.hip")
+PCG_PROFILE = os.path.join(ROOT, "profiles", "k_pcg_huber256_pmc.md")
+PCG_SOURCE = os.path.join(ROOT, "paper_2606_13825_amd", "csrc", "k_pcg.hip")
 
 
 def psd_order_class(orders):
@@ -58,21 +60,22 @@ def psd_order_class(orders):
     return np.where(o <= 32, 0, np.where(o <= 64, 1, np.where(o <= 128, 2, 3)))
 
 
-def traffic_from_profile(cls):
-    """HBM bytes per dispatch of the class's eigensolve kernel, from the
-    committed counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the same
-    counters on a copy kernel of known size); None when there is none for this
-    class or the kernel source has changed since the counters were taken."""
+def traffic_from_profile(profile, source, **match):
+    """HBM bytes per dispatch of a kernel, from a committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a copy kernel of
+    known size); None when there is none, when its keys (order class, CG
+    form) differ from `match`, or when the kernel source has changed since the
+    counters were taken."""
     try:
         kv = {}
-        with open(EIG_PROFILE) as f:
+        with open(profile) as f:
             for line in f:
                 if ":" in line and line[:1].isalpha():
                     k, v = line.split(":", 1)
                     kv[k.strip()] = v.strip()
-        with open(EIG_SOURCE, "rb") as f:
+        with open(source, "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
-        if kv.get("source_sha256") != sha or int(kv.get("order_class", -1)) != int(cls):
+        if kv.get("source_sha256") != sha or any(int(kv.get(k, -1)) != int(v) for k, v in match.items()):
             return None
         return float(kv["traffic_bytes_per_dispatch"])
     except (OSError, KeyError, ValueError):
@@ -177,6 +180,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--cpu-sample", type=int, default=None, help="instances in the oracle sample")
+    ap.add_argument("--schedule", default="auto", choices=["auto", "eager0"],
+                    help="auto: the autotuner's choice; eager0: CG form 0, eager launches")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain (unbatched forward-only) comparison")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -255,10 +260,16 @@ def main():
         return fw, loss, bw
 
     # the project's autotuner fixes the schedule (CG form, graph replay or
-    # eager launches) before anything is timed
-    form, ms = batch.autotune(rho, alpha, fws)
-    sched = {"pcg_form": form, "graph": batch.graph(),
-             "autotune_forward_ms": dict(zip(("form0", "form1", "form2", "form0_graph"), ms))}
+    # eager launches) before anything is timed; --schedule eager0 pins CG form
+    # 0 with eager launches (the form the counter summaries were taken with)
+    if args.schedule == "auto":
+        form, ms = batch.autotune(rho, alpha, fws)
+        sched = {"pcg_form": form, "graph": batch.graph(),
+                 "autotune_forward_ms": dict(zip(("form0", "form1", "form2", "form0_graph"), ms))}
+    else:
+        batch.set_graph(False)
+        batch.set_pcg_form(0)
+        sched = {"pcg_form": 0, "graph": False, "autotune_forward_ms": None}
     print(f"[bench] autotune: {sched}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
@@ -310,22 +321,30 @@ def main():
         name = EIG_KERNEL_NAMES[dom] if wl["dtype"] == "f32" else EIG_KERNEL_NAMES[dom].replace("float", "double")
         rooflines["eig"] = {"kernel": name, "bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
                             "frac": ach / peak,
-                            "traffic": traffic_from_profile(dom) if args.workload == "c2" else None,
+                            "traffic": (traffic_from_profile(EIG_PROFILE, EIG_SOURCE, order_class=dom)
+                                        if args.workload == "c2" else None),
                             "flops_per_launch": flops, "blocks_per_launch": int(np.sum(cls_of == dom)),
                             "avg_launch_ms": avg_ms, "launches": n_dom}
     n_pcg, ms_pcg = fam["pcg"]
     if n_pcg > 0:
         esz = 4 if wl["dtype"] == "f32" else 8
         iters = sprof["cg_iters_total"].astype(np.float64)
-        # each launch solves every instance once: (iterations + 1) operator applications
-        total = sum((iters[i] + n_pcg) * pcg_bytes_per_iteration(inst, esz) for i, inst in enumerate(insts))
+        passes = sprof["cg_passes_total"].astype(np.float64)
+        # operator applications: one per iteration and one per float64 true-residual pass
+        total = sum((iters[i] + passes[i]) * pcg_bytes_per_iteration(inst, esz) for i, inst in enumerate(insts))
         avg_ms = ms_pcg / n_pcg
         ach = total / n_pcg / (avg_ms * 1e-3) / 1e9
-        rooflines["pcg"] = {"kernel": "k_pcg<%s> (one workgroup per instance)" % ("float" if esz == 4 else "double"),
-                            "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                            "frac": ach / PEAK_HBM_GBS, "traffic": None, "bytes_per_launch": total / n_pcg,
-                            "avg_launch_ms": avg_ms, "launches": n_pcg,
-                            "mean_cg_iterations": float(iters.sum() / (n_pcg * B))}
+        form = batch.pcg_form()
+        tn = "float" if esz == 4 else "double"
+        kname = (f"k_pcg_coop<{tn}> (cooperative, <= {form} workgroups per CU)" if form > 0
+                 else f"k_pcg<{tn}> (one workgroup per instance)")
+        rooflines["pcg"] = {"kernel": kname, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                            "frac": ach / PEAK_HBM_GBS,
+                            "traffic": (traffic_from_profile(PCG_PROFILE, PCG_SOURCE, pcg_form=form)
+                                        if args.workload == "c4" else None),
+                            "bytes_per_launch": total / n_pcg, "avg_launch_ms": avg_ms, "launches": n_pcg,
+                            "mean_cg_iterations": float(iters.sum() / (n_pcg * B)),
+                            "mean_residual_passes": float(passes.sum() / (n_pcg * B))}
     primary = wl["roofline"] if wl["roofline"] in rooflines else next(iter(rooflines), None)
 
     plain = None

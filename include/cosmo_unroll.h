@@ -125,7 +125,8 @@ typedef struct {
  * 2^31). */
 typedef struct {
   int32_t cg_iters_max;        /* largest PCG iteration count of any solve             */
-  int32_t cg_not_converged;    /* number of solves that hit cg_max_iter                */
+  int32_t cg_not_converged;    /* solves that ended with the true residual above tol
+                                  (iteration cap, or the working precision's floor)     */
   int32_t eig_sweeps_max;      /* largest Jacobi sweep count of any PSD block          */
   int32_t eig_not_converged;   /* PSD eigensolves that hit eig_max_sweeps              */
   int32_t nonfinite;           /* 1 if a non-finite value reached the iterate          */
@@ -133,6 +134,8 @@ typedef struct {
   int32_t eig_solves;          /* PSD block eigensolves (eig_sweeps_total / eig_solves
                                   is the mean sweep count)                              */
   int32_t cg_iters_total;      /* PCG iterations summed over the solves                */
+  int32_t cg_passes_total;     /* float64 true-residual passes summed over the solves
+                                  (each is one more operator application)               */
 } cosmo_stats;
 
 const char *cosmo_status_string(cosmo_status s);

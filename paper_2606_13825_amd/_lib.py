@@ -65,12 +65,14 @@ class CosmoStats(ctypes.Structure):
     _fields_ = [("cg_iters_max", ctypes.c_int32), ("cg_not_converged", ctypes.c_int32),
                 ("eig_sweeps_max", ctypes.c_int32), ("eig_not_converged", ctypes.c_int32),
                 ("nonfinite", ctypes.c_int32), ("eig_sweeps_total", ctypes.c_int32),
-                ("eig_solves", ctypes.c_int32), ("cg_iters_total", ctypes.c_int32)]
+                ("eig_solves", ctypes.c_int32), ("cg_iters_total", ctypes.c_int32),
+                ("cg_passes_total", ctypes.c_int32)]
 
 
 STATS_FIELDS = ["cg_iters_max", "cg_not_converged", "eig_sweeps_max", "eig_not_converged", "nonfinite",
-                "eig_sweeps_total", "eig_solves", "cg_iters_total"]
-STATS_INTS = 8
+                "eig_sweeps_total", "eig_solves", "cg_iters_total",
+                "cg_passes_total"]
+STATS_INTS = len(STATS_FIELDS)
 
 _lib = None
 

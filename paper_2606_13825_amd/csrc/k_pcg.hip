@@ -260,7 +260,7 @@ __device__ inline void op_residual64(const View<T> &v, const T *__restrict__ rho
 
 // Epilogue shared by both forms, over instance b's columns.
 template <int NTH, typename T>
-__device__ inline void finish(const View<T> &v, int b, bool fail, int it, double rrt, double thr, T *x,
+__device__ inline void finish(const View<T> &v, int b, bool fail, int it, int passes, double rrt, double thr, T *x,
                               const T *alpha_k, const T *xold, T *xnew, const T *gx_in, T *gx_out, int32_t mode,
                               cosmo_stats *stats) {
   const int64_t n0 = v.n_off[b], n1 = v.n_off[b + 1];
@@ -276,6 +276,7 @@ __device__ inline void finish(const View<T> &v, int b, bool fail, int it, double
   if (stats && threadIdx.x == 0) {
     atomicMax(&stats[b].cg_iters_max, it);
     atomicAdd(&stats[b].cg_iters_total, it);
+    atomicAdd(&stats[b].cg_passes_total, passes);
     if (!(rrt <= thr)) atomicAdd(&stats[b].cg_not_converged, 1);
   }
 }
@@ -302,11 +303,12 @@ __global__ __launch_bounds__(PT) void k_pcg(View<T> v, const T *__restrict__ rho
   wg_sum2<PT>(bb, dd, redd);
   const double thr = (double)tol * (double)tol * bb;
   bool fail = !isfinite(bb);
-  int it = 0;
+  int it = 0, passes = 0;
   double rrt = 0, rrt_prev = 0;
   for (int restart = 0;; ++restart) {
     // true residual, z = r / diag M, p = z
     op_residual64<PT, false>(v, rho_hat, rhs, x, t64, r, b, b + 1, all, all, bar);
+    ++passes;
     T rz = 0, rr = 0;
     rrt = 0;
     for (int64_t j = n0 + threadIdx.x; j < n1; j += PT) {
@@ -362,7 +364,7 @@ __global__ __launch_bounds__(PT) void k_pcg(View<T> v, const T *__restrict__ rho
     __syncthreads();   // x complete before the residual reads it
   }
   __syncthreads();
-  finish<PT>(v, b, fail, it, rrt, thr, x, alpha_k, xold, xnew, gx_in, gx_out, mode, stats);
+  finish<PT>(v, b, fail, it, passes, rrt, thr, x, alpha_k, xold, xnew, gx_in, gx_out, mode, stats);
 }
 
 // ---- cooperative form ------------------------------------------------------------
@@ -413,11 +415,11 @@ __global__ void k_bar_reset(uint32_t *words) {
 // Per-instance state of the cooperative solve (caller workspace, 16 (B + 1)
 // + 256 elements of T): the three barrier words (768 bytes), then rz, rr,
 // tgt [B] in T, thr, rrt, rrt_prev [B] in float64, then int32 it, act, done,
-// fail [B] and two counters.
+// fail, passes [B] and two counters.
 template <typename T> struct CoopState {
   T *rz, *rr, *tgt;
   double *thr, *rrt, *rrt_prev;
-  int32_t *it, *act, *done, *fail, *cnt;
+  int32_t *it, *act, *done, *fail, *passes, *cnt;
 };
 
 constexpr size_t BAR_BYTES = 768;
@@ -437,7 +439,8 @@ template <typename T> __device__ inline CoopState<T> coop_state(void *ws, int B)
   c.act = i + B;
   c.done = i + 2 * B;
   c.fail = i + 3 * B;
-  c.cnt = i + 4 * B;
+  c.passes = i + 4 * B;
+  c.cnt = i + 5 * B;
   return c;
 }
 
@@ -478,6 +481,7 @@ __global__ __launch_bounds__(CT) void k_pcg_coop(View<T> v, const T *__restrict_
     cs.done[b] = 0;
     cs.act[b] = 0;
     cs.it[b] = 0;
+    cs.passes[b] = 0;
   }
   if (blockIdx.x == 0 && threadIdx.x < 2) cs.cnt[threadIdx.x] = 0;
   for (int b = blockIdx.x; b < v.B; b += gridDim.x) {
@@ -520,6 +524,7 @@ __global__ __launch_bounds__(CT) void k_pcg_coop(View<T> v, const T *__restrict_
         cs.tgt[b] = tgt;
         cs.rrt[b] = rrt;
         cs.rrt_prev[b] = rrt;
+        cs.passes[b] += 1;
         cs.fail[b] = fail;
         cs.done[b] = done;
         cs.act[b] = !done && rr > tgt;
@@ -582,7 +587,7 @@ __global__ __launch_bounds__(CT) void k_pcg_coop(View<T> v, const T *__restrict_
   // after an abort the solutions are marked non-finite (the state of the
   // instances is not trusted)
   for (int b = blockIdx.x; b < v.B; b += gridDim.x)
-    finish<CT>(v, b, aborted || cs.fail[b] != 0, cs.it[b], cs.rrt[b], cs.thr[b], x, alpha_k, xold, xnew, gx_in,
+    finish<CT>(v, b, aborted || cs.fail[b] != 0, cs.it[b], cs.passes[b], cs.rrt[b], cs.thr[b], x, alpha_k, xold, xnew, gx_in,
                gx_out, mode, stats);
 }
 

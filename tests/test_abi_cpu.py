@@ -37,6 +37,17 @@ def test_every_declared_symbol_is_exported(L):
     assert sorted(L.EXPORTED) == declared
 
 
+def test_stats_struct_matches_header(L):
+    """The per-instance counter block the kernels write has the header's
+    layout: one int32 per field, in the same order."""
+    import re
+    hdr = open(os.path.join(ROOT, "include", "cosmo_unroll.h")).read()
+    body = re.search(r"typedef struct \{([^}]*)\} cosmo_stats;", hdr).group(1)
+    fields = re.findall(r"int32_t\s+(\w+);", body)
+    assert fields == L.STATS_FIELDS
+    assert ctypes.sizeof(L.CosmoStats) == 4 * len(fields) == 4 * L.STATS_INTS
+
+
 def test_status_strings_and_version(L):
     lib = L.lib()
     assert lib.cosmo_abi_version() == 1
