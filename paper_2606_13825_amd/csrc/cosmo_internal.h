@@ -37,10 +37,18 @@ struct RectDesc {     // a block whose penalty is averaged (SOC or PSD)
   int32_t pad;
 };
 
+// Entry range [kb, k1) of one row, listed beside the bucket lists so a row's
+// range is one 16-byte load rather than a load of the row id and then two of
+// the row pointer.
+struct alignas(16) RowSpan {
+  int64_t kb, k1;
+};
+
 // Rows (or columns) of a CSR matrix grouped into three length classes so a
 // sub-wave of L lanes serves one row with coalesced loads.
 struct RowBuckets {
   int32_t *d_rows = nullptr;   // concatenated row ids of the three classes
+  RowSpan *d_span = nullptr;   // entry range of each listed row
   int64_t begin[4] = {0, 0, 0, 0};
   int32_t lanes[3] = {1, 8, 64};
 };
@@ -68,6 +76,7 @@ template <typename T> struct View {
   // per instance b and row-length class c (1, 8, 64 lanes per row): its rows
   // of A (columns of A for At) are rowsA[instA[c (B+1) + b] .. instA[c (B+1) + b + 1])
   const int32_t *rowsA; const int32_t *rowsAt;
+  const RowSpan *spanA; const RowSpan *spanAt;   // entry ranges, aligned with rowsA / rowsAt
   const int64_t *instA; const int64_t *instAt;
   int32_t B; int64_t n_tot, m_tot;
   T sigma;

@@ -49,7 +49,9 @@
 namespace cosmo {
 namespace {
 
-constexpr int PT = 512;      // threads per instance workgroup
+// threads per instance workgroup: 16 waves (float32) keep more rows in flight
+// per CU; the float64 instantiation needs more registers and runs 8 waves
+template <typename T> constexpr int PT = sizeof(T) == 4 ? 1024 : 512;
 constexpr int CT = 256;      // threads per workgroup of the cooperative form
 constexpr int NRESTART = 4;          // restarts from a float64 residual, at most
 constexpr double ROUND_DROP2 = 1e-4;  // a restarted round lowers its residual by 1e-2 (squared here)
@@ -91,8 +93,8 @@ template <int NTH, typename T> __device__ inline void wg_sum2(T &a, T &b, T *red
 // pass, all entries read with clamped indices and masks so the whole gather is
 // in flight at once.
 template <typename AT, typename T, typename VT, typename Act, typename F>
-__device__ inline void short_rows(const int32_t *__restrict__ rows, int64_t first, int64_t r1, int64_t stride,
-                                  const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+__device__ inline void short_rows(const int32_t *__restrict__ rows, const RowSpan *__restrict__ span, int64_t first,
+                                  int64_t r1, int64_t stride, const int32_t *__restrict__ col,
                                   const T *__restrict__ val, const VT *__restrict__ vin, Act active, F emit) {
   for (int64_t base = first; base < r1; base += 4 * stride) {
     int32_t rw[4];
@@ -103,12 +105,14 @@ __device__ inline void short_rows(const int32_t *__restrict__ rows, int64_t firs
       const int64_t ri = base + u * stride;
       ok[u] = ri < r1;
       rw[u] = ok[u] ? rows[ri] : 0;
+      const RowSpan sp = ok[u] ? span[ri] : RowSpan{0, 0};
+      k0[u] = sp.kb;
+      nk[u] = sp.k1 - sp.kb;
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       ok[u] = ok[u] && active(rw[u]);
-      k0[u] = ok[u] ? rowptr[rw[u]] : 0;
-      nk[u] = ok[u] ? rowptr[rw[u] + 1] - k0[u] : 0;
+      if (!ok[u]) nk[u] = 0;
     }
     AT acc[4];
 #pragma unroll
@@ -142,29 +146,42 @@ template <int N> struct alignas(4 * N) ColPiece {
 // arrays are 16-byte aligned): entries before its first aligned piece and
 // after its last full piece one per lane, the full pieces two per lane per
 // pass (the second clamped and masked), so that four 16-byte loads and 2 VE
-// gathers are in flight per lane.  gsub / nsub: this thread's row group and
-// the number of row groups of the pass.
+// gathers are in flight per lane.  The next row's id and entry range are
+// loaded while the current row is summed, so the index loads are off the
+// critical path.  gsub / nsub: this thread's row group and the number of row
+// groups of the pass.
 template <int L, typename AT, typename T, typename VT, typename Act, typename F>
-__device__ inline void row_pass(const int32_t *__restrict__ rows, int64_t r0, int64_t r1, int64_t gsub, int64_t nsub,
-                                const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+__device__ inline void row_pass(const int32_t *__restrict__ rows, const RowSpan *__restrict__ span, int64_t r0,
+                                int64_t r1, int64_t gsub, int64_t nsub, const int32_t *__restrict__ col,
                                 const T *__restrict__ val, const VT *__restrict__ vin, Act active, F emit) {
   if constexpr (L == 1) {
-    short_rows<AT>(rows, r0 + gsub, r1, nsub, rowptr, col, val, vin, active, emit);
+    short_rows<AT>(rows, span, r0 + gsub, r1, nsub, col, val, vin, active, emit);
   } else {
     constexpr int VE = 16 / sizeof(T);
     using VP = ValPiece<T>;
     using CP = ColPiece<VE>;
     const int lane = threadIdx.x % L;
-    for (int64_t base = r0; base < r1; base += nsub) {
-      const int64_t ri = base + gsub;
-      int32_t row = 0;
+    int64_t ri = r0 + gsub;
+    int32_t nrow = 0;
+    RowSpan nsp{0, 0};
+    if (ri < r1) {
+      nrow = rows[ri];
+      nsp = span[ri];
+    }
+    for (int64_t base = r0; base < r1; base += nsub, ri += nsub) {
+      const int32_t row = nrow;
+      const RowSpan sp = nsp;
+      const bool in = ri < r1;
+      if (ri + nsub < r1) {
+        nrow = rows[ri + nsub];
+        nsp = span[ri + nsub];
+      }
       bool ok = false;
       AT a0 = 0, a1 = 0;
-      if (ri < r1) {
-        row = rows[ri];
+      if (in) {
         ok = active(row);
         if (ok) {
-          const int64_t kb = rowptr[row], k1 = rowptr[row + 1];
+          const int64_t kb = sp.kb, k1 = sp.k1;
           int64_t ka = (kb + VE - 1) / VE * VE;
           if (ka > k1) ka = k1;
           const int64_t np = (k1 - ka) / VE, kt = ka + np * VE;
@@ -172,17 +189,26 @@ __device__ inline void row_pass(const int32_t *__restrict__ rows, int64_t r0, in
           if (lane < k1 - kt) a1 += (AT)val[kt + lane] * (AT)vin[col[kt + lane]];
           const VP *vp = reinterpret_cast<const VP *>(val + ka);
           const CP *cp = reinterpret_cast<const CP *>(col + ka);
-          for (int64_t q = lane; q < np; q += 2 * L) {
-            const bool two = q + L < np;
-            const int64_t q1 = two ? q + L : q;
-            const VP v0 = vp[q], v1 = vp[q1];
-            const CP c0 = cp[q], c1 = cp[q1];
+          constexpr int U = 2;
+          for (int64_t q = lane; q < np; q += U * L) {
+            VP vv[U];
+            CP cc[U];
+            bool has[U];
 #pragma unroll
-            for (int e = 0; e < VE; ++e) {
-              a0 += (AT)v0.v[e] * (AT)vin[c0.c[e]];
-              const AT p1 = (AT)v1.v[e] * (AT)vin[c1.c[e]];
-              a1 += two ? p1 : (AT)0;
+            for (int u = 0; u < U; ++u) {
+              has[u] = q + u * L < np;
+              const int64_t qu = has[u] ? q + u * L : q;
+              vv[u] = vp[qu];
+              cc[u] = cp[qu];
             }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+              for (int e = 0; e < VE; ++e) {
+                const AT pr = (AT)vv[u].v[e] * (AT)vin[cc[u].c[e]];
+                if (u % 2 == 0) a0 += has[u] ? pr : (AT)0;
+                else a1 += has[u] ? pr : (AT)0;
+              }
           }
         }
       }
@@ -196,9 +222,9 @@ __device__ inline void row_pass(const int32_t *__restrict__ rows, int64_t r0, in
 // the rows of instances [b0, b1): per-instance passes use b1 = b0 + 1, grid
 // passes b0 = 0, b1 = B.
 template <int NTH, bool GRID, typename AT, typename T, typename VT, typename Act, typename F>
-__device__ inline void class_passes(const int32_t *rows, const int64_t *cls_off, int64_t B1, int b0, int b1,
-                                    const int64_t *rowptr, const int32_t *col, const T *val, const VT *vin,
-                                    Act active, F emit) {
+__device__ inline void class_passes(const int32_t *rows, const RowSpan *span, const int64_t *cls_off, int64_t B1,
+                                    int b0, int b1, const int32_t *col, const T *val, const VT *vin, Act active,
+                                    F emit) {
   auto sub = [&](int L, int64_t &g, int64_t &n) {
     if (GRID) {
       g = (int64_t)blockIdx.x * (NTH / L) + threadIdx.x / L;
@@ -210,11 +236,11 @@ __device__ inline void class_passes(const int32_t *rows, const int64_t *cls_off,
   };
   int64_t g, n;
   sub(1, g, n);
-  row_pass<1, AT>(rows, cls_off[b0], cls_off[b1], g, n, rowptr, col, val, vin, active, emit);
+  row_pass<1, AT>(rows, span, cls_off[b0], cls_off[b1], g, n, col, val, vin, active, emit);
   sub(8, g, n);
-  row_pass<8, AT>(rows, cls_off[B1 + b0], cls_off[B1 + b1], g, n, rowptr, col, val, vin, active, emit);
+  row_pass<8, AT>(rows, span, cls_off[B1 + b0], cls_off[B1 + b1], g, n, col, val, vin, active, emit);
   sub(64, g, n);
-  row_pass<64, AT>(rows, cls_off[2 * B1 + b0], cls_off[2 * B1 + b1], g, n, rowptr, col, val, vin, active, emit);
+  row_pass<64, AT>(rows, span, cls_off[2 * B1 + b0], cls_off[2 * B1 + b1], g, n, col, val, vin, active, emit);
 }
 
 // t = rho_hat o (A vin), then out = A' t + P vin + sigma vin, over the
@@ -225,10 +251,10 @@ __device__ inline void op_apply(const View<T> &v, const T *__restrict__ rho_hat,
                                 T *__restrict__ t, T *__restrict__ out, int b0, int b1, RowAct row_act,
                                 ColAct col_act, Sync sync) {
   const int64_t B1 = v.B + 1;
-  class_passes<NTH, GRID, T>(v.rowsA, v.instA, B1, b0, b1, v.A_rowptr, v.A_col, v.A_val, vin, row_act,
+  class_passes<NTH, GRID, T>(v.rowsA, v.spanA, v.instA, B1, b0, b1, v.A_col, v.A_val, vin, row_act,
                              [&](int32_t i, T acc) { t[i] = rho_hat[i] * acc; });
   sync();
-  class_passes<NTH, GRID, T>(v.rowsAt, v.instAt, B1, b0, b1, v.At_rowptr, v.At_col, v.At_val, t, col_act,
+  class_passes<NTH, GRID, T>(v.rowsAt, v.spanAt, v.instAt, B1, b0, b1, v.At_col, v.At_val, t, col_act,
                              [&](int32_t j, T acc) {
                                if (v.P_rowptr)
                                  for (int64_t k = v.P_rowptr[j]; k < v.P_rowptr[j + 1]; ++k)
@@ -245,10 +271,10 @@ __device__ inline void op_residual64(const View<T> &v, const T *__restrict__ rho
                                      const T *__restrict__ x, double *__restrict__ t64, T *__restrict__ r, int b0,
                                      int b1, RowAct row_act, ColAct col_act, Sync sync) {
   const int64_t B1 = v.B + 1;
-  class_passes<NTH, GRID, double>(v.rowsA, v.instA, B1, b0, b1, v.A_rowptr, v.A_col, v.A_val, x, row_act,
+  class_passes<NTH, GRID, double>(v.rowsA, v.spanA, v.instA, B1, b0, b1, v.A_col, v.A_val, x, row_act,
                                   [&](int32_t i, double acc) { t64[i] = (double)rho_hat[i] * acc; });
   sync();
-  class_passes<NTH, GRID, double>(v.rowsAt, v.instAt, B1, b0, b1, v.At_rowptr, v.At_col, v.At_val, t64, col_act,
+  class_passes<NTH, GRID, double>(v.rowsAt, v.spanAt, v.instAt, B1, b0, b1, v.At_col, v.At_val, t64, col_act,
                                   [&](int32_t j, double acc) {
                                     if (v.P_rowptr)
                                       for (int64_t k = v.P_rowptr[j]; k < v.P_rowptr[j + 1]; ++k)
@@ -284,34 +310,34 @@ __device__ inline void finish(const View<T> &v, int b, bool fail, int it, int pa
 // ---- per-instance form -------------------------------------------------------------
 
 template <typename T>
-__global__ __launch_bounds__(PT) void k_pcg(View<T> v, const T *__restrict__ rho_hat, const T *__restrict__ dg,
+__global__ __launch_bounds__(PT<T>) void k_pcg(View<T> v, const T *__restrict__ rho_hat, const T *__restrict__ dg,
                                             const double *__restrict__ rhs, T *__restrict__ x, T *__restrict__ r,
                                             T *__restrict__ z, T *__restrict__ p, T *__restrict__ Mp,
                                             T *__restrict__ t, double *__restrict__ t64, T tol, int32_t max_iter,
                                             const T *__restrict__ alpha_k, const T *__restrict__ xold,
                                             T *__restrict__ xnew, const T *__restrict__ gx_in,
                                             T *__restrict__ gx_out, int32_t mode, cosmo_stats *stats) {
-  __shared__ T red[2 * (PT / 64)];
-  __shared__ double redd[2 * (PT / 64)];
+  __shared__ T red[2 * (PT<T> / 64)];
+  __shared__ double redd[2 * (PT<T> / 64)];
   const int b = blockIdx.x;
   const int64_t n0 = v.n_off[b], n1 = v.n_off[b + 1];
   auto all = [](int32_t) { return true; };
   auto bar = []() { __syncthreads(); };
 
   double bb = 0, dd = 0;
-  for (int64_t j = n0 + threadIdx.x; j < n1; j += PT) bb += rhs[j] * rhs[j];
-  wg_sum2<PT>(bb, dd, redd);
+  for (int64_t j = n0 + threadIdx.x; j < n1; j += PT<T>) bb += rhs[j] * rhs[j];
+  wg_sum2<PT<T>>(bb, dd, redd);
   const double thr = (double)tol * (double)tol * bb;
   bool fail = !isfinite(bb);
   int it = 0, passes = 0;
   double rrt = 0, rrt_prev = 0;
   for (int restart = 0;; ++restart) {
     // true residual, z = r / diag M, p = z
-    op_residual64<PT, false>(v, rho_hat, rhs, x, t64, r, b, b + 1, all, all, bar);
+    op_residual64<PT<T>, false>(v, rho_hat, rhs, x, t64, r, b, b + 1, all, all, bar);
     ++passes;
     T rz = 0, rr = 0;
     rrt = 0;
-    for (int64_t j = n0 + threadIdx.x; j < n1; j += PT) {
+    for (int64_t j = n0 + threadIdx.x; j < n1; j += PT<T>) {
       const T rj = r[j];
       const T zj = rj / dg[j];
       z[j] = zj;
@@ -320,8 +346,8 @@ __global__ __launch_bounds__(PT) void k_pcg(View<T> v, const T *__restrict__ rho
       rr += rj * rj;
       rrt += (double)rj * (double)rj;
     }
-    wg_sum2<PT>(rz, rr, red);
-    wg_sum2<PT>(rrt, dd, redd);
+    wg_sum2<PT<T>>(rz, rr, red);
+    wg_sum2<PT<T>>(rrt, dd, redd);
     fail = fail || !isfinite(rrt);
     const bool stalled = restart > 0 && rrt > STALL2 * rrt_prev;
     if (fail || rrt <= thr || it >= max_iter || restart > NRESTART || stalled) break;
@@ -330,17 +356,17 @@ __global__ __launch_bounds__(PT) void k_pcg(View<T> v, const T *__restrict__ rho
     // CG on the recursive residual
     while (rr > target && it < max_iter) {
       __syncthreads();   // p complete before the operator reads it
-      op_apply<PT, false>(v, rho_hat, p, t, Mp, b, b + 1, all, all, bar);
+      op_apply<PT<T>, false>(v, rho_hat, p, t, Mp, b, b + 1, all, all, bar);
       T pMp = 0, dummy = 0;
-      for (int64_t j = n0 + threadIdx.x; j < n1; j += PT) pMp += p[j] * Mp[j];
-      wg_sum2<PT>(pMp, dummy, red);
+      for (int64_t j = n0 + threadIdx.x; j < n1; j += PT<T>) pMp += p[j] * Mp[j];
+      wg_sum2<PT<T>>(pMp, dummy, red);
       if (!(pMp > (T)0)) {   // breakdown: restart from the true residual (or fail if non-finite)
         fail = !isfinite(pMp);
         break;
       }
       const T a = rz / pMp;
       T rz_new = 0, rr_new = 0;
-      for (int64_t j = n0 + threadIdx.x; j < n1; j += PT) {
+      for (int64_t j = n0 + threadIdx.x; j < n1; j += PT<T>) {
         x[j] += a * p[j];
         const T rj = r[j] - a * Mp[j];
         const T zj = rj / dg[j];
@@ -349,11 +375,11 @@ __global__ __launch_bounds__(PT) void k_pcg(View<T> v, const T *__restrict__ rho
         rz_new += rj * zj;
         rr_new += rj * rj;
       }
-      wg_sum2<PT>(rz_new, rr_new, red);
+      wg_sum2<PT<T>>(rz_new, rr_new, red);
       const T beta = rz_new / rz;
       rz = rz_new;
       rr = rr_new;
-      for (int64_t j = n0 + threadIdx.x; j < n1; j += PT) p[j] = z[j] + beta * p[j];
+      for (int64_t j = n0 + threadIdx.x; j < n1; j += PT<T>) p[j] = z[j] + beta * p[j];
       ++it;
       if (!isfinite(rr)) {
         fail = true;
@@ -364,7 +390,7 @@ __global__ __launch_bounds__(PT) void k_pcg(View<T> v, const T *__restrict__ rho
     __syncthreads();   // x complete before the residual reads it
   }
   __syncthreads();
-  finish<PT>(v, b, fail, it, passes, rrt, thr, x, alpha_k, xold, xnew, gx_in, gx_out, mode, stats);
+  finish<PT<T>>(v, b, fail, it, passes, rrt, thr, x, alpha_k, xold, xnew, gx_in, gx_out, mode, stats);
 }
 
 // ---- cooperative form ------------------------------------------------------------
@@ -632,7 +658,7 @@ void launch_pcg(const View<T> &v, const T *rho_hat, const T *dg, const double *r
       return;
     (void)hipGetLastError();
   }
-  k_pcg<T><<<v.B, PT, 0, st>>>(v, rho_hat, dg, rhs, x, r, z, p, Mp, t, t64, (T)tol, max_iter, alpha_k, xold, xnew,
+  k_pcg<T><<<v.B, PT<T>, 0, st>>>(v, rho_hat, dg, rhs, x, r, z, p, Mp, t, t64, (T)tol, max_iter, alpha_k, xold, xnew,
                                gx_in, gx_out, mode, stats);
 }
 

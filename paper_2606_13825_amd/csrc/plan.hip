@@ -173,6 +173,8 @@ template <typename T> View<T> make_view(const cosmo_plan *pl) {
   v.m_off = pl->d_m_off;
   v.rowsA = pl->bkA.d_rows;
   v.rowsAt = pl->bkAt.d_rows;
+  v.spanA = pl->bkA.d_span;
+  v.spanAt = pl->bkAt.d_span;
   v.instA = pl->d_instA;
   v.instAt = pl->d_instAt;
   v.B = pl->B;
@@ -436,6 +438,14 @@ cosmo_status build_plan(cosmo_plan *pl, const cosmo_problem *p) {
   const size_t o_rect = take(std::max<size_t>(rects.size(), 1) * sizeof(RectDesc));
   const size_t o_bA = take(std::max<size_t>(rowsA.size(), 1) * sizeof(int32_t));
   const size_t o_bAt = take(std::max<size_t>(rowsAt.size(), 1) * sizeof(int32_t));
+  auto spans = [](const std::vector<int32_t> &rows, const std::vector<int64_t> &ptr) {
+    std::vector<RowSpan> sp(rows.size());
+    for (size_t i = 0; i < rows.size(); ++i) sp[i] = RowSpan{ptr[rows[i]], ptr[rows[i] + 1]};
+    return sp;
+  };
+  const std::vector<RowSpan> spA = spans(rowsA, rp), spAt = spans(rowsAt, trp);
+  const size_t o_sA = take(std::max<size_t>(spA.size(), 1) * sizeof(RowSpan));
+  const size_t o_sAt = take(std::max<size_t>(spAt.size(), 1) * sizeof(RowSpan));
   if (hipMalloc(&pl->mem.ptr, off) != hipSuccess) {
     pl->mem.ptr = nullptr;
     FAIL(COSMO_ENOMEM, "plan allocation of " + std::to_string(off) + " bytes failed");
@@ -461,6 +471,8 @@ cosmo_status build_plan(cosmo_plan *pl, const cosmo_problem *p) {
   HIPCHK(up(o_rect, rects.data(), rects.size() * sizeof(RectDesc)));
   HIPCHK(up(o_bA, rowsA.data(), rowsA.size() * sizeof(int32_t)));
   HIPCHK(up(o_bAt, rowsAt.data(), rowsAt.size() * sizeof(int32_t)));
+  HIPCHK(up(o_sA, spA.data(), spA.size() * sizeof(RowSpan)));
+  HIPCHK(up(o_sAt, spAt.data(), spAt.size() * sizeof(RowSpan)));
   pl->d_n_off = reinterpret_cast<int64_t *>(base + o_noff);
   pl->d_m_off = reinterpret_cast<int64_t *>(base + o_moff);
   pl->d_At_rowptr = reinterpret_cast<int64_t *>(base + o_trp);
@@ -477,6 +489,8 @@ cosmo_status build_plan(cosmo_plan *pl, const cosmo_problem *p) {
   pl->d_rect = reinterpret_cast<RectDesc *>(base + o_rect);
   pl->bkA.d_rows = reinterpret_cast<int32_t *>(base + o_bA);
   pl->bkAt.d_rows = reinterpret_cast<int32_t *>(base + o_bAt);
+  pl->bkA.d_span = reinterpret_cast<RowSpan *>(base + o_sA);
+  pl->bkAt.d_span = reinterpret_cast<RowSpan *>(base + o_sAt);
   return COSMO_OK;
 }
 
