@@ -248,7 +248,8 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
                                                 const T *__restrict__ y, T *__restrict__ s_new,
                                                 T *__restrict__ y_new, T *__restrict__ Uout,
                                                 T *__restrict__ lamout, cosmo_stats *stats, int32_t refine,
-                                                double *__restrict__ rscratch, const T *__restrict__ Uprev) {
+                                                double *__restrict__ rscratch, const T *__restrict__ Uprev,
+                                                int32_t attempt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *W = reinterpret_cast<T *>(smem_raw);
   __shared__ T red[NT / 64];
@@ -259,9 +260,26 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
   __shared__ int flags[3];
   __shared__ int bigf[3];
   __shared__ int npos_s;
+  __shared__ int redo_s;
 
   const PsdDesc d = descs[blockIdx.x];
   const int p = d.p;
+  // Early-stopped sweeps (float32, orders up to 128, with refinement) can
+  // leave a pair across the positive / non-positive split too coupled for
+  // the refinement's first-order rotation; such a block writes only its
+  // current eigenvectors (to the eigenvector output, when there is one), sets
+  // its flag (a slot of the refinement scratch these classes do not use
+  // otherwise), and a second launch (attempt 1) solves only the flagged
+  // blocks, started from those eigenvectors, with the sweeps run to
+  // convergence.
+  constexpr bool EARLY = std::is_same<T, float>::value && PMAX <= 128;
+  int *redo_g = (EARLY && refine > 0 && rscratch) ? reinterpret_cast<int *>(rscratch + 3 * (size_t)d.uoff) : nullptr;
+  if (attempt == 1) {
+    if (!redo_g || *redo_g == 0) return;   // the same value in every thread
+  } else if (redo_g && threadIdx.x == 0) {
+    *redo_g = 0;
+  }
+  const T *Uwarm = (attempt == 1 && Uout) ? Uout : Uprev;   // warm start of this attempt
   const int ld = eig_ld<T, G, PMAX>(p);
   const int nrows = p * (p + 1) / 2;
   const T *v = vin + d.row0;
@@ -288,6 +306,7 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
     }
   }
   if (tid < 3) flags[tid] = bigf[tid] = 0;
+  if (tid == 0) redo_s = 0;
   fro2 = wg_sum<T, NT>(fro2, red);   // contains barriers: W complete after this
   if (!isfinite(fro2)) {
     // a non-finite block yields a non-finite projection (never a clipped one)
@@ -316,13 +335,13 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
   // a nearly diagonalising start only shortens the sweeps.
   bool started = false;
   if constexpr (std::is_same<T, float>::value && PMAX <= 128) {
-    if (Uprev && refine > 0) {
+    if (Uwarm && refine > 0) {
       // U_prev staged in the refinement buffer (free until the refinement);
       // S is in W, so the products are held in registers until all are done
       constexpr int NWs = NT / 64;
       constexpr int NTM = (PMAX + 15) / 16;
       constexpr int HOLDS = (NTM * NTM + NWs - 1) / NWs;
-      const float *Up = Uprev + d.uoff;
+      const float *Up = Uwarm + d.uoff;
       float *Ub = W + p * ld;
       for (int e = tid; e < p * p; e += NT) {
         const int j = e / p;
@@ -351,8 +370,8 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
       started = true;
     }
   }
-  if (!started && Uprev) {
-    const T *Up = Uprev + d.uoff;
+  if (!started && Uwarm) {
+    const T *Up = Uwarm + d.uoff;
     const int nt0 = (p + 15) / 16;
     const int wave0 = tid >> 6, lane0 = tid & 63;
     for (int t = wave0; t < nt0 * nt0; t += NT / 64) {
@@ -392,7 +411,7 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
   // are then of order 1e-6, well inside what one refinement step removes.
   // The largest class converges fully (stopping early there left 1e-4
   // errors on order-196 blocks).
-  const T stop2 = (std::is_same<T, float>::value && PMAX <= 128 && refine > 0) ? (T)1e-6 : (T)0;
+  const T stop2 = (redo_g && attempt == 0) ? (T)1e-6 : (T)0;
   for (; sweep < max_sweeps && !converged; ++sweep) {
     const int fslot = sweep % 3;
     for (int r = 0; r < P - 1; ++r) {
@@ -555,7 +574,8 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
       //   E_ij = (S~_ij + lam_j R_ij) / (lam_j - lam_i)  for pairs across the split
       //          between positive and non-positive eigenvalues whose gap exceeds
       //          delta = 2 (||S~ - diag(lam)||_F + ||S||_F ||R||_F) and whose
-      //          coupling is small (<= 1e-3 of the gap);  E_ij = R_ij / 2 otherwise
+      //          coupling th = cpl / gap leaves a second-order remainder
+      //          th^2 max|lam| below 1e-7 ||S||_F;  E_ij = R_ij / 2 otherwise
       //   X <- X + X E
       //   Pi = X+ M X+',  M = X+' S X+ to first order in E:
       //          M_ii = lam_i,  M_ij = S~_ij + (lam_i + lam_j) R_ij / 2.
@@ -683,7 +703,12 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
         if (li * lj < 0.0) {
           const double gap = lj - li;
           const double cpl = fabs(s) + fmax(fabs(li), fabs(lj)) * fabs(r);
-          const bool rot = fabs(gap) > delta && cpl <= 1e-3 * fabs(gap);
+          // first-order rotation when its second-order remainder, th^2
+          // max(|l_i|, |l_j|) with th = cpl / gap, is below 1e-7 ||S||_F
+          const double th = cpl / fabs(gap);
+          const bool rot = fabs(gap) > delta && th <= 0.1 &&
+                           th * th * fmax(fabs(li), fabs(lj)) <= 1e-7 * sqrt((double)fro2);
+          if (!rot && fabs(gap) > delta && stop2 > (T)0) redo_s = 1;   // resolvable, but not to first order
           SR[i + j * ld] = (float)(rot ? (s + lj * r) / gap : 0.5 * r);
           SR[j + i * ld] = (float)(rot ? (s + li * r) / (-gap) : 0.5 * r);
         } else {
@@ -692,6 +717,15 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
         }
       }
       __syncthreads();
+      if (redo_s) {   // read after the barrier above: the same in every thread
+        if (Uout)
+          for (int e = tid; e < p * p; e += NT) {
+            const int j = e / p, i = e - j * p;
+            Uout[d.uoff + e] = W[i + j * ld];
+          }
+        if (tid == 0) *redo_g = 1;
+        return;
+      }
       // X <- X + X E, in place in W
       auto Eget = [&](int k, int j) -> float {
         return (k >= j || cls[k] * cls[j] < 0) ? SR[k + j * ld] : SR[j + k * ld];
@@ -939,7 +973,10 @@ void run_eig(const PsdDesc *d, int32_t n, int32_t max_p, const PsdLaunchCfg &cfg
     attr_set = true;
   }
   k_psd_eig<T, NT, G, PMAX><<<n, NT, dyn, st>>>(d, cfg.max_sweeps, (T)cfg.tol, mode, rho_hat, vv, sh, y, s_new,
-                                                y_new, U, lam, stats, refine, rscratch, Uprev);
+                                                y_new, U, lam, stats, refine, rscratch, Uprev, 0);
+  if (std::is_same<T, float>::value && PMAX <= 128 && refine > 0 && rscratch)   // the flagged blocks again
+    k_psd_eig<T, NT, G, PMAX><<<n, NT, dyn, st>>>(d, cfg.max_sweeps, (T)cfg.tol, mode, rho_hat, vv, sh, y, s_new,
+                                                  y_new, U, lam, stats, refine, rscratch, Uprev, 1);
 }
 
 }  // namespace

@@ -65,8 +65,11 @@ def _check_one_steps(wl, rhos, alphas, batch, fw, samples):
     worst = 0.0
     for i, k in samples:
         inst = wl["insts"][i]
-        e, _ = one_step_err(inst, _iterate(batch, fw, i, k), _iterate(batch, fw, i, k + 1), rhos[i][k],
-                            alphas[i][k], floor_of(inst))
+        try:
+            e, _ = one_step_err(inst, _iterate(batch, fw, i, k), _iterate(batch, fw, i, k + 1), rhos[i][k],
+                                alphas[i][k], floor_of(inst))
+        except AssertionError as err:
+            raise AssertionError(f"instance {i}, step {k}: {err}") from None
         worst = max(worst, e)
     where = samples if len(samples) <= 8 else f"{len(samples)} steps"
     say(f"  one-step parity at {where}: worst rel err {worst:.2e}")
