@@ -51,6 +51,35 @@ def test_psd_proj_sizes_and_tails(dtype, tol):
         off += nr
 
 
+def test_psd_proj_small_split_gap():
+    """Blocks whose positive / non-positive split is narrow against their
+    norm: an eigenvalue just below zero beside a small positive one, the rest
+    spread to +-100 (the shape of a maxcut iterate block that once left
+    1.3e-4 in the projection).  Float32 Jacobi cannot take such a pair's
+    mixing angle below ~1e-3; the refinement's first-order rotation has to
+    resolve it (or the block is solved again with converged sweeps)."""
+    ensure_lib()
+    rng = np.random.default_rng(5)
+    mats = []
+    for p, (neg, pos) in ((40, (-8.5e-4, 0.26)), (89, (-8.5e-4, 0.26)), (100, (-1e-2, 1e-2)),
+                          (128, (-5e-3, 0.5)), (64, (-0.3, 0.3))):
+        big = rng.uniform(1.0, 100.0, p - 2) * rng.choice([-1.0, 1.0], p - 2)
+        lam = np.concatenate([[neg, pos], big])
+        Q = random_orthogonal(p, rng)
+        mats.append(((Q * lam) @ Q.T).astype(np.float32).astype(np.float64))
+    mats = [0.5 * (m + m.T) for m in mats]
+    say("psd_proj small split gaps, orders " + str([m.shape[0] for m in mats]))
+    out, _, _, _ = _run_psd(mats, np.float32)
+    off = 0
+    for S in mats:
+        p = S.shape[0]
+        nr = p * (p + 1) // 2
+        ref = oracle.proj_psd(oracle.svec(S))[0]
+        e = rel_err(out[off:off + nr], ref, 1e-6 * np.linalg.norm(oracle.svec(S)))
+        assert e <= 2e-6 * max(1.0, np.sqrt(p) / 4), (p, e)
+        off += nr
+
+
 @pytest.mark.parametrize("delta", [1.0, 1e-4, 1e-10])
 def test_psd_proj_clustered_and_repeated_eigenvalues(delta):
     ensure_lib()
