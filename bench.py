@@ -265,7 +265,7 @@ def main():
     if args.schedule == "auto":
         form, ms = batch.autotune(rho, alpha, fws)
         sched = {"pcg_form": form, "graph": batch.graph(),
-                 "autotune_forward_ms": dict(zip(("form0", "form1", "form2", "form0_graph"), ms))}
+                 "autotune_forward_ms": dict(zip(("form0", "form2", "form4", "form0_graph"), ms))}
     else:
         batch.set_graph(False)
         batch.set_pcg_form(0)

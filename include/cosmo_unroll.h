@@ -226,13 +226,13 @@ cosmo_status socp_proj_vjp(int32_t ncones, const int32_t *dim, const int64_t *of
 
 /* Schedules of the CG solves (Table 2; Sec. "Matrix-Free Implicit
  * Differentiation"): form 0 = one workgroup per instance iterating to its own
- * tolerance (the default); form f = 1 or 2 = one cooperative launch over the
+ * tolerance (the default); form f = 1..4 = one cooperative launch over the
  * whole device with at most f workgroups per compute unit, the operator
  * passes of all instances spread over every workgroup and grid barriers
  * between phases (falls back to form 0 where cooperative launch is not
  * available).  Both forms compute the same iteration with the same stopping
  * rule; their sums are taken in different orders, each deterministic.
- * set_pcg_form: form outside 0..2 is COSMO_EINVAL; a cooperative form while
+ * set_pcg_form: form outside 0..4 is COSMO_EINVAL; a cooperative form while
  * graph mode is on is COSMO_EUNSUPPORTED. */
 cosmo_status cosmo_plan_set_pcg_form(cosmo_plan *plan, int32_t form);
 cosmo_status cosmo_plan_get_pcg_form(const cosmo_plan *plan, int32_t *form);
@@ -254,7 +254,7 @@ cosmo_status cosmo_plan_set_graph(cosmo_plan *plan, int32_t enable);
 cosmo_status cosmo_plan_get_graph(const cosmo_plan *plan, int32_t *enabled);
 
 /* Autotuner: runs the forward unroll (no tape) under each schedule -- CG
- * forms 0, 1, 2 launched eagerly, and form 0 replayed from a graph -- on the
+ * forms 0, 2, 4 launched eagerly, and form 0 replayed from a graph -- on the
  * given rho, alpha and forward workspace, times the second of two runs with
  * events on `stream`, and keeps the fastest (CG form and graph mode) in the
  * plan.  A setup call, not for the hot path: it allocates a scratch output

@@ -279,7 +279,7 @@ class CosmoBatch:
 
     # -- schedules ----------------------------------------------------------------
     def set_pcg_form(self, form: int):
-        """CG schedule: 0 one workgroup per instance, 1 or 2 cooperative (that
+        """CG schedule: 0 one workgroup per instance, 1..4 cooperative (that
         many workgroups per compute unit at most)."""
         L.check(L.lib().cosmo_plan_set_pcg_form(self._plan, int(form)), "cosmo_plan_set_pcg_form")
 
@@ -299,7 +299,7 @@ class CosmoBatch:
         return bool(f.value)
 
     def autotune(self, rho: torch.Tensor, alpha: torch.Tensor, ws: Optional[torch.Tensor] = None):
-        """Time the schedules (CG forms 0, 1, 2 eager; form 0 from a graph) on
+        """Time the schedules (CG forms 0, 2, 4 eager; form 0 from a graph) on
         a forward unroll and keep the fastest; returns (chosen CG form,
         [ms per schedule], -1 where not run).  graph() tells whether graph
         mode was chosen."""

@@ -953,7 +953,7 @@ cosmo_status cosmo_residual_loss(cosmo_plan *plan, const void *x, const void *s,
 cosmo_status cosmo_plan_set_pcg_form(cosmo_plan *plan, int32_t form) {
   cosmo_status s = check_plan(plan);
   if (s != COSMO_OK) return s;
-  if (form < 0 || form > 2) FAIL(COSMO_EINVAL, "form must be 0, 1 or 2");
+  if (form < 0 || form > 4) FAIL(COSMO_EINVAL, "form must be 0..4");
   if (form != 0 && plan->graph) FAIL(COSMO_EUNSUPPORTED, "the cooperative CG forms are not recorded into graphs");
   plan->pcg_form = form;
   return COSMO_OK;
@@ -1004,8 +1004,8 @@ cosmo_status cosmo_plan_autotune(cosmo_plan *plan, const void *rho, const void *
     (void)hipEventDestroy(e0);
     FAIL(COSMO_EHIP, "hipEventCreate failed");
   }
-  // candidates: CG forms 0, 1, 2 launched eagerly, then form 0 replayed from a graph
-  const int32_t cand_form[4] = {0, 1, 2, 0};
+  // candidates: CG forms 0, 2, 4 launched eagerly, then form 0 replayed from a graph
+  const int32_t cand_form[4] = {0, 2, 4, 0};
   const bool cand_graph[4] = {false, false, false, true};
   const int32_t keep_form = plan->pcg_form;
   const bool keep_graph = plan->graph, keep_prof = plan->profiling;
