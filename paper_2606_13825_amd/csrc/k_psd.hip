@@ -842,9 +842,16 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
   }
 }
 
-// DK VJP: out = svec(U (L o (U' smat(g) U)) U').  Buffers: B0 and B1 (p x p)
-// in LDS when they fit, else B1 in global scratch; U read from LDS when a
-// third buffer fits, else from global memory.
+// Leading dimension of the DK VJP's LDS buffers: the smallest stride >= p
+// that is 4 modulo 8 words, so the 16 columns one matrix-core operand read
+// touches (16 lanes, one column each, four consecutive rows per column
+// group) fall on distinct banks; a stride that is a multiple of 16 would put
+// all 16 on one bank.
+__host__ __device__ constexpr int dk_ld(int p) { return p + ((4 - p % 8) + 8) % 8; }
+
+// DK VJP: out = svec(U (L o (U' smat(g) U)) U').  Buffers: B0 and B1 (p x p,
+// stride dk_ld(p)) in LDS when they fit, else B1 in global scratch (stride
+// p); U read from LDS when a third buffer fits, else from global memory.
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_psd_vjp(const PsdDesc *__restrict__ descs, const T *__restrict__ Ug,
                                                 const T *__restrict__ lam, const T *__restrict__ g,
@@ -853,15 +860,23 @@ __global__ __launch_bounds__(NT) void k_psd_vjp(const PsdDesc *__restrict__ desc
   T *lds = reinterpret_cast<T *>(smem_raw);
   __shared__ T lam_s[MAXP];
   const PsdDesc d = descs[blockIdx.x];
-  const int p = d.p, pp = p * p;
+  const int p = d.p, pp = p * p, lp = dk_ld(p), ppl = p * lp;
   const int tid = threadIdx.x;
   T *B0 = lds;
-  T *B1 = (2 * pp <= lds_elems) ? lds + pp : scratch + d.uoff;
+  const int l0 = lp;
+  const bool b1_lds = 2 * ppl <= lds_elems;
+  T *B1 = b1_lds ? lds + ppl : scratch + d.uoff;
+  const int l1 = b1_lds ? lp : p;
   const T *U = Ug + d.uoff;
-  if (3 * pp <= lds_elems) {
-    T *Ul = lds + 2 * pp;
-    for (int e = tid; e < pp; e += NT) Ul[e] = U[e];
+  int lu = p;
+  if (3 * ppl <= lds_elems) {
+    T *Ul = lds + 2 * ppl;
+    for (int e = tid; e < pp; e += NT) {
+      const int j = e / p;
+      Ul[(e - j * p) + j * lp] = U[e];
+    }
     U = Ul;
+    lu = lp;
   }
   for (int i = tid; i < p; i += NT) lam_s[i] = lam[d.loff + i];
   const T *gb = g + d.row0;
@@ -871,8 +886,8 @@ __global__ __launch_bounds__(NT) void k_psd_vjp(const PsdDesc *__restrict__ desc
     const int i = idx - j * (j + 1) / 2;
     T val = gb[idx];
     if (i != j) val *= (T)RSQRT2;
-    B0[i + j * p] = val;
-    B0[j + i * p] = val;
+    B0[i + j * l0] = val;
+    B0[j + i * l0] = val;
   }
   __syncthreads();
   const int nt = (p + 15) / 16;
@@ -881,22 +896,22 @@ __global__ __launch_bounds__(NT) void k_psd_vjp(const PsdDesc *__restrict__ desc
   // B1 = B0 U
   for (int t = wave; t < nt * nt; t += NWv) {
     const int I = t / nt, J = t % nt;
-    auto fa = [&](int i, int k) -> T { return (i < p && k < p) ? B0[i + k * p] : (T)0; };
-    auto fb = [&](int k, int j) -> T { return (k < p && j < p) ? U[k + j * p] : (T)0; };
+    auto fa = [&](int i, int k) -> T { return (i < p && k < p) ? B0[i + k * l0] : (T)0; };
+    auto fb = [&](int k, int j) -> T { return (k < p && j < p) ? U[k + j * lu] : (T)0; };
     const typename Mma<T>::v4 acc = tile_mma<T>(I * 16, J * 16, p, fa, fb);
     const int col = J * 16 + (lane & 15);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int row = I * 16 + Mma<T>::row(lane, e);
-      if (row < p && col < p) B1[row + col * p] = acc[e];
+      if (row < p && col < p) B1[row + col * l1] = acc[e];
     }
   }
   __syncthreads();
   // B0 = L o (U' B1)
   for (int t = wave; t < nt * nt; t += NWv) {
     const int I = t / nt, J = t % nt;
-    auto fa = [&](int i, int k) -> T { return (i < p && k < p) ? U[k + i * p] : (T)0; };
-    auto fb = [&](int k, int j) -> T { return (k < p && j < p) ? B1[k + j * p] : (T)0; };
+    auto fa = [&](int i, int k) -> T { return (i < p && k < p) ? U[k + i * lu] : (T)0; };
+    auto fb = [&](int k, int j) -> T { return (k < p && j < p) ? B1[k + j * l1] : (T)0; };
     const typename Mma<T>::v4 acc = tile_mma<T>(I * 16, J * 16, p, fa, fb);
     const int col = J * 16 + (lane & 15);
 #pragma unroll
@@ -908,7 +923,7 @@ __global__ __launch_bounds__(NT) void k_psd_vjp(const PsdDesc *__restrict__ desc
         if (li > (T)0 && lj > (T)0) L = (T)1;
         else if (li <= (T)0 && lj <= (T)0) L = (T)0;
         else L = fmax(li, lj) / (fabs(li) + fabs(lj));
-        B0[row + col * p] = L * acc[e];
+        B0[row + col * l0] = L * acc[e];
       }
     }
   }
@@ -916,14 +931,14 @@ __global__ __launch_bounds__(NT) void k_psd_vjp(const PsdDesc *__restrict__ desc
   // B1 = U B0
   for (int t = wave; t < nt * nt; t += NWv) {
     const int I = t / nt, J = t % nt;
-    auto fa = [&](int i, int k) -> T { return (i < p && k < p) ? U[i + k * p] : (T)0; };
-    auto fb = [&](int k, int j) -> T { return (k < p && j < p) ? B0[k + j * p] : (T)0; };
+    auto fa = [&](int i, int k) -> T { return (i < p && k < p) ? U[i + k * lu] : (T)0; };
+    auto fb = [&](int k, int j) -> T { return (k < p && j < p) ? B0[k + j * l0] : (T)0; };
     const typename Mma<T>::v4 acc = tile_mma<T>(I * 16, J * 16, p, fa, fb);
     const int col = J * 16 + (lane & 15);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int row = I * 16 + Mma<T>::row(lane, e);
-      if (row < p && col < p) B1[row + col * p] = acc[e];
+      if (row < p && col < p) B1[row + col * l1] = acc[e];
     }
   }
   __syncthreads();
@@ -933,8 +948,8 @@ __global__ __launch_bounds__(NT) void k_psd_vjp(const PsdDesc *__restrict__ desc
   for (int t = wave; t < ntiles; t += NWv) {
     int I, J;
     upper_tile(t, I, J);
-    auto fa = [&](int i, int k) -> T { return (i < p && k < p) ? B1[i + k * p] : (T)0; };
-    auto fb = [&](int k, int j) -> T { return (k < p && j < p) ? U[j + k * p] : (T)0; };
+    auto fa = [&](int i, int k) -> T { return (i < p && k < p) ? B1[i + k * l1] : (T)0; };
+    auto fb = [&](int k, int j) -> T { return (k < p && j < p) ? U[j + k * lu] : (T)0; };
     const typename Mma<T>::v4 acc = tile_mma<T>(I * 16, J * 16, p, fa, fb);
     const int col = J * 16 + (lane & 15);
 #pragma unroll
@@ -1005,7 +1020,7 @@ template <typename T>
 void launch_psd_vjp(const PsdDesc *d, int32_t n, int32_t max_p, const T *U, const T *lam, const T *g, T *out,
                     T *scratch, hipStream_t st) {
   if (n <= 0) return;
-  const size_t pp = (size_t)max_p * max_p;
+  const size_t pp = (size_t)max_p * dk_ld(max_p);   // p dk_ld(p) does not decrease with p
   const size_t budget = (LDS_LIMIT - 4096) / sizeof(T);
   size_t elems = pp;
   if (3 * pp <= budget) elems = 3 * pp;
