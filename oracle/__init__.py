@@ -17,7 +17,10 @@ It is a plain, slow, step-by-step restatement of:
     eq:lowner);
   * the per-block rectification of penalties (App. D, "Hyperparameter
     policy", last paragraph);
-  * the final-residual training loss used by the batched max-cut workload.
+  * the final-residual training loss used by the batched max-cut workload;
+  * the comparison backward rules of the PSD projection: the eigendecomposition
+    rule (eq:psd-cotangent), Tikhonov-shifted and Newton-Schulz
+    (eq:newton-schulz) variants.
 
 Precision: float64 throughout.  The linear system is solved exactly with a
 sparse LU factorisation (scipy SuperLU), the tol -> 0 limit of the paper's CG.
@@ -31,11 +34,13 @@ from .cosmo import (Hyper, step_forward, unroll_forward, unroll_backward, residu
                     residual_loss_grad, kkt_residuals, solve_reduced, reduced_matrix,
                     implicit_solve_vjp, step_backward, run_fixed)
 from .fd import fd_check_unroll, fd_directional
+from .psd_rules import psd_vjp_tikhonov, ns_forward, ns_vjp, psd_vjp_ns
 
 __all__ = [
     "svec", "smat", "svec_len", "order_from_len",
     "rectify", "rectify_adjoint", "proj_cone", "proj_cone_vjp", "proj_soc", "proj_soc_vjp",
     "proj_psd", "psd_vjp_dk", "lowner_matrix", "proj_nonneg", "psd_vjp_naive",
+    "psd_vjp_tikhonov", "ns_forward", "ns_vjp", "psd_vjp_ns",
     "Hyper", "step_forward", "unroll_forward", "unroll_backward", "residual_loss",
     "residual_loss_grad", "kkt_residuals", "solve_reduced", "reduced_matrix",
     "implicit_solve_vjp", "step_backward", "run_fixed",
