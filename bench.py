@@ -173,6 +173,67 @@ def _copy_calibration():
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "dispatches": 5}))
 
 
+def psd_rules_study(samples=100, orders=(10, 20, 40, 80, 160, 320), delta=1e-5, ns_iters=20, reps=5):
+    """Backward cost of the PSD-projection rules against the matrix order (the
+    appendix's timing experiment): `samples` matrices per order from the App.
+    C sampler at gap `delta`, one batched call per rule, HIP events on the
+    launching stream.  DK, the eigendecomposition rule and Tikhonov reuse one
+    decomposition (orders the eigensolver takes, <= 200 in float32);
+    Newton-Schulz runs `ns_iters` steps forward, then its reverse pass is
+    timed.  Prints one JSON line."""
+    import torch
+    from paper_2606_13825_amd import NewtonSchulzProj, psd_proj, psd_proj_vjp_rule
+    from synth import svec_of_dense
+    from synth.workloads import appc_matrix
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(7)
+    rows, ns_roof = [], None
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    for n in orders:
+        mats = [appc_matrix(n, delta, rng)[0] for _ in range(samples)]
+        x = np.concatenate([svec_of_dense(m) for m in mats]).astype(np.float32)
+        g = rng.standard_normal(x.shape).astype(np.float32)
+        xt, gt = torch.from_numpy(x).to(dev), torch.from_numpy(g).to(dev)
+        ords = [n] * samples
+        row = {"order": n}
+        if n <= 200:
+            row["eigh_fwd_ms"] = timed(lambda: psd_proj(xt, ords, max_sweeps=60))
+            _, lam, U = psd_proj(xt, ords, max_sweeps=60)
+            for rule, eps in (("dk", 0.0), ("naive", 0.0), ("tikhonov", 1e-3), ("tikhonov", 1e-6)):
+                key = rule if rule != "tikhonov" else f"tikhonov_{eps:.0e}"
+                row[f"{key}_bwd_ms"] = timed(lambda: psd_proj_vjp_rule(lam, U, gt, ords, rule=rule, eps=eps))
+        ns = NewtonSchulzProj(ords, ns_iters, torch.float32, dev)
+        row["ns_fwd_ms"] = timed(lambda: ns.forward(xt))
+        gin = torch.empty_like(gt)
+        row["ns_bwd_ms"] = timed(lambda: ns.vjp(gt, gin))
+        # reverse pass: 4 products per step plus 2 at the output, 2 p^3 flops each
+        flops = samples * (4 * ns_iters + 2) * 2.0 * n ** 3
+        row["ns_bwd_tflops"] = flops / (row["ns_bwd_ms"] * 1e-3) / 1e12
+        rows.append(row)
+        ns_roof = {"kernel": "k_ns_gemm<float> (Newton-Schulz reverse pass)", "order": n, "bound": "mfma",
+                   "achieved": row["ns_bwd_tflops"], "peak": 157.3, "unit": "TFLOP/s",
+                   "frac": row["ns_bwd_tflops"] / 157.3, "traffic": None}
+        print(f"[bench] psd rules order {n}: " + ", ".join(f"{k}={v:.3f}" for k, v in row.items() if k != "order"),
+              file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "PSD-projection backward time per batch by rule (App. C matrices)",
+                      "unit": "ms", "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": f"appc_delta{delta:g}_x{samples}", "samples": samples,
+                                 "ns_iters": ns_iters, "reps": reps},
+                      "rows": rows, "roofline": ns_roof}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,7 +250,12 @@ def main():
     ap.add_argument("--quick", action="store_true",
                     help="counter-collection run: the timed steps only (no plain-forward comparison, "
                          "no event-timed step, no CPU leg)")
+    ap.add_argument("--study", default=None, choices=["psd_rules"],
+                    help="psd_rules: backward time of the PSD-projection rules against the matrix order")
     args = ap.parse_args()
+    if args.study == "psd_rules" and args.gpus == 1:
+        psd_rules_study()
+        return
     if args.quick:
         args.no_cpu_baseline = True
         args.no_plain = True

@@ -216,6 +216,48 @@ cosmo_status psd_proj_vjp(int32_t nblk, const int32_t *order, const int64_t *off
                           const void *eigvals, const void *eigvecs, const void *gout, void *gin, void *ws,
                           void *stream);
 
+/* Comparison backward rules of the PSD projection (Sec. "Differentiating
+ * Through the PSD Projection", paragraph "Alternative Approaches", and the
+ * appendix on the PSD backward experiments).  Same arguments, layout and
+ * errors as psd_proj_vjp, plus:
+ *   rule COSMO_PSD_RULE_DK (0): eq:psd-cotangent-dk, identical to psd_proj_vjp;
+ *   rule COSMO_PSD_RULE_NAIVE (1): eq:psd-cotangent with the cotangents that
+ *     reverse mode gives U and L for U max(L, 0) U', F_ij = 1/(l_j - l_i)
+ *     formed as written: on tied eigenvalues the result is inf or NaN, on
+ *     close ones it loses accuracy (this is the rule's behaviour, not an
+ *     error: no status reports it);
+ *   rule COSMO_PSD_RULE_TIKHONOV (2): rule 1 for the projection of S + eps I,
+ *     from the decomposition of S (same U, eigenvalues l + eps).
+ * eps (finite) is read by rule 2 only.  Unknown rule: COSMO_EINVAL. */
+#define COSMO_PSD_RULE_DK 0
+#define COSMO_PSD_RULE_NAIVE 1
+#define COSMO_PSD_RULE_TIKHONOV 2
+cosmo_status psd_proj_vjp_rule(int32_t nblk, const int32_t *order, const int64_t *offset, cosmo_dtype dtype,
+                               int32_t rule, double eps, const void *eigvals, const void *eigvecs, const void *gout,
+                               void *gin, void *ws, void *stream);
+
+/* Newton-Schulz comparison rule (eq:newton-schulz): the projection
+ * Pi(S) = (S + sign(S) S) / 2 with sign(S) approximated by `iters` steps of
+ * S_{k+1} = S_k (3 I - S_k^2) / 2 from S_0 = S / ||S||_F, and the reverse pass
+ * through those unrolled products.  Blocks as for psd_proj (svec rows at
+ * `offset`, order p <= COSMO_NS_MAX_ORDER, 0 <= iters <= COSMO_NS_MAX_ITERS);
+ * out = svec of the symmetric part of Pi, gin = the input cotangent for the
+ * output cotangent gout.
+ * `tape` (device, caller-owned, psd_ns_tape_size bytes for the same blocks,
+ * dtype and iters, 8-byte aligned) holds block descriptors, the norms and
+ * (2 iters + 8) p^2 elements per block: every iterate and its square, kept by
+ * psd_proj_ns for psd_proj_ns_vjp, which must follow with the same blocks,
+ * dtype and iters on the same stream.  psd_proj_ns copies the descriptors in
+ * and waits for that copy; both are otherwise stream-asynchronous.
+ * psd_ns_tape_size returns 0 for invalid arguments. */
+#define COSMO_NS_MAX_ORDER 1024
+#define COSMO_NS_MAX_ITERS 200
+size_t psd_ns_tape_size(int32_t nblk, const int32_t *order, cosmo_dtype dtype, int32_t iters);
+cosmo_status psd_proj_ns(int32_t nblk, const int32_t *order, const int64_t *offset, cosmo_dtype dtype,
+                         int32_t iters, const void *in, void *out, void *tape, void *stream);
+cosmo_status psd_proj_ns_vjp(int32_t nblk, const int32_t *order, const int64_t *offset, cosmo_dtype dtype,
+                             int32_t iters, const void *gout, void *gin, void *tape, void *stream);
+
 /* Projection onto SOC blocks (t, w) of `dim` rows (closed form), and its VJP
  * (J is symmetric: identity inside the cone, zero inside its polar, else
  * 1/2 [[1, u'], [u, (1 + t/|w|) I - (t/|w|) u u']] with u = w/|w|). */

@@ -23,7 +23,10 @@ EXPORTED = [
     "cosmo_plan_set_profiling", "cosmo_plan_profile_read",
     "cosmo_plan_set_pcg_form", "cosmo_plan_get_pcg_form", "cosmo_plan_autotune",
     "cosmo_plan_set_graph", "cosmo_plan_get_graph",
+    "psd_proj_vjp_rule", "psd_ns_tape_size", "psd_proj_ns", "psd_proj_ns_vjp",
 ]
+
+PSD_RULES = {"dk": 0, "naive": 1, "tikhonov": 2}
 
 
 class CosmoProblem(ctypes.Structure):
@@ -112,6 +115,14 @@ def _sig(lib):
     lib.psd_proj.argtypes = [i32, P32, P64, ctypes.c_int, vp, vp, vp, vp, i32, dbl, i32, vp, vp]
     lib.psd_proj_vjp.restype = ctypes.c_int
     lib.psd_proj_vjp.argtypes = [i32, P32, P64, ctypes.c_int, vp, vp, vp, vp, vp, vp]
+    lib.psd_proj_vjp_rule.restype = ctypes.c_int
+    lib.psd_proj_vjp_rule.argtypes = [i32, P32, P64, ctypes.c_int, i32, dbl, vp, vp, vp, vp, vp, vp]
+    lib.psd_ns_tape_size.restype = sz
+    lib.psd_ns_tape_size.argtypes = [i32, P32, ctypes.c_int, i32]
+    lib.psd_proj_ns.restype = ctypes.c_int
+    lib.psd_proj_ns.argtypes = [i32, P32, P64, ctypes.c_int, i32, vp, vp, vp, vp]
+    lib.psd_proj_ns_vjp.restype = ctypes.c_int
+    lib.psd_proj_ns_vjp.argtypes = [i32, P32, P64, ctypes.c_int, i32, vp, vp, vp, vp]
     lib.socp_proj.restype = ctypes.c_int
     lib.socp_proj.argtypes = [i32, P32, P64, ctypes.c_int, vp, vp, vp, vp]
     lib.socp_proj_vjp.restype = ctypes.c_int

@@ -399,6 +399,67 @@ def psd_proj_vjp(eigvals, eigvecs, gout: torch.Tensor, orders, offsets=None):
     return gin
 
 
+def psd_proj_vjp_rule(eigvals, eigvecs, gout: torch.Tensor, orders, rule: str = "dk", eps: float = 0.0,
+                      offsets=None):
+    """A comparison backward rule of psd_proj from its decomposition: "dk"
+    (eq:psd-cotangent-dk), "naive" (eq:psd-cotangent as autograd forms it) or
+    "tikhonov" (the naive rule for the projection of S + eps I)."""
+    orders = np.asarray(orders, np.int32)
+    if offsets is None:
+        offsets = np.concatenate([[0], np.cumsum([_psd_rows(int(p)) for p in orders])[:-1]])
+    offsets = np.asarray(offsets, np.int64)
+    gin = torch.empty_like(gout)
+    ws = _proj_ws(len(orders), orders, gout.device)
+    st = L.lib().psd_proj_vjp_rule(len(orders), orders.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dt_code(gout.dtype),
+                                   int(L.PSD_RULES[rule]), float(eps), _ptr(eigvals), _ptr(eigvecs),
+                                   _ptr(gout.contiguous()), _ptr(gin), _ptr(ws), _stream(gout.device))
+    L.check(st, "psd_proj_vjp_rule")
+    return gin
+
+
+class NewtonSchulzProj:
+    """The Newton-Schulz comparison rule (eq:newton-schulz) over a set of
+    svec blocks: forward() projects and keeps every iterate in a device tape,
+    vjp() runs the reverse pass through the unrolled products."""
+
+    def __init__(self, orders, iters: int, dtype=torch.float32, device="cuda:0", offsets=None):
+        self.orders = np.asarray(orders, np.int32)
+        if offsets is None:
+            offsets = np.concatenate([[0], np.cumsum([_psd_rows(int(p)) for p in self.orders])[:-1]])
+        self.offsets = np.asarray(offsets, np.int64)
+        self.iters, self.dtype, self.device = int(iters), dtype, torch.device(device)
+        nb = L.lib().psd_ns_tape_size(len(self.orders), self._o(), _dt_code(dtype), self.iters)
+        if nb == 0:
+            raise L.CosmoError(L.COSMO_EINVAL, "psd_ns_tape_size", "invalid blocks, dtype or step count")
+        self.tape = torch.empty(int(nb), dtype=torch.uint8, device=self.device)
+        self._ready = False
+
+    def _o(self):
+        return self.orders.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+    def _off(self):
+        return self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        assert x.dtype == self.dtype and x.device == self.device
+        out = torch.empty_like(x)
+        st = L.lib().psd_proj_ns(len(self.orders), self._o(), self._off(), _dt_code(x.dtype), self.iters,
+                                 _ptr(x.contiguous()), _ptr(out), _ptr(self.tape), _stream(x.device))
+        L.check(st, "psd_proj_ns")
+        self._ready = True
+        return out
+
+    def vjp(self, gout: torch.Tensor, gin: Optional[torch.Tensor] = None) -> torch.Tensor:
+        if not self._ready:
+            raise RuntimeError("NewtonSchulzProj.vjp needs a forward() first")
+        gin = torch.empty_like(gout) if gin is None else gin
+        st = L.lib().psd_proj_ns_vjp(len(self.orders), self._o(), self._off(), _dt_code(gout.dtype), self.iters,
+                                     _ptr(gout.contiguous()), _ptr(gin), _ptr(self.tape), _stream(gout.device))
+        L.check(st, "psd_proj_ns_vjp")
+        return gin
+
+
 def socp_proj(x: torch.Tensor, dims: Sequence[int], offsets=None):
     dims = np.asarray(dims, np.int32)
     if offsets is None:

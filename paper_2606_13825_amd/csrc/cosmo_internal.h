@@ -156,8 +156,39 @@ template <typename T> void launch_psd_step(const PsdDesc *d, int32_t n, const Ps
                                            const T *rho_hat, const T *vv, const T *sh, const T *y, T *s_new,
                                            T *y_new, T *U, T *lam, double *rscratch, const T *Uprev,
                                            cosmo_stats *stats, hipStream_t st);
+// rule 0 = Daleckii-Krein, 1 = eigendecomposition rule as autograd forms it,
+// 2 = rule 1 at the eigenvalues shifted by eps (Tikhonov)
 template <typename T> void launch_psd_vjp(const PsdDesc *d, int32_t n, int32_t max_p, const T *U, const T *lam,
-                                          const T *g, T *out, T *scratch, hipStream_t st);
+                                          const T *g, T *out, T *scratch, hipStream_t st, int32_t rule = 0,
+                                          double eps = 0.0);
+
+// Newton-Schulz comparison rule: one block of the tape.
+struct NsDesc {
+  int64_t row0;    // first row of its svec in the input / output vectors
+  int64_t moff;    // element offset of its matrix area in the tape
+  int32_t p;       // matrix order
+  int32_t tile0;   // index of its first 32 x 32 tile in a product launch
+};
+// One product C = alpha op(A) op(B) + beta D over every block (slots of the
+// block's matrix area; d = -1: no D term; ta / tb: transpose A / B).
+struct NsGemm {
+  int32_t a, b, c, d, ta, tb;
+  double alpha, beta;
+};
+// Slots of a block's matrix area for K steps: X_0..X_K, Q_0..Q_{K-1}, then
+// S, W (forward output), TB, SB, Y, Z, QB (reverse pass).
+struct NsSlots {
+  int32_t K, S, W, TB, SB, Y, Z, QB;
+  explicit NsSlots(int32_t k)
+      : K(k), S(2 * k + 1), W(2 * k + 2), TB(2 * k + 3), SB(2 * k + 4), Y(2 * k + 5), Z(2 * k + 6), QB(2 * k + 7) {}
+  int32_t x(int32_t k) const { return k; }
+  int32_t q(int32_t k) const { return K + 1 + k; }
+  static int64_t count(int32_t k) { return 2 * (int64_t)k + 8; }
+};
+template <typename T> void launch_ns_forward(const NsDesc *d, int32_t nblk, int32_t ntiles, int32_t K, const T *v,
+                                             T *out, T *base, double *cnorm, hipStream_t st);
+template <typename T> void launch_ns_vjp(const NsDesc *d, int32_t nblk, int32_t ntiles, int32_t K, const T *g,
+                                         T *gin, T *base, const double *cnorm, hipStream_t st);
 
 // bookkeeping for profiling: kernel-family events
 void set_last_error(const std::string &msg);

@@ -849,13 +849,35 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
 // all 16 on one bank.
 __host__ __device__ constexpr int dk_ld(int p) { return p + ((4 - p % 8) + 8) % 8; }
 
-// DK VJP: out = svec(U (L o (U' smat(g) U)) U').  Buffers: B0 and B1 (p x p,
-// stride dk_ld(p)) in LDS when they fit, else B1 in global scratch (stride
-// p); U read from LDS when a third buffer fits, else from global memory.
+// Weight of entry (i, j) of U' smat(g) U in the input cotangent.
+//   rule 0 (DK, eq:lowner): divided differences of max(., 0), f' on ties,
+//     f'(0) = 0.
+//   rule 1 (eq:psd-cotangent as autograd evaluates it on U max(L, 0) U', then
+//     symmetrised by the svec adjoint): f'(l_i) on the diagonal, else
+//     f(l_j) / (l_j - l_i) + f(l_i) / (l_i - l_j) with both quotients formed,
+//     so a tie gives inf - inf or 0 / 0 and close eigenvalues cancel.
+//   rule 2 (Tikhonov): rule 1 at the eigenvalues of S + eps I.
+template <typename T> __device__ inline T vjp_weight(int rule, T li, T lj, bool diag, T eps) {
+  if (rule == 0) {
+    if (li > (T)0 && lj > (T)0) return (T)1;
+    if (li <= (T)0 && lj <= (T)0) return (T)0;
+    return fmax(li, lj) / (fabs(li) + fabs(lj));
+  }
+  const T a = li + eps, b = lj + eps;
+  if (diag) return a > (T)0 ? (T)1 : (T)0;
+  const T fa = fmax(a, (T)0), fb = fmax(b, (T)0);
+  return fb / (b - a) + fa / (a - b);
+}
+
+// PSD VJP: out = svec(U (W o (U' smat(g) U)) U'), W from vjp_weight.  Buffers:
+// B0 and B1 (p x p, stride dk_ld(p)) in LDS when they fit, else B1 in global
+// scratch (stride p); U read from LDS when a third buffer fits, else from
+// global memory.
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_psd_vjp(const PsdDesc *__restrict__ descs, const T *__restrict__ Ug,
                                                 const T *__restrict__ lam, const T *__restrict__ g,
-                                                T *__restrict__ out, T *__restrict__ scratch, int32_t lds_elems) {
+                                                T *__restrict__ out, T *__restrict__ scratch, int32_t lds_elems,
+                                                int32_t rule, T eps) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *lds = reinterpret_cast<T *>(smem_raw);
   __shared__ T lam_s[MAXP];
@@ -907,7 +929,7 @@ __global__ __launch_bounds__(NT) void k_psd_vjp(const PsdDesc *__restrict__ desc
     }
   }
   __syncthreads();
-  // B0 = L o (U' B1)
+  // B0 = W o (U' B1)
   for (int t = wave; t < nt * nt; t += NWv) {
     const int I = t / nt, J = t % nt;
     auto fa = [&](int i, int k) -> T { return (i < p && k < p) ? U[k + i * lu] : (T)0; };
@@ -917,14 +939,7 @@ __global__ __launch_bounds__(NT) void k_psd_vjp(const PsdDesc *__restrict__ desc
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int row = I * 16 + Mma<T>::row(lane, e);
-      if (row < p && col < p) {
-        const T li = lam_s[row], lj = lam_s[col];
-        T L;
-        if (li > (T)0 && lj > (T)0) L = (T)1;
-        else if (li <= (T)0 && lj <= (T)0) L = (T)0;
-        else L = fmax(li, lj) / (fabs(li) + fabs(lj));
-        B0[row + col * l0] = L * acc[e];
-      }
+      if (row < p && col < p) B0[row + col * l0] = vjp_weight<T>(rule, lam_s[row], lam_s[col], row == col, eps) * acc[e];
     }
   }
   __syncthreads();
@@ -960,6 +975,137 @@ __global__ __launch_bounds__(NT) void k_psd_vjp(const PsdDesc *__restrict__ desc
         ob[idx] = (row == col) ? acc[e] : acc[e] * (T)SQRT2;
       }
     }
+  }
+}
+
+// ---- Newton-Schulz comparison rule (eq:newton-schulz) ----------------------
+// Matrices live in a caller tape, column-major p x p per block, addressed by
+// slot: base + d.moff + slot p^2.
+
+// C = alpha op(A) op(B) + beta D over every block; one workgroup of four
+// waves per 32 x 32 tile of C, each wave one 16 x 16 matrix-core tile.
+// op(X) = X' when the flag is set.  D may be C itself (each element is read
+// and written by the lane that owns it); A and B are never C.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ns_gemm(const NsDesc *__restrict__ descs, int32_t nblk, T *base,
+                                                 NsGemm g) {
+  const int t = blockIdx.x;
+  int lo = 0, hi = nblk - 1;                 // last block with tile0 <= t
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].tile0 <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  const NsDesc d = descs[lo];
+  const int p = d.p, nt = (p + 31) / 32, lt = t - d.tile0;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int I = (lt / nt) * 2 + (wave >> 1), J = (lt % nt) * 2 + (wave & 1);
+  if (I * 16 >= p || J * 16 >= p) return;
+  const size_t pp = (size_t)p * p;
+  T *blk = base + d.moff;
+  const T *A = blk + g.a * pp, *B = blk + g.b * pp;
+  T *C = blk + g.c * pp;
+  const T *D = g.d >= 0 ? blk + g.d * pp : nullptr;
+  const bool ta = g.ta, tb = g.tb;
+  auto fa = [&](int i, int k) -> T { return (i < p && k < p) ? (ta ? A[k + (size_t)i * p] : A[i + (size_t)k * p]) : (T)0; };
+  auto fb = [&](int k, int j) -> T { return (k < p && j < p) ? (tb ? B[j + (size_t)k * p] : B[k + (size_t)j * p]) : (T)0; };
+  const typename Mma<T>::v4 acc = tile_mma<T>(I * 16, J * 16, p, fa, fb);
+  const int col = J * 16 + (lane & 15);
+  const T alpha = (T)g.alpha, beta = (T)g.beta;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int row = I * 16 + Mma<T>::row(lane, e);
+    if (row < p && col < p) {
+      const size_t o = row + (size_t)col * p;
+      C[o] = D ? alpha * acc[e] + beta * D[o] : alpha * acc[e];
+    }
+  }
+}
+
+// Forward set-up, one workgroup per block: c = ||smat(v)||_F = ||v||_2,
+// slot S = smat(v), slot X_0 = S / c.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ns_init(const NsDesc *__restrict__ descs, const T *__restrict__ v,
+                                                 T *base, double *cnorm, int32_t slot_x0, int32_t slot_s) {
+  __shared__ double red[256 / 64];
+  const NsDesc d = descs[blockIdx.x];
+  const int p = d.p, nrows = p * (p + 1) / 2;
+  const T *vb = v + d.row0;
+  double ss = 0.0;
+  for (int idx = threadIdx.x; idx < nrows; idx += 256) {
+    const double x = (double)vb[idx];
+    ss += x * x;
+  }
+  const double c = sqrt(wg_sum<double, 256>(ss, red));
+  if (threadIdx.x == 0) cnorm[blockIdx.x] = c;
+  const size_t pp = (size_t)p * p;
+  T *S = base + d.moff + slot_s * pp, *X = base + d.moff + slot_x0 * pp;
+  const T inv = (T)(1.0 / c);
+  for (int idx = threadIdx.x; idx < nrows; idx += 256) {
+    const int j = svec_col(idx);
+    const int i = idx - j * (j + 1) / 2;
+    const T val = (i == j) ? vb[idx] : vb[idx] * (T)RSQRT2;
+    S[i + (size_t)j * p] = val;
+    S[j + (size_t)i * p] = val;
+    X[i + (size_t)j * p] = val * inv;
+    X[j + (size_t)i * p] = val * inv;
+  }
+}
+
+// out = svec of the symmetric part of slot W.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ns_pack(const NsDesc *__restrict__ descs, const T *base, int32_t slot_w,
+                                                 T *__restrict__ out) {
+  const NsDesc d = descs[blockIdx.x];
+  const int p = d.p, nrows = p * (p + 1) / 2;
+  const T *W = base + d.moff + slot_w * (size_t)p * p;
+  for (int idx = threadIdx.x; idx < nrows; idx += 256) {
+    const int j = svec_col(idx);
+    const int i = idx - j * (j + 1) / 2;
+    out[d.row0 + idx] = (i == j) ? W[i + (size_t)i * p]
+                                 : (W[i + (size_t)j * p] + W[j + (size_t)i * p]) * (T)(0.5 * SQRT2);
+  }
+}
+
+// slot TB = smat(g).
+template <typename T>
+__global__ __launch_bounds__(256) void k_ns_unpack(const NsDesc *__restrict__ descs, const T *__restrict__ g,
+                                                   T *base, int32_t slot_t) {
+  const NsDesc d = descs[blockIdx.x];
+  const int p = d.p, nrows = p * (p + 1) / 2;
+  T *Tb = base + d.moff + slot_t * (size_t)p * p;
+  for (int idx = threadIdx.x; idx < nrows; idx += 256) {
+    const int j = svec_col(idx);
+    const int i = idx - j * (j + 1) / 2;
+    const T val = (i == j) ? g[d.row0 + idx] : g[d.row0 + idx] * (T)RSQRT2;
+    Tb[i + (size_t)j * p] = val;
+    Tb[j + (size_t)i * p] = val;
+  }
+}
+
+// Reverse of S_0 = S / c and of smat: Sbar += Y / c - <Y, S> S / c^3 with
+// Y = cotangent of S_0, then gin = svec of the symmetric part of Sbar.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ns_final(const NsDesc *__restrict__ descs, const T *base,
+                                                  const double *cnorm, int32_t slot_y, int32_t slot_s,
+                                                  int32_t slot_sb, T *__restrict__ gin) {
+  __shared__ double red[256 / 64];
+  const NsDesc d = descs[blockIdx.x];
+  const int p = d.p, nrows = p * (p + 1) / 2;
+  const size_t pp = (size_t)p * p;
+  const T *Y = base + d.moff + slot_y * pp, *S = base + d.moff + slot_s * pp, *SB = base + d.moff + slot_sb * pp;
+  double dot = 0.0;
+  for (size_t e = threadIdx.x; e < pp; e += 256) dot += (double)Y[e] * (double)S[e];
+  dot = wg_sum<double, 256>(dot, red);
+  const double c = cnorm[blockIdx.x];
+  const T ic = (T)(1.0 / c), k3 = (T)(dot / (c * c * c));
+  for (int idx = threadIdx.x; idx < nrows; idx += 256) {
+    const int j = svec_col(idx);
+    const int i = idx - j * (j + 1) / 2;
+    const size_t a = i + (size_t)j * p, b = j + (size_t)i * p;
+    const T ga = SB[a] + Y[a] * ic - k3 * S[a];
+    if (i == j) gin[d.row0 + idx] = ga;
+    else gin[d.row0 + idx] = (ga + SB[b] + Y[b] * ic - k3 * S[b]) * (T)RSQRT2;
   }
 }
 
@@ -1018,7 +1164,7 @@ void launch_psd_step(const PsdDesc *d, int32_t n, const PsdLaunchCfg &cfg, const
 
 template <typename T>
 void launch_psd_vjp(const PsdDesc *d, int32_t n, int32_t max_p, const T *U, const T *lam, const T *g, T *out,
-                    T *scratch, hipStream_t st) {
+                    T *scratch, hipStream_t st, int32_t rule, double eps) {
   if (n <= 0) return;
   const size_t pp = (size_t)max_p * dk_ld(max_p);   // p dk_ld(p) does not decrease with p
   const size_t budget = (LDS_LIMIT - 4096) / sizeof(T);
@@ -1030,7 +1176,43 @@ void launch_psd_vjp(const PsdDesc *d, int32_t n, int32_t max_p, const T *U, cons
     set_dyn_lds_cap(reinterpret_cast<const void *>(&k_psd_vjp<T, 512>));
     attr_set = true;
   }
-  k_psd_vjp<T, 512><<<n, 512, elems * sizeof(T), st>>>(d, U, lam, g, out, scratch, (int32_t)elems);
+  k_psd_vjp<T, 512><<<n, 512, elems * sizeof(T), st>>>(d, U, lam, g, out, scratch, (int32_t)elems, rule, (T)eps);
+}
+
+// Newton-Schulz forward: K steps of eq:newton-schulz, every iterate X_k and
+// square Q_k kept in the tape for the reverse pass, then
+// out = svec(sym((S + X_K S) / 2)).
+template <typename T>
+void launch_ns_forward(const NsDesc *d, int32_t nblk, int32_t ntiles, int32_t K, const T *v, T *out, T *base,
+                       double *cnorm, hipStream_t st) {
+  const NsSlots sl(K);
+  k_ns_init<T><<<nblk, 256, 0, st>>>(d, v, base, cnorm, sl.x(0), sl.S);
+  for (int k = 0; k < K; ++k) {
+    k_ns_gemm<T><<<ntiles, 256, 0, st>>>(d, nblk, base, NsGemm{sl.x(k), sl.x(k), sl.q(k), -1, 0, 0, 1.0, 0.0});
+    k_ns_gemm<T><<<ntiles, 256, 0, st>>>(d, nblk, base, NsGemm{sl.x(k), sl.q(k), sl.x(k + 1), sl.x(k), 0, 0, -0.5, 1.5});
+  }
+  k_ns_gemm<T><<<ntiles, 256, 0, st>>>(d, nblk, base, NsGemm{sl.x(K), sl.S, sl.W, sl.S, 0, 0, 0.5, 0.5});
+  k_ns_pack<T><<<nblk, 256, 0, st>>>(d, base, sl.W, out);
+}
+
+// Newton-Schulz reverse pass from the tape of launch_ns_forward (same blocks
+// and K): for C = A B, Abar = Cbar B' and Bbar = A' Cbar.
+template <typename T>
+void launch_ns_vjp(const NsDesc *d, int32_t nblk, int32_t ntiles, int32_t K, const T *g, T *gin, T *base,
+                   const double *cnorm, hipStream_t st) {
+  const NsSlots sl(K);
+  k_ns_unpack<T><<<nblk, 256, 0, st>>>(d, g, base, sl.TB);
+  // Pi = S / 2 + X_K S / 2
+  k_ns_gemm<T><<<ntiles, 256, 0, st>>>(d, nblk, base, NsGemm{sl.x(K), sl.TB, sl.SB, sl.TB, 1, 0, 0.5, 0.5});
+  k_ns_gemm<T><<<ntiles, 256, 0, st>>>(d, nblk, base, NsGemm{sl.TB, sl.S, sl.Y, -1, 0, 1, 0.5, 0.0});
+  for (int k = K - 1; k >= 0; --k) {
+    // X_{k+1} = 3/2 X_k - 1/2 X_k Q_k with Q_k = X_k X_k; Y = cotangent of X_{k+1}
+    k_ns_gemm<T><<<ntiles, 256, 0, st>>>(d, nblk, base, NsGemm{sl.Y, sl.q(k), sl.Z, sl.Y, 0, 1, -0.5, 1.5});
+    k_ns_gemm<T><<<ntiles, 256, 0, st>>>(d, nblk, base, NsGemm{sl.x(k), sl.Y, sl.QB, -1, 1, 0, -0.5, 0.0});
+    k_ns_gemm<T><<<ntiles, 256, 0, st>>>(d, nblk, base, NsGemm{sl.QB, sl.x(k), sl.Z, sl.Z, 0, 1, 1.0, 1.0});
+    k_ns_gemm<T><<<ntiles, 256, 0, st>>>(d, nblk, base, NsGemm{sl.x(k), sl.QB, sl.Y, sl.Z, 1, 0, 1.0, 1.0});
+  }
+  k_ns_final<T><<<nblk, 256, 0, st>>>(d, base, cnorm, sl.Y, sl.S, sl.SB, gin);
 }
 
 template void launch_psd_step<float>(const PsdDesc *, int32_t, const PsdLaunchCfg &, const float *, const float *,
@@ -1040,8 +1222,16 @@ template void launch_psd_step<double>(const PsdDesc *, int32_t, const PsdLaunchC
                                       const double *, const double *, const double *, double *, double *, double *,
                                       double *, double *, const double *, cosmo_stats *, hipStream_t);
 template void launch_psd_vjp<float>(const PsdDesc *, int32_t, int32_t, const float *, const float *, const float *,
-                                    float *, float *, hipStream_t);
+                                    float *, float *, hipStream_t, int32_t, double);
 template void launch_psd_vjp<double>(const PsdDesc *, int32_t, int32_t, const double *, const double *,
-                                     const double *, double *, double *, hipStream_t);
+                                     const double *, double *, double *, hipStream_t, int32_t, double);
+template void launch_ns_forward<float>(const NsDesc *, int32_t, int32_t, int32_t, const float *, float *, float *,
+                                       double *, hipStream_t);
+template void launch_ns_forward<double>(const NsDesc *, int32_t, int32_t, int32_t, const double *, double *,
+                                        double *, double *, hipStream_t);
+template void launch_ns_vjp<float>(const NsDesc *, int32_t, int32_t, int32_t, const float *, float *, float *,
+                                   const double *, hipStream_t);
+template void launch_ns_vjp<double>(const NsDesc *, int32_t, int32_t, int32_t, const double *, double *, double *,
+                                    const double *, hipStream_t);
 
 }  // namespace cosmo

@@ -1160,6 +1160,16 @@ cosmo_status psd_proj(int32_t nblk, const int32_t *order, const int64_t *offset,
 cosmo_status psd_proj_vjp(int32_t nblk, const int32_t *order, const int64_t *offset, cosmo_dtype dtype,
                           const void *eigvals, const void *eigvecs, const void *gout, void *gin, void *ws,
                           void *stream) {
+  return psd_proj_vjp_rule(nblk, order, offset, dtype, COSMO_PSD_RULE_DK, 0.0, eigvals, eigvecs, gout, gin, ws,
+                           stream);
+}
+
+cosmo_status psd_proj_vjp_rule(int32_t nblk, const int32_t *order, const int64_t *offset, cosmo_dtype dtype,
+                               int32_t rule, double eps, const void *eigvals, const void *eigvecs, const void *gout,
+                               void *gin, void *ws, void *stream) {
+  if (rule < COSMO_PSD_RULE_DK || rule > COSMO_PSD_RULE_TIKHONOV) FAIL(COSMO_EINVAL, "unknown PSD backward rule");
+  if (!std::isfinite(eps)) FAIL(COSMO_EINVAL, "eps must be finite");
+  if (rule != COSMO_PSD_RULE_TIKHONOV) eps = 0.0;
   if (!eigvals || !eigvecs || !gout || !gin) FAIL(COSMO_EINVAL, "eigvals, eigvecs, gout and gin are required");
   hipStream_t st = static_cast<hipStream_t>(stream);
   std::vector<PsdDesc> descs;
@@ -1175,11 +1185,106 @@ cosmo_status psd_proj_vjp(int32_t nblk, const int32_t *order, const int64_t *off
     if (!n) continue;
     if (dtype == COSMO_F32)
       launch_psd_vjp<float>(d + cb[c], n, cm[c], (const float *)eigvecs, (const float *)eigvals, (const float *)gout,
-                            (float *)gin, (float *)scratch, st);
+                            (float *)gin, (float *)scratch, st, rule, eps);
     else
       launch_psd_vjp<double>(d + cb[c], n, cm[c], (const double *)eigvecs, (const double *)eigvals,
-                             (const double *)gout, (double *)gin, (double *)scratch, st);
+                             (const double *)gout, (double *)gin, (double *)scratch, st, rule, eps);
   }
+  HIPCHK(hipGetLastError());
+  return COSMO_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Layout of a Newton-Schulz tape: block descriptors, the per-block norms,
+// then (2K + 8) p^2 elements per block.
+struct NsLayout {
+  std::vector<NsDesc> d;
+  int64_t ntiles = 0;
+  size_t off_c = 0, off_m = 0, bytes = 0;
+};
+
+cosmo_status ns_layout(int32_t nblk, const int32_t *order, const int64_t *offset, cosmo_dtype dt, int32_t iters,
+                       NsLayout &L) {
+  if (nblk < 1 || !order) FAIL(COSMO_EINVAL, "need nblk >= 1 and a host order array");
+  if (dt != COSMO_F32 && dt != COSMO_F64) FAIL(COSMO_EINVAL, "bad dtype");
+  if (iters < 0 || iters > COSMO_NS_MAX_ITERS) FAIL(COSMO_EINVAL, "Newton-Schulz step count out of range");
+  const size_t esz = dt == COSMO_F32 ? 4 : 8;
+  L.d.resize(nblk);
+  int64_t mo = 0, tiles = 0;
+  std::vector<std::pair<int64_t, int64_t>> ranges;
+  for (int b = 0; b < nblk; ++b) {
+    const int p = order[b];
+    if (p < 1 || p > COSMO_NS_MAX_ORDER) FAIL(p < 1 ? COSMO_EINVAL : COSMO_EUNSUPPORTED, "PSD order out of range");
+    const int64_t r0 = offset ? offset[b] : 0;
+    if (offset && r0 < 0) FAIL(COSMO_EINVAL, "negative offset");
+    const int nt = (p + 31) / 32;
+    L.d[b] = {r0, mo, p, (int32_t)tiles};
+    mo += NsSlots::count(iters) * p * p;
+    tiles += (int64_t)nt * nt;
+    if (tiles > INT32_MAX) FAIL(COSMO_EUNSUPPORTED, "too many product tiles");
+    if (offset) ranges.push_back({r0, r0 + (int64_t)p * (p + 1) / 2});
+  }
+  std::sort(ranges.begin(), ranges.end());
+  for (size_t i = 1; i < ranges.size(); ++i)
+    if (ranges[i].first < ranges[i - 1].second) FAIL(COSMO_EINVAL, "PSD blocks overlap");
+  L.ntiles = tiles;
+  L.off_c = align_up((size_t)nblk * sizeof(NsDesc), 256);
+  L.off_m = L.off_c + align_up((size_t)nblk * sizeof(double), 256);
+  L.bytes = L.off_m + (size_t)mo * esz;
+  return COSMO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t psd_ns_tape_size(int32_t nblk, const int32_t *order, cosmo_dtype dtype, int32_t iters) {
+  NsLayout L;
+  if (ns_layout(nblk, order, nullptr, dtype, iters, L) != COSMO_OK) return 0;
+  return L.bytes;
+}
+
+cosmo_status psd_proj_ns(int32_t nblk, const int32_t *order, const int64_t *offset, cosmo_dtype dtype,
+                         int32_t iters, const void *in, void *out, void *tape, void *stream) {
+  if (!offset || !in || !out || !tape) FAIL(COSMO_EINVAL, "offset, in, out and tape are required");
+  NsLayout L;
+  cosmo_status s = ns_layout(nblk, order, offset, dtype, iters, L);
+  if (s != COSMO_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char *t = static_cast<char *>(tape);
+  HIPCHK(hipMemcpyAsync(t, L.d.data(), (size_t)nblk * sizeof(NsDesc), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const NsDesc *d = reinterpret_cast<const NsDesc *>(t);
+  double *cn = reinterpret_cast<double *>(t + L.off_c);
+  if (dtype == COSMO_F32)
+    launch_ns_forward<float>(d, nblk, (int32_t)L.ntiles, iters, (const float *)in, (float *)out,
+                             reinterpret_cast<float *>(t + L.off_m), cn, st);
+  else
+    launch_ns_forward<double>(d, nblk, (int32_t)L.ntiles, iters, (const double *)in, (double *)out,
+                              reinterpret_cast<double *>(t + L.off_m), cn, st);
+  HIPCHK(hipGetLastError());
+  return COSMO_OK;
+}
+
+cosmo_status psd_proj_ns_vjp(int32_t nblk, const int32_t *order, const int64_t *offset, cosmo_dtype dtype,
+                             int32_t iters, const void *gout, void *gin, void *tape, void *stream) {
+  if (!offset || !gout || !gin || !tape) FAIL(COSMO_EINVAL, "offset, gout, gin and tape are required");
+  NsLayout L;
+  cosmo_status s = ns_layout(nblk, order, offset, dtype, iters, L);
+  if (s != COSMO_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char *t = static_cast<char *>(tape);
+  const NsDesc *d = reinterpret_cast<const NsDesc *>(t);
+  const double *cn = reinterpret_cast<const double *>(t + L.off_c);
+  if (dtype == COSMO_F32)
+    launch_ns_vjp<float>(d, nblk, (int32_t)L.ntiles, iters, (const float *)gout, (float *)gin,
+                         reinterpret_cast<float *>(t + L.off_m), cn, st);
+  else
+    launch_ns_vjp<double>(d, nblk, (int32_t)L.ntiles, iters, (const double *)gout, (double *)gin,
+                          reinterpret_cast<double *>(t + L.off_m), cn, st);
   HIPCHK(hipGetLastError());
   return COSMO_OK;
 }

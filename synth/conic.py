@@ -44,6 +44,14 @@ def svec_index(i: int, j: int) -> int:
     return j * (j + 1) // 2 + i
 
 
+def svec_of_dense(X: np.ndarray) -> np.ndarray:
+    """Encode a symmetric matrix in the svec layout of svec_index (upper
+    triangle column by column, off-diagonal entries times sqrt(2))."""
+    p = X.shape[0]
+    r, c = np.tril_indices(p)            # row-major lower = column-major upper of X'
+    return X[c, r] * np.where(r == c, 1.0, np.sqrt(2.0))
+
+
 @dataclass
 class ConicInstance:
     P: sp.csr_matrix          # n x n, symmetric, full storage (may be empty)

@@ -137,6 +137,39 @@ def test_null_arguments_rejected(L):
     assert lib.socp_proj(0, P32, P64, 0, None, None, None, None) == L.COSMO_EINVAL
 
 
+def test_comparison_rule_entry_points_validate_on_host(L):
+    lib = L.lib()
+    orders = np.array([3, 40], np.int32)
+    offs = np.array([0, 6], np.int64)
+    P32 = orders.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    P64 = offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    fake = ctypes.c_void_p(256)   # never dereferenced: every case fails before any device call
+    # unknown rule, non-finite eps, missing buffers
+    assert lib.psd_proj_vjp_rule(2, P32, P64, 0, 3, 0.0, fake, fake, fake, fake, fake, None) == L.COSMO_EINVAL
+    assert lib.psd_proj_vjp_rule(2, P32, P64, 0, -1, 0.0, fake, fake, fake, fake, fake, None) == L.COSMO_EINVAL
+    assert lib.psd_proj_vjp_rule(2, P32, P64, 0, 2, float("nan"), fake, fake, fake, fake, fake, None) == L.COSMO_EINVAL
+    assert lib.psd_proj_vjp_rule(2, P32, P64, 0, 1, 0.0, None, fake, fake, fake, fake, None) == L.COSMO_EINVAL
+    # Newton-Schulz: tape size is descriptors + norms + (2K + 8) p^2 elements
+    for dt, esz in ((0, 4), (1, 8)):
+        for K in (0, 5, 30):
+            nb = lib.psd_ns_tape_size(2, P32, dt, K)
+            mats = (2 * K + 8) * (9 + 1600) * esz
+            assert mats < nb <= mats + 512 + 256
+    assert lib.psd_ns_tape_size(2, P32, 0, -1) == 0
+    assert lib.psd_ns_tape_size(2, P32, 0, 201) == 0
+    assert lib.psd_ns_tape_size(0, P32, 0, 5) == 0
+    big = np.array([1025], np.int32)
+    assert lib.psd_ns_tape_size(1, big.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 0, 5) == 0
+    assert lib.psd_proj_ns(2, P32, P64, 0, -1, fake, fake, fake, None) == L.COSMO_EINVAL
+    assert lib.psd_proj_ns(2, P32, P64, 0, 5, None, fake, fake, None) == L.COSMO_EINVAL
+    assert lib.psd_proj_ns(2, P32, P64, 2, 5, fake, fake, fake, None) == L.COSMO_EINVAL
+    bad = np.array([0, 2], np.int64)   # block 1 overlaps block 0's six rows
+    assert lib.psd_proj_ns(2, P32, bad.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 0, 5, fake, fake, fake,
+                           None) == L.COSMO_EINVAL
+    assert lib.psd_proj_ns_vjp(2, P32, P64, 0, 5, fake, None, fake, None) == L.COSMO_EINVAL
+    assert lib.psd_proj_ns_vjp(2, P32, P64, 0, 300, fake, fake, fake, None) == L.COSMO_EINVAL
+
+
 def test_binding_fails_loudly_without_library(monkeypatch, L):
     monkeypatch.setattr(L, "_lib", None)
     monkeypatch.setattr(L, "LIB_PATH", "/nonexistent/libcosmo_unroll.so")
