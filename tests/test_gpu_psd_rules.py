@@ -164,3 +164,47 @@ def test_newton_schulz_zero_steps_and_reuse_with_other_sizes():
             assert rel_err(out[off:off + nr], ro) <= 1e-12
             assert rel_err(gin[off:off + nr], rg) <= 1e-11
             off += nr
+
+
+def test_rule_errors_against_finite_differences_over_the_gap():
+    """The appendix's accuracy experiment in float64: App. C matrices of order
+    40 with two eigenvalue clusters at +-delta/2, delta from 1 to 1e-10; each
+    rule's directional derivative <gin, E> against central differences of the
+    float64 projection along E.  DK and Newton-Schulz stay accurate at every
+    gap, the eigendecomposition rule stays finite on these (distinct)
+    eigenvalues, Tikhonov with eps = 1e-3 is biased once eps exceeds the gap."""
+    ensure_lib()
+    from paper_2606_13825_amd import NewtonSchulzProj, psd_proj_vjp_rule
+    rng = np.random.default_rng(16)
+    n, K = 40, 30
+    deltas = (1.0, 1e-2, 1e-4, 1e-6, 1e-8, 1e-10)
+    mats = [appc_matrix(n, d, rng)[0] for d in deltas]
+    G = [_sym(rng, n) for _ in deltas]
+    E = [[_sym(rng, n) for _ in range(3)] for _ in deltas]
+    orders = [n] * len(deltas)
+    x = torch.from_numpy(np.concatenate([oracle.svec(m) for m in mats])).to(DEV)
+    g = torch.from_numpy(np.concatenate([oracle.svec(m) for m in G])).to(DEV)
+    lam, U, _ = _decompose(mats, np.float64)
+    out = {r: psd_proj_vjp_rule(lam, U, g, orders, rule=r, eps=1e-3).cpu().numpy()
+           for r in ("dk", "naive", "tikhonov")}
+    ns = NewtonSchulzProj(orders, K, torch.float64, DEV)
+    ns.forward(x)
+    out["ns"] = ns.vjp(g).cpu().numpy()
+    nr = n * (n + 1) // 2
+    for b, (d, S, Gm) in enumerate(zip(deltas, mats, G)):
+        h = 1e-4 * d                  # no eigenvalue reaches 0 along the segment
+        errs = {r: 0.0 for r in out}
+        for Em in E[b]:
+            fd = (oracle.proj_psd(oracle.svec(S + h * Em))[0] - oracle.proj_psd(oracle.svec(S - h * Em))[0]) / (2 * h)
+            ref = oracle.svec(Gm) @ fd
+            for r, gin in out.items():
+                errs[r] = max(errs[r], abs(gin[b * nr:(b + 1) * nr] @ oracle.svec(Em) - ref) / abs(ref))
+        say(f"delta={d:.0e} " + " ".join(f"{r}={e:.2e}" for r, e in errs.items()))
+        # the differences themselves carry ~1e-6 (truncation of the curvature
+        # ~1/delta at step 1e-4 delta)
+        assert errs["dk"] <= 1e-5 and errs["ns"] <= 1e-5, (d, errs)
+        assert np.all(np.isfinite(out["naive"][b * nr:(b + 1) * nr]))
+        if d <= 1e-4:
+            assert errs["tikhonov"] >= 0.1, (d, errs)
+        if d == 1.0:
+            assert errs["tikhonov"] <= 1e-2, (d, errs)
