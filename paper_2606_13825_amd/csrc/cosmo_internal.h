@@ -162,12 +162,12 @@ template <typename T> void launch_psd_vjp(const PsdDesc *d, int32_t n, int32_t m
                                           const T *g, T *out, T *scratch, hipStream_t st, int32_t rule = 0,
                                           double eps = 0.0);
 
-// Newton-Schulz comparison rule: one block of the tape.
+// Newton-Schulz comparison rule.  One block of the tape:
 struct NsDesc {
   int64_t row0;    // first row of its svec in the input / output vectors
   int64_t moff;    // element offset of its matrix area in the tape
   int32_t p;       // matrix order
-  int32_t tile0;   // index of its first 32 x 32 tile in a product launch
+  int32_t tile0;   // index of its first output tile in a product launch
 };
 // One product C = alpha op(A) op(B) + beta D over every block (slots of the
 // block's matrix area; d = -1: no D term; ta / tb: transpose A / B).
@@ -185,10 +185,12 @@ struct NsSlots {
   int32_t q(int32_t k) const { return K + 1 + k; }
   static int64_t count(int32_t k) { return 2 * (int64_t)k + 8; }
 };
-template <typename T> void launch_ns_forward(const NsDesc *d, int32_t nblk, int32_t ntiles, int32_t K, const T *v,
-                                             T *out, T *base, double *cnorm, hipStream_t st);
-template <typename T> void launch_ns_vjp(const NsDesc *d, int32_t nblk, int32_t ntiles, int32_t K, const T *g,
-                                         T *gin, T *base, const double *cnorm, hipStream_t st);
+// tile: output tile edge of one product workgroup, 64 or 32 (ntiles tiles
+// of that edge over all blocks, tile0 counted in them).
+template <typename T> void launch_ns_forward(const NsDesc *d, int32_t nblk, int32_t ntiles, int32_t tile, int32_t K,
+                                             const T *v, T *out, T *base, double *cnorm, hipStream_t st);
+template <typename T> void launch_ns_vjp(const NsDesc *d, int32_t nblk, int32_t ntiles, int32_t tile, int32_t K,
+                                         const T *g, T *gin, T *base, const double *cnorm, hipStream_t st);
 
 // bookkeeping for profiling: kernel-family events
 void set_last_error(const std::string &msg);

@@ -982,13 +982,53 @@ __global__ __launch_bounds__(NT) void k_psd_vjp(const PsdDesc *__restrict__ desc
 // Matrices live in a caller tape, column-major p x p per block, addressed by
 // slot: base + d.moff + slot p^2.
 
+// 32 x 32 block of C = A B per wave as 2 x 2 matrix-core tiles that share
+// their operand reads: per k step a lane loads two A and two B values and
+// issues four products (the 16 x 16 tile_mma issues one per two loads).
+// acc[2 a + b] is the tile at rows I0 + 16 a, columns J0 + 16 b, laid out as
+// in tile_mma.
+template <typename T, typename FA, typename FB>
+__device__ inline void tile_mma22(int I0, int J0, int kdim, FA fa, FB fb, typename Mma<T>::v4 acc[4]) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, kk = lane >> 4;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = typename Mma<T>::v4{0, 0, 0, 0};
+  int k0 = 0;
+  for (; k0 + 8 <= kdim; k0 += 8) {
+    T a[2][2], b[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int k = k0 + 4 * u + kk;
+      a[u][0] = fa(I0 + r, k);
+      a[u][1] = fa(I0 + 16 + r, k);
+      b[u][0] = fb(k, J0 + r);
+      b[u][1] = fb(k, J0 + 16 + r);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = Mma<T>::op(a[u][t >> 1], b[u][t & 1], acc[t]);
+  }
+  for (; k0 < kdim; k0 += 4) {
+    const int k = k0 + kk;
+    const T a0 = fa(I0 + r, k), a1 = fa(I0 + 16 + r, k), b0 = fb(k, J0 + r), b1 = fb(k, J0 + 16 + r);
+    acc[0] = Mma<T>::op(a0, b0, acc[0]);
+    acc[1] = Mma<T>::op(a0, b1, acc[1]);
+    acc[2] = Mma<T>::op(a1, b0, acc[2]);
+    acc[3] = Mma<T>::op(a1, b1, acc[3]);
+  }
+}
+
 // C = alpha op(A) op(B) + beta D over every block; one workgroup of four
-// waves per 32 x 32 tile of C, each wave one 16 x 16 matrix-core tile.
+// waves per TILE x TILE tile of C: TILE = 64, each wave a 32 x 32 block
+// (tile_mma22), or TILE = 32, each wave one 16 x 16 tile (tile_mma) when the
+// larger tiles would leave the chip short of workgroups.
 // op(X) = X' when the flag is set.  D may be C itself (each element is read
 // and written by the lane that owns it); A and B are never C.
-template <typename T>
+template <typename T, int TILE>
 __global__ __launch_bounds__(256) void k_ns_gemm(const NsDesc *__restrict__ descs, int32_t nblk, T *base,
                                                  NsGemm g) {
+  constexpr int W = TILE / 2;                // edge of one wave's block
   const int t = blockIdx.x;
   int lo = 0, hi = nblk - 1;                 // last block with tile0 <= t
   while (lo < hi) {
@@ -997,10 +1037,10 @@ __global__ __launch_bounds__(256) void k_ns_gemm(const NsDesc *__restrict__ desc
     else hi = mid - 1;
   }
   const NsDesc d = descs[lo];
-  const int p = d.p, nt = (p + 31) / 32, lt = t - d.tile0;
+  const int p = d.p, nt = (p + TILE - 1) / TILE, lt = t - d.tile0;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int I = (lt / nt) * 2 + (wave >> 1), J = (lt % nt) * 2 + (wave & 1);
-  if (I * 16 >= p || J * 16 >= p) return;
+  const int I0 = (lt / nt) * TILE + (wave >> 1) * W, J0 = (lt % nt) * TILE + (wave & 1) * W;
+  if (I0 >= p || J0 >= p) return;
   const size_t pp = (size_t)p * p;
   T *blk = base + d.moff;
   const T *A = blk + g.a * pp, *B = blk + g.b * pp;
@@ -1009,15 +1049,21 @@ __global__ __launch_bounds__(256) void k_ns_gemm(const NsDesc *__restrict__ desc
   const bool ta = g.ta, tb = g.tb;
   auto fa = [&](int i, int k) -> T { return (i < p && k < p) ? (ta ? A[k + (size_t)i * p] : A[i + (size_t)k * p]) : (T)0; };
   auto fb = [&](int k, int j) -> T { return (k < p && j < p) ? (tb ? B[j + (size_t)k * p] : B[k + (size_t)j * p]) : (T)0; };
-  const typename Mma<T>::v4 acc = tile_mma<T>(I * 16, J * 16, p, fa, fb);
-  const int col = J * 16 + (lane & 15);
+  constexpr int NQ = TILE == 64 ? 4 : 1;
+  typename Mma<T>::v4 acc[NQ];
+  if constexpr (TILE == 64) tile_mma22<T>(I0, J0, p, fa, fb, acc);
+  else acc[0] = tile_mma<T>(I0, J0, p, fa, fb);
   const T alpha = (T)g.alpha, beta = (T)g.beta;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int row = I * 16 + Mma<T>::row(lane, e);
-    if (row < p && col < p) {
-      const size_t o = row + (size_t)col * p;
-      C[o] = D ? alpha * acc[e] + beta * D[o] : alpha * acc[e];
+  for (int q = 0; q < NQ; ++q) {
+    const int col = J0 + 16 * (q & 1) + (lane & 15);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = I0 + 16 * (q >> 1) + Mma<T>::row(lane, e);
+      if (row < p && col < p) {
+        const size_t o = row + (size_t)col * p;
+        C[o] = D ? alpha * acc[q][e] + beta * D[o] : alpha * acc[q][e];
+      }
     }
   }
 }
@@ -1162,6 +1208,10 @@ void launch_psd_step(const PsdDesc *d, int32_t n, const PsdLaunchCfg &cfg, const
                                                 rscratch, Uprev, st);
 }
 
+// 16 waves: a block of order ~100 has 49 output tiles per product, so the
+// longest wave runs 4 of them instead of 7 with 8 waves.
+constexpr int VJP_NT = 1024;
+
 template <typename T>
 void launch_psd_vjp(const PsdDesc *d, int32_t n, int32_t max_p, const T *U, const T *lam, const T *g, T *out,
                     T *scratch, hipStream_t st, int32_t rule, double eps) {
@@ -1173,44 +1223,50 @@ void launch_psd_vjp(const PsdDesc *d, int32_t n, int32_t max_p, const T *U, cons
   else if (2 * pp <= budget) elems = 2 * pp;
   static bool attr_set = false;
   if (!attr_set) {
-    set_dyn_lds_cap(reinterpret_cast<const void *>(&k_psd_vjp<T, 512>));
+    set_dyn_lds_cap(reinterpret_cast<const void *>(&k_psd_vjp<T, VJP_NT>));
     attr_set = true;
   }
-  k_psd_vjp<T, 512><<<n, 512, elems * sizeof(T), st>>>(d, U, lam, g, out, scratch, (int32_t)elems, rule, (T)eps);
+  k_psd_vjp<T, VJP_NT><<<n, VJP_NT, elems * sizeof(T), st>>>(d, U, lam, g, out, scratch, (int32_t)elems, rule, (T)eps);
+}
+
+template <typename T>
+void ns_gemm(const NsDesc *d, int32_t nblk, int32_t ntiles, int32_t tile, T *base, const NsGemm &g, hipStream_t st) {
+  if (tile == 64) k_ns_gemm<T, 64><<<ntiles, 256, 0, st>>>(d, nblk, base, g);
+  else k_ns_gemm<T, 32><<<ntiles, 256, 0, st>>>(d, nblk, base, g);
 }
 
 // Newton-Schulz forward: K steps of eq:newton-schulz, every iterate X_k and
 // square Q_k kept in the tape for the reverse pass, then
 // out = svec(sym((S + X_K S) / 2)).
 template <typename T>
-void launch_ns_forward(const NsDesc *d, int32_t nblk, int32_t ntiles, int32_t K, const T *v, T *out, T *base,
-                       double *cnorm, hipStream_t st) {
+void launch_ns_forward(const NsDesc *d, int32_t nblk, int32_t ntiles, int32_t tile, int32_t K, const T *v, T *out,
+                       T *base, double *cnorm, hipStream_t st) {
   const NsSlots sl(K);
   k_ns_init<T><<<nblk, 256, 0, st>>>(d, v, base, cnorm, sl.x(0), sl.S);
   for (int k = 0; k < K; ++k) {
-    k_ns_gemm<T><<<ntiles, 256, 0, st>>>(d, nblk, base, NsGemm{sl.x(k), sl.x(k), sl.q(k), -1, 0, 0, 1.0, 0.0});
-    k_ns_gemm<T><<<ntiles, 256, 0, st>>>(d, nblk, base, NsGemm{sl.x(k), sl.q(k), sl.x(k + 1), sl.x(k), 0, 0, -0.5, 1.5});
+    ns_gemm<T>(d, nblk, ntiles, tile, base, NsGemm{sl.x(k), sl.x(k), sl.q(k), -1, 0, 0, 1.0, 0.0}, st);
+    ns_gemm<T>(d, nblk, ntiles, tile, base, NsGemm{sl.x(k), sl.q(k), sl.x(k + 1), sl.x(k), 0, 0, -0.5, 1.5}, st);
   }
-  k_ns_gemm<T><<<ntiles, 256, 0, st>>>(d, nblk, base, NsGemm{sl.x(K), sl.S, sl.W, sl.S, 0, 0, 0.5, 0.5});
+  ns_gemm<T>(d, nblk, ntiles, tile, base, NsGemm{sl.x(K), sl.S, sl.W, sl.S, 0, 0, 0.5, 0.5}, st);
   k_ns_pack<T><<<nblk, 256, 0, st>>>(d, base, sl.W, out);
 }
 
 // Newton-Schulz reverse pass from the tape of launch_ns_forward (same blocks
 // and K): for C = A B, Abar = Cbar B' and Bbar = A' Cbar.
 template <typename T>
-void launch_ns_vjp(const NsDesc *d, int32_t nblk, int32_t ntiles, int32_t K, const T *g, T *gin, T *base,
-                   const double *cnorm, hipStream_t st) {
+void launch_ns_vjp(const NsDesc *d, int32_t nblk, int32_t ntiles, int32_t tile, int32_t K, const T *g, T *gin,
+                   T *base, const double *cnorm, hipStream_t st) {
   const NsSlots sl(K);
   k_ns_unpack<T><<<nblk, 256, 0, st>>>(d, g, base, sl.TB);
   // Pi = S / 2 + X_K S / 2
-  k_ns_gemm<T><<<ntiles, 256, 0, st>>>(d, nblk, base, NsGemm{sl.x(K), sl.TB, sl.SB, sl.TB, 1, 0, 0.5, 0.5});
-  k_ns_gemm<T><<<ntiles, 256, 0, st>>>(d, nblk, base, NsGemm{sl.TB, sl.S, sl.Y, -1, 0, 1, 0.5, 0.0});
+  ns_gemm<T>(d, nblk, ntiles, tile, base, NsGemm{sl.x(K), sl.TB, sl.SB, sl.TB, 1, 0, 0.5, 0.5}, st);
+  ns_gemm<T>(d, nblk, ntiles, tile, base, NsGemm{sl.TB, sl.S, sl.Y, -1, 0, 1, 0.5, 0.0}, st);
   for (int k = K - 1; k >= 0; --k) {
     // X_{k+1} = 3/2 X_k - 1/2 X_k Q_k with Q_k = X_k X_k; Y = cotangent of X_{k+1}
-    k_ns_gemm<T><<<ntiles, 256, 0, st>>>(d, nblk, base, NsGemm{sl.Y, sl.q(k), sl.Z, sl.Y, 0, 1, -0.5, 1.5});
-    k_ns_gemm<T><<<ntiles, 256, 0, st>>>(d, nblk, base, NsGemm{sl.x(k), sl.Y, sl.QB, -1, 1, 0, -0.5, 0.0});
-    k_ns_gemm<T><<<ntiles, 256, 0, st>>>(d, nblk, base, NsGemm{sl.QB, sl.x(k), sl.Z, sl.Z, 0, 1, 1.0, 1.0});
-    k_ns_gemm<T><<<ntiles, 256, 0, st>>>(d, nblk, base, NsGemm{sl.x(k), sl.QB, sl.Y, sl.Z, 1, 0, 1.0, 1.0});
+    ns_gemm<T>(d, nblk, ntiles, tile, base, NsGemm{sl.Y, sl.q(k), sl.Z, sl.Y, 0, 1, -0.5, 1.5}, st);
+    ns_gemm<T>(d, nblk, ntiles, tile, base, NsGemm{sl.x(k), sl.Y, sl.QB, -1, 1, 0, -0.5, 0.0}, st);
+    ns_gemm<T>(d, nblk, ntiles, tile, base, NsGemm{sl.QB, sl.x(k), sl.Z, sl.Z, 0, 1, 1.0, 1.0}, st);
+    ns_gemm<T>(d, nblk, ntiles, tile, base, NsGemm{sl.x(k), sl.QB, sl.Y, sl.Z, 1, 0, 1.0, 1.0}, st);
   }
   k_ns_final<T><<<nblk, 256, 0, st>>>(d, base, cnorm, sl.Y, sl.S, sl.SB, gin);
 }
@@ -1225,13 +1281,13 @@ template void launch_psd_vjp<float>(const PsdDesc *, int32_t, int32_t, const flo
                                     float *, float *, hipStream_t, int32_t, double);
 template void launch_psd_vjp<double>(const PsdDesc *, int32_t, int32_t, const double *, const double *,
                                      const double *, double *, double *, hipStream_t, int32_t, double);
-template void launch_ns_forward<float>(const NsDesc *, int32_t, int32_t, int32_t, const float *, float *, float *,
-                                       double *, hipStream_t);
-template void launch_ns_forward<double>(const NsDesc *, int32_t, int32_t, int32_t, const double *, double *,
+template void launch_ns_forward<float>(const NsDesc *, int32_t, int32_t, int32_t, int32_t, const float *, float *,
+                                       float *, double *, hipStream_t);
+template void launch_ns_forward<double>(const NsDesc *, int32_t, int32_t, int32_t, int32_t, const double *, double *,
                                         double *, double *, hipStream_t);
-template void launch_ns_vjp<float>(const NsDesc *, int32_t, int32_t, int32_t, const float *, float *, float *,
+template void launch_ns_vjp<float>(const NsDesc *, int32_t, int32_t, int32_t, int32_t, const float *, float *, float *,
                                    const double *, hipStream_t);
-template void launch_ns_vjp<double>(const NsDesc *, int32_t, int32_t, int32_t, const double *, double *, double *,
-                                    const double *, hipStream_t);
+template void launch_ns_vjp<double>(const NsDesc *, int32_t, int32_t, int32_t, int32_t, const double *, double *,
+                                    double *, const double *, hipStream_t);
 
 }  // namespace cosmo

@@ -1203,6 +1203,7 @@ namespace {
 struct NsLayout {
   std::vector<NsDesc> d;
   int64_t ntiles = 0;
+  int32_t tile = 64;
   size_t off_c = 0, off_m = 0, bytes = 0;
 };
 
@@ -1212,6 +1213,15 @@ cosmo_status ns_layout(int32_t nblk, const int32_t *order, const int64_t *offset
   if (dt != COSMO_F32 && dt != COSMO_F64) FAIL(COSMO_EINVAL, "bad dtype");
   if (iters < 0 || iters > COSMO_NS_MAX_ITERS) FAIL(COSMO_EINVAL, "Newton-Schulz step count out of range");
   const size_t esz = dt == COSMO_F32 ? 4 : 8;
+  // 64 x 64 output tiles per workgroup while they still give two workgroups
+  // per CU (256 CUs), else 32 x 32 tiles; the choice depends on the orders
+  // only, so the forward and the reverse call agree.
+  int64_t t64 = 0;
+  for (int b = 0; b < nblk; ++b) {
+    const int64_t n64 = (std::max(order[b], 1) + 63) / 64;
+    t64 += n64 * n64;
+  }
+  L.tile = t64 >= 512 ? 64 : 32;
   L.d.resize(nblk);
   int64_t mo = 0, tiles = 0;
   std::vector<std::pair<int64_t, int64_t>> ranges;
@@ -1220,7 +1230,7 @@ cosmo_status ns_layout(int32_t nblk, const int32_t *order, const int64_t *offset
     if (p < 1 || p > COSMO_NS_MAX_ORDER) FAIL(p < 1 ? COSMO_EINVAL : COSMO_EUNSUPPORTED, "PSD order out of range");
     const int64_t r0 = offset ? offset[b] : 0;
     if (offset && r0 < 0) FAIL(COSMO_EINVAL, "negative offset");
-    const int nt = (p + 31) / 32;
+    const int nt = (p + L.tile - 1) / L.tile;
     L.d[b] = {r0, mo, p, (int32_t)tiles};
     mo += NsSlots::count(iters) * p * p;
     tiles += (int64_t)nt * nt;
@@ -1260,10 +1270,10 @@ cosmo_status psd_proj_ns(int32_t nblk, const int32_t *order, const int64_t *offs
   const NsDesc *d = reinterpret_cast<const NsDesc *>(t);
   double *cn = reinterpret_cast<double *>(t + L.off_c);
   if (dtype == COSMO_F32)
-    launch_ns_forward<float>(d, nblk, (int32_t)L.ntiles, iters, (const float *)in, (float *)out,
+    launch_ns_forward<float>(d, nblk, (int32_t)L.ntiles, L.tile, iters, (const float *)in, (float *)out,
                              reinterpret_cast<float *>(t + L.off_m), cn, st);
   else
-    launch_ns_forward<double>(d, nblk, (int32_t)L.ntiles, iters, (const double *)in, (double *)out,
+    launch_ns_forward<double>(d, nblk, (int32_t)L.ntiles, L.tile, iters, (const double *)in, (double *)out,
                               reinterpret_cast<double *>(t + L.off_m), cn, st);
   HIPCHK(hipGetLastError());
   return COSMO_OK;
@@ -1280,10 +1290,10 @@ cosmo_status psd_proj_ns_vjp(int32_t nblk, const int32_t *order, const int64_t *
   const NsDesc *d = reinterpret_cast<const NsDesc *>(t);
   const double *cn = reinterpret_cast<const double *>(t + L.off_c);
   if (dtype == COSMO_F32)
-    launch_ns_vjp<float>(d, nblk, (int32_t)L.ntiles, iters, (const float *)gout, (float *)gin,
+    launch_ns_vjp<float>(d, nblk, (int32_t)L.ntiles, L.tile, iters, (const float *)gout, (float *)gin,
                          reinterpret_cast<float *>(t + L.off_m), cn, st);
   else
-    launch_ns_vjp<double>(d, nblk, (int32_t)L.ntiles, iters, (const double *)gout, (double *)gin,
+    launch_ns_vjp<double>(d, nblk, (int32_t)L.ntiles, L.tile, iters, (const double *)gout, (double *)gin,
                           reinterpret_cast<double *>(t + L.off_m), cn, st);
   HIPCHK(hipGetLastError());
   return COSMO_OK;

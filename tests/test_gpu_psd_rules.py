@@ -208,3 +208,36 @@ def test_rule_errors_against_finite_differences_over_the_gap():
             assert errs["tikhonov"] >= 0.1, (d, errs)
         if d == 1.0:
             assert errs["tikhonov"] <= 1e-2, (d, errs)
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float32, 1e-4), (np.float64, 1e-10)])
+def test_newton_schulz_many_blocks_large_product_tiles(dtype, tol):
+    # enough 64 x 64 output tiles (>= 512) that the products run in the
+    # 2 x 2-blocked form; orders 20..70 put partial tiles everywhere.  Every
+    # 8th block is checked against the oracle, all blocks for finiteness.
+    ensure_lib()
+    from paper_2606_13825_amd import NewtonSchulzProj
+    rng = np.random.default_rng(17)
+    orders = [int(p) for p in rng.integers(20, 71, size=512)]
+    K = 12
+    mats = [_spaced(rng, p).astype(dtype).astype(np.float64) for p in orders]
+    x = np.concatenate([oracle.svec(m) for m in mats])
+    g = np.concatenate([oracle.svec(_sym(rng, p)) for p in orders]).astype(dtype)
+    tdt = torch.float32 if dtype == np.float32 else torch.float64
+    say(f"newton-schulz 512 blocks dtype={np.dtype(dtype).name} K={K}")
+    ns = NewtonSchulzProj(orders, K, tdt, DEV)
+    out = ns.forward(torch.from_numpy(x.astype(dtype)).to(DEV)).double().cpu().numpy()
+    gin = ns.vjp(torch.from_numpy(g).to(DEV)).double().cpu().numpy()
+    assert np.all(np.isfinite(out)) and np.all(np.isfinite(gin))
+    off = 0
+    for b, p in enumerate(orders):
+        nr = p * (p + 1) // 2
+        if b % 8 == 0:
+            v = x[off:off + nr]
+            ro, tape = oracle.ns_forward(v, K)
+            gv = g[off:off + nr].astype(np.float64)
+            rg = oracle.ns_vjp(tape, gv)
+            eo = rel_err(out[off:off + nr], ro, 1e-6 * np.linalg.norm(v))
+            eg = rel_err(gin[off:off + nr], rg, 1e-6 * np.linalg.norm(gv))
+            assert eo <= tol and eg <= tol, (b, p, eo, eg)
+        off += nr
