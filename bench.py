@@ -234,6 +234,93 @@ def psd_rules_study(samples=100, orders=(10, 20, 40, 80, 160, 320), delta=1e-5, 
                       "rows": rows, "roofline": ns_roof}))
 
 
+# CG tolerance of the App. B runs: the float32 CG then stops at the
+# precision floor of its float64 true residual (as for the parity tests).
+APPB_CG_TOL = 1e-10
+
+
+def appb_study(ns=(1000, 2000, 5000, 10000, 20000, 50000), reps=3, seed=8):
+    """Memory and time of the matrix-free backward against the problem size
+    (the linear-solve backward experiment of App. B): one instance per size
+    from the App. B sampler (diagonal P ~ U(0, 10), m = n/2, A 1 % dense,
+    rho ~ U(0, 1), b ~ N(0, 1), q = -P x*), one unrolled step (K = 1,
+    alpha = 1, nonnegative cone on the rows) through the library's forward,
+    residual loss and backward, float32, cooperative CG over the whole chip
+    (tolerance APPB_CG_TOL).
+    Peak HBM = the peak of torch's allocations (problem data, tape,
+    workspaces, outputs) over forward + loss + backward plus the plan's own
+    device buffer; the backward alone is timed with HIP events.  The dense
+    reduced matrix (n^2) and saddle-point matrix ((n + m)^2) that the paper's
+    comparison methods form are reported by size only.  Prints one JSON line."""
+    import torch
+    from paper_2606_13825_amd import CosmoBatch
+    from synth import Cone, ConicInstance
+    from synth.workloads import appb_instance
+    dev = torch.device("cuda:0")
+    torch.zeros(1, device=dev)
+    rng = np.random.default_rng(seed)
+    rows = []
+    # one untimed pass on a small instance first: the runtime's one-time
+    # device allocations (code objects, first plan) stay out of the figures
+    for n in (200,) + tuple(ns):
+        P, A, rho_row, b, xstar = appb_instance(n, rng)
+        m = A.shape[0]
+        inst = ConicInstance(P=P.tocsr(), q=-(P @ xstar), A=A.tocsr(), b=b, cones=[Cone("nonneg", m)])
+        inst = inst.astype(np.float32)
+        torch.cuda.synchronize(dev)
+        torch.cuda.empty_cache()
+        free0, res0 = torch.cuda.mem_get_info(dev)[0], torch.cuda.memory_reserved(dev)
+        torch.cuda.reset_peak_memory_stats(dev)
+        base = torch.cuda.memory_allocated(dev)
+        batch = CosmoBatch([inst], K=1, dtype=torch.float32, device=dev, cg_tol=APPB_CG_TOL)
+        torch.cuda.synchronize(dev)
+        plan_bytes = max(0, (free0 - torch.cuda.mem_get_info(dev)[0]) - (torch.cuda.memory_reserved(dev) - res0))
+        batch.set_pcg_form(4)
+        rho = torch.from_numpy(rho_row.astype(np.float32)[None, :].copy()).to(dev)
+        alpha = torch.ones((1, 1), dtype=torch.float32, device=dev)
+        tape, fws, bws = batch.new_tape(), batch.new_fwd_ws(), batch.new_bwd_ws()
+        stats = batch.new_stats()
+        fw = batch.forward(rho, alpha, tape=tape, ws=fws, stats=stats)
+        _, g = batch.residual_loss(fw.x, fw.s, fw.y, ws=fws)
+        bw = batch.backward(rho, alpha, fw.tape, *g, ws=bws, stats=stats)
+        torch.cuda.synchronize(dev)
+        peak = torch.cuda.max_memory_allocated(dev) - base + plan_bytes
+        assert torch.isfinite(bw.grho).all(), "non-finite gradient"
+        st2 = batch.new_stats()
+        out = (bw.grho, bw.galpha, bw.gx0, bw.gs0, bw.gy0)
+        cur = torch.cuda.current_stream(dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(cur)
+        for _ in range(reps):
+            batch.backward(rho, alpha, fw.tape, *g, ws=bws, stats=st2, out=out)
+        e1.record(cur)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        sd = batch.stats_dict(st2)
+        ops = float(sd["cg_iters_total"].sum() + sd["cg_passes_total"].sum()) / reps
+        cg_bytes = ops * pcg_bytes_per_iteration(inst, 4)
+        row = {"n": n, "m": m, "nnz_A": int(inst.A.nnz), "peak_hbm_bytes": int(peak), "plan_bytes": int(plan_bytes),
+               "bwd_ms": ms, "bwd_cg_operator_applications": ops, "bwd_cg_bytes": cg_bytes,
+               "bwd_cg_gbs": cg_bytes / (ms * 1e-3) / 1e9,
+               "dense_reduced_matrix_bytes": 4 * n * n, "dense_kkt_bytes": 4 * (n + m) ** 2}
+        if n == 200:
+            del batch, tape, fws, bws, fw, bw, g, out
+            continue
+        rows.append(row)
+        print(f"[bench] appb n={n}: peak {peak / 2**20:.1f} MiB, backward {ms:.2f} ms, "
+              f"{ops:.0f} operator applications, {row['bwd_cg_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
+        del batch, tape, fws, bws, fw, bw, g, out
+    last = rows[-1]
+    print(json.dumps({"metric": "peak HBM and backward time of the matrix-free backward vs problem size (App. B)",
+                      "unit": "bytes, ms", "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "appb_one_instance_per_size", "sizes": list(ns), "K": 1,
+                                 "pcg_form": 4, "cg_tol": APPB_CG_TOL, "reps": reps},
+                      "rows": rows,
+                      "roofline": {"kernel": "k_pcg_coop<float> (backward adjoint solve)", "n": last["n"],
+                                   "bound": "hbm", "achieved": last["bwd_cg_gbs"], "peak": PEAK_HBM_GBS,
+                                   "unit": "GB/s", "frac": last["bwd_cg_gbs"] / PEAK_HBM_GBS, "traffic": None}}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -250,11 +337,15 @@ def main():
     ap.add_argument("--quick", action="store_true",
                     help="counter-collection run: the timed steps only (no plain-forward comparison, "
                          "no event-timed step, no CPU leg)")
-    ap.add_argument("--study", default=None, choices=["psd_rules"],
-                    help="psd_rules: backward time of the PSD-projection rules against the matrix order")
+    ap.add_argument("--study", default=None, choices=["psd_rules", "appb"],
+                    help="psd_rules: backward time of the PSD-projection rules against the matrix order; "
+                         "appb: peak HBM and time of the matrix-free backward against the problem size")
     args = ap.parse_args()
     if args.study == "psd_rules" and args.gpus == 1:
         psd_rules_study()
+        return
+    if args.study == "appb" and args.gpus == 1:
+        appb_study()
         return
     if args.quick:
         args.no_cpu_baseline = True

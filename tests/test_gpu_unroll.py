@@ -142,3 +142,51 @@ def test_first_instance_and_forward_only_path_fp64():
     torch.cuda.synchronize()
     for a, b in ((plain.x, fw.x), (plain.s, fw.s), (plain.y, fw.y)):
         assert torch.equal(a, b)
+
+
+def _appb(n, seed):
+    """App. B sampler as a conic instance: nonnegative cone on all m = n/2
+    rows, q = -P x*; returns the instance and its rho ~ U(0, 1)."""
+    from synth.workloads import appb_instance
+    P, A, rho, b, xstar = appb_instance(n, np.random.default_rng(seed))
+    inst = synth.ConicInstance(P=P.tocsr(), q=-(P @ xstar), A=A.tocsr(), b=b,
+                               cones=[synth.Cone("nonneg", A.shape[0])])
+    return inst, rho
+
+
+@pytest.mark.parametrize("n", [1000, 2000])
+def test_appb_instances_fp64(n):
+    # the linear-solve backward experiment's instances (App. B), two steps
+    ensure_lib()
+    inst, rho = _appb(n, 30 + n)
+    K = 2
+    rhos = [np.stack([rho, 0.5 + rho]).astype(np.float64)]
+    alphas = [np.array([1.0, 1.6])]
+    say(f"App. B n={n} m={inst.m} nnz={inst.A.nnz} fp64 K={K}")
+    batch, fw, loss, bw, st = _run([inst], K, np.float64, rhos, alphas, cg_tol=1e-13)
+    assert st["cg_not_converged"].max() == 0
+    _check(batch, fw, loss, bw, [inst], rhos, alphas, 1e-9, 1e-8, every_k=True)
+
+
+def test_appb_instance_fp32_cooperative_cg():
+    # the configuration the App. B study times: float32, cooperative CG
+    # (4 workgroups per CU at most), CG to its precision floor
+    ensure_lib()
+    from paper_2606_13825_amd import CosmoBatch
+    inst, rho = _appb(2000, 40)
+    inst = inst.astype(np.float32)
+    K = 2
+    rhos = [np.stack([rho, 0.5 + rho]).astype(np.float32)]
+    alphas = [np.array([1.0, 1.6], np.float32)]
+    say(f"App. B n=2000 fp32 cooperative K={K}")
+    batch = CosmoBatch([inst], K=K, dtype=torch.float32, device=DEV, cg_tol=1e-10)
+    batch.set_pcg_form(4)
+    r = torch.from_numpy(rhos[0]).to(DEV)
+    a = torch.from_numpy(alphas[0].reshape(K, 1)).to(DEV)
+    stats = batch.new_stats()
+    fw = batch.forward(r, a, stats=stats)
+    loss, g = batch.residual_loss(fw.x, fw.s, fw.y)
+    bw = batch.backward(r, a, fw.tape, *g, stats=stats)
+    torch.cuda.synchronize()
+    assert batch.stats_dict(stats)["nonfinite"].max() == 0
+    _check(batch, fw, loss, bw, [inst], rhos, alphas, 1e-5, 1e-4, every_k=True)
