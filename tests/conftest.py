@@ -14,6 +14,6 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(config, items):
-    # GPU tests run in one process on the GPU machine; elsewhere they are skipped
+    # GPU tests run in one process on a machine with the GPU; elsewhere they are skipped
     # unless explicitly selected with -m gpu (then they fail loudly).
     pass
