@@ -929,9 +929,13 @@ __global__ __launch_bounds__(NT) void k_psd_vjp(const PsdDesc *__restrict__ desc
     }
   }
   __syncthreads();
-  // B0 = W o (U' B1)
-  for (int t = wave; t < nt * nt; t += NWv) {
-    const int I = t / nt, J = t % nt;
+  // B0 = W o (U' B1): U' smat(g) U and W are symmetric, so only the upper
+  // tiles are formed; entry (row, col), row <= col, is written to both
+  // places by the lane that owns it (one writer per element).
+  const int nup = nt * (nt + 1) / 2;
+  for (int t = wave; t < nup; t += NWv) {
+    int I, J;
+    upper_tile(t, I, J);
     auto fa = [&](int i, int k) -> T { return (i < p && k < p) ? U[k + i * lu] : (T)0; };
     auto fb = [&](int k, int j) -> T { return (k < p && j < p) ? B1[k + j * l1] : (T)0; };
     const typename Mma<T>::v4 acc = tile_mma<T>(I * 16, J * 16, p, fa, fb);
@@ -939,7 +943,11 @@ __global__ __launch_bounds__(NT) void k_psd_vjp(const PsdDesc *__restrict__ desc
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int row = I * 16 + Mma<T>::row(lane, e);
-      if (row < p && col < p) B0[row + col * l0] = vjp_weight<T>(rule, lam_s[row], lam_s[col], row == col, eps) * acc[e];
+      if (row <= col && col < p) {
+        const T val = vjp_weight<T>(rule, lam_s[row], lam_s[col], row == col, eps) * acc[e];
+        B0[row + col * l0] = val;
+        B0[col + row * l0] = val;
+      }
     }
   }
   __syncthreads();
