@@ -50,7 +50,9 @@ EIG_KERNEL_NAMES = {0: "k_psd_eig<float,64,4,32> (orders <= 32)", 1: "k_psd_eig<
                     2: "k_psd_eig<float,512,8,128> (orders 65-128)",
                     3: "k_psd_eig<float,1024,8,200> (orders 129-200)"}
 EIG_PROFILE = os.path.join(ROOT, "profiles", "k_psd_eig_maxcut64_pmc.md")
-EIG_SOURCE = os.path.join(ROOT, "paper_2606_13825_amd", "csrc", "k_psd.hip")
+# the eigensolve kernels are built from k_psd.hip and the shared tile helpers
+EIG_SOURCE = [os.path.join(ROOT, "paper_2606_13825_amd", "csrc", "k_psd.hip"),
+              os.path.join(ROOT, "paper_2606_13825_amd", "csrc", "mma_tiles.h")]
 PCG_PROFILE = os.path.join(ROOT, "profiles", "k_pcg_huber256_pmc.md")
 PCG_SOURCE = os.path.join(ROOT, "paper_2606_13825_amd", "csrc", "k_pcg.hip")
 
@@ -65,7 +67,8 @@ def traffic_from_profile(profile, source, **match):
     (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a copy kernel of
     known size); None when there is none, when its keys (order class, CG
     form) differ from `match`, or when the kernel source has changed since the
-    counters were taken."""
+    counters were taken.  `source` is one file or a list of files, hashed
+    together in that order."""
     try:
         kv = {}
         with open(profile) as f:
@@ -73,8 +76,11 @@ def traffic_from_profile(profile, source, **match):
                 if ":" in line and line[:1].isalpha():
                     k, v = line.split(":", 1)
                     kv[k.strip()] = v.strip()
-        with open(source, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        h = hashlib.sha256()
+        for src in ([source] if isinstance(source, str) else source):
+            with open(src, "rb") as f:
+                h.update(f.read())
+        sha = h.hexdigest()
         if kv.get("source_sha256") != sha or any(int(kv.get(k, -1)) != int(v) for k, v in match.items()):
             return None
         return float(kv["traffic_bytes_per_dispatch"])

@@ -19,93 +19,20 @@
 //
 // Reconstruction Pi = U diag(max(lam, 0)) U' and the four products of the DK
 // rule U (L o (U' T U)) U' run on the matrix cores (v_mfma 16x16x4, FP32 or
-// FP64), on 16 x 16 output tiles, one wave per tile.
+// FP64; helpers in mma_tiles.h), on 16 x 16 output tiles, one wave per tile.
 #include <type_traits>
 
 #include "cosmo_internal.h"
+#include "mma_tiles.h"
 
 namespace cosmo {
 namespace {
-
-// 16 x 16 x 4 matrix-core products.  Both take A(i, k) from lane i + 16 k and
-// B(k, j) from lane j + 16 k; they differ in where result row i of column j
-// lands: f32 puts rows 4 (l/16) .. 4 (l/16) + 3 in the four accumulator
-// registers of lane l, f64 interleaves them (register e of lane l holds row
-// l/16 + 4 e).
-template <typename T> struct Mma;
-template <> struct Mma<float> {
-  typedef float v4 __attribute__((ext_vector_type(4)));
-  static __device__ inline v4 op(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-  static __device__ inline int row(int lane, int e) { return 4 * (lane >> 4) + e; }
-};
-template <> struct Mma<double> {
-  typedef double v4 __attribute__((ext_vector_type(4)));
-  static __device__ inline v4 op(double a, double b, v4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ inline int row(int lane, int e) { return (lane >> 4) + 4 * e; }
-};
 
 template <typename T> struct Unit;
 template <> struct Unit<float> { static constexpr float eps = 5.96e-8f; };
 template <> struct Unit<double> { static constexpr double eps = 1.11e-16; };
 
-constexpr double RSQRT2 = 0.70710678118654752440;
-constexpr double SQRT2 = 1.41421356237309504880;
 constexpr int MAXP = COSMO_MAX_PSD_ORDER_F32;
-
-// 16 x 16 tile of C = A B with A(i, k), B(k, j) given by functors that return
-// 0 outside the matrices.  Lane l feeds A(I0 + l%16, k0 + l/16) and
-// B(k0 + l/16, J0 + l%16); accumulator element e of lane l is
-// C(I0 + Mma<T>::row(l, e), J0 + l%16).
-// The k loop is unrolled by four products so the operand reads of a group
-// are issued together.
-template <typename T, typename FA, typename FB>
-__device__ inline typename Mma<T>::v4 tile_mma(int I0, int J0, int kdim, FA fa, FB fb) {
-  const int lane = threadIdx.x & 63;
-  const int r = lane & 15, kk = lane >> 4;
-  typename Mma<T>::v4 acc = {0, 0, 0, 0};
-  int k0 = 0;
-  for (; k0 + 16 <= kdim; k0 += 16) {
-    T a[4], b[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a[u] = fa(I0 + r, k0 + 4 * u + kk);
-      b[u] = fb(k0 + 4 * u + kk, J0 + r);
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) acc = Mma<T>::op(a[u], b[u], acc);
-  }
-  for (; k0 < kdim; k0 += 4) {
-    const int k = k0 + kk;
-    acc = Mma<T>::op(fa(I0 + r, k), fb(k, J0 + r), acc);
-  }
-  return acc;
-}
-
-// Upper-triangle tile enumeration: t -> (I, J), I <= J.
-__device__ inline void upper_tile(int t, int &I, int &J) {
-  J = 0;
-  while ((J + 1) * (J + 2) / 2 <= t) ++J;
-  I = t - J * (J + 1) / 2;
-}
-
-__device__ inline int svec_col(int idx) {
-  int j = (int)((sqrtf(8.0f * (float)idx + 1.0f) - 1.0f) * 0.5f);
-  while (j * (j + 1) / 2 > idx) --j;
-  while ((j + 1) * (j + 2) / 2 <= idx) ++j;
-  return j;
-}
-
-template <typename T, int NT> __device__ inline T wg_sum(T v, T *red) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  T t = 0;
-  for (int w = 0; w < NT / 64; ++w) t += red[w];
-  return t;
-}
 
 template <typename T, int NT> __device__ inline T wg_max(T v, T *red) {
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
@@ -986,183 +913,6 @@ __global__ __launch_bounds__(NT) void k_psd_vjp(const PsdDesc *__restrict__ desc
   }
 }
 
-// ---- Newton-Schulz comparison rule (eq:newton-schulz) ----------------------
-// Matrices live in a caller tape, column-major p x p per block, addressed by
-// slot: base + d.moff + slot p^2.
-
-// 32 x 32 block of C = A B per wave as 2 x 2 matrix-core tiles that share
-// their operand reads: per k step a lane loads two A and two B values and
-// issues four products (the 16 x 16 tile_mma issues one per two loads).
-// acc[2 a + b] is the tile at rows I0 + 16 a, columns J0 + 16 b, laid out as
-// in tile_mma.
-template <typename T, typename FA, typename FB>
-__device__ inline void tile_mma22(int I0, int J0, int kdim, FA fa, FB fb, typename Mma<T>::v4 acc[4]) {
-  const int lane = threadIdx.x & 63;
-  const int r = lane & 15, kk = lane >> 4;
-#pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = typename Mma<T>::v4{0, 0, 0, 0};
-  int k0 = 0;
-  for (; k0 + 8 <= kdim; k0 += 8) {
-    T a[2][2], b[2][2];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int k = k0 + 4 * u + kk;
-      a[u][0] = fa(I0 + r, k);
-      a[u][1] = fa(I0 + 16 + r, k);
-      b[u][0] = fb(k, J0 + r);
-      b[u][1] = fb(k, J0 + 16 + r);
-    }
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int t = 0; t < 4; ++t) acc[t] = Mma<T>::op(a[u][t >> 1], b[u][t & 1], acc[t]);
-  }
-  for (; k0 < kdim; k0 += 4) {
-    const int k = k0 + kk;
-    const T a0 = fa(I0 + r, k), a1 = fa(I0 + 16 + r, k), b0 = fb(k, J0 + r), b1 = fb(k, J0 + 16 + r);
-    acc[0] = Mma<T>::op(a0, b0, acc[0]);
-    acc[1] = Mma<T>::op(a0, b1, acc[1]);
-    acc[2] = Mma<T>::op(a1, b0, acc[2]);
-    acc[3] = Mma<T>::op(a1, b1, acc[3]);
-  }
-}
-
-// C = alpha op(A) op(B) + beta D over every block; one workgroup of four
-// waves per TILE x TILE tile of C: TILE = 64, each wave a 32 x 32 block
-// (tile_mma22), or TILE = 32, each wave one 16 x 16 tile (tile_mma) when the
-// larger tiles would leave the chip short of workgroups.
-// op(X) = X' when the flag is set.  D may be C itself (each element is read
-// and written by the lane that owns it); A and B are never C.
-template <typename T, int TILE>
-__global__ __launch_bounds__(256) void k_ns_gemm(const NsDesc *__restrict__ descs, int32_t nblk, T *base,
-                                                 NsGemm g) {
-  constexpr int W = TILE / 2;                // edge of one wave's block
-  const int t = blockIdx.x;
-  int lo = 0, hi = nblk - 1;                 // last block with tile0 <= t
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (descs[mid].tile0 <= t) lo = mid;
-    else hi = mid - 1;
-  }
-  const NsDesc d = descs[lo];
-  const int p = d.p, nt = (p + TILE - 1) / TILE, lt = t - d.tile0;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int I0 = (lt / nt) * TILE + (wave >> 1) * W, J0 = (lt % nt) * TILE + (wave & 1) * W;
-  if (I0 >= p || J0 >= p) return;
-  const size_t pp = (size_t)p * p;
-  T *blk = base + d.moff;
-  const T *A = blk + g.a * pp, *B = blk + g.b * pp;
-  T *C = blk + g.c * pp;
-  const T *D = g.d >= 0 ? blk + g.d * pp : nullptr;
-  const bool ta = g.ta, tb = g.tb;
-  auto fa = [&](int i, int k) -> T { return (i < p && k < p) ? (ta ? A[k + (size_t)i * p] : A[i + (size_t)k * p]) : (T)0; };
-  auto fb = [&](int k, int j) -> T { return (k < p && j < p) ? (tb ? B[j + (size_t)k * p] : B[k + (size_t)j * p]) : (T)0; };
-  constexpr int NQ = TILE == 64 ? 4 : 1;
-  typename Mma<T>::v4 acc[NQ];
-  if constexpr (TILE == 64) tile_mma22<T>(I0, J0, p, fa, fb, acc);
-  else acc[0] = tile_mma<T>(I0, J0, p, fa, fb);
-  const T alpha = (T)g.alpha, beta = (T)g.beta;
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const int col = J0 + 16 * (q & 1) + (lane & 15);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int row = I0 + 16 * (q >> 1) + Mma<T>::row(lane, e);
-      if (row < p && col < p) {
-        const size_t o = row + (size_t)col * p;
-        C[o] = D ? alpha * acc[q][e] + beta * D[o] : alpha * acc[q][e];
-      }
-    }
-  }
-}
-
-// Forward set-up, one workgroup per block: c = ||smat(v)||_F = ||v||_2,
-// slot S = smat(v), slot X_0 = S / c.
-template <typename T>
-__global__ __launch_bounds__(256) void k_ns_init(const NsDesc *__restrict__ descs, const T *__restrict__ v,
-                                                 T *base, double *cnorm, int32_t slot_x0, int32_t slot_s) {
-  __shared__ double red[256 / 64];
-  const NsDesc d = descs[blockIdx.x];
-  const int p = d.p, nrows = p * (p + 1) / 2;
-  const T *vb = v + d.row0;
-  double ss = 0.0;
-  for (int idx = threadIdx.x; idx < nrows; idx += 256) {
-    const double x = (double)vb[idx];
-    ss += x * x;
-  }
-  const double c = sqrt(wg_sum<double, 256>(ss, red));
-  if (threadIdx.x == 0) cnorm[blockIdx.x] = c;
-  const size_t pp = (size_t)p * p;
-  T *S = base + d.moff + slot_s * pp, *X = base + d.moff + slot_x0 * pp;
-  const T inv = (T)(1.0 / c);
-  for (int idx = threadIdx.x; idx < nrows; idx += 256) {
-    const int j = svec_col(idx);
-    const int i = idx - j * (j + 1) / 2;
-    const T val = (i == j) ? vb[idx] : vb[idx] * (T)RSQRT2;
-    S[i + (size_t)j * p] = val;
-    S[j + (size_t)i * p] = val;
-    X[i + (size_t)j * p] = val * inv;
-    X[j + (size_t)i * p] = val * inv;
-  }
-}
-
-// out = svec of the symmetric part of slot W.
-template <typename T>
-__global__ __launch_bounds__(256) void k_ns_pack(const NsDesc *__restrict__ descs, const T *base, int32_t slot_w,
-                                                 T *__restrict__ out) {
-  const NsDesc d = descs[blockIdx.x];
-  const int p = d.p, nrows = p * (p + 1) / 2;
-  const T *W = base + d.moff + slot_w * (size_t)p * p;
-  for (int idx = threadIdx.x; idx < nrows; idx += 256) {
-    const int j = svec_col(idx);
-    const int i = idx - j * (j + 1) / 2;
-    out[d.row0 + idx] = (i == j) ? W[i + (size_t)i * p]
-                                 : (W[i + (size_t)j * p] + W[j + (size_t)i * p]) * (T)(0.5 * SQRT2);
-  }
-}
-
-// slot TB = smat(g).
-template <typename T>
-__global__ __launch_bounds__(256) void k_ns_unpack(const NsDesc *__restrict__ descs, const T *__restrict__ g,
-                                                   T *base, int32_t slot_t) {
-  const NsDesc d = descs[blockIdx.x];
-  const int p = d.p, nrows = p * (p + 1) / 2;
-  T *Tb = base + d.moff + slot_t * (size_t)p * p;
-  for (int idx = threadIdx.x; idx < nrows; idx += 256) {
-    const int j = svec_col(idx);
-    const int i = idx - j * (j + 1) / 2;
-    const T val = (i == j) ? g[d.row0 + idx] : g[d.row0 + idx] * (T)RSQRT2;
-    Tb[i + (size_t)j * p] = val;
-    Tb[j + (size_t)i * p] = val;
-  }
-}
-
-// Reverse of S_0 = S / c and of smat: Sbar += Y / c - <Y, S> S / c^3 with
-// Y = cotangent of S_0, then gin = svec of the symmetric part of Sbar.
-template <typename T>
-__global__ __launch_bounds__(256) void k_ns_final(const NsDesc *__restrict__ descs, const T *base,
-                                                  const double *cnorm, int32_t slot_y, int32_t slot_s,
-                                                  int32_t slot_sb, T *__restrict__ gin) {
-  __shared__ double red[256 / 64];
-  const NsDesc d = descs[blockIdx.x];
-  const int p = d.p, nrows = p * (p + 1) / 2;
-  const size_t pp = (size_t)p * p;
-  const T *Y = base + d.moff + slot_y * pp, *S = base + d.moff + slot_s * pp, *SB = base + d.moff + slot_sb * pp;
-  double dot = 0.0;
-  for (size_t e = threadIdx.x; e < pp; e += 256) dot += (double)Y[e] * (double)S[e];
-  dot = wg_sum<double, 256>(dot, red);
-  const double c = cnorm[blockIdx.x];
-  const T ic = (T)(1.0 / c), k3 = (T)(dot / (c * c * c));
-  for (int idx = threadIdx.x; idx < nrows; idx += 256) {
-    const int j = svec_col(idx);
-    const int i = idx - j * (j + 1) / 2;
-    const size_t a = i + (size_t)j * p, b = j + (size_t)i * p;
-    const T ga = SB[a] + Y[a] * ic - k3 * S[a];
-    if (i == j) gin[d.row0 + idx] = ga;
-    else gin[d.row0 + idx] = (ga + SB[b] + Y[b] * ic - k3 * S[b]) * (T)RSQRT2;
-  }
-}
-
 constexpr size_t LDS_LIMIT = 163840;
 
 // Allow a kernel the whole LDS of a workgroup minus its static allocation.
@@ -1237,48 +987,6 @@ void launch_psd_vjp(const PsdDesc *d, int32_t n, int32_t max_p, const T *U, cons
   k_psd_vjp<T, VJP_NT><<<n, VJP_NT, elems * sizeof(T), st>>>(d, U, lam, g, out, scratch, (int32_t)elems, rule, (T)eps);
 }
 
-template <typename T>
-void ns_gemm(const NsDesc *d, int32_t nblk, int32_t ntiles, int32_t tile, T *base, const NsGemm &g, hipStream_t st) {
-  if (tile == 64) k_ns_gemm<T, 64><<<ntiles, 256, 0, st>>>(d, nblk, base, g);
-  else k_ns_gemm<T, 32><<<ntiles, 256, 0, st>>>(d, nblk, base, g);
-}
-
-// Newton-Schulz forward: K steps of eq:newton-schulz, every iterate X_k and
-// square Q_k kept in the tape for the reverse pass, then
-// out = svec(sym((S + X_K S) / 2)).
-template <typename T>
-void launch_ns_forward(const NsDesc *d, int32_t nblk, int32_t ntiles, int32_t tile, int32_t K, const T *v, T *out,
-                       T *base, double *cnorm, hipStream_t st) {
-  const NsSlots sl(K);
-  k_ns_init<T><<<nblk, 256, 0, st>>>(d, v, base, cnorm, sl.x(0), sl.S);
-  for (int k = 0; k < K; ++k) {
-    ns_gemm<T>(d, nblk, ntiles, tile, base, NsGemm{sl.x(k), sl.x(k), sl.q(k), -1, 0, 0, 1.0, 0.0}, st);
-    ns_gemm<T>(d, nblk, ntiles, tile, base, NsGemm{sl.x(k), sl.q(k), sl.x(k + 1), sl.x(k), 0, 0, -0.5, 1.5}, st);
-  }
-  ns_gemm<T>(d, nblk, ntiles, tile, base, NsGemm{sl.x(K), sl.S, sl.W, sl.S, 0, 0, 0.5, 0.5}, st);
-  k_ns_pack<T><<<nblk, 256, 0, st>>>(d, base, sl.W, out);
-}
-
-// Newton-Schulz reverse pass from the tape of launch_ns_forward (same blocks
-// and K): for C = A B, Abar = Cbar B' and Bbar = A' Cbar.
-template <typename T>
-void launch_ns_vjp(const NsDesc *d, int32_t nblk, int32_t ntiles, int32_t tile, int32_t K, const T *g, T *gin,
-                   T *base, const double *cnorm, hipStream_t st) {
-  const NsSlots sl(K);
-  k_ns_unpack<T><<<nblk, 256, 0, st>>>(d, g, base, sl.TB);
-  // Pi = S / 2 + X_K S / 2
-  ns_gemm<T>(d, nblk, ntiles, tile, base, NsGemm{sl.x(K), sl.TB, sl.SB, sl.TB, 1, 0, 0.5, 0.5}, st);
-  ns_gemm<T>(d, nblk, ntiles, tile, base, NsGemm{sl.TB, sl.S, sl.Y, -1, 0, 1, 0.5, 0.0}, st);
-  for (int k = K - 1; k >= 0; --k) {
-    // X_{k+1} = 3/2 X_k - 1/2 X_k Q_k with Q_k = X_k X_k; Y = cotangent of X_{k+1}
-    ns_gemm<T>(d, nblk, ntiles, tile, base, NsGemm{sl.Y, sl.q(k), sl.Z, sl.Y, 0, 1, -0.5, 1.5}, st);
-    ns_gemm<T>(d, nblk, ntiles, tile, base, NsGemm{sl.x(k), sl.Y, sl.QB, -1, 1, 0, -0.5, 0.0}, st);
-    ns_gemm<T>(d, nblk, ntiles, tile, base, NsGemm{sl.QB, sl.x(k), sl.Z, sl.Z, 0, 1, 1.0, 1.0}, st);
-    ns_gemm<T>(d, nblk, ntiles, tile, base, NsGemm{sl.x(k), sl.QB, sl.Y, sl.Z, 1, 0, 1.0, 1.0}, st);
-  }
-  k_ns_final<T><<<nblk, 256, 0, st>>>(d, base, cnorm, sl.Y, sl.S, sl.SB, gin);
-}
-
 template void launch_psd_step<float>(const PsdDesc *, int32_t, const PsdLaunchCfg &, const float *, const float *,
                                      const float *, const float *, float *, float *, float *, float *, double *,
                                      const float *, cosmo_stats *, hipStream_t);
@@ -1289,13 +997,4 @@ template void launch_psd_vjp<float>(const PsdDesc *, int32_t, int32_t, const flo
                                     float *, float *, hipStream_t, int32_t, double);
 template void launch_psd_vjp<double>(const PsdDesc *, int32_t, int32_t, const double *, const double *,
                                      const double *, double *, double *, hipStream_t, int32_t, double);
-template void launch_ns_forward<float>(const NsDesc *, int32_t, int32_t, int32_t, int32_t, const float *, float *,
-                                       float *, double *, hipStream_t);
-template void launch_ns_forward<double>(const NsDesc *, int32_t, int32_t, int32_t, int32_t, const double *, double *,
-                                        double *, double *, hipStream_t);
-template void launch_ns_vjp<float>(const NsDesc *, int32_t, int32_t, int32_t, int32_t, const float *, float *, float *,
-                                   const double *, hipStream_t);
-template void launch_ns_vjp<double>(const NsDesc *, int32_t, int32_t, int32_t, int32_t, const double *, double *,
-                                    double *, const double *, hipStream_t);
-
 }  // namespace cosmo
