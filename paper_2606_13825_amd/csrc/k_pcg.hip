@@ -529,7 +529,28 @@ __global__ __launch_bounds__(CT) void k_pcg_coop(View<T> v, const T *__restrict_
       const int64_t n0 = v.n_off[b], n1 = v.n_off[b + 1];
       T rz = 0, rr = 0;
       double rrt = 0, dd = 0;
-      for (int64_t j = n0 + threadIdx.x; j < n1; j += CT) {
+      // four strides per pass, loads first (one workgroup streams the whole
+      // instance here); each thread still adds in index order
+      int64_t j = n0 + threadIdx.x;
+      for (; j + 3 * CT < n1; j += 4 * CT) {
+        T rv[4], dv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          rv[u] = r[j + u * CT];
+          dv[u] = dg[j + u * CT];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const T rj = rv[u];
+          const T zj = rj / dv[u];
+          z[j + u * CT] = zj;
+          p[j + u * CT] = zj;
+          rz += rj * zj;
+          rr += rj * rj;
+          rrt += (double)rj * (double)rj;
+        }
+      }
+      for (; j < n1; j += CT) {
         const T rj = r[j];
         const T zj = rj / dg[j];
         z[j] = zj;
@@ -567,7 +588,20 @@ __global__ __launch_bounds__(CT) void k_pcg_coop(View<T> v, const T *__restrict_
         if (!cs.act[b]) continue;
         const int64_t n0 = v.n_off[b], n1 = v.n_off[b + 1];
         T pMp = 0, dummy = 0;
-        for (int64_t j = n0 + threadIdx.x; j < n1; j += CT) pMp += p[j] * Mp[j];
+        {
+          int64_t j = n0 + threadIdx.x;
+          for (; j + 3 * CT < n1; j += 4 * CT) {
+            T pv[4], mv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              pv[u] = p[j + u * CT];
+              mv[u] = Mp[j + u * CT];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pMp += pv[u] * mv[u];
+          }
+          for (; j < n1; j += CT) pMp += p[j] * Mp[j];
+        }
         wg_sum2<CT>(pMp, dummy, red);
         const T rz = cs.rz[b];
         const bool step = pMp > (T)0;   // else breakdown: back to the true residual (fail if non-finite)
@@ -576,7 +610,29 @@ __global__ __launch_bounds__(CT) void k_pcg_coop(View<T> v, const T *__restrict_
         T rz_new = 0, rr_new = 0;
         if (step) {
           const T a = rz / pMp;
-          for (int64_t j = n0 + threadIdx.x; j < n1; j += CT) {
+          int64_t j = n0 + threadIdx.x;
+          for (; j + 3 * CT < n1; j += 4 * CT) {
+            T pv[4], mv[4], xv[4], rv[4], dv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              pv[u] = p[j + u * CT];
+              mv[u] = Mp[j + u * CT];
+              xv[u] = x[j + u * CT];
+              rv[u] = r[j + u * CT];
+              dv[u] = dg[j + u * CT];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              x[j + u * CT] = xv[u] + a * pv[u];
+              const T rj = rv[u] - a * mv[u];
+              const T zj = rj / dv[u];
+              r[j + u * CT] = rj;
+              z[j + u * CT] = zj;
+              rz_new += rj * zj;
+              rr_new += rj * rj;
+            }
+          }
+          for (; j < n1; j += CT) {
             x[j] += a * p[j];
             const T rj = r[j] - a * Mp[j];
             const T zj = rj / dg[j];
@@ -587,7 +643,18 @@ __global__ __launch_bounds__(CT) void k_pcg_coop(View<T> v, const T *__restrict_
           }
           wg_sum2<CT>(rz_new, rr_new, red);
           const T beta = rz_new / rz;
-          for (int64_t j = n0 + threadIdx.x; j < n1; j += CT) p[j] = z[j] + beta * p[j];
+          j = n0 + threadIdx.x;
+          for (; j + 3 * CT < n1; j += 4 * CT) {
+            T zv[4], pv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              zv[u] = z[j + u * CT];
+              pv[u] = p[j + u * CT];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) p[j + u * CT] = zv[u] + beta * pv[u];
+          }
+          for (; j < n1; j += CT) p[j] = z[j] + beta * p[j];
           fail = !isfinite(rr_new);
           act = !fail && rr_new > cs.tgt[b] && cs.it[b] + 1 < max_iter;
         }
