@@ -53,6 +53,9 @@ namespace {
 // per CU; the float64 instantiation needs more registers and runs 8 waves
 template <typename T> constexpr int PT = sizeof(T) == 4 ? 1024 : 512;
 constexpr int CT = 256;      // threads per workgroup of the cooperative form
+// strides per pass of the cooperative form's per-instance vector loops (8
+// keeps float32 within 128 VGPRs; float64 stays at 4)
+template <typename T> constexpr int VLOOP = sizeof(T) == 4 ? 8 : 4;
 constexpr int NRESTART = 4;          // restarts from a float64 residual, at most
 constexpr double ROUND_DROP2 = 1e-4;  // a restarted round lowers its residual by 1e-2 (squared here)
 constexpr double STALL2 = 0.25;       // a true residual that fell by less than 2x ends the refinement
@@ -482,6 +485,7 @@ __global__ __launch_bounds__(CT) void k_pcg_coop(View<T> v, const T *__restrict_
   __shared__ T red[2 * (CT / 64)];
   __shared__ double redd[2 * (CT / 64)];
   __shared__ int32_t bar_flag;
+  constexpr int VU = VLOOP<T>;
   const CoopState<T> cs = coop_state<T>(state, v.B);
   uint32_t *words = static_cast<uint32_t *>(state);
   const GridBar gb{words, words + 64, words + 128, gridDim.x};
@@ -529,18 +533,18 @@ __global__ __launch_bounds__(CT) void k_pcg_coop(View<T> v, const T *__restrict_
       const int64_t n0 = v.n_off[b], n1 = v.n_off[b + 1];
       T rz = 0, rr = 0;
       double rrt = 0, dd = 0;
-      // four strides per pass, loads first (one workgroup streams the whole
+      // VU strides per pass, loads first (one workgroup streams the whole
       // instance here); each thread still adds in index order
       int64_t j = n0 + threadIdx.x;
-      for (; j + 3 * CT < n1; j += 4 * CT) {
-        T rv[4], dv[4];
+      for (; j + (VU - 1) * CT < n1; j += VU * CT) {
+        T rv[VU], dv[VU];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < VU; ++u) {
           rv[u] = r[j + u * CT];
           dv[u] = dg[j + u * CT];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < VU; ++u) {
           const T rj = rv[u];
           const T zj = rj / dv[u];
           z[j + u * CT] = zj;
@@ -590,15 +594,15 @@ __global__ __launch_bounds__(CT) void k_pcg_coop(View<T> v, const T *__restrict_
         T pMp = 0, dummy = 0;
         {
           int64_t j = n0 + threadIdx.x;
-          for (; j + 3 * CT < n1; j += 4 * CT) {
-            T pv[4], mv[4];
+          for (; j + (VU - 1) * CT < n1; j += VU * CT) {
+            T pv[VU], mv[VU];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < VU; ++u) {
               pv[u] = p[j + u * CT];
               mv[u] = Mp[j + u * CT];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) pMp += pv[u] * mv[u];
+            for (int u = 0; u < VU; ++u) pMp += pv[u] * mv[u];
           }
           for (; j < n1; j += CT) pMp += p[j] * Mp[j];
         }
@@ -611,10 +615,10 @@ __global__ __launch_bounds__(CT) void k_pcg_coop(View<T> v, const T *__restrict_
         if (step) {
           const T a = rz / pMp;
           int64_t j = n0 + threadIdx.x;
-          for (; j + 3 * CT < n1; j += 4 * CT) {
-            T pv[4], mv[4], xv[4], rv[4], dv[4];
+          for (; j + (VU - 1) * CT < n1; j += VU * CT) {
+            T pv[VU], mv[VU], xv[VU], rv[VU], dv[VU];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < VU; ++u) {
               pv[u] = p[j + u * CT];
               mv[u] = Mp[j + u * CT];
               xv[u] = x[j + u * CT];
@@ -622,7 +626,7 @@ __global__ __launch_bounds__(CT) void k_pcg_coop(View<T> v, const T *__restrict_
               dv[u] = dg[j + u * CT];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < VU; ++u) {
               x[j + u * CT] = xv[u] + a * pv[u];
               const T rj = rv[u] - a * mv[u];
               const T zj = rj / dv[u];
@@ -644,15 +648,15 @@ __global__ __launch_bounds__(CT) void k_pcg_coop(View<T> v, const T *__restrict_
           wg_sum2<CT>(rz_new, rr_new, red);
           const T beta = rz_new / rz;
           j = n0 + threadIdx.x;
-          for (; j + 3 * CT < n1; j += 4 * CT) {
-            T zv[4], pv[4];
+          for (; j + (VU - 1) * CT < n1; j += VU * CT) {
+            T zv[VU], pv[VU];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < VU; ++u) {
               zv[u] = z[j + u * CT];
               pv[u] = p[j + u * CT];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) p[j + u * CT] = zv[u] + beta * pv[u];
+            for (int u = 0; u < VU; ++u) p[j + u * CT] = zv[u] + beta * pv[u];
           }
           for (; j < n1; j += CT) p[j] = z[j] + beta * p[j];
           fail = !isfinite(rr_new);
