@@ -54,6 +54,10 @@ EIG_PROFILE = os.path.join(ROOT, "profiles", "k_psd_eig_maxcut64_pmc.md")
 EIG_SOURCE = [os.path.join(ROOT, "paper_2606_13825_amd", "csrc", "k_psd.hip"),
               os.path.join(ROOT, "paper_2606_13825_amd", "csrc", "mma_tiles.h")]
 PCG_PROFILE = os.path.join(ROOT, "profiles", "k_pcg_huber256_pmc.md")
+NS_PROFILE = os.path.join(ROOT, "profiles", "k_ns_gemm_appc_pmc.md")
+NS_SOURCE = [os.path.join(ROOT, "paper_2606_13825_amd", "csrc", "k_ns.hip"),
+             os.path.join(ROOT, "paper_2606_13825_amd", "csrc", "mma_tiles.h")]
+APPB_PROFILE = os.path.join(ROOT, "profiles", "k_pcg_coop_appb_pmc.md")
 PCG_SOURCE = os.path.join(ROOT, "paper_2606_13825_amd", "csrc", "k_pcg.hip")
 
 
@@ -230,7 +234,10 @@ def psd_rules_study(samples=100, orders=(10, 20, 40, 80, 160, 320), delta=1e-5, 
         rows.append(row)
         ns_roof = {"kernel": "k_ns_gemm<float> (Newton-Schulz reverse pass)", "order": n, "bound": "mfma",
                    "achieved": row["ns_bwd_tflops"], "peak": 157.3, "unit": "TFLOP/s",
-                   "frac": row["ns_bwd_tflops"] / 157.3, "traffic": None}
+                   "frac": row["ns_bwd_tflops"] / 157.3,
+                   "traffic": traffic_from_profile(NS_PROFILE, NS_SOURCE, order=n),
+                   "traffic_per": "one k_ns_gemm launch (100 blocks) at this order; achieved is the "
+                                  "reverse pass's product flops over its event-timed duration"}
         print(f"[bench] psd rules order {n}: " + ", ".join(f"{k}={v:.3f}" for k, v in row.items() if k != "order"),
               file=sys.stderr, flush=True)
     print(json.dumps({"metric": "PSD-projection backward time per batch by rule (App. C matrices)",
@@ -324,7 +331,9 @@ def appb_study(ns=(1000, 2000, 5000, 10000, 20000, 50000), reps=3, seed=8):
                       "rows": rows,
                       "roofline": {"kernel": "k_pcg_coop<float> (backward adjoint solve)", "n": last["n"],
                                    "bound": "hbm", "achieved": last["bwd_cg_gbs"], "peak": PEAK_HBM_GBS,
-                                   "unit": "GB/s", "frac": last["bwd_cg_gbs"] / PEAK_HBM_GBS, "traffic": None}}))
+                                   "unit": "GB/s", "frac": last["bwd_cg_gbs"] / PEAK_HBM_GBS,
+                                   "traffic": traffic_from_profile(APPB_PROFILE, PCG_SOURCE, n=last["n"]),
+                                   "traffic_per": "one backward adjoint solve (one k_pcg_coop launch)"}}))
 
 
 def main():

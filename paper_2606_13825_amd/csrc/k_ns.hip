@@ -8,6 +8,8 @@
 namespace cosmo {
 namespace {
 
+constexpr int NXCD = 8;   // accelerator complex dies of the MI355X, one L2 each
+
 // Matrices live in a caller tape, column-major p x p per block, addressed by
 // slot: base + d.moff + slot p^2.
 
@@ -66,7 +68,13 @@ __global__ __launch_bounds__(256) void k_ns_gemm(const NsDesc *__restrict__ desc
   // each) start 16 banks apart
   constexpr int LDP = TILE + 16;
   __shared__ T As[TILE == 64 ? KC * LDP : 1], Bs[TILE == 64 ? KC * LDP : 1];
-  const int t = blockIdx.x;
+  // Workgroups are dealt to the 8 XCDs round-robin (workgroup b to XCD
+  // b mod 8), each XCD with its own L2: give XCD x a contiguous range of
+  // tiles, so the tiles of one matrix, which read the same operand panels,
+  // share an L2.  With N tiles, XCD x holds N/8 (+1 for x < N mod 8) of them.
+  const int nwg = gridDim.x, x = blockIdx.x % NXCD, k = blockIdx.x / NXCD;
+  const int q = nwg / NXCD, rem = nwg % NXCD;
+  const int t = x * q + (x < rem ? x : rem) + k;
   int lo = 0, hi = nblk - 1;                 // last block with tile0 <= t
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
