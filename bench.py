@@ -1,18 +1,20 @@
 """Benchmark: batched forward + backward unrolled COSMO on one MI355X.
 
 Workloads (synthetic stand-ins with the shapes of the paper's App. F
-classes; `--workload`, default c2):
+classes; `--workload`, default c4, the largest configuration that runs on
+one GPU):
 
   c1  one max-cut SDP on G(20, 0.3), float64, K = 100, forward only,
       CG tolerance 1e-10
   c2  64 max-cut SDPs, orders p ~ U{30..100}, edge probability U(0.1, 0.5),
       float32, K = 50 with per-step, per-row rho^k and per-instance alpha^k,
-      forward + loss + backward (the headline configuration)
+      forward + loss + backward
   c3  32 Lovasz theta SDPs on random circulant graphs, n ~ U{64..200},
       float32, K = 50, forward + loss + backward
   c4  256 Huber-regression SOCPs (2000 x 500 Gaussian design, Student-t
       noise, 200 second-order cones of dimension 3-10), float32, K = 40,
-      forward + loss + backward
+      forward + loss + backward; the design is passed once as a dense block
+      placed at +G and -G (the default line)
   c5  128 covariance-steering SDPs (nx in {4..12}, nu = nx/2, T ~ U{30..100}),
       float32, K = 30, forward + loss + backward
 
@@ -21,8 +23,10 @@ inputs resident in HBM.  Prints one JSON line: instance-iterations per
 second (B K / time per step), peak HBM of the batched pass against the plain
 forward (B sequential single-instance forward-only calls, no tape), the
 roofline of the dominant kernel measured with HIP events recorded by the
-library on the stream the kernel runs on, and the float64 oracle's own
-throughput on the host cores over a bounded sample (cpu_baseline).
+library on the stream the kernel runs on, the float64 oracle's own
+throughput on the host cores over a bounded sample (cpu_baseline), and the
+error of the timed run against the oracle's full K-step runs of sampled
+instances (rel_err_vs_oracle).
 """
 import argparse
 import hashlib
@@ -93,12 +97,33 @@ def traffic_from_profile(profile, source, **match):
 
 
 def pcg_bytes_per_iteration(inst, esz):
-    """Algorithmic HBM bytes of one PCG iteration on one instance: the values
-    and column indices of A and A' (one pass each) and of P, plus the vectors
-    the iteration streams (p, t = rho A p, M p, x, r, z)."""
+    """Algorithmic HBM bytes of one PCG iteration (one operator application)
+    on one instance: the values and column indices of A and A' (one pass
+    each) and of P, plus the vectors the iteration streams (p, t = rho A p,
+    M p, x, r, z).  A dense block (meta["dense"]) counts once, rows x cols
+    values, however many placements it has; the CSR remainder counts as
+    above."""
     nnz_a = inst.A.nnz
+    dense_bytes = 0
+    d = (getattr(inst, "meta", None) or {}).get("dense")
+    if d:
+        A = inst.A.tocsr()
+        for (r0, _) in d["place"]:
+            nnz_a -= A[int(r0):int(r0) + d["rows"], d["col0"]:d["col0"] + d["cols"]].nnz
+        dense_bytes = d["rows"] * d["cols"] * esz
     nnz_p = inst.P.nnz if inst.P is not None else 0
-    return 2 * nnz_a * (esz + 4) + nnz_p * (esz + 4) + esz * (6 * inst.n + 2 * inst.m)
+    return dense_bytes + 2 * nnz_a * (esz + 4) + nnz_p * (esz + 4) + esz * (6 * inst.n + 2 * inst.m)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def _workload(name):
@@ -106,23 +131,23 @@ def _workload(name):
     f32 = lambda xs: [x.astype(np.float32) for x in xs]
     if name == "c1":
         return dict(name="maxcut_sdp_G20p0.3_fp64_K100_forward", insts=[synth.c1_instance()], K=100, dtype="f64",
-                    backward=False, cg_tol=1e-10, hyper="default", cpu_sample=1, cpu_steps=100, roofline="eig")
+                    backward=False, cg_tol=1e-10, hyper="default", cpu_sample=1, cpu_steps=100, err_sample=0)
     if name == "c2":
         return dict(name="maxcut_sdp_batch64_p30-100_fp32_K50", insts=f32(synth.c2_batch()), K=50, dtype="f32",
-                    backward=True, hyper="perturbed", seed=2, cpu_sample=16, cpu_steps=50, roofline="eig")
+                    backward=True, hyper="perturbed", seed=2, cpu_sample=16, cpu_steps=50, err_sample=0)
     if name == "c3":
         # cond(M) ~ 2e5 here (trace row, rho_eq n): a relative residual of 1e-8 admits solve errors of ~2e-3
         # against the exact solve, so the CG runs to 1e-10 (in float32 it then stops at the precision floor)
         return dict(name="lovasz_circulant_batch32_n64-200_fp32_K50", insts=f32(synth.c3_batch()), K=50,
-                    dtype="f32", backward=True, hyper="default", cpu_sample=16, cpu_steps=10, roofline="eig",
+                    dtype="f32", backward=True, hyper="default", cpu_sample=16, cpu_steps=10, err_sample=2,
                     cg_tol=1e-10)
     if name == "c4":
         return dict(name="huber_socp_batch256_2000x500_200soc_fp32_K40", insts=f32(synth.c4_batch()), K=40,
-                    dtype="f32", backward=True, hyper="default", cpu_sample=16, cpu_steps=2, roofline="pcg",
+                    dtype="f32", backward=True, hyper="default", cpu_sample=16, cpu_steps=2, err_sample=2,
                     cg_max_iter=1000)
     if name == "c5":
         return dict(name="covsteer_sdp_batch128_nx4-12_T30-100_fp32_K30", insts=f32(synth.c5_batch()), K=30,
-                    dtype="f32", backward=True, hyper="default", cpu_sample=16, cpu_steps=30, roofline="eig",
+                    dtype="f32", backward=True, hyper="default", cpu_sample=16, cpu_steps=30, err_sample=0,
                     cg_max_iter=2000)
     raise SystemExit(f"unknown workload {name}")
 
@@ -170,6 +195,19 @@ def cpu_baseline(wl, rhos, alphas, n_sample, steps, workers):
     with ctx.Pool(workers) as pool:
         res = pool.map(_oracle_job, jobs)
     return time.perf_counter() - t0, res
+
+
+def start_error_leg(wl, rhos, alphas, n_err):
+    """The oracle's full K-step runs (forward and, if timed, backward) of the
+    first n_err instances, one process each, started before this process
+    touches the GPU and collected after the timed GPU run; they give the
+    error of that run against the oracle when the throughput sample covers
+    fewer than K steps.  Returns (pool, async result)."""
+    import multiprocessing as mp
+    jobs = [(wl["insts"][i], rhos[i].astype(np.float64), alphas[i].astype(np.float64), wl["backward"])
+            for i in range(n_err)]
+    pool = mp.get_context("fork").Pool(n_err)
+    return pool, pool.map_async(_oracle_job, jobs)
 
 
 def _copy_calibration():
@@ -341,7 +379,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--cpu-sample", type=int, default=None, help="instances in the oracle sample")
     ap.add_argument("--schedule", default="auto", choices=["auto", "eager0"],
                     help="auto: the autotuner's choice; eager0: CG form 0, eager launches")
@@ -380,14 +418,21 @@ def main():
     print(f"[bench] workload {wl['name']}: B={B} K={K}", file=sys.stderr, flush=True)
 
     cpu = None
+    err_leg = None
     if not args.no_cpu_baseline:
         try:
             aff = len(os.sched_getaffinity(0))
         except AttributeError:
             aff = os.cpu_count() or 1
+        aff = min(16, aff)
         n_s = min(args.cpu_sample or wl["cpu_sample"], B)
-        workers = max(1, min(16, aff, n_s))
         steps = min(wl["cpu_steps"], K)
+        n_err = min(wl["err_sample"], B) if steps < K else 0
+        if n_err:
+            err_leg = (start_error_leg(wl, rhos, alphas, n_err), n_err)
+            print(f"[bench] error leg: oracle runs of {n_err} instances x {K} steps started", file=sys.stderr,
+                  flush=True)
+        workers = max(1, min(aff - n_err, n_s))
         wall, res = cpu_baseline(wl, rhos, alphas, n_s, steps, workers)
         cpu = (wall, res, workers, n_s, steps)
         print(f"[bench] cpu baseline: {n_s} instances x {steps} steps in {wall:.1f} s on {workers} processes",
@@ -404,9 +449,15 @@ def main():
         if key in wl:
             kw[key] = wl[key]
 
+    torch.cuda.synchronize(dev)
     torch.cuda.reset_peak_memory_stats(dev)
     base_mem = torch.cuda.memory_allocated(dev)
+    free0, res0 = torch.cuda.mem_get_info(dev)[0], torch.cuda.memory_reserved(dev)
     batch = CosmoBatch(insts, K=K, dtype=tdt, device=dev, **kw)
+    torch.cuda.synchronize(dev)
+    # the plan's own device buffer (transposed CSR, descriptors, maps): the
+    # device's free memory fell by more than torch reserved
+    plan_bytes = max(0, (free0 - torch.cuda.mem_get_info(dev)[0]) - (torch.cuda.memory_reserved(dev) - res0))
     rho = torch.from_numpy(np.concatenate(rhos, axis=1)).to(dev)
     alpha = torch.from_numpy(np.stack(alphas, axis=1)).to(dev)
     tape = batch.new_tape() if backward else None
@@ -451,7 +502,7 @@ def main():
         fw, loss, bw = step()
     torch.cuda.synchronize(dev)
     dt = (time.perf_counter() - t0) / args.steps
-    peak_fb = torch.cuda.max_memory_allocated(dev) - base_mem
+    peak_fb = torch.cuda.max_memory_allocated(dev) - base_mem + plan_bytes
     print(f"[bench] {'fwd+bwd' if backward else 'fwd'} {dt * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
 
     if args.quick:
@@ -496,7 +547,7 @@ def main():
                             "traffic": (traffic_from_profile(EIG_PROFILE, EIG_SOURCE, order_class=dom)
                                         if args.workload == "c2" else None),
                             "flops_per_launch": flops, "blocks_per_launch": int(np.sum(cls_of == dom)),
-                            "avg_launch_ms": avg_ms, "launches": n_dom}
+                            "avg_launch_ms": avg_ms, "launches": n_dom, "ms_per_step": ms_dom}
     n_pcg, ms_pcg = fam["pcg"]
     if n_pcg > 0:
         esz = 4 if wl["dtype"] == "f32" else 8
@@ -509,24 +560,31 @@ def main():
         form = batch.pcg_form()
         tn = "float" if esz == 4 else "double"
         kname = (f"k_pcg_coop<{tn}> (cooperative, <= {form} workgroups per CU)" if form > 0
-                 else f"k_pcg<{tn}> (one workgroup per instance)")
+                 else f"k_pcg<{tn}> (one workgroup per instance"
+                      + (", dense blocks fused)" if batch.n_dense else ")"))
         rooflines["pcg"] = {"kernel": kname, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                             "frac": ach / PEAK_HBM_GBS,
                             "traffic": (traffic_from_profile(PCG_PROFILE, PCG_SOURCE, pcg_form=form)
                                         if args.workload == "c4" else None),
                             "bytes_per_launch": total / n_pcg, "avg_launch_ms": avg_ms, "launches": n_pcg,
                             "mean_cg_iterations": float(iters.sum() / (n_pcg * B)),
-                            "mean_residual_passes": float(passes.sum() / (n_pcg * B))}
-    primary = wl["roofline"] if wl["roofline"] in rooflines else next(iter(rooflines), None)
+                            "mean_residual_passes": float(passes.sum() / (n_pcg * B)),
+                            "ms_per_step": ms_pcg}
+    # the primary roofline is that of the kernel taking the most time per step
+    primary = max(rooflines, key=lambda k: rooflines[k]["ms_per_step"]) if rooflines else None
 
     plain = None
     peak_plain = None
     if not args.no_plain:
         del tape, fws, bws
         torch.cuda.empty_cache()
+        torch.cuda.synchronize(dev)
         torch.cuda.reset_peak_memory_stats(dev)
         base_mem2 = torch.cuda.memory_allocated(dev)
+        free1, res1 = torch.cuda.mem_get_info(dev)[0], torch.cuda.memory_reserved(dev)
         singles = [CosmoBatch([inst], K=K, dtype=tdt, device=dev, **kw) for inst in insts]
+        torch.cuda.synchronize(dev)
+        plan_bytes_plain = max(0, (free1 - torch.cuda.mem_get_info(dev)[0]) - (torch.cuda.memory_reserved(dev) - res1))
         srho = [torch.from_numpy(r).to(dev) for r in rhos]
         salpha = [torch.from_numpy(a.reshape(K, 1)).to(dev) for a in alphas]
         for i in range(min(2, B)):
@@ -537,7 +595,7 @@ def main():
             singles[i].forward(srho[i], salpha[i], tape=False)
         torch.cuda.synchronize(dev)
         dt_plain = time.perf_counter() - t1
-        peak_plain = torch.cuda.max_memory_allocated(dev) - base_mem2
+        peak_plain = torch.cuda.max_memory_allocated(dev) - base_mem2 + plan_bytes_plain
         plain = {"value": B * K / dt_plain, "unit": "instance-iterations/s", "ms_total": dt_plain * 1e3}
         print(f"[bench] plain forward {dt_plain * 1e3:.2f} ms for B={B}", file=sys.stderr, flush=True)
 
@@ -569,15 +627,24 @@ def main():
     if cpu is not None:
         wall, res, workers, n_s, steps = cpu
         out["cpu_baseline"] = {"value": n_s * steps / wall, "unit": "instance-iterations/s", "cores": workers,
-                               "kind": "oracle",
+                               "kind": "oracle", "cpu_model": cpu_model(),
                                "sample": f"first {n_s} instances of the batch, first {steps} of {K} steps, "
                                          f"{'forward+loss+backward' if backward else 'forward'}, float64, "
                                          f"{workers} single-threaded processes"}
+        # error of the timed GPU run against the oracle's full K-step runs:
+        # the throughput sample when it covers all K steps, else the error leg
+        ref_runs = None
         if steps == K:
-            # error of the timed GPU run against the oracle on the same sample
+            ref_runs = res
+        elif err_leg is not None:
+            (pool, pending), n_err = err_leg
+            ref_runs = pending.get()
+            pool.close()
+            pool.join()
+        if ref_runs is not None:
             e_it, e_g = 0.0, 0.0
             xs, ss, ys = batch.split_n(fw.x), batch.split_m(fw.s), batch.split_m(fw.y)
-            for i, (_, x, s, y, grho, galpha) in enumerate(res):
+            for i, (_, x, s, y, grho, galpha) in enumerate(ref_runs):
                 for gpu, ref in ((xs[i], x), (ss[i], s), (ys[i], y)):
                     e_it = max(e_it, np.linalg.norm(gpu.double().cpu().numpy() - ref) /
                                max(np.linalg.norm(ref), 1e-12))
@@ -587,7 +654,7 @@ def main():
                     ga = bw.galpha[:, i].double().cpu().numpy()
                     e_g = max(e_g, np.linalg.norm(ga - galpha) / max(np.linalg.norm(galpha), 1e-12))
             out["rel_err_vs_oracle"] = {"final_iterates_max": e_it, "gradients_max": e_g if backward else None,
-                                        "instances": n_s}
+                                        "instances": len(ref_runs), "steps": K}
     print(json.dumps(out))
 
 

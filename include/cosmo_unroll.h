@@ -5,7 +5,7 @@
  * K a product of zero, nonnegative, second-order (SOC) and PSD cones.
  *
  * One forward step k (Sec. "Conic Operator Splitting Method", indirect mode
- * eq:cosmo_linear_system_reduced; per-block penalty rectification of App. D,
+ * eq:cosmo_linear_system_reduced; per-block penalty rectification of App. E,
  * "Hyperparameter policy"):
  *   rho_hat = rectify(rho^k)                       (mean over each SOC/PSD block)
  *   x~  solves (P + sigma I + A' D(rho_hat) A) x~ = sigma x - q + A'(y + rho_hat o (b - s))
@@ -76,6 +76,38 @@ typedef enum {
 
 typedef struct cosmo_plan cosmo_plan;
 
+/* A dense sub-block of A (Sec. "Matrix-Free Implicit Differentiation": the
+ * method only ever applies A and A' to vectors, at O(n + nnz(A)) cost, so a
+ * dense block is read as a dense block instead of as CSR with an index per
+ * entry).  The matrix the library uses is
+ *     A = (the CSR arrays of cosmo_problem)
+ *         + sum over dense blocks and their placements of scale[p] * G
+ *           placed at rows row0[p] .. row0[p] + rows - 1 and columns
+ *           col0 .. col0 + cols - 1,
+ * so the CSR arrays hold only the entries outside the dense blocks.  One G
+ * may be placed at several row offsets with different scales (e.g. [G; -G]):
+ * every operator application then reads G once.
+ * Constraints (COSMO_EINVAL otherwise, before any device access): all rows
+ * and columns of a block lie inside one instance; no row of A lies in two
+ * placements (of any blocks); no column lies in two blocks; 1 <= cols <=
+ * COSMO_DENSE_MAX_COLS; ld >= cols and ld a multiple of 16 / sizeof(dtype);
+ * val 16-byte aligned.  While dense blocks are present the CG runs in form 0
+ * (cosmo_plan_set_pcg_form with form > 0 returns COSMO_EUNSUPPORTED). */
+#define COSMO_DENSE_MAX_PLACEMENTS 4
+#define COSMO_DENSE_MAX_COLS 1024
+typedef struct {
+  const void *val;             /* (d) rows x ld, row-major, dtype; valid and unchanged
+                                  until cosmo_plan_destroy                              */
+  int32_t rows;                /* >= 1                                                  */
+  int32_t cols;                /* 1 .. COSMO_DENSE_MAX_COLS                             */
+  int64_t ld;                  /* elements between consecutive rows of val              */
+  int64_t col0;                /* first column of the block in the stacked A           */
+  int32_t n_place;             /* placements, 1 .. COSMO_DENSE_MAX_PLACEMENTS           */
+  int32_t reserved;            /* must be 0                                             */
+  int64_t row0[COSMO_DENSE_MAX_PLACEMENTS];   /* first row of each placement            */
+  double scale[COSMO_DENSE_MAX_PLACEMENTS];   /* finite multiplier of each placement    */
+} cosmo_dense_block;
+
 /* Problem data of a super-batch.  Arrays marked (d) are device pointers that
  * must stay valid and unchanged until cosmo_plan_destroy; (h) are host arrays
  * read during cosmo_plan_create only. */
@@ -99,6 +131,9 @@ typedef struct {
                                   covering rows 0..m_tot, none straddling instances     */
   const int32_t *cone_kind;    /* (h) [n_cones] cosmo_cone_kind                         */
   const int32_t *cone_size;    /* (h) [n_cones] rows (zero/nonneg/soc) or order p (psd) */
+  int32_t n_dense;             /* dense sub-blocks of A (0: A is the CSR arrays alone)  */
+  const cosmo_dense_block *dense;   /* (h) [n_dense] descriptors; the blocks' values
+                                       are device arrays (see cosmo_dense_block)        */
 } cosmo_problem;
 
 typedef struct {
@@ -275,7 +310,10 @@ cosmo_status socp_proj_vjp(int32_t ncones, const int32_t *dim, const int64_t *of
  * available).  Both forms compute the same iteration with the same stopping
  * rule; their sums are taken in different orders, each deterministic.
  * set_pcg_form: form outside 0..4 is COSMO_EINVAL; a cooperative form while
- * graph mode is on is COSMO_EUNSUPPORTED. */
+ * graph mode is on, or on a plan with dense blocks, is COSMO_EUNSUPPORTED.
+ * With dense blocks, form 0 reads each block once per operator application:
+ * the row products G v, the penalty weights and the transposed products
+ * G'(D (A v)) are fused per row of G inside the instance's workgroup. */
 cosmo_status cosmo_plan_set_pcg_form(cosmo_plan *plan, int32_t form);
 cosmo_status cosmo_plan_get_pcg_form(const cosmo_plan *plan, int32_t *form);
 

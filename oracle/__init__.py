@@ -15,7 +15,7 @@ It is a plain, slow, step-by-step restatement of:
     for the linear solve (eq:grad_rho and the stacked gradient after it) and
     the Daleckii-Krein rule for the PSD projection (eq:psd-cotangent-dk,
     eq:lowner);
-  * the per-block rectification of penalties (App. D, "Hyperparameter
+  * the per-block rectification of penalties (App. E, "Hyperparameter
     policy", last paragraph);
   * the final-residual training loss used by the batched max-cut workload;
   * the comparison backward rules of the PSD projection: the eigendecomposition

@@ -24,7 +24,7 @@ def _blocks(cones):
         r += d
 
 
-# --- rectification (App. D "Hyperparameter policy", final paragraph) -------
+# --- rectification (App. E "Hyperparameter policy", final paragraph) -------
 
 def rectify(rho: np.ndarray, cones) -> np.ndarray:
     """Average the per-row penalties inside every SOC and PSD block and

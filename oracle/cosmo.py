@@ -5,7 +5,7 @@ An instance is any object with attributes P (n x n sparse, symmetric), q [n],
 A (m x n sparse), b [m] and cones (see cones.py).
 
 Forward step k (Sec. "Conic Operator Splitting Method", reduced form
-eq:cosmo_linear_system_reduced; penalties rectified per App. D):
+eq:cosmo_linear_system_reduced; penalties rectified per App. E):
     rho_hat = rectify(rho^k)
     M       = P + sigma I + A' D(rho_hat) A
     xi      = sigma x - q + A'(y + rho_hat o (b - s))
@@ -147,7 +147,7 @@ def unroll_backward(inst, tape: List[dict], gxK, gsK, gyK, sigma=1e-6):
 def kkt_residuals(inst, x, s, y):
     """Primal r_p = Ax + s - b and dual r_d = Px + q - A'y.
 
-    The paper prints the dual residual with +A'y (loss, App. D); with the
+    The paper prints the dual residual with +A'y (loss features, App. E); with the
     iteration as written the fixed point satisfies Px + q - A'y = 0
     (y lies in the polar cone), so the minus sign is the reading used."""
     rp = inst.A @ x + s - inst.b

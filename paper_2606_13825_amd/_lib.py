@@ -29,6 +29,24 @@ EXPORTED = [
 PSD_RULES = {"dk": 0, "naive": 1, "tikhonov": 2}
 
 
+DENSE_MAX_PLACEMENTS = 4
+DENSE_MAX_COLS = 1024
+
+
+class CosmoDenseBlock(ctypes.Structure):
+    _fields_ = [
+        ("val", ctypes.c_void_p),
+        ("rows", ctypes.c_int32),
+        ("cols", ctypes.c_int32),
+        ("ld", ctypes.c_int64),
+        ("col0", ctypes.c_int64),
+        ("n_place", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("row0", ctypes.c_int64 * DENSE_MAX_PLACEMENTS),
+        ("scale", ctypes.c_double * DENSE_MAX_PLACEMENTS),
+    ]
+
+
 class CosmoProblem(ctypes.Structure):
     _fields_ = [
         ("B", ctypes.c_int32),
@@ -47,6 +65,8 @@ class CosmoProblem(ctypes.Structure):
         ("n_cones", ctypes.c_int32),
         ("cone_kind", ctypes.POINTER(ctypes.c_int32)),
         ("cone_size", ctypes.POINTER(ctypes.c_int32)),
+        ("n_dense", ctypes.c_int32),
+        ("dense", ctypes.POINTER(CosmoDenseBlock)),
     ]
 
 

@@ -7,6 +7,10 @@ computed here.
 An instance is any object with attributes P (n x n scipy sparse, symmetric),
 q [n], A (m x n scipy sparse), b [m] and cones (objects with .kind in
 {"zero", "nonneg", "soc", "psd"} and .size = rows, or matrix order for psd).
+An instance may describe a dense sub-block of A in meta["dense"] =
+{"col0", "rows", "cols", "place": [(row0, scale), ...]} (first scale 1): the
+library then receives that block once as a dense array (cosmo_dense_block)
+and A without those entries as CSR.
 """
 from __future__ import annotations
 
@@ -43,6 +47,33 @@ def _psd_rows(p: int) -> int:
     return p * (p + 1) // 2
 
 
+def _split_dense(inst, npdt):
+    """(CSR remainder of A, dense block G or None, its description).  G is
+    read from A at the first placement (scale 1); every other placement
+    must hold exactly scale * G in the run dtype, and the entries of every
+    placement are dropped from the CSR remainder.  A copy, no arithmetic."""
+    desc = (getattr(inst, "meta", None) or {}).get("dense")
+    A = inst.A.tocsr()
+    if not desc:
+        return A, None, None
+    r0, c0 = int(desc["place"][0][0]), int(desc["col0"])
+    rows, cols = int(desc["rows"]), int(desc["cols"])
+    if float(desc["place"][0][1]) != 1.0:
+        raise ValueError("the first placement of a dense block must have scale 1")
+    G = A[r0:r0 + rows, c0:c0 + cols].toarray().astype(npdt)
+    for (row0, sc) in desc["place"][1:]:
+        blk = A[int(row0):int(row0) + rows, c0:c0 + cols].toarray().astype(npdt)
+        if not np.array_equal(blk, (npdt(sc) * G).astype(npdt)):
+            raise ValueError("a dense placement does not hold scale * G")
+    C = A.tocoo()
+    keep = np.ones(C.nnz, bool)
+    for (row0, _) in desc["place"]:
+        keep &= ~((C.row >= int(row0)) & (C.row < int(row0) + rows) & (C.col >= c0) & (C.col < c0 + cols))
+    import scipy.sparse as sp
+    R = sp.csr_matrix((C.data[keep], (C.row[keep], C.col[keep])), shape=A.shape)
+    return R, G, desc
+
+
 @dataclass
 class ForwardResult:
     x: torch.Tensor
@@ -66,7 +97,8 @@ class CosmoBatch:
 
     def __init__(self, instances: Sequence, *, K: int, dtype=torch.float32, sigma: float = 1e-6,
                  cg_tol: Optional[float] = None, cg_max_iter: int = 500, eig_max_sweeps: int = 60,
-                 eig_tol: float = 0.0, eig_refine: int = 1, eig_warm_start: bool = True, device="cuda:0"):
+                 eig_tol: float = 0.0, eig_refine: int = 1, eig_warm_start: bool = True, dense: bool = True,
+                 device="cuda:0"):
         self.device = torch.device(device)
         self.code = _dt_code(dtype)
         self.dtype = _TORCH_DT[self.code]
@@ -85,8 +117,14 @@ class CosmoBatch:
         arp, acol, aval, prp, pcol, pval = [np.zeros(1, np.int64)], [], [], [np.zeros(1, np.int64)], [], []
         annz = pnnz = 0
         kinds, sizes = [], []
+        dense_parts = []   # (instance, G, description)
         for i, inst in enumerate(instances):
-            A = inst.A.tocsr()
+            if dense:
+                A, G, desc = _split_dense(inst, npdt)
+                if G is not None:
+                    dense_parts.append((i, G, desc))
+            else:
+                A = inst.A.tocsr()
             A.sort_indices()
             arp.append(A.indptr[1:].astype(np.int64) + annz)
             acol.append(A.indices.astype(np.int32) + np.int32(self.n_off[i]))
@@ -117,6 +155,34 @@ class CosmoBatch:
         self.b = torch.from_numpy(np.concatenate([np.asarray(inst.b, np.float64) for inst in instances]).astype(npdt)).to(dev)
         self.cone_kind = np.asarray(kinds, np.int32)
         self.cone_size = np.asarray(sizes, np.int32)
+        # dense blocks: one device array, each block row-major with ld a
+        # multiple of 16 bytes (every block starts 16-byte aligned)
+        ve = 16 // np.dtype(npdt).itemsize
+        self.n_dense = len(dense_parts)
+        self._dense_desc = (L.CosmoDenseBlock * max(1, self.n_dense))()
+        self.dense_val = None
+        if dense_parts:
+            chunks, offs, off = [], [], 0
+            for k, (i, G, desc) in enumerate(dense_parts):
+                rows, cols = G.shape
+                ld = (cols + ve - 1) // ve * ve
+                Gp = np.zeros((rows, ld), npdt)
+                Gp[:, :cols] = G
+                chunks.append(Gp.ravel())
+                d = self._dense_desc[k]
+                d.rows, d.cols, d.ld = rows, cols, ld
+                d.col0 = int(self.n_off[i]) + int(desc["col0"])
+                d.n_place = len(desc["place"])
+                d.reserved = 0
+                for q, (row0, sc) in enumerate(desc["place"]):
+                    d.row0[q] = int(self.m_off[i]) + int(row0)
+                    d.scale[q] = float(sc)
+                offs.append(off)   # element offset in the device array
+                off += Gp.size
+            self.dense_val = torch.from_numpy(np.concatenate(chunks)).to(self.device)
+            base = self.dense_val.data_ptr()
+            for k in range(self.n_dense):
+                self._dense_desc[k].val = base + offs[k] * np.dtype(npdt).itemsize
         self.instances_meta = [(ns[i], ms[i]) for i in range(self.B)]
         prob = L.CosmoProblem()
         prob.B = self.B
@@ -135,6 +201,8 @@ class CosmoBatch:
         prob.n_cones = len(kinds)
         prob.cone_kind = self.cone_kind.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         prob.cone_size = self.cone_size.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        prob.n_dense = self.n_dense
+        prob.dense = ctypes.cast(self._dense_desc, ctypes.POINTER(L.CosmoDenseBlock))
         opt = L.CosmoOptions()
         opt.dtype = self.code
         opt.K = self.K

@@ -37,6 +37,22 @@ struct RectDesc {     // a block whose penalty is averaged (SOC or PSD)
   int32_t pad;
 };
 
+// One dense sub-block G of A (cosmo_dense_block) as the kernels see it: its
+// placements, the instance owning it, and where its per-row and per-column
+// results go in the dense scratch vectors (doff: rows, coff: columns).
+struct DenseDesc {
+  const void *val;    // rows x ld, row-major, dtype
+  int64_t ld;
+  int64_t col0;
+  int64_t doff, coff;
+  int64_t row0[COSMO_DENSE_MAX_PLACEMENTS];
+  double scale[COSMO_DENSE_MAX_PLACEMENTS];
+  int32_t rows, cols;
+  int32_t nplace, inst;
+  int32_t wg_rows0;   // first workgroup of this block in a row-product launch
+  int32_t wg_cols0;   // first workgroup of this block in a column-product launch
+};
+
 // Entry range [kb, k1) of one row, listed beside the bucket lists so a row's
 // range is one 16-byte load rather than a load of the row id and then two of
 // the row pointer.
@@ -80,6 +96,15 @@ template <typename T> struct View {
   const int64_t *instA; const int64_t *instAt;
   int32_t B; int64_t n_tot, m_tot;
   T sigma;
+  // dense sub-blocks (dense == nullptr: none).  dense_inst[b] .. dense_inst[b + 1]
+  // are instance b's blocks; drow[i] is row i's entry in dn (or -1) and
+  // dscale[i] the scale of the placement covering it; dcol[j] is column j's
+  // entry in ec / ed (or -1).  dn, ec, ed are float64 scratch vectors of the
+  // call's workspace (block rows, block columns, block columns).
+  const DenseDesc *dense; const int32_t *dense_inst;
+  const int32_t *drow; const double *dscale; const int32_t *dcol;
+  int32_t n_dense, dense_maxcols, dense_wg_rows, dense_wg_cols;
+  double *dn; double *ec; double *ed;
 };
 
 // Outputs of the in-kernel diagonal solve (all null: the PCG kernel solves).
@@ -126,6 +151,23 @@ template <typename T> void launch_fill(T *dst, T val, int64_t n, hipStream_t st)
 template <typename T> void launch_nonfinite_check(const View<T> &v, const T *x, const T *s, const T *y,
                                                   cosmo_stats *stats, hipStream_t st);
 
+// Dense sub-blocks (k_dense.hip).  Row products: dn[doff + r] = G_r . vin
+// over the block's columns (float64 accumulation).  Column products:
+// ec[coff + c] = sum_r G_rc w_r with w_r = sum_p scale_p u(row0_p + r), and
+// (with the Jacobi diagonal) ed[coff + c] = sum_r G_rc^2 sum_p scale_p^2 rho_hat(row0_p + r),
+// where u depends on the mode.
+enum DenseColMode : int32_t {
+  DC_XI = 0,    // u = y + rho_hat (b - s), with ed
+  DC_GST = 1,   // u = gst, with ed
+  DC_Y = 2,     // u = y
+  DC_RP = 3     // u = rp
+};
+template <typename T> void launch_dense_rows(const View<T> &v, const T *vin, hipStream_t st);
+int32_t dense_row_workgroups(int32_t rows);
+int32_t dense_col_workgroups(int32_t cols, size_t esz);
+template <typename T> void launch_dense_cols(const View<T> &v, int32_t mode, const T *rho_hat, const T *u,
+                                            const T *s, hipStream_t st);
+
 // PCG (k_pcg.hip): one workgroup per instance.
 //   mode 0 (forward): solves M x = rhs, warm start from x (in/out), writes
 //     xt_out (may alias x) and, if xnew != nullptr, x+ = alpha x~ + (1 - alpha) xold.
@@ -157,8 +199,9 @@ template <typename T> void launch_psd_step(const PsdDesc *d, int32_t n, const Ps
                                            T *y_new, T *U, T *lam, double *rscratch, const T *Uprev,
                                            cosmo_stats *stats, hipStream_t st);
 // rule 0 = Daleckii-Krein, 1 = eigendecomposition rule as autograd forms it,
-// 2 = rule 1 at the eigenvalues shifted by eps (Tikhonov)
-template <typename T> void launch_psd_vjp(const PsdDesc *d, int32_t n, int32_t max_p, const T *U, const T *lam,
+// 2 = rule 1 at the eigenvalues shifted by eps (Tikhonov).  Returns false
+// (nothing launched) when a block of order max_p does not fit in LDS.
+template <typename T> bool launch_psd_vjp(const PsdDesc *d, int32_t n, int32_t max_p, const T *U, const T *lam,
                                           const T *g, T *out, T *scratch, hipStream_t st, int32_t rule = 0,
                                           double eps = 0.0);
 

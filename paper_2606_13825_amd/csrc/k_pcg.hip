@@ -53,9 +53,15 @@ namespace {
 // per CU; the float64 instantiation needs more registers and runs 8 waves
 template <typename T> constexpr int PT = sizeof(T) == 4 ? 1024 : 512;
 constexpr int CT = 256;      // threads per workgroup of the cooperative form
+// threads of the instantiations that fuse dense sub-blocks: 8 waves, so a
+// wave may hold 256 registers (its pieces of a dense row, of the vector and
+// of the partial product, in float64 for the residual pass)
+template <typename T, int DMP> constexpr int PTK = DMP == 0 ? PT<T> : 512;
 // strides per pass of the cooperative form's per-instance vector loops (8
 // keeps float32 within 128 VGPRs; float64 stays at 4)
 template <typename T> constexpr int VLOOP = sizeof(T) == 4 ? 8 : 4;
+// 16-byte pieces of a dense row per lane for COSMO_DENSE_MAX_COLS columns
+template <typename T> constexpr int MAXPC = COSMO_DENSE_MAX_COLS / (64 * (16 / (int)sizeof(T)));
 constexpr int NRESTART = 4;          // restarts from a float64 residual, at most
 constexpr double ROUND_DROP2 = 1e-4;  // a restarted round lowers its residual by 1e-2 (squared here)
 constexpr double STALL2 = 0.25;       // a true residual that fell by less than 2x ends the refinement
@@ -246,22 +252,139 @@ __device__ inline void class_passes(const int32_t *rows, const RowSpan *span, co
   row_pass<64, AT>(rows, span, cls_off[2 * B1 + b0], cls_off[2 * B1 + b1], g, n, col, val, vin, active, emit);
 }
 
+// ---- dense sub-blocks inside one instance's workgroup ----------------------------
+//
+// Rows of A covered by a dense placement hold only their CSR part in t after
+// the row passes.  Per row r of each dense block G of instance b, one wave
+// forms d = G_r . vin, turns every placement's row i = row0_p + r of t into
+// rho_hat_i (t_i + scale_p d), and adds w_r G_r, w_r = sum_p scale_p t_i, to
+// its partial of G'w -- so G is read once per operator application.  The
+// waves' partials are added in wave order into ec (the column passes add
+// ec to the CSR part of A' t).  MP: 16-byte pieces of a row per lane.
+template <typename T> struct alignas(16) DPiece {
+  T v[16 / sizeof(T)];
+};
+
+template <int NTH, int MP, typename AT, typename T, typename TT>
+__device__ inline void dense_block_fused(const DenseDesc &d, const T *__restrict__ rho_hat, const T *__restrict__ vin,
+                                         TT *__restrict__ t, AT *__restrict__ lds, double *__restrict__ ec) {
+  constexpr int VE = 16 / sizeof(T);
+  constexpr int NW = NTH / 64;
+  constexpr int U = 2;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int npieces = (d.cols + VE - 1) / VE;
+  AT xv[MP][VE], acc[MP][VE];
+#pragma unroll
+  for (int q = 0; q < MP; ++q)
+#pragma unroll
+    for (int e = 0; e < VE; ++e) {
+      const int c = (lane + 64 * q) * VE + e;
+      xv[q][e] = c < d.cols ? (AT)vin[d.col0 + c] : (AT)0;
+      acc[q][e] = (AT)0;
+    }
+  const DPiece<T> *G = static_cast<const DPiece<T> *>(d.val);
+  const int64_t ldp = d.ld / VE;
+  for (int r0 = wave; r0 < d.rows; r0 += U * NW) {
+    DPiece<T> g[U][MP];
+    AT tp[U][COSMO_DENSE_MAX_PLACEMENTS], rp[U][COSMO_DENSE_MAX_PLACEMENTS];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = min(r0 + u * NW, d.rows - 1);   // clamped; surplus rows change nothing
+#pragma unroll
+      for (int q = 0; q < MP; ++q) {
+        const int pc = lane + 64 * q;
+        if (pc < npieces) g[u][q] = G[(int64_t)r * ldp + pc];
+      }
+#pragma unroll
+      for (int p = 0; p < COSMO_DENSE_MAX_PLACEMENTS; ++p)
+        if (p < d.nplace) {
+          tp[u][p] = (AT)t[d.row0[p] + r];
+          rp[u][p] = (AT)rho_hat[d.row0[p] + r];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = r0 + u * NW;
+      AT dot = 0;
+#pragma unroll
+      for (int q = 0; q < MP; ++q) {
+        const int pc = lane + 64 * q;
+        if (pc < npieces)
+#pragma unroll
+          for (int e = 0; e < VE; ++e) dot += (pc * VE + e < d.cols ? (AT)g[u][q].v[e] : (AT)0) * xv[q][e];
+      }
+      dot = sub_sum(dot, 64);
+      if (r < d.rows) {
+        AT w = 0;
+#pragma unroll
+        for (int p = 0; p < COSMO_DENSE_MAX_PLACEMENTS; ++p)
+          if (p < d.nplace) {
+            const AT sc = (AT)d.scale[p];
+            const AT ti = rp[u][p] * (tp[u][p] + sc * dot);
+            if (lane == 0) t[d.row0[p] + r] = (TT)ti;
+            w += sc * ti;
+          }
+#pragma unroll
+        for (int q = 0; q < MP; ++q) {
+          const int pc = lane + 64 * q;
+          if (pc < npieces)
+#pragma unroll
+            for (int e = 0; e < VE; ++e)
+              if (pc * VE + e < d.cols) acc[q][e] += w * (AT)g[u][q].v[e];
+        }
+      }
+    }
+  }
+  // partials of the waves, added in wave order
+#pragma unroll
+  for (int q = 0; q < MP; ++q)
+#pragma unroll
+    for (int e = 0; e < VE; ++e) {
+      const int c = (lane + 64 * q) * VE + e;
+      if (c < d.cols) lds[wave * d.cols + c] = acc[q][e];
+    }
+  __syncthreads();
+  for (int c = threadIdx.x; c < d.cols; c += NTH) {
+    AT sum = 0;
+    for (int w = 0; w < NW; ++w) sum += lds[w * d.cols + c];
+    ec[d.coff + c] = (double)sum;
+  }
+  __syncthreads();   // the partials are read before the next block overwrites them
+}
+
+// DMP: pieces per lane the kernel instantiation holds (the plan's widest
+// block fits in it).
+template <int NTH, int DMP, typename AT, typename T, typename TT>
+__device__ inline void dense_fused(const View<T> &v, int b, const T *rho_hat, const T *vin, TT *t) {
+  extern __shared__ double dyn_lds[];
+  AT *lds = reinterpret_cast<AT *>(dyn_lds);
+  for (int k = v.dense_inst[b]; k < v.dense_inst[b + 1]; ++k)
+    dense_block_fused<NTH, DMP, AT>(v.dense[k], rho_hat, vin, t, lds, v.ec);
+}
+
 // t = rho_hat o (A vin), then out = A' t + P vin + sigma vin, over the
 // instances [b0, b1), with sync() between and after the halves (workgroup
 // barrier in the per-instance form, grid barrier in the cooperative form).
-template <int NTH, bool GRID, typename T, typename RowAct, typename ColAct, typename Sync>
+template <int NTH, bool GRID, int DMP = 0, typename T, typename RowAct, typename ColAct, typename Sync>
 __device__ inline void op_apply(const View<T> &v, const T *__restrict__ rho_hat, const T *__restrict__ vin,
                                 T *__restrict__ t, T *__restrict__ out, int b0, int b1, RowAct row_act,
                                 ColAct col_act, Sync sync) {
   const int64_t B1 = v.B + 1;
   class_passes<NTH, GRID, T>(v.rowsA, v.spanA, v.instA, B1, b0, b1, v.A_col, v.A_val, vin, row_act,
-                             [&](int32_t i, T acc) { t[i] = rho_hat[i] * acc; });
+                             [&](int32_t i, T acc) { t[i] = (v.drow && v.drow[i] >= 0) ? acc : rho_hat[i] * acc; });
   sync();
+  if constexpr (!GRID && DMP > 0) {
+    if (v.dense) {
+      dense_fused<NTH, DMP, T>(v, b0, rho_hat, vin, t);
+      sync();
+    }
+  }
   class_passes<NTH, GRID, T>(v.rowsAt, v.spanAt, v.instAt, B1, b0, b1, v.At_col, v.At_val, t, col_act,
                              [&](int32_t j, T acc) {
                                if (v.P_rowptr)
                                  for (int64_t k = v.P_rowptr[j]; k < v.P_rowptr[j + 1]; ++k)
                                    acc += v.P_val[k] * vin[v.P_col[k]];
+                               if (v.dcol && v.dcol[j] >= 0) acc += (T)v.ec[v.dcol[j]];
                                out[j] = acc + v.sigma * vin[j];
                              });
   sync();
@@ -269,19 +392,28 @@ __device__ inline void op_apply(const View<T> &v, const T *__restrict__ rho_hat,
 
 // r = rhs - M x with float64 accumulation (t64 holds rho_hat o (A x) in
 // float64); r is stored in the working precision.
-template <int NTH, bool GRID, typename T, typename RowAct, typename ColAct, typename Sync>
+template <int NTH, bool GRID, int DMP = 0, typename T, typename RowAct, typename ColAct, typename Sync>
 __device__ inline void op_residual64(const View<T> &v, const T *__restrict__ rho_hat, const double *__restrict__ rhs,
                                      const T *__restrict__ x, double *__restrict__ t64, T *__restrict__ r, int b0,
                                      int b1, RowAct row_act, ColAct col_act, Sync sync) {
   const int64_t B1 = v.B + 1;
   class_passes<NTH, GRID, double>(v.rowsA, v.spanA, v.instA, B1, b0, b1, v.A_col, v.A_val, x, row_act,
-                                  [&](int32_t i, double acc) { t64[i] = (double)rho_hat[i] * acc; });
+                                  [&](int32_t i, double acc) {
+                                    t64[i] = (v.drow && v.drow[i] >= 0) ? acc : (double)rho_hat[i] * acc;
+                                  });
   sync();
+  if constexpr (!GRID && DMP > 0) {
+    if (v.dense) {
+      dense_fused<NTH, DMP, double>(v, b0, rho_hat, x, t64);
+      sync();
+    }
+  }
   class_passes<NTH, GRID, double>(v.rowsAt, v.spanAt, v.instAt, B1, b0, b1, v.At_col, v.At_val, t64, col_act,
                                   [&](int32_t j, double acc) {
                                     if (v.P_rowptr)
                                       for (int64_t k = v.P_rowptr[j]; k < v.P_rowptr[j + 1]; ++k)
                                         acc += (double)v.P_val[k] * (double)x[v.P_col[k]];
+                                    if (v.dcol && v.dcol[j] >= 0) acc += v.ec[v.dcol[j]];
                                     r[j] = (T)(rhs[j] - acc - (double)v.sigma * (double)x[j]);
                                   });
   sync();
@@ -312,35 +444,35 @@ __device__ inline void finish(const View<T> &v, int b, bool fail, int it, int pa
 
 // ---- per-instance form -------------------------------------------------------------
 
-template <typename T>
-__global__ __launch_bounds__(PT<T>) void k_pcg(View<T> v, const T *__restrict__ rho_hat, const T *__restrict__ dg,
+template <typename T, int DMP>
+__global__ __launch_bounds__((PTK<T, DMP>)) void k_pcg(View<T> v, const T *__restrict__ rho_hat, const T *__restrict__ dg,
                                             const double *__restrict__ rhs, T *__restrict__ x, T *__restrict__ r,
                                             T *__restrict__ z, T *__restrict__ p, T *__restrict__ Mp,
                                             T *__restrict__ t, double *__restrict__ t64, T tol, int32_t max_iter,
                                             const T *__restrict__ alpha_k, const T *__restrict__ xold,
                                             T *__restrict__ xnew, const T *__restrict__ gx_in,
                                             T *__restrict__ gx_out, int32_t mode, cosmo_stats *stats) {
-  __shared__ T red[2 * (PT<T> / 64)];
-  __shared__ double redd[2 * (PT<T> / 64)];
+  __shared__ T red[2 * (PTK<T, DMP> / 64)];
+  __shared__ double redd[2 * (PTK<T, DMP> / 64)];
   const int b = blockIdx.x;
   const int64_t n0 = v.n_off[b], n1 = v.n_off[b + 1];
   auto all = [](int32_t) { return true; };
   auto bar = []() { __syncthreads(); };
 
   double bb = 0, dd = 0;
-  for (int64_t j = n0 + threadIdx.x; j < n1; j += PT<T>) bb += rhs[j] * rhs[j];
-  wg_sum2<PT<T>>(bb, dd, redd);
+  for (int64_t j = n0 + threadIdx.x; j < n1; j += PTK<T, DMP>) bb += rhs[j] * rhs[j];
+  wg_sum2<PTK<T, DMP>>(bb, dd, redd);
   const double thr = (double)tol * (double)tol * bb;
   bool fail = !isfinite(bb);
   int it = 0, passes = 0;
   double rrt = 0, rrt_prev = 0;
   for (int restart = 0;; ++restart) {
     // true residual, z = r / diag M, p = z
-    op_residual64<PT<T>, false>(v, rho_hat, rhs, x, t64, r, b, b + 1, all, all, bar);
+    op_residual64<PTK<T, DMP>, false, DMP>(v, rho_hat, rhs, x, t64, r, b, b + 1, all, all, bar);
     ++passes;
     T rz = 0, rr = 0;
     rrt = 0;
-    for (int64_t j = n0 + threadIdx.x; j < n1; j += PT<T>) {
+    for (int64_t j = n0 + threadIdx.x; j < n1; j += PTK<T, DMP>) {
       const T rj = r[j];
       const T zj = rj / dg[j];
       z[j] = zj;
@@ -349,8 +481,8 @@ __global__ __launch_bounds__(PT<T>) void k_pcg(View<T> v, const T *__restrict__ 
       rr += rj * rj;
       rrt += (double)rj * (double)rj;
     }
-    wg_sum2<PT<T>>(rz, rr, red);
-    wg_sum2<PT<T>>(rrt, dd, redd);
+    wg_sum2<PTK<T, DMP>>(rz, rr, red);
+    wg_sum2<PTK<T, DMP>>(rrt, dd, redd);
     fail = fail || !isfinite(rrt);
     const bool stalled = restart > 0 && rrt > STALL2 * rrt_prev;
     if (fail || rrt <= thr || it >= max_iter || restart > NRESTART || stalled) break;
@@ -359,17 +491,17 @@ __global__ __launch_bounds__(PT<T>) void k_pcg(View<T> v, const T *__restrict__ 
     // CG on the recursive residual
     while (rr > target && it < max_iter) {
       __syncthreads();   // p complete before the operator reads it
-      op_apply<PT<T>, false>(v, rho_hat, p, t, Mp, b, b + 1, all, all, bar);
+      op_apply<PTK<T, DMP>, false, DMP>(v, rho_hat, p, t, Mp, b, b + 1, all, all, bar);
       T pMp = 0, dummy = 0;
-      for (int64_t j = n0 + threadIdx.x; j < n1; j += PT<T>) pMp += p[j] * Mp[j];
-      wg_sum2<PT<T>>(pMp, dummy, red);
+      for (int64_t j = n0 + threadIdx.x; j < n1; j += PTK<T, DMP>) pMp += p[j] * Mp[j];
+      wg_sum2<PTK<T, DMP>>(pMp, dummy, red);
       if (!(pMp > (T)0)) {   // breakdown: restart from the true residual (or fail if non-finite)
         fail = !isfinite(pMp);
         break;
       }
       const T a = rz / pMp;
       T rz_new = 0, rr_new = 0;
-      for (int64_t j = n0 + threadIdx.x; j < n1; j += PT<T>) {
+      for (int64_t j = n0 + threadIdx.x; j < n1; j += PTK<T, DMP>) {
         x[j] += a * p[j];
         const T rj = r[j] - a * Mp[j];
         const T zj = rj / dg[j];
@@ -378,11 +510,11 @@ __global__ __launch_bounds__(PT<T>) void k_pcg(View<T> v, const T *__restrict__ 
         rz_new += rj * zj;
         rr_new += rj * rj;
       }
-      wg_sum2<PT<T>>(rz_new, rr_new, red);
+      wg_sum2<PTK<T, DMP>>(rz_new, rr_new, red);
       const T beta = rz_new / rz;
       rz = rz_new;
       rr = rr_new;
-      for (int64_t j = n0 + threadIdx.x; j < n1; j += PT<T>) p[j] = z[j] + beta * p[j];
+      for (int64_t j = n0 + threadIdx.x; j < n1; j += PTK<T, DMP>) p[j] = z[j] + beta * p[j];
       ++it;
       if (!isfinite(rr)) {
         fail = true;
@@ -393,7 +525,7 @@ __global__ __launch_bounds__(PT<T>) void k_pcg(View<T> v, const T *__restrict__ 
     __syncthreads();   // x complete before the residual reads it
   }
   __syncthreads();
-  finish<PT<T>>(v, b, fail, it, passes, rrt, thr, x, alpha_k, xold, xnew, gx_in, gx_out, mode, stats);
+  finish<PTK<T, DMP>>(v, b, fail, it, passes, rrt, thr, x, alpha_k, xold, xnew, gx_in, gx_out, mode, stats);
 }
 
 // ---- cooperative form ------------------------------------------------------------
@@ -716,7 +848,7 @@ void launch_pcg(const View<T> &v, const T *rho_hat, const T *dg, const double *r
   // form 0: one workgroup per instance; form f > 0: the cooperative form
   // with at most f workgroups per compute unit (the runtime refuses a grid
   // that would not be resident at once; the per-instance form then runs)
-  const int grid = (form > 0 && state) ? pcg_coop_grid<T>(form) : 0;
+  const int grid = (form > 0 && state && v.n_dense == 0) ? pcg_coop_grid<T>(form) : 0;
   if (grid > 0) {
     View<T> va = v;
     T tl = (T)tol;
@@ -729,8 +861,32 @@ void launch_pcg(const View<T> &v, const T *rho_hat, const T *dg, const double *r
       return;
     (void)hipGetLastError();
   }
-  k_pcg<T><<<v.B, PT<T>, 0, st>>>(v, rho_hat, dg, rhs, x, r, z, p, Mp, t, t64, (T)tol, max_iter, alpha_k, xold, xnew,
-                               gx_in, gx_out, mode, stats);
+  if (v.n_dense <= 0) {
+    k_pcg<T, 0><<<v.B, PT<T>, 0, st>>>(v, rho_hat, dg, rhs, x, r, z, p, Mp, t, t64, (T)tol, max_iter, alpha_k, xold,
+                                       xnew, gx_in, gx_out, mode, stats);
+    return;
+  }
+  // dense sub-blocks: the instantiation holding the widest block's pieces, and
+  // LDS for the waves' partials of G'w (float64 in the residual pass)
+  constexpr int VE = 16 / sizeof(T);
+  const int pieces = (v.dense_maxcols + 64 * VE - 1) / (64 * VE);
+  const size_t lds = (size_t)(512 / 64) * v.dense_maxcols * sizeof(double);
+  auto go = [&](auto kern) {
+    static bool attr_set = false;   // more than the default 64 KiB of dynamic LDS may be needed
+    if (!attr_set) {
+      hipFuncAttributes a{};
+      size_t stat = 4096;
+      if (hipFuncGetAttributes(&a, reinterpret_cast<const void *>(kern)) == hipSuccess) stat = a.sharedSizeBytes;
+      (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(163840 - stat));
+      attr_set = true;
+    }
+    kern<<<v.B, 512, lds, st>>>(v, rho_hat, dg, rhs, x, r, z, p, Mp, t, t64, (T)tol, max_iter, alpha_k, xold, xnew,
+                                  gx_in, gx_out, mode, stats);
+  };
+  if (pieces <= MAXPC<T> / 4) go(&k_pcg<T, MAXPC<T> / 4>);
+  else if (pieces <= MAXPC<T> / 2) go(&k_pcg<T, MAXPC<T> / 2>);
+  else go(&k_pcg<T, MAXPC<T>>);
 }
 
 template void launch_pcg<float>(const View<float> &, const float *, const float *, const double *, float *, float *,

@@ -812,7 +812,8 @@ __global__ __launch_bounds__(NT) void k_psd_vjp(const PsdDesc *__restrict__ desc
   const int p = d.p, pp = p * p, lp = dk_ld(p), ppl = p * lp;
   const int tid = threadIdx.x;
   T *B0 = lds;
-  const int l0 = lp;
+  // B0 keeps the padded stride when it fits, else p (the largest orders)
+  const int l0 = ppl <= lds_elems ? lp : p;
   const bool b1_lds = 2 * ppl <= lds_elems;
   T *B1 = b1_lds ? lds + ppl : scratch + d.uoff;
   const int l1 = b1_lds ? lp : p;
@@ -915,12 +916,14 @@ __global__ __launch_bounds__(NT) void k_psd_vjp(const PsdDesc *__restrict__ desc
 
 constexpr size_t LDS_LIMIT = 163840;
 
-// Allow a kernel the whole LDS of a workgroup minus its static allocation.
-void set_dyn_lds_cap(const void *fn) {
+// Allow a kernel the whole LDS of a workgroup minus its static allocation;
+// returns the dynamic LDS bytes it may use.
+size_t set_dyn_lds_cap(const void *fn) {
   hipFuncAttributes a{};
   size_t stat = 4096;
   if (hipFuncGetAttributes(&a, fn) == hipSuccess) stat = a.sharedSizeBytes;
   (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(LDS_LIMIT - stat));
+  return LDS_LIMIT - stat;
 }
 
 template <typename T, int NT, int G, int PMAX>
@@ -971,20 +974,25 @@ void launch_psd_step(const PsdDesc *d, int32_t n, const PsdLaunchCfg &cfg, const
 constexpr int VJP_NT = 1024;
 
 template <typename T>
-void launch_psd_vjp(const PsdDesc *d, int32_t n, int32_t max_p, const T *U, const T *lam, const T *g, T *out,
+bool launch_psd_vjp(const PsdDesc *d, int32_t n, int32_t max_p, const T *U, const T *lam, const T *g, T *out,
                     T *scratch, hipStream_t st, int32_t rule, double eps) {
-  if (n <= 0) return;
-  const size_t pp = (size_t)max_p * dk_ld(max_p);   // p dk_ld(p) does not decrease with p
-  const size_t budget = (LDS_LIMIT - 4096) / sizeof(T);
-  size_t elems = pp;
-  if (3 * pp <= budget) elems = 3 * pp;
-  else if (2 * pp <= budget) elems = 2 * pp;
-  static bool attr_set = false;
-  if (!attr_set) {
-    set_dyn_lds_cap(reinterpret_cast<const void *>(&k_psd_vjp<T, VJP_NT>));
-    attr_set = true;
-  }
+  if (n <= 0) return true;
+  static size_t dyn_bytes = 0;
+  if (dyn_bytes == 0) dyn_bytes = set_dyn_lds_cap(reinterpret_cast<const void *>(&k_psd_vjp<T, VJP_NT>));
+  // LDS holds B0 (and B1, then U) at the padded stride while they fit; the
+  // largest orders keep only B0, unpadded (order 200 in float32: 160,000
+  // bytes), with B1 in the global scratch.
+  const size_t ppl = (size_t)max_p * dk_ld(max_p);   // p dk_ld(p) does not decrease with p
+  const size_t pp = (size_t)max_p * max_p;
+  const size_t budget = dyn_bytes / sizeof(T);
+  size_t elems;
+  if (3 * ppl <= budget) elems = 3 * ppl;
+  else if (2 * ppl <= budget) elems = 2 * ppl;
+  else if (ppl <= budget) elems = ppl;
+  else if (pp <= budget) elems = pp;   // every order the validation admits fits here
+  else return false;
   k_psd_vjp<T, VJP_NT><<<n, VJP_NT, elems * sizeof(T), st>>>(d, U, lam, g, out, scratch, (int32_t)elems, rule, (T)eps);
+  return true;
 }
 
 template void launch_psd_step<float>(const PsdDesc *, int32_t, const PsdLaunchCfg &, const float *, const float *,
@@ -993,8 +1001,8 @@ template void launch_psd_step<float>(const PsdDesc *, int32_t, const PsdLaunchCf
 template void launch_psd_step<double>(const PsdDesc *, int32_t, const PsdLaunchCfg &, const double *,
                                       const double *, const double *, const double *, double *, double *, double *,
                                       double *, double *, const double *, cosmo_stats *, hipStream_t);
-template void launch_psd_vjp<float>(const PsdDesc *, int32_t, int32_t, const float *, const float *, const float *,
+template bool launch_psd_vjp<float>(const PsdDesc *, int32_t, int32_t, const float *, const float *, const float *,
                                     float *, float *, hipStream_t, int32_t, double);
-template void launch_psd_vjp<double>(const PsdDesc *, int32_t, int32_t, const double *, const double *,
+template bool launch_psd_vjp<double>(const PsdDesc *, int32_t, int32_t, const double *, const double *,
                                      const double *, double *, double *, hipStream_t, int32_t, double);
 }  // namespace cosmo

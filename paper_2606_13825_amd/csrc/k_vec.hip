@@ -30,6 +30,25 @@ template <typename T> __device__ inline double v_of(T al, T stl, T s, T y, T r) 
   return shat_of(al, stl, s) + (double)y / (double)r;
 }
 
+// Contributions of the dense sub-blocks of A (computed beforehand by the
+// dense product kernels into the call's float64 scratch): row i's entry of
+// the row product (times its placement's scale) and column j's entries of
+// the column products.
+template <typename T> __device__ inline double dense_row_term(const View<T> &v, int64_t i) {
+  if (!v.drow) return 0.0;
+  const int32_t r = v.drow[i];
+  return r >= 0 ? v.dscale[i] * v.dn[r] : 0.0;
+}
+template <typename T> __device__ inline void dense_col_terms(const View<T> &v, int64_t j, double &e, double &d) {
+  e = d = 0.0;
+  if (!v.dcol) return;
+  const int32_t c = v.dcol[j];
+  if (c >= 0) {
+    e = v.ec[c];
+    if (v.ed) d = v.ed[c];
+  }
+}
+
 // Position of this thread inside the bucketed row list: returns false when
 // the sub-wave has no row.  All lanes of a sub-wave agree.
 struct BucketPos {
@@ -143,6 +162,10 @@ __global__ __launch_bounds__(NT) void k_cols_pre(View<T> v, BucketArgs ba, const
   a_xi = subwave_sum(a_xi, bp.L);
   a_d = subwave_sum(a_d, bp.L);
   if (bp.lane == 0) {
+    double e_xi, e_d;
+    dense_col_terms(v, j, e_xi, e_d);
+    a_xi += e_xi;
+    a_d += e_d;
     const T d = (T)((double)v.Pdiag[j] + (double)v.sigma + a_d);
     const double r = (double)v.sigma * (double)x[j] - (double)v.q[j] + a_xi;
     dg[j] = d;
@@ -173,6 +196,7 @@ __global__ __launch_bounds__(NT) void k_rows_post(View<T> v, BucketArgs ba, cons
     ax += (double)v.A_val[k] * (double)xt[v.A_col[k]];
   ax = subwave_sum(ax, bp.L);
   if (bp.lane != 0) return;
+  ax += dense_row_term(v, i);
   const T al = alpha_k[v.row_inst[i]];
   const T r = rho_hat[i];
   const T stl = (T)((double)v.b[i] - ax);   // stored; s^ and v below use the stored value
@@ -272,6 +296,10 @@ __global__ __launch_bounds__(NT) void k_bwd_cols(View<T> v, BucketArgs ba, const
   acc = subwave_sum(acc, bp.L);
   a_d = subwave_sum(a_d, bp.L);
   if (bp.lane == 0) {
+    double e_g, e_d;
+    dense_col_terms(v, j, e_g, e_d);
+    acc += e_g;
+    a_d += e_d;
     const T al = alpha_k[v.col_inst[j]];
     const double r = (double)al * (double)gx_in[j] - acc;
     const T d = (T)((double)v.Pdiag[j] + (double)v.sigma + a_d);
@@ -300,6 +328,7 @@ __global__ __launch_bounds__(NT) void k_bwd_rows_c(View<T> v, BucketArgs ba, con
     g += (double)v.A_val[k] * (double)w[v.A_col[k]];
   g = subwave_sum(g, bp.L);
   if (bp.lane != 0) return;
+  g += dense_row_term(v, i);
   grh[i] = (T)((double)grh[i] + g * ((double)stl[i] - (double)s[i]));
   gy_out[i] = (T)((double)gy_out[i] + g);
   gs_out[i] = (T)((double)gs_out[i] - (double)rho_hat[i] * g);
@@ -355,7 +384,7 @@ __global__ __launch_bounds__(NT) void k_loss_rp(View<T> v, BucketArgs ba, const 
   for (int64_t k = v.A_rowptr[i] + bp.lane; k < v.A_rowptr[i + 1]; k += bp.L)
     ax += (double)v.A_val[k] * (double)x[v.A_col[k]];
   ax = subwave_sum(ax, bp.L);
-  if (bp.lane == 0) rp[i] = (T)(ax + (double)s[i] - (double)v.b[i]);
+  if (bp.lane == 0) rp[i] = (T)(ax + dense_row_term(v, i) + (double)s[i] - (double)v.b[i]);
 }
 
 // rd_j = (P x)_j + q_j - (A' y)_j
@@ -371,7 +400,11 @@ __global__ __launch_bounds__(NT) void k_loss_rd(View<T> v, BucketArgs ba, const 
     for (int64_t k = v.P_rowptr[j] + bp.lane; k < v.P_rowptr[j + 1]; k += bp.L)
       acc += (double)v.P_val[k] * (double)x[v.P_col[k]];
   acc = subwave_sum(acc, bp.L);
-  if (bp.lane == 0) rd[j] = (T)(acc + (double)v.q[j]);
+  if (bp.lane == 0) {
+    double e, d;
+    dense_col_terms(v, j, e, d);
+    rd[j] = (T)(acc - e + (double)v.q[j]);
+  }
 }
 
 template <typename T>
@@ -397,7 +430,11 @@ __global__ __launch_bounds__(NT) void k_loss_gx(View<T> v, BucketArgs ba, const 
   if (v.P_rowptr)
     for (int64_t k = v.P_rowptr[j] + bp.lane; k < v.P_rowptr[j + 1]; k += bp.L) acc += v.P_val[k] * rd[v.P_col[k]];
   acc = subwave_sum(acc, bp.L);
-  if (bp.lane == 0) gx[j] = (T)2 * acc;
+  if (bp.lane == 0) {
+    double e, d;
+    dense_col_terms(v, j, e, d);
+    gx[j] = (T)2 * (acc + (T)e);
+  }
 }
 
 // gs_i = 2 rp_i ; gy_i = -2 (A rd)_i
@@ -411,6 +448,7 @@ __global__ __launch_bounds__(NT) void k_loss_gsy(View<T> v, BucketArgs ba, const
   for (int64_t k = v.A_rowptr[i] + bp.lane; k < v.A_rowptr[i + 1]; k += bp.L) acc += v.A_val[k] * rd[v.A_col[k]];
   acc = subwave_sum(acc, bp.L);
   if (bp.lane == 0) {
+    acc += (T)dense_row_term(v, i);
     if (gs) gs[i] = (T)2 * rp[i];
     if (gy) gy[i] = (T)-2 * acc;
   }
@@ -523,10 +561,15 @@ template <typename T>
 void launch_loss(const View<T> &v, const RowBuckets &bkA, const RowBuckets &bkAt, const T *x, const T *s, const T *y,
                  T *rp, T *rd, T *loss, T *gx, T *gs, T *gy, hipStream_t st) {
   BucketArgs a = make_bucket_args(bkA), at = make_bucket_args(bkAt);
+  // each dense product feeds the kernel right after it (the scratch is reused)
+  launch_dense_rows<T>(v, x, st);
   if (nblocks_bucket(a) > 0) k_loss_rp<T><<<(int)nblocks_bucket(a), NT, 0, st>>>(v, a, x, s, rp);
+  launch_dense_cols<T>(v, DC_Y, nullptr, y, nullptr, st);
   if (nblocks_bucket(at) > 0) k_loss_rd<T><<<(int)nblocks_bucket(at), NT, 0, st>>>(v, at, x, y, rd);
   k_loss_reduce<T><<<v.B, NT, 0, st>>>(v, rp, rd, loss);
+  if (gx) launch_dense_cols<T>(v, DC_RP, nullptr, rp, nullptr, st);
   if (gx && nblocks_bucket(at) > 0) k_loss_gx<T><<<(int)nblocks_bucket(at), NT, 0, st>>>(v, at, rp, rd, gx);
+  if (gs || gy) launch_dense_rows<T>(v, rd, st);
   if ((gs || gy) && nblocks_bucket(a) > 0) k_loss_gsy<T><<<(int)nblocks_bucket(a), NT, 0, st>>>(v, a, rp, rd, gs, gy);
 }
 

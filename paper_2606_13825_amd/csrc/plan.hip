@@ -24,7 +24,7 @@ using namespace cosmo;
 
 namespace {
 
-constexpr int32_t ABI_VERSION = 1;
+constexpr int32_t ABI_VERSION = 2;
 
 #define FAIL(code, msg)            \
   do {                             \
@@ -97,19 +97,25 @@ struct cosmo_plan {
   int32_t n_rect = 0;
   RowBuckets bkA, bkAt;
   int64_t sum_p = 0, sum_p2 = 0, sum_p2_large = 0;
+  // dense sub-blocks of A (descriptors ordered by instance)
+  int32_t n_dense = 0, dense_maxcols = 0, dense_wg_rows = 0, dense_wg_cols = 0;
+  int64_t dense_rows_tot = 0, dense_cols_tot = 0;
+  DenseDesc *d_dense = nullptr;
+  int32_t *d_dense_inst = nullptr, *d_drow = nullptr, *d_dcol = nullptr;
+  double *d_dscale = nullptr;
   // M = P + sigma I + A' D A is diagonal when every row of A has at most one
   // nonzero and P is diagonal; the linear solves are then done in the
   // column kernels (x~ = xi / diag M) and the PCG kernel is not launched.
   bool diag_M = false;
   // layouts (element offsets of T)
   struct {
-    size_t rho_hat, dg, xi, r, z, p, Mp, t, t64, cg, sh, vv, itA, itB, xt, st, U, lam, rp, rd, rs, total;
+    size_t rho_hat, dg, xi, r, z, p, Mp, t, t64, cg, sh, vv, itA, itB, xt, st, U, lam, rp, rd, rs, dn, ec, ed, total;
   } fw{};
   struct {
     size_t slot, step, xt, st, lam, U, total;  // per-slot / per-step sizes and offsets inside a step
   } tp{};
   struct {
-    size_t rho_hat, gA, gB, gsn, gv, gsh, gst, grh, gxt, w, dg, r, z, p, Mp, t, t64, cg, vv, dk, zero, total;
+    size_t rho_hat, gA, gB, gsn, gv, gsh, gst, grh, gxt, w, dg, r, z, p, Mp, t, t64, cg, vv, dk, dn, ec, ed, zero, total;
   } bw{};
   bool profiling = false;
   ProfileSlot prof[8];   // kinds of cosmo_plan_profile_read
@@ -181,7 +187,25 @@ template <typename T> View<T> make_view(const cosmo_plan *pl) {
   v.n_tot = pl->n_tot;
   v.m_tot = pl->m_tot;
   v.sigma = (T)pl->opt.sigma;
+  v.dense = pl->n_dense > 0 ? pl->d_dense : nullptr;
+  v.dense_inst = pl->d_dense_inst;
+  v.drow = pl->n_dense > 0 ? pl->d_drow : nullptr;
+  v.dscale = pl->d_dscale;
+  v.dcol = pl->n_dense > 0 ? pl->d_dcol : nullptr;
+  v.n_dense = pl->n_dense;
+  v.dense_maxcols = pl->dense_maxcols;
+  v.dense_wg_rows = pl->dense_wg_rows;
+  v.dense_wg_cols = pl->dense_wg_cols;
+  v.dn = v.ec = v.ed = nullptr;   // set per call from the call's workspace
   return v;
+}
+
+// The dense scratch vectors of a call's workspace (float64, at element
+// offsets of T).
+template <typename T> void bind_dense(View<T> &v, T *ws, size_t dn, size_t ec, size_t ed) {
+  v.dn = reinterpret_cast<double *>(ws + dn);
+  v.ec = reinterpret_cast<double *>(ws + ec);
+  v.ed = reinterpret_cast<double *>(ws + ed);
 }
 
 // Profiling: events around launches of one kernel family.
@@ -258,6 +282,45 @@ cosmo_status validate_problem_host(const cosmo_problem *p, const cosmo_options *
     row += rows;
   }
   if (row != m_tot) FAIL(COSMO_EINVAL, "cone rows sum to " + std::to_string(row) + " but m_tot is " + std::to_string(m_tot));
+  // dense sub-blocks
+  if (p->n_dense < 0) FAIL(COSMO_EINVAL, "n_dense < 0");
+  if (p->n_dense > 0 && !p->dense) FAIL(COSMO_EINVAL, "dense descriptors are NULL");
+  const size_t esz = o->dtype == COSMO_F32 ? 4 : 8;
+  std::vector<std::pair<int64_t, int64_t>> rspans, cspans;
+  auto inst_of = [&](const int64_t *off, int64_t idx) {
+    return (int)(std::upper_bound(off, off + p->B + 1, idx) - off) - 1;
+  };
+  for (int k = 0; k < p->n_dense; ++k) {
+    const cosmo_dense_block &d = p->dense[k];
+    const std::string at = " (dense block " + std::to_string(k) + ")";
+    if (!d.val) FAIL(COSMO_EINVAL, "dense values are NULL" + at);
+    if (reinterpret_cast<uintptr_t>(d.val) % 16 != 0) FAIL(COSMO_EINVAL, "dense values must be 16-byte aligned" + at);
+    if (d.rows < 1 || d.cols < 1) FAIL(COSMO_EINVAL, "dense block needs rows, cols >= 1" + at);
+    if (d.cols > COSMO_DENSE_MAX_COLS) FAIL(COSMO_EINVAL, "dense block wider than COSMO_DENSE_MAX_COLS" + at);
+    if (d.ld < d.cols || d.ld % (int64_t)(16 / esz) != 0)
+      FAIL(COSMO_EINVAL, "dense ld must be >= cols and a multiple of 16 / sizeof(dtype)" + at);
+    if (d.n_place < 1 || d.n_place > COSMO_DENSE_MAX_PLACEMENTS) FAIL(COSMO_EINVAL, "dense n_place out of range" + at);
+    if (d.reserved != 0) FAIL(COSMO_EINVAL, "dense reserved field must be 0" + at);
+    if (d.col0 < 0 || d.col0 + d.cols > n_tot) FAIL(COSMO_EINVAL, "dense columns outside A" + at);
+    const int ci = inst_of(p->n_off, d.col0);
+    if (d.col0 + d.cols > p->n_off[ci + 1]) FAIL(COSMO_EINVAL, "dense columns straddle instances" + at);
+    cspans.push_back({d.col0, d.col0 + d.cols});
+    for (int q = 0; q < d.n_place; ++q) {
+      if (!std::isfinite(d.scale[q])) FAIL(COSMO_EINVAL, "dense scale must be finite" + at);
+      if (d.row0[q] < 0 || d.row0[q] + d.rows > m_tot) FAIL(COSMO_EINVAL, "dense rows outside A" + at);
+      const int ri = inst_of(p->m_off, d.row0[q]);
+      if (d.row0[q] + d.rows > p->m_off[ri + 1] || ri != ci)
+        FAIL(COSMO_EINVAL, "dense rows and columns must lie in one instance" + at);
+      rspans.push_back({d.row0[q], d.row0[q] + d.rows});
+    }
+  }
+  for (auto *sp : {&rspans, &cspans}) {
+    std::sort(sp->begin(), sp->end());
+    for (size_t i = 1; i < sp->size(); ++i)
+      if ((*sp)[i].first < (*sp)[i - 1].second)
+        FAIL(COSMO_EINVAL, sp == &rspans ? "a row of A lies in two dense placements"
+                                         : "a column of A lies in two dense blocks");
+  }
   return COSMO_OK;
 }
 
@@ -399,7 +462,61 @@ cosmo_status build_plan(cosmo_plan *pl, const cosmo_problem *p) {
       for (int64_t j = 0; j < n && dm; ++j)
         for (int64_t k = prp[j]; k < prp[j + 1] && dm; ++k) dm = (pc[k] == j);
     }
-    pl->diag_M = dm;
+    pl->diag_M = dm && p->n_dense == 0;
+  }
+  // dense sub-blocks: descriptors ordered by instance, their scratch offsets
+  // and launch layouts, and the per-row / per-column maps
+  std::vector<DenseDesc> dens;
+  std::vector<int32_t> dinst(pl->B + 1, 0), drow, dcolm;
+  std::vector<double> dscale;
+  if (p->n_dense > 0) {
+    drow.assign(m, -1);
+    dscale.assign(m, 0.0);
+    dcolm.assign(n, -1);
+    for (int k = 0; k < p->n_dense; ++k) {
+      const cosmo_dense_block &b = p->dense[k];
+      DenseDesc d{};
+      d.val = b.val;
+      d.ld = b.ld;
+      d.col0 = b.col0;
+      d.rows = b.rows;
+      d.cols = b.cols;
+      d.nplace = b.n_place;
+      d.inst = cinst[b.col0];
+      for (int q = 0; q < COSMO_DENSE_MAX_PLACEMENTS; ++q) {
+        d.row0[q] = q < b.n_place ? b.row0[q] : 0;
+        d.scale[q] = q < b.n_place ? b.scale[q] : 0.0;
+      }
+      dens.push_back(d);
+    }
+    std::stable_sort(dens.begin(), dens.end(), [](const DenseDesc &a, const DenseDesc &b) { return a.inst < b.inst; });
+    int64_t doff = 0, coff = 0;
+    int32_t wr = 0, wc = 0;
+    for (size_t k = 0; k < dens.size(); ++k) {
+      DenseDesc &d = dens[k];
+      d.doff = doff;
+      d.coff = coff;
+      d.wg_rows0 = wr;
+      d.wg_cols0 = wc;
+      for (int q = 0; q < d.nplace; ++q)
+        for (int r = 0; r < d.rows; ++r) {
+          drow[d.row0[q] + r] = (int32_t)(doff + r);
+          dscale[d.row0[q] + r] = d.scale[q];
+        }
+      for (int c = 0; c < d.cols; ++c) dcolm[d.col0 + c] = (int32_t)(coff + c);
+      doff += d.rows;
+      coff += d.cols;
+      wr += dense_row_workgroups(d.rows);
+      wc += dense_col_workgroups(d.cols, sizeof(T));
+      pl->dense_maxcols = std::max(pl->dense_maxcols, d.cols);
+      dinst[d.inst + 1]++;
+    }
+    for (int b = 0; b < pl->B; ++b) dinst[b + 1] += dinst[b];
+    pl->n_dense = (int32_t)dens.size();
+    pl->dense_rows_tot = doff;
+    pl->dense_cols_tot = coff;
+    pl->dense_wg_rows = wr;
+    pl->dense_wg_cols = wc;
   }
   pl->n_soc = (int32_t)socs.size();
   pl->n_psd = (int32_t)psds.size();
@@ -446,6 +563,11 @@ cosmo_status build_plan(cosmo_plan *pl, const cosmo_problem *p) {
   const std::vector<RowSpan> spA = spans(rowsA, rp), spAt = spans(rowsAt, trp);
   const size_t o_sA = take(std::max<size_t>(spA.size(), 1) * sizeof(RowSpan));
   const size_t o_sAt = take(std::max<size_t>(spAt.size(), 1) * sizeof(RowSpan));
+  const size_t o_dense = take(std::max<size_t>(dens.size(), 1) * sizeof(DenseDesc));
+  const size_t o_dinst = take(dinst.size() * sizeof(int32_t));
+  const size_t o_drow = take(std::max<size_t>(drow.size(), 1) * sizeof(int32_t));
+  const size_t o_dscale = take(std::max<size_t>(dscale.size(), 1) * sizeof(double));
+  const size_t o_dcol = take(std::max<size_t>(dcolm.size(), 1) * sizeof(int32_t));
   if (hipMalloc(&pl->mem.ptr, off) != hipSuccess) {
     pl->mem.ptr = nullptr;
     FAIL(COSMO_ENOMEM, "plan allocation of " + std::to_string(off) + " bytes failed");
@@ -473,6 +595,11 @@ cosmo_status build_plan(cosmo_plan *pl, const cosmo_problem *p) {
   HIPCHK(up(o_bAt, rowsAt.data(), rowsAt.size() * sizeof(int32_t)));
   HIPCHK(up(o_sA, spA.data(), spA.size() * sizeof(RowSpan)));
   HIPCHK(up(o_sAt, spAt.data(), spAt.size() * sizeof(RowSpan)));
+  HIPCHK(up(o_dense, dens.data(), dens.size() * sizeof(DenseDesc)));
+  HIPCHK(up(o_dinst, dinst.data(), dinst.size() * sizeof(int32_t)));
+  HIPCHK(up(o_drow, drow.data(), drow.size() * sizeof(int32_t)));
+  HIPCHK(up(o_dscale, dscale.data(), dscale.size() * sizeof(double)));
+  HIPCHK(up(o_dcol, dcolm.data(), dcolm.size() * sizeof(int32_t)));
   pl->d_n_off = reinterpret_cast<int64_t *>(base + o_noff);
   pl->d_m_off = reinterpret_cast<int64_t *>(base + o_moff);
   pl->d_At_rowptr = reinterpret_cast<int64_t *>(base + o_trp);
@@ -491,6 +618,11 @@ cosmo_status build_plan(cosmo_plan *pl, const cosmo_problem *p) {
   pl->bkAt.d_rows = reinterpret_cast<int32_t *>(base + o_bAt);
   pl->bkA.d_span = reinterpret_cast<RowSpan *>(base + o_sA);
   pl->bkAt.d_span = reinterpret_cast<RowSpan *>(base + o_sAt);
+  pl->d_dense = reinterpret_cast<DenseDesc *>(base + o_dense);
+  pl->d_dense_inst = reinterpret_cast<int32_t *>(base + o_dinst);
+  pl->d_drow = reinterpret_cast<int32_t *>(base + o_drow);
+  pl->d_dscale = reinterpret_cast<double *>(base + o_dscale);
+  pl->d_dcol = reinterpret_cast<int32_t *>(base + o_dcol);
   return COSMO_OK;
 }
 
@@ -528,6 +660,10 @@ void build_layouts(cosmo_plan *pl) {
   f.rp = take(m);
   f.rd = take(n);
   f.rs = take(3 * (size_t)pl->sum_p2 * 8 / pl->esz);   // eigensolver refinement scratch
+  // float64 scratch of the dense sub-blocks: row products, column products, Jacobi terms
+  f.dn = take((size_t)pl->dense_rows_tot * 8 / pl->esz);
+  f.ec = take((size_t)pl->dense_cols_tot * 8 / pl->esz);
+  f.ed = take((size_t)pl->dense_cols_tot * 8 / pl->esz);
   f.total = o;
   // tape: slot k (x, s, y) for k = 0..K, then per step (x~, s~, lam, U)
   auto &t = pl->tp;
@@ -560,6 +696,9 @@ void build_layouts(cosmo_plan *pl) {
   w.cg = take(16 * ((size_t)pl->B + 1) + 256);
   w.vv = take(m);
   w.dk = take(pl->sum_p2_large);
+  w.dn = take((size_t)pl->dense_rows_tot * 8 / pl->esz);
+  w.ec = take((size_t)pl->dense_cols_tot * 8 / pl->esz);
+  w.ed = take((size_t)pl->dense_cols_tot * 8 / pl->esz);
   w.total = o;
 }
 
@@ -604,21 +743,24 @@ void launch_psd_classes(cosmo_plan *pl, const T *rho_hat, const T *vv, const T *
 }
 
 template <typename T>
-void launch_dk_classes(cosmo_plan *pl, const T *U, const T *lam, const T *g, T *out, T *scratch, hipStream_t st) {
+bool launch_dk_classes(cosmo_plan *pl, const T *U, const T *lam, const T *g, T *out, T *scratch, hipStream_t st) {
   ProfScope ps(pl, 1, st);
+  bool ok = true;
   fork_classes(pl, st, [&](int c, hipStream_t s) {
     const int n = pl->psd_cls_begin[c + 1] - pl->psd_cls_begin[c];
-    launch_psd_vjp<T>(pl->d_psd + pl->psd_cls_begin[c], n, pl->psd_cls_maxp[c], U, lam, g, out, scratch, s);
+    ok = launch_psd_vjp<T>(pl->d_psd + pl->psd_cls_begin[c], n, pl->psd_cls_maxp[c], U, lam, g, out, scratch, s) && ok;
   });
+  return ok;
 }
 
 template <typename T>
 cosmo_status forward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T *x0, const T *s0, const T *y0, T *xK,
                           T *sK, T *yK, T *tape, T *ws, cosmo_stats *stats, hipStream_t st) {
-  const View<T> v = make_view<T>(pl);
+  View<T> v = make_view<T>(pl);
   const int64_t n = pl->n_tot, m = pl->m_tot;
   const int K = pl->opt.K;
   auto &f = pl->fw;
+  bind_dense(v, ws, f.dn, f.ec, f.ed);
   T *rho_hat = ws + f.rho_hat;
   launch_rectify<T>(v, pl->d_rect, pl->n_rect, rho, rho_hat, K, st);
   auto X = [&](int k) -> T * { return tape ? tape + slot_x(pl, k) : ws + ((k & 1) ? f.itB : f.itA); };
@@ -652,6 +794,7 @@ cosmo_status forward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T 
     }
     {
       ProfScope ps(pl, 3, st);
+      launch_dense_cols<T>(v, DC_XI, rh, y, s, st);
       launch_cols_pre<T>(v, pl->bkAt, rh, x, s, y, ws + f.dg, reinterpret_cast<double *>(ws + f.xi), ds, st);
     }
     if (!pl->diag_M) {
@@ -661,6 +804,7 @@ cosmo_status forward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T 
     }
     {
       ProfScope ps(pl, 3, st);
+      launch_dense_rows<T>(v, xt, st);
       launch_rows_post<T>(v, pl->bkA, rh, al, xt, s, y, ST(k), ws + f.sh, ws + f.vv, sn, yn, st);
     }
     launch_soc_step<T>(pl->d_soc, pl->n_soc, rh, ws + f.vv, ws + f.sh, y, sn, yn, st);
@@ -683,10 +827,11 @@ template <typename T>
 cosmo_status backward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T *tape, const T *gxK, const T *gsK,
                            const T *gyK, T *grho, T *galpha, T *gx0, T *gs0, T *gy0, T *ws, cosmo_stats *stats,
                            hipStream_t st) {
-  const View<T> v = make_view<T>(pl);
+  View<T> v = make_view<T>(pl);
   const int64_t n = pl->n_tot, m = pl->m_tot;
   const int K = pl->opt.K;
   auto &w = pl->bw;
+  bind_dense(v, ws, w.dn, w.ec, w.ed);
   T *rho_hat = ws + w.rho_hat;
   launch_rectify<T>(v, pl->d_rect, pl->n_rect, rho, rho_hat, K, st);
   const size_t on = 0, os = align_up(n, 64), oy = align_up(n, 64) + align_up(m, 64);
@@ -715,7 +860,8 @@ cosmo_status backward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T
       launch_rows_v<T>(v, rh, al, stl, s, y, ws + w.vv, st);
     }
     launch_soc_vjp<T>(pl->d_soc, pl->n_soc, ws + w.vv, ws + w.gsn, ws + w.gv, st);
-    launch_dk_classes<T>(pl, U, lam, ws + w.gsn, ws + w.gv, scratch, st);
+    if (!launch_dk_classes<T>(pl, U, lam, ws + w.gsn, ws + w.gv, scratch, st))
+      FAIL(COSMO_EUNSUPPORTED, "a PSD block is too large for the VJP's LDS layout");
     {
       ProfScope ps(pl, 3, st);
       launch_bwd_rows_b<T>(v, rh, al, stl, s, y, sn, gy_in, ws + w.gv, ws + w.gsh, ws + w.gst, gs_out, gy_out,
@@ -726,6 +872,7 @@ cosmo_status backward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T
         ds.xn = gx_out;
         ds.alpha_k = al;
       }
+      launch_dense_cols<T>(v, DC_GST, rh, ws + w.gst, nullptr, st);
       launch_bwd_cols<T>(v, pl->bkAt, rh, al, ws + w.gst, gx_in, reinterpret_cast<double *>(ws + w.gxt), ws + w.dg, ds, st);
     }
     if (!pl->diag_M) {
@@ -736,6 +883,7 @@ cosmo_status backward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T
     }
     {
       ProfScope ps(pl, 3, st);
+      launch_dense_rows<T>(v, ws + w.w, st);
       launch_bwd_rows_c<T>(v, pl->bkA, rh, ws + w.w, stl, s, ws + w.grh, gs_out, gy_out, st);
     }
     if (grho) launch_rect_adjoint<T>(v, pl->d_rect, pl->n_rect, ws + w.grh, grho + (size_t)k * m, st);
@@ -934,13 +1082,15 @@ cosmo_status cosmo_residual_loss(cosmo_plan *plan, const void *x, const void *s,
   if (!x || !s || !y || !loss || !ws) FAIL(COSMO_EINVAL, "x, s, y, loss and ws are required");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (plan->opt.dtype == COSMO_F32) {
-    const View<float> v = make_view<float>(plan);
+    View<float> v = make_view<float>(plan);
     float *w = (float *)ws;
+    bind_dense(v, w, plan->fw.dn, plan->fw.ec, plan->fw.ed);
     launch_loss<float>(v, plan->bkA, plan->bkAt, (const float *)x, (const float *)s, (const float *)y, w + plan->fw.rp,
                        w + plan->fw.rd, (float *)loss, (float *)gx, (float *)gs, (float *)gy, st);
   } else {
-    const View<double> v = make_view<double>(plan);
+    View<double> v = make_view<double>(plan);
     double *w = (double *)ws;
+    bind_dense(v, w, plan->fw.dn, plan->fw.ec, plan->fw.ed);
     launch_loss<double>(v, plan->bkA, plan->bkAt, (const double *)x, (const double *)s, (const double *)y,
                         w + plan->fw.rp, w + plan->fw.rd, (double *)loss, (double *)gx, (double *)gs, (double *)gy, st);
   }
@@ -955,6 +1105,7 @@ cosmo_status cosmo_plan_set_pcg_form(cosmo_plan *plan, int32_t form) {
   if (s != COSMO_OK) return s;
   if (form < 0 || form > 4) FAIL(COSMO_EINVAL, "form must be 0..4");
   if (form != 0 && plan->graph) FAIL(COSMO_EUNSUPPORTED, "the cooperative CG forms are not recorded into graphs");
+  if (form != 0 && plan->n_dense > 0) FAIL(COSMO_EUNSUPPORTED, "dense sub-blocks are applied by CG form 0 only");
   plan->pcg_form = form;
   return COSMO_OK;
 }
@@ -1013,7 +1164,7 @@ cosmo_status cosmo_plan_autotune(cosmo_plan *plan, const void *rho, const void *
   double best = -1.0;
   int best_c = -1;
   for (int c = 0; c < 4 && s == COSMO_OK; ++c) {
-    if (plan->diag_M && cand_form[c] != 0) continue;   // no CG to schedule
+    if ((plan->diag_M || plan->n_dense > 0) && cand_form[c] != 0) continue;   // no CG to schedule, or form 0 only
     plan->drop_graphs();
     plan->pcg_form = cand_form[c];
     plan->graph = cand_graph[c];
@@ -1183,12 +1334,12 @@ cosmo_status psd_proj_vjp_rule(int32_t nblk, const int32_t *order, const int64_t
   for (int c = 0; c < 4; ++c) {
     const int n = cb[c + 1] - cb[c];
     if (!n) continue;
-    if (dtype == COSMO_F32)
-      launch_psd_vjp<float>(d + cb[c], n, cm[c], (const float *)eigvecs, (const float *)eigvals, (const float *)gout,
-                            (float *)gin, (float *)scratch, st, rule, eps);
-    else
-      launch_psd_vjp<double>(d + cb[c], n, cm[c], (const double *)eigvecs, (const double *)eigvals,
-                             (const double *)gout, (double *)gin, (double *)scratch, st, rule, eps);
+    const bool ok = dtype == COSMO_F32
+        ? launch_psd_vjp<float>(d + cb[c], n, cm[c], (const float *)eigvecs, (const float *)eigvals,
+                                (const float *)gout, (float *)gin, (float *)scratch, st, rule, eps)
+        : launch_psd_vjp<double>(d + cb[c], n, cm[c], (const double *)eigvecs, (const double *)eigvals,
+                                 (const double *)gout, (double *)gin, (double *)scratch, st, rule, eps);
+    if (!ok) FAIL(COSMO_EUNSUPPORTED, "a PSD block is too large for the VJP's LDS layout");
   }
   HIPCHK(hipGetLastError());
   return COSMO_OK;

@@ -124,7 +124,9 @@ def huber_socp(rng: np.random.Generator, n_obs: int = 2000, n_coef: int = 500,
     cones = [Cone(NONNEG, 2 * n_obs)] + [Cone(SOC, int(d)) for d in dims]
     inst = ConicInstance(P, q, A, b, cones,
                          {"class": "huber", "n_obs": n_obs, "n_coef": n_coef,
-                          "dense_block": (0, 0, n_obs, n_coef)})
+                          # the design G sits at rows 0.. and (negated) at rows n_obs..
+                          "dense": {"col0": 0, "rows": n_obs, "cols": n_coef,
+                                    "place": [(0, 1.0), (n_obs, -1.0)]}})
     inst.check()
     return inst
 

@@ -50,7 +50,7 @@ def test_stats_struct_matches_header(L):
 
 def test_status_strings_and_version(L):
     lib = L.lib()
-    assert lib.cosmo_abi_version() == 1
+    assert lib.cosmo_abi_version() == 2
     assert b"EINVAL" in lib.cosmo_status_string(L.COSMO_EINVAL)
 
 
@@ -175,3 +175,84 @@ def test_binding_fails_loudly_without_library(monkeypatch, L):
     monkeypatch.setattr(L, "LIB_PATH", "/nonexistent/libcosmo_unroll.so")
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         L.lib()
+
+
+def test_struct_layouts_match_the_c_compiler(L, tmp_path):
+    """The ctypes mirrors of the header's structs have the C compiler's sizes
+    and field offsets (a mismatch would pass wrong pointers silently)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"cosmo_problem": L.CosmoProblem, "cosmo_options": L.CosmoOptions,
+               "cosmo_stats": L.CosmoStats, "cosmo_dense_block": L.CosmoDenseBlock}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "cosmo_unroll.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
+def _dense_block(L, **kw):
+    d = L.CosmoDenseBlock()
+    d.val, d.rows, d.cols, d.ld, d.col0, d.n_place, d.reserved = 256, 2, 2, 4, 0, 1, 0
+    d.row0[0], d.scale[0] = 0, 1.0
+    for k, v in kw.items():
+        if k in ("row0", "scale"):
+            for q, x in enumerate(v):
+                getattr(d, k)[q] = x
+        else:
+            setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("blocks", [
+    [dict(val=0)],                                   # NULL values
+    [dict(val=264)],                                 # not 16-byte aligned
+    [dict(cols=0)],
+    [dict(rows=0)],
+    [dict(cols=1025, ld=1028)],                      # wider than COSMO_DENSE_MAX_COLS
+    [dict(ld=3)],                                    # ld < cols ... and not a multiple of 4
+    [dict(ld=6)],                                    # not a multiple of 16 bytes (float32)
+    [dict(n_place=0)],
+    [dict(n_place=5)],
+    [dict(reserved=1)],
+    [dict(scale=[float("nan")])],
+    [dict(col0=3)],                                  # columns outside A (n_tot = 4)
+    [dict(row0=[3])],                                # rows outside A (m_tot = 4)
+    [dict(n_place=2, row0=[0, 1], scale=[1.0, -1.0])],   # one row in two placements
+    [dict(), dict(row0=[2], col0=1)],                # one column in two blocks
+    [dict(rows=2, cols=2, col0=1, row0=[1])],        # straddles the two instances (rows)
+])
+def test_invalid_dense_blocks_rejected_on_host(L, blocks):
+    # two instances: columns 0-1 | 2-3, rows 0-1 | 2-3
+    p, keep = _problem(L, B=2, n_off=(0, 2, 4), m_off=(0, 2, 4), kinds=(1, 1), sizes=(2, 2))
+    arr = (L.CosmoDenseBlock * len(blocks))(*[_dense_block(L, **b) for b in blocks])
+    p.n_dense = len(blocks)
+    p.dense = ctypes.cast(arr, ctypes.POINTER(L.CosmoDenseBlock))
+    h = ctypes.c_void_p()
+    st = L.lib().cosmo_plan_create(ctypes.byref(h), ctypes.byref(p), ctypes.byref(_options(L)))
+    assert st == L.COSMO_EINVAL, L.lib().cosmo_last_error()
+    assert h.value is None
+
+
+def test_dense_blocks_null_with_count_rejected(L):
+    p, keep = _problem(L)
+    p.n_dense = 1
+    p.dense = None
+    h = ctypes.c_void_p()
+    assert L.lib().cosmo_plan_create(ctypes.byref(h), ctypes.byref(p), ctypes.byref(_options(L))) == L.COSMO_EINVAL
+    p.n_dense = -1
+    assert L.lib().cosmo_plan_create(ctypes.byref(h), ctypes.byref(p), ctypes.byref(_options(L))) == L.COSMO_EINVAL

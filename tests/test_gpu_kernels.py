@@ -123,13 +123,20 @@ def test_psd_eigenpairs_are_orthonormal_and_accurate():
         uo += p * p
 
 
-@pytest.mark.parametrize("dtype,tol", [(np.float32, 3e-5), (np.float64, 1e-11)])
-def test_dk_vjp_matches_oracle(dtype, tol):
+# Orders up to each dtype's maximum, across all four order classes: the
+# largest (float32 200, float64 140) need the unpadded LDS layout of the
+# VJP's first buffer.
+@pytest.mark.parametrize("dtype,tol,orders", [
+    (np.float32, 3e-5, (3, 16, 17, 40, 64, 100)),
+    (np.float32, 3e-5, (129, 160, 199, 200)),
+    (np.float64, 1e-11, (3, 16, 17, 40, 64, 100, 129, 140)),
+])
+def test_dk_vjp_matches_oracle(dtype, tol, orders):
     ensure_lib()
     from paper_2606_13825_amd import psd_proj_vjp
     rng = np.random.default_rng(4)
     mats = []
-    for p in (3, 16, 17, 40, 64, 100):
+    for p in orders:
         mats.append(_sym(rng, p).astype(dtype).astype(np.float64))
     S2, _ = appc_matrix(40, 1e-8, rng, centers=(-1.0, 1.0))
     mats.append(S2.astype(dtype).astype(np.float64))
