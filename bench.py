@@ -12,9 +12,11 @@ one GPU):
   c3  32 Lovasz theta SDPs on random circulant graphs, n ~ U{64..200},
       float32, K = 50, forward + loss + backward
   c4  256 Huber-regression SOCPs (2000 x 500 Gaussian design, Student-t
-      noise, 200 second-order cones of dimension 3-10), float32, K = 40,
-      forward + loss + backward; the design is passed once as a dense block
-      placed at +G and -G (the default line)
+      noise, 200 second-order cones of dimension 3-10), K = 40, forward +
+      loss + backward; the design is passed once as a dense block placed at
+      +G and -G and stored as float32 (the data are float32 numbers), the
+      iteration runs in float64 (the default line; --dtype f32 runs it in
+      float32 throughout)
   c5  128 covariance-steering SDPs (nx in {4..12}, nu = nx/2, T ~ U{30..100}),
       float32, K = 30, forward + loss + backward
 
@@ -96,7 +98,7 @@ def traffic_from_profile(profile, source, **match):
         return None
 
 
-def pcg_bytes_per_iteration(inst, esz):
+def pcg_bytes_per_iteration(inst, esz, gsz=None):
     """Algorithmic HBM bytes of one PCG iteration (one operator application)
     on one instance: the values and column indices of A and A' (one pass
     each) and of P, plus the vectors the iteration streams (p, t = rho A p,
@@ -110,7 +112,7 @@ def pcg_bytes_per_iteration(inst, esz):
         A = inst.A.tocsr()
         for (r0, _) in d["place"]:
             nnz_a -= A[int(r0):int(r0) + d["rows"], d["col0"]:d["col0"] + d["cols"]].nnz
-        dense_bytes = d["rows"] * d["cols"] * esz
+        dense_bytes = d["rows"] * d["cols"] * (gsz or esz)
     nnz_p = inst.P.nnz if inst.P is not None else 0
     return dense_bytes + 2 * nnz_a * (esz + 4) + nnz_p * (esz + 4) + esz * (6 * inst.n + 2 * inst.m)
 
@@ -142,9 +144,11 @@ def _workload(name):
                     dtype="f32", backward=True, hyper="default", cpu_sample=16, cpu_steps=10, err_sample=2,
                     cg_tol=1e-10)
     if name == "c4":
-        return dict(name="huber_socp_batch256_2000x500_200soc_fp32_K40", insts=f32(synth.c4_batch()), K=40,
-                    dtype="f32", backward=True, hyper="default", cpu_sample=16, cpu_steps=2, err_sample=2,
-                    cg_max_iter=1000)
+        # float64 iterations on float32 data: the design block (the traffic)
+        # is stored as float32, losslessly, the vectors and sums are float64
+        return dict(name="huber_socp_batch256_2000x500_200soc_f64_blockf32_K40", insts=f32(synth.c4_batch()),
+                    K=40, dtype="f64", dense_f32=True, backward=True, hyper="default", cpu_sample=16, cpu_steps=2,
+                    err_sample=2, cg_tol=1e-10, cg_max_iter=1000)
     if name == "c5":
         return dict(name="covsteer_sdp_batch128_nx4-12_T30-100_fp32_K30", insts=f32(synth.c5_batch()), K=30,
                     dtype="f32", backward=True, hyper="default", cpu_sample=16, cpu_steps=30, err_sample=0,
@@ -180,6 +184,38 @@ def _oracle_job(args):
         g = oracle.residual_loss_grad(inst, x, s, y)
         grho, galpha, *_ = oracle.unroll_backward(inst, tape, *g)
     return time.perf_counter() - t0, x, s, y, grho, galpha
+
+
+def _floor_job(args):
+    """One realisation of the oracle's float32 rounding model on one instance
+    (the floor float32 storage alone sets on it)."""
+    inst, rho, alpha, backward, resid, r = args
+    import oracle
+    return oracle.rounding_floor_runs(inst, rho, alpha, backward=backward, solve_resid=resid, which=(r,))[0]
+
+
+def float32_floor(wl, rhos, alphas, idx, ref_runs):
+    """Largest relative errors (iterates, gradients) of the rounding model's
+    three realisations against the oracle's exact runs, over instances idx
+    (ref_runs[j] is the exact run of idx[j]).  Solves stop at the float32 CG
+    residual (1e-7, or the workload's tolerance if larger) except on the
+    max-cut family, whose reduced matrix is diagonal."""
+    import multiprocessing as mp
+    resid = 0.0 if wl["name"].startswith("maxcut") else max(wl.get("cg_tol", 1e-8), 1e-7)
+    jobs = [(wl["insts"][i], rhos[i].astype(np.float64), alphas[i].astype(np.float64), wl["backward"], resid, r)
+            for i in idx for r in range(3)]
+    # this process has initialised the GPU: the workers are fresh interpreters
+    with mp.get_context("spawn").Pool(min(len(jobs), 12)) as pool:
+        runs = pool.map(_floor_job, jobs)
+    e_it = e_g = 0.0
+    for j, (x, s, y, grho, galpha) in enumerate(runs):
+        ref = ref_runs[j // 3]
+        for a, b in zip((x, s, y), ref[1:4]):
+            e_it = max(e_it, np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-12))
+        if wl["backward"]:
+            e_g = max(e_g, np.linalg.norm(grho - ref[4]) / max(np.linalg.norm(ref[4]), 1e-12),
+                      np.linalg.norm(galpha - ref[5]) / max(np.linalg.norm(ref[5]), 1e-12))
+    return e_it, e_g
 
 
 def cpu_baseline(wl, rhos, alphas, n_sample, steps, workers):
@@ -381,9 +417,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--cpu-sample", type=int, default=None, help="instances in the oracle sample")
+    ap.add_argument("--dtype", default=None, choices=["f32"],
+                    help="f32: run the workload in float32 throughout (dense blocks, vectors, sums)")
+    ap.add_argument("--plain-sample", type=int, default=32,
+                    help="instances timed in the plain (unbatched forward-only) comparison")
     ap.add_argument("--schedule", default="auto", choices=["auto", "eager0"],
                     help="auto: the autotuner's choice; eager0: CG form 0, eager launches")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-floor", action="store_true",
+                    help="skip the float32 floor of the error sample (the oracle's rounding model)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain (unbatched forward-only) comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 256 MiB five times (reference for the HBM byte counters)")
@@ -412,6 +454,10 @@ def main():
         return
 
     wl = _workload(args.workload)
+    if args.dtype == "f32" and wl["dtype"] != "f32":
+        wl = dict(wl, dtype="f32", name=wl["name"].replace("_f64_blockf32", "_fp32"))
+        for key in ("dense_f32", "cg_tol"):
+            wl.pop(key, None)
     insts, K, backward = wl["insts"], wl["K"], wl["backward"]
     B = len(insts)
     rhos, alphas = _hyper(wl)
@@ -445,7 +491,7 @@ def main():
     torch.zeros(1, device=dev)          # initialise the device before the memory counters
     tdt = torch.float32 if wl["dtype"] == "f32" else torch.float64
     kw = {}
-    for key in ("cg_tol", "cg_max_iter"):
+    for key in ("cg_tol", "cg_max_iter", "dense_f32"):
         if key in wl:
             kw[key] = wl[key]
 
@@ -551,17 +597,20 @@ def main():
     n_pcg, ms_pcg = fam["pcg"]
     if n_pcg > 0:
         esz = 4 if wl["dtype"] == "f32" else 8
+        gsz = 4 if wl.get("dense_f32") else esz
         iters = sprof["cg_iters_total"].astype(np.float64)
         passes = sprof["cg_passes_total"].astype(np.float64)
         # operator applications: one per iteration and one per float64 true-residual pass
-        total = sum((iters[i] + passes[i]) * pcg_bytes_per_iteration(inst, esz) for i, inst in enumerate(insts))
+        total = sum((iters[i] + passes[i]) * pcg_bytes_per_iteration(inst, esz, gsz)
+                    for i, inst in enumerate(insts))
         avg_ms = ms_pcg / n_pcg
         ach = total / n_pcg / (avg_ms * 1e-3) / 1e9
         form = batch.pcg_form()
         tn = "float" if esz == 4 else "double"
         kname = (f"k_pcg_coop<{tn}> (cooperative, <= {form} workgroups per CU)" if form > 0
                  else f"k_pcg<{tn}> (one workgroup per instance"
-                      + (", dense blocks fused)" if batch.n_dense else ")"))
+                      + ((", dense blocks fused" + (", stored float32)" if gsz < esz else ")"))
+                         if batch.n_dense else ")"))
         rooflines["pcg"] = {"kernel": kname, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                             "frac": ach / PEAK_HBM_GBS,
                             "traffic": (traffic_from_profile(PCG_PROFILE, PCG_SOURCE, pcg_form=form)
@@ -576,28 +625,36 @@ def main():
     plain = None
     peak_plain = None
     if not args.no_plain:
+        # the plain form: each instance alone, forward only, no tape, one
+        # plan at a time (created, warmed up, timed, destroyed); its peak HBM
+        # is the largest footprint of one such call (plan + buffers)
         del tape, fws, bws
         torch.cuda.empty_cache()
-        torch.cuda.synchronize(dev)
-        torch.cuda.reset_peak_memory_stats(dev)
-        base_mem2 = torch.cuda.memory_allocated(dev)
-        free1, res1 = torch.cuda.mem_get_info(dev)[0], torch.cuda.memory_reserved(dev)
-        singles = [CosmoBatch([inst], K=K, dtype=tdt, device=dev, **kw) for inst in insts]
-        torch.cuda.synchronize(dev)
-        plan_bytes_plain = max(0, (free1 - torch.cuda.mem_get_info(dev)[0]) - (torch.cuda.memory_reserved(dev) - res1))
-        srho = [torch.from_numpy(r).to(dev) for r in rhos]
-        salpha = [torch.from_numpy(a.reshape(K, 1)).to(dev) for a in alphas]
-        for i in range(min(2, B)):
-            singles[i].forward(srho[i], salpha[i], tape=False)
-        torch.cuda.synchronize(dev)
-        t1 = time.perf_counter()
-        for i in range(B):
-            singles[i].forward(srho[i], salpha[i], tape=False)
-        torch.cuda.synchronize(dev)
-        dt_plain = time.perf_counter() - t1
-        peak_plain = torch.cuda.max_memory_allocated(dev) - base_mem2 + plan_bytes_plain
-        plain = {"value": B * K / dt_plain, "unit": "instance-iterations/s", "ms_total": dt_plain * 1e3}
-        print(f"[bench] plain forward {dt_plain * 1e3:.2f} ms for B={B}", file=sys.stderr, flush=True)
+        n_plain = min(B, max(1, args.plain_sample))
+        dt_plain, peak_plain = 0.0, 0
+        for i in range(n_plain):
+            torch.cuda.synchronize(dev)
+            torch.cuda.reset_peak_memory_stats(dev)
+            base_i = torch.cuda.memory_allocated(dev)
+            free_i, res_i = torch.cuda.mem_get_info(dev)[0], torch.cuda.memory_reserved(dev)
+            single = CosmoBatch([insts[i]], K=K, dtype=tdt, device=dev, **kw)
+            torch.cuda.synchronize(dev)
+            pb = max(0, (free_i - torch.cuda.mem_get_info(dev)[0]) - (torch.cuda.memory_reserved(dev) - res_i))
+            srho = torch.from_numpy(rhos[i]).to(dev)
+            salpha = torch.from_numpy(alphas[i].reshape(K, 1)).to(dev)
+            single.forward(srho, salpha, tape=False)
+            torch.cuda.synchronize(dev)
+            t1 = time.perf_counter()
+            single.forward(srho, salpha, tape=False)
+            torch.cuda.synchronize(dev)
+            dt_plain += time.perf_counter() - t1
+            peak_plain = max(peak_plain, torch.cuda.max_memory_allocated(dev) - base_i + pb)
+            single.close()
+            del single, srho, salpha
+        plain = {"value": n_plain * K / dt_plain, "unit": "instance-iterations/s", "ms_total": dt_plain * 1e3,
+                 "instances": n_plain}
+        print(f"[bench] plain forward {dt_plain * 1e3:.2f} ms for the first {n_plain} instances one by one",
+              file=sys.stderr, flush=True)
 
     out = {
         "metric": METRIC,
@@ -614,7 +671,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["name"], "instances": B, "unroll_K": K,
                    "pass": "forward+loss+backward" if backward else "forward"},
-        "peak_hbm_bytes": {"batched": int(peak_fb), "plain_fwd_unbatched": None if peak_plain is None
+        "peak_hbm_bytes": {"batched": int(peak_fb), "plain_fwd_one_instance": None if peak_plain is None
                            else int(peak_plain)},
         "plain_fwd": plain,
         "kernel_families_ms_per_step": {k: v[1] for k, v in fam.items()},
@@ -642,9 +699,10 @@ def main():
             pool.close()
             pool.join()
         if ref_runs is not None:
-            e_it, e_g = 0.0, 0.0
+            per = []   # (iterate error, gradient error) per sampled instance
             xs, ss, ys = batch.split_n(fw.x), batch.split_m(fw.s), batch.split_m(fw.y)
             for i, (_, x, s, y, grho, galpha) in enumerate(ref_runs):
+                e_it, e_g = 0.0, 0.0
                 for gpu, ref in ((xs[i], x), (ss[i], s), (ys[i], y)):
                     e_it = max(e_it, np.linalg.norm(gpu.double().cpu().numpy() - ref) /
                                max(np.linalg.norm(ref), 1e-12))
@@ -653,8 +711,23 @@ def main():
                     e_g = max(e_g, np.linalg.norm(gr - grho) / max(np.linalg.norm(grho), 1e-12))
                     ga = bw.galpha[:, i].double().cpu().numpy()
                     e_g = max(e_g, np.linalg.norm(ga - galpha) / max(np.linalg.norm(galpha), 1e-12))
+                per.append((e_it, e_g))
+            e_it = max(p[0] for p in per)
+            e_g = max(p[1] for p in per)
             out["rel_err_vs_oracle"] = {"final_iterates_max": e_it, "gradients_max": e_g if backward else None,
                                         "instances": len(ref_runs), "steps": K}
+            if wl["dtype"] == "f32" and not args.no_floor:
+                # the float32 floor of the two sampled instances with the largest errors
+                key = 1 if backward else 0
+                worst = sorted(range(len(per)), key=lambda j: -per[j][key])[:2]
+                f_it, f_g = float32_floor(wl, rhos, alphas, worst, [ref_runs[j] for j in worst])
+                out["rel_err_vs_oracle"]["float32_floor"] = {
+                    "instances": worst, "final_iterates_max": f_it, "gradients_max": f_g if backward else None,
+                    "model": "the oracle with every stored per-step value rounded to float32 (nearest, and "
+                             "two runs within one unit in the last place with solves stopped at the float32 "
+                             "CG residual); largest error of the three against the exact run"}
+                print(f"[bench] float32 floor on instances {worst}: iterates {f_it:.2e}, gradients {f_g:.2e}",
+                      file=sys.stderr, flush=True)
     print(json.dumps(out))
 
 

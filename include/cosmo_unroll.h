@@ -90,20 +90,29 @@ typedef struct cosmo_plan cosmo_plan;
  * Constraints (COSMO_EINVAL otherwise, before any device access): all rows
  * and columns of a block lie inside one instance; no row of A lies in two
  * placements (of any blocks); no column lies in two blocks; 1 <= cols <=
- * COSMO_DENSE_MAX_COLS; ld >= cols and ld a multiple of 16 / sizeof(dtype);
- * val 16-byte aligned.  While dense blocks are present the CG runs in form 0
- * (cosmo_plan_set_pcg_form with form > 0 returns COSMO_EUNSUPPORTED). */
+ * COSMO_DENSE_MAX_COLS; ld >= cols and ld a multiple of 16 / (bytes per
+ * stored value); val 16-byte aligned; val_f32 the same for every block of a
+ * plan.  While dense blocks are present the CG runs in form 0
+ * (cosmo_plan_set_pcg_form with form > 0 returns COSMO_EUNSUPPORTED).
+ *
+ * Storage type: with val_f32 = 1 a float64 plan reads the values of G as
+ * float32 and does all its arithmetic in float64; G then is, by definition,
+ * those float32 values.  A product with G is bound by reading G (one value
+ * per multiply-add), so problems whose data are float32 numbers (e.g. data
+ * generated in float64 and rounded to float32) run float64 iterations at the
+ * float32 cost of their dense blocks.  In a float32 plan val_f32 may be 0 or
+ * 1 (both mean float32). */
 #define COSMO_DENSE_MAX_PLACEMENTS 4
 #define COSMO_DENSE_MAX_COLS 1024
 typedef struct {
-  const void *val;             /* (d) rows x ld, row-major, dtype; valid and unchanged
+  const void *val;             /* (d) rows x ld, row-major, dtype or float32 (val_f32); valid and unchanged
                                   until cosmo_plan_destroy                              */
   int32_t rows;                /* >= 1                                                  */
   int32_t cols;                /* 1 .. COSMO_DENSE_MAX_COLS                             */
   int64_t ld;                  /* elements between consecutive rows of val              */
   int64_t col0;                /* first column of the block in the stacked A           */
   int32_t n_place;             /* placements, 1 .. COSMO_DENSE_MAX_PLACEMENTS           */
-  int32_t reserved;            /* must be 0                                             */
+  int32_t val_f32;             /* 1: val holds float32 values (see above); 0: dtype    */
   int64_t row0[COSMO_DENSE_MAX_PLACEMENTS];   /* first row of each placement            */
   double scale[COSMO_DENSE_MAX_PLACEMENTS];   /* finite multiplier of each placement    */
 } cosmo_dense_block;
@@ -171,6 +180,8 @@ typedef struct {
   int32_t cg_iters_total;      /* PCG iterations summed over the solves                */
   int32_t cg_passes_total;     /* float64 true-residual passes summed over the solves
                                   (each is one more operator application)               */
+  int32_t eig_refine_steps_total; /* float32 eigenpair refinement steps summed over the
+                                  PSD block solves (1 to 3 per solve)                   */
 } cosmo_stats;
 
 const char *cosmo_status_string(cosmo_status s);

@@ -32,7 +32,7 @@ from .cones import (rectify, rectify_adjoint, proj_cone, proj_cone_vjp, proj_soc
                     proj_psd, psd_vjp_dk, lowner_matrix, proj_nonneg, psd_vjp_naive)
 from .cosmo import (Hyper, step_forward, unroll_forward, unroll_backward, residual_loss,
                     residual_loss_grad, kkt_residuals, solve_reduced, reduced_matrix,
-                    implicit_solve_vjp, step_backward, run_fixed)
+                    implicit_solve_vjp, step_backward, run_fixed, rounding_floor_runs)
 from .fd import fd_check_unroll, fd_directional
 from .psd_rules import psd_vjp_tikhonov, ns_forward, ns_vjp, psd_vjp_ns
 
@@ -43,6 +43,6 @@ __all__ = [
     "psd_vjp_tikhonov", "ns_forward", "ns_vjp", "psd_vjp_ns",
     "Hyper", "step_forward", "unroll_forward", "unroll_backward", "residual_loss",
     "residual_loss_grad", "kkt_residuals", "solve_reduced", "reduced_matrix",
-    "implicit_solve_vjp", "step_backward", "run_fixed",
+    "implicit_solve_vjp", "step_backward", "run_fixed", "rounding_floor_runs",
     "fd_check_unroll", "fd_directional",
 ]

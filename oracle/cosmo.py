@@ -43,38 +43,102 @@ def solve_reduced(inst, rho_hat: np.ndarray, sigma: float):
     return spla.splu(reduced_matrix(inst, rho_hat, sigma))
 
 
-def step_forward(inst, x, s, y, rho, alpha, sigma=1e-6, lu=None) -> dict:
-    """One COSMO step z^k -> z^{k+1}; returns every intermediate."""
+def _keep(a):
+    return a
+
+
+def step_forward(inst, x, s, y, rho, alpha, sigma=1e-6, lu=None, store=_keep, solve_err=None) -> dict:
+    """One COSMO step z^k -> z^{k+1}; returns every intermediate.
+
+    store: applied to every quantity a pipeline keeps in memory as soon as it
+    is formed (identity by default); solve_err(xi) -> r: the solve returns
+    M^{-1}(xi + r) instead of M^{-1} xi (None: exact).  Both only serve
+    unroll_forward's rounding model."""
     A, b, q = inst.A, inst.b, inst.q
-    rho_hat = rectify(rho, inst.cones)
+    rho_hat = store(rectify(rho, inst.cones))
     if lu is None:
         lu = solve_reduced(inst, rho_hat, sigma)
     xi = sigma * x - q + A.T @ (y + rho_hat * (b - s))
-    xt = lu.solve(xi)
-    st = b - A @ xt
-    xn = alpha * xt + (1.0 - alpha) * x
-    sh = alpha * st + (1.0 - alpha) * s
-    v = sh + y / rho_hat
+    xt = store(lu.solve(xi if solve_err is None else xi + solve_err(xi)))
+    st = store(b - A @ xt)
+    xn = store(alpha * xt + (1.0 - alpha) * x)
+    sh = store(alpha * st + (1.0 - alpha) * s)
+    v = store(sh + y / rho_hat)
     sn, aux = proj_cone(v, inst.cones)
-    yn = y + rho_hat * (sh - sn)
+    sn = store(sn)
+    if store is not _keep:
+        aux = [None if a is None else (store(a[0]), store(a[1])) for a in aux]
+    yn = store(y + rho_hat * (sh - sn))
     return dict(x=x, s=s, y=y, rho=rho, rho_hat=rho_hat, alpha=alpha, xi=xi, xt=xt,
                 st=st, sh=sh, v=v, aux=aux, lu=lu, xn=xn, sn=sn, yn=yn)
 
 
 def unroll_forward(inst, rho: np.ndarray, alpha: np.ndarray, x0=None, s0=None, y0=None,
-                   sigma: float = 1e-6):
+                   sigma: float = 1e-6, store_dtype=None, store_rng=None, solve_resid: float = 0.0):
     """K steps with per-iteration (rho^k, alpha^k); z^0 = 0 unless given
-    (App. D: zero default initialisation).  Returns (tape, (xK, sK, yK))."""
+    (App. D: zero default initialisation).  Returns (tape, (xK, sK, yK)).
+
+    Rounding model (not the method; None / 0 by default).  store_dtype (e.g.
+    np.float32): every per-step quantity a pipeline of that precision stores
+    -- rho_hat, x~, s~, x+, s^, v, s+ with its PSD eigenpairs, y+ -- is
+    rounded to it as soon as it is formed; the arithmetic stays float64.
+    store_rng (a numpy Generator, with store_dtype): each stored value then
+    moves by -1, 0 or +1 unit in the last place of store_dtype, uniformly at
+    random -- one of the pipelines whose stored values are within one unit of
+    the exact ones.  solve_resid (with store_rng): every solve stops at that
+    relative residual, in a random direction.  unroll_backward runs on the
+    rounded tape, so the model measures how far storage precision (and solve
+    tolerance) alone move a trajectory and its gradients: a floor that a
+    pipeline of that precision cannot beat."""
     n, m = inst.A.shape[1], inst.A.shape[0]
     x = np.zeros(n) if x0 is None else np.asarray(x0, np.float64).copy()
     s = np.zeros(m) if s0 is None else np.asarray(s0, np.float64).copy()
     y = np.zeros(m) if y0 is None else np.asarray(y0, np.float64).copy()
+    store, solve_err = _keep, None
+    if store_dtype is not None:
+        dt = np.dtype(store_dtype)
+
+        def store(a):
+            r = np.asarray(a).astype(dt)
+            if store_rng is not None:
+                step = store_rng.integers(-1, 2, size=r.shape)
+                r = np.where(step > 0, np.nextafter(r, dt.type(np.inf)),
+                             np.where(step < 0, np.nextafter(r, dt.type(-np.inf)), r))
+            return r.astype(np.float64)
+
+        if store_rng is not None and solve_resid > 0:
+            def solve_err(xi):
+                r = store_rng.standard_normal(xi.shape)
+                return r * (solve_resid * np.linalg.norm(xi) / max(np.linalg.norm(r), 1e-300))
     tape = []
     for k in range(rho.shape[0]):
-        st = step_forward(inst, x, s, y, rho[k], float(alpha[k]), sigma)
+        st = step_forward(inst, x, s, y, rho[k], float(alpha[k]), sigma, store=store, solve_err=solve_err)
         tape.append(st)
         x, s, y = st["xn"], st["sn"], st["yn"]
     return tape, (x, s, y)
+
+
+def rounding_floor_runs(inst, rho: np.ndarray, alpha: np.ndarray, x0=None, s0=None, y0=None,
+                        backward: bool = True, solve_resid: float = 0.0, store_dtype=np.float32,
+                        which=(0, 1, 2)):
+    """Three realisations of the rounding model (unroll_forward): stored values
+    rounded to nearest with exact solves, and two (seeds 1 and 2) with every
+    stored value moved by up to one unit in the last place and the solves
+    stopped at solve_resid.  Returns [(x, s, y, grho, galpha)] (gradients of
+    the residual loss; None when backward is False).  Against the exact run,
+    the largest of their errors is the floor a pipeline storing store_dtype
+    cannot beat on this instance.  which: the realisations to run."""
+    out = []
+    for r in which:
+        kw = dict(store_dtype=store_dtype)
+        if r > 0:
+            kw.update(store_rng=np.random.default_rng(r), solve_resid=solve_resid)
+        tape, (x, s, y) = unroll_forward(inst, rho, alpha, x0, s0, y0, **kw)
+        grho = galpha = None
+        if backward:
+            grho, galpha, *_ = unroll_backward(inst, tape, *residual_loss_grad(inst, x, s, y))
+        out.append((x, s, y, grho, galpha))
+    return out
 
 
 def step_backward(inst, st: dict, gxn, gsn, gyn, sigma=1e-6):

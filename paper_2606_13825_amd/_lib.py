@@ -41,7 +41,7 @@ class CosmoDenseBlock(ctypes.Structure):
         ("ld", ctypes.c_int64),
         ("col0", ctypes.c_int64),
         ("n_place", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("val_f32", ctypes.c_int32),
         ("row0", ctypes.c_int64 * DENSE_MAX_PLACEMENTS),
         ("scale", ctypes.c_double * DENSE_MAX_PLACEMENTS),
     ]
@@ -89,12 +89,12 @@ class CosmoStats(ctypes.Structure):
                 ("eig_sweeps_max", ctypes.c_int32), ("eig_not_converged", ctypes.c_int32),
                 ("nonfinite", ctypes.c_int32), ("eig_sweeps_total", ctypes.c_int32),
                 ("eig_solves", ctypes.c_int32), ("cg_iters_total", ctypes.c_int32),
-                ("cg_passes_total", ctypes.c_int32)]
+                ("cg_passes_total", ctypes.c_int32), ("eig_refine_steps_total", ctypes.c_int32)]
 
 
 STATS_FIELDS = ["cg_iters_max", "cg_not_converged", "eig_sweeps_max", "eig_not_converged", "nonfinite",
                 "eig_sweeps_total", "eig_solves", "cg_iters_total",
-                "cg_passes_total"]
+                "cg_passes_total", "eig_refine_steps_total"]
 STATS_INTS = len(STATS_FIELDS)
 
 _lib = None

@@ -98,7 +98,7 @@ class CosmoBatch:
     def __init__(self, instances: Sequence, *, K: int, dtype=torch.float32, sigma: float = 1e-6,
                  cg_tol: Optional[float] = None, cg_max_iter: int = 500, eig_max_sweeps: int = 60,
                  eig_tol: float = 0.0, eig_refine: int = 1, eig_warm_start: bool = True, dense: bool = True,
-                 device="cuda:0"):
+                 dense_f32: bool = False, device="cuda:0"):
         self.device = torch.device(device)
         self.code = _dt_code(dtype)
         self.dtype = _TORCH_DT[self.code]
@@ -157,7 +157,14 @@ class CosmoBatch:
         self.cone_size = np.asarray(sizes, np.int32)
         # dense blocks: one device array, each block row-major with ld a
         # multiple of 16 bytes (every block starts 16-byte aligned)
-        ve = 16 // np.dtype(npdt).itemsize
+        # dense_f32: a float64 batch stores its dense blocks as float32; only
+        # blocks whose values are float32 numbers qualify (then nothing is lost)
+        gdt = np.float32 if dense_f32 else npdt
+        if dense_f32:
+            for _, G, _ in dense_parts:
+                if not np.array_equal(G.astype(np.float32).astype(G.dtype), G):
+                    raise ValueError("dense_f32: a dense block has values that are not float32 numbers")
+        ve = 16 // np.dtype(gdt).itemsize
         self.n_dense = len(dense_parts)
         self._dense_desc = (L.CosmoDenseBlock * max(1, self.n_dense))()
         self.dense_val = None
@@ -166,14 +173,14 @@ class CosmoBatch:
             for k, (i, G, desc) in enumerate(dense_parts):
                 rows, cols = G.shape
                 ld = (cols + ve - 1) // ve * ve
-                Gp = np.zeros((rows, ld), npdt)
+                Gp = np.zeros((rows, ld), gdt)
                 Gp[:, :cols] = G
                 chunks.append(Gp.ravel())
                 d = self._dense_desc[k]
                 d.rows, d.cols, d.ld = rows, cols, ld
                 d.col0 = int(self.n_off[i]) + int(desc["col0"])
                 d.n_place = len(desc["place"])
-                d.reserved = 0
+                d.val_f32 = 1 if gdt == np.float32 else 0
                 for q, (row0, sc) in enumerate(desc["place"]):
                     d.row0[q] = int(self.m_off[i]) + int(row0)
                     d.scale[q] = float(sc)
@@ -182,7 +189,7 @@ class CosmoBatch:
             self.dense_val = torch.from_numpy(np.concatenate(chunks)).to(self.device)
             base = self.dense_val.data_ptr()
             for k in range(self.n_dense):
-                self._dense_desc[k].val = base + offs[k] * np.dtype(npdt).itemsize
+                self._dense_desc[k].val = base + offs[k] * np.dtype(gdt).itemsize
         self.instances_meta = [(ns[i], ms[i]) for i in range(self.B)]
         prob = L.CosmoProblem()
         prob.B = self.B

@@ -41,7 +41,7 @@ struct RectDesc {     // a block whose penalty is averaged (SOC or PSD)
 // placements, the instance owning it, and where its per-row and per-column
 // results go in the dense scratch vectors (doff: rows, coff: columns).
 struct DenseDesc {
-  const void *val;    // rows x ld, row-major, dtype
+  const void *val;    // rows x ld, row-major, the plan's dtype or float32 (View::dense_g32)
   int64_t ld;
   int64_t col0;
   int64_t doff, coff;
@@ -96,14 +96,16 @@ template <typename T> struct View {
   const int64_t *instA; const int64_t *instAt;
   int32_t B; int64_t n_tot, m_tot;
   T sigma;
-  // dense sub-blocks (dense == nullptr: none).  dense_inst[b] .. dense_inst[b + 1]
+  // dense sub-blocks (dense == nullptr: none).  dense_g32: the blocks' values
+  // are stored as float32 (in a float64 View; a float32 View stores float32
+  // anyway).  dense_inst[b] .. dense_inst[b + 1]
   // are instance b's blocks; drow[i] is row i's entry in dn (or -1) and
   // dscale[i] the scale of the placement covering it; dcol[j] is column j's
   // entry in ec / ed (or -1).  dn, ec, ed are float64 scratch vectors of the
   // call's workspace (block rows, block columns, block columns).
   const DenseDesc *dense; const int32_t *dense_inst;
   const int32_t *drow; const double *dscale; const int32_t *dcol;
-  int32_t n_dense, dense_maxcols, dense_wg_rows, dense_wg_cols;
+  int32_t n_dense, dense_maxcols, dense_wg_rows, dense_wg_cols, dense_g32;
   double *dn; double *ec; double *ed;
 };
 

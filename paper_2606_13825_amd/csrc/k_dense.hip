@@ -51,11 +51,12 @@ template <bool ROWS> __device__ inline int find_block(const DenseDesc *dd, int32
 // Pieces per lane needed for up to COSMO_DENSE_MAX_COLS columns.
 template <typename T> constexpr int MAXP = COSMO_DENSE_MAX_COLS / (64 * (16 / (int)sizeof(T)));
 
-template <typename T>
+// T: the plan's arithmetic type; TG: the stored type of the blocks' values.
+template <typename T, typename TG>
 __global__ __launch_bounds__(NT) void k_dense_rows(const DenseDesc *__restrict__ dd, int32_t nd,
                                                    const T *__restrict__ vin, double *__restrict__ dn) {
-  constexpr int VE = 16 / sizeof(T);
-  constexpr int MP = MAXP<T>;
+  constexpr int VE = 16 / sizeof(TG);
+  constexpr int MP = MAXP<TG>;
   const DenseDesc d = dd[find_block<true>(dd, nd)];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int npieces = (d.cols + VE - 1) / VE;
@@ -68,13 +69,13 @@ __global__ __launch_bounds__(NT) void k_dense_rows(const DenseDesc *__restrict__
       const int c = (lane + 64 * q) * VE + e;
       xv[q][e] = c < d.cols ? (double)vin[d.col0 + c] : 0.0;
     }
-  const Piece<T> *G = static_cast<const Piece<T> *>(d.val);
+  const Piece<TG> *G = static_cast<const Piece<TG> *>(d.val);
   const int64_t ldp = d.ld / VE;   // pieces per row
   const int r_begin = (int)(blockIdx.x - d.wg_rows0) * ROWS_PER_WG + wave;
   const int r_end = min(d.rows, (int)(blockIdx.x - d.wg_rows0 + 1) * ROWS_PER_WG);
   constexpr int U = 4;
   for (int r0 = r_begin; r0 < r_end; r0 += U * NW) {
-    Piece<T> g[U][MP];
+    Piece<TG> g[U][MP];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int r = min(r0 + u * NW, r_end - 1);   // clamped; surplus rows are not written
@@ -129,10 +130,10 @@ __device__ inline void row_weights(const DenseDesc &d, const ColArgs &a, int r, 
   }
 }
 
-template <typename T>
+template <typename T, typename TG>
 __global__ __launch_bounds__(NT) void k_dense_cols(const DenseDesc *__restrict__ dd, int32_t nd, ColArgs a,
                                                    double *__restrict__ ec, double *__restrict__ ed) {
-  constexpr int VE = 16 / sizeof(T);
+  constexpr int VE = 16 / sizeof(TG);
   __shared__ double wt[TILE], wdt[TILE];
   __shared__ double part[2][NW][64 * VE];
   const DenseDesc d = dd[find_block<false>(dd, nd)];
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(NT) void k_dense_cols(const DenseDesc *__restrict__
   const int npieces = (d.cols + VE - 1) / VE;
   const int pc = (int)(blockIdx.x - d.wg_cols0) * 64 + lane;   // this lane's piece of the strip
   const bool has = pc < npieces;
-  const Piece<T> *G = static_cast<const Piece<T> *>(d.val);
+  const Piece<TG> *G = static_cast<const Piece<TG> *>(d.val);
   const int64_t ldp = d.ld / VE;
   double acc[VE], accd[VE];
 #pragma unroll
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(NT) void k_dense_cols(const DenseDesc *__restrict__
     const int q1 = min(nr, q0 + TILE / NW);
     constexpr int U = 8;
     for (int q = q0; q < q1; q += U) {
-      Piece<T> g[U];
+      Piece<TG> g[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int r = min(q + u, q1 - 1);
@@ -202,19 +203,25 @@ __global__ __launch_bounds__(NT) void k_dense_cols(const DenseDesc *__restrict__
 }  // namespace
 
 template <typename T> void launch_dense_rows(const View<T> &v, const T *vin, hipStream_t st) {
-  if (v.n_dense > 0 && v.dense_wg_rows > 0)
-    k_dense_rows<T><<<v.dense_wg_rows, NT, 0, st>>>(v.dense, v.n_dense, vin, v.dn);
+  if (v.n_dense <= 0 || v.dense_wg_rows <= 0) return;
+  if (sizeof(T) == 8 && v.dense_g32)
+    k_dense_rows<T, float><<<v.dense_wg_rows, NT, 0, st>>>(v.dense, v.n_dense, vin, v.dn);
+  else
+    k_dense_rows<T, T><<<v.dense_wg_rows, NT, 0, st>>>(v.dense, v.n_dense, vin, v.dn);
 }
 
 template <typename T>
 void launch_dense_cols(const View<T> &v, int32_t mode, const T *rho_hat, const T *u, const T *s, hipStream_t st) {
   if (v.n_dense <= 0 || v.dense_wg_cols <= 0) return;
   ColArgs a{mode, rho_hat, u, s, v.b};
-  k_dense_cols<T><<<v.dense_wg_cols, NT, 0, st>>>(v.dense, v.n_dense, a, v.ec, v.ed);
+  if (sizeof(T) == 8 && v.dense_g32)
+    k_dense_cols<T, float><<<v.dense_wg_cols, NT, 0, st>>>(v.dense, v.n_dense, a, v.ec, v.ed);
+  else
+    k_dense_cols<T, T><<<v.dense_wg_cols, NT, 0, st>>>(v.dense, v.n_dense, a, v.ec, v.ed);
 }
 
 // Workgroup counts of the two launches for a block (the host lays out
-// DenseDesc::wg_rows0 / wg_cols0 with these).
+// DenseDesc::wg_rows0 / wg_cols0 with these); esz: bytes per stored value.
 int32_t dense_row_workgroups(int32_t rows) { return (rows + ROWS_PER_WG - 1) / ROWS_PER_WG; }
 int32_t dense_col_workgroups(int32_t cols, size_t esz) {
   const int32_t strip = 64 * (int32_t)(16 / esz);

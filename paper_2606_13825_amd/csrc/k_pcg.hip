@@ -265,10 +265,10 @@ template <typename T> struct alignas(16) DPiece {
   T v[16 / sizeof(T)];
 };
 
-template <int NTH, int MP, typename AT, typename T, typename TT>
+template <int NTH, int MP, typename AT, typename TG, typename T, typename TT>
 __device__ inline void dense_block_fused(const DenseDesc &d, const T *__restrict__ rho_hat, const T *__restrict__ vin,
                                          TT *__restrict__ t, AT *__restrict__ lds, double *__restrict__ ec) {
-  constexpr int VE = 16 / sizeof(T);
+  constexpr int VE = 16 / sizeof(TG);
   constexpr int NW = NTH / 64;
   constexpr int U = 2;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -282,10 +282,10 @@ __device__ inline void dense_block_fused(const DenseDesc &d, const T *__restrict
       xv[q][e] = c < d.cols ? (AT)vin[d.col0 + c] : (AT)0;
       acc[q][e] = (AT)0;
     }
-  const DPiece<T> *G = static_cast<const DPiece<T> *>(d.val);
+  const DPiece<TG> *G = static_cast<const DPiece<TG> *>(d.val);
   const int64_t ldp = d.ld / VE;
   for (int r0 = wave; r0 < d.rows; r0 += U * NW) {
-    DPiece<T> g[U][MP];
+    DPiece<TG> g[U][MP];
     AT tp[U][COSMO_DENSE_MAX_PLACEMENTS], rp[U][COSMO_DENSE_MAX_PLACEMENTS];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -353,19 +353,20 @@ __device__ inline void dense_block_fused(const DenseDesc &d, const T *__restrict
 }
 
 // DMP: pieces per lane the kernel instantiation holds (the plan's widest
-// block fits in it).
-template <int NTH, int DMP, typename AT, typename T, typename TT>
+// block fits in it); TG: the stored type of the blocks' values.
+template <int NTH, int DMP, typename AT, typename TG, typename T, typename TT>
 __device__ inline void dense_fused(const View<T> &v, int b, const T *rho_hat, const T *vin, TT *t) {
   extern __shared__ double dyn_lds[];
   AT *lds = reinterpret_cast<AT *>(dyn_lds);
   for (int k = v.dense_inst[b]; k < v.dense_inst[b + 1]; ++k)
-    dense_block_fused<NTH, DMP, AT>(v.dense[k], rho_hat, vin, t, lds, v.ec);
+    dense_block_fused<NTH, DMP, AT, TG>(v.dense[k], rho_hat, vin, t, lds, v.ec);
 }
 
 // t = rho_hat o (A vin), then out = A' t + P vin + sigma vin, over the
 // instances [b0, b1), with sync() between and after the halves (workgroup
 // barrier in the per-instance form, grid barrier in the cooperative form).
-template <int NTH, bool GRID, int DMP = 0, typename T, typename RowAct, typename ColAct, typename Sync>
+template <int NTH, bool GRID, int DMP = 0, typename TG = float, typename T, typename RowAct, typename ColAct,
+          typename Sync>
 __device__ inline void op_apply(const View<T> &v, const T *__restrict__ rho_hat, const T *__restrict__ vin,
                                 T *__restrict__ t, T *__restrict__ out, int b0, int b1, RowAct row_act,
                                 ColAct col_act, Sync sync) {
@@ -375,7 +376,7 @@ __device__ inline void op_apply(const View<T> &v, const T *__restrict__ rho_hat,
   sync();
   if constexpr (!GRID && DMP > 0) {
     if (v.dense) {
-      dense_fused<NTH, DMP, T>(v, b0, rho_hat, vin, t);
+      dense_fused<NTH, DMP, T, TG>(v, b0, rho_hat, vin, t);
       sync();
     }
   }
@@ -392,7 +393,8 @@ __device__ inline void op_apply(const View<T> &v, const T *__restrict__ rho_hat,
 
 // r = rhs - M x with float64 accumulation (t64 holds rho_hat o (A x) in
 // float64); r is stored in the working precision.
-template <int NTH, bool GRID, int DMP = 0, typename T, typename RowAct, typename ColAct, typename Sync>
+template <int NTH, bool GRID, int DMP = 0, typename TG = float, typename T, typename RowAct, typename ColAct,
+          typename Sync>
 __device__ inline void op_residual64(const View<T> &v, const T *__restrict__ rho_hat, const double *__restrict__ rhs,
                                      const T *__restrict__ x, double *__restrict__ t64, T *__restrict__ r, int b0,
                                      int b1, RowAct row_act, ColAct col_act, Sync sync) {
@@ -404,7 +406,7 @@ __device__ inline void op_residual64(const View<T> &v, const T *__restrict__ rho
   sync();
   if constexpr (!GRID && DMP > 0) {
     if (v.dense) {
-      dense_fused<NTH, DMP, double>(v, b0, rho_hat, x, t64);
+      dense_fused<NTH, DMP, double, TG>(v, b0, rho_hat, x, t64);
       sync();
     }
   }
@@ -444,7 +446,7 @@ __device__ inline void finish(const View<T> &v, int b, bool fail, int it, int pa
 
 // ---- per-instance form -------------------------------------------------------------
 
-template <typename T, int DMP>
+template <typename T, int DMP, typename TG = T>
 __global__ __launch_bounds__((PTK<T, DMP>)) void k_pcg(View<T> v, const T *__restrict__ rho_hat, const T *__restrict__ dg,
                                             const double *__restrict__ rhs, T *__restrict__ x, T *__restrict__ r,
                                             T *__restrict__ z, T *__restrict__ p, T *__restrict__ Mp,
@@ -468,7 +470,7 @@ __global__ __launch_bounds__((PTK<T, DMP>)) void k_pcg(View<T> v, const T *__res
   double rrt = 0, rrt_prev = 0;
   for (int restart = 0;; ++restart) {
     // true residual, z = r / diag M, p = z
-    op_residual64<PTK<T, DMP>, false, DMP>(v, rho_hat, rhs, x, t64, r, b, b + 1, all, all, bar);
+    op_residual64<PTK<T, DMP>, false, DMP, TG>(v, rho_hat, rhs, x, t64, r, b, b + 1, all, all, bar);
     ++passes;
     T rz = 0, rr = 0;
     rrt = 0;
@@ -491,7 +493,7 @@ __global__ __launch_bounds__((PTK<T, DMP>)) void k_pcg(View<T> v, const T *__res
     // CG on the recursive residual
     while (rr > target && it < max_iter) {
       __syncthreads();   // p complete before the operator reads it
-      op_apply<PTK<T, DMP>, false, DMP>(v, rho_hat, p, t, Mp, b, b + 1, all, all, bar);
+      op_apply<PTK<T, DMP>, false, DMP, TG>(v, rho_hat, p, t, Mp, b, b + 1, all, all, bar);
       T pMp = 0, dummy = 0;
       for (int64_t j = n0 + threadIdx.x; j < n1; j += PTK<T, DMP>) pMp += p[j] * Mp[j];
       wg_sum2<PTK<T, DMP>>(pMp, dummy, red);
@@ -866,10 +868,9 @@ void launch_pcg(const View<T> &v, const T *rho_hat, const T *dg, const double *r
                                        xnew, gx_in, gx_out, mode, stats);
     return;
   }
-  // dense sub-blocks: the instantiation holding the widest block's pieces, and
-  // LDS for the waves' partials of G'w (float64 in the residual pass)
-  constexpr int VE = 16 / sizeof(T);
-  const int pieces = (v.dense_maxcols + 64 * VE - 1) / (64 * VE);
+  // dense sub-blocks: the instantiation for the blocks' stored type holding
+  // the widest block's pieces, and LDS for the waves' partials of G'w
+  // (float64 in the residual pass)
   const size_t lds = (size_t)(512 / 64) * v.dense_maxcols * sizeof(double);
   auto go = [&](auto kern) {
     static bool attr_set = false;   // more than the default 64 KiB of dynamic LDS may be needed
@@ -884,9 +885,16 @@ void launch_pcg(const View<T> &v, const T *rho_hat, const T *dg, const double *r
     kern<<<v.B, 512, lds, st>>>(v, rho_hat, dg, rhs, x, r, z, p, Mp, t, t64, (T)tol, max_iter, alpha_k, xold, xnew,
                                   gx_in, gx_out, mode, stats);
   };
-  if (pieces <= MAXPC<T> / 4) go(&k_pcg<T, MAXPC<T> / 4>);
-  else if (pieces <= MAXPC<T> / 2) go(&k_pcg<T, MAXPC<T> / 2>);
-  else go(&k_pcg<T, MAXPC<T>>);
+  auto pick = [&](auto tg) {
+    using TG = decltype(tg);
+    constexpr int VE = 16 / sizeof(TG);
+    const int pieces = (v.dense_maxcols + 64 * VE - 1) / (64 * VE);
+    if (pieces <= MAXPC<TG> / 4) go(&k_pcg<T, MAXPC<TG> / 4, TG>);
+    else if (pieces <= MAXPC<TG> / 2) go(&k_pcg<T, MAXPC<TG> / 2, TG>);
+    else go(&k_pcg<T, MAXPC<TG>, TG>);
+  };
+  if (sizeof(T) == 8 && v.dense_g32) pick(float{});
+  else pick(T{});
 }
 
 template void launch_pcg<float>(const View<float> &, const float *, const float *, const double *, float *, float *,

@@ -167,6 +167,14 @@ struct Acc2d {
   Mma<double>::v4 g, h;
 };
 
+// Refinement pair tag: the lowest mantissa bit of a stored E entry marks a
+// pair on one side of the positive / non-positive split that was rotated.
+__device__ inline float pair_tag(float e, bool rotated) {
+  const unsigned int u = __float_as_uint(e);
+  return __uint_as_float(rotated ? (u | 1u) : (u & ~1u));
+}
+__device__ inline bool pair_rotated(float e) { return (__float_as_uint(e) & 1u) != 0; }
+
 // mode 0: COSMO step on the block (s+ and y+ rows); mode 1: projection only.
 template <typename T, int NT, int G, int PMAX>
 __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ descs, int32_t max_sweeps, T tol_base,
@@ -183,11 +191,13 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
   __shared__ double redd[2 * (NT / 64)];
   __shared__ double lamd[PMAX];
   __shared__ short pos_idx[PMAX];
+  __shared__ short posof[PMAX];
   __shared__ signed char cls[PMAX];
   __shared__ int flags[3];
   __shared__ int bigf[3];
   __shared__ int npos_s;
   __shared__ int redo_s;
+  __shared__ int again_s;
 
   const PsdDesc d = descs[blockIdx.x];
   const int p = d.p;
@@ -491,42 +501,46 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
 
   if constexpr (std::is_same<T, float>::value) {
     if (refine > 0) {
-      // One refinement step of the float32 eigenpairs (after Ogita & Aishima,
+      // Refinement of the float32 eigenpairs (after Ogita & Aishima,
       // "Iterative refinement for symmetric eigenvalue decomposition", 2018)
       // with float64-accumulated residual products, then the projection by
-      // Rayleigh-Ritz on the positive subspace.  With X the Jacobi
-      // eigenvectors and lam~ the Jacobi eigenvalues:
+      // Rayleigh-Ritz on the positive subspace.  One step, with X the current
+      // eigenvectors and lam~ the current eigenvalues:
       //   D = S X - X diag(lam~)                       (small; stored in float32)
       //   R = I - X'X,  S~ = X'S X = (X'X) diag(lam~) + X'D,  lam_i = S~_ii / (1 - R_ii)
-      //   E_ij = (S~_ij + lam_j R_ij) / (lam_j - lam_i)  for pairs across the split
-      //          between positive and non-positive eigenvalues whose gap exceeds
-      //          delta = 2 (||S~ - diag(lam)||_F + ||S||_F ||R||_F) and whose
-      //          coupling th = cpl / gap leaves a second-order remainder
-      //          th^2 max|lam| below 1e-7 ||S||_F;  E_ij = R_ij / 2 otherwise
-      //   X <- X + X E
+      //   a pair (i, j) is resolvable when its gap exceeds
+      //          delta = 2 (||S~ - diag(lam)||_F + ||S||_F ||R||_F) and its
+      //          coupling-to-gap ratio th = cpl / gap is at most 0.1;
+      //   E_ij = (S~_ij + lam_j R_ij) / (lam_j - lam_i)  for rotated pairs,
+      //   E_ij = R_ij / 2 otherwise (re-orthogonalisation only)
+      //   X <- X + X E.
+      // Every resolvable pair is rotated, on either side of the split: the
+      // projection needs only the positive subspace, but the Daleckii-Krein
+      // weights of a pair across the split depend on the individual
+      // eigenvalues on each side, so the taped eigenvectors must be
+      // eigenvectors, not just a basis of the right subspace.  A step is the
+      // last when every resolvable pair's second-order remainder
+      // th^2 max|lam| is below 1e-7 ||S||_F (else another step follows: the
+      // remainders shrink quadratically), at most REFINE_STEPS steps.  In the
+      // last step only pairs that meet that bound rotate; the others are
+      // re-orthogonalised and the projection's middle factor absorbs their
+      // coupling:
       //   Pi = X+ M X+',  M = X+' S X+ to first order in E:
-      //          M_ii = lam_i,  M_ij = S~_ij + (lam_i + lam_j) R_ij / 2.
-      // The projection depends only on the positive subspace, so pairs on the
-      // same side of the split are only re-orthogonalised, and M absorbs
-      // their remaining coupling; E + E' = R entry by entry keeps X
-      // orthonormal to second order.  Only D and the products building S~ and
-      // R need float64 accumulation; the correction X E is small and runs in
-      // float32.
+      //          M_ii = lam_i,  M_ij = 0 for rotated pairs,
+      //          M_ij = S~_ij + (lam_i + lam_j) R_ij / 2 otherwise.
+      // E + E' = R entry by entry keeps X orthonormal to second order.  Only
+      // D and the products building S~ and R need float64 accumulation; the
+      // correction X E is small and runs in float32.
+      //
+      // Storage of a pair i < j in the p x p buffer SR: slot (j, i) holds
+      // E_ji.  Slot (i, j) holds E_ij when the pair rotates, else (pairs on
+      // one side of the split) M_ij; for pairs on one side the lowest
+      // mantissa bit of slot (j, i) says which (1: rotated, then M_ij = 0).
+      // One unit in the last place of E is far below what E corrects.
       constexpr bool INPL = PMAX <= 128;   // second p x p buffer in LDS, else global scratch
+      constexpr int REFINE_STEPS = 3;
       float *Db = INPL ? W + p * ld : reinterpret_cast<float *>(rscratch + 3 * (size_t)d.uoff);
       float *SR = INPL ? Db : Db + p * ld;   // S~ (upper) and R (lower), then E and M
-      float *Cb = Db;                        // X+ M
-      if constexpr (INPL) {
-        for (int idx = tid; idx < nrows; idx += NT) {
-          const int j = svec_col(idx);
-          const int i = idx - j * (j + 1) / 2;
-          float val = v[idx];
-          if (i != j) val *= (float)RSQRT2;
-          Db[i + j * ld] = val;
-          Db[j + i * ld] = val;
-        }
-        __syncthreads();
-      }
       auto Sget = [&](int i, int k) -> double {
         if constexpr (INPL) {
           return (double)Db[i + k * ld];
@@ -536,128 +550,220 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
           return a == b ? val : val * RSQRT2;
         }
       };
-      // D = S X - X diag(lam~)
-      tile_pass<HOLD, INPL>(
-          nt * nt, wave, NWv,
-          [&](int t) {
-            const int I = t / nt, J = t % nt;
-            return tile_mma<double>(
-                I * 16, J * 16, p, [&](int i, int k) -> double { return (i < p && k < p) ? Sget(i, k) : 0.0; },
-                [&](int k, int j) -> double { return (k < p && j < p) ? (double)W[k + j * ld] : 0.0; });
-          },
-          [&](int t, const Mma<double>::v4 &acc) {
-            const int I = t / nt, J = t % nt;
-            const int col = J * 16 + (lane & 15);
+      const double thr2 = 1e-7 * sqrt((double)fro2);
+      // This block's part of the refinement scratch (3 p^2 doubles) beyond
+      // the redo flag (orders up to 128) or beyond D, S~ and R (larger
+      // orders): the refined eigenvalues of a step (float64), then L+ and C
+      // of the projection (below).
+      double *xs = rscratch + 3 * (size_t)d.uoff + (INPL ? 1 : (size_t)p * ld);
+      // E_kj from the pair storage (see above)
+      auto Eget = [&](int k, int j) -> float {
+        if (k >= j || cls[k] * cls[j] < 0) return SR[k + j * ld];
+        const float low = SR[j + k * ld];
+        return pair_rotated(low) ? SR[k + j * ld] : low;
+      };
+      const int wave_o = wave, lane_o = lane;
+      int rsteps = 0;
+#pragma nounroll
+      for (int rstep = 0; rstep < REFINE_STEPS; ++rstep) {
+        // The wave and lane numbers are re-read opaquely in every step so
+        // that the compiler does not hoist each tile's addresses out of the
+        // loop (which exhausts the registers).
+        int wave = wave_o, lane = lane_o;
+        asm volatile("" : "+v"(wave), "+v"(lane));
+        const bool last_allowed = rstep == REFINE_STEPS - 1;
+        if constexpr (INPL) {   // S into the second buffer (the D pass overwrites it in place)
+          for (int idx = tid; idx < nrows; idx += NT) {
+            const int j = svec_col(idx);
+            const int i = idx - j * (j + 1) / 2;
+            float val = v[idx];
+            if (i != j) val *= (float)RSQRT2;
+            Db[i + j * ld] = val;
+            Db[j + i * ld] = val;
+          }
+          __syncthreads();
+        }
+        // D = S X - X diag(lam~)
+        tile_pass<HOLD, INPL>(
+            nt * nt, wave, NWv,
+            [&](int t) {
+              const int I = t / nt, J = t % nt;
+              return tile_mma<double>(
+                  I * 16, J * 16, p, [&](int i, int k) -> double { return (i < p && k < p) ? Sget(i, k) : 0.0; },
+                  [&](int k, int j) -> double { return (k < p && j < p) ? (double)W[k + j * ld] : 0.0; });
+            },
+            [&](int t, const Mma<double>::v4 &acc) {
+              const int I = t / nt, J = t % nt;
+              const int col = J * 16 + (lane & 15);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const int row = I * 16 + Mma<double>::row(lane, e);
-              if (row < p && col < p) Db[row + col * ld] = (float)(acc[e] - (double)W[row + col * ld] * lamd[col]);
-            }
-          });
-      // S~ into the upper triangle, R into the lower, lam_i on the diagonal
-      double nS = 0, nR = 0;
-      tile_pass<HOLDU, INPL>(
-          ntiles, wave, NWv,
-          [&](int t) {
-            int I, J;
-            upper_tile(t, I, J);
-            Acc2d a;
-            tile_mma2<double>(
-                I * 16, J * 16, p, [&](int i, int k) -> double { return (i < p && k < p) ? (double)W[k + i * ld] : 0.0; },
-                [&](int k, int j) -> double { return (k < p && j < p) ? (double)W[k + j * ld] : 0.0; },
-                [&](int k, int j) -> double { return (k < p && j < p) ? (double)Db[k + j * ld] : 0.0; }, a.g, a.h);
-            return a;
-          },
-          [&](int t, const Acc2d &a) {
-            int I, J;
-            upper_tile(t, I, J);
-            const int col = J * 16 + (lane & 15);
+              for (int e = 0; e < 4; ++e) {
+                const int row = I * 16 + Mma<double>::row(lane, e);
+                if (row < p && col < p) Db[row + col * ld] = (float)(acc[e] - (double)W[row + col * ld] * lamd[col]);
+              }
+            });
+        // S~ into the upper triangle, R into the lower, lam_i on the diagonal
+        double nS = 0, nR = 0;
+        tile_pass<HOLDU, INPL>(
+            ntiles, wave, NWv,
+            [&](int t) {
+              int I, J;
+              upper_tile(t, I, J);
+              Acc2d a;
+              tile_mma2<double>(
+                  I * 16, J * 16, p,
+                  [&](int i, int k) -> double { return (i < p && k < p) ? (double)W[k + i * ld] : 0.0; },
+                  [&](int k, int j) -> double { return (k < p && j < p) ? (double)W[k + j * ld] : 0.0; },
+                  [&](int k, int j) -> double { return (k < p && j < p) ? (double)Db[k + j * ld] : 0.0; }, a.g, a.h);
+              return a;
+            },
+            [&](int t, const Acc2d &a) {
+              int I, J;
+              upper_tile(t, I, J);
+              const int col = J * 16 + (lane & 15);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const int row = I * 16 + Mma<double>::row(lane, e);
-              if (row <= col && col < p) {
-                const double st = a.h[e] + a.g[e] * lamd[col];
-                if (row < col) {
-                  const double r = -a.g[e];
-                  SR[row + col * ld] = (float)st;
-                  SR[col + row * ld] = (float)r;
-                  nS += 2.0 * st * st;
-                  nR += 2.0 * r * r;
-                } else {
-                  const double lam = a.g[e] > 0.0 ? st / a.g[e] : 0.0;
-                  const double r = 1.0 - a.g[e];
-                  SR[row + row * ld] = (float)lam;
-                  nS += (st - lam) * (st - lam);
-                  nR += r * r;
+              for (int e = 0; e < 4; ++e) {
+                const int row = I * 16 + Mma<double>::row(lane, e);
+                if (row <= col && col < p) {
+                  const double st = a.h[e] + a.g[e] * lamd[col];
+                  if (row < col) {
+                    const double r = -a.g[e];
+                    SR[row + col * ld] = (float)st;
+                    SR[col + row * ld] = (float)r;
+                    nS += 2.0 * st * st;
+                    nR += 2.0 * r * r;
+                  } else {
+                    const double lam = a.g[e] > 0.0 ? st / a.g[e] : 0.0;
+                    const double r = 1.0 - a.g[e];
+                    xs[row] = lam;   // kept in float64
+                    nS += (st - lam) * (st - lam);
+                    nR += r * r;
+                  }
                 }
               }
-            }
-          });
-      for (int off = 32; off > 0; off >>= 1) {
-        nS += __shfl_xor(nS, off, 64);
-        nR += __shfl_xor(nR, off, 64);
-      }
-      if (lane == 0) {
-        redd[wave] = nS;
-        redd[NWv + wave] = nR;
-      }
-      // refined eigenvalues, their signs, and E_ii = R_ii / 2 on the diagonal
-      for (int i = tid; i < p; i += NT) {
-        const double lam = (double)SR[i + i * ld];
-        double g = 0;
-        for (int k = 0; k < p; ++k) {
-          const double x = (double)W[k + i * ld];
-          g += x * x;
+            });
+        for (int off = 32; off > 0; off >>= 1) {
+          nS += __shfl_xor(nS, off, 64);
+          nR += __shfl_xor(nR, off, 64);
         }
-        lamd[i] = lam;
-        cls[i] = lam > 0.0 ? 1 : (lam < 0.0 ? -1 : 0);
-        SR[i + i * ld] = (float)(0.5 * (1.0 - g));
-      }
-      __syncthreads();
-      double ts = 0, tr = 0;
-      for (int w = 0; w < NWv; ++w) {
-        ts += redd[w];
-        tr += redd[NWv + w];
-      }
-      const double delta = 2.0 * (sqrt(ts) + sqrt((double)fro2) * sqrt(tr));
-      // off-diagonal pairs i < j: across the split, E_ij into (i, j) and E_ji
-      // into (j, i); on one side, M_ij into (i, j) and E_ij = E_ji into (j, i)
-      for (int e = tid; e < p * p; e += NT) {
-        const int j = e / p, i = e - j * p;
-        if (i >= j) continue;
-        const double s = (double)SR[i + j * ld], r = (double)SR[j + i * ld];
-        const double li = lamd[i], lj = lamd[j];
-        if (li * lj < 0.0) {
-          const double gap = lj - li;
-          const double cpl = fabs(s) + fmax(fabs(li), fabs(lj)) * fabs(r);
-          // first-order rotation when its second-order remainder, th^2
-          // max(|l_i|, |l_j|) with th = cpl / gap, is below 1e-7 ||S||_F
-          const double th = cpl / fabs(gap);
-          const bool rot = fabs(gap) > delta && th <= 0.1 &&
-                           th * th * fmax(fabs(li), fabs(lj)) <= 1e-7 * sqrt((double)fro2);
-          if (!rot && fabs(gap) > delta && stop2 > (T)0) redo_s = 1;   // resolvable, but not to first order
-          SR[i + j * ld] = (float)(rot ? (s + lj * r) / gap : 0.5 * r);
-          SR[j + i * ld] = (float)(rot ? (s + li * r) / (-gap) : 0.5 * r);
-        } else {
-          SR[i + j * ld] = (float)(s + 0.5 * (li + lj) * r);
-          SR[j + i * ld] = (float)(0.5 * r);
+        if (lane == 0) {
+          redd[wave] = nS;
+          redd[NWv + wave] = nR;
         }
-      }
-      __syncthreads();
-      if (redo_s) {   // read after the barrier above: the same in every thread
-        if (Uout)
-          for (int e = tid; e < p * p; e += NT) {
-            const int j = e / p, i = e - j * p;
-            Uout[d.uoff + e] = W[i + j * ld];
+        if (tid == 0) again_s = 0;
+        // refined eigenvalues, their signs, and E_ii = R_ii / 2 on the diagonal
+        for (int i = tid; i < p; i += NT) {
+          const double lam = xs[i];
+          double g = 0;
+          for (int k = 0; k < p; ++k) {
+            const double x = (double)W[k + i * ld];
+            g += x * x;
           }
-        if (tid == 0) *redo_g = 1;
-        return;
+          lamd[i] = lam;
+          cls[i] = lam > 0.0 ? 1 : (lam < 0.0 ? -1 : 0);
+          SR[i + i * ld] = (float)(0.5 * (1.0 - g));
+        }
+        __syncthreads();
+        double ts = 0, tr = 0;
+        for (int w = 0; w < NWv; ++w) {
+          ts += redd[w];
+          tr += redd[NWv + w];
+        }
+        const double delta = 2.0 * (sqrt(ts) + sqrt((double)fro2) * sqrt(tr));
+        // Pairs i < j: which rotate in this step if it is not the last, and
+        // whether any of them leaves a remainder above the bound (then this
+        // step is not the last).
+        int more = 0;
+        for (int e = tid; e < p * p; e += NT) {
+          const int j = e / p, i = e - j * p;
+          if (i >= j) continue;
+          const double s = (double)SR[i + j * ld], r = (double)SR[j + i * ld];
+          const double li = lamd[i], lj = lamd[j];
+          const double gap = lj - li;
+          const double th = (fabs(s) + fmax(fabs(li), fabs(lj)) * fabs(r)) / fabs(gap);
+          if (fabs(gap) > delta && th <= 0.1 && th * th * fmax(fabs(li), fabs(lj)) > thr2) more = 1;
+        }
+        if (more) again_s = 1;
+        __syncthreads();
+        const bool last = last_allowed || again_s == 0;
+        for (int e = tid; e < p * p; e += NT) {
+          const int j = e / p, i = e - j * p;
+          if (i >= j) continue;
+          const double s = (double)SR[i + j * ld], r = (double)SR[j + i * ld];
+          const double li = lamd[i], lj = lamd[j];
+          const double gap = lj - li;
+          const double th = (fabs(s) + fmax(fabs(li), fabs(lj)) * fabs(r)) / fabs(gap);
+          const bool ok = fabs(gap) > delta && th <= 0.1;
+          const bool fin = th * th * fmax(fabs(li), fabs(lj)) <= thr2;
+          const bool rot = ok && (fin || !last);
+          const float eij = (float)(rot ? (s + lj * r) / gap : 0.5 * r);
+          const float eji = (float)(rot ? (s + li * r) / (-gap) : 0.5 * r);
+          if (li * lj < 0.0) {
+            if (last && ok && !fin && stop2 > (T)0) redo_s = 1;   // resolvable, but not to first order
+            SR[i + j * ld] = eij;
+            SR[j + i * ld] = eji;
+          } else {
+            SR[i + j * ld] = rot ? eij : (float)(s + 0.5 * (li + lj) * r);
+            SR[j + i * ld] = pair_tag(eji, rot);
+          }
+        }
+        __syncthreads();
+        if (last && redo_s) {   // read after the barrier above: the same in every thread
+          if (Uout)
+            for (int e = tid; e < p * p; e += NT) {
+              const int j = e / p, i = e - j * p;
+              Uout[d.uoff + e] = W[i + j * ld];
+            }
+          if (tid == 0) *redo_g = 1;
+          return;
+        }
+        rsteps = rstep + 1;
+        if (last) break;
+        // X <- X + X E, in place in W (the last step's correction is kept apart, below)
+        tile_pass<HOLD, true>(
+            nt * nt, wave, NWv,
+            [&](int t) {
+              const int I = t / nt, J = t % nt;
+              return tile_mma<float>(
+                  I * 16, J * 16, p, [&](int i, int k) -> float { return (i < p && k < p) ? W[i + k * ld] : 0.f; },
+                  [&](int k, int j) -> float { return (k < p && j < p) ? Eget(k, j) : 0.f; });
+            },
+            [&](int t, const Mma<float>::v4 &acc) {
+              const int I = t / nt, J = t % nt;
+              const int col = J * 16 + (lane & 15);
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const int row = I * 16 + Mma<float>::row(lane, e);
+                if (row < p && col < p) W[row + col * ld] += acc[e];
+              }
+            });
       }
-      // X <- X + X E, in place in W
-      auto Eget = [&](int k, int j) -> float {
-        return (k >= j || cls[k] * cls[j] < 0) ? SR[k + j * ld] : SR[j + k * ld];
-      };
-      tile_pass<HOLD, true>(
+      if (stats && tid == 0) atomicAdd(&stats[d.inst].eig_refine_steps_total, rsteps);
+      if (lamout)
+        for (int i = tid; i < p; i += NT) lamout[d.loff + i] = (float)lamd[i];
+      if (tid == 0) {
+        int np = 0;
+        for (int i = 0; i < p; ++i) {
+          posof[i] = cls[i] > 0 ? (short)np : (short)-1;
+          if (cls[i] > 0) pos_idx[np++] = (short)i;
+        }
+        npos_s = np;
+        count();
+      }
+      __syncthreads();
+      const int npos = npos_s;
+      const int ntp = (npos + 15) / 16;
+      // The last step's correction L = X E is not rounded into X: the
+      // refined eigenvectors are X + L with both parts float32 (their sum is
+      // carried to about twice the float32 precision), and the projection is
+      // formed from them with float64 products,
+      //   C = (X+ + L+) M,   Pi = C (X+ + L+)',
+      // so its accuracy is that of the refinement, not that of float32
+      // eigenvectors.  The taped eigenvectors are X + L rounded to float32.
+      // L+ (p x npos, float32) and C (p x npos, float64) live in this
+      // block's part of the refinement scratch (xs).
+      float *Lg = reinterpret_cast<float *>(xs);
+      double *Cg = xs + ((size_t)p * npos + 1) / 2;
+      tile_pass<HOLD, false>(
           nt * nt, wave, NWv,
           [&](int t) {
             const int I = t / nt, J = t % nt;
@@ -671,61 +777,50 @@ __global__ __launch_bounds__(NT) void k_psd_eig(const PsdDesc *__restrict__ desc
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
               const int row = I * 16 + Mma<float>::row(lane, e);
-              if (row < p && col < p) W[row + col * ld] += acc[e];
+              if (row < p && col < p) {
+                if (Uout) Uout[d.uoff + row + col * p] = W[row + col * ld] + acc[e];
+                const int q = posof[col];
+                if (q >= 0) Lg[row + q * p] = acc[e];
+              }
             }
           });
-      if (lamout)
-        for (int i = tid; i < p; i += NT) lamout[d.loff + i] = (float)lamd[i];
-      if (Uout)
-        for (int e = tid; e < p * p; e += NT) {
-          const int j = e / p, i = e - j * p;
-          Uout[d.uoff + e] = W[i + j * ld];
-        }
-      if (tid == 0) {
-        int np = 0;
-        for (int i = 0; i < p; ++i)
-          if (cls[i] > 0) pos_idx[np++] = (short)i;
-        npos_s = np;
-        count();
-      }
-      __syncthreads();
-      const int npos = npos_s;
-      const int ntp = (npos + 15) / 16;
-      // C = X+ M  (p x npos)
-      auto Mget = [&](int a, int b) -> float {
-        if (a == b) return (float)lamd[a];
-        return a < b ? SR[a + b * ld] : SR[b + a * ld];
+      // M on the positive pairs: lam_i (float64) on the diagonal
+      auto Mget = [&](int a, int b) -> double {
+        if (a == b) return lamd[a];
+        const int lo = a < b ? a : b, hi = a < b ? b : a;
+        return pair_rotated(SR[hi + lo * ld]) ? 0.0 : (double)SR[lo + hi * ld];
       };
-      tile_pass<HOLD, INPL>(
+      auto Xp = [&](int i, int k) -> double { return (double)W[i + pos_idx[k] * ld] + (double)Lg[i + k * p]; };
+      // C = (X+ + L+) M  (p x npos)
+      tile_pass<HOLD, false>(
           nt * ntp, wave, NWv,
           [&](int t) {
             const int I = t / ntp, J = t % ntp;
-            return tile_mma<float>(
-                I * 16, J * 16, npos,
-                [&](int i, int k) -> float { return (i < p && k < npos) ? W[i + pos_idx[k] * ld] : 0.f; },
-                [&](int k, int j) -> float { return (k < npos && j < npos) ? Mget(pos_idx[k], pos_idx[j]) : 0.f; });
+            return tile_mma<double>(
+                I * 16, J * 16, npos, [&](int i, int k) -> double { return (i < p && k < npos) ? Xp(i, k) : 0.0; },
+                [&](int k, int j) -> double { return (k < npos && j < npos) ? Mget(pos_idx[k], pos_idx[j]) : 0.0; });
           },
-          [&](int t, const Mma<float>::v4 &acc) {
+          [&](int t, const Mma<double>::v4 &acc) {
             const int I = t / ntp, J = t % ntp;
             const int col = J * 16 + (lane & 15);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-              const int row = I * 16 + Mma<float>::row(lane, e);
-              if (row < p && col < npos) Cb[row + col * ld] = acc[e];
+              const int row = I * 16 + Mma<double>::row(lane, e);
+              if (row < p && col < npos) Cg[row + col * p] = acc[e];
             }
           });
-      // Pi = C X+', upper-triangle tiles
+      // Pi = C (X+ + L+)', upper-triangle tiles
       for (int t = wave; t < ntiles; t += NWv) {
         int I, J;
         upper_tile(t, I, J);
-        const Mma<float>::v4 acc = tile_mma<float>(
-            I * 16, J * 16, npos, [&](int i, int k) -> float { return (i < p && k < npos) ? Cb[i + k * ld] : 0.f; },
-            [&](int k, int j) -> float { return (j < p && k < npos) ? W[j + pos_idx[k] * ld] : 0.f; });
+        const Mma<double>::v4 acc = tile_mma<double>(
+            I * 16, J * 16, npos, [&](int i, int k) -> double { return (i < p && k < npos) ? Cg[i + k * p] : 0.0; },
+            [&](int k, int j) -> double { return (j < p && k < npos) ? Xp(j, k) : 0.0; });
         const int col = J * 16 + (lane & 15);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int row = I * 16 + Mma<float>::row(lane, e);
-          if (row <= col && col < p) put(row, col, (double)acc[e]);
+          const int row = I * 16 + Mma<double>::row(lane, e);
+          if (row <= col && col < p) put(row, col, acc[e]);
         }
       }
       return;

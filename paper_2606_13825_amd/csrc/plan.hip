@@ -99,6 +99,7 @@ struct cosmo_plan {
   int64_t sum_p = 0, sum_p2 = 0, sum_p2_large = 0;
   // dense sub-blocks of A (descriptors ordered by instance)
   int32_t n_dense = 0, dense_maxcols = 0, dense_wg_rows = 0, dense_wg_cols = 0;
+  bool dense_g32 = false;   // the blocks' values are stored as float32
   int64_t dense_rows_tot = 0, dense_cols_tot = 0;
   DenseDesc *d_dense = nullptr;
   int32_t *d_dense_inst = nullptr, *d_drow = nullptr, *d_dcol = nullptr;
@@ -196,6 +197,7 @@ template <typename T> View<T> make_view(const cosmo_plan *pl) {
   v.dense_maxcols = pl->dense_maxcols;
   v.dense_wg_rows = pl->dense_wg_rows;
   v.dense_wg_cols = pl->dense_wg_cols;
+  v.dense_g32 = pl->dense_g32 ? 1 : 0;
   v.dn = v.ec = v.ed = nullptr;   // set per call from the call's workspace
   return v;
 }
@@ -293,14 +295,16 @@ cosmo_status validate_problem_host(const cosmo_problem *p, const cosmo_options *
   for (int k = 0; k < p->n_dense; ++k) {
     const cosmo_dense_block &d = p->dense[k];
     const std::string at = " (dense block " + std::to_string(k) + ")";
+    if (d.val_f32 != 0 && d.val_f32 != 1) FAIL(COSMO_EINVAL, "dense val_f32 must be 0 or 1" + at);
+    if (d.val_f32 != p->dense[0].val_f32) FAIL(COSMO_EINVAL, "dense val_f32 differs between blocks" + at);
+    const size_t gsz = d.val_f32 ? 4 : esz;   // bytes per stored value
     if (!d.val) FAIL(COSMO_EINVAL, "dense values are NULL" + at);
     if (reinterpret_cast<uintptr_t>(d.val) % 16 != 0) FAIL(COSMO_EINVAL, "dense values must be 16-byte aligned" + at);
     if (d.rows < 1 || d.cols < 1) FAIL(COSMO_EINVAL, "dense block needs rows, cols >= 1" + at);
     if (d.cols > COSMO_DENSE_MAX_COLS) FAIL(COSMO_EINVAL, "dense block wider than COSMO_DENSE_MAX_COLS" + at);
-    if (d.ld < d.cols || d.ld % (int64_t)(16 / esz) != 0)
-      FAIL(COSMO_EINVAL, "dense ld must be >= cols and a multiple of 16 / sizeof(dtype)" + at);
+    if (d.ld < d.cols || d.ld % (int64_t)(16 / gsz) != 0)
+      FAIL(COSMO_EINVAL, "dense ld must be >= cols and a multiple of 16 / (bytes per stored value)" + at);
     if (d.n_place < 1 || d.n_place > COSMO_DENSE_MAX_PLACEMENTS) FAIL(COSMO_EINVAL, "dense n_place out of range" + at);
-    if (d.reserved != 0) FAIL(COSMO_EINVAL, "dense reserved field must be 0" + at);
     if (d.col0 < 0 || d.col0 + d.cols > n_tot) FAIL(COSMO_EINVAL, "dense columns outside A" + at);
     const int ci = inst_of(p->n_off, d.col0);
     if (d.col0 + d.cols > p->n_off[ci + 1]) FAIL(COSMO_EINVAL, "dense columns straddle instances" + at);
@@ -470,6 +474,7 @@ cosmo_status build_plan(cosmo_plan *pl, const cosmo_problem *p) {
   std::vector<int32_t> dinst(pl->B + 1, 0), drow, dcolm;
   std::vector<double> dscale;
   if (p->n_dense > 0) {
+    pl->dense_g32 = p->dense[0].val_f32 != 0 || sizeof(T) == 4;
     drow.assign(m, -1);
     dscale.assign(m, 0.0);
     dcolm.assign(n, -1);
@@ -507,7 +512,7 @@ cosmo_status build_plan(cosmo_plan *pl, const cosmo_problem *p) {
       doff += d.rows;
       coff += d.cols;
       wr += dense_row_workgroups(d.rows);
-      wc += dense_col_workgroups(d.cols, sizeof(T));
+      wc += dense_col_workgroups(d.cols, pl->dense_g32 ? 4 : sizeof(T));
       pl->dense_maxcols = std::max(pl->dense_maxcols, d.cols);
       dinst[d.inst + 1]++;
     }

@@ -76,3 +76,77 @@ def one_step_err(inst, z, z_next, rho_k, alpha_k, fl, tol=1e-5):
         n_floor += f > np.linalg.norm(r)
         worst = max(worst, assert_close(g, r, tol, f, nm))
     return worst, n_floor
+
+
+# ---- float32 bars from measured floors ------------------------------------
+#
+# A float32 pipeline stores every per-step value in float32 and stops its
+# solves at a float32 residual.  How far that alone moves a K-step
+# trajectory and its gradients depends on the instance (some families
+# amplify it a thousandfold: their iterates shrink by orders of magnitude
+# while the rounding of the early, large ones stays), so each checked
+# instance gets its floor measured by the oracle's rounding model
+# (unroll_forward with store_dtype): the largest error, against the exact
+# float64 run, of three realisations -- values rounded to nearest with exact
+# solves, and two with every stored value moved by up to one unit in the last
+# place and solves stopped at the run's CG residual.  The bar is the
+# contract's (1e-5 iterates, 1e-4 gradients) or FLOOR_FACTOR times that
+# floor, whichever is larger.
+FLOOR_FACTOR = 2.0
+FLOAT32_CG_RESID = 1e-7   # where a float32 CG's true residual stops, at the smallest
+
+
+def fp32_floor(inst, rho_k_m, alpha_k, ref, x0=None, s0=None, y0=None, with_grad=True, cg_tol=0.0, runs=None):
+    """(iterate floor, gradient floor) of one instance against its float64 run
+    `ref` (oracle_run's output), per array, the largest over the model's
+    realisations (oracle.rounding_floor_runs); cg_tol = 0: the pipeline's
+    solves are exact (diagonal M).  runs: a list that receives each
+    realisation's final (x, s, y)."""
+    resid = max(cg_tol, FLOAT32_CG_RESID) if cg_tol > 0 else 0.0
+    fl = floor_of(inst)
+    e_it = e_g = 0.0
+    for x, s, y, grho, galpha in oracle.rounding_floor_runs(inst, rho_k_m, alpha_k, x0, s0, y0,
+                                                            backward=with_grad, solve_resid=resid):
+        if runs is not None:
+            runs.append((x, s, y))
+        e_it = max([e_it] + [rel_err(a, ref[k], fl) for a, k in ((x, "x"), (s, "s"), (y, "y"))])
+        if with_grad:
+            e_g = max(e_g, rel_err(grho, ref["grho"]), rel_err(galpha, ref["galpha"]))
+    return e_it, e_g
+
+
+def floor_bars(inst, rho_k_m, alpha_k, ref, tol_it=1e-5, tol_g=1e-4, **kw):
+    """(iterate bar, gradient bar, (iterate floor, gradient floor)); kw as
+    fp32_floor's."""
+    f_it, f_g = fp32_floor(inst, rho_k_m, alpha_k, ref, **kw)
+    return max(tol_it, FLOOR_FACTOR * f_it), max(tol_g, FLOOR_FACTOR * f_g), (f_it, f_g)
+
+
+def _row_blocks(inst):
+    """Row ranges of the cone blocks (zero and nonnegative rows one block each)."""
+    out, r = [], 0
+    for c in inst.cones:
+        n = c.size * (c.size + 1) // 2 if c.kind == "psd" else c.size
+        out.append((r, r + n))
+        r += n
+    return out
+
+
+def assert_blocks_close(gpu, ref, inst, tol, what, rel_floor=1e-3, floor=0.0, floor_runs=()):
+    """Per cone block: ||gpu - ref||_blk <= bar max(||ref||_blk, rel_floor
+    ||ref||, floor), so one wrong block among hundreds is not diluted by the
+    others (a block with a negligible share of the array is measured against
+    rel_floor of the whole).  bar: tol, or FLOOR_FACTOR times the same block's
+    error in the floor realisations `floor_runs` (arrays like ref), whichever
+    is larger."""
+    gpu = np.asarray(gpu, np.float64)
+    ref = np.asarray(ref, np.float64)
+    whole = np.linalg.norm(ref)
+    worst = 0.0
+    for a, b in _row_blocks(inst):
+        den = max(np.linalg.norm(ref[a:b]), rel_floor * whole, floor, 1e-300)
+        bar = max([tol] + [FLOOR_FACTOR * np.linalg.norm(np.asarray(f)[a:b] - ref[a:b]) / den for f in floor_runs])
+        e = np.linalg.norm(gpu[a:b] - ref[a:b]) / den
+        assert e <= bar, f"{what}: rows {a}:{b} relative error {e:.3e} > {bar:.1e}"
+        worst = max(worst, e)
+    return worst

@@ -207,7 +207,7 @@ def test_struct_layouts_match_the_c_compiler(L, tmp_path):
 
 def _dense_block(L, **kw):
     d = L.CosmoDenseBlock()
-    d.val, d.rows, d.cols, d.ld, d.col0, d.n_place, d.reserved = 256, 2, 2, 4, 0, 1, 0
+    d.val, d.rows, d.cols, d.ld, d.col0, d.n_place, d.val_f32 = 256, 2, 2, 4, 0, 1, 0
     d.row0[0], d.scale[0] = 0, 1.0
     for k, v in kw.items():
         if k in ("row0", "scale"):
@@ -228,7 +228,8 @@ def _dense_block(L, **kw):
     [dict(ld=6)],                                    # not a multiple of 16 bytes (float32)
     [dict(n_place=0)],
     [dict(n_place=5)],
-    [dict(reserved=1)],
+    [dict(val_f32=2)],
+    [dict(), dict(row0=[2], col0=2, val_f32=1)],     # stored types differ between blocks
     [dict(scale=[float("nan")])],
     [dict(col0=3)],                                  # columns outside A (n_tot = 4)
     [dict(row0=[3])],                                # rows outside A (m_tot = 4)

@@ -7,7 +7,8 @@ batch passed as CSR alone.
 Cases: uneven batches mixing instances with and without a dense block;
 widths that are not a multiple of the 16-byte piece nor of the 64-lane strip
 (ragged tails); row counts not a multiple of a workgroup's rows; one, two and
-three placements with scales other than +-1; float64 and float32."""
+three placements with scales other than +-1; float64 and float32; float32
+storage of the blocks in a float64 batch."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -68,10 +69,11 @@ def _batch(dtype):
     return [x.astype(dtype) for x in insts]
 
 
-def _run(insts, K, dtype, rhos, alphas, dense, cg_tol):
+def _run(insts, K, dtype, rhos, alphas, dense, cg_tol, dense_f32=False):
     from paper_2606_13825_amd import CosmoBatch
     tdt = torch.float32 if dtype == np.float32 else torch.float64
-    batch = CosmoBatch(insts, K=K, dtype=tdt, device=DEV, cg_tol=cg_tol, cg_max_iter=2000, dense=dense)
+    batch = CosmoBatch(insts, K=K, dtype=tdt, device=DEV, cg_tol=cg_tol, cg_max_iter=2000, dense=dense,
+                       dense_f32=dense_f32)
     rho = torch.from_numpy(np.concatenate(rhos, axis=1)).to(DEV)
     alpha = torch.from_numpy(np.stack(alphas, axis=1)).to(DEV)
     stats = batch.new_stats()
@@ -122,6 +124,41 @@ def test_dense_blocks_every_iterate_and_gradients(dtype, tol_it, tol_g, cg_tol):
                            ("grad y0", bw.gy0[sl_m], ref["gy0"])):
             worst_g = max(worst_g, assert_close(g_.double().cpu().numpy(), r_, tol_g, 0.0, f"inst {i} {nm}"))
     say(f"  worst iterate error {worst_it:.2e}, worst gradient error {worst_g:.2e}")
+
+
+def test_float32_stored_blocks_in_a_float64_batch():
+    """Data that are float32 numbers (generated in float64, rounded), a
+    float64 batch whose dense blocks are stored as float32: every iterate
+    and gradient at the float64 bars, and the same as the all-float64 CSR
+    path up to the order of the sums.  Blocks whose values are not float32
+    numbers are refused by the binding."""
+    ensure_lib()
+    from paper_2606_13825_amd import CosmoBatch
+    insts = [x.astype(np.float32).astype(np.float64) for x in _batch(np.float64)]
+    K = 4
+    rhos, alphas = _hyper(insts, K, np.float64, seed=8)
+    say(f"float32-stored dense blocks in a float64 batch: B={len(insts)} K={K}")
+    b1, f1, l1, g1 = _run(insts, K, np.float64, rhos, alphas, True, 1e-13, dense_f32=True)
+    b2, f2, l2, g2 = _run(insts, K, np.float64, rhos, alphas, False, 1e-13)
+    assert b1.n_dense == 4 and b1.dense_val.dtype == torch.float32
+    for a, b in ((f1.x, f2.x), (f1.s, f2.s), (f1.y, f2.y), (l1, l2), (g1.grho, g2.grho), (g1.galpha, g2.galpha),
+                 (g1.gx0, g2.gx0), (g1.gs0, g2.gs0), (g1.gy0, g2.gy0)):
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        assert np.linalg.norm(a - b) <= 1e-10 * max(np.linalg.norm(b), 1e-30)
+    worst = 0.0
+    for i, inst in enumerate(insts):
+        ref = oracle_run(inst, rhos[i], alphas[i])
+        fl = floor_of(inst)
+        sl_n = slice(b1.n_off[i], b1.n_off[i + 1])
+        sl_m = slice(b1.m_off[i], b1.m_off[i + 1])
+        for nm, g_, r_, tol, f in (("x", f1.x[sl_n], ref["x"], 1e-9, fl), ("s", f1.s[sl_m], ref["s"], 1e-9, fl),
+                                   ("y", f1.y[sl_m], ref["y"], 1e-9, fl),
+                                   ("grad rho", g1.grho[:, sl_m], ref["grho"], 1e-8, 0.0),
+                                   ("grad alpha", g1.galpha[:, i], ref["galpha"], 1e-8, 0.0)):
+            worst = max(worst, assert_close(g_.cpu().numpy(), r_, tol, f, f"inst {i} {nm}"))
+    say(f"  worst error against the oracle {worst:.2e}")
+    with pytest.raises(ValueError):
+        CosmoBatch(_batch(np.float64), K=1, dtype=torch.float64, device=DEV, dense_f32=True)
 
 
 def test_dense_path_equals_csr_path_fp64():

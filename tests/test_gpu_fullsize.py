@@ -9,13 +9,16 @@ sampled outputs the float64 oracle can compute one by one:
 
   * c5 (128 covariance-steering SDPs, K = 30): whole trajectories and
     gradients of two sampled instances (the largest, and the first);
-  * c3 (32 Lovasz SDPs, K = 50) and c4 (256 Huber SOCPs, K = 40), whose full
-    oracle runs take minutes per instance: one-step parity of the forward at
-    sampled steps (the oracle started from the GPU's own iterate), and the
-    gradients of the last steps, reverse mode in the oracle from the GPU's
-    own iterates and loss seeds (those gradients depend on nothing earlier),
-    both at the GPU's own taped solves and against exact solves with a floor
-    for the float32 rounding of the stored steps.
+  * c4 (256 Huber SOCPs, K = 40, float64 iterations with the design block
+    stored as float32): whole trajectories and gradients of two sampled
+    instances, and one-step parity at sampled steps;
+  * c3 (32 Lovasz SDPs, K = 50), whose full oracle runs take minutes per
+    instance: one-step parity of the forward at sampled steps (the oracle
+    started from the GPU's own iterate), and the gradients of the last
+    steps, reverse mode in the oracle from the GPU's own iterates and loss
+    seeds (those gradients depend on nothing earlier), both at the GPU's own
+    taped solves and against exact solves with a floor for the float32
+    rounding of the stored steps.
 """
 import numpy as np
 import pytest
@@ -23,7 +26,8 @@ import torch
 
 import oracle
 from oracle.cones import proj_cone
-from gpu_common import assert_close, ensure_lib, floor_of, one_step_err, oracle_run, say
+from gpu_common import (assert_blocks_close, assert_close, ensure_lib, floor_bars, floor_of, one_step_err,
+                        oracle_run, say)
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -36,8 +40,9 @@ def _bench_run(name):
     from paper_2606_13825_amd import CosmoBatch
     wl = bench._workload(name)
     rhos, alphas = bench._hyper(wl)
-    kw = {k: wl[k] for k in ("cg_tol", "cg_max_iter") if k in wl}
-    batch = CosmoBatch(wl["insts"], K=wl["K"], dtype=torch.float32, device=DEV, **kw)
+    kw = {k: wl[k] for k in ("cg_tol", "cg_max_iter", "dense_f32") if k in wl}
+    tdt = torch.float32 if wl["dtype"] == "f32" else torch.float64
+    batch = CosmoBatch(wl["insts"], K=wl["K"], dtype=tdt, device=DEV, **kw)
     rho = torch.from_numpy(np.concatenate(rhos, axis=1)).to(DEV)
     alpha = torch.from_numpy(np.stack(alphas, axis=1)).to(DEV)
     form, ms = batch.autotune(rho, alpha)
@@ -167,14 +172,43 @@ def _check_tail_gradients(wl, rhos, alphas, batch, fw, bw, i, tail, tol, exact=T
     assert_close(g_r, ref_r, tol, 4 * d / tol, f"inst {i} grad rho tail")
 
 
+def _check_whole_run(wl, rhos, alphas, batch, fw, bw, i):
+    """Final iterates and all K steps' gradients of instance i against the
+    oracle's own float64 run, at the contract bars (1e-5, 1e-4) or twice the
+    instance's float32 floor, whichever is larger (gpu_common), array by
+    array and, for the slacks and duals, cone block by cone block.  Returns
+    (iterate error, gradient error, floors)."""
+    inst = wl["insts"][i]
+    r64, a64 = rhos[i].astype(np.float64), alphas[i].astype(np.float64)
+    ref = oracle_run(inst, r64, a64)
+    runs = []
+    if wl["dtype"] == "f32":
+        # max-cut's M is diagonal (exact solves); the other families run the CG
+        cg = 0.0 if wl["name"].startswith("maxcut") else wl.get("cg_tol", 1e-8)
+        b_it, b_g, f = floor_bars(inst, r64, a64, ref, cg_tol=cg, runs=runs)
+    else:
+        b_it, b_g, f = 1e-5, 1e-4, (0.0, 0.0)
+    fl = floor_of(inst)
+    sl_n = slice(batch.n_off[i], batch.n_off[i + 1])
+    sl_m = slice(batch.m_off[i], batch.m_off[i + 1])
+    e = [assert_close(a.double().cpu().numpy(), r, b_it, fl, f"inst {i} final {nm}")
+         for nm, a, r in (("x", fw.x[sl_n], ref["x"]), ("s", fw.s[sl_m], ref["s"]), ("y", fw.y[sl_m], ref["y"]))]
+    e += [assert_blocks_close(a.double().cpu().numpy(), r, inst, 1e-5, f"inst {i} final {nm}", floor=fl,
+                              floor_runs=[run[j] for run in runs])
+          for j, nm, a, r in ((1, "s", fw.s[sl_m], ref["s"]), (2, "y", fw.y[sl_m], ref["y"]))]
+    g = [assert_close(bw.grho[:, sl_m].double().cpu().numpy(), ref["grho"], b_g, 0.0, f"inst {i} grad rho"),
+         assert_close(bw.galpha[:, i].double().cpu().numpy(), ref["galpha"], b_g, 0.0, f"inst {i} grad alpha")]
+    return max(e), max(g), f
+
+
 def test_c2_maxcut_full_batch_sampled_instances():
-    """Iterates: every one-step check at 1e-5 and the final iterate of the
-    oracle's own float64 run at 1e-5.  Gradients: the oracle's reverse pass
-    over the GPU's own forward record (iterates, solves, next slacks) at
-    1e-4 for all 50 steps.  Against the oracle's own float64 trajectory the
-    gradients carry the float32 trajectory's sensitivity on top (the oracle
-    itself, with its iterates rounded to float32 after every step, moves by
-    about 5e-5); that comparison is reported and held to 1e-3."""
+    """Iterates: every one-step check at 1e-5.  Gradients: the oracle's
+    reverse pass over the GPU's own forward record (iterates, solves, next
+    slacks) at 1e-4 for all 50 steps.  Against the oracle's own float64
+    trajectory the final iterates and the gradients are held to the contract
+    bars or twice the instance's float32 floor (the oracle's rounding model;
+    on some instances of this batch float32 storage alone moves the
+    gradients by 1e-4 and more)."""
     ensure_lib()
     wl, rhos, alphas, batch, fw, bw = _bench_run("c2")
     insts, K = wl["insts"], wl["K"]
@@ -184,15 +218,9 @@ def test_c2_maxcut_full_batch_sampled_instances():
         inst = insts[i]
         _check_one_steps(wl, rhos, alphas, batch, fw, [(i, k) for k in range(K)])
         _check_tail_gradients(wl, rhos, alphas, batch, fw, bw, i, K, 1e-4, exact=False)
-        ref = oracle_run(inst, rhos[i].astype(np.float64), alphas[i].astype(np.float64))
-        fl = floor_of(inst)
-        sl_n = slice(batch.n_off[i], batch.n_off[i + 1])
-        sl_m = slice(batch.m_off[i], batch.m_off[i + 1])
-        e = [assert_close(a.double().cpu().numpy(), r, 1e-5, fl, f"inst {i} final {nm}")
-             for nm, a, r in (("x", fw.x[sl_n], ref["x"]), ("s", fw.s[sl_m], ref["s"]), ("y", fw.y[sl_m], ref["y"]))]
-        g = [assert_close(bw.grho[:, sl_m].double().cpu().numpy(), ref["grho"], 1e-3, 0.0, f"inst {i} grad rho"),
-             assert_close(bw.galpha[:, i].double().cpu().numpy(), ref["galpha"], 1e-3, 0.0, f"inst {i} grad alpha")]
-        say(f"  instance {i} (p={orders[i]}): final iterates vs the oracle's run {max(e):.2e}, gradients {max(g):.2e}")
+        e, g, f = _check_whole_run(wl, rhos, alphas, batch, fw, bw, i)
+        say(f"  instance {i} (p={orders[i]}): final iterates vs the oracle's run {e:.2e}, gradients {g:.2e} "
+            f"(float32 floor {f[0]:.1e}, {f[1]:.1e})")
 
 
 def test_c5_covsteer_full_batch_sampled_instances():
@@ -202,16 +230,9 @@ def test_c5_covsteer_full_batch_sampled_instances():
     largest = int(np.argmax([inst.n for inst in insts]))
     for i in sorted({0, largest}):
         inst = insts[i]
-        ref = oracle_run(inst, rhos[i].astype(np.float64), alphas[i].astype(np.float64))
-        fl = floor_of(inst)
-        sl_n = slice(batch.n_off[i], batch.n_off[i + 1])
-        sl_m = slice(batch.m_off[i], batch.m_off[i + 1])
-        e = [assert_close(a.double().cpu().numpy(), r, 1e-4, fl, f"inst {i} final {nm}")
-             for nm, a, r in (("x", fw.x[sl_n], ref["x"]), ("s", fw.s[sl_m], ref["s"]), ("y", fw.y[sl_m], ref["y"]))]
-        e.append(assert_close(bw.grho[:, sl_m].double().cpu().numpy(), ref["grho"], 1e-3, 0.0, f"inst {i} grad rho"))
-        e.append(assert_close(bw.galpha[:, i].double().cpu().numpy(), ref["galpha"], 1e-3, 0.0,
-                              f"inst {i} grad alpha"))
-        say(f"  instance {i} (n={inst.n}, m={inst.m}): max rel err {max(e):.2e}")
+        e, g, f = _check_whole_run(wl, rhos, alphas, batch, fw, bw, i)
+        say(f"  instance {i} (n={inst.n}, m={inst.m}): final iterates {e:.2e}, gradients {g:.2e} "
+            f"(float32 floor {f[0]:.1e}, {f[1]:.1e})")
 
 
 def test_c3_lovasz_full_batch_sampled_steps():
@@ -222,11 +243,25 @@ def test_c3_lovasz_full_batch_sampled_steps():
     _check_one_steps(wl, rhos, alphas, batch, fw, [(0, 0), (big, 0), (big, K // 2), (big, K - 3), (big, K - 2),
                                                    (B - 1, K - 1)])
     _check_tail_gradients(wl, rhos, alphas, batch, fw, bw, big, 3, 1e-4)
+    # whole trajectories: this family's float32 floor is large (its iterates
+    # shrink by four orders of magnitude over the unroll while the rounding
+    # of the early, large ones stays), and the bars follow it
+    for i in (0, big):
+        e, g, f = _check_whole_run(wl, rhos, alphas, batch, fw, bw, i)
+        say(f"  instance {i} (order {wl['insts'][i].meta['order']}): final iterates {e:.2e}, gradients {g:.2e} "
+            f"(float32 floor {f[0]:.1e}, {f[1]:.1e})")
 
 
-def test_c4_huber_full_batch_sampled_steps():
+def test_c4_huber_full_batch_sampled_instances():
+    """The benchmark's line: float64 iterations on float32 data, the design
+    block stored as float32 (lossless).  Whole trajectories and gradients of
+    two sampled instances against the oracle's own float64 runs at the
+    contract bars, plus one-step parity at sampled steps."""
     ensure_lib()
     wl, rhos, alphas, batch, fw, bw = _bench_run("c4")
     K, B = wl["K"], len(wl["insts"])
+    assert batch.n_dense == B and batch.dense_val.dtype == torch.float32
     _check_one_steps(wl, rhos, alphas, batch, fw, [(0, 0), (B - 1, K // 2), (B // 2, K - 1)])
-    _check_tail_gradients(wl, rhos, alphas, batch, fw, bw, B - 1, 2, 1e-4)
+    for i in (0, B - 1):
+        e, g, _ = _check_whole_run(wl, rhos, alphas, batch, fw, bw, i)
+        say(f"  instance {i}: final iterates vs the oracle's run {e:.2e}, gradients {g:.2e}")

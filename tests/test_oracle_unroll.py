@@ -216,3 +216,66 @@ def test_table2_defaults_drive_default_rho():
     for c, sl in synth.cone_row_slices(inst.cones):
         assert np.allclose(r[:, sl], t2["rho_init"][c.kind])
     assert t2["alpha_init"] == 1.6 and t2["sigma"] == oracle.Hyper().sigma
+
+
+def test_stored_precision_rounding_option():
+    """unroll_forward(store_dtype=...) rounds what a pipeline of that
+    precision stores, nothing else: float64 leaves the run bit for bit as it
+    is; float32 leaves every stored per-step value (and the PSD eigenpairs of
+    the reverse pass) a float32 number, keeps the float64 right-hand side,
+    and on a contractive instance moves the iterates by no more than the
+    rounding of K steps."""
+    inst, rng = _mixed(13)
+    K = 8
+    rho, alpha = synth.perturbed_hyper(inst, K, rng)
+    rho, alpha = rho.astype(np.float32).astype(np.float64), alpha.astype(np.float32).astype(np.float64)
+    tape, z = oracle.unroll_forward(inst, rho, alpha)
+    tape64, z64 = oracle.unroll_forward(inst, rho, alpha, store_dtype=np.float64)
+    for a, b in zip(z, z64):
+        assert np.array_equal(a, b)
+    for st, st64 in zip(tape, tape64):
+        for key in ("xt", "st", "xn", "sh", "v", "sn", "yn", "xi"):
+            assert np.array_equal(st[key], st64[key])
+    tape32, z32 = oracle.unroll_forward(inst, rho, alpha, store_dtype=np.float32)
+    is32 = lambda a: np.array_equal(np.asarray(a).astype(np.float32).astype(np.float64), a)
+    for st in tape32:
+        for key in ("rho_hat", "xt", "st", "xn", "sh", "v", "sn", "yn"):
+            assert is32(st[key]), key
+        assert not is32(st["xi"])          # formed and used in float64, never stored
+        for a in st["aux"]:
+            if a is not None:
+                assert is32(a[0]) and is32(a[1])
+    # max-cut on K_6 from z0 = 0 with the default penalties contracts toward its
+    # KKT point: the rounded run stays within K float32 roundings of the exact one
+    inst2 = synth.maxcut_sdp(6, synth.complete_graph(6))
+    r2 = synth.default_rho(inst2, 30)
+    _, za = oracle.unroll_forward(inst2, r2, np.full(30, 1.6))
+    _, zb = oracle.unroll_forward(inst2, r2, np.full(30, 1.6), store_dtype=np.float32)
+    for a, b in zip(za, zb):
+        assert 0 < np.linalg.norm(a - b) <= 30 * 6e-8 * 10 * np.linalg.norm(a)
+
+
+def test_rounding_model_dither_and_solve_residual():
+    """The rounding model's realisations: dithered stored values stay float32
+    numbers within one unit in the last place of the nearest rounding, and a
+    modelled solve residual is what was asked for."""
+    inst, rng = _mixed(17)
+    K = 5
+    rho, alpha = synth.perturbed_hyper(inst, K, rng)
+    tape_n, _ = oracle.unroll_forward(inst, rho, alpha, store_dtype=np.float32)
+    tape_d, _ = oracle.unroll_forward(inst, rho, alpha, store_dtype=np.float32,
+                                      store_rng=np.random.default_rng(3))
+    # rho_hat, the first stored value of step 0, comes from the same input in
+    # both runs: the two differ by the dither alone
+    a, b = tape_n[0]["rho_hat"], tape_d[0]["rho_hat"]
+    ulp = np.abs(np.spacing(a.astype(np.float32))).astype(np.float64)
+    assert np.all(np.abs(a - b) <= ulp * 1.0000001) and np.any(a != b)
+    for st in tape_d:
+        for key in ("rho_hat", "xt", "st", "xn", "sh", "v", "sn", "yn"):
+            assert np.array_equal(st[key].astype(np.float32).astype(np.float64), st[key]), key
+    tape_r, _ = oracle.unroll_forward(inst, rho, alpha, store_dtype=np.float32,
+                                      store_rng=np.random.default_rng(4), solve_resid=1e-3)
+    st = tape_r[0]
+    M = oracle.reduced_matrix(inst, st["rho_hat"], 1e-6)
+    res = np.linalg.norm(M @ st["xt"] - st["xi"]) / np.linalg.norm(st["xi"])
+    assert 0.5e-3 < res < 2e-3          # 1e-3 up to the float32 rounding of x~
