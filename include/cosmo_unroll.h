@@ -255,6 +255,20 @@ cosmo_status psd_proj(int32_t nblk, const int32_t *order, const int64_t *offset,
                       const void *in, void *out, void *eigvals, void *eigvecs, int32_t max_sweeps,
                       double eig_tol, int32_t refine, void *ws, void *stream);
 
+/* psd_proj for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same operation, arguments and results as psd_proj, without `ws`.  The
+ * scratch is the library's own device array of COSMO_PSD_STATIC_SCRATCH_BYTES
+ * (one per device, held until the process ends); blocks whose
+ * cosmo_proj_workspace_size exceeds it return COSMO_EUNSUPPORTED before any
+ * launch.  The call allocates nothing.  Every call on a device shares that
+ * device's array: calls that overlap on one device (several host threads or
+ * streams) race and must be serialised by the caller. */
+#define COSMO_PSD_STATIC_SCRATCH_BYTES (64u << 20)
+cosmo_status psd_proj_static_scratch(int32_t nblk, const int32_t *order, const int64_t *offset, cosmo_dtype dtype,
+                                     const void *in, void *out, void *eigvals, void *eigvecs, int32_t max_sweeps,
+                                     double eig_tol, int32_t refine, void *stream);
+
 /* eq:psd-cotangent-dk per block, reusing the decomposition of psd_proj:
  * gin = svec(U (L o (U' smat(gout) U)) U'), L the Loewner matrix of max(., 0)
  * (eq:lowner; f'(0) taken as 0). */

@@ -11,6 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcosmo_unroll.so")
 
 COSMO_OK, COSMO_EINVAL, COSMO_ENOMEM, COSMO_EHIP, COSMO_EUNSUPPORTED = 0, -1, -2, -3, -4
+COSMO_PSD_STATIC_SCRATCH_BYTES = 64 << 20   # include/cosmo_unroll.h
 COSMO_F32, COSMO_F64 = 0, 1
 CONE_CODES = {"zero": 0, "nonneg": 1, "soc": 2, "psd": 3}
 
@@ -19,7 +20,7 @@ EXPORTED = [
     "cosmo_status_string", "cosmo_last_error", "cosmo_abi_version",
     "cosmo_plan_create", "cosmo_plan_destroy", "cosmo_workspace_size", "cosmo_tape_offsets",
     "cosmo_unroll_forward", "cosmo_unroll_backward", "cosmo_residual_loss",
-    "cosmo_proj_workspace_size", "psd_proj", "psd_proj_vjp", "socp_proj", "socp_proj_vjp",
+    "cosmo_proj_workspace_size", "psd_proj", "psd_proj_static_scratch", "psd_proj_vjp", "socp_proj", "socp_proj_vjp",
     "cosmo_plan_set_profiling", "cosmo_plan_profile_read",
     "cosmo_plan_set_pcg_form", "cosmo_plan_get_pcg_form", "cosmo_plan_autotune",
     "cosmo_plan_set_graph", "cosmo_plan_get_graph",
@@ -133,6 +134,8 @@ def _sig(lib):
     lib.cosmo_proj_workspace_size.argtypes = [i32, P32]
     lib.psd_proj.restype = ctypes.c_int
     lib.psd_proj.argtypes = [i32, P32, P64, ctypes.c_int, vp, vp, vp, vp, i32, dbl, i32, vp, vp]
+    lib.psd_proj_static_scratch.restype = ctypes.c_int
+    lib.psd_proj_static_scratch.argtypes = [i32, P32, P64, ctypes.c_int, vp, vp, vp, vp, i32, dbl, i32, vp]
     lib.psd_proj_vjp.restype = ctypes.c_int
     lib.psd_proj_vjp.argtypes = [i32, P32, P64, ctypes.c_int, vp, vp, vp, vp, vp, vp]
     lib.psd_proj_vjp_rule.restype = ctypes.c_int

@@ -1496,4 +1496,57 @@ cosmo_status socp_proj_vjp(int32_t ncones, const int32_t *dim, const int64_t *of
   return COSMO_OK;
 }
 
+
+// ---- psd_proj without allocation -------------------------------------------
+//
+// psd_proj_static_scratch runs psd_proj with this library's own device
+// scratch instead of a caller workspace: a file-scope array, one copy per
+// device, held until the process ends.  Host code must never pass the
+// array's name to a kernel or a copy (it is a host-side stand-in, not a
+// device address): the device address is taken once per device with
+// hipGetSymbolAddress and kept below.
+}  // extern "C"
+
+static __device__ __align__(256) unsigned char scratch[COSMO_PSD_STATIC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<std::pair<int, void *>> g_scratch_dev;   // (device, address of scratch on it)
+
+cosmo_status static_scratch(void **ptr) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  for (const auto &e : g_scratch_dev)
+    if (e.first == dev) {
+      *ptr = e.second;
+      return COSMO_OK;
+    }
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    FAIL(COSMO_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_dev.push_back({dev, p});
+  *ptr = p;
+  return COSMO_OK;
+}
+}  // namespace
+
+extern "C" {
+
+cosmo_status psd_proj_static_scratch(int32_t nblk, const int32_t *order, const int64_t *offset, cosmo_dtype dtype,
+                                     const void *in, void *out, void *eigvals, void *eigvecs, int32_t max_sweeps,
+                                     double eig_tol, int32_t refine, void *stream) {
+  if (nblk < 1 || !order) FAIL(COSMO_EINVAL, "need nblk >= 1 and a host order array");
+  const size_t need = cosmo_proj_workspace_size(nblk, order);
+  if (need > (size_t)COSMO_PSD_STATIC_SCRATCH_BYTES)
+    FAIL(COSMO_EUNSUPPORTED, "psd_proj_static_scratch: these blocks need " + std::to_string(need) +
+                                 " bytes of scratch; the static scratch holds " +
+                                 std::to_string((size_t)COSMO_PSD_STATIC_SCRATCH_BYTES) + " (use psd_proj)");
+  void *ws = nullptr;
+  const cosmo_status st = static_scratch(&ws);
+  if (st != COSMO_OK) return st;
+  return psd_proj(nblk, order, offset, dtype, in, out, eigvals, eigvecs, max_sweeps, eig_tol, refine, ws, stream);
+}
+
 }  // extern "C"

@@ -257,3 +257,23 @@ def test_dense_blocks_null_with_count_rejected(L):
     assert L.lib().cosmo_plan_create(ctypes.byref(h), ctypes.byref(p), ctypes.byref(_options(L))) == L.COSMO_EINVAL
     p.n_dense = -1
     assert L.lib().cosmo_plan_create(ctypes.byref(h), ctypes.byref(p), ctypes.byref(_options(L))) == L.COSMO_EINVAL
+
+
+def test_static_scratch_projection_refuses_oversized_requests(L):
+    """psd_proj_static_scratch checks its request against the static scratch
+    before touching the device (no pointers needed for the refusal)."""
+    import numpy as np
+    orders = np.full(200, 200, np.int32)              # 200 blocks of order 200: ~192 MB of scratch
+    P32 = ctypes.POINTER(ctypes.c_int32)
+    need = L.lib().cosmo_proj_workspace_size(len(orders), orders.ctypes.data_as(P32))
+    assert need > L.COSMO_PSD_STATIC_SCRATCH_BYTES
+    rows = orders.astype(np.int64) * (orders + 1) // 2
+    offs = np.concatenate([[0], np.cumsum(rows)[:-1]]).astype(np.int64)
+    st = L.lib().psd_proj_static_scratch(len(orders), orders.ctypes.data_as(P32),
+                                         offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), L.COSMO_F32,
+                                         None, None, None, None, 60, 0.0, 1, None)
+    assert st == L.COSMO_EUNSUPPORTED
+    assert b"static scratch" in L.lib().cosmo_last_error()
+    hdr = open(os.path.join(ROOT, "include", "cosmo_unroll.h")).read()
+    assert "#define COSMO_PSD_STATIC_SCRATCH_BYTES (64u << 20)" in hdr
+    assert L.COSMO_PSD_STATIC_SCRATCH_BYTES == 64 << 20
