@@ -60,13 +60,17 @@ typedef enum {
   COSMO_EUNSUPPORTED = -4   /* valid request outside the implemented envelope */
 } cosmo_status;
 
-typedef enum { COSMO_F32 = 0, COSMO_F64 = 1 } cosmo_dtype;
+/* The last enumerator of each enum taken from callers widens its range to
+ * every int32 value, so a caller's out-of-range value is a valid (rejected)
+ * enum value on the library side, not undefined behaviour. */
+typedef enum { COSMO_F32 = 0, COSMO_F64 = 1, COSMO_DTYPE_MAX_ENUM = 0x7fffffff } cosmo_dtype;
 
 typedef enum {
   COSMO_CONE_ZERO = 0,      /* s = 0            (equality rows)          */
   COSMO_CONE_NONNEG = 1,    /* s >= 0                                     */
   COSMO_CONE_SOC = 2,       /* (t, w): ||w||_2 <= t, size = rows (>= 1)   */
-  COSMO_CONE_PSD = 3        /* svec(S), S psd, size = matrix order p      */
+  COSMO_CONE_PSD = 3,       /* svec(S), S psd, size = matrix order p      */
+  COSMO_CONE_MAX_ENUM = 0x7fffffff
 } cosmo_cone_kind;
 
 /* Largest PSD order handled: the one-sided Jacobi eigensolver keeps one

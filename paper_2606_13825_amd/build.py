@@ -33,9 +33,14 @@ def common_flags():
             "-Wall", "-Wno-unused-result"]
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-    cmd = [hipcc()] + common_flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
+# Host-side AddressSanitizer and UndefinedBehaviorSanitizer for the plan,
+# validation and launch code; device code is built as usual.
+HOST_SANITIZE = "-Xarch_host -fsanitize=address -Xarch_host -fsanitize=undefined -Xarch_host -fno-omit-frame-pointer".split()
+
+
+def _compile(src: str, verbose: bool, build_dir: str = BUILD, extra=()) -> str:
+    obj = os.path.join(build_dir, src.replace(".hip", ".o"))
+    cmd = [hipcc()] + common_flags() + list(extra) + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in (r.stderr or "").splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:
@@ -46,16 +51,33 @@ def _compile(src: str, verbose: bool) -> str:
 
 
 def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+    return _build(LIB, BUILD, (), verbose)
+
+
+def build_host_sanitized(verbose: bool = False) -> str:
+    """The same library with ASan and UBSan on its host code, under _build/
+    (never the shipped library).  A process that loads it must preload the
+    ASan runtime (sanitizer_runtime())."""
+    out_dir = os.path.join(BUILD, "host_sanitized")
+    return _build(os.path.join(out_dir, "libcosmo_unroll.so"), out_dir, HOST_SANITIZE, verbose)
+
+
+def sanitizer_runtime() -> str:
+    r = subprocess.run([hipcc(), "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    return r.stdout.strip()
+
+
+def _build(lib: str, build_dir: str, extra, verbose: bool) -> str:
+    os.makedirs(build_dir, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+        objs = list(ex.map(lambda s: _compile(s, verbose, build_dir, extra), SOURCES))
+    tmp = lib + ".tmp"
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + list(extra) + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"linking failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -15,6 +15,8 @@ HEADER = os.path.join(ROOT, "include", "cosmo_unroll.h")
 @pytest.fixture(scope="module")
 def L():
     from paper_2606_13825_amd import _lib
+    if os.environ.get("COSMO_TEST_LIB_PATH"):   # the host-sanitized build (test below)
+        _lib.LIB_PATH = os.environ["COSMO_TEST_LIB_PATH"]
     if not os.path.exists(_lib.LIB_PATH):
         from paper_2606_13825_amd import build
         build.build()
@@ -277,3 +279,30 @@ def test_static_scratch_projection_refuses_oversized_requests(L):
     hdr = open(os.path.join(ROOT, "include", "cosmo_unroll.h")).read()
     assert "#define COSMO_PSD_STATIC_SCRATCH_BYTES (64u << 20)" in hdr
     assert L.COSMO_PSD_STATIC_SCRATCH_BYTES == 64 << 20
+
+
+def test_loaded_library_is_the_requested_one(L):
+    L.lib()
+    maps = open("/proc/self/maps").read()
+    assert os.path.realpath(L.LIB_PATH) in maps
+
+
+@pytest.mark.skipif(bool(os.environ.get("COSMO_TEST_LIB_PATH")), reason="this is the sanitized run itself")
+def test_host_code_clean_under_asan_and_ubsan():
+    """The host side of the library (plan building, descriptor validation,
+    the no-allocation entry point's size check) built with AddressSanitizer
+    and UndefinedBehaviorSanitizer, and every test of this file run against
+    it in a fresh process with the ASan runtime preloaded: no report, and the
+    sanitized library is the one loaded."""
+    import subprocess
+    import sys
+    from paper_2606_13825_amd import build
+    lib = build.build_host_sanitized()
+    env = dict(os.environ, LD_PRELOAD=build.sanitizer_runtime(), COSMO_TEST_LIB_PATH=lib,
+               ASAN_OPTIONS="detect_leaks=0:abort_on_error=1", UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+    r = subprocess.run([sys.executable, "-m", "pytest", os.path.abspath(__file__), "-q", "-x", "-p", "no:cacheprovider"],
+                       env=env, capture_output=True, text=True, timeout=900, cwd=ROOT)
+    out = r.stdout + r.stderr
+    assert r.returncode == 0, out[-4000:]
+    assert "runtime error" not in out and "AddressSanitizer" not in out, out[-4000:]
+    assert " passed" in r.stdout and " skipped" in r.stdout   # this test skipped itself there

@@ -162,6 +162,33 @@ def test_dk_vjp_matches_oracle(dtype, tol, orders):
         assert e <= tol, (p, e)
 
 
+@pytest.mark.parametrize("dtype,tol", [(np.float32, 1e-6), (np.float64, 1e-13)])
+def test_dk_vjp_ties_at_zero_match_oracle(dtype, tol):
+    """Diagonal blocks with exactly repeated zero eigenvalues: the GPU's
+    Loewner weights at ties on the kink (vjp_weight) take the same
+    convention as the oracle's (f'(0) = 0, reading R8), so the VJPs agree."""
+    ensure_lib()
+    from paper_2606_13825_amd import psd_proj_vjp
+    rng = np.random.default_rng(8)
+    mats = [np.diag([0.0, 0.0, 2.0, -1.0, 0.0, 0.5]), np.diag([0.0] * 4 + [1.0] * 3),
+            np.diag(np.r_[np.zeros(20), rng.uniform(0.5, 2.0, 20), -rng.uniform(0.5, 2.0, 20)])]
+    _, lam, U, orders = _run_psd(mats, dtype)
+    lam_h = lam.double().cpu().numpy()
+    assert np.sum(lam_h == 0.0) == 3 + 4 + 20     # the zeros come out exactly
+    G = [_sym(rng, m.shape[0]) for m in mats]
+    g = np.concatenate([oracle.svec(x) for x in G]).astype(dtype)
+    gin = psd_proj_vjp(lam, U, torch.from_numpy(g).to(DEV), orders)
+    torch.cuda.synchronize()
+    gin = gin.double().cpu().numpy()
+    off = 0
+    for S, Gm in zip(mats, G):
+        p = S.shape[0]
+        nr = p * (p + 1) // 2
+        ref = oracle.psd_vjp_dk(np.eye(p), np.diag(S).copy(), oracle.svec(Gm).astype(dtype).astype(np.float64))
+        assert rel_err(gin[off:off + nr], ref, 1e-6) <= tol, p
+        off += nr
+
+
 def test_soc_projection_and_vjp():
     ensure_lib()
     from paper_2606_13825_amd import socp_proj, socp_proj_vjp

@@ -206,3 +206,20 @@ def test_rectify_block_means_and_adjoint():
     rng = np.random.default_rng(1)
     a, b = rng.standard_normal(11), rng.standard_normal(11)
     assert np.isclose(oracle.rectify(a, cones) @ b, a @ oracle.rectify_adjoint(b, cones))
+
+
+def test_lowner_ties_at_zero_take_the_nonpositive_side():
+    """Reading R8: at an exact tie on the kink of max(., 0) the Loewner entry
+    is the limit of the divided differences from the non-positive side
+    (f'(0) = 0), a valid element of the generalized Jacobian; entries pairing
+    0 with a positive eigenvalue stay ordinary divided differences.  The
+    limits are taken on the oracle's divided differences of distinct values
+    (pinned separately by finite differences), not on its tie branch."""
+    L = oracle.lowner_matrix(np.array([0.0, 0.0, 2.0, -1.0, 0.0]))
+    for eps in (1e-3, 1e-6, 1e-9):
+        near = oracle.lowner_matrix(np.array([-eps, -2 * eps, 2.0, -1.0, -3 * eps]))
+        assert np.allclose(L[[0, 1, 4]][:, [0, 1, 4]], near[[0, 1, 4]][:, [0, 1, 4]], atol=0.0)
+    assert L[0, 0] == 0.0 and L[0, 1] == 0.0 and L[4, 4] == 0.0
+    assert L[0, 2] == L[2, 0] == 1.0          # (f(2) - f(0)) / (2 - 0)
+    assert L[0, 3] == L[3, 0] == 0.0          # (f(-1) - f(0)) / (-1 - 0)
+    assert L[2, 2] == 1.0 and L[3, 3] == 0.0
