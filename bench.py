@@ -326,7 +326,76 @@ def psd_rules_study(samples=100, orders=(10, 20, 40, 80, 160, 320), delta=1e-5, 
 APPB_CG_TOL = 1e-10
 
 
-def appb_study(ns=(1000, 2000, 5000, 10000, 20000, 50000), reps=3, seed=8):
+DENSE_SOLVE_MAX_ELEMENTS = 2**31 - 1
+
+
+def _appb_dense_baseline(kind, P, A, rho_row, b, q, xstar, dev, reps=1):
+    """One of the appendix's dense comparison methods for the App. B solve,
+    with PyTorch's dense solver and autograd (a measured baseline, not the
+    library's path): 'direct' forms the saddle-point matrix of
+    eq:cosmo_linear_system, 'indirect_full' the reduced matrix M of
+    eq:cosmo_linear_system_reduced; both solve the first step from z = 0 and
+    backpropagate the least-squares loss 1/2 ||x~ - x*||^2 to rho.  Returns
+    peak HBM of forward + backward (bytes over the state before) and the
+    backward time (HIP events, the mean of `reps`), or the error when the
+    device runs out of memory."""
+    import torch
+    f32 = torch.float32
+    n, m = A.shape[1], A.shape[0]
+    sigma = 1e-6
+    dim = n + m if kind == "direct" else n
+    if dim * dim > DENSE_SOLVE_MAX_ELEMENTS:
+        # the dense LU (rocSOLVER through torch) indexes its matrix with 32-bit
+        # integers: a 75000^2 saddle-point matrix (5.6e9 elements) faulted the GPU
+        return {"error": "not run", "detail": f"the dense matrix would hold {dim * dim:.3g} elements, beyond the "
+                                                f"dense solver's 32-bit element indexing ({DENSE_SOLVE_MAX_ELEMENTS})"}
+    torch.cuda.synchronize(dev)
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats(dev)
+    base = torch.cuda.memory_allocated(dev)
+    try:
+        Ac = A.tocoo()
+        Ad = torch.sparse_coo_tensor(np.vstack([Ac.row, Ac.col]), Ac.data.astype(np.float32), (m, n),
+                                     device=dev).to_dense()
+        pd = torch.from_numpy(P.diagonal().astype(np.float32)).to(dev)
+        qd = torch.from_numpy(q.astype(np.float32)).to(dev)
+        bd = torch.from_numpy(b.astype(np.float32)).to(dev)
+        xs = torch.from_numpy(xstar.astype(np.float32)).to(dev)
+        rho = torch.from_numpy(rho_row.astype(np.float32)).to(dev).requires_grad_(True)
+        ms = 0.0
+        for _ in range(reps):
+            if kind == "direct":
+                K = torch.zeros((n + m, n + m), dtype=f32, device=dev)
+                K[:n, :n] = torch.diag(pd + sigma)
+                K[:n, n:] = Ad.T
+                K[n:, :n] = Ad
+                K = K - torch.diag(torch.cat([torch.zeros(n, dtype=f32, device=dev), 1.0 / rho]))
+                rhs = torch.cat([-qd, bd])
+                xt = torch.linalg.solve(K, rhs)[:n]
+            else:
+                M = torch.diag(pd + sigma) + Ad.T @ (rho[:, None] * Ad)
+                xi = -qd + Ad.T @ (rho * bd)
+                xt = torch.linalg.solve(M, xi)
+            loss = 0.5 * torch.sum((xt - xs) ** 2)
+            cur = torch.cuda.current_stream(dev)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(cur)
+            (g,) = torch.autograd.grad(loss, rho)
+            e1.record(cur)
+            e1.synchronize()
+            ms += e0.elapsed_time(e1) / reps
+            ok = bool(torch.isfinite(g).all())
+            del g, loss, xt
+        peak = torch.cuda.max_memory_allocated(dev) - base
+        return {"peak_hbm_bytes": int(peak), "bwd_ms": ms, "finite": ok}
+    except torch.cuda.OutOfMemoryError as e:
+        return {"error": "out of memory", "detail": str(e).split("\n")[0][:200]}
+    finally:
+        torch.cuda.synchronize(dev)
+        torch.cuda.empty_cache()
+
+
+def appb_study(ns=(1000, 2000, 5000, 10000, 20000, 50000), reps=3, seed=8, dense_baselines=False):
     """Memory and time of the matrix-free backward against the problem size
     (the linear-solve backward experiment of App. B): one instance per size
     from the App. B sampler (diagonal P ~ U(0, 10), m = n/2, A 1 % dense,
@@ -338,7 +407,9 @@ def appb_study(ns=(1000, 2000, 5000, 10000, 20000, 50000), reps=3, seed=8):
     workspaces, outputs) over forward + loss + backward plus the plan's own
     device buffer; the backward alone is timed with HIP events.  The dense
     reduced matrix (n^2) and saddle-point matrix ((n + m)^2) that the paper's
-    comparison methods form are reported by size only.  Prints one JSON line."""
+    comparison methods form are reported by size, and with dense_baselines
+    both methods run (PyTorch dense solve and autograd, float32) on the same
+    instance: peak HBM and backward time.  Prints one JSON line."""
     import torch
     from paper_2606_13825_amd import CosmoBatch
     from synth import Cone, ConicInstance
@@ -390,18 +461,26 @@ def appb_study(ns=(1000, 2000, 5000, 10000, 20000, 50000), reps=3, seed=8):
                "bwd_ms": ms, "bwd_cg_operator_applications": ops, "bwd_cg_bytes": cg_bytes,
                "bwd_cg_gbs": cg_bytes / (ms * 1e-3) / 1e9,
                "dense_reduced_matrix_bytes": 4 * n * n, "dense_kkt_bytes": 4 * (n + m) ** 2}
+        # every plan is destroyed here, on a synchronised device, not at interpreter exit
+        torch.cuda.synchronize(dev)
+        batch.close()
+        del batch, tape, fws, bws, fw, bw, g, out
         if n == 200:
-            del batch, tape, fws, bws, fw, bw, g, out
             continue
+        if dense_baselines:
+            for kind in ("indirect_full", "direct"):
+                row[kind] = _appb_dense_baseline(kind, P, A.tocsr(), rho_row, b, -(P @ xstar), xstar, dev)
+                print(f"[bench] appb n={n} {kind}: {row[kind]}", file=sys.stderr, flush=True)
         rows.append(row)
         print(f"[bench] appb n={n}: peak {peak / 2**20:.1f} MiB, backward {ms:.2f} ms, "
               f"{ops:.0f} operator applications, {row['bwd_cg_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
-        del batch, tape, fws, bws, fw, bw, g, out
+    torch.cuda.synchronize(dev)
     last = rows[-1]
     print(json.dumps({"metric": "peak HBM and backward time of the matrix-free backward vs problem size (App. B)",
                       "unit": "bytes, ms", "higher_is_better": False, "dtype": "f32", "data": "synthetic",
                       "config": {"workload": "appb_one_instance_per_size", "sizes": list(ns), "K": 1,
-                                 "pcg_form": 4, "cg_tol": APPB_CG_TOL, "reps": reps},
+                                 "pcg_form": 4, "cg_tol": APPB_CG_TOL, "reps": reps,
+                                 "dense_baselines": dense_baselines},
                       "rows": rows,
                       "roofline": {"kernel": "k_pcg_coop<float> (backward adjoint solve)", "n": last["n"],
                                    "bound": "hbm", "achieved": last["bwd_cg_gbs"], "peak": PEAK_HBM_GBS,
@@ -432,6 +511,8 @@ def main():
     ap.add_argument("--quick", action="store_true",
                     help="counter-collection run: the timed steps only (no plain-forward comparison, "
                          "no event-timed step, no CPU leg)")
+    ap.add_argument("--dense-baselines", action="store_true",
+                    help="with --study appb: also run the dense Direct and Indirect-Full backward passes")
     ap.add_argument("--study", default=None, choices=["psd_rules", "appb"],
                     help="psd_rules: backward time of the PSD-projection rules against the matrix order; "
                          "appb: peak HBM and time of the matrix-free backward against the problem size")
@@ -440,7 +521,7 @@ def main():
         psd_rules_study()
         return
     if args.study == "appb" and args.gpus == 1:
-        appb_study()
+        appb_study(dense_baselines=args.dense_baselines)
         return
     if args.quick:
         args.no_cpu_baseline = True
