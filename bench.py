@@ -345,10 +345,10 @@ def _appb_dense_baseline(kind, P, A, rho_row, b, q, xstar, dev, reps=1):
     sigma = 1e-6
     dim = n + m if kind == "direct" else n
     if dim * dim > DENSE_SOLVE_MAX_ELEMENTS:
-        # the dense LU (rocSOLVER through torch) indexes its matrix with 32-bit
-        # integers: a 75000^2 saddle-point matrix (5.6e9 elements) faulted the GPU
-        return {"error": "not run", "detail": f"the dense matrix would hold {dim * dim:.3g} elements, beyond the "
-                                                f"dense solver's 32-bit element indexing ({DENSE_SOLVE_MAX_ELEMENTS})"}
+        # a 75000^2 saddle-point solve (5.6e9 elements) faulted the GPU inside
+        # the vendor dense solver; solves past a 32-bit element count are not run
+        return {"error": "not run", "detail": f"the dense matrix would hold {dim * dim:.3g} elements, more than "
+                                                f"the {DENSE_SOLVE_MAX_ELEMENTS} this study hands the dense solver"}
     torch.cuda.synchronize(dev)
     torch.cuda.empty_cache()
     torch.cuda.reset_peak_memory_stats(dev)
@@ -489,6 +489,127 @@ def appb_study(ns=(1000, 2000, 5000, 10000, 20000, 50000), reps=3, seed=8, dense
                                    "traffic_per": "one backward adjoint solve (one k_pcg_coop launch)"}}))
 
 
+def psd_trajectory_study(K=100, seed=5, alpha=1.6, ns_iters=40, fd_rel_step=1e-6):
+    """The PSD-backward rules along a real COSMO trajectory (Fig. 3 and its
+    appendix): the double-integrator covariance-steering SDP (N = 10, one PSD
+    block of order 44), K steps in float64 at the default penalties and fixed
+    alpha, from a standard-normal (x0, s0, y0), the final-residual loss, and
+    one backward pass with the per-step tap on: at each step k the matrix S_k
+    the solver projects (v^k on the PSD rows) and the cotangent Tbar_k the
+    reverse pass delivers to the projection's output.  Every rule is applied
+    to that pair, in float64 and in float32 (S_k and Tbar_k rounded): DK
+    (eq:psd-cotangent-dk), the eigendecomposition rule as autograd forms it
+    (eq:psd-cotangent), Tikhonov at eps 1e-3 and 1e-6, and Newton-Schulz
+    (eq:newton-schulz, ns_iters steps, reverse pass through them).  Per step:
+    Frobenius norm of each rule's Sbar_k (the svec 2-norm), whether it is
+    finite, its relative distance from the float64 DK result, the minimum
+    eigenvalue gap of S_k, and the true directional derivative
+    <Tbar_k, dPi(S_k)[E]> by a central difference of the float64 projection
+    along a random unit E (step fd_rel_step max(1, ||S_k||)) against each
+    rule's <Sbar_k, E>.  Prints one JSON line."""
+    import torch
+    from paper_2606_13825_amd import CosmoBatch, NewtonSchulzProj, psd_proj, psd_proj_vjp_rule
+    from synth import cone_row_slices, default_rho, double_integrator_cs
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(seed)
+    inst = double_integrator_cs(rng)
+    (psd_cone, rows), = [(c, sl) for c, sl in cone_row_slices(inst.cones) if c.kind == "psd"]
+    p = psd_cone.size
+    batch = CosmoBatch([inst], K=K, dtype=torch.float64, device=dev, cg_tol=1e-12, cg_max_iter=2000)
+    rho = torch.from_numpy(default_rho(inst, K)).to(dev)
+    al = torch.full((K, 1), alpha, dtype=torch.float64, device=dev)
+    z0 = [torch.from_numpy(rng.standard_normal(d)).to(dev) for d in (inst.n, inst.m, inst.m)]
+    stats = batch.new_stats()
+    fw = batch.forward(rho, al, *z0, stats=stats)
+    loss, g = batch.residual_loss(fw.x, fw.s, fw.y)
+    tap = torch.zeros((K, 2, inst.m), dtype=torch.float64, device=dev)
+    batch.set_tap(tap)
+    bw = batch.backward(rho, al, fw.tape, *g, stats=stats)
+    batch.set_tap(None)
+    torch.cuda.synchronize(dev)
+    sd = batch.stats_dict(stats)
+    S = tap[:, 0, rows].contiguous().view(-1)
+    T = tap[:, 1, rows].contiguous().view(-1)
+    orders = [p] * K
+    nr = p * (p + 1) // 2
+
+    def per_block_norm(v):
+        return torch.linalg.vector_norm(v.view(K, nr).double(), dim=1).cpu().numpy()
+
+    def apply_rules(Sd, Td, dt):
+        Sx, Tx = Sd.to(dt).contiguous(), Td.to(dt).contiguous()
+        _, lam, U = psd_proj(Sx, orders, max_sweeps=60)
+        out = {}
+        for key, rule, eps in (("dk", "dk", 0.0), ("autograd", "naive", 0.0),
+                               ("tikhonov_1e-03", "tikhonov", 1e-3), ("tikhonov_1e-06", "tikhonov", 1e-6)):
+            out[key] = psd_proj_vjp_rule(lam, U, Tx, orders, rule=rule, eps=eps)
+        ns = NewtonSchulzProj(orders, ns_iters, dt, dev)
+        pns = ns.forward(Sx)
+        out["newton_schulz"] = ns.vjp(Tx)
+        return out, lam, pns
+
+    proj64, lam64, _ = psd_proj(S, orders, max_sweeps=60)
+    r64, _, pns64 = apply_rules(S, T, torch.float64)
+    r32, _, _ = apply_rules(S, T, torch.float32)
+    # the true directional derivative of <Tbar, Pi(.)> at S_k along a random unit E
+    E = torch.from_numpy(rng.standard_normal((K, nr))).to(dev)
+    E = (E / torch.linalg.vector_norm(E, dim=1, keepdim=True)).view(-1)
+    h = fd_rel_step * np.maximum(1.0, per_block_norm(S))
+    hv = torch.from_numpy(np.repeat(h, nr)).to(dev)
+    pp, _, _ = psd_proj(S + hv * E, orders, max_sweeps=60, want_eig=False)
+    pm, _, _ = psd_proj(S - hv * E, orders, max_sweeps=60, want_eig=False)
+    fd = ((T * (pp - pm)).view(K, nr).sum(1) / torch.from_numpy(2 * h).to(dev)).cpu().numpy()
+    lam_np = lam64.view(K, p).cpu().numpy()
+    lam_sorted = np.sort(lam_np, axis=1)
+    gaps = np.diff(lam_sorted, axis=1).min(axis=1)
+    dk64 = r64["dk"].view(K, nr)
+    dk_norm = per_block_norm(r64["dk"])
+    steps = []
+    for k in range(K):
+        row = {"k": k, "min_eig_gap": float(gaps[k]), "min_abs_eig": float(np.abs(lam_np[k]).min()),
+               "n_negative": int((lam_np[k] < 0).sum()), "cotangent_norm": float(per_block_norm(T)[k]),
+               "S_norm": float(per_block_norm(S)[k]), "fd_directional": float(fd[k]),
+               "ns_forward_rel_err": float(torch.linalg.vector_norm((pns64 - proj64).view(K, nr)[k]) /
+                                           max(float(torch.linalg.vector_norm(proj64.view(K, nr)[k])), 1e-300))}
+        for prec, res in (("f64", r64), ("f32", r32)):
+            for key, gin in res.items():
+                gk = gin.view(K, nr)[k].double()
+                fin = bool(torch.isfinite(gk).all())
+                nrm = float(torch.linalg.vector_norm(gk)) if fin else None
+                dirv = float((gk * E.view(K, nr)[k]).sum()) if fin else None
+                row[f"{key}_{prec}"] = {
+                    "norm": nrm, "finite": fin,
+                    "rel_to_dk_f64": (float(torch.linalg.vector_norm(gk - dk64[k])) / max(dk_norm[k], 1e-300))
+                    if fin else None,
+                    "fd_rel_err": abs(dirv - fd[k]) / max(abs(fd[k]), 1e-12 * row["cotangent_norm"], 1e-300)
+                    if fin else None}
+        steps.append(row)
+    summary = {}
+    for prec in ("f64", "f32"):
+        for key in r64:
+            nm = f"{key}_{prec}"
+            bad = [s["k"] for s in steps if not s[nm]["finite"]]
+            fin = [s for s in steps if s[nm]["finite"]]
+            summary[nm] = {"nonfinite_steps": len(bad), "first_nonfinite_step": bad[0] if bad else None,
+                           "max_rel_to_dk_f64": max((s[nm]["rel_to_dk_f64"] for s in fin), default=None),
+                           "median_fd_rel_err": float(np.median([s[nm]["fd_rel_err"] for s in fin])) if fin else None}
+        print(f"[bench] psd trajectory {prec}: " + "; ".join(
+            f"{key} nonfinite {summary[f'{key}_{prec}']['nonfinite_steps']}/{K}" for key in r64),
+            file=sys.stderr, flush=True)
+    batch.close()
+    print(json.dumps({"metric": "PSD-projection backward rules along a COSMO trajectory (Fig. 3)",
+                      "unit": "Frobenius norm per step", "higher_is_better": None, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": f"double_integrator_cs_N10_psd{p}_K{K}", "n": inst.n, "m": inst.m,
+                                 "psd_order": p, "K": K, "alpha": alpha, "ns_iters": ns_iters, "seed": seed,
+                                 "rho": "default penalties (zero-cone rows 100, others 0.1)",
+                                 "z0": "standard normal", "loss": "final residual"},
+                      "loss": float(loss[0]), "grad_alpha_norm": float(torch.linalg.vector_norm(bw.galpha)),
+                      "cg_iters_max": int(sd["cg_iters_max"][0]), "nonfinite": int(sd["nonfinite"][0]),
+                      "eig_not_converged": int(sd["eig_not_converged"][0]),
+                      "min_eig_gap_first_last": [float(gaps[0]), float(gaps[-1])],
+                      "summary": summary, "steps": steps}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -513,15 +634,19 @@ def main():
                          "no event-timed step, no CPU leg)")
     ap.add_argument("--dense-baselines", action="store_true",
                     help="with --study appb: also run the dense Direct and Indirect-Full backward passes")
-    ap.add_argument("--study", default=None, choices=["psd_rules", "appb"],
+    ap.add_argument("--study", default=None, choices=["psd_rules", "appb", "psd_trajectory"],
                     help="psd_rules: backward time of the PSD-projection rules against the matrix order; "
-                         "appb: peak HBM and time of the matrix-free backward against the problem size")
+                         "appb: peak HBM and time of the matrix-free backward against the problem size; "
+                         "psd_trajectory: the PSD-projection backward rules along a COSMO trajectory")
     args = ap.parse_args()
     if args.study == "psd_rules" and args.gpus == 1:
         psd_rules_study()
         return
     if args.study == "appb" and args.gpus == 1:
         appb_study(dense_baselines=args.dense_baselines)
+        return
+    if args.study == "psd_trajectory" and args.gpus == 1:
+        psd_trajectory_study()
         return
     if args.quick:
         args.no_cpu_baseline = True

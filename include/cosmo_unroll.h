@@ -374,6 +374,16 @@ cosmo_status cosmo_plan_get_graph(const cosmo_plan *plan, int32_t *enabled);
 cosmo_status cosmo_plan_autotune(cosmo_plan *plan, const void *rho, const void *alpha, void *ws, void *stream,
                                  double *ms);
 
+/* Per-step taps for the PSD-backward comparison study (Fig. 3 of the paper:
+ * each backward rule applied to the matrix the solver actually projects and
+ * to the cotangent the reverse pass actually delivers).  tap (d): [K][2][m_tot]
+ * of the plan's dtype, or NULL to stop.  While set, cosmo_unroll_backward
+ * stores for each unrolled step k, at tap + 2 k m_tot, the projection input
+ * v^k = s^ + y / rho_hat, and at tap + (2 k + 1) m_tot the cotangent of the
+ * projection's output s+ (net of the dual update's share), both on every row.  The tap is caller-owned and must stay valid while
+ * set; a recorded backward is recorded again when it changes. */
+cosmo_status cosmo_plan_set_tap(cosmo_plan *plan, void *tap);
+
 /* Measurement support (not needed on the hot path).  With profiling on, the
  * library records a pair of HIP events on the call's stream around every
  * launch of a kernel family: 0 = PSD eigensolve + reconstruction (all order

@@ -21,7 +21,7 @@ EXPORTED = [
     "cosmo_plan_create", "cosmo_plan_destroy", "cosmo_workspace_size", "cosmo_tape_offsets",
     "cosmo_unroll_forward", "cosmo_unroll_backward", "cosmo_residual_loss",
     "cosmo_proj_workspace_size", "psd_proj", "psd_proj_static_scratch", "psd_proj_vjp", "socp_proj", "socp_proj_vjp",
-    "cosmo_plan_set_profiling", "cosmo_plan_profile_read",
+    "cosmo_plan_set_profiling", "cosmo_plan_profile_read", "cosmo_plan_set_tap",
     "cosmo_plan_set_pcg_form", "cosmo_plan_get_pcg_form", "cosmo_plan_autotune",
     "cosmo_plan_set_graph", "cosmo_plan_get_graph",
     "psd_proj_vjp_rule", "psd_ns_tape_size", "psd_proj_ns", "psd_proj_ns_vjp",
@@ -132,6 +132,8 @@ def _sig(lib):
     lib.cosmo_residual_loss.argtypes = [vp] * 10
     lib.cosmo_proj_workspace_size.restype = sz
     lib.cosmo_proj_workspace_size.argtypes = [i32, P32]
+    lib.cosmo_plan_set_tap.restype = ctypes.c_int
+    lib.cosmo_plan_set_tap.argtypes = [vp, vp]
     lib.psd_proj.restype = ctypes.c_int
     lib.psd_proj.argtypes = [i32, P32, P64, ctypes.c_int, vp, vp, vp, vp, i32, dbl, i32, vp, vp]
     lib.psd_proj_static_scratch.restype = ctypes.c_int

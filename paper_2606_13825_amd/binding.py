@@ -349,6 +349,17 @@ class CosmoBatch:
         return [v[..., self.m_off[i]:self.m_off[i + 1]] for i in range(self.B)]
 
     # -- measurement -------------------------------------------------------------
+    def set_tap(self, tap: Optional[torch.Tensor]):
+        """Per-step taps of the backward (cosmo_plan_set_tap): tap [K, 2, m_tot]
+        of the batch's dtype receives v^k and the cotangent of the projection's
+        output, every row, at every step; None stops."""
+        if tap is not None:
+            if tap.dtype != self.dtype or tap.device != self.device or not tap.is_contiguous() or \
+                    tuple(tap.shape) != (self.K, 2, self.m_tot):
+                raise ValueError(f"tap must be a contiguous {self.dtype} tensor of shape ({self.K}, 2, {self.m_tot})")
+        self._tap = tap
+        L.check(L.lib().cosmo_plan_set_tap(self._plan, _ptr(tap)), "cosmo_plan_set_tap")
+
     def set_profiling(self, on: bool):
         L.check(L.lib().cosmo_plan_set_profiling(self._plan, int(on)), "cosmo_plan_set_profiling")
 

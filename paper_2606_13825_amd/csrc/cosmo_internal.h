@@ -128,7 +128,7 @@ template <typename T> void launch_rows_post(const View<T> &v, const RowBuckets &
                                             T *sh, T *vv, T *s_new, T *y_new, hipStream_t st);
 template <typename T> void launch_bwd_rows_a(const View<T> &v, const T *rho_hat, const T *alpha_k, const T *stl,
                                              const T *s, const T *y, const T *s_new, const T *gs_in,
-                                             const T *gy_in, T *gsn, T *gv, hipStream_t st);
+                                             const T *gy_in, T *gsn, T *gv, bool all_rows, hipStream_t st);
 template <typename T> void launch_rows_v(const View<T> &v, const T *rho_hat, const T *alpha_k, const T *stl,
                                          const T *s, const T *y, T *vv, hipStream_t st);
 template <typename T> void launch_bwd_rows_b(const View<T> &v, const T *rho_hat, const T *alpha_k, const T *stl,

@@ -217,13 +217,14 @@ __global__ __launch_bounds__(NT) void k_rows_post(View<T> v, BucketArgs ba, cons
 // ---- backward ---------------------------------------------------------------
 
 // Per row: the cotangent reaching s+ after the y-update, gsn = gs+ - rho_hat gy+;
-// separable cones apply their Jacobian (zero: 0, nonneg: mask v > 0).
+// separable cones apply their Jacobian (zero: 0, nonneg: mask v > 0).  gsn is
+// written on SOC and PSD rows, on every row when all_rows is set.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_bwd_rows_a(View<T> v, const T *__restrict__ rho_hat,
                                                    const T *__restrict__ alpha_k, const T *__restrict__ stl,
                                                    const T *__restrict__ s, const T *__restrict__ y,
                                                    const T *__restrict__ gs_in, const T *__restrict__ gy_in,
-                                                   T *__restrict__ gsn, T *__restrict__ gv) {
+                                                   T *__restrict__ gsn, T *__restrict__ gv, int all_rows) {
   const int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x;
   if (i >= v.m_tot) return;
   const T r = rho_hat[i];
@@ -234,9 +235,8 @@ __global__ __launch_bounds__(NT) void k_bwd_rows_a(View<T> v, const T *__restric
   } else if (kind == ROW_NONNEG) {
     const double vi = v_of(alpha_k[v.row_inst[i]], stl[i], s[i], y[i], r);
     gv[i] = vi > 0.0 ? g : (T)0;
-  } else {
-    gsn[i] = g;
   }
+  if (all_rows || (kind != ROW_ZERO && kind != ROW_NONNEG)) gsn[i] = g;
 }
 
 // v = s^ + y / rho_hat on every row (recomputed from the tape in the reverse pass).
@@ -516,9 +516,10 @@ void launch_rows_post(const View<T> &v, const RowBuckets &bk, const T *rho_hat, 
 
 template <typename T>
 void launch_bwd_rows_a(const View<T> &v, const T *rho_hat, const T *alpha_k, const T *stl, const T *s, const T *y,
-                       const T *s_new, const T *gs_in, const T *gy_in, T *gsn, T *gv, hipStream_t st) {
+                       const T *s_new, const T *gs_in, const T *gy_in, T *gsn, T *gv, bool all_rows, hipStream_t st) {
   (void)s_new;
-  k_bwd_rows_a<T><<<grid_for(v.m_tot), NT, 0, st>>>(v, rho_hat, alpha_k, stl, s, y, gs_in, gy_in, gsn, gv);
+  k_bwd_rows_a<T><<<grid_for(v.m_tot), NT, 0, st>>>(v, rho_hat, alpha_k, stl, s, y, gs_in, gy_in, gsn, gv,
+                                                    all_rows ? 1 : 0);
 }
 
 template <typename T>
@@ -596,7 +597,7 @@ void launch_nonfinite_check(const View<T> &v, const T *x, const T *s, const T *y
   template void launch_rows_post<T>(const View<T> &, const RowBuckets &, const T *, const T *, const T *,       \
                                     const T *, const T *, T *, T *, T *, T *, T *, hipStream_t);                \
   template void launch_bwd_rows_a<T>(const View<T> &, const T *, const T *, const T *, const T *, const T *,    \
-                                     const T *, const T *, const T *, T *, T *, hipStream_t);                   \
+                                     const T *, const T *, const T *, T *, T *, bool, hipStream_t);             \
   template void launch_rows_v<T>(const View<T> &, const T *, const T *, const T *, const T *, const T *, T *,  \
                                  hipStream_t);                                                                \
   template void launch_bwd_rows_b<T>(const View<T> &, const T *, const T *, const T *, const T *, const T *,    \

@@ -119,6 +119,7 @@ struct cosmo_plan {
     size_t rho_hat, gA, gB, gsn, gv, gsh, gst, grh, gxt, w, dg, r, z, p, Mp, t, t64, cg, vv, dk, dn, ec, ed, zero, total;
   } bw{};
   bool profiling = false;
+  void *tap = nullptr;   // cosmo_plan_set_tap: per-step projection input and output cotangent
   ProfileSlot prof[8];   // kinds of cosmo_plan_profile_read
   // auxiliary streams (default priority) and events for concurrent order classes
   hipStream_t aux[3] = {nullptr, nullptr, nullptr};
@@ -858,11 +859,16 @@ cosmo_status backward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T
     T *gx_out = gB + on, *gs_out = gB + os, *gy_out = gB + oy;
     {
       ProfScope ps(pl, 3, st);
-      launch_bwd_rows_a<T>(v, rh, al, stl, s, y, sn, gs_in, gy_in, ws + w.gsn, ws + w.gv, st);
+      launch_bwd_rows_a<T>(v, rh, al, stl, s, y, sn, gs_in, gy_in, ws + w.gsn, ws + w.gv, pl->tap != nullptr, st);
     }
-    if (pl->n_soc > 0 || pl->n_psd > 0) {
-      // v = s^ + y / rho_hat on cone rows, recomputed from the tape
+    if (pl->n_soc > 0 || pl->n_psd > 0 || pl->tap) {
+      // v = s^ + y / rho_hat on every row, recomputed from the tape
       launch_rows_v<T>(v, rh, al, stl, s, y, ws + w.vv, st);
+    }
+    if (pl->tap) {   // v^k and the cotangent of the projection's output
+      T *tp = static_cast<T *>(pl->tap) + (size_t)k * 2 * m;
+      launch_copy<T>(tp, ws + w.vv, m, st);
+      launch_copy<T>(tp + m, ws + w.gsn, m, st);
     }
     launch_soc_vjp<T>(pl->d_soc, pl->n_soc, ws + w.vv, ws + w.gsn, ws + w.gv, st);
     if (!launch_dk_classes<T>(pl, U, lam, ws + w.gsn, ws + w.gv, scratch, st))
@@ -1068,7 +1074,8 @@ cosmo_status cosmo_unroll_backward(cosmo_plan *plan, const void *rho, const void
   if (!tape) FAIL(COSMO_EINVAL, "the backward pass needs the tape written by cosmo_unroll_forward");
   if (!ws) FAIL(COSMO_EINVAL, "workspace is required");
   auto *stp = static_cast<cosmo_stats *>(stats);
-  return run_recorded(plan, plan->rec_bwd, {rho, alpha, tape, gxK, gsK, gyK, grho, galpha, gx0, gs0, gy0, ws, stats},
+  return run_recorded(plan, plan->rec_bwd,
+                      {rho, alpha, tape, gxK, gsK, gyK, grho, galpha, gx0, gs0, gy0, ws, stats, plan->tap},
                       static_cast<hipStream_t>(stream), [&](hipStream_t st) {
     if (plan->opt.dtype == COSMO_F32)
       return backward_impl<float>(plan, (const float *)rho, (const float *)alpha, (const float *)tape,
@@ -1202,6 +1209,13 @@ cosmo_status cosmo_plan_autotune(cosmo_plan *plan, const void *rho, const void *
 }
 
 // ---- profiling (not part of the hot path) -------------------------------------
+
+cosmo_status cosmo_plan_set_tap(cosmo_plan *plan, void *tap) {
+  cosmo_status s = check_plan(plan);
+  if (s != COSMO_OK) return s;
+  plan->tap = tap;
+  return COSMO_OK;
+}
 
 cosmo_status cosmo_plan_set_profiling(cosmo_plan *plan, int32_t enable) {
   cosmo_status s = check_plan(plan);

@@ -1,0 +1,116 @@
+"""The double-integrator covariance-steering generator against the problem it
+encodes (App. F, "Covariance Steering"): the PSD rows are the terminal
+Schur-complement LMI of the closed-loop covariance, and 0.5 x'Px + q'x is the
+mean-plus-covariance cost up to a constant.  Both sides are written here
+from the dynamics directly (stacked rollout matrices, traces), not from the
+generator's sparse assembly."""
+import numpy as np
+
+import synth
+from oracle.svec import smat
+
+
+def _unpack_k(inst, x):
+    """The strictly block lower-triangular feedback gain K (N nu x N nx) from x."""
+    md = inst.meta
+    N, nx, nu = md["N"], md["nx"], md["nu"]
+    K = np.zeros((N * nu, N * nx))
+    idx = md["k_base"]
+    for t in range(N):
+        for tau in range(t):
+            K[t * nu:(t + 1) * nu, tau * nx:(tau + 1) * nx] = x[idx:idx + nu * nx].reshape(nu, nx)
+            idx += nu * nx
+    assert idx == md["k_base"] + md["nk"]
+    return K
+
+
+def _rollout(A, B, t, N, nx, nu):
+    """Bbar_t, Dbar_t: x_t = A^t x_0 + Bbar_t U + Dbar_t W over the first t steps."""
+    Bb, Db = np.zeros((nx, N * nu)), np.zeros((nx, N * nx))
+    for tp in range(t):
+        Ap = np.linalg.matrix_power(A, t - 1 - tp)
+        Bb[:, tp * nu:(tp + 1) * nu] = Ap @ B
+        Db[:, tp * nx:(tp + 1) * nx] = Ap
+    return Bb, Db
+
+
+def _direct_cost(inst, x):
+    md = inst.meta
+    N, nx, nu, A, B, W = md["N"], md["nx"], md["nu"], md["A"], md["B"], md["W"]
+    K = _unpack_k(inst, x)
+    SW = np.kron(np.eye(N), W)
+    Q = np.diag([1.0, 1.0, 0.3, 0.3])
+    R = 0.1 * np.eye(nu)
+    f = 0.0
+    for t in range(N + 1):
+        Qt = 10.0 * Q if t == N else Q
+        mu = x[t * nx:(t + 1) * nx]
+        f += mu @ Qt @ mu
+        if t >= 1:
+            Bb, Db = _rollout(A, B, t, N, nx, nu)
+            F = Db + Bb @ K
+            f += np.trace(Qt @ F @ SW @ F.T)
+    v0 = (N + 1) * nx
+    for t in range(N):
+        v = x[v0 + t * nu:v0 + (t + 1) * nu]
+        f += v @ R @ v
+        Kt = K[t * nu:(t + 1) * nu]
+        f += np.trace(R @ Kt @ SW @ Kt.T)
+    f += 100.0 * x[-N * nx:].sum()
+    return f
+
+
+def test_double_integrator_lmi_is_the_terminal_covariance_bound():
+    rng = np.random.default_rng(0)
+    inst = synth.double_integrator_cs(rng)
+    md = inst.meta
+    N, nx, nu, A, B, W = md["N"], md["nx"], md["nu"], md["A"], md["B"], md["W"]
+    assert [c.kind for c in inst.cones] == ["zero", "nonneg", "psd"]
+    p = inst.cones[-1].size
+    assert p == nx + N * nx
+    for _ in range(3):
+        x = rng.standard_normal(inst.n)
+        K = _unpack_k(inst, x)
+        Bb, Db = _rollout(A, B, N, N, nx, nu)
+        F = (Db + Bb @ K) @ np.sqrt(np.kron(np.eye(N), W))
+        AN = np.linalg.matrix_power(A, N)
+        lmi = np.block([[md["sigma_N"] ** 2 * np.eye(nx) - AN @ md["Sigma_0"] @ AN.T, F],
+                        [F.T, np.eye(N * nx)]])
+        s = inst.b - inst.A @ x
+        got = smat(s[-p * (p + 1) // 2:])
+        assert np.abs(got - lmi).max() <= 1e-13 * max(1.0, np.abs(lmi).max())
+        # Schur complement: the LMI holds iff Sigma_N <= sigma_N^2 I
+        SigN = AN @ md["Sigma_0"] @ AN.T + F @ F.T
+        assert (np.linalg.eigvalsh(lmi).min() >= -1e-12) == \
+            (np.linalg.eigvalsh(md["sigma_N"] ** 2 * np.eye(nx) - SigN).min() >= -1e-12)
+
+
+def test_double_integrator_cost_matches_the_direct_cost():
+    rng = np.random.default_rng(1)
+    inst = synth.double_integrator_cs(rng)
+    obj = lambda x: 0.5 * x @ (inst.P @ x) + inst.q @ x
+    for _ in range(3):
+        x, y = rng.standard_normal(inst.n), rng.standard_normal(inst.n)
+        d_direct = _direct_cost(inst, x) - _direct_cost(inst, y)
+        assert abs((obj(x) - obj(y)) - d_direct) <= 1e-10 * max(1.0, abs(d_direct))
+
+
+def test_double_integrator_rows_encode_dynamics_and_l1_epigraph():
+    rng = np.random.default_rng(2)
+    inst = synth.double_integrator_cs(rng)
+    md = inst.meta
+    N, nx, nu, A, B = md["N"], md["nx"], md["nu"], md["A"], md["B"]
+    x = rng.standard_normal(inst.n)
+    s = inst.b - inst.A @ x
+    mu = x[:(N + 1) * nx].reshape(N + 1, nx)
+    v = x[(N + 1) * nx:(N + 1) * nx + N * nu].reshape(N, nu)
+    nuv = x[-2 * N * nx:-N * nx].reshape(N, nx)
+    e = x[-N * nx:]
+    n0, n1 = inst.cones[0].size, inst.cones[1].size
+    z = s[:n0]
+    # zero-cone slack b - A x is minus the residual of each equality
+    assert np.allclose(z[:nx], -mu[0])
+    for t in range(N):
+        assert np.allclose(z[nx + t * nx:nx + (t + 1) * nx], -(mu[t + 1] - A @ mu[t] - B @ v[t] - nuv[t]))
+    assert np.allclose(z[(N + 1) * nx:], md["goal"] - mu[N])
+    assert np.allclose(s[n0:n0 + n1], np.concatenate([e - nuv.ravel(), e + nuv.ravel()]))
