@@ -20,7 +20,10 @@ It is a plain, slow, step-by-step restatement of:
   * the final-residual training loss used by the batched max-cut workload;
   * the comparison backward rules of the PSD projection: the eigendecomposition
     rule (eq:psd-cotangent), Tikhonov-shifted and Newton-Schulz
-    (eq:newton-schulz) variants.
+    (eq:newton-schulz) variants;
+  * the learned hyperparameter policy inside the unroll and the log-residual
+    training loss (App. E "Policy Parameterization", Sec. "Experiments"),
+    in `oracle.policy`.
 
 Precision: float64 throughout.  The linear system is solved exactly with a
 sparse LU factorisation (scipy SuperLU), the tol -> 0 limit of the paper's CG.
@@ -35,6 +38,7 @@ from .cosmo import (Hyper, step_forward, unroll_forward, unroll_backward, residu
                     implicit_solve_vjp, step_backward, run_fixed, rounding_floor_runs)
 from .fd import fd_check_unroll, fd_directional
 from .psd_rules import psd_vjp_tikhonov, ns_forward, ns_vjp, psd_vjp_ns
+from . import policy
 
 __all__ = [
     "svec", "smat", "svec_len", "order_from_len",
@@ -44,5 +48,5 @@ __all__ = [
     "Hyper", "step_forward", "unroll_forward", "unroll_backward", "residual_loss",
     "residual_loss_grad", "kkt_residuals", "solve_reduced", "reduced_matrix",
     "implicit_solve_vjp", "step_backward", "run_fixed", "rounding_floor_runs",
-    "fd_check_unroll", "fd_directional",
+    "fd_check_unroll", "fd_directional", "policy",
 ]

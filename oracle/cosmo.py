@@ -141,9 +141,11 @@ def rounding_floor_runs(inst, rho: np.ndarray, alpha: np.ndarray, x0=None, s0=No
     return out
 
 
-def step_backward(inst, st: dict, gxn, gsn, gyn, sigma=1e-6):
+def step_backward(inst, st: dict, gxn, gsn, gyn, sigma=1e-6, gst_extra=None):
     """Reverse of one step: cotangents of (x+, s+, y+) -> cotangents of
-    (x, s, y) and of (rho^k, alpha^k).
+    (x, s, y) and of (rho^k, alpha^k).  gst_extra: a cotangent of s~ from
+    outside the step (the learned policy reads s~ in its delta_p feature,
+    App. E), added to the step's own.
 
     Linear solve: with the adjoint lam~ solving M lam~ = -grad_{x~}
     (eq:grad_rho), the matrix part of the penalty gradient is
@@ -167,6 +169,8 @@ def step_backward(inst, st: dict, gxn, gsn, gyn, sigma=1e-6):
     grh = grh - gv * y / rho_hat ** 2
     # s^ = alpha s~ + (1 - alpha) s ;  x+ = alpha x~ + (1 - alpha) x
     gst = alpha * gsh
+    if gst_extra is not None:
+        gst = gst + gst_extra
     gs = (1.0 - alpha) * gsh
     galpha = float(gsh @ (stl - s) + gxn @ (xt - x))
     gx = (1.0 - alpha) * gxn
