@@ -610,6 +610,87 @@ def psd_trajectory_study(K=100, seed=5, alpha=1.6, ns_iters=40, fd_rel_step=1e-6
                       "summary": summary, "steps": steps}))
 
 
+# Algorithmic flops per row of one reverse pass of the penalty network
+# (k_pol_rho_bwd): the forward recomputed (X W1' over 8 inputs, H1 W2, the
+# head) and the reverse (head, W2-bar = H1' H2-bar, H1-bar = H2-bar W2',
+# W1'-bar = X' H1-bar, the 7 feature cotangents), 2 flops per multiply-add.
+POLICY_BWD_FLOPS_PER_ROW = 2 * (8 * 32 + 32 * 32 + 32) + 2 * (32 + 32 * 32 + 32 * 32 + 8 * 32 + 7 * 32)
+
+
+def policy_study(workload="c2", reps=3, head_scale=0.05, seed=3):
+    """Cost of the learned policy inside the unroll (App. E): on the batch of
+    `workload`, one forward + backward pass with the policy choosing rho^k and
+    alpha^k at every step (cosmo_policy_forward / cosmo_policy_backward, the
+    log-residual loss) against the same batch with fixed penalties
+    (cosmo_unroll_forward, final-residual loss, cosmo_unroll_backward), HIP
+    events on the stream, mean of `reps` after one untimed pass.  No trained
+    weights exist: the parameters are App. E's initialisation with the last
+    layers drawn from U(-head_scale, head_scale) so the penalties move.
+    Prints one JSON line."""
+    import torch
+    from paper_2606_13825_amd import CosmoBatch, policy_init
+    wl = _workload(workload)
+    dev = torch.device("cuda:0")
+    tdt = torch.float32 if wl["dtype"] == "f32" else torch.float64
+    batch = CosmoBatch(wl["insts"], K=wl["K"], dtype=tdt, device=dev, cg_tol=wl.get("cg_tol"),
+                       cg_max_iter=wl.get("cg_max_iter", 500), dense_f32=wl.get("dense_f32", False))
+    theta = policy_init(seed, head_scale, tdt, dev)
+    rhos, alphas = _hyper(wl)
+    rho = torch.from_numpy(np.concatenate(rhos, axis=1)).to(dev)
+    alpha = torch.from_numpy(np.stack(alphas, axis=1)).to(dev)
+    tape, fws, bws = batch.new_tape(), batch.new_fwd_ws(), batch.new_bwd_ws()
+    pt, pw = batch.policy_sizes()
+    ptape = torch.empty(pt, dtype=torch.uint8, device=dev)
+    pws = torch.empty(pw, dtype=torch.uint8, device=dev)
+    stats = batch.new_stats()
+
+    def fixed():
+        fw = batch.forward(rho, alpha, tape=tape, ws=fws, stats=stats)
+        _, g = batch.residual_loss(fw.x, fw.s, fw.y, ws=fws)
+        batch.backward(rho, alpha, fw.tape, *g, ws=bws, stats=stats)
+
+    out = {}
+
+    def policy():
+        fw = batch.policy_forward(theta, tape=tape, ptape=ptape, pws=pws, ws=fws, stats=stats)
+        out["fw"] = fw
+        out["g"] = batch.policy_backward(theta, fw, ws=bws, stats=stats)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize(dev)
+        cur = torch.cuda.current_stream(dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(cur)
+        for _ in range(reps):
+            fn()
+        e1.record(cur)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_fixed = timed(fixed)
+    ms_policy = timed(policy)
+    fw, g = out["fw"], out["g"]
+    rho_k = fw.rho.double()
+    sd = batch.stats_dict(stats)
+    row = {"fixed_fwd_bwd_ms": ms_fixed, "policy_fwd_bwd_ms": ms_policy,
+           "policy_overhead": ms_policy / ms_fixed - 1.0,
+           "policy_loss_mean": float(fw.loss.double().mean()),
+           "rho_range": [float(rho_k.min()), float(rho_k.max())],
+           "alpha_range": [float(fw.alpha.min()), float(fw.alpha.max())],
+           "gtheta_norm": float(torch.linalg.vector_norm(g[0].double())),
+           "gtheta_finite": bool(torch.isfinite(g[0]).all()), "nonfinite": int(sd["nonfinite"].max())}
+    print(f"[bench] policy study {workload}: " + ", ".join(f"{k}={v}" for k, v in row.items()), file=sys.stderr,
+          flush=True)
+    print(json.dumps({"metric": "fwd+bwd unrolled COSMO with the learned policy vs fixed penalties (App. E)",
+                      "unit": "ms per pass", "higher_is_better": False, "dtype": wl["dtype"], "data": "synthetic",
+                      "config": {"workload": wl["name"], "K": wl["K"], "B": len(wl["insts"]), "reps": reps,
+                                 "m_tot": batch.m_tot, "n_tot": batch.n_tot, "head_scale": head_scale,
+                                 "policy_bwd_flops_per_row": POLICY_BWD_FLOPS_PER_ROW},
+                      "result": row}))
+    batch.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -634,10 +715,11 @@ def main():
                          "no event-timed step, no CPU leg)")
     ap.add_argument("--dense-baselines", action="store_true",
                     help="with --study appb: also run the dense Direct and Indirect-Full backward passes")
-    ap.add_argument("--study", default=None, choices=["psd_rules", "appb", "psd_trajectory"],
+    ap.add_argument("--study", default=None, choices=["psd_rules", "appb", "psd_trajectory", "policy"],
                     help="psd_rules: backward time of the PSD-projection rules against the matrix order; "
                          "appb: peak HBM and time of the matrix-free backward against the problem size; "
-                         "psd_trajectory: the PSD-projection backward rules along a COSMO trajectory")
+                         "psd_trajectory: the PSD-projection backward rules along a COSMO trajectory; "
+                         "policy: the learned policy's cost inside the unroll (on --workload)")
     args = ap.parse_args()
     if args.study == "psd_rules" and args.gpus == 1:
         psd_rules_study()
@@ -647,6 +729,9 @@ def main():
         return
     if args.study == "psd_trajectory" and args.gpus == 1:
         psd_trajectory_study()
+        return
+    if args.study == "policy" and args.gpus == 1:
+        policy_study(args.workload)
         return
     if args.quick:
         args.no_cpu_baseline = True

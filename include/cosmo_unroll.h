@@ -233,6 +233,60 @@ cosmo_status cosmo_unroll_backward(cosmo_plan *plan, const void *rho, const void
                                    void *galpha, void *gx0, void *gs0, void *gy0, void *ws, void *stats,
                                    void *stream);
 
+/* ---- Learned hyperparameter policy inside the unroll ---------------------
+ * App. E "Policy Parameterization" (widths, bounds and initial values from
+ * Table 2) and the log-residual loss of Sec. "Experiments".  At iterate z^k
+ * a per-row network over xi_rho,i = (l_rho,i, s_i, y_i, rbar_p,i,
+ * log(|rbar_d|_inf + 1e-12), s_i - s~_i, s_i - s^{k-1}_i) and a per-instance
+ * network over xi_alpha = (l_alpha, log(|rbar_p|_inf + 1e-12),
+ * log(|rbar_d|_inf + 1e-12), log(|s - s~|_inf + 1e-12), log(|s - s^{k-1}|_inf
+ * + 1e-12)) move the logits, l^{k+1} = l^k + MLP(xi^k), and
+ *   rho^k = exp(log 1e-3 + (log 1e3 - log 1e-3) sigmoid(l_rho^{k+1})),
+ *   alpha^k = 2 sigmoid(l_alpha^{k+1})
+ * drive the step z^k -> z^{k+1} (rho^k rectified per SOC/PSD block).  Here
+ * r_p = A x + s - b, r_d = P x + q - A'y (the sign of cosmo_residual_loss),
+ * rbar = r / N with N_p = max(|Ax|, |s|, |b|)_inf, N_d = max(|Px|, |q|,
+ * |A'y|)_inf (rbar = 0 when N = 0); the two ADMM residuals are 0 at k = 0.
+ * Loss per instance: L = sum_{k=1..K} log(|r_d^k|^2 / D_d + |r_p^k|^2 / D_p),
+ * with D = the squared norms at z^0 held constant (1 when zero).
+ *
+ * theta (d) [COSMO_POLICY_PARAMS] of the plan's dtype, shared by the batch:
+ *   penalty network: W1 [7][32] (input-major), b1 [32], W2 [32][32]
+ *   (input-major), b2 [32], w3 [32], b3 [1]; then the relaxation network the
+ *   same with W1 [5][32]; then l_rho^0 [4] for zero, nonnegative, SOC and PSD
+ *   rows, and l_alpha^0 [1].  Hidden layers are ReLU.
+ * Reverse mode: ties in an infinity norm or a normaliser's max share the
+ * cotangent evenly; |.| has derivative 0 at 0.  Calls run eagerly (they are
+ * not recorded into graphs) and, like the other calls, use no floating-point
+ * atomics: results are deterministic. */
+#define COSMO_POLICY_PARAMS 2631
+
+/* Bytes of the policy's own device memory: ptape (the logits of every step
+ * and the loss denominators; written by the forward, read by the backward)
+ * and pws (scratch, used by both).  Either pointer may be NULL. */
+cosmo_status cosmo_policy_sizes(const cosmo_plan *plan, size_t *ptape_bytes, size_t *pws_bytes);
+
+/* K steps with the policy choosing (rho^k, alpha^k).
+ *   theta (d) as above.  x0, s0, y0 (d, nullable: zeros).
+ *   rho (d) [K][m_tot], alpha (d) [K][B]: outputs, the penalties and
+ *   relaxations chosen (pass them to cosmo_policy_backward).
+ *   xK, sK, yK (d, nullable) outputs.  loss (d) [B] output.
+ *   tape (d) [tape_bytes] (NULL: forward only), ptape (d) [ptape_bytes],
+ *   ws (d) [fwd_ws_bytes], pws (d) [pws_bytes], stats (d, nullable). */
+cosmo_status cosmo_policy_forward(cosmo_plan *plan, const void *theta, const void *x0, const void *s0,
+                                  const void *y0, void *rho, void *alpha, void *xK, void *sK, void *yK, void *loss,
+                                  void *tape, void *ptape, void *ws, void *pws, void *stats, void *stream);
+
+/* Gradient of the summed loss over the batch.  theta, rho, alpha, tape,
+ * ptape as written by cosmo_policy_forward.  Outputs (d): gtheta
+ * [COSMO_POLICY_PARAMS] (required), grho [K][m_tot] and galpha [K][B]
+ * (required: the cotangents of the chosen penalties and relaxations),
+ * gx0, gs0, gy0 (nullable).  ws (d) [bwd_ws_bytes], pws (d) [pws_bytes]. */
+cosmo_status cosmo_policy_backward(cosmo_plan *plan, const void *theta, const void *rho, const void *alpha,
+                                   const void *tape, const void *ptape, void *gtheta, void *grho, void *galpha,
+                                   void *gx0, void *gs0, void *gy0, void *ws, void *pws, void *stats,
+                                   void *stream);
+
 /* Final-residual loss per instance, L_i = ||A x + s - b||^2 + ||P x + q - A'y||^2
  * (the dual residual sign follows the fixed point of the iteration above,
  * at which P x + q - A'y = 0), and its gradient when gx, gs, gy are non-NULL:

@@ -4,13 +4,16 @@ Forward: matrix-free Jacobi-PCG on the reduced system, projections onto the
 zero, nonnegative, second-order and PSD cones.  Backward: adjoint PCG
 (matrix-free implicit differentiation) and the Daleckii-Krein VJP of the PSD
 projection; the paper's comparison backward rules of the PSD projection
-(eigendecomposition rule, Tikhonov shift, Newton-Schulz).  All of it runs in the HIP library libcosmo_unroll.so behind the
-C ABI of include/cosmo_unroll.h; this package only marshals arguments.
+(eigendecomposition rule, Tikhonov shift, Newton-Schulz); the learned
+hyperparameter policy inside the unroll with the log-residual loss.  All of
+it runs in the HIP library libcosmo_unroll.so behind the C ABI of
+include/cosmo_unroll.h; this package only marshals arguments.
 """
 from .binding import (CosmoBatch, CosmoUnroll, ResidualLoss, psd_proj, psd_proj_vjp, socp_proj,
-                      socp_proj_vjp, ForwardResult, BackwardResult, psd_proj_vjp_rule, NewtonSchulzProj)
+                      socp_proj_vjp, ForwardResult, BackwardResult, psd_proj_vjp_rule, NewtonSchulzProj,
+                      PolicyForwardResult, policy_init)
 from ._lib import CosmoError, lib, LIB_PATH
 
 __all__ = ["CosmoBatch", "CosmoUnroll", "ResidualLoss", "psd_proj", "psd_proj_vjp", "socp_proj",
            "socp_proj_vjp", "ForwardResult", "BackwardResult", "CosmoError", "lib", "LIB_PATH",
-           "psd_proj_vjp_rule", "NewtonSchulzProj"]
+           "psd_proj_vjp_rule", "NewtonSchulzProj", "PolicyForwardResult", "policy_init"]

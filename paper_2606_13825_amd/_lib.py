@@ -25,7 +25,11 @@ EXPORTED = [
     "cosmo_plan_set_pcg_form", "cosmo_plan_get_pcg_form", "cosmo_plan_autotune",
     "cosmo_plan_set_graph", "cosmo_plan_get_graph",
     "psd_proj_vjp_rule", "psd_ns_tape_size", "psd_proj_ns", "psd_proj_ns_vjp",
+    "cosmo_policy_sizes", "cosmo_policy_forward", "cosmo_policy_backward",
 ]
+
+# The learned policy's flat parameter vector (include/cosmo_unroll.h)
+COSMO_POLICY_PARAMS = 2631
 
 PSD_RULES = {"dk": 0, "naive": 1, "tikhonov": 2}
 
@@ -134,6 +138,12 @@ def _sig(lib):
     lib.cosmo_proj_workspace_size.argtypes = [i32, P32]
     lib.cosmo_plan_set_tap.restype = ctypes.c_int
     lib.cosmo_plan_set_tap.argtypes = [vp, vp]
+    lib.cosmo_policy_sizes.restype = ctypes.c_int
+    lib.cosmo_policy_sizes.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+    lib.cosmo_policy_forward.restype = ctypes.c_int
+    lib.cosmo_policy_forward.argtypes = [vp] * 17
+    lib.cosmo_policy_backward.restype = ctypes.c_int
+    lib.cosmo_policy_backward.argtypes = [vp] * 16
     lib.psd_proj.restype = ctypes.c_int
     lib.psd_proj.argtypes = [i32, P32, P64, ctypes.c_int, vp, vp, vp, vp, i32, dbl, i32, vp, vp]
     lib.psd_proj_static_scratch.restype = ctypes.c_int

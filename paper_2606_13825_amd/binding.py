@@ -83,6 +83,19 @@ class ForwardResult:
 
 
 @dataclass
+class PolicyForwardResult:
+    x: torch.Tensor
+    s: torch.Tensor
+    y: torch.Tensor
+    rho: torch.Tensor
+    alpha: torch.Tensor
+    loss: torch.Tensor
+    tape: Optional[torch.Tensor]
+    ptape: torch.Tensor
+    pws: torch.Tensor
+
+
+@dataclass
 class BackwardResult:
     grho: torch.Tensor
     galpha: torch.Tensor
@@ -315,6 +328,57 @@ class CosmoBatch:
         L.check(st, "cosmo_unroll_backward")
         return BackwardResult(grho, galpha, gx0, gs0, gy0)
 
+    # -- learned policy (cosmo_policy_forward / cosmo_policy_backward) -----------
+    def policy_sizes(self):
+        """(ptape_bytes, pws_bytes) of the policy calls."""
+        pt, pw = ctypes.c_size_t(), ctypes.c_size_t()
+        L.check(L.lib().cosmo_policy_sizes(self._plan, ctypes.byref(pt), ctypes.byref(pw)), "cosmo_policy_sizes")
+        return pt.value, pw.value
+
+    def policy_forward(self, theta: torch.Tensor, x0=None, s0=None, y0=None, *, tape=True, ptape=None, pws=None,
+                       ws=None, stats=None) -> "PolicyForwardResult":
+        """K steps with the policy choosing rho^k and alpha^k; returns the final
+        iterate, the chosen rho [K, m_tot] and alpha [K, B], the per-instance
+        log-residual loss and the buffers the backward pass needs."""
+        self._check_vec(theta, L.COSMO_POLICY_PARAMS, "theta")
+        for t, n, nm in ((x0, self.n_tot, "x0"), (s0, self.m_tot, "s0"), (y0, self.m_tot, "y0")):
+            self._check_vec(t, n, nm)
+        pt_bytes, pw_bytes = self.policy_sizes()
+        tp = tape if isinstance(tape, torch.Tensor) else (self.new_tape() if tape else None)
+        ptape = ptape if ptape is not None else torch.empty(pt_bytes, dtype=torch.uint8, device=self.device)
+        pws = pws if pws is not None else torch.empty(pw_bytes, dtype=torch.uint8, device=self.device)
+        ws = ws if ws is not None else self.new_fwd_ws()
+        rho = torch.empty((self.K, self.m_tot), dtype=self.dtype, device=self.device)
+        alpha = torch.empty((self.K, self.B), dtype=self.dtype, device=self.device)
+        x = torch.empty(self.n_tot, dtype=self.dtype, device=self.device)
+        s = torch.empty(self.m_tot, dtype=self.dtype, device=self.device)
+        y = torch.empty(self.m_tot, dtype=self.dtype, device=self.device)
+        loss = torch.empty(self.B, dtype=self.dtype, device=self.device)
+        st = L.lib().cosmo_policy_forward(self._plan, _ptr(theta), _ptr(x0), _ptr(s0), _ptr(y0), _ptr(rho),
+                                          _ptr(alpha), _ptr(x), _ptr(s), _ptr(y), _ptr(loss), _ptr(tp), _ptr(ptape),
+                                          _ptr(ws), _ptr(pws), _ptr(stats), _stream(self.device))
+        L.check(st, "cosmo_policy_forward")
+        return PolicyForwardResult(x, s, y, rho, alpha, loss, tp, ptape, pws)
+
+    def policy_backward(self, theta: torch.Tensor, fw: "PolicyForwardResult", *, ws=None, stats=None):
+        """(gtheta, grho [K, m_tot], galpha [K, B], gx0, gs0, gy0) of the summed loss."""
+        if fw.tape is None:
+            raise ValueError("policy_backward needs a forward run with a tape")
+        self._check_vec(theta, L.COSMO_POLICY_PARAMS, "theta")
+        ws = ws if ws is not None else self.new_bwd_ws()
+        gtheta = torch.empty(L.COSMO_POLICY_PARAMS, dtype=self.dtype, device=self.device)
+        grho = torch.empty((self.K, self.m_tot), dtype=self.dtype, device=self.device)
+        galpha = torch.empty((self.K, self.B), dtype=self.dtype, device=self.device)
+        gx0 = torch.empty(self.n_tot, dtype=self.dtype, device=self.device)
+        gs0 = torch.empty(self.m_tot, dtype=self.dtype, device=self.device)
+        gy0 = torch.empty(self.m_tot, dtype=self.dtype, device=self.device)
+        st = L.lib().cosmo_policy_backward(self._plan, _ptr(theta), _ptr(fw.rho), _ptr(fw.alpha), _ptr(fw.tape),
+                                           _ptr(fw.ptape), _ptr(gtheta), _ptr(grho), _ptr(galpha), _ptr(gx0),
+                                           _ptr(gs0), _ptr(gy0), _ptr(ws), _ptr(fw.pws), _ptr(stats),
+                                           _stream(self.device))
+        L.check(st, "cosmo_policy_backward")
+        return gtheta, grho, galpha, gx0, gs0, gy0
+
     def residual_loss(self, x, s, y, *, grad=True, ws=None):
         ws = ws if ws is not None else self.new_fwd_ws()
         loss = torch.empty(self.B, dtype=self.dtype, device=self.device)
@@ -502,6 +566,28 @@ def psd_proj_vjp_rule(eigvals, eigvecs, gout: torch.Tensor, orders, rule: str = 
                                    _ptr(gout.contiguous()), _ptr(gin), _ptr(ws), _stream(gout.device))
     L.check(st, "psd_proj_vjp_rule")
     return gin
+
+
+def policy_init(seed: int = 0, head_scale: float = 0.0, dtype=torch.float32, device="cuda:0") -> torch.Tensor:
+    """Initial parameters of the learned policy, in the flat layout of
+    cosmo_policy_forward (App. E's initialisation): the first two layers of
+    each network ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in)); the last layer zero,
+    so the untrained policy is COSMO with fixed penalties (or, head_scale > 0,
+    ~ U(-head_scale, head_scale)); the initial logits those of Table 2's
+    penalties (100 on zero rows, 0.1 on nonnegative, SOC and PSD rows) and
+    relaxation 1.6."""
+    rng = np.random.default_rng(seed)
+    hid, parts = 32, []
+    for n_in in (7, 5):
+        parts += [rng.uniform(-1, 1, n_in * hid) / np.sqrt(n_in), rng.uniform(-1, 1, hid) / np.sqrt(n_in),
+                  rng.uniform(-1, 1, hid * hid) / np.sqrt(hid), rng.uniform(-1, 1, hid) / np.sqrt(hid)]
+        parts += [rng.uniform(-head_scale, head_scale, hid + 1) if head_scale > 0 else np.zeros(hid + 1)]
+    lmin, lmax = np.log(1e-3), np.log(1e3)
+    t = (np.log(np.array([100.0, 0.1, 0.1, 0.1])) - lmin) / (lmax - lmin)
+    parts += [np.log(t / (1 - t)), [np.log(0.8 / 0.2)]]
+    theta = np.concatenate([np.asarray(q, np.float64).ravel() for q in parts])
+    assert theta.size == L.COSMO_POLICY_PARAMS
+    return torch.from_numpy(theta).to(dtype=dtype, device=device)
 
 
 class NewtonSchulzProj:

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcosmo_unroll.so")
-SOURCES = ["plan.hip", "k_vec.hip", "k_pcg.hip", "k_soc.hip", "k_psd.hip", "k_ns.hip", "k_dense.hip"]
+SOURCES = ["plan.hip", "k_vec.hip", "k_pcg.hip", "k_soc.hip", "k_psd.hip", "k_ns.hip", "k_dense.hip", "k_policy.hip"]
 ARCH = "gfx950"
 
 

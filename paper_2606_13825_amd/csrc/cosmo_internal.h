@@ -133,7 +133,8 @@ template <typename T> void launch_rows_v(const View<T> &v, const T *rho_hat, con
                                          const T *s, const T *y, T *vv, hipStream_t st);
 template <typename T> void launch_bwd_rows_b(const View<T> &v, const T *rho_hat, const T *alpha_k, const T *stl,
                                              const T *s, const T *y, const T *s_new, const T *gy_in, const T *gv,
-                                             T *gsh, T *gst, T *gs_out, T *gy_out, T *grh, hipStream_t st);
+                                             T *gsh, T *gst, T *gs_out, T *gy_out, T *grh, const T *gst_extra,
+                                             hipStream_t st);
 template <typename T> void launch_bwd_cols(const View<T> &v, const RowBuckets &bk, const T *rho_hat,
                                            const T *alpha_k, const T *gst, const T *gx_in, double *gxt, T *dg,
                                            DiagSolve<T> ds, hipStream_t st);
@@ -148,6 +149,67 @@ template <typename T> void launch_alpha_reduce(const View<T> &v, const T *gsh, c
 template <typename T> void launch_loss(const View<T> &v, const RowBuckets &bkA, const RowBuckets &bkAt,
                                        const T *x, const T *s, const T *y, T *rp, T *rd, T *loss, T *gx,
                                        T *gs, T *gy, hipStream_t st);
+// ---- learned policy (k_policy.hip) ------------------------------------------------
+// Two networks with hidden layers of POL_H: the per-row penalty network
+// (POL_FR features) and the per-instance relaxation network (POL_FA); the
+// flat parameter layout is the public header's (COSMO_POLICY_PARAMS).
+constexpr int POL_H = 32, POL_FR = 7, POL_FA = 5;
+constexpr int POL_RHO_PARAMS = POL_FR * POL_H + POL_H + POL_H * POL_H + POL_H + POL_H + 1;
+constexpr int POL_ALPHA_PARAMS = POL_FA * POL_H + POL_H + POL_H * POL_H + POL_H + POL_H + 1;
+constexpr int POL_L0 = POL_RHO_PARAMS + POL_ALPHA_PARAMS;   // 4 per-kind penalty logits, then alpha's
+constexpr int POL_PARAMS = POL_L0 + 5;
+constexpr int POL_WAVES = 2;                                 // waves per workgroup of the per-row network
+constexpr int POL_PART_STRIDE = POL_RHO_PARAMS + 4;          // a workgroup's partial: the network, 4 kind sums
+static_assert(POL_PARAMS == COSMO_POLICY_PARAMS, "policy parameter count");
+
+// Per instance at one iterate: infinity norms of A x (nu), s, b, P x (np),
+// q, A' y (nw), r_p, r_d, dp, dd; squared norms of r_p and r_d; how many
+// entries attain each norm (ties).
+struct PolRec {
+  double nu, ns, nb, np, nq, nw, mrp, mrd, mdp, mdd, ssp, ssd;
+  int32_t cu, cs, crp, cp, cw, crd, cdp, cdd;
+};
+// Per instance, the reverse step's coefficients: 1/N_p; the cotangent
+// reaching each entry that attains a norm (already divided by the tie count)
+// for r_p, A x, s, r_d, P x, A' y, dp, dd; and the loss term's 2/(D S).
+struct PolCoef {
+  double inv_np, c_rp, c_u, c_s, c_rd, c_p, c_w, c_dp, c_dd, cl_p, cl_d;
+};
+int64_t pol_row_blocks(int64_t m);
+template <typename T> void launch_pol_norms(const View<T> &v, const T *u, const T *rp, const T *p, const T *w,
+                                            const T *rd, const T *s, const T *s_prev, const T *st_prev, PolRec *rec,
+                                            hipStream_t st);
+template <typename T> void launch_pol_inst_fwd(const View<T> &v, const T *theta, const PolRec *rec, int32_t k,
+                                               int32_t policy, const T *la_in, T *la_out, T *alpha_k, double *acc3,
+                                               T *loss, hipStream_t st);
+template <typename T> void launch_pol_rho_fwd(const View<T> &v, const T *theta, const PolRec *rec, const T *l_in,
+                                              T *l_out, T *rho_k, const T *s, const T *y, const T *rp,
+                                              const T *s_prev, const T *st_prev, hipStream_t st);
+template <typename T> void launch_pol_rho_bwd(const View<T> &v, const T *theta, const PolRec *rec, const T *l_in,
+                                              const T *s, const T *y, const T *rp, const T *s_prev,
+                                              const T *st_prev, const T *grho_k, T *C, T *gs, T *gy, T *xb, T *part,
+                                              hipStream_t st);
+template <typename T> void launch_pol_inst_bwd(const View<T> &v, const T *theta, const PolRec *rec, int32_t k,
+                                               int32_t policy, int32_t loss_term, const T *la_in, const T *galpha_k,
+                                               T *Ca, const T *xb, const T *rp, const double *acc3, PolCoef *coef,
+                                               T *parta, hipStream_t st);
+template <typename T> void launch_pol_rows_bwd(const View<T> &v, const PolRec *rec, const PolCoef *coef, const T *xb,
+                                               const T *rp, const T *u, const T *s, const T *s_prev,
+                                               const T *st_prev, T *gs, T *ub, T *pend_st, T *pend_s,
+                                               int32_t add_pend, int32_t write_pend, hipStream_t st);
+template <typename T> void launch_pol_cols_bwd(const View<T> &v, const PolRec *rec, const PolCoef *coef, const T *rd,
+                                               const T *p, const T *w, T *pb, T *wb, hipStream_t st);
+template <typename T> void launch_pol_grad(const View<T> &v, const T *part, int64_t nblk, const T *parta, const T *Ca,
+                                           T *gtheta, hipStream_t st);
+
+// Learned policy (k_vec.hip): u = A x, rp = u + s - b, p = P x, w = A' y,
+// rd = p + q - w; and the adjoint gx += A' ub + P pb, gy += A wb.
+template <typename T> void launch_pol_resid(const View<T> &v, const RowBuckets &bkA, const RowBuckets &bkAt,
+                                            const T *x, const T *s, const T *y, T *u, T *rp, T *p, T *w, T *rd,
+                                            hipStream_t st);
+template <typename T> void launch_pol_resid_adjoint(const View<T> &v, const RowBuckets &bkA, const RowBuckets &bkAt,
+                                                    const T *ub, const T *pb, const T *wb, T *gx, T *gy,
+                                                    hipStream_t st);
 template <typename T> void launch_copy(T *dst, const T *src, int64_t n, hipStream_t st);
 template <typename T> void launch_fill(T *dst, T val, int64_t n, hipStream_t st);
 template <typename T> void launch_nonfinite_check(const View<T> &v, const T *x, const T *s, const T *y,

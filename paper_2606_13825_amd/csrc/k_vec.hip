@@ -252,7 +252,8 @@ __global__ __launch_bounds__(NT) void k_rows_v(View<T> v, const T *__restrict__ 
 
 // Per row, once every cone has produced v-bar:
 //   gs^ = rho_hat gy+ + gv;  gy = gy+ + gv / rho_hat;
-//   grh = gy+ (s^ - s+) - gv y / rho_hat^2;  gs~ = alpha gs^;  gs = (1 - alpha) gs^.
+//   grh = gy+ (s^ - s+) - gv y / rho_hat^2;  gs~ = alpha gs^ (+ gst_extra, a
+//   cotangent of s~ from outside the step);  gs = (1 - alpha) gs^.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_bwd_rows_b(View<T> v, const T *__restrict__ rho_hat,
                                                    const T *__restrict__ alpha_k, const T *__restrict__ stl,
@@ -260,7 +261,8 @@ __global__ __launch_bounds__(NT) void k_bwd_rows_b(View<T> v, const T *__restric
                                                    const T *__restrict__ s_new, const T *__restrict__ gy_in,
                                                    const T *__restrict__ gv, T *__restrict__ gsh,
                                                    T *__restrict__ gst, T *__restrict__ gs_out,
-                                                   T *__restrict__ gy_out, T *__restrict__ grh) {
+                                                   T *__restrict__ gy_out, T *__restrict__ grh,
+                                                   const T *__restrict__ gst_extra) {
   const int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x;
   if (i >= v.m_tot) return;
   const double r = rho_hat[i];
@@ -272,7 +274,7 @@ __global__ __launch_bounds__(NT) void k_bwd_rows_b(View<T> v, const T *__restric
   gsh[i] = (T)g_sh;
   gy_out[i] = (T)(gyp + g_v / r);
   grh[i] = (T)(gyp * (shat - (double)s_new[i]) - g_v * (double)y[i] / (r * r));
-  gst[i] = (T)((double)al * g_sh);
+  gst[i] = (T)((double)al * g_sh + (gst_extra ? (double)gst_extra[i] : 0.0));
   gs_out[i] = (T)((1.0 - (double)al) * g_sh);
 }
 
@@ -454,6 +456,83 @@ __global__ __launch_bounds__(NT) void k_loss_gsy(View<T> v, BucketArgs ba, const
   }
 }
 
+// ---- learned policy: KKT residual vectors and their adjoint (App. E) ---------
+
+// u = A x and rp = u + s - b on every row.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_pol_rows(View<T> v, BucketArgs ba, const T *__restrict__ x,
+                                                 const T *__restrict__ s, T *__restrict__ u, T *__restrict__ rp) {
+  BUCKET_PREAMBLE
+  const int64_t i = bp.row;
+  double ax = 0;
+  for (int64_t k = v.A_rowptr[i] + bp.lane; k < v.A_rowptr[i + 1]; k += bp.L)
+    ax += (double)v.A_val[k] * (double)x[v.A_col[k]];
+  ax = subwave_sum(ax, bp.L);
+  if (bp.lane == 0) {
+    ax += dense_row_term(v, i);
+    u[i] = (T)ax;
+    rp[i] = (T)(ax + (double)s[i] - (double)v.b[i]);
+  }
+}
+
+// p = P x, w = A' y and rd = p + q - w on every column.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_pol_cols(View<T> v, BucketArgs ba, const T *__restrict__ x,
+                                                 const T *__restrict__ y, T *__restrict__ p, T *__restrict__ w,
+                                                 T *__restrict__ rd) {
+  BUCKET_PREAMBLE
+  const int64_t j = bp.row;
+  double aw = 0, ap = 0;
+  for (int64_t k = v.At_rowptr[j] + bp.lane; k < v.At_rowptr[j + 1]; k += bp.L)
+    aw += (double)v.At_val[k] * (double)y[v.At_col[k]];
+  if (v.P_rowptr)
+    for (int64_t k = v.P_rowptr[j] + bp.lane; k < v.P_rowptr[j + 1]; k += bp.L)
+      ap += (double)v.P_val[k] * (double)x[v.P_col[k]];
+  aw = subwave_sum(aw, bp.L);
+  ap = subwave_sum(ap, bp.L);
+  if (bp.lane == 0) {
+    double e, d;
+    dense_col_terms(v, j, e, d);
+    aw += e;
+    p[j] = (T)ap;
+    w[j] = (T)aw;
+    rd[j] = (T)(ap + (double)v.q[j] - aw);
+  }
+}
+
+// gx_j += (A' ub)_j + (P pb)_j  (P symmetric)
+template <typename T>
+__global__ __launch_bounds__(NT) void k_pol_adj_cols(View<T> v, BucketArgs ba, const T *__restrict__ ub,
+                                                     const T *__restrict__ pb, T *__restrict__ gx) {
+  BUCKET_PREAMBLE
+  const int64_t j = bp.row;
+  double acc = 0;
+  for (int64_t k = v.At_rowptr[j] + bp.lane; k < v.At_rowptr[j + 1]; k += bp.L)
+    acc += (double)v.At_val[k] * (double)ub[v.At_col[k]];
+  if (v.P_rowptr)
+    for (int64_t k = v.P_rowptr[j] + bp.lane; k < v.P_rowptr[j + 1]; k += bp.L)
+      acc += (double)v.P_val[k] * (double)pb[v.P_col[k]];
+  acc = subwave_sum(acc, bp.L);
+  if (bp.lane == 0) {
+    double e, d;
+    dense_col_terms(v, j, e, d);
+    gx[j] = (T)((double)gx[j] + acc + e);
+  }
+}
+
+// gy_i += (A wb)_i
+template <typename T>
+__global__ __launch_bounds__(NT) void k_pol_adj_rows(View<T> v, BucketArgs ba, const T *__restrict__ wb,
+                                                     T *__restrict__ gy) {
+  BUCKET_PREAMBLE
+  const int64_t i = bp.row;
+  double acc = 0;
+  for (int64_t k = v.A_rowptr[i] + bp.lane; k < v.A_rowptr[i + 1]; k += bp.L)
+    acc += (double)v.A_val[k] * (double)wb[v.A_col[k]];
+  acc = subwave_sum(acc, bp.L);
+  if (bp.lane == 0) gy[i] = (T)((double)gy[i] + acc + dense_row_term(v, i));
+}
+
 // ---- health check ---------------------------------------------------------------
 
 template <typename T>
@@ -531,9 +610,9 @@ void launch_rows_v(const View<T> &v, const T *rho_hat, const T *alpha_k, const T
 template <typename T>
 void launch_bwd_rows_b(const View<T> &v, const T *rho_hat, const T *alpha_k, const T *stl, const T *s, const T *y,
                        const T *s_new, const T *gy_in, const T *gv, T *gsh, T *gst, T *gs_out, T *gy_out, T *grh,
-                       hipStream_t st) {
+                       const T *gst_extra, hipStream_t st) {
   k_bwd_rows_b<T><<<grid_for(v.m_tot), NT, 0, st>>>(v, rho_hat, alpha_k, stl, s, y, s_new, gy_in, gv, gsh, gst,
-                                                    gs_out, gy_out, grh);
+                                                    gs_out, gy_out, grh, gst_extra);
 }
 
 template <typename T>
@@ -574,6 +653,26 @@ void launch_loss(const View<T> &v, const RowBuckets &bkA, const RowBuckets &bkAt
   if ((gs || gy) && nblocks_bucket(a) > 0) k_loss_gsy<T><<<(int)nblocks_bucket(a), NT, 0, st>>>(v, a, rp, rd, gs, gy);
 }
 
+template <typename T>
+void launch_pol_resid(const View<T> &v, const RowBuckets &bkA, const RowBuckets &bkAt, const T *x, const T *s,
+                      const T *y, T *u, T *rp, T *p, T *w, T *rd, hipStream_t st) {
+  BucketArgs a = make_bucket_args(bkA), at = make_bucket_args(bkAt);
+  launch_dense_rows<T>(v, x, st);
+  if (nblocks_bucket(a) > 0) k_pol_rows<T><<<(int)nblocks_bucket(a), NT, 0, st>>>(v, a, x, s, u, rp);
+  launch_dense_cols<T>(v, DC_Y, nullptr, y, nullptr, st);
+  if (nblocks_bucket(at) > 0) k_pol_cols<T><<<(int)nblocks_bucket(at), NT, 0, st>>>(v, at, x, y, p, w, rd);
+}
+
+template <typename T>
+void launch_pol_resid_adjoint(const View<T> &v, const RowBuckets &bkA, const RowBuckets &bkAt, const T *ub,
+                              const T *pb, const T *wb, T *gx, T *gy, hipStream_t st) {
+  BucketArgs a = make_bucket_args(bkA), at = make_bucket_args(bkAt);
+  launch_dense_cols<T>(v, DC_RP, nullptr, ub, nullptr, st);
+  if (nblocks_bucket(at) > 0) k_pol_adj_cols<T><<<(int)nblocks_bucket(at), NT, 0, st>>>(v, at, ub, pb, gx);
+  launch_dense_rows<T>(v, wb, st);
+  if (nblocks_bucket(a) > 0) k_pol_adj_rows<T><<<(int)nblocks_bucket(a), NT, 0, st>>>(v, a, wb, gy);
+}
+
 template <typename T> void launch_copy(T *dst, const T *src, int64_t n, hipStream_t st) {
   if (n > 0) k_copy<T><<<grid_for(n), NT, 0, st>>>(dst, src, n);
 }
@@ -601,7 +700,7 @@ void launch_nonfinite_check(const View<T> &v, const T *x, const T *s, const T *y
   template void launch_rows_v<T>(const View<T> &, const T *, const T *, const T *, const T *, const T *, T *,  \
                                  hipStream_t);                                                                \
   template void launch_bwd_rows_b<T>(const View<T> &, const T *, const T *, const T *, const T *, const T *,    \
-                                     const T *, const T *, const T *, T *, T *, T *, T *, T *, hipStream_t);    \
+                                     const T *, const T *, const T *, T *, T *, T *, T *, T *, const T *, hipStream_t);    \
   template void launch_bwd_cols<T>(const View<T> &, const RowBuckets &, const T *, const T *, const T *,        \
                                    const T *, double *, T *, DiagSolve<T>, hipStream_t);                             \
   template void launch_bwd_rows_c<T>(const View<T> &, const RowBuckets &, const T *, const T *, const T *,      \
@@ -610,6 +709,10 @@ void launch_nonfinite_check(const View<T> &v, const T *x, const T *s, const T *y
                                        const T *, T *, hipStream_t);                                            \
   template void launch_loss<T>(const View<T> &, const RowBuckets &, const RowBuckets &, const T *, const T *,   \
                                const T *, T *, T *, T *, T *, T *, T *, hipStream_t);                           \
+  template void launch_pol_resid<T>(const View<T> &, const RowBuckets &, const RowBuckets &, const T *,         \
+                                    const T *, const T *, T *, T *, T *, T *, T *, hipStream_t);                \
+  template void launch_pol_resid_adjoint<T>(const View<T> &, const RowBuckets &, const RowBuckets &, const T *, \
+                                            const T *, const T *, T *, T *, hipStream_t);                       \
   template void launch_copy<T>(T *, const T *, int64_t, hipStream_t);                                           \
   template void launch_fill<T>(T *, T, int64_t, hipStream_t);                                                   \
   template void launch_nonfinite_check<T>(const View<T> &, const T *, const T *, const T *, cosmo_stats *,      \

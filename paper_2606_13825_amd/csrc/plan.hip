@@ -759,16 +759,140 @@ bool launch_dk_classes(cosmo_plan *pl, const T *U, const T *lam, const T *g, T *
   return ok;
 }
 
+// ---- learned policy (App. E "Policy Parameterization") -------------------------
+
+// Byte offsets of the policy's tape (logits of every step, the loss's
+// denominators and running sum) and of its scratch.
+struct PolLayout {
+  size_t lr, la, acc3, ptape;
+  size_t u, rp, p, w, rd, rec, coef, C, Ca, xb, ub, pb, wb, pend_st, pend_s, part, parta, pws;
+  int64_t nblk;
+};
+
+PolLayout policy_layout(const cosmo_plan *pl) {
+  const size_t esz = pl->esz, m = (size_t)pl->m_tot, n = (size_t)pl->n_tot, B = (size_t)pl->B;
+  const size_t K = (size_t)pl->opt.K;
+  PolLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = o;
+    o = align_up(o + std::max<size_t>(bytes, 1), 256);
+    return r;
+  };
+  L.lr = take((K + 1) * m * esz);
+  L.la = take((K + 1) * B * esz);
+  L.acc3 = take(3 * B * sizeof(double));
+  L.ptape = o;
+  o = 0;
+  L.u = take(m * esz);
+  L.rp = take(m * esz);
+  L.p = take(n * esz);
+  L.w = take(n * esz);
+  L.rd = take(n * esz);
+  L.rec = take(B * sizeof(PolRec));
+  L.coef = take(B * sizeof(PolCoef));
+  L.C = take(m * esz);
+  L.Ca = take(B * esz);
+  L.xb = take(4 * m * esz);
+  L.ub = take(m * esz);
+  L.pb = take(n * esz);
+  L.wb = take(n * esz);
+  L.pend_st = take(m * esz);
+  L.pend_s = take(m * esz);
+  L.nblk = pol_row_blocks(pl->m_tot);
+  L.part = take((size_t)L.nblk * POL_PART_STRIDE * esz);
+  L.parta = take(B * POL_ALPHA_PARAMS * esz);
+  L.pws = o;
+  return L;
+}
+
+// One policy call's buffers.
+template <typename T> struct PolRun {
+  PolLayout L;
+  const T *theta = nullptr;
+  T *rho = nullptr, *alpha = nullptr, *loss = nullptr;   // forward outputs
+  T *lr = nullptr, *la = nullptr;                        // logits l^0..l^K (slot 0 unused: theta's)
+  double *acc3 = nullptr;                                // per instance D_d, D_p, loss sum
+  unsigned char *pws = nullptr;
+  T *gtheta = nullptr;
+  template <typename U> U *at(size_t off) const { return reinterpret_cast<U *>(pws + off); }
+};
+
+template <typename T>
+PolRun<T> make_pol_run(const cosmo_plan *plan, const void *theta, void *ptape, void *pws) {
+  PolRun<T> P;
+  P.L = policy_layout(plan);
+  P.theta = static_cast<const T *>(theta);
+  auto *pt = static_cast<unsigned char *>(ptape);
+  P.lr = reinterpret_cast<T *>(pt + P.L.lr);
+  P.la = reinterpret_cast<T *>(pt + P.L.la);
+  P.acc3 = reinterpret_cast<double *>(pt + P.L.acc3);
+  P.pws = static_cast<unsigned char *>(pws);
+  return P;
+}
+// The policy at iterate k < K (features -> logits -> rho^k, alpha^k, then
+// rho^k rectified into rho_hat), or at k = K only the loss term.
+template <typename T>
+void policy_fwd_at(cosmo_plan *pl, const View<T> &v, const PolRun<T> &P, int k, const T *x, const T *s, const T *y,
+                   const T *s_prev, const T *st_prev, T *rho_hat, hipStream_t st) {
+  const size_t m = (size_t)pl->m_tot, B = (size_t)pl->B;
+  const bool pol = k < pl->opt.K;
+  T *u = P.template at<T>(P.L.u), *rp = P.template at<T>(P.L.rp), *p = P.template at<T>(P.L.p);
+  T *w = P.template at<T>(P.L.w), *rd = P.template at<T>(P.L.rd);
+  PolRec *rec = P.template at<PolRec>(P.L.rec);
+  launch_pol_resid<T>(v, pl->bkA, pl->bkAt, x, s, y, u, rp, p, w, rd, st);
+  launch_pol_norms<T>(v, u, rp, p, w, rd, s, s_prev, st_prev, rec, st);
+  launch_pol_inst_fwd<T>(v, P.theta, rec, k, pol ? 1 : 0, k > 0 ? P.la + k * B : nullptr,
+                         pol ? P.la + (k + 1) * B : nullptr, pol ? P.alpha + k * B : nullptr, P.acc3, P.loss, st);
+  if (!pol) return;
+  launch_pol_rho_fwd<T>(v, P.theta, rec, k > 0 ? P.lr + k * m : nullptr, P.lr + (k + 1) * m, P.rho + k * m, s, y, rp,
+                        s_prev, st_prev, st);
+  launch_rectify<T>(v, pl->d_rect, pl->n_rect, P.rho + k * m, rho_hat + k * m, 1, st);
+}
+
+// Reverse of the policy and of the loss term at iterate k: adds their
+// cotangents of z^k into (gx, gs, gy); k = K: the loss term only.
+template <typename T>
+void policy_bwd_at(cosmo_plan *pl, const View<T> &v, const PolRun<T> &P, int k, const T *tape, const T *grho,
+                   const T *galpha, T *gx, T *gs, T *gy, hipStream_t st) {
+  const size_t m = (size_t)pl->m_tot, B = (size_t)pl->B;
+  const bool pol = k < pl->opt.K;
+  const T *x = tape + slot_x(pl, k), *s = tape + slot_s(pl, k), *y = tape + slot_y(pl, k);
+  const T *s_prev = (pol && k > 0) ? tape + slot_s(pl, k - 1) : nullptr;
+  const T *st_prev = (pol && k > 0) ? tape + step_base(pl, k - 1) + pl->tp.st : nullptr;
+  T *u = P.template at<T>(P.L.u), *rp = P.template at<T>(P.L.rp), *p = P.template at<T>(P.L.p);
+  T *w = P.template at<T>(P.L.w), *rd = P.template at<T>(P.L.rd), *xb = P.template at<T>(P.L.xb);
+  T *C = P.template at<T>(P.L.C), *Ca = P.template at<T>(P.L.Ca);
+  T *ub = P.template at<T>(P.L.ub), *pb = P.template at<T>(P.L.pb), *wb = P.template at<T>(P.L.wb);
+  T *pend_st = P.template at<T>(P.L.pend_st), *pend_s = P.template at<T>(P.L.pend_s);
+  PolRec *rec = P.template at<PolRec>(P.L.rec);
+  PolCoef *coef = P.template at<PolCoef>(P.L.coef);
+  launch_pol_resid<T>(v, pl->bkA, pl->bkAt, x, s, y, u, rp, p, w, rd, st);
+  launch_pol_norms<T>(v, u, rp, p, w, rd, s, s_prev, st_prev, rec, st);
+  if (pol)
+    launch_pol_rho_bwd<T>(v, P.theta, rec, k > 0 ? P.lr + k * m : nullptr, s, y, rp, s_prev, st_prev, grho + k * m, C,
+                          gs, gy, xb, P.template at<T>(P.L.part), st);
+  launch_pol_inst_bwd<T>(v, P.theta, rec, k, pol ? 1 : 0, k >= 1 ? 1 : 0, k > 0 ? P.la + k * B : nullptr,
+                         pol ? galpha + k * B : nullptr, Ca, pol ? xb : nullptr, rp, P.acc3, coef,
+                         P.template at<T>(P.L.parta), st);
+  launch_pol_rows_bwd<T>(v, rec, coef, pol ? xb : nullptr, rp, u, s, s_prev, st_prev, gs, ub, pend_st, pend_s,
+                         pol ? 1 : 0, pol ? 1 : 0, st);
+  launch_pol_cols_bwd<T>(v, rec, coef, rd, p, w, pb, wb, st);
+  launch_pol_resid_adjoint<T>(v, pl->bkA, pl->bkAt, ub, pb, wb, gx, gy, st);
+}
+
 template <typename T>
 cosmo_status forward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T *x0, const T *s0, const T *y0, T *xK,
-                          T *sK, T *yK, T *tape, T *ws, cosmo_stats *stats, hipStream_t st) {
+                          T *sK, T *yK, T *tape, T *ws, cosmo_stats *stats, hipStream_t st,
+                          const PolRun<T> *pol = nullptr) {
   View<T> v = make_view<T>(pl);
   const int64_t n = pl->n_tot, m = pl->m_tot;
   const int K = pl->opt.K;
   auto &f = pl->fw;
   bind_dense(v, ws, f.dn, f.ec, f.ed);
   T *rho_hat = ws + f.rho_hat;
-  launch_rectify<T>(v, pl->d_rect, pl->n_rect, rho, rho_hat, K, st);
+  // with the policy, each step's penalties are chosen and rectified at its iterate
+  if (!pol) launch_rectify<T>(v, pl->d_rect, pl->n_rect, rho, rho_hat, K, st);
   auto X = [&](int k) -> T * { return tape ? tape + slot_x(pl, k) : ws + ((k & 1) ? f.itB : f.itA); };
   auto S = [&](int k) -> T * {
     return tape ? tape + slot_s(pl, k) : ws + ((k & 1) ? f.itB : f.itA) + align_up(n, 64);
@@ -784,8 +908,12 @@ cosmo_status forward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T 
   if (s0) launch_copy<T>(S(0), s0, m, st); else launch_fill<T>(S(0), (T)0, m, st);
   if (y0) launch_copy<T>(Y(0), y0, m, st); else launch_fill<T>(Y(0), (T)0, m, st);
   for (int k = 0; k < K; ++k) {
+    // s^{k-1} and the s~ that produced s^k: without a tape they are the other
+    // iterate buffer and the single s~ buffer, both still intact here
+    if (pol) policy_fwd_at<T>(pl, v, *pol, k, X(k), S(k), Y(k), k > 0 ? S(k - 1) : nullptr, k > 0 ? ST(k - 1) : nullptr,
+                              rho_hat, st);
     const T *rh = rho_hat + (size_t)k * m;
-    const T *al = alpha + (size_t)k * pl->B;
+    const T *al = (pol ? pol->alpha : alpha) + (size_t)k * pl->B;
     T *x = X(k), *s = S(k), *y = Y(k), *xn = X(k + 1), *sn = S(k + 1), *yn = Y(k + 1);
     T *xt = XT(k);
     DiagSolve<T> ds;
@@ -821,6 +949,7 @@ cosmo_status forward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T 
     launch_psd_classes<T>(pl, rh, ws + f.vv, ws + f.sh, y, sn, yn, UU(k), LAM(k),
                           reinterpret_cast<double *>(ws + f.rs), Uprev, stats, st);
   }
+  if (pol) policy_fwd_at<T>(pl, v, *pol, K, X(K), S(K), Y(K), nullptr, nullptr, rho_hat, st);
   launch_nonfinite_check<T>(v, X(K), S(K), Y(K), stats, st);
   if (xK) launch_copy<T>(xK, X(K), n, st);
   if (sK) launch_copy<T>(sK, S(K), m, st);
@@ -832,7 +961,7 @@ cosmo_status forward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T 
 template <typename T>
 cosmo_status backward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T *tape, const T *gxK, const T *gsK,
                            const T *gyK, T *grho, T *galpha, T *gx0, T *gs0, T *gy0, T *ws, cosmo_stats *stats,
-                           hipStream_t st) {
+                           hipStream_t st, const PolRun<T> *pol = nullptr) {
   View<T> v = make_view<T>(pl);
   const int64_t n = pl->n_tot, m = pl->m_tot;
   const int K = pl->opt.K;
@@ -845,6 +974,18 @@ cosmo_status backward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T
   if (gxK) launch_copy<T>(gA + on, gxK, n, st); else launch_fill<T>(gA + on, (T)0, n, st);
   if (gsK) launch_copy<T>(gA + os, gsK, m, st); else launch_fill<T>(gA + os, (T)0, m, st);
   if (gyK) launch_copy<T>(gA + oy, gyK, m, st); else launch_fill<T>(gA + oy, (T)0, m, st);
+  T *pend_st = nullptr;
+  if (pol) {
+    // the policy's accumulators start at zero; the loss term at z^K seeds the reverse pass
+    pend_st = pol->template at<T>(pol->L.pend_st);
+    launch_fill<T>(pol->template at<T>(pol->L.C), (T)0, m, st);
+    launch_fill<T>(pol->template at<T>(pol->L.Ca), (T)0, pl->B, st);
+    launch_fill<T>(pend_st, (T)0, m, st);
+    launch_fill<T>(pol->template at<T>(pol->L.pend_s), (T)0, m, st);
+    launch_fill<T>(pol->template at<T>(pol->L.part), (T)0, pol->L.nblk * POL_PART_STRIDE, st);
+    launch_fill<T>(pol->template at<T>(pol->L.parta), (T)0, (int64_t)pl->B * POL_ALPHA_PARAMS, st);
+    policy_bwd_at<T>(pl, v, *pol, K, tape, grho, galpha, gA + on, gA + os, gA + oy, st);
+  }
   launch_fill<T>(ws + w.w, (T)0, n, st);
   launch_fill<T>(ws + w.gsn, (T)0, m, st);
   T *scratch = ws + w.dk;
@@ -876,7 +1017,7 @@ cosmo_status backward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T
     {
       ProfScope ps(pl, 3, st);
       launch_bwd_rows_b<T>(v, rh, al, stl, s, y, sn, gy_in, ws + w.gv, ws + w.gsh, ws + w.gst, gs_out, gy_out,
-                           ws + w.grh, st);
+                           ws + w.grh, pend_st, st);
       DiagSolve<T> ds;
       if (pl->diag_M) {
         ds.xt = ws + w.w;
@@ -899,8 +1040,12 @@ cosmo_status backward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T
     }
     if (grho) launch_rect_adjoint<T>(v, pl->d_rect, pl->n_rect, ws + w.grh, grho + (size_t)k * m, st);
     if (galpha) launch_alpha_reduce<T>(v, ws + w.gsh, stl, s, gx_in, xt, x, galpha + (size_t)k * pl->B, st);
+    if (pol) policy_bwd_at<T>(pl, v, *pol, k, tape, grho, galpha, gx_out, gs_out, gy_out, st);
     std::swap(gA, gB);
   }
+  if (pol)
+    launch_pol_grad<T>(v, pol->template at<T>(pol->L.part), pol->L.nblk, pol->template at<T>(pol->L.parta),
+                       pol->template at<T>(pol->L.Ca), pol->gtheta, st);
   if (gx0) launch_copy<T>(gx0, gA + on, n, st);
   if (gs0) launch_copy<T>(gs0, gA + os, m, st);
   if (gy0) launch_copy<T>(gy0, gA + oy, m, st);
@@ -1085,6 +1230,74 @@ cosmo_status cosmo_unroll_backward(cosmo_plan *plan, const void *rho, const void
                                  (const double *)gxK, (const double *)gsK, (const double *)gyK, (double *)grho,
                                  (double *)galpha, (double *)gx0, (double *)gs0, (double *)gy0, (double *)ws, stp, st);
   });
+}
+
+cosmo_status cosmo_policy_sizes(const cosmo_plan *plan, size_t *ptape_bytes, size_t *pws_bytes) {
+  cosmo_status s0 = check_plan(plan);
+  if (s0 != COSMO_OK) return s0;
+  const PolLayout L = policy_layout(plan);
+  if (ptape_bytes) *ptape_bytes = L.ptape;
+  if (pws_bytes) *pws_bytes = L.pws;
+  return COSMO_OK;
+}
+
+cosmo_status cosmo_policy_forward(cosmo_plan *plan, const void *theta, const void *x0, const void *s0,
+                                  const void *y0, void *rho, void *alpha, void *xK, void *sK, void *yK, void *loss,
+                                  void *tape, void *ptape, void *ws, void *pws, void *stats, void *stream) {
+  cosmo_status st0 = check_plan(plan);
+  if (st0 != COSMO_OK) return st0;
+  if (!theta || !rho || !alpha || !loss || !ptape || !ws || !pws)
+    FAIL(COSMO_EINVAL, "theta, rho, alpha, loss, ptape, ws and pws are required");
+  auto *stp = static_cast<cosmo_stats *>(stats);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  cosmo_status r;
+  if (plan->opt.dtype == COSMO_F32) {
+    PolRun<float> P = make_pol_run<float>(plan, theta, ptape, pws);
+    P.rho = (float *)rho;
+    P.alpha = (float *)alpha;
+    P.loss = (float *)loss;
+    r = forward_impl<float>(plan, nullptr, nullptr, (const float *)x0, (const float *)s0, (const float *)y0,
+                            (float *)xK, (float *)sK, (float *)yK, (float *)tape, (float *)ws, stp, st, &P);
+  } else {
+    PolRun<double> P = make_pol_run<double>(plan, theta, ptape, pws);
+    P.rho = (double *)rho;
+    P.alpha = (double *)alpha;
+    P.loss = (double *)loss;
+    r = forward_impl<double>(plan, nullptr, nullptr, (const double *)x0, (const double *)s0, (const double *)y0,
+                             (double *)xK, (double *)sK, (double *)yK, (double *)tape, (double *)ws, stp, st, &P);
+  }
+  if (r != COSMO_OK) return r;
+  HIPCHK(hipGetLastError());
+  return COSMO_OK;
+}
+
+cosmo_status cosmo_policy_backward(cosmo_plan *plan, const void *theta, const void *rho, const void *alpha,
+                                   const void *tape, const void *ptape, void *gtheta, void *grho, void *galpha,
+                                   void *gx0, void *gs0, void *gy0, void *ws, void *pws, void *stats,
+                                   void *stream) {
+  cosmo_status st0 = check_plan(plan);
+  if (st0 != COSMO_OK) return st0;
+  if (!theta || !rho || !alpha || !tape || !ptape || !gtheta || !grho || !galpha || !ws || !pws)
+    FAIL(COSMO_EINVAL, "theta, rho, alpha, tape, ptape, gtheta, grho, galpha, ws and pws are required");
+  auto *stp = static_cast<cosmo_stats *>(stats);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  cosmo_status r;
+  if (plan->opt.dtype == COSMO_F32) {
+    PolRun<float> P = make_pol_run<float>(plan, theta, const_cast<void *>(ptape), pws);
+    P.gtheta = (float *)gtheta;
+    r = backward_impl<float>(plan, (const float *)rho, (const float *)alpha, (const float *)tape, nullptr, nullptr,
+                             nullptr, (float *)grho, (float *)galpha, (float *)gx0, (float *)gs0, (float *)gy0,
+                             (float *)ws, stp, st, &P);
+  } else {
+    PolRun<double> P = make_pol_run<double>(plan, theta, const_cast<void *>(ptape), pws);
+    P.gtheta = (double *)gtheta;
+    r = backward_impl<double>(plan, (const double *)rho, (const double *)alpha, (const double *)tape, nullptr,
+                              nullptr, nullptr, (double *)grho, (double *)galpha, (double *)gx0, (double *)gs0,
+                              (double *)gy0, (double *)ws, stp, st, &P);
+  }
+  if (r != COSMO_OK) return r;
+  HIPCHK(hipGetLastError());
+  return COSMO_OK;
 }
 
 cosmo_status cosmo_residual_loss(cosmo_plan *plan, const void *x, const void *s, const void *y, void *loss, void *gx,

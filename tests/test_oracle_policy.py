@@ -186,3 +186,21 @@ def test_unrolled_loss_gradients_match_finite_differences(family):
         fd = (L(theta, zp) - L(theta, zm)) / (2 * h)
         an = float(bw["g" + nm] @ dv)
         assert abs(fd - an) <= 1e-5 * max(abs(fd), 1e-2), (nm, fd, an)
+
+
+def test_package_initialiser_follows_the_documented_layout():
+    """The package's policy_init and the oracle read the same flat layout:
+    zero last layers, Table 2's penalties and relaxation at l^0."""
+    import torch
+    from paper_2606_13825_amd.binding import policy_init
+    th = policy_init(0, 0.0, torch.float64, "cpu").numpy()
+    assert th.size == pol.PARAM_COUNT
+    p = pol.unpack(th)
+    for key in ("rw3", "rb3", "aw3", "ab3"):
+        assert np.all(p[key] == 0.0)
+    rho0 = pol.squash_rho(torch.from_numpy(np.array(p["l_rho0"]))).numpy()
+    assert np.allclose(rho0, pol.TABLE2_RHO0, rtol=1e-12)
+    a0 = float(pol.squash_alpha(torch.tensor(float(p["l_alpha0"]), dtype=torch.float64)))
+    assert a0 == pytest.approx(pol.TABLE2_ALPHA0, rel=1e-14)
+    th2 = policy_init(0, 0.1, torch.float64, "cpu").numpy()
+    assert np.abs(pol.unpack(th2)["rw3"]).max() > 0
