@@ -21,6 +21,8 @@ It is a plain, slow, step-by-step restatement of:
   * the comparison backward rules of the PSD projection: the eigendecomposition
     rule (eq:psd-cotangent), Tikhonov-shifted and Newton-Schulz
     (eq:newton-schulz) variants;
+  * the vanilla baseline: COSMO run to tolerance with the residual-balancing
+    penalty (Sec. "Experiments", App. D);
   * the learned hyperparameter policy inside the unroll and the log-residual
     training loss (App. E "Policy Parameterization", Sec. "Experiments"),
     in `oracle.policy`.
@@ -35,7 +37,8 @@ from .cones import (rectify, rectify_adjoint, proj_cone, proj_cone_vjp, proj_soc
                     proj_psd, psd_vjp_dk, lowner_matrix, proj_nonneg, psd_vjp_naive)
 from .cosmo import (Hyper, step_forward, unroll_forward, unroll_backward, residual_loss,
                     residual_loss_grad, kkt_residuals, solve_reduced, reduced_matrix,
-                    implicit_solve_vjp, step_backward, run_fixed, rounding_floor_runs)
+                    implicit_solve_vjp, step_backward, run_fixed, rounding_floor_runs,
+                    solve_residual_balancing)
 from .fd import fd_check_unroll, fd_directional
 from .psd_rules import psd_vjp_tikhonov, ns_forward, ns_vjp, psd_vjp_ns
 from . import policy
@@ -47,6 +50,6 @@ __all__ = [
     "psd_vjp_tikhonov", "ns_forward", "ns_vjp", "psd_vjp_ns",
     "Hyper", "step_forward", "unroll_forward", "unroll_backward", "residual_loss",
     "residual_loss_grad", "kkt_residuals", "solve_reduced", "reduced_matrix",
-    "implicit_solve_vjp", "step_backward", "run_fixed", "rounding_floor_runs",
+    "implicit_solve_vjp", "step_backward", "run_fixed", "rounding_floor_runs", "solve_residual_balancing",
     "fd_check_unroll", "fd_directional", "policy",
 ]

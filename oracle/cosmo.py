@@ -251,3 +251,54 @@ def run_fixed(inst, rho_row: np.ndarray, alpha: float, iters: int, sigma: float 
         st = step_forward(inst, x, s, y, rho_row, alpha, sigma, lu=lu)
         x, s, y = st["xn"], st["sn"], st["yn"]
     return x, s, y
+
+
+def solve_residual_balancing(inst, rho0: float = 0.1, eq_scale: float = 1e3, alpha: float = 1.6,
+                             eps_abs: float = 1e-3, eps_rel: float = 1e-3, max_iter: int = 10000,
+                             interval: int = 40, tol_factor: float = 5.0, rho_min: float = 1e-6,
+                             rho_max: float = 1e6, adapt: bool = True, sigma: float = 1e-6, z0=None):
+    """COSMO run to tolerance with the residual-balancing penalty: the vanilla
+    baseline of Sec. "Experiments" (App. D: zero start, fixed alpha = 1.6;
+    Fig. 8's caption: one scalar rho, scaled by 1e3 on equality rows).
+
+    Stopping (checked after every step k, on z^k):
+        |r_p|_inf <= eps_abs + eps_rel N_p  and  |r_d|_inf <= eps_abs + eps_rel N_d
+    with r_p, r_d of kkt_residuals and the normalisers of App. E,
+    N_p = max(|Ax|, |s|, |b|)_inf, N_d = max(|Px|, |q|, |A'y|)_inf.
+    Penalty update (every `interval` steps, the residual-balancing rule the
+    paper cites from OSQP): rho <- clip(rho sqrt((|r_p|/N_p) / (|r_d|/N_d)),
+    rho_min, rho_max), taken only when it changes rho by more than a factor
+    tol_factor (then M is refactorised).  The paper prints neither the rule
+    nor its constants; the readings are listed with the design notes.
+    Returns (iterations, (x, s, y), rho) with iterations = None when
+    max_iter steps do not reach the tolerance."""
+    n, m = inst.A.shape[1], inst.A.shape[0]
+    if z0 is None:
+        x, s, y = np.zeros(n), np.zeros(m), np.zeros(m)
+    else:
+        x, s, y = (np.asarray(z, np.float64).copy() for z in z0)
+    eq = np.zeros(m, bool)
+    r = 0
+    for c in inst.cones:
+        rows = c.size * (c.size + 1) // 2 if c.kind == "psd" else c.size
+        eq[r:r + rows] = c.kind == "zero"
+        r += rows
+    rho, lu = float(rho0), None
+    for k in range(1, max_iter + 1):
+        row = rho * np.where(eq, eq_scale, 1.0)
+        if lu is None:
+            lu = solve_reduced(inst, rectify(row, inst.cones), sigma)
+        st = step_forward(inst, x, s, y, row, alpha, sigma, lu=lu)
+        x, s, y = st["xn"], st["sn"], st["yn"]
+        rp, rd = kkt_residuals(inst, x, s, y)
+        Np = max(np.abs(inst.A @ x).max(initial=0.0), np.abs(s).max(initial=0.0), np.abs(inst.b).max(initial=0.0))
+        Nd = max(np.abs(inst.P @ x).max(initial=0.0), np.abs(inst.q).max(initial=0.0),
+                 np.abs(inst.A.T @ y).max(initial=0.0))
+        ep, ed = np.abs(rp).max(initial=0.0), np.abs(rd).max(initial=0.0)
+        if ep <= eps_abs + eps_rel * Np and ed <= eps_abs + eps_rel * Nd:
+            return k, (x, s, y), rho
+        if adapt and k % interval == 0 and Np > 0 and Nd > 0 and ed > 0:
+            new = min(max(rho * np.sqrt((ep / Np) / (ed / Nd)), rho_min), rho_max)
+            if new > tol_factor * rho or new < rho / tol_factor:
+                rho, lu = new, None
+    return None, (x, s, y), rho

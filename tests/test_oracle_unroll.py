@@ -279,3 +279,53 @@ def test_rounding_model_dither_and_solve_residual():
     M = oracle.reduced_matrix(inst, st["rho_hat"], 1e-6)
     res = np.linalg.norm(M @ st["xt"] - st["xi"]) / np.linalg.norm(st["xi"])
     assert 0.5e-3 < res < 2e-3          # 1e-3 up to the float32 rounding of x~
+
+
+# ---- the vanilla baseline: COSMO to tolerance with residual balancing ----------
+
+def _stop_ok(inst, x, s, y, eps_abs, eps_rel):
+    rp, rd = oracle.kkt_residuals(inst, x, s, y)
+    Np = max(np.abs(inst.A @ x).max(), np.abs(s).max(), np.abs(inst.b).max())
+    Nd = max(np.abs(inst.P @ x).max(), np.abs(inst.q).max(), np.abs(inst.A.T @ y).max())
+    return np.abs(rp).max() <= eps_abs + eps_rel * Np and np.abs(rd).max() <= eps_abs + eps_rel * Nd
+
+
+@pytest.mark.parametrize("entry", json.load(open(os.path.join(GOLD, "closed_forms.json")))["entries"],
+                         ids=lambda e: e["name"])
+def test_residual_balancing_stops_at_the_first_passing_iterate(entry):
+    """The returned count is the first iterate that meets the stopping test;
+    the value there is the closed form to within the tolerance's reach."""
+    inst = _build(entry)
+    k, (x, s, y), rho = oracle.solve_residual_balancing(inst)
+    assert k is not None and _stop_ok(inst, x, s, y, 1e-3, 1e-3)
+    k1, (x1, s1, y1), _ = oracle.solve_residual_balancing(inst, max_iter=k - 1)
+    assert k1 is None and not _stop_ok(inst, x1, s1, y1, 1e-3, 1e-3)
+    assert abs(-float(inst.q @ x) - entry["value"]) <= 3e-2 * entry["value"]
+
+
+def test_residual_balancing_without_updates_is_fixed_penalty_cosmo():
+    inst = _build({"problem": "lovasz", "graph": "petersen", "n": 10})
+    k, (x, s, y), rho = oracle.solve_residual_balancing(inst, adapt=False)
+    assert rho == 0.1
+    xf, sf, yf = run_fixed(inst, synth.default_rho(inst, 1)[0], 1.6, k)
+    assert np.allclose(x, xf, rtol=0, atol=1e-12) and np.allclose(y, yf, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("c", [1e-2, 30.0])
+def test_residual_balancing_is_invariant_to_cost_scaling(c):
+    """Scaling P, q (and sigma, rho) by c scales y and r_d by c and leaves x,
+    s and the normalised residuals unchanged, so with relative tolerances the
+    same steps are taken, the updates happen at the same steps and the final
+    penalty is c times the unscaled one.  A rule that dropped a normaliser
+    or the square root would break this."""
+    import copy
+    inst = _build({"problem": "lovasz", "graph": "cycle", "n": 7})
+    k, (x, s, y), rho = oracle.solve_residual_balancing(inst, eps_abs=0.0)
+    assert rho != 0.1                      # the rule fired
+    sc = copy.copy(inst)
+    sc.P, sc.q = inst.P * c, inst.q * c
+    kc, (xc, sc_, yc), rhoc = oracle.solve_residual_balancing(sc, rho0=0.1 * c, eps_abs=0.0, sigma=1e-6 * c,
+                                                              rho_min=1e-6 * c, rho_max=1e6 * c)
+    assert kc == k
+    assert rhoc == pytest.approx(c * rho, rel=1e-9)
+    assert np.allclose(xc, x, rtol=1e-7, atol=1e-9) and np.allclose(yc, c * y, rtol=1e-7, atol=1e-9 * c)
