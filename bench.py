@@ -691,6 +691,49 @@ def policy_study(workload="c2", reps=3, head_scale=0.05, seed=3):
     batch.close()
 
 
+def vanilla_study(workload="c2", max_iter=4000, check=1):
+    """The vanilla baseline of Sec. "Experiments": every instance of
+    `workload` solved to eps = 1e-3 (absolute and relative) by COSMO with the
+    residual-balancing penalty (cosmo_solve; zero start, alpha = 1.6, one
+    penalty scalar per instance starting at 0.1, x 1e3 on zero rows), the
+    whole batch in one call, checked every `check` steps.  Reports the steps
+    to tolerance per instance (median, quartiles), the batch's wall-clock
+    time (HIP events) and time per step.  Prints one JSON line."""
+    import torch
+    from paper_2606_13825_amd import CosmoBatch
+    wl = _workload(workload)
+    dev = torch.device("cuda:0")
+    tdt = torch.float32 if wl["dtype"] == "f32" else torch.float64
+    batch = CosmoBatch(wl["insts"], K=check, dtype=tdt, device=dev, cg_tol=wl.get("cg_tol"),
+                       cg_max_iter=wl.get("cg_max_iter", 500), dense_f32=wl.get("dense_f32", False))
+    stats = batch.new_stats()
+    cur = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize(dev)
+    e0.record(cur)
+    iters, rho, x, s, y = batch.solve(max_iter=max_iter, stats=stats)
+    e1.record(cur)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    ok = iters[iters > 0]
+    steps = int(iters.max()) if np.all(iters > 0) else max_iter
+    row = {"instances": int(len(iters)), "converged": int((iters > 0).sum()),
+           "iters_median": float(np.median(ok)) if ok.size else None,
+           "iters_q1_q3": [float(np.percentile(ok, 25)), float(np.percentile(ok, 75))] if ok.size else None,
+           "iters_max": int(ok.max()) if ok.size else None, "batch_steps": steps, "batch_ms": ms,
+           "ms_per_step": ms / steps, "rho_final_median": float(np.median(rho)),
+           "cg_not_converged": int(batch.stats_dict(stats)["cg_not_converged"].sum())}
+    print(f"[bench] vanilla {workload}: " + ", ".join(f"{k}={v}" for k, v in row.items()), file=sys.stderr,
+          flush=True)
+    print(json.dumps({"metric": "steps and time to eps = 1e-3, COSMO with residual balancing (vanilla baseline)",
+                      "unit": "steps, ms", "higher_is_better": False, "dtype": wl["dtype"], "data": "synthetic",
+                      "config": {"workload": wl["name"], "B": len(wl["insts"]), "check_every": check,
+                                 "max_iter": max_iter, "eps_abs": 1e-3, "eps_rel": 1e-3, "rho0": 0.1,
+                                 "eq_scale": 1e3, "alpha": 1.6, "interval": 40, "tol_factor": 5},
+                      "result": row, "iters": iters.tolist()}))
+    batch.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -715,11 +758,13 @@ def main():
                          "no event-timed step, no CPU leg)")
     ap.add_argument("--dense-baselines", action="store_true",
                     help="with --study appb: also run the dense Direct and Indirect-Full backward passes")
-    ap.add_argument("--study", default=None, choices=["psd_rules", "appb", "psd_trajectory", "policy"],
+    ap.add_argument("--study", default=None,
+                    choices=["psd_rules", "appb", "psd_trajectory", "policy", "vanilla"],
                     help="psd_rules: backward time of the PSD-projection rules against the matrix order; "
                          "appb: peak HBM and time of the matrix-free backward against the problem size; "
                          "psd_trajectory: the PSD-projection backward rules along a COSMO trajectory; "
-                         "policy: the learned policy's cost inside the unroll (on --workload)")
+                         "policy: the learned policy's cost inside the unroll (on --workload); "
+                         "vanilla: steps and time to eps = 1e-3 with residual balancing (on --workload)")
     args = ap.parse_args()
     if args.study == "psd_rules" and args.gpus == 1:
         psd_rules_study()
@@ -732,6 +777,9 @@ def main():
         return
     if args.study == "policy" and args.gpus == 1:
         policy_study(args.workload)
+        return
+    if args.study == "vanilla" and args.gpus == 1:
+        vanilla_study(args.workload)
         return
     if args.quick:
         args.no_cpu_baseline = True

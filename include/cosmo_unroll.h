@@ -287,6 +287,45 @@ cosmo_status cosmo_policy_backward(cosmo_plan *plan, const void *theta, const vo
                                    void *gx0, void *gs0, void *gy0, void *ws, void *pws, void *stats,
                                    void *stream);
 
+/* ---- Vanilla COSMO run to tolerance ---------------------------------------
+ * The baseline of Sec. "Experiments" (App. D: zero start, fixed alpha; the
+ * residual-balancing penalty the paper cites from OSQP: one scalar per
+ * instance, times eq_scale on zero-cone rows).  Each instance runs until
+ *   |r_p|_inf <= eps_abs + eps_rel N_p  and  |r_d|_inf <= eps_abs + eps_rel N_d
+ * (r_p = A x + s - b, r_d = P x + q - A'y, N_p = max(|Ax|, |s|, |b|)_inf,
+ * N_d = max(|Px|, |q|, |A'y|)_inf), checked every K steps (the plan's K;
+ * K = 1 counts steps exactly).  With `adapt`, every `interval` steps (a
+ * multiple of K) the penalty of each instance not yet converged becomes
+ * clip(rho sqrt((|r_p|/N_p) / (|r_d|/N_d)), rho_min, rho_max) when that
+ * moves it by more than a factor tol_factor.  The batch runs until every
+ * instance has passed the test or max_iter steps are done; an instance that
+ * passed keeps iterating with the others (its count is the first check it
+ * passed). */
+typedef struct {
+  double rho0;        /* initial penalty scalar (> 0) */
+  double eq_scale;    /* multiplier on zero-cone rows (> 0) */
+  double alpha;       /* relaxation, in (0, 2) */
+  double eps_abs, eps_rel;   /* >= 0, not both 0 */
+  double tol_factor;  /* >= 1 */
+  double rho_min, rho_max;   /* 0 < rho_min <= rho0 <= rho_max */
+  int32_t max_iter;   /* >= 1 */
+  int32_t interval;   /* >= 1, a multiple of K */
+  int32_t adapt;      /* 0 or 1 */
+  int32_t pad;
+} cosmo_solve_options;
+
+/* Bytes of the solver's own device scratch (penalties and relaxations of a
+ * chunk, residual vectors and per-instance norms). */
+cosmo_status cosmo_solve_size(const cosmo_plan *plan, size_t *sws_bytes);
+
+/* x (d) [n_tot], s, y (d) [m_tot]: the start (in) and the last iterate (out).
+ * iters (h) [B]: steps to tolerance, -1 where max_iter was reached first.
+ * rho_out (h, nullable) [B]: the final penalty scalars.  ws (d)
+ * [fwd_ws_bytes], sws (d) [sws_bytes], stats (d, nullable).  Returns when the
+ * solve is done: the host reads the B residual norms after every K steps. */
+cosmo_status cosmo_solve(cosmo_plan *plan, const cosmo_solve_options *opt, void *x, void *s, void *y,
+                         int32_t *iters, double *rho_out, void *ws, void *sws, void *stats, void *stream);
+
 /* Final-residual loss per instance, L_i = ||A x + s - b||^2 + ||P x + q - A'y||^2
  * (the dual residual sign follows the fixed point of the iteration above,
  * at which P x + q - A'y = 0), and its gradient when gx, gs, gy are non-NULL:

@@ -256,7 +256,8 @@ def run_fixed(inst, rho_row: np.ndarray, alpha: float, iters: int, sigma: float 
 def solve_residual_balancing(inst, rho0: float = 0.1, eq_scale: float = 1e3, alpha: float = 1.6,
                              eps_abs: float = 1e-3, eps_rel: float = 1e-3, max_iter: int = 10000,
                              interval: int = 40, tol_factor: float = 5.0, rho_min: float = 1e-6,
-                             rho_max: float = 1e6, adapt: bool = True, sigma: float = 1e-6, z0=None):
+                             rho_max: float = 1e6, adapt: bool = True, sigma: float = 1e-6, z0=None,
+                             check: int = 1):
     """COSMO run to tolerance with the residual-balancing penalty: the vanilla
     baseline of Sec. "Experiments" (App. D: zero start, fixed alpha = 1.6;
     Fig. 8's caption: one scalar rho, scaled by 1e3 on equality rows).
@@ -270,8 +271,10 @@ def solve_residual_balancing(inst, rho0: float = 0.1, eq_scale: float = 1e3, alp
     rho_min, rho_max), taken only when it changes rho by more than a factor
     tol_factor (then M is refactorised).  The paper prints neither the rule
     nor its constants; the readings are listed with the design notes.
-    Returns (iterations, (x, s, y), rho) with iterations = None when
-    max_iter steps do not reach the tolerance."""
+    check: the stopping test runs on every check-th iterate only (a solver
+    that reads its residuals every few steps).  Returns (iterations, (x, s,
+    y), rho) with iterations = None when max_iter steps do not reach the
+    tolerance."""
     n, m = inst.A.shape[1], inst.A.shape[0]
     if z0 is None:
         x, s, y = np.zeros(n), np.zeros(m), np.zeros(m)
@@ -295,7 +298,7 @@ def solve_residual_balancing(inst, rho0: float = 0.1, eq_scale: float = 1e3, alp
         Nd = max(np.abs(inst.P @ x).max(initial=0.0), np.abs(inst.q).max(initial=0.0),
                  np.abs(inst.A.T @ y).max(initial=0.0))
         ep, ed = np.abs(rp).max(initial=0.0), np.abs(rd).max(initial=0.0)
-        if ep <= eps_abs + eps_rel * Np and ed <= eps_abs + eps_rel * Nd:
+        if k % check == 0 and ep <= eps_abs + eps_rel * Np and ed <= eps_abs + eps_rel * Nd:
             return k, (x, s, y), rho
         if adapt and k % interval == 0 and Np > 0 and Nd > 0 and ed > 0:
             new = min(max(rho * np.sqrt((ep / Np) / (ed / Nd)), rho_min), rho_max)

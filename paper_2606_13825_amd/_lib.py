@@ -26,6 +26,7 @@ EXPORTED = [
     "cosmo_plan_set_graph", "cosmo_plan_get_graph",
     "psd_proj_vjp_rule", "psd_ns_tape_size", "psd_proj_ns", "psd_proj_ns_vjp",
     "cosmo_policy_sizes", "cosmo_policy_forward", "cosmo_policy_backward",
+    "cosmo_solve_size", "cosmo_solve",
 ]
 
 # The learned policy's flat parameter vector (include/cosmo_unroll.h)
@@ -89,6 +90,23 @@ class CosmoOptions(ctypes.Structure):
     ]
 
 
+class CosmoSolveOptions(ctypes.Structure):
+    _fields_ = [
+        ("rho0", ctypes.c_double),
+        ("eq_scale", ctypes.c_double),
+        ("alpha", ctypes.c_double),
+        ("eps_abs", ctypes.c_double),
+        ("eps_rel", ctypes.c_double),
+        ("tol_factor", ctypes.c_double),
+        ("rho_min", ctypes.c_double),
+        ("rho_max", ctypes.c_double),
+        ("max_iter", ctypes.c_int32),
+        ("interval", ctypes.c_int32),
+        ("adapt", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+    ]
+
+
 class CosmoStats(ctypes.Structure):
     _fields_ = [("cg_iters_max", ctypes.c_int32), ("cg_not_converged", ctypes.c_int32),
                 ("eig_sweeps_max", ctypes.c_int32), ("eig_not_converged", ctypes.c_int32),
@@ -144,6 +162,11 @@ def _sig(lib):
     lib.cosmo_policy_forward.argtypes = [vp] * 17
     lib.cosmo_policy_backward.restype = ctypes.c_int
     lib.cosmo_policy_backward.argtypes = [vp] * 16
+    lib.cosmo_solve_size.restype = ctypes.c_int
+    lib.cosmo_solve_size.argtypes = [vp, ctypes.POINTER(sz)]
+    lib.cosmo_solve.restype = ctypes.c_int
+    lib.cosmo_solve.argtypes = [vp, ctypes.POINTER(CosmoSolveOptions), vp, vp, vp, P32,
+                                ctypes.POINTER(ctypes.c_double), vp, vp, vp, vp]
     lib.psd_proj.restype = ctypes.c_int
     lib.psd_proj.argtypes = [i32, P32, P64, ctypes.c_int, vp, vp, vp, vp, i32, dbl, i32, vp, vp]
     lib.psd_proj_static_scratch.restype = ctypes.c_int

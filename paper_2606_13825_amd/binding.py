@@ -328,6 +328,34 @@ class CosmoBatch:
         L.check(st, "cosmo_unroll_backward")
         return BackwardResult(grho, galpha, gx0, gs0, gy0)
 
+    # -- vanilla COSMO to tolerance (cosmo_solve) ---------------------------------
+    def solve(self, *, rho0: float = 0.1, eq_scale: float = 1e3, alpha: float = 1.6, eps_abs: float = 1e-3,
+              eps_rel: float = 1e-3, max_iter: int = 10000, interval: int = 40, tol_factor: float = 5.0,
+              rho_min: float = 1e-6, rho_max: float = 1e6, adapt: bool = True, x0=None, s0=None, y0=None,
+              stats=None, ws=None):
+        """COSMO run to tolerance with the residual-balancing penalty, checked
+        every K steps (K = 1: exact counts).  Returns (iters [B] numpy int32,
+        -1 where max_iter came first; final penalty scalars [B]; x, s, y)."""
+        opt = L.CosmoSolveOptions(rho0=rho0, eq_scale=eq_scale, alpha=alpha, eps_abs=eps_abs, eps_rel=eps_rel,
+                                  tol_factor=tol_factor, rho_min=rho_min, rho_max=rho_max, max_iter=max_iter,
+                                  interval=interval, adapt=int(adapt), pad=0)
+        z = []
+        for t, n in ((x0, self.n_tot), (s0, self.m_tot), (y0, self.m_tot)):
+            z.append(torch.zeros(n, dtype=self.dtype, device=self.device) if t is None else t.clone())
+        x, s, y = z
+        sb = ctypes.c_size_t()
+        L.check(L.lib().cosmo_solve_size(self._plan, ctypes.byref(sb)), "cosmo_solve_size")
+        sws = torch.empty(max(sb.value, 1), dtype=torch.uint8, device=self.device)
+        ws = ws if ws is not None else self.new_fwd_ws()
+        iters = np.zeros(self.B, np.int32)
+        rho = np.zeros(self.B, np.float64)
+        st = L.lib().cosmo_solve(self._plan, ctypes.byref(opt), _ptr(x), _ptr(s), _ptr(y),
+                                 iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                 rho.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(ws), _ptr(sws),
+                                 _ptr(stats), _stream(self.device))
+        L.check(st, "cosmo_solve")
+        return iters, rho, x, s, y
+
     # -- learned policy (cosmo_policy_forward / cosmo_policy_backward) -----------
     def policy_sizes(self):
         """(ptape_bytes, pws_bytes) of the policy calls."""

@@ -210,6 +210,9 @@ template <typename T> void launch_pol_resid(const View<T> &v, const RowBuckets &
 template <typename T> void launch_pol_resid_adjoint(const View<T> &v, const RowBuckets &bkA, const RowBuckets &bkAt,
                                                     const T *ub, const T *pb, const T *wb, T *gx, T *gy,
                                                     hipStream_t st);
+// Vanilla solve (k_vec.hip): rho[k][i] = rho_b[instance] (x eq_scale on zero rows), k < K.
+template <typename T> void launch_solve_rho(const View<T> &v, const double *rho_b, double eq_scale, T *rho,
+                                            int32_t K, hipStream_t st);
 template <typename T> void launch_copy(T *dst, const T *src, int64_t n, hipStream_t st);
 template <typename T> void launch_fill(T *dst, T val, int64_t n, hipStream_t st);
 template <typename T> void launch_nonfinite_check(const View<T> &v, const T *x, const T *s, const T *y,

@@ -533,6 +533,18 @@ __global__ __launch_bounds__(NT) void k_pol_adj_rows(View<T> v, BucketArgs ba, c
   if (bp.lane == 0) gy[i] = (T)((double)gy[i] + acc + dense_row_term(v, i));
 }
 
+// ---- vanilla solve: per-row penalties from per-instance scalars ---------------
+
+// rho[k][i] = rho_b[instance of i] (times eq_scale on zero-cone rows), k < K.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_solve_rho(View<T> v, const double *__restrict__ rho_b, double eq_scale,
+                                                  T *__restrict__ rho, int32_t K) {
+  const int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x;
+  if (i >= v.m_tot) return;
+  const T r = (T)(rho_b[v.row_inst[i]] * (v.row_kind[i] == ROW_ZERO ? eq_scale : 1.0));
+  for (int32_t k = 0; k < K; ++k) rho[(int64_t)k * v.m_tot + i] = r;
+}
+
 // ---- health check ---------------------------------------------------------------
 
 template <typename T>
@@ -673,6 +685,11 @@ void launch_pol_resid_adjoint(const View<T> &v, const RowBuckets &bkA, const Row
   if (nblocks_bucket(a) > 0) k_pol_adj_rows<T><<<(int)nblocks_bucket(a), NT, 0, st>>>(v, a, wb, gy);
 }
 
+template <typename T>
+void launch_solve_rho(const View<T> &v, const double *rho_b, double eq_scale, T *rho, int32_t K, hipStream_t st) {
+  k_solve_rho<T><<<grid_for(v.m_tot), NT, 0, st>>>(v, rho_b, eq_scale, rho, K);
+}
+
 template <typename T> void launch_copy(T *dst, const T *src, int64_t n, hipStream_t st) {
   if (n > 0) k_copy<T><<<grid_for(n), NT, 0, st>>>(dst, src, n);
 }
@@ -713,6 +730,7 @@ void launch_nonfinite_check(const View<T> &v, const T *x, const T *s, const T *y
                                     const T *, const T *, T *, T *, T *, T *, T *, hipStream_t);                \
   template void launch_pol_resid_adjoint<T>(const View<T> &, const RowBuckets &, const RowBuckets &, const T *, \
                                             const T *, const T *, T *, T *, hipStream_t);                       \
+  template void launch_solve_rho<T>(const View<T> &, const double *, double, T *, int32_t, hipStream_t);    \
   template void launch_copy<T>(T *, const T *, int64_t, hipStream_t);                                           \
   template void launch_fill<T>(T *, T, int64_t, hipStream_t);                                                   \
   template void launch_nonfinite_check<T>(const View<T> &, const T *, const T *, const T *, cosmo_stats *,      \

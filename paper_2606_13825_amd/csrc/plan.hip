@@ -884,7 +884,7 @@ void policy_bwd_at(cosmo_plan *pl, const View<T> &v, const PolRun<T> &P, int k, 
 template <typename T>
 cosmo_status forward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T *x0, const T *s0, const T *y0, T *xK,
                           T *sK, T *yK, T *tape, T *ws, cosmo_stats *stats, hipStream_t st,
-                          const PolRun<T> *pol = nullptr) {
+                          const PolRun<T> *pol = nullptr, bool continues = false) {
   View<T> v = make_view<T>(pl);
   const int64_t n = pl->n_tot, m = pl->m_tot;
   const int K = pl->opt.K;
@@ -922,9 +922,10 @@ cosmo_status forward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T 
       ds.xn = xn;
       ds.alpha_k = al;
     } else {
-      // warm start of the CG: previous x~ (first step: x^0)
+      // warm start of the CG: previous x~ (first step: x^0; a call that
+      // continues the previous one without a tape keeps that call's last x~)
       if (tape) launch_copy<T>(xt, k == 0 ? x : XT(k - 1), n, st);
-      else if (k == 0) launch_copy<T>(xt, x, n, st);
+      else if (k == 0 && !continues) launch_copy<T>(xt, x, n, st);
     }
     {
       ProfScope ps(pl, 3, st);
@@ -945,7 +946,8 @@ cosmo_status forward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T 
     // warm start from the previous step's eigenvectors of the same blocks (the
     // tape keeps them; without a tape the single buffer is updated in place,
     // each block reading its own slot before overwriting it)
-    const T *Uprev = (pl->opt.eig_warm_start && k > 0) ? (tape ? UU(k - 1) : UU(k)) : nullptr;
+    const T *Uprev = (pl->opt.eig_warm_start && (k > 0 || (continues && !tape))) ? (tape ? UU(k - 1) : UU(k))
+                                                                                  : nullptr;
     launch_psd_classes<T>(pl, rh, ws + f.vv, ws + f.sh, y, sn, yn, UU(k), LAM(k),
                           reinterpret_cast<double *>(ws + f.rs), Uprev, stats, st);
   }
@@ -954,6 +956,101 @@ cosmo_status forward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T 
   if (xK) launch_copy<T>(xK, X(K), n, st);
   if (sK) launch_copy<T>(sK, S(K), m, st);
   if (yK) launch_copy<T>(yK, Y(K), m, st);
+  HIPCHK(hipGetLastError());
+  return COSMO_OK;
+}
+
+// ---- vanilla COSMO to tolerance (residual balancing) ------------------------------
+
+struct SolveLayout {
+  size_t rho, alpha, rho_b, u, rp, p, w, rd, rec, total;
+};
+
+SolveLayout solve_layout(const cosmo_plan *pl) {
+  const size_t esz = pl->esz, m = (size_t)pl->m_tot, n = (size_t)pl->n_tot, B = (size_t)pl->B;
+  const size_t K = (size_t)pl->opt.K;
+  SolveLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = o;
+    o = align_up(o + std::max<size_t>(bytes, 1), 256);
+    return r;
+  };
+  L.rho = take(K * m * esz);
+  L.alpha = take(K * B * esz);
+  L.rho_b = take(B * sizeof(double));
+  L.u = take(m * esz);
+  L.rp = take(m * esz);
+  L.p = take(n * esz);
+  L.w = take(n * esz);
+  L.rd = take(n * esz);
+  L.rec = take(B * sizeof(PolRec));
+  L.total = o;
+  return L;
+}
+
+template <typename T>
+cosmo_status solve_impl(cosmo_plan *pl, const cosmo_solve_options &o, T *x, T *s, T *y, int32_t *iters,
+                        double *rho_out, T *ws, unsigned char *sws, cosmo_stats *stats, hipStream_t st) {
+  const SolveLayout L = solve_layout(pl);
+  const int K = pl->opt.K, B = pl->B;
+  View<T> v = make_view<T>(pl);
+  bind_dense(v, ws, pl->fw.dn, pl->fw.ec, pl->fw.ed);
+  T *rho = reinterpret_cast<T *>(sws + L.rho), *alpha = reinterpret_cast<T *>(sws + L.alpha);
+  double *rho_b_d = reinterpret_cast<double *>(sws + L.rho_b);
+  T *u = reinterpret_cast<T *>(sws + L.u), *rp = reinterpret_cast<T *>(sws + L.rp);
+  T *p = reinterpret_cast<T *>(sws + L.p), *w = reinterpret_cast<T *>(sws + L.w);
+  T *rd = reinterpret_cast<T *>(sws + L.rd);
+  PolRec *rec = reinterpret_cast<PolRec *>(sws + L.rec);
+  std::vector<double> rho_b(B, o.rho0);
+  std::vector<PolRec> hrec(B);
+  std::vector<char> done(B, 0);
+  for (int b = 0; b < B; ++b) iters[b] = -1;
+  launch_fill<T>(alpha, (T)o.alpha, (int64_t)K * B, st);
+  auto upload = [&]() -> cosmo_status {
+    HIPCHK(hipMemcpyAsync(rho_b_d, rho_b.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_solve_rho<T>(v, rho_b_d, o.eq_scale, rho, K, st);
+    return COSMO_OK;
+  };
+  cosmo_status r = upload();
+  if (r != COSMO_OK) return r;
+  int remaining = B;
+  for (int it = K; it <= o.max_iter && remaining > 0; it += K) {
+    // each call continues the previous one (CG and eigensolver warm starts kept)
+    r = forward_impl<T>(pl, rho, alpha, x, s, y, x, s, y, nullptr, ws, stats, st, nullptr, it > K);
+    if (r != COSMO_OK) return r;
+    // the residual vectors and per-instance norms of the policy's features
+    launch_pol_resid<T>(v, pl->bkA, pl->bkAt, x, s, y, u, rp, p, w, rd, st);
+    launch_pol_norms<T>(v, u, rp, p, w, rd, s, nullptr, nullptr, rec, st);
+    HIPCHK(hipMemcpyAsync(hrec.data(), rec, B * sizeof(PolRec), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    bool changed = false;
+    for (int b = 0; b < B; ++b) {
+      if (done[b]) continue;
+      const PolRec &R = hrec[b];
+      const double Np = std::max(std::max(R.nu, R.ns), R.nb), Nd = std::max(std::max(R.np, R.nq), R.nw);
+      if (R.mrp <= o.eps_abs + o.eps_rel * Np && R.mrd <= o.eps_abs + o.eps_rel * Nd) {
+        done[b] = 1;
+        iters[b] = it;
+        --remaining;
+        continue;
+      }
+      if (o.adapt && it % o.interval == 0 && Np > 0 && Nd > 0 && R.mrd > 0) {
+        const double nr = std::min(std::max(rho_b[b] * std::sqrt((R.mrp / Np) / (R.mrd / Nd)), o.rho_min),
+                                   o.rho_max);
+        if (nr > o.tol_factor * rho_b[b] || nr < rho_b[b] / o.tol_factor) {
+          rho_b[b] = nr;
+          changed = true;
+        }
+      }
+    }
+    if (changed && remaining > 0) {
+      r = upload();
+      if (r != COSMO_OK) return r;
+    }
+  }
+  if (rho_out)
+    for (int b = 0; b < B; ++b) rho_out[b] = rho_b[b];
   HIPCHK(hipGetLastError());
   return COSMO_OK;
 }
@@ -1298,6 +1395,37 @@ cosmo_status cosmo_policy_backward(cosmo_plan *plan, const void *theta, const vo
   if (r != COSMO_OK) return r;
   HIPCHK(hipGetLastError());
   return COSMO_OK;
+}
+
+cosmo_status cosmo_solve_size(const cosmo_plan *plan, size_t *sws_bytes) {
+  cosmo_status s0 = check_plan(plan);
+  if (s0 != COSMO_OK) return s0;
+  if (sws_bytes) *sws_bytes = solve_layout(plan).total;
+  return COSMO_OK;
+}
+
+cosmo_status cosmo_solve(cosmo_plan *plan, const cosmo_solve_options *opt, void *x, void *s, void *y,
+                         int32_t *iters, double *rho_out, void *ws, void *sws, void *stats, void *stream) {
+  cosmo_status st0 = check_plan(plan);
+  if (st0 != COSMO_OK) return st0;
+  if (!opt || !x || !s || !y || !iters || !ws || !sws) FAIL(COSMO_EINVAL, "opt, x, s, y, iters, ws and sws are required");
+  const cosmo_solve_options &o = *opt;
+  if (!(o.rho_min > 0 && o.rho_min <= o.rho0 && o.rho0 <= o.rho_max && std::isfinite(o.rho_max)))
+    FAIL(COSMO_EINVAL, "need 0 < rho_min <= rho0 <= rho_max < inf");
+  if (!(o.eq_scale > 0 && std::isfinite(o.eq_scale))) FAIL(COSMO_EINVAL, "eq_scale must be positive and finite");
+  if (!(o.alpha > 0 && o.alpha < 2)) FAIL(COSMO_EINVAL, "alpha must lie in (0, 2)");
+  if (!(o.eps_abs >= 0 && o.eps_rel >= 0 && o.eps_abs + o.eps_rel > 0))
+    FAIL(COSMO_EINVAL, "eps_abs and eps_rel must be >= 0 and not both 0");
+  if (!(o.tol_factor >= 1)) FAIL(COSMO_EINVAL, "tol_factor must be >= 1");
+  if (o.max_iter < 1) FAIL(COSMO_EINVAL, "max_iter must be >= 1");
+  if (o.adapt != 0 && o.adapt != 1) FAIL(COSMO_EINVAL, "adapt must be 0 or 1");
+  if (o.interval < 1 || o.interval % plan->opt.K != 0) FAIL(COSMO_EINVAL, "interval must be a positive multiple of K");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto *stp = static_cast<cosmo_stats *>(stats);
+  auto *sw = static_cast<unsigned char *>(sws);
+  if (plan->opt.dtype == COSMO_F32)
+    return solve_impl<float>(plan, o, (float *)x, (float *)s, (float *)y, iters, rho_out, (float *)ws, sw, stp, st);
+  return solve_impl<double>(plan, o, (double *)x, (double *)s, (double *)y, iters, rho_out, (double *)ws, sw, stp, st);
 }
 
 cosmo_status cosmo_residual_loss(cosmo_plan *plan, const void *x, const void *s, const void *y, void *loss, void *gx,

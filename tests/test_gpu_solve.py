@@ -1,0 +1,117 @@
+"""Vanilla COSMO run to tolerance on the GPU (cosmo_solve: residual-balancing
+penalty, Sec. "Experiments", App. D) against the float64 oracle
+(oracle.solve_residual_balancing): steps to tolerance, final penalty
+scalars, and the final iterate of single-instance runs."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_common import ensure_lib, say
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _closed_form_instances():
+    out = []
+    for e in json.load(open(os.path.join(GOLD, "closed_forms.json")))["entries"]:
+        n = e["n"]
+        g = {"cycle": synth.cycle_graph, "complete": synth.complete_graph}.get(e["graph"])
+        edges = synth.petersen_graph() if e["graph"] == "petersen" else g(n)
+        out.append(synth.lovasz_theta_sdp(n, edges) if e["problem"] == "lovasz" else synth.maxcut_sdp(n, edges))
+    return out
+
+
+def _batch(insts, K=1, dtype=torch.float64, cg_tol=1e-12):
+    from paper_2606_13825_amd import CosmoBatch
+    return CosmoBatch(insts, K=K, dtype=dtype, device=DEV, cg_tol=cg_tol, cg_max_iter=2000)
+
+
+def test_solve_batch_counts_and_penalties_fp64():
+    ensure_lib()
+    insts = _closed_form_instances()
+    rng = np.random.default_rng(70)
+    insts += [synth.random_mixed(rng, n=10, soc_dims=(3, 4), psd_orders=(3, 4)) for _ in range(2)]
+    batch = _batch(insts)
+    iters, rho, x, s, y = batch.solve(max_iter=3000)
+    torch.cuda.synchronize()
+    for b, inst in enumerate(insts):
+        # the random mixed-cone programs do not reach the tolerance (their
+        # penalties climb towards the bound): both sides must agree on that
+        k, _, r = oracle.solve_residual_balancing(inst, max_iter=3000)
+        say(f"  instance {b}: gpu {iters[b]} steps rho {rho[b]:.4g}; oracle {k} steps rho {r:.4g}")
+        assert iters[b] == (-1 if k is None else k)
+        # the rule reads residuals of ~1e-3 off iterates the CG leaves ~1e-12
+        # apart; without convergence the trajectories drift further apart
+        assert rho[b] == pytest.approx(r, rel=1e-6 if k is not None else 1e-2)
+
+
+@pytest.mark.parametrize("idx", [0, 2, 4])
+def test_solve_single_instance_final_iterate_fp64(idx):
+    ensure_lib()
+    inst = _closed_form_instances()[idx]
+    batch = _batch([inst])
+    iters, rho, x, s, y = batch.solve()
+    k, (xr, sr, yr), _ = oracle.solve_residual_balancing(inst)
+    assert iters[0] == k
+    for a, r in ((x, xr), (s, sr), (y, yr)):
+        a = a.double().cpu().numpy()
+        assert np.linalg.norm(a - r) <= 1e-8 * max(np.linalg.norm(r), 1.0)
+
+
+def test_solve_without_updates_and_budget_exhaustion_fp64():
+    ensure_lib()
+    insts = _closed_form_instances()
+    batch = _batch(insts)
+    iters, rho, *_ = batch.solve(adapt=False)
+    for b, inst in enumerate(insts):
+        k, _, _ = oracle.solve_residual_balancing(inst, adapt=False)
+        assert iters[b] == k and rho[b] == 0.1
+    lim = int(min(iters)) - 1
+    iters2, *_ = _batch(insts).solve(adapt=False, max_iter=lim)
+    assert np.all(iters2 == -1)
+
+
+def test_solve_chunked_checks():
+    """With K = 5 the stopping test runs every 5 steps (the penalty updates
+    still fall on every 40th): the counts are the oracle's with the same
+    check interval (residuals are not monotone, so that is not always the
+    first multiple of 5 after the exact count)."""
+    ensure_lib()
+    insts = _closed_form_instances()
+    exact, *_ = _batch(insts).solve()
+    chunk, *_ = _batch(insts, K=5).solve()
+    say(f"  exact {exact.tolist()} chunked {chunk.tolist()}")
+    for b, inst in enumerate(insts):
+        k5, _, _ = oracle.solve_residual_balancing(inst, check=5)
+        assert chunk[b] == k5 and chunk[b] >= exact[b]
+
+
+def test_solve_fp32_maxcut_batch():
+    """Float32: every instance reaches the tolerance, its final iterate passes
+    the float64 test (at 1.05 eps, for float32 rounding of the norms), and the
+    count is within 10 % of the oracle's."""
+    ensure_lib()
+    insts = [x.astype(np.float32) for x in synth.c2_batch(B=6, p_lo=20, p_hi=40, seed=71)]
+    batch = _batch(insts, dtype=torch.float32, cg_tol=1e-7)
+    iters, rho, x, s, y = batch.solve()
+    xs, ss, ys = (t.double().cpu().numpy() for t in (x, s, y))
+    for b, inst in enumerate(insts):
+        k, _, _ = oracle.solve_residual_balancing(inst)
+        say(f"  instance {b}: gpu {iters[b]}, oracle {k}")
+        assert iters[b] > 0 and abs(int(iters[b]) - k) <= max(2, 0.1 * k)
+    # the last instance to converge stops the batch: its iterate is the one at its count
+    b = int(np.argmax(iters))
+    inst = insts[b]
+    sl_n, sl_m = slice(batch.n_off[b], batch.n_off[b + 1]), slice(batch.m_off[b], batch.m_off[b + 1])
+    xb, sb, yb = xs[sl_n], ss[sl_m], ys[sl_m]
+    rp, rd = oracle.kkt_residuals(inst, xb, sb, yb)
+    Np = max(np.abs(inst.A @ xb).max(), np.abs(sb).max(), np.abs(inst.b).max())
+    Nd = max(np.abs(inst.P @ xb).max(), np.abs(inst.q).max(), np.abs(inst.A.T @ yb).max())
+    assert np.abs(rp).max() <= 1.05 * (1e-3 + 1e-3 * Np) and np.abs(rd).max() <= 1.05 * (1e-3 + 1e-3 * Nd)
