@@ -23,6 +23,8 @@ It is a plain, slow, step-by-step restatement of:
     (eq:newton-schulz) variants;
   * the vanilla baseline: COSMO run to tolerance with the residual-balancing
     penalty (Sec. "Experiments", App. D);
+  * sequential convex programming for nonlinear covariance steering (App. F),
+    its convex steps solved by the vanilla baseline, in `oracle.scp`;
   * the learned hyperparameter policy inside the unroll and the log-residual
     training loss (App. E "Policy Parameterization", Sec. "Experiments"),
     in `oracle.policy`.
@@ -41,7 +43,7 @@ from .cosmo import (Hyper, step_forward, unroll_forward, unroll_backward, residu
                     solve_residual_balancing)
 from .fd import fd_check_unroll, fd_directional
 from .psd_rules import psd_vjp_tikhonov, ns_forward, ns_vjp, psd_vjp_ns
-from . import policy
+from . import policy, scp
 
 __all__ = [
     "svec", "smat", "svec_len", "order_from_len",
@@ -51,5 +53,5 @@ __all__ = [
     "Hyper", "step_forward", "unroll_forward", "unroll_backward", "residual_loss",
     "residual_loss_grad", "kkt_residuals", "solve_reduced", "reduced_matrix",
     "implicit_solve_vjp", "step_backward", "run_fixed", "rounding_floor_runs", "solve_residual_balancing",
-    "fd_check_unroll", "fd_directional", "policy",
+    "fd_check_unroll", "fd_directional", "policy", "scp",
 ]

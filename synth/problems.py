@@ -292,141 +292,18 @@ def double_integrator_cs(rng: np.random.Generator, N: int = 10, dt: float = 0.5,
     mu_N = goal), nonnegative cone (e - nu, e + nu), and one PSD block of
     order nx + N nx: the Schur complement of
     sigma_N^2 I - A^N Sigma_0 A^N' - (Dbar_N + Bbar_N K) Sigma_W (...)' >= 0."""
+    from .covsteer import covsteer_ltv
     nx, nu = 4, 2
     I2 = np.eye(2)
     A = np.block([[I2, dt * I2], [np.zeros((2, 2)), I2]])
     B = np.vstack([0.5 * dt * dt * I2, dt * I2])
     W = np.diag([dt ** 3 / 3 * sigma_a ** 2] * 2 + [dt * sigma_a ** 2] * 2)
-    Wh = np.sqrt(W)                                   # W is diagonal
     Sig0 = sigma_0 ** 2 * np.eye(nx)
     Q = np.diag([1.0, 1.0, 0.3, 0.3])
-    R = 0.1 * np.eye(nu)
-    QN = 10.0 * Q
     goal = np.concatenate([rng.uniform(-np.asarray(goal_box), np.asarray(goal_box)), np.zeros(2)])
-    Ap = [np.linalg.matrix_power(A, t) for t in range(N + 1)]
-    # variable layout
-    mu_off = lambda t: t * nx
-    v_base = (N + 1) * nx
-    v_off = lambda t: v_base + t * nu
-    k_base = v_base + N * nu
-    k_index = {}
-    for t in range(N):
-        for tau in range(t):
-            k_index[(t, tau)] = k_base + len(k_index) * nu * nx
-    nk = len(k_index) * nu * nx
-    nu_base = k_base + nk
-    e_base = nu_base + N * nx
-    n = e_base + N * nx
-
-    def kvar(t, tau, r, c):
-        return k_index[(t, tau)] + r * nx + c
-
-    # covariance terms: for t, the nx x (N nx) matrix (Dbar_t + Bbar_t K) Sigma_W^1/2
-    # as constant + linear map in K; Bbar_t K has block (.., tau) = sum_{t' > tau, t' < t} A^{t-1-t'} B K[t', tau]
-    def cov_factor(t):
-        const = np.zeros((nx, N * nx))
-        lin = defaultdict(dict)                       # (row, col) -> {var: coef}
-        for tau in range(t):
-            const[:, tau * nx:(tau + 1) * nx] = Ap[t - 1 - tau] @ Wh
-        for tp in range(t):                           # input of step t' reaches x_t through A^{t-1-t'} B
-            G = Ap[t - 1 - tp] @ B                    # nx x nu
-            for tau in range(tp):
-                for a in range(nx):
-                    for c in range(nx):               # column tau*nx + c of (...) Sigma_W^1/2
-                        for r in range(nu):
-                            coef = G[a, r] * Wh[c, c]
-                            if coef != 0.0:
-                                d = lin[(a, tau * nx + c)]
-                                v = kvar(tp, tau, r, c)
-                                d[v] = d.get(v, 0.0) + coef
-        return const, lin
-
-    def dense_map(lin, shape):
-        """The linear part as a dense (prod(shape) x n) matrix, row-major entries."""
-        M = np.zeros((shape[0] * shape[1], n))
-        for (a, c), terms in lin.items():
-            for v, f in terms.items():
-                M[a * shape[1] + c, v] += f
-        return M
-
-    Pm = np.zeros((n, n))
-    qv = np.zeros(n)
-    for t in range(N + 1):
-        Qt = QN if t == N else Q
-        Pm[mu_off(t):mu_off(t) + nx, mu_off(t):mu_off(t) + nx] += 2.0 * Qt
-        if t >= 1:                                    # tr(Q_t Sigma_t): ||Q_t^1/2 F_t||_F^2, F_t affine in K
-            const, lin = cov_factor(t)
-            Qh = np.sqrt(Qt)                          # Q is diagonal
-            Mlin = dense_map(lin, (nx, N * nx))
-            Mq = np.kron(Qh, np.eye(N * nx)) @ Mlin   # rows (a, col): Qh[a, a] * F[a, col]
-            cq = (Qh @ const).ravel()
-            Pm += 2.0 * Mq.T @ Mq
-            qv += 2.0 * Mq.T @ cq
-    for t in range(N):
-        Pm[v_off(t):v_off(t) + nu, v_off(t):v_off(t) + nu] += 2.0 * R
-        # tr(R Sigma_u,t) = ||R^1/2 K_t Sigma_W^1/2||_F^2, K_t = block row t of K
-        Gm = np.zeros((nu * N * nx, n))
-        for tau in range(t):
-            for r in range(nu):
-                for c in range(nx):
-                    Gm[r * N * nx + tau * nx + c, kvar(t, tau, r, c)] = np.sqrt(R[r, r]) * Wh[c, c]
-        Pm += 2.0 * Gm.T @ Gm
-    qv[e_base:e_base + N * nx] = lam_nu
-    # rows: zero cone
-    rows, cols, vals, b = [], [], [], []
-    r = 0
-    for i in range(nx):                               # mu_0 = 0
-        rows.append(r); cols.append(mu_off(0) + i); vals.append(1.0); b.append(0.0); r += 1
-    for t in range(N):                                # mu_{t+1} - A mu_t - B v_t - nu_t = 0
-        for i in range(nx):
-            rows.append(r); cols.append(mu_off(t + 1) + i); vals.append(1.0)
-            for j in range(nx):
-                if A[i, j] != 0.0:
-                    rows.append(r); cols.append(mu_off(t) + j); vals.append(-A[i, j])
-            for j in range(nu):
-                if B[i, j] != 0.0:
-                    rows.append(r); cols.append(v_off(t) + j); vals.append(-B[i, j])
-            rows.append(r); cols.append(nu_base + t * nx + i); vals.append(-1.0)
-            b.append(0.0); r += 1
-    for i in range(nx):                               # mu_N = goal
-        rows.append(r); cols.append(mu_off(N) + i); vals.append(1.0); b.append(goal[i]); r += 1
-    n_zero = r
-    for sgn in (-1.0, 1.0):                           # s = e + sgn nu >= 0, i.e. A = -(e + sgn nu)
-        for j in range(N * nx):
-            rows.append(r); cols.append(e_base + j); vals.append(-1.0)
-            rows.append(r); cols.append(nu_base + j); vals.append(-sgn)
-            b.append(0.0); r += 1
-    n_nonneg = r - n_zero
-    # PSD: [[sigma_N^2 I - A^N Sig0 A^N', F_N], [F_N', I]] >= 0
-    p = nx + N * nx
-    bld = _LmiBuilder()
-    const_F, lin_F = cov_factor(N)
-    top = sigma_N ** 2 * np.eye(nx) - Ap[N] @ Sig0 @ Ap[N].T
-    lin, const = defaultdict(dict), defaultdict(float)
-    for c in range(nx):
-        for a in range(c + 1):
-            const[(a, c)] = top[a, c]
-    for a in range(nx):
-        for j in range(N * nx):
-            const[(a, nx + j)] = const_F[a, j]
-            if (a, j) in lin_F:
-                lin[(a, nx + j)] = dict(lin_F[(a, j)])
-    for j in range(N * nx):
-        const[(nx + j, nx + j)] = 1.0
-    bld.add_block(p, lin, const)
-    A_rows = sp.csr_matrix((vals, (rows, cols)), shape=(r, n))
-    A_psd = sp.csr_matrix((bld.vals, ([v + 0 for v in bld.rows], bld.cols)), shape=(bld.m, n))
-    Amat = sp.vstack([A_rows, A_psd]).tocsr()
-    Amat.sum_duplicates()
-    bvec = np.concatenate([np.array(b), np.array(bld.b)])
-    cones = [Cone(ZERO, n_zero), Cone(NONNEG, n_nonneg)] + bld.cones
-    Pm = 0.5 * (Pm + Pm.T)
-    inst = ConicInstance(sp.csr_matrix(Pm), qv, Amat, bvec, cones,
-                         {"class": "double_integrator_cs", "N": N, "nx": nx, "nu": nu, "dt": dt,
-                          "sigma_a": sigma_a, "sigma_N": sigma_N, "goal": goal, "k_base": k_base, "nk": nk,
-                          "A": A, "B": B, "W": W, "Sigma_0": Sig0})
-    inst.check()
-    return inst
+    return covsteer_ltv([A] * N, [B] * N, [np.zeros(nx)] * N, W, np.zeros(nx), goal, Sig0, sigma_N, Q,
+                        0.1 * np.eye(nu), 10.0 * Q, lam_nu,
+                        meta={"class": "double_integrator_cs", "dt": dt, "sigma_a": sigma_a, "A": A, "B": B})
 
 
 def random_mixed(rng: np.random.Generator, n: int = 8, n_zero: int = 2, n_nonneg: int = 3,

@@ -329,3 +329,62 @@ def test_residual_balancing_is_invariant_to_cost_scaling(c):
     assert kc == k
     assert rhoc == pytest.approx(c * rho, rel=1e-9)
     assert np.allclose(xc, x, rtol=1e-7, atol=1e-9) and np.allclose(yc, c * y, rtol=1e-7, atol=1e-9 * c)
+
+
+# ---- SCP for nonlinear covariance steering (App. F) ------------------------------
+
+def _unicycle_scp(seed, N=4, **kw):
+    from oracle.scp import scp
+    from synth.covsteer import (unicycle_scenario, unicycle_subproblem, unicycle_initial_reference, unicycle_step,
+                                unicycle_jacobians, unpack_solution)
+    sc = unicycle_scenario(np.random.default_rng(seed), N=N)
+    mu0, v0 = unicycle_initial_reference(sc)
+    out = scp(sc, lambda x, u: unicycle_step(x, u, sc["dt"]), lambda x, u: unicycle_jacobians(x, u, sc["dt"]),
+              unicycle_subproblem, unpack_solution, mu0, v0, **kw)
+    return sc, out
+
+
+def test_scp_on_linear_dynamics_converges_in_one_step():
+    """App. F: with linear dynamics (the double integrator) the SCP loop
+    converges in a single iteration -- the linearisation is exact, so the
+    first convex step has no defect and the ratio is one."""
+    from oracle.scp import scp
+    from synth.covsteer import covsteer_ltv, unpack_solution
+    dt, N = 0.5, 5
+    I2 = np.eye(2)
+    A = np.block([[I2, dt * I2], [np.zeros((2, 2)), I2]])
+    B = np.vstack([0.5 * dt * dt * I2, dt * I2])
+    Q = np.diag([1.0, 1.0, 0.3, 0.3])
+    sc = dict(N=N, W=np.diag([dt ** 3 / 3 * 0.09] * 2 + [dt * 0.09] * 2), Sigma0=1e-4 * np.eye(4), sigma_N=0.25,
+              Q=Q, R=0.1 * np.eye(2), QN=10 * Q, lam_nu=100.0, rho_x=5.0, mu0=np.zeros(4),
+              goal=np.array([2.0, -1.0, 0.0, 0.0]))
+
+    def sub(sc, mu_r, v_r, rx, ru):
+        return covsteer_ltv([A] * N, [B] * N, [np.zeros(4)] * N, sc["W"], sc["mu0"], sc["goal"], sc["Sigma0"],
+                            sc["sigma_N"], sc["Q"], sc["R"], sc["QN"], sc["lam_nu"], trust=(mu_r, v_r, rx, ru))
+
+    lam = np.linspace(0, 1, N + 1)[:, None]
+    out = scp(sc, lambda x, u: A @ x + B @ u, lambda x, u: (A, B), sub, unpack_solution,
+              sc["goal"][None, :] * lam, np.zeros((N, 2)), eps=1e-9)
+    assert out["converged"] and out["outer"] == 1
+    h = out["history"][0]
+    assert h["ratio"] == pytest.approx(1.0, abs=1e-6) and h["defect"] < 1e-6
+
+
+def test_scp_unicycle_converges_with_monotone_merit():
+    """The accepted merits decrease, the radius follows the ratio rule, and
+    the final trajectory meets the stopping test on the nonlinear dynamics."""
+    from synth.covsteer import unicycle_step
+    sc, out = _unicycle_scp(1, N=4)
+    assert out["converged"]
+    acc = [h for h in out["history"] if h["accepted"]]
+    merits = [acc[0]["phi_ref"]] + [h["phi_new"] for h in acc]
+    assert all(b < a for a, b in zip(merits, merits[1:]))
+    for h0, h1 in zip(out["history"], out["history"][1:]):
+        r = h0["ratio"]
+        expect = h0["rho"] * (0.5 if r < 0.25 else (2.0 if r > 0.75 else 1.0))
+        assert h1["rho"] == pytest.approx(expect)
+    mu, v = out["mu"], out["v"]
+    d = np.array([mu[t + 1] - unicycle_step(mu[t], v[t], sc["dt"]) for t in range(sc["N"])])
+    assert np.abs(d).max() < 1e-3
+    assert np.allclose(mu[0], sc["mu0"], atol=1e-4) and np.allclose(mu[-1], sc["goal"], atol=1e-4)

@@ -114,3 +114,101 @@ def test_double_integrator_rows_encode_dynamics_and_l1_epigraph():
         assert np.allclose(z[nx + t * nx:nx + (t + 1) * nx], -(mu[t + 1] - A @ mu[t] - B @ v[t] - nuv[t]))
     assert np.allclose(z[(N + 1) * nx:], md["goal"] - mu[N])
     assert np.allclose(s[n0:n0 + n1], np.concatenate([e - nuv.ravel(), e + nuv.ravel()]))
+
+
+# ---- the LTV builder with trust regions, and the unicycle ---------------------------
+
+def test_unicycle_jacobians_match_finite_differences():
+    from synth.covsteer import unicycle_jacobians, unicycle_step
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        x, u = rng.standard_normal(3), rng.standard_normal(2)
+        A, B = unicycle_jacobians(x, u)
+        h = 1e-6
+        Afd = np.stack([(unicycle_step(x + h * e, u) - unicycle_step(x - h * e, u)) / (2 * h) for e in np.eye(3)], 1)
+        Bfd = np.stack([(unicycle_step(x, u + h * e) - unicycle_step(x, u - h * e)) / (2 * h) for e in np.eye(2)], 1)
+        assert np.allclose(A, Afd, atol=1e-8) and np.allclose(B, Bfd, atol=1e-8)
+
+
+def _ltv_case(rng, N=4, nx=3, nu=2):
+    from synth.covsteer import covsteer_ltv
+    A = [np.eye(nx) + 0.2 * rng.standard_normal((nx, nx)) for _ in range(N)]
+    B = [rng.standard_normal((nx, nu)) for _ in range(N)]
+    r = [rng.standard_normal(nx) for _ in range(N)]
+    W = np.diag(rng.uniform(0.01, 0.05, nx))
+    Q = np.diag(rng.uniform(0.5, 2.0, nx))
+    R = np.diag(rng.uniform(0.1, 0.5, nu))
+    mu_ref, v_ref = rng.standard_normal((N + 1, nx)), rng.standard_normal((N, nu))
+    inst = covsteer_ltv(A, B, r, W, rng.standard_normal(nx), rng.standard_normal(nx), 0.01 * np.eye(nx), 0.5, Q, R,
+                        5.0 * Q, 100.0, trust=(mu_ref, v_ref, 2.0, 3.0))
+    return inst, A, B, r, W, Q, R, mu_ref, v_ref
+
+
+def _phi(A, t, tau):
+    M = np.eye(A[0].shape[0])
+    for s in range(tau, t):
+        M = A[s] @ M
+    return M
+
+
+def test_ltv_builder_terminal_lmi_trust_regions_and_dynamics():
+    from synth.covsteer import unpack_solution
+    rng = np.random.default_rng(4)
+    inst, A, B, r, W, Q, R, mu_ref, v_ref = _ltv_case(rng)
+    md = inst.meta
+    N, nx, nu = md["N"], md["nx"], md["nu"]
+    x = rng.standard_normal(inst.n)
+    s = inst.b - inst.A @ x
+    mu, v, K, vn = unpack_solution(inst, x)
+    kinds = [c.kind for c in inst.cones]
+    assert kinds == ["zero", "nonneg"] + ["soc"] * (2 * N + 1) + ["psd"]
+    n0 = inst.cones[0].size
+    for t in range(N):
+        assert np.allclose(-s[nx + t * nx:nx + (t + 1) * nx], mu[t + 1] - A[t] @ mu[t] - B[t] @ v[t] - vn[t] - r[t])
+    o = n0 + inst.cones[1].size
+    for t in range(N + 1):
+        assert s[o] == 2.0 and np.allclose(s[o + 1:o + 1 + nx], mu[t] - mu_ref[t])
+        o += nx + 1
+    for t in range(N):
+        assert s[o] == 3.0 and np.allclose(s[o + 1:o + 1 + nu], v[t] - v_ref[t])
+        o += nu + 1
+    # terminal LMI: x_N's disturbance response (Dbar_N + Bbar_N K) Sigma_W^1/2
+    Db = np.hstack([_phi(A, N, tau + 1) for tau in range(N)])
+    Bb = np.hstack([_phi(A, N, tau + 1) @ B[tau] for tau in range(N)])
+    F = (Db + Bb @ K) @ np.sqrt(np.kron(np.eye(N), W))
+    PN = _phi(A, N, 0)
+    lmi = np.block([[0.25 * np.eye(nx) - PN @ md["Sigma_0"] @ PN.T, F], [F.T, np.eye(N * nx)]])
+    p = nx + N * nx
+    assert np.abs(smat(s[-p * (p + 1) // 2:]) - lmi).max() <= 1e-12 * max(1.0, np.abs(lmi).max())
+
+
+def test_ltv_builder_cost_matches_the_expected_cost():
+    from synth.covsteer import unpack_solution
+    rng = np.random.default_rng(5)
+    inst, A, B, r, W, Q, R, mu_ref, v_ref = _ltv_case(rng)
+    md = inst.meta
+    N, nx, nu = md["N"], md["nx"], md["nu"]
+    SW = np.kron(np.eye(N), W)
+
+    def direct(x):
+        mu, v, K, vn = unpack_solution(inst, x)
+        f = 0.0
+        for t in range(N + 1):
+            Qt = 5.0 * Q if t == N else Q
+            f += mu[t] @ Qt @ mu[t]
+            if t >= 1:
+                Db = np.hstack([_phi(A, t, tau + 1) if tau < t else np.zeros((nx, nx)) for tau in range(N)])
+                Bb = np.hstack([_phi(A, t, tau + 1) @ B[tau] if tau < t else np.zeros((nx, nu)) for tau in range(N)])
+                Ft = Db + Bb @ K
+                f += np.trace(Qt @ Ft @ SW @ Ft.T)
+        for t in range(N):
+            f += v[t] @ R @ v[t]
+            Kt = K[t * nu:(t + 1) * nu]
+            f += np.trace(R @ Kt @ SW @ Kt.T)
+        return f + 100.0 * x[md["e_base"]:].sum()
+
+    obj = lambda x: 0.5 * x @ (inst.P @ x) + inst.q @ x
+    for _ in range(3):
+        x, y = rng.standard_normal(inst.n), rng.standard_normal(inst.n)
+        d = direct(x) - direct(y)
+        assert abs((obj(x) - obj(y)) - d) <= 1e-10 * max(1.0, abs(d))
