@@ -734,6 +734,72 @@ def vanilla_study(workload="c2", max_iter=4000, check=1):
     batch.close()
 
 
+def scp_study(scenarios=20, horizon=20, seed=11, eps=1e-6, check=10, max_outer=30, inner_max=50000, cg_tol=1e-8):
+    """Sequential convex programming for the unicycle of App. F (Fig. 1's
+    setting: 20 sampled scenarios, SCP tolerance 1e-3 on the nonlinear
+    defect and the virtual control; horizon 20 as in the standalone-results
+    table's unicycle row, the appendix's 30 with --scp-horizon 30), every
+    convex step solved by the vanilla COSMO on the GPU to `eps` (float64, CG
+    relative tolerance `cg_tol` as in that table's caption, stopping test
+    every `check` steps), all scenarios advancing together in one
+    super-batch per outer iteration.  Reports per scenario the outer iterations and inner
+    steps, the median and quartiles of the SCP residual max(|defect|, |nu|)
+    against the outer iteration, and where the wall-clock time went (host
+    assembly, upload, GPU solve, host ratio tests).  Prints one JSON line."""
+    import torch
+    from paper_2606_13825_amd.scp import scp_solve, ScpTiming
+    from synth.covsteer import (unicycle_scenario, unicycle_subproblem, unicycle_initial_reference, unicycle_step,
+                                unicycle_jacobians, unpack_solution, UNICYCLE_DT)
+    rng = np.random.default_rng(seed)
+    scs = [unicycle_scenario(rng, N=horizon) for _ in range(scenarios)]
+    tm = ScpTiming()
+    dev = torch.device("cuda:0")
+    print(f"[bench] scp: {scenarios} unicycle scenarios, N={horizon}, inner eps={eps}, check every {check}",
+          file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    res = scp_solve(scs, step=lambda x, u: unicycle_step(x, u, UNICYCLE_DT),
+                    jacobians=lambda x, u: unicycle_jacobians(x, u, UNICYCLE_DT), subproblem=unicycle_subproblem,
+                    unpack=unpack_solution, reference=unicycle_initial_reference, eps=eps, check=check,
+                    max_outer=max_outer, inner_max=inner_max, dtype=torch.float64, device=dev, timing=tm,
+                    cg_tol=cg_tol,
+                    progress=lambda r, n, dt: print(f"[bench] scp outer {r}: {n} scenarios running, "
+                                                    f"{dt:.2f}s", file=sys.stderr, flush=True))
+    wall = time.perf_counter() - t0
+    ok = [r for r in res if r.converged]
+    outers = np.array([r.outer for r in ok]) if ok else np.zeros(0)
+    # the SCP residual max(|defect|, |nu|) of the current reference after each
+    # outer iteration (nan before the first accepted step; a finished
+    # scenario keeps its last value)
+    C = np.full((len(res), max(r.outer for r in res)), np.nan)
+    for i, r in enumerate(res):
+        cur = np.nan
+        for j, h in enumerate(r.history):
+            if h.accepted:
+                cur = max(h.defect, h.nu)
+            C[i, j] = cur
+        C[i, r.outer:] = cur
+    conv = {"median": np.nanmedian(C, axis=0).tolist(), "q1": np.nanpercentile(C, 25, axis=0).tolist(),
+            "q3": np.nanpercentile(C, 75, axis=0).tolist()}
+    row = {"scenarios": scenarios, "converged": len(ok),
+           "outer_median": float(np.median(outers)) if ok else None,
+           "outer_q1_q3": [float(np.percentile(outers, 25)), float(np.percentile(outers, 75))] if ok else None,
+           "inner_total_median": float(np.median([r.inner_total for r in res])),
+           "wall_s": wall, "wall_s_per_scenario": wall / scenarios, "gpu_solve_s": tm.solve_s,
+           "host_build_s": tm.build_s, "upload_s": tm.upload_s, "host_ratio_s": tm.host_s, "rounds": tm.rounds}
+    print(f"[bench] scp: " + ", ".join(f"{k}={v}" for k, v in row.items()), file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "SCP outer iterations and time to the 1e-3 SCP residual, unicycle covariance "
+                                "steering, convex steps by vanilla COSMO on the GPU",
+                      "unit": "iterations, s", "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": f"unicycle covariance steering, {scenarios} scenarios, N={horizon}",
+                                 "inner_eps": eps, "cg_tol": cg_tol, "check_every": check, "max_outer": max_outer,
+                                 "inner_max": inner_max, "seed": seed},
+                      "result": row, "residual_curve": conv,
+                      "per_scenario": [{"converged": r.converged, "outer": r.outer, "inner_total": r.inner_total,
+                                        "inner": [h.inner for h in r.history],
+                                        "accepted": [h.accepted for h in r.history]} for r in res]}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -759,12 +825,15 @@ def main():
     ap.add_argument("--dense-baselines", action="store_true",
                     help="with --study appb: also run the dense Direct and Indirect-Full backward passes")
     ap.add_argument("--study", default=None,
-                    choices=["psd_rules", "appb", "psd_trajectory", "policy", "vanilla"],
+                    choices=["psd_rules", "appb", "psd_trajectory", "policy", "vanilla", "scp"],
                     help="psd_rules: backward time of the PSD-projection rules against the matrix order; "
                          "appb: peak HBM and time of the matrix-free backward against the problem size; "
                          "psd_trajectory: the PSD-projection backward rules along a COSMO trajectory; "
                          "policy: the learned policy's cost inside the unroll (on --workload); "
-                         "vanilla: steps and time to eps = 1e-3 with residual balancing (on --workload)")
+                         "vanilla: steps and time to eps = 1e-3 with residual balancing (on --workload); "
+                         "scp: sequential convex programming for the unicycle, convex steps by vanilla COSMO")
+    ap.add_argument("--scp-horizon", type=int, default=20, help="with --study scp: the horizon N")
+    ap.add_argument("--scp-scenarios", type=int, default=20, help="with --study scp: the number of scenarios")
     args = ap.parse_args()
     if args.study == "psd_rules" and args.gpus == 1:
         psd_rules_study()
@@ -777,6 +846,9 @@ def main():
         return
     if args.study == "policy" and args.gpus == 1:
         policy_study(args.workload)
+        return
+    if args.study == "scp" and args.gpus == 1:
+        scp_study(scenarios=args.scp_scenarios, horizon=args.scp_horizon)
         return
     if args.study == "vanilla" and args.gpus == 1:
         vanilla_study(args.workload)

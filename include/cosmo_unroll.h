@@ -315,10 +315,11 @@ typedef struct {
 } cosmo_solve_options;
 
 /* Bytes of the solver's own device scratch (penalties and relaxations of a
- * chunk, residual vectors and per-instance norms). */
+ * chunk, residual vectors and per-instance norms, a copy of the iterate). */
 cosmo_status cosmo_solve_size(const cosmo_plan *plan, size_t *sws_bytes);
 
-/* x (d) [n_tot], s, y (d) [m_tot]: the start (in) and the last iterate (out).
+/* x (d) [n_tot], s, y (d) [m_tot]: the start (in) and, per instance, the
+ * iterate at its own count (out; the last one where max_iter came first).
  * iters (h) [B]: steps to tolerance, -1 where max_iter was reached first.
  * rho_out (h, nullable) [B]: the final penalty scalars.  ws (d)
  * [fwd_ws_bytes], sws (d) [sws_bytes], stats (d, nullable).  Returns when the

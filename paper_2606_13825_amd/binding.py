@@ -335,7 +335,8 @@ class CosmoBatch:
               stats=None, ws=None):
         """COSMO run to tolerance with the residual-balancing penalty, checked
         every K steps (K = 1: exact counts).  Returns (iters [B] numpy int32,
-        -1 where max_iter came first; final penalty scalars [B]; x, s, y)."""
+        -1 where max_iter came first; final penalty scalars [B]; x, s, y, each
+        instance's slice the iterate at its own count)."""
         opt = L.CosmoSolveOptions(rho0=rho0, eq_scale=eq_scale, alpha=alpha, eps_abs=eps_abs, eps_rel=eps_rel,
                                   tol_factor=tol_factor, rho_min=rho_min, rho_max=rho_max, max_iter=max_iter,
                                   interval=interval, adapt=int(adapt), pad=0)

@@ -963,7 +963,7 @@ cosmo_status forward_impl(cosmo_plan *pl, const T *rho, const T *alpha, const T 
 // ---- vanilla COSMO to tolerance (residual balancing) ------------------------------
 
 struct SolveLayout {
-  size_t rho, alpha, rho_b, u, rp, p, w, rd, rec, total;
+  size_t rho, alpha, rho_b, u, rp, p, w, rd, rec, xs, ss, ys, total;
 };
 
 SolveLayout solve_layout(const cosmo_plan *pl) {
@@ -985,6 +985,9 @@ SolveLayout solve_layout(const cosmo_plan *pl) {
   L.w = take(n * esz);
   L.rd = take(n * esz);
   L.rec = take(B * sizeof(PolRec));
+  L.xs = take(n * esz);   // each instance's iterate at its own count
+  L.ss = take(m * esz);
+  L.ys = take(m * esz);
   L.total = o;
   return L;
 }
@@ -1012,6 +1015,19 @@ cosmo_status solve_impl(cosmo_plan *pl, const cosmo_solve_options &o, T *x, T *s
     launch_solve_rho<T>(v, rho_b_d, o.eq_scale, rho, K, st);
     return COSMO_OK;
   };
+  T *xs = reinterpret_cast<T *>(sws + L.xs), *ss = reinterpret_cast<T *>(sws + L.ss);
+  T *ys = reinterpret_cast<T *>(sws + L.ys);
+  // copies instance b's slices of (x, s, y) into the saved iterate or back
+  auto save = [&](int b, bool out) -> cosmo_status {
+    const int64_t n0 = pl->n_off[b], n1 = pl->n_off[b + 1], m0 = pl->m_off[b], m1 = pl->m_off[b + 1];
+    const hipMemcpyKind kd = hipMemcpyDeviceToDevice;
+    if (n1 > n0) HIPCHK(hipMemcpyAsync(out ? xs + n0 : x + n0, out ? x + n0 : xs + n0, (n1 - n0) * sizeof(T), kd, st));
+    if (m1 > m0) {
+      HIPCHK(hipMemcpyAsync(out ? ss + m0 : s + m0, out ? s + m0 : ss + m0, (m1 - m0) * sizeof(T), kd, st));
+      HIPCHK(hipMemcpyAsync(out ? ys + m0 : y + m0, out ? y + m0 : ys + m0, (m1 - m0) * sizeof(T), kd, st));
+    }
+    return COSMO_OK;
+  };
   cosmo_status r = upload();
   if (r != COSMO_OK) return r;
   int remaining = B;
@@ -1033,6 +1049,9 @@ cosmo_status solve_impl(cosmo_plan *pl, const cosmo_solve_options &o, T *x, T *s
         done[b] = 1;
         iters[b] = it;
         --remaining;
+        // the batch keeps stepping for the others: keep this instance's iterate
+        r = save(b, true);
+        if (r != COSMO_OK) return r;
         continue;
       }
       if (o.adapt && it % o.interval == 0 && Np > 0 && Nd > 0 && R.mrd > 0) {
@@ -1049,6 +1068,11 @@ cosmo_status solve_impl(cosmo_plan *pl, const cosmo_solve_options &o, T *x, T *s
       if (r != COSMO_OK) return r;
     }
   }
+  for (int b = 0; b < B; ++b)
+    if (done[b]) {
+      r = save(b, false);
+      if (r != COSMO_OK) return r;
+    }
   if (rho_out)
     for (int b = 0; b < B; ++b) rho_out[b] = rho_b[b];
   HIPCHK(hipGetLastError());

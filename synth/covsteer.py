@@ -96,38 +96,48 @@ def covsteer_ltv(A_list: Sequence[np.ndarray], B_list: Sequence[np.ndarray], r_l
                                 d[var] = d.get(var, 0.0) + coef
         return const, lin
 
-    def dense_map(lin, ncols):
-        M = np.zeros((nx * ncols, n))
+    def sparse_map(lin, ncols):
+        r_, c_, v_ = [], [], []
         for (a, c), terms in lin.items():
             for var, f in terms.items():
-                M[a * ncols + c, var] += f
-        return M
+                r_.append(a * ncols + c); c_.append(var); v_.append(f)
+        return sp.csr_matrix((v_, (r_, c_)), shape=(nx * ncols, n))
 
-    Pm = np.zeros((n, n))
+    Pm = sp.csr_matrix((n, n))
     qv = np.zeros(n)
+    blocks_r, blocks_c, blocks_v = [], [], []
     for t in range(N + 1):
         Qt = QN if t == N else Q
-        Pm[mu_off(t):mu_off(t) + nx, mu_off(t):mu_off(t) + nx] += 2.0 * Qt
+        for i in range(nx):
+            for j in range(nx):
+                if Qt[i, j] != 0.0:
+                    blocks_r.append(mu_off(t) + i); blocks_c.append(mu_off(t) + j); blocks_v.append(2.0 * Qt[i, j])
         if t >= 1:                                    # tr(Q_t Sigma_t) = |Q_t^1/2 F_t|_F^2 + const
             const, lin = cov_factor(t)
             Qh = np.linalg.cholesky(Qt).T             # Q_t = Qh' Qh
-            Mlin = dense_map(lin, N * nx)
-            Mq = np.kron(Qh, np.eye(N * nx)) @ Mlin
+            Mq = sp.kron(sp.csr_matrix(Qh), sp.identity(N * nx), format="csr") @ sparse_map(lin, N * nx)
             cq = (Qh @ const).ravel()
-            Pm += 2.0 * Mq.T @ Mq
-            qv += 2.0 * Mq.T @ cq
+            Pm = Pm + 2.0 * (Mq.T @ Mq)
+            qv += 2.0 * (Mq.T @ cq)
     Rh = np.linalg.cholesky(R).T                      # R = Rh' Rh
     for t in range(N):
-        Pm[v_off(t):v_off(t) + nu, v_off(t):v_off(t) + nu] += 2.0 * R
+        for i in range(nu):
+            for j in range(nu):
+                if R[i, j] != 0.0:
+                    blocks_r.append(v_off(t) + i); blocks_c.append(v_off(t) + j); blocks_v.append(2.0 * R[i, j])
         # tr(R K_t Sigma_W K_t') = |R^1/2 K_t Sigma_W^1/2|_F^2, K_t = block row t of K
-        Gm = np.zeros((nu * N * nx, n))
+        gr, gc, gv = [], [], []
         for tau in range(t):
             for r in range(nu):
                 for c in range(nx):
                     for r2 in range(nu):
                         if Rh[r2, r] != 0.0:
-                            Gm[r2 * N * nx + tau * nx + c, kvar(t, tau, r, c)] += Rh[r2, r] * Wh[c]
-        Pm += 2.0 * Gm.T @ Gm
+                            gr.append(r2 * N * nx + tau * nx + c); gc.append(kvar(t, tau, r, c))
+                            gv.append(Rh[r2, r] * Wh[c])
+        if gr:
+            Gm = sp.csr_matrix((gv, (gr, gc)), shape=(nu * N * nx, n))
+            Pm = Pm + 2.0 * (Gm.T @ Gm)
+    Pm = Pm + sp.csr_matrix((blocks_v, (blocks_r, blocks_c)), shape=(n, n))
     qv[e_base:e_base + N * nx] = lam_nu
     rows, cols, vals, b = [], [], [], []
     r = 0
@@ -188,13 +198,15 @@ def covsteer_ltv(A_list: Sequence[np.ndarray], B_list: Sequence[np.ndarray], r_l
     A.sum_duplicates()
     bvec = np.concatenate([np.array(b), bb])
     cones = [Cone(ZERO, n_zero), Cone(NONNEG, n_nonneg)] + soc_cones + [Cone(PSD, p)]
-    Pm = 0.5 * (Pm + Pm.T)
+    Pm = (0.5 * (Pm + Pm.T)).tocsr()
+    Pm.sum_duplicates()
+    Pm.eliminate_zeros()
     md = {"class": "covsteer_ltv", "N": N, "nx": nx, "nu": nu, "k_base": k_base, "nk": nk, "v_base": v_base,
           "nu_base": nu_base, "e_base": e_base, "Sigma_0": Sigma0, "sigma_N": sigma_N, "W": W, "goal": goal,
           "mu0": mu0, "lam_nu": lam_nu}
     if meta:
         md.update(meta)
-    inst = ConicInstance(sp.csr_matrix(Pm), qv, A, bvec, cones, md)
+    inst = ConicInstance(Pm, qv, A, bvec, cones, md)
     inst.check()
     return inst
 

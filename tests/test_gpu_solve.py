@@ -106,12 +106,28 @@ def test_solve_fp32_maxcut_batch():
         k, _, _ = oracle.solve_residual_balancing(inst)
         say(f"  instance {b}: gpu {iters[b]}, oracle {k}")
         assert iters[b] > 0 and abs(int(iters[b]) - k) <= max(2, 0.1 * k)
-    # the last instance to converge stops the batch: its iterate is the one at its count
-    b = int(np.argmax(iters))
-    inst = insts[b]
-    sl_n, sl_m = slice(batch.n_off[b], batch.n_off[b + 1]), slice(batch.m_off[b], batch.m_off[b + 1])
-    xb, sb, yb = xs[sl_n], ss[sl_m], ys[sl_m]
-    rp, rd = oracle.kkt_residuals(inst, xb, sb, yb)
-    Np = max(np.abs(inst.A @ xb).max(), np.abs(sb).max(), np.abs(inst.b).max())
-    Nd = max(np.abs(inst.P @ xb).max(), np.abs(inst.q).max(), np.abs(inst.A.T @ yb).max())
-    assert np.abs(rp).max() <= 1.05 * (1e-3 + 1e-3 * Np) and np.abs(rd).max() <= 1.05 * (1e-3 + 1e-3 * Nd)
+    # each instance's slice holds its iterate at its own count
+    for b, inst in enumerate(insts):
+        sl_n, sl_m = slice(batch.n_off[b], batch.n_off[b + 1]), slice(batch.m_off[b], batch.m_off[b + 1])
+        xb, sb, yb = xs[sl_n], ss[sl_m], ys[sl_m]
+        rp, rd = oracle.kkt_residuals(inst, xb, sb, yb)
+        Np = max(np.abs(inst.A @ xb).max(), np.abs(sb).max(), np.abs(inst.b).max())
+        Nd = max(np.abs(inst.P @ xb).max(), np.abs(inst.q).max(), np.abs(inst.A.T @ yb).max())
+        assert np.abs(rp).max() <= 1.05 * (1e-3 + 1e-3 * Np) and np.abs(rd).max() <= 1.05 * (1e-3 + 1e-3 * Nd)
+
+
+def test_solve_batch_keeps_each_iterate_at_its_own_count_fp64():
+    """In a batch whose instances stop at different counts, every slice of
+    (x, s, y) is the oracle's iterate at that instance's count."""
+    ensure_lib()
+    insts = _closed_form_instances()
+    iters, rho, x, s, y = _batch(insts).solve()
+    assert len(set(iters.tolist())) > 1
+    xs, ss, ys = (t.cpu().numpy() for t in (x, s, y))
+    batch = _batch(insts)
+    for b, inst in enumerate(insts):
+        k, (xr, sr, yr), _ = oracle.solve_residual_balancing(inst)
+        assert iters[b] == k
+        for a, r, off in ((xs, xr, batch.n_off), (ss, sr, batch.m_off), (ys, yr, batch.m_off)):
+            a = a[off[b]:off[b + 1]]
+            assert np.linalg.norm(a - r) <= 1e-8 * max(np.linalg.norm(r), 1.0)

@@ -212,3 +212,23 @@ def test_ltv_builder_cost_matches_the_expected_cost():
         x, y = rng.standard_normal(inst.n), rng.standard_normal(inst.n)
         d = direct(x) - direct(y)
         assert abs((obj(x) - obj(y)) - d) <= 1e-10 * max(1.0, abs(d))
+
+
+def test_scp_expected_cost_recursion_matches_the_oracle_rollout():
+    """The package's SCP merit carries the covariance forward step by step;
+    the oracle's sums transition products.  Both are App. F's expected cost."""
+    import oracle.scp
+    from paper_2606_13825_amd.scp import expected_cost
+    from synth.covsteer import unicycle_scenario
+    rng = np.random.default_rng(6)
+    sc = unicycle_scenario(rng, N=5)
+    N = sc["N"]
+    A = [np.eye(3) + 0.1 * rng.standard_normal((3, 3)) for _ in range(N)]
+    B = [rng.standard_normal((3, 2)) for _ in range(N)]
+    mu, v = rng.standard_normal((N + 1, 3)), rng.standard_normal((N, 2))
+    K = np.zeros((N * 2, N * 3))
+    for t in range(N):
+        K[t * 2:(t + 1) * 2, :t * 3] = rng.standard_normal((2, t * 3))
+    a = expected_cost(sc, A, B, mu, v, K)
+    b = oracle.scp.expected_cost(sc, A, B, mu, v, K)
+    assert abs(a - b) <= 1e-12 * abs(b)
