@@ -145,8 +145,9 @@ def scp_solve(scenarios: Sequence[dict], *, step: Callable, jacobians: Callable,
     number of COSMO steps between their stopping tests (1: exact counts);
     further keywords go to `CosmoBatch.solve`.  Returns one ScpResult per
     scenario; `timing`, when given, collects where the time went, and
-    `progress(round, scenarios_running, seconds)` is called after each outer
-    iteration."""
+    `progress(round, scenarios_running, seconds, inner_steps)` is called
+    after each outer iteration (inner_steps: the convex solves' step counts,
+    -1 where the budget ran out)."""
     if check < 1:
         raise ValueError("check must be >= 1")
     tm = timing if timing is not None else ScpTiming()
@@ -198,6 +199,6 @@ def scp_solve(scenarios: Sequence[dict], *, step: Callable, jacobians: Callable,
         tm.rounds += 1
         tm.batch_sizes.append(len(active))
         if progress is not None:
-            progress(tm.rounds, len(active), t4 - t0)
+            progress(tm.rounds, len(active), t4 - t0, np.asarray(iters))
     return [ScpResult(converged=r.converged, outer=len(r.history), history=r.history, mu=r.mu, v=r.v, K=r.K,
                       inner_total=int(sum(max(h.inner, 0) for h in r.history))) for r in runs]
