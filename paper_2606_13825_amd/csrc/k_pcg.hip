@@ -252,6 +252,47 @@ __device__ inline void class_passes(const int32_t *rows, const RowSpan *span, co
   row_pass<64, AT>(rows, span, cls_off[2 * B1 + b0], cls_off[2 * B1 + b1], g, n, col, val, vin, active, emit);
 }
 
+// The value of v held by lane l, in every lane (no LDS round trip).
+template <typename AT> __device__ inline AT read_lane(AT v, int l) {
+  if constexpr (sizeof(AT) == 8) {
+    const long long b = __double_as_longlong((double)v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return (AT)__longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  } else {
+    return (AT)__int_as_float(__builtin_amdgcn_readlane(__float_as_int((float)v), l));
+  }
+}
+
+// Wave sums of U = 2^k values per lane with 6 + U - 2 shuffles instead of 6 U:
+// each of the first k butterfly steps halves the values a lane holds (the
+// lanes with the step's bit set keep the upper half, the others the lower),
+// the remaining steps sum one value; row u's total then sits in lane
+// u << (6 - k), from where it is read into every lane.
+template <int U, typename AT> __device__ inline void wave_sums(AT (&v)[U]) {
+  static_assert(U == 1 || U == 2 || U == 4 || U == 8, "U must be a power of two <= 8");
+  constexpr int K = U == 1 ? 0 : (U == 2 ? 1 : (U == 4 ? 2 : 3));
+  const int lane = threadIdx.x % 64;
+  AT w[U];
+#pragma unroll
+  for (int i = 0; i < U; ++i) w[i] = v[i];
+#pragma unroll
+  for (int s = 0, cnt = U; s < K; ++s) {
+    const int off = 32 >> s, half = cnt / 2;
+    const bool up = (lane & off) != 0;
+#pragma unroll
+    for (int i = 0; i < half; ++i) {
+      const AT send = up ? w[i] : w[i + half];
+      const AT keep = up ? w[i + half] : w[i];
+      w[i] = keep + __shfl_xor(send, off, 64);
+    }
+    cnt = half;
+  }
+#pragma unroll
+  for (int off = 32 >> K; off > 0; off >>= 1) w[0] += __shfl_xor(w[0], off, 64);
+#pragma unroll
+  for (int u = 0; u < U; ++u) v[u] = read_lane(w[0], u << (6 - K));
+}
+
 // ---- dense sub-blocks inside one instance's workgroup ----------------------------
 //
 // Rows of A covered by a dense placement hold only their CSR part in t after
@@ -270,7 +311,13 @@ __device__ inline void dense_block_fused(const DenseDesc &d, const T *__restrict
                                          TT *__restrict__ t, AT *__restrict__ lds, double *__restrict__ ec) {
   constexpr int VE = 16 / sizeof(TG);
   constexpr int NW = NTH / 64;
-  constexpr int U = 2;
+  // rows in flight per wave: four while a row spans at most two pieces per
+  // lane, two for wider rows (register budget); the block read is bound by
+  // the bytes each CU keeps in flight
+  constexpr int U = MP <= 2 ? 4 : 2;
+  // placements whose t and rho_hat are loaded together with the block row;
+  // further ones are read after the row's dot product
+  constexpr int PRE = 2;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int npieces = (d.cols + VE - 1) / VE;
   AT xv[MP][VE], acc[MP][VE];
@@ -286,51 +333,58 @@ __device__ inline void dense_block_fused(const DenseDesc &d, const T *__restrict
   const int64_t ldp = d.ld / VE;
   for (int r0 = wave; r0 < d.rows; r0 += U * NW) {
     DPiece<TG> g[U][MP];
-    AT tp[U][COSMO_DENSE_MAX_PLACEMENTS], rp[U][COSMO_DENSE_MAX_PLACEMENTS];
+    AT tp[U][PRE], rp[U][PRE];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int r = min(r0 + u * NW, d.rows - 1);   // clamped; surplus rows change nothing
 #pragma unroll
       for (int q = 0; q < MP; ++q) {
-        const int pc = lane + 64 * q;
-        if (pc < npieces) g[u][q] = G[(int64_t)r * ldp + pc];
+        // lanes past the row's end re-read its last piece (their terms are
+        // masked below), so every load of the pass is issued unconditionally
+        const int pc = min(lane + 64 * q, npieces - 1);
+        g[u][q] = G[(int64_t)r * ldp + pc];
       }
 #pragma unroll
-      for (int p = 0; p < COSMO_DENSE_MAX_PLACEMENTS; ++p)
+      for (int p = 0; p < PRE; ++p)
         if (p < d.nplace) {
           tp[u][p] = (AT)t[d.row0[p] + r];
           rp[u][p] = (AT)rho_hat[d.row0[p] + r];
         }
     }
+    // the U rows' dot products, summed over the wave together
+    AT dots[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int r = r0 + u * NW;
-      AT dot = 0;
+      dots[u] = 0;
 #pragma unroll
       for (int q = 0; q < MP; ++q) {
         const int pc = lane + 64 * q;
-        if (pc < npieces)
 #pragma unroll
-          for (int e = 0; e < VE; ++e) dot += (pc * VE + e < d.cols ? (AT)g[u][q].v[e] : (AT)0) * xv[q][e];
+        for (int e = 0; e < VE; ++e) dots[u] += (pc * VE + e < d.cols ? (AT)g[u][q].v[e] : (AT)0) * xv[q][e];
       }
-      dot = sub_sum(dot, 64);
+    }
+    wave_sums<U>(dots);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = r0 + u * NW;
+      const AT dot = dots[u];
       if (r < d.rows) {
         AT w = 0;
 #pragma unroll
         for (int p = 0; p < COSMO_DENSE_MAX_PLACEMENTS; ++p)
           if (p < d.nplace) {
             const AT sc = (AT)d.scale[p];
-            const AT ti = rp[u][p] * (tp[u][p] + sc * dot);
+            const AT tv = p < PRE ? tp[u][p < PRE ? p : 0] : (AT)t[d.row0[p] + r];
+            const AT rv = p < PRE ? rp[u][p < PRE ? p : 0] : (AT)rho_hat[d.row0[p] + r];
+            const AT ti = rv * (tv + sc * dot);
             if (lane == 0) t[d.row0[p] + r] = (TT)ti;
             w += sc * ti;
           }
 #pragma unroll
         for (int q = 0; q < MP; ++q) {
           const int pc = lane + 64 * q;
-          if (pc < npieces)
 #pragma unroll
-            for (int e = 0; e < VE; ++e)
-              if (pc * VE + e < d.cols) acc[q][e] += w * (AT)g[u][q].v[e];
+          for (int e = 0; e < VE; ++e) acc[q][e] += (pc * VE + e < d.cols ? w * (AT)g[u][q].v[e] : (AT)0);
         }
       }
     }
