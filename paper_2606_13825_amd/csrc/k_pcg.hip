@@ -315,9 +315,7 @@ __device__ inline void dense_block_fused(const DenseDesc &d, const T *__restrict
   // lane, two for wider rows (register budget); the block read is bound by
   // the bytes each CU keeps in flight
   constexpr int U = MP <= 2 ? 4 : 2;
-  // placements whose t and rho_hat are loaded together with the block row;
-  // further ones are read after the row's dot product
-  constexpr int PRE = 2;
+  static_assert(COSMO_DENSE_MAX_PLACEMENTS == 4, "one lane per (row, placement): four placements per row");
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int npieces = (d.cols + VE - 1) / VE;
   AT xv[MP][VE], acc[MP][VE];
@@ -329,11 +327,26 @@ __device__ inline void dense_block_fused(const DenseDesc &d, const T *__restrict
       xv[q][e] = c < d.cols ? (AT)vin[d.col0 + c] : (AT)0;
       acc[q][e] = (AT)0;
     }
+  // Lane 4u + p of a pass handles placement p of the pass's row u: it loads
+  // that entry of t and rho_hat (two vector loads per pass instead of one
+  // per row and placement), forms and stores the new entry, and the four
+  // lanes of the row sum their scale * entry into the row's weight.  Lanes
+  // of placements the block does not have take scale 0 and store nothing.
+  const int lu = (lane >> 2) & (U - 1), lp = lane & 3;
+  const bool lplace = lp < d.nplace;
+  int64_t lrow0 = d.row0[0];
+  AT lsc = (AT)d.scale[0];
+#pragma unroll
+  for (int q = 1; q < COSMO_DENSE_MAX_PLACEMENTS; ++q)
+    if (lp == q && lplace) {
+      lrow0 = d.row0[q];
+      lsc = (AT)d.scale[q];
+    }
+  if (!lplace) lsc = (AT)0;
   const DPiece<TG> *G = static_cast<const DPiece<TG> *>(d.val);
   const int64_t ldp = d.ld / VE;
   for (int r0 = wave; r0 < d.rows; r0 += U * NW) {
     DPiece<TG> g[U][MP];
-    AT tp[U][PRE], rp[U][PRE];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int r = min(r0 + u * NW, d.rows - 1);   // clamped; surplus rows change nothing
@@ -344,48 +357,37 @@ __device__ inline void dense_block_fused(const DenseDesc &d, const T *__restrict
         const int pc = min(lane + 64 * q, npieces - 1);
         g[u][q] = G[(int64_t)r * ldp + pc];
       }
-#pragma unroll
-      for (int p = 0; p < PRE; ++p)
-        if (p < d.nplace) {
-          tp[u][p] = (AT)t[d.row0[p] + r];
-          rp[u][p] = (AT)rho_hat[d.row0[p] + r];
-        }
     }
+    const int lr = r0 + lu * NW;
+    const int lrc = min(lr, d.rows - 1);
+    const AT tl = (AT)t[lrow0 + lrc], rl = (AT)rho_hat[lrow0 + lrc];
     // the U rows' dot products, summed over the wave together
     AT dots[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       dots[u] = 0;
 #pragma unroll
-      for (int q = 0; q < MP; ++q) {
-        const int pc = lane + 64 * q;
+      for (int q = 0; q < MP; ++q)
 #pragma unroll
-        for (int e = 0; e < VE; ++e) dots[u] += (pc * VE + e < d.cols ? (AT)g[u][q].v[e] : (AT)0) * xv[q][e];
-      }
+        for (int e = 0; e < VE; ++e) dots[u] += (AT)g[u][q].v[e] * xv[q][e];   // xv is 0 past the row's end
     }
     wave_sums<U>(dots);
+    AT dl = dots[0];
+#pragma unroll
+    for (int u = 1; u < U; ++u) dl = lu == u ? dots[u] : dl;
+    const AT ti = rl * (tl + lsc * dl);
+    if (lane < 4 * U && lplace && lr < d.rows) t[lrow0 + lr] = (TT)ti;
+    AT wl = lsc * ti;
+    wl += __shfl_xor(wl, 1, 64);
+    wl += __shfl_xor(wl, 2, 64);   // lane 4u: row u's weight
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int r = r0 + u * NW;
-      const AT dot = dots[u];
-      if (r < d.rows) {
-        AT w = 0;
+      if (r0 + u * NW < d.rows) {
+        const AT w = read_lane(wl, 4 * u);
 #pragma unroll
-        for (int p = 0; p < COSMO_DENSE_MAX_PLACEMENTS; ++p)
-          if (p < d.nplace) {
-            const AT sc = (AT)d.scale[p];
-            const AT tv = p < PRE ? tp[u][p < PRE ? p : 0] : (AT)t[d.row0[p] + r];
-            const AT rv = p < PRE ? rp[u][p < PRE ? p : 0] : (AT)rho_hat[d.row0[p] + r];
-            const AT ti = rv * (tv + sc * dot);
-            if (lane == 0) t[d.row0[p] + r] = (TT)ti;
-            w += sc * ti;
-          }
+        for (int q = 0; q < MP; ++q)
 #pragma unroll
-        for (int q = 0; q < MP; ++q) {
-          const int pc = lane + 64 * q;
-#pragma unroll
-          for (int e = 0; e < VE; ++e) acc[q][e] += (pc * VE + e < d.cols ? w * (AT)g[u][q].v[e] : (AT)0);
-        }
+          for (int e = 0; e < VE; ++e) acc[q][e] += w * (AT)g[u][q].v[e];   // entries past cols are never read
       }
     }
   }
