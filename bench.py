@@ -64,7 +64,8 @@ NS_PROFILE = os.path.join(ROOT, "profiles", "k_ns_gemm_appc_pmc.md")
 NS_SOURCE = [os.path.join(ROOT, "paper_2606_13825_amd", "csrc", "k_ns.hip"),
              os.path.join(ROOT, "paper_2606_13825_amd", "csrc", "mma_tiles.h")]
 APPB_PROFILE = os.path.join(ROOT, "profiles", "k_pcg_coop_appb_pmc.md")
-PCG_SOURCE = os.path.join(ROOT, "paper_2606_13825_amd", "csrc", "k_pcg.hip")
+PCG_SOURCE = [os.path.join(ROOT, "paper_2606_13825_amd", "csrc", "k_pcg.hip"),
+              os.path.join(ROOT, "paper_2606_13825_amd", "csrc", "wave_ops.h")]
 
 
 def psd_order_class(orders):

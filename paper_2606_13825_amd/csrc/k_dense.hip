@@ -7,15 +7,17 @@
 //
 // Row products   dn[doff + r] = sum_c G_rc vin[col0 + c]
 //   one wave per row, a row's pieces spread over the 64 lanes, four rows in
-//   flight per wave, float64 accumulation, fixed butterfly over the wave.
+//   flight per wave, float64 accumulation, the four rows summed over the
+//   wave together (fixed order).
 // Column products ec[coff + c] = sum_r G_rc w_r  (and ed = sum_r G_rc^2 wd_r)
 //   one workgroup per (block, 64-piece column strip); the workgroup first
-//   forms the row weights of a tile of 256 rows in LDS (w_r sums the
+//   forms the row weights of a tile of 2048 rows in LDS (w_r sums the
 //   placements' scale times the mode's per-row value), then its four waves
 //   walk a quarter of the tile each, every lane owning one piece of the
 //   strip; the four waves' partial sums are added in wave order.  Sums are
 //   float64 and deterministic.
 #include "cosmo_internal.h"
+#include "wave_ops.h"
 
 namespace cosmo {
 namespace {
@@ -23,16 +25,12 @@ namespace {
 constexpr int NT = 256;
 constexpr int NW = NT / 64;
 constexpr int ROWS_PER_WG = 64;     // row products: 16 rows per wave
-constexpr int TILE = 256;           // column products: rows per weight tile
+constexpr int TILE = 2048;          // column products: rows per weight tile (one tile for most blocks)
 
 template <typename T> struct alignas(16) Piece {
   T v[16 / sizeof(T)];
 };
 
-__device__ inline double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
 // Block of the launch's workgroup: the last descriptor whose first workgroup
 // is <= blockIdx.x (descriptors are in increasing order of it).
@@ -80,26 +78,27 @@ __global__ __launch_bounds__(NT) void k_dense_rows(const DenseDesc *__restrict__
     for (int u = 0; u < U; ++u) {
       const int r = min(r0 + u * NW, r_end - 1);   // clamped; surplus rows are not written
 #pragma unroll
-      for (int q = 0; q < MP; ++q) {
-        const int pc = lane + 64 * q;
-        if (pc < npieces) g[u][q] = G[(int64_t)r * ldp + pc];
-      }
+      for (int q = 0; q < MP; ++q)
+        if (q * 64 < npieces)   // uniform over the wave: pieces the block has
+          g[u][q] = G[(int64_t)r * ldp + min(lane + 64 * q, npieces - 1)];   // past the end: its last piece
     }
+    // xv is zero past the block's columns, so the re-read pieces add nothing
+    double dots[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      double acc = 0.0;
+      dots[u] = 0.0;
 #pragma unroll
-      for (int q = 0; q < MP; ++q) {
-        const int pc = lane + 64 * q;
-        if (pc < npieces)
+      for (int q = 0; q < MP; ++q)
+        if (q * 64 < npieces)
 #pragma unroll
-          for (int e = 0; e < VE; ++e)
-            if (pc * VE + e < d.cols) acc += (double)g[u][q].v[e] * xv[q][e];
-      }
-      acc = wave_sum(acc);
-      const int r = r0 + u * NW;
-      if (lane == 0 && r < r_end) dn[d.doff + r] = acc;
+          for (int e = 0; e < VE; ++e) dots[u] += (double)g[u][q].v[e] * xv[q][e];
     }
+    wave_sums<U>(dots);
+    // lane u writes row u's product: one store per pass
+    double mine = dots[0];
+#pragma unroll
+    for (int u = 1; u < U; ++u) mine = lane == u ? dots[u] : mine;
+    if (lane < U && r0 + lane * NW < r_end) dn[d.doff + r0 + lane * NW] = mine;
   }
 }
 
@@ -150,11 +149,11 @@ __global__ __launch_bounds__(NT) void k_dense_cols(const DenseDesc *__restrict__
   for (int t0 = 0; t0 < d.rows; t0 += TILE) {
     const int nr = min(TILE, d.rows - t0);
     __syncthreads();   // the previous tile's weights are no longer read
-    if ((int)threadIdx.x < nr) {
+    for (int i = threadIdx.x; i < nr; i += NT) {
       double w, wd;
-      row_weights<T>(d, a, t0 + threadIdx.x, w, wd);
-      wt[threadIdx.x] = w;
-      wdt[threadIdx.x] = wd;
+      row_weights<T>(d, a, t0 + i, w, wd);
+      wt[i] = w;
+      wdt[i] = wd;
     }
     __syncthreads();
     const int q0 = wave * (TILE / NW);
