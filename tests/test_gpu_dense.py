@@ -6,8 +6,8 @@ batch passed as CSR alone.
 
 Cases: uneven batches mixing instances with and without a dense block;
 widths that are not a multiple of the 16-byte piece nor of the 64-lane strip
-(ragged tails); row counts not a multiple of a workgroup's rows; one, two and
-three placements with scales other than +-1; float64 and float32; float32
+(ragged tails); row counts not a multiple of a workgroup's rows; one to
+four placements with scales other than +-1; float64 and float32; float32
 storage of the blocks in a float64 batch."""
 import numpy as np
 import pytest
@@ -62,7 +62,8 @@ def _batch(dtype):
     insts = [_stacked_instance(rng, 70, 37, (1.0, -1.0)),          # ragged width, two placements
              synth.huber_socp(rng, n_obs=130, n_coef=61, n_soc=6),  # the Huber form, 61 columns
              _stacked_instance(rng, 65, 300, (1.0, -0.5, 2.0)),     # three placements, width > one strip
-             _stacked_instance(rng, 33, 8, (1.0,))]                 # one placement
+             _stacked_instance(rng, 33, 8, (1.0,)),                 # one placement
+             _stacked_instance(rng, 41, 23, (1.0, -1.0, 0.5, -2.0))]  # the most placements a block may have
     plain = synth.huber_socp(rng, n_obs=40, n_coef=9, n_soc=2)
     plain.meta.pop("dense")                                         # an instance given as CSR alone
     insts.insert(2, plain)
@@ -105,7 +106,7 @@ def test_dense_blocks_every_iterate_and_gradients(dtype, tol_it, tol_g, cg_tol):
     rhos, alphas = _hyper(insts, K, dtype)
     say(f"dense blocks {np.dtype(dtype).name}: B={len(insts)} shapes {[x.A.shape for x in insts]} K={K}")
     batch, fw, loss, bw = _run(insts, K, dtype, rhos, alphas, True, cg_tol)
-    assert batch.n_dense == 4
+    assert batch.n_dense == 5
     worst_it = worst_g = 0.0
     for i, inst in enumerate(insts):
         ref = oracle_run(inst, rhos[i].astype(np.float64), alphas[i].astype(np.float64))
@@ -140,7 +141,7 @@ def test_float32_stored_blocks_in_a_float64_batch():
     say(f"float32-stored dense blocks in a float64 batch: B={len(insts)} K={K}")
     b1, f1, l1, g1 = _run(insts, K, np.float64, rhos, alphas, True, 1e-13, dense_f32=True)
     b2, f2, l2, g2 = _run(insts, K, np.float64, rhos, alphas, False, 1e-13)
-    assert b1.n_dense == 4 and b1.dense_val.dtype == torch.float32
+    assert b1.n_dense == 5 and b1.dense_val.dtype == torch.float32
     for a, b in ((f1.x, f2.x), (f1.s, f2.s), (f1.y, f2.y), (l1, l2), (g1.grho, g2.grho), (g1.galpha, g2.galpha),
                  (g1.gx0, g2.gx0), (g1.gs0, g2.gs0), (g1.gy0, g2.gy0)):
         a, b = a.cpu().numpy(), b.cpu().numpy()
@@ -170,7 +171,7 @@ def test_dense_path_equals_csr_path_fp64():
     rhos, alphas = _hyper(insts, K, np.float64, seed=6)
     b1, f1, l1, g1 = _run(insts, K, np.float64, rhos, alphas, True, 1e-13)
     b2, f2, l2, g2 = _run(insts, K, np.float64, rhos, alphas, False, 1e-13)
-    assert b1.n_dense == 4 and b2.n_dense == 0
+    assert b1.n_dense == 5 and b2.n_dense == 0
     assert b1.A_nnz < b2.A_nnz
     for a, b in ((f1.x, f2.x), (f1.s, f2.s), (f1.y, f2.y), (l1, l2), (g1.grho, g2.grho), (g1.galpha, g2.galpha),
                  (g1.gx0, g2.gx0), (g1.gs0, g2.gs0), (g1.gy0, g2.gy0)):
