@@ -60,6 +60,7 @@ EIG_PROFILE = os.path.join(ROOT, "profiles", "k_psd_eig_maxcut64_pmc.md")
 EIG_SOURCE = [os.path.join(ROOT, "paper_2606_13825_amd", "csrc", "k_psd.hip"),
               os.path.join(ROOT, "paper_2606_13825_amd", "csrc", "mma_tiles.h")]
 PCG_PROFILE = os.path.join(ROOT, "profiles", "k_pcg_huber256_pmc.md")
+PCG_C5_PROFILE = os.path.join(ROOT, "profiles", "k_pcg_coop_covsteer128_pmc.md")
 NS_PROFILE = os.path.join(ROOT, "profiles", "k_ns_gemm_appc_pmc.md")
 NS_SOURCE = [os.path.join(ROOT, "paper_2606_13825_amd", "csrc", "k_ns.hip"),
              os.path.join(ROOT, "paper_2606_13825_amd", "csrc", "mma_tiles.h")]
@@ -1032,8 +1033,9 @@ def main():
                          if batch.n_dense else ")"))
         rooflines["pcg"] = {"kernel": kname, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                             "frac": ach / PEAK_HBM_GBS,
-                            "traffic": (traffic_from_profile(PCG_PROFILE, PCG_SOURCE, pcg_form=form)
-                                        if args.workload == "c4" else None),
+                            "traffic": ({"c4": lambda: traffic_from_profile(PCG_PROFILE, PCG_SOURCE, pcg_form=form),
+                                         "c5": lambda: traffic_from_profile(PCG_C5_PROFILE, PCG_SOURCE, pcg_form=form)}
+                                        .get(args.workload, lambda: None)()),
                             "bytes_per_launch": total / n_pcg, "avg_launch_ms": avg_ms, "launches": n_pcg,
                             "mean_cg_iterations": float(iters.sum() / (n_pcg * B)),
                             "mean_residual_passes": float(passes.sum() / (n_pcg * B)),
