@@ -91,12 +91,12 @@ class ScpRecord:
 @dataclass
 class ScpResult:
     converged: bool
-    outer: int
+    outer: int               # outer iterations run
     history: List[ScpRecord]
-    mu: np.ndarray
+    mu: np.ndarray           # the last accepted reference
     v: np.ndarray
     K: np.ndarray
-    inner_total: int = 0
+    inner_total: int = 0     # COSMO steps over all convex solves (a solve stopped by the budget counts it)
 
 
 @dataclass
@@ -200,5 +200,8 @@ def scp_solve(scenarios: Sequence[dict], *, step: Callable, jacobians: Callable,
         tm.batch_sizes.append(len(active))
         if progress is not None:
             progress(tm.rounds, len(active), t4 - t0, np.asarray(iters))
+    # steps actually run: a solve that stopped at the budget ran the budget's
+    # last multiple of the check interval
+    spent = lambda h: h.inner if h.inner >= 0 else inner_max // check * check
     return [ScpResult(converged=r.converged, outer=len(r.history), history=r.history, mu=r.mu, v=r.v, K=r.K,
-                      inner_total=int(sum(max(h.inner, 0) for h in r.history))) for r in runs]
+                      inner_total=int(sum(spent(h) for h in r.history))) for r in runs]
