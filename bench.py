@@ -51,10 +51,17 @@ PEAK_HBM_GBS = 8000.0
 # Algorithmic work of one PSD block of order p: 9 p^3 for a textbook symmetric
 # eigendecomposition (eigenvectors included) + 2 p^3 for U max(L, 0) U'.
 EIG_FLOPS_PER_P3 = 11.0
-# The library's PSD order classes and their float32 eigensolve kernels.
-EIG_KERNEL_NAMES = {0: "k_psd_eig<float,64,4,32> (orders <= 32)", 1: "k_psd_eig<float,256,8,64> (orders 33-64)",
-                    2: "k_psd_eig<float,512,8,128> (orders 65-128)",
-                    3: "k_psd_eig<float,1024,8,200> (orders 129-200)"}
+# The library's PSD order classes: lanes per Jacobi pair, largest order (per
+# dtype for the last class) and the orders they hold.
+EIG_CLASSES = {0: (4, "32", "orders <= 32"), 1: (8, "64", "orders 33-64"), 2: (8, "128", "orders 65-128"),
+               3: (8, None, "orders above 128")}
+
+
+def eig_kernel_name(cls: int, threads: int, f32: bool) -> str:
+    """Instantiation of the eigensolve kernel that ran order class cls."""
+    g, pmax, what = EIG_CLASSES[cls]
+    pmax = pmax or ("200" if f32 else "140")
+    return f"k_psd_eig<{'float' if f32 else 'double'},{threads},{g},{pmax}> ({what})"
 EIG_PROFILE = os.path.join(ROOT, "profiles", "k_psd_eig_maxcut64_pmc.md")
 # the eigensolve kernels are built from k_psd.hip and the shared tile helpers
 EIG_SOURCE = [os.path.join(ROOT, "paper_2606_13825_amd", "csrc", "k_psd.hip"),
@@ -955,6 +962,9 @@ def main():
         form, ms = batch.autotune(rho, alpha, fws)
         sched = {"pcg_form": form, "graph": batch.graph(),
                  "autotune_forward_ms": dict(zip(("form0", "form2", "form4", "form0_graph"), ms))}
+        if any(c.kind == "psd" for inst in insts for c in inst.cones):
+            eig, vjp = batch.psd_schedule()
+            sched.update({"eig_threads_per_class": eig, "vjp_threads": vjp, "autotune_psd_ms": batch.psd_tune_ms()})
     else:
         batch.set_graph(False)
         batch.set_pcg_form(0)
@@ -1007,10 +1017,11 @@ def main():
         avg_ms = ms_dom / max(n_dom, 1)
         ach = flops / (avg_ms * 1e-3) / 1e12
         peak = PEAK_FP32_VECTOR_TFLOPS if wl["dtype"] == "f32" else PEAK_FP64_TFLOPS
-        name = EIG_KERNEL_NAMES[dom] if wl["dtype"] == "f32" else EIG_KERNEL_NAMES[dom].replace("float", "double")
+        name = eig_kernel_name(dom, batch.psd_schedule()[0][dom], wl["dtype"] == "f32")
         rooflines["eig"] = {"kernel": name, "bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
                             "frac": ach / peak,
-                            "traffic": (traffic_from_profile(EIG_PROFILE, EIG_SOURCE, order_class=dom)
+                            "traffic": (traffic_from_profile(EIG_PROFILE, EIG_SOURCE, order_class=dom,
+                                                             threads=batch.psd_schedule()[0][dom])
                                         if args.workload == "c2" else None),
                             "flops_per_launch": flops, "blocks_per_launch": int(np.sum(cls_of == dom)),
                             "avg_launch_ms": avg_ms, "launches": n_dom, "ms_per_step": ms_dom}

@@ -460,13 +460,36 @@ cosmo_status cosmo_plan_get_graph(const cosmo_plan *plan, int32_t *enabled);
  * forms 0, 2, 4 launched eagerly, and form 0 replayed from a graph -- on the
  * given rho, alpha and forward workspace, times the second of two runs with
  * events on `stream`, and keeps the fastest (CG form and graph mode) in the
- * plan.  A setup call, not for the hot path: it allocates a scratch output
- * buffer and waits for the stream.  ms (host, nullable) [4] receives the
+ * plan.  Then, on plans with PSD blocks, it picks the PSD launch shapes (see
+ * cosmo_plan_set_psd_schedule): each order class's eigensolve is timed alone
+ * over forward runs under the class defaults and under the alternatives, and
+ * the DK VJP on the last step's eigenpairs under both thread counts; each
+ * keeps the faster.  A setup call, not for the hot path: it allocates scratch
+ * buffers and waits for the stream.  ms (host, nullable) [4] receives the CG
  * timings in that order (-1 for schedules not run: problems whose reduced
  * matrix is diagonal have no CG, and only the eager and graph runs of form
- * 0 are timed for them). */
+ * 0 are timed for them); cosmo_plan_psd_tune_ms returns the PSD timings. */
 cosmo_status cosmo_plan_autotune(cosmo_plan *plan, const void *rho, const void *alpha, void *ws, void *stream,
                                  double *ms);
+
+/* Launch shapes of the PSD kernels (eq:psd-proj and eq:psd-cotangent-dk; a
+ * schedule choice, not part of the method).  eig_threads (host) [4]: threads
+ * per workgroup of the eigensolve for the order classes p <= 32, <= 64,
+ * <= 128 and larger; each is the class default {64, 256, 512, 1024} or twice
+ * it for the three smaller classes {128, 512, 1024} (the largest class has
+ * no alternative).  vjp_threads: 1024 (16 waves, default) or 512 (8 waves)
+ * per workgroup of the DK VJP.  Other values are COSMO_EINVAL.  The VJP
+ * gives bitwise the same result in both shapes; the eigensolve's workgroup
+ * sums are taken in a different order (results agree to rounding).  Setting
+ * drops graph recordings.  Set-up calls. */
+cosmo_status cosmo_plan_set_psd_schedule(cosmo_plan *plan, const int32_t *eig_threads, int32_t vjp_threads);
+cosmo_status cosmo_plan_get_psd_schedule(const cosmo_plan *plan, int32_t *eig_threads, int32_t *vjp_threads);
+/* Timings (ms) of the last cosmo_plan_autotune's PSD phase.  ms (host) [10]:
+ * ms[c] for c = 0..3 is order class c's eigensolve over one forward under
+ * the defaults, ms[4] one DK VJP pass under 1024 threads; ms[5 + c] and
+ * ms[9] the same under the alternatives; -1 where nothing was timed (absent
+ * classes, plans without PSD blocks, before the first autotune). */
+cosmo_status cosmo_plan_psd_tune_ms(const cosmo_plan *plan, double *ms);
 
 /* Per-step taps for the PSD-backward comparison study (Fig. 3 of the paper:
  * each backward rule applied to the matrix the solver actually projects and

@@ -24,6 +24,7 @@ EXPORTED = [
     "cosmo_plan_set_profiling", "cosmo_plan_profile_read", "cosmo_plan_set_tap",
     "cosmo_plan_set_pcg_form", "cosmo_plan_get_pcg_form", "cosmo_plan_autotune",
     "cosmo_plan_set_graph", "cosmo_plan_get_graph",
+    "cosmo_plan_set_psd_schedule", "cosmo_plan_get_psd_schedule", "cosmo_plan_psd_tune_ms",
     "psd_proj_vjp_rule", "psd_ns_tape_size", "psd_proj_ns", "psd_proj_ns_vjp",
     "cosmo_policy_sizes", "cosmo_policy_forward", "cosmo_policy_backward",
     "cosmo_solve_size", "cosmo_solve",
@@ -199,6 +200,12 @@ def _sig(lib):
     lib.cosmo_plan_get_graph.argtypes = [vp, ctypes.POINTER(i32)]
     lib.cosmo_plan_autotune.restype = ctypes.c_int
     lib.cosmo_plan_autotune.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(dbl)]
+    lib.cosmo_plan_set_psd_schedule.restype = ctypes.c_int
+    lib.cosmo_plan_set_psd_schedule.argtypes = [vp, ctypes.POINTER(i32), i32]
+    lib.cosmo_plan_get_psd_schedule.restype = ctypes.c_int
+    lib.cosmo_plan_get_psd_schedule.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.cosmo_plan_psd_tune_ms.restype = ctypes.c_int
+    lib.cosmo_plan_psd_tune_ms.argtypes = [vp, ctypes.POINTER(dbl)]
 
 
 def lib():

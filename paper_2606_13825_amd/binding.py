@@ -477,11 +477,32 @@ class CosmoBatch:
         L.check(L.lib().cosmo_plan_get_graph(self._plan, ctypes.byref(f)), "cosmo_plan_get_graph")
         return bool(f.value)
 
+    def set_psd_schedule(self, eig_threads, vjp_threads: int = 1024):
+        """PSD launch shapes: eigensolve threads per order class (p <= 32,
+        <= 64, <= 128, larger; defaults 64, 256, 512, 1024, alternatives
+        twice that for the first three) and DK VJP threads (1024 or 512)."""
+        arr = (ctypes.c_int32 * 4)(*[int(t) for t in eig_threads])
+        L.check(L.lib().cosmo_plan_set_psd_schedule(self._plan, arr, int(vjp_threads)), "cosmo_plan_set_psd_schedule")
+
+    def psd_schedule(self):
+        """(eigensolve threads per order class, DK VJP threads) in use."""
+        arr, v = (ctypes.c_int32 * 4)(), ctypes.c_int32()
+        L.check(L.lib().cosmo_plan_get_psd_schedule(self._plan, arr, ctypes.byref(v)), "cosmo_plan_get_psd_schedule")
+        return [int(t) for t in arr], int(v.value)
+
+    def psd_tune_ms(self):
+        """The last autotune's PSD timings: {"default"|"alt": [class 0..3
+        eigensolve ms over one forward, DK VJP ms]}, -1 where not timed."""
+        ms = (ctypes.c_double * 10)()
+        L.check(L.lib().cosmo_plan_psd_tune_ms(self._plan, ms), "cosmo_plan_psd_tune_ms")
+        return {"default": [float(x) for x in ms[:5]], "alt": [float(x) for x in ms[5:]]}
+
     def autotune(self, rho: torch.Tensor, alpha: torch.Tensor, ws: Optional[torch.Tensor] = None):
         """Time the schedules (CG forms 0, 2, 4 eager; form 0 from a graph) on
-        a forward unroll and keep the fastest; returns (chosen CG form,
-        [ms per schedule], -1 where not run).  graph() tells whether graph
-        mode was chosen."""
+        a forward unroll and keep the fastest; then the PSD launch shapes
+        (psd_schedule(), psd_tune_ms()).  Returns (chosen CG form, [ms per
+        schedule], -1 where not run).  graph() tells whether graph mode was
+        chosen."""
         rho = self._check_vec(rho.contiguous(), self.K * self.m_tot, "rho")
         alpha = self._check_vec(alpha.contiguous(), self.K * self.B, "alpha")
         ws = ws if ws is not None else self.new_fwd_ws()

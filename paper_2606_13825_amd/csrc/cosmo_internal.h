@@ -260,7 +260,15 @@ struct PsdLaunchCfg {
   double tol;
   int32_t refine;          // float64 refinement steps after the Jacobi sweeps
   int32_t max_p;           // largest order in the list
+  int32_t threads = 0;     // threads per workgroup of the eigensolve; 0 = the class default
 };
+// Eigensolve threads per workgroup of order class c (orders <= 32, <= 64,
+// <= 128, larger): the default and the one alternative the autotuner times
+// (twice the threads for the three smaller classes; none for the largest).
+constexpr int32_t kEigThreads[4] = {64, 256, 512, 1024};
+constexpr int32_t kEigThreadsAlt[4] = {128, 512, 1024, 1024};
+// Threads per workgroup of the DK VJP: 16 waves (default) or 8.
+constexpr int32_t kVjpThreads = 1024, kVjpThreadsAlt = 512;
 template <typename T> void launch_psd_step(const PsdDesc *d, int32_t n, const PsdLaunchCfg &cfg,
                                            const T *rho_hat, const T *vv, const T *sh, const T *y, T *s_new,
                                            T *y_new, T *U, T *lam, double *rscratch, const T *Uprev,
@@ -268,9 +276,10 @@ template <typename T> void launch_psd_step(const PsdDesc *d, int32_t n, const Ps
 // rule 0 = Daleckii-Krein, 1 = eigendecomposition rule as autograd forms it,
 // 2 = rule 1 at the eigenvalues shifted by eps (Tikhonov).  Returns false
 // (nothing launched) when a block of order max_p does not fit in LDS.
+// threads: kVjpThreads or kVjpThreadsAlt (0 = the default).
 template <typename T> bool launch_psd_vjp(const PsdDesc *d, int32_t n, int32_t max_p, const T *U, const T *lam,
                                           const T *g, T *out, T *scratch, hipStream_t st, int32_t rule = 0,
-                                          double eps = 0.0);
+                                          double eps = 0.0, int32_t threads = 0);
 
 // Newton-Schulz comparison rule.  One block of the tape:
 struct NsDesc {

@@ -1053,27 +1053,37 @@ void launch_psd_step(const PsdDesc *d, int32_t n, const PsdLaunchCfg &cfg, const
   if (n <= 0) return;
   const int mode = (y_new != nullptr) ? 0 : 1;
   const int mp = cfg.max_p;
-  if (mp <= 32) run_eig<T, 64, 4, 32>(d, n, mp, cfg, mode, rho_hat, vv, sh, y, s_new, y_new, U, lam, stats, rscratch, Uprev, st);
-  else if (mp <= 64) run_eig<T, 256, 8, 64>(d, n, mp, cfg, mode, rho_hat, vv, sh, y, s_new, y_new, U, lam, stats, rscratch, Uprev, st);
-  else if (mp <= 128) run_eig<T, 512, 8, 128>(d, n, mp, cfg, mode, rho_hat, vv, sh, y, s_new, y_new, U, lam, stats, rscratch, Uprev, st);
-  else if constexpr (std::is_same<T, float>::value)
-    run_eig<T, 1024, 8, COSMO_MAX_PSD_ORDER_F32>(d, n, mp, cfg, mode, rho_hat, vv, sh, y, s_new, y_new, U, lam, stats,
-                                                rscratch, Uprev, st);
-  else
-    run_eig<T, 1024, 8, COSMO_MAX_PSD_ORDER_F64>(d, n, mp, cfg, mode, rho_hat, vv, sh, y, s_new, y_new, U, lam, stats,
-                                                rscratch, Uprev, st);
+  const int cls = mp <= 32 ? 0 : mp <= 64 ? 1 : mp <= 128 ? 2 : 3;
+  const bool alt = cfg.threads != 0 && cfg.threads == kEigThreadsAlt[cls] && cfg.threads != kEigThreads[cls];
+#define COSMO_EIG(NT_, G_, PMAX_) \
+  run_eig<T, NT_, G_, PMAX_>(d, n, mp, cfg, mode, rho_hat, vv, sh, y, s_new, y_new, U, lam, stats, rscratch, Uprev, st)
+  static_assert(kEigThreads[0] == 64 && kEigThreads[1] == 256 && kEigThreads[2] == 512 && kEigThreads[3] == 1024,
+                "class defaults");
+  static_assert(kEigThreadsAlt[0] == 128 && kEigThreadsAlt[1] == 512 && kEigThreadsAlt[2] == 1024, "class alternatives");
+  if (cls == 0) {
+    if (alt) COSMO_EIG(128, 4, 32); else COSMO_EIG(64, 4, 32);
+  } else if (cls == 1) {
+    if (alt) COSMO_EIG(512, 8, 64); else COSMO_EIG(256, 8, 64);
+  } else if (cls == 2) {
+    if (alt) COSMO_EIG(1024, 8, 128); else COSMO_EIG(512, 8, 128);
+  } else if constexpr (std::is_same<T, float>::value) {
+    COSMO_EIG(1024, 8, COSMO_MAX_PSD_ORDER_F32);
+  } else {
+    COSMO_EIG(1024, 8, COSMO_MAX_PSD_ORDER_F64);
+  }
+#undef COSMO_EIG
 }
 
-// 16 waves: a block of order ~100 has 49 output tiles per product, so the
-// longest wave runs 4 of them instead of 7 with 8 waves.
-constexpr int VJP_NT = 1024;
-
-template <typename T>
-bool launch_psd_vjp(const PsdDesc *d, int32_t n, int32_t max_p, const T *U, const T *lam, const T *g, T *out,
-                    T *scratch, hipStream_t st, int32_t rule, double eps) {
-  if (n <= 0) return true;
+// 16 waves by default: a block of order ~100 has 49 output tiles per
+// product, so the longest wave runs 4 of them instead of 7 with 8 waves; the
+// autotuner may pick 8 waves (two workgroups per compute unit where LDS
+// allows).  Every tile is formed by one wave with the same instructions
+// whichever wave it is, so both shapes give bitwise the same result.
+template <typename T, int NT>
+bool run_vjp(const PsdDesc *d, int32_t n, int32_t max_p, const T *U, const T *lam, const T *g, T *out, T *scratch,
+             hipStream_t st, int32_t rule, double eps) {
   static size_t dyn_bytes = 0;
-  if (dyn_bytes == 0) dyn_bytes = set_dyn_lds_cap(reinterpret_cast<const void *>(&k_psd_vjp<T, VJP_NT>));
+  if (dyn_bytes == 0) dyn_bytes = set_dyn_lds_cap(reinterpret_cast<const void *>(&k_psd_vjp<T, NT>));
   // LDS holds B0 (and B1, then U) at the padded stride while they fit; the
   // largest orders keep only B0, unpadded (order 200 in float32: 160,000
   // bytes), with B1 in the global scratch.
@@ -1086,8 +1096,17 @@ bool launch_psd_vjp(const PsdDesc *d, int32_t n, int32_t max_p, const T *U, cons
   else if (ppl <= budget) elems = ppl;
   else if (pp <= budget) elems = pp;   // every order the validation admits fits here
   else return false;
-  k_psd_vjp<T, VJP_NT><<<n, VJP_NT, elems * sizeof(T), st>>>(d, U, lam, g, out, scratch, (int32_t)elems, rule, (T)eps);
+  k_psd_vjp<T, NT><<<n, NT, elems * sizeof(T), st>>>(d, U, lam, g, out, scratch, (int32_t)elems, rule, (T)eps);
   return true;
+}
+
+template <typename T>
+bool launch_psd_vjp(const PsdDesc *d, int32_t n, int32_t max_p, const T *U, const T *lam, const T *g, T *out,
+                    T *scratch, hipStream_t st, int32_t rule, double eps, int32_t threads) {
+  if (n <= 0) return true;
+  static_assert(kVjpThreads == 1024 && kVjpThreadsAlt == 512, "VJP shapes");
+  if (threads == kVjpThreadsAlt) return run_vjp<T, 512>(d, n, max_p, U, lam, g, out, scratch, st, rule, eps);
+  return run_vjp<T, 1024>(d, n, max_p, U, lam, g, out, scratch, st, rule, eps);
 }
 
 template void launch_psd_step<float>(const PsdDesc *, int32_t, const PsdLaunchCfg &, const float *, const float *,
@@ -1097,7 +1116,7 @@ template void launch_psd_step<double>(const PsdDesc *, int32_t, const PsdLaunchC
                                       const double *, const double *, const double *, double *, double *, double *,
                                       double *, double *, const double *, cosmo_stats *, hipStream_t);
 template bool launch_psd_vjp<float>(const PsdDesc *, int32_t, int32_t, const float *, const float *, const float *,
-                                    float *, float *, hipStream_t, int32_t, double);
+                                    float *, float *, hipStream_t, int32_t, double, int32_t);
 template bool launch_psd_vjp<double>(const PsdDesc *, int32_t, int32_t, const double *, const double *,
-                                     const double *, double *, double *, hipStream_t, int32_t, double);
+                                     const double *, double *, double *, hipStream_t, int32_t, double, int32_t);
 }  // namespace cosmo

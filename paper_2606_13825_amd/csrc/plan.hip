@@ -93,6 +93,10 @@ struct cosmo_plan {
   int32_t n_psd = 0;
   int32_t psd_cls_begin[5] = {0, 0, 0, 0, 0};
   int32_t psd_cls_maxp[4] = {0, 0, 0, 0};
+  // launch shapes of the PSD kernels: eigensolve threads per order class, DK VJP threads
+  int32_t eig_threads[4] = {kEigThreads[0], kEigThreads[1], kEigThreads[2], kEigThreads[3]};
+  int32_t vjp_threads = kVjpThreads;
+  double psd_tune_ms[2][5] = {{-1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1}};   // last autotune: [default|alt][class 0..3, VJP]
   RectDesc *d_rect = nullptr;
   int32_t n_rect = 0;
   RowBuckets bkA, bkAt;
@@ -741,7 +745,8 @@ void launch_psd_classes(cosmo_plan *pl, const T *rho_hat, const T *vv, const T *
   const bool refine = pl->opt.dtype == COSMO_F32 && pl->opt.eig_refine > 0;
   fork_classes(pl, st, [&](int c, hipStream_t s) {
     const int n = pl->psd_cls_begin[c + 1] - pl->psd_cls_begin[c];
-    PsdLaunchCfg cfg{pl->opt.eig_max_sweeps, pl->opt.eig_tol, refine ? pl->opt.eig_refine : 0, pl->psd_cls_maxp[c]};
+    PsdLaunchCfg cfg{pl->opt.eig_max_sweeps, pl->opt.eig_tol, refine ? pl->opt.eig_refine : 0, pl->psd_cls_maxp[c],
+                     pl->eig_threads[c]};
     ProfScope pc(pl, 4 + c, s);   // this class's kernel alone, on the stream it runs on
     launch_psd_step<T>(pl->d_psd + pl->psd_cls_begin[c], n, cfg, rho_hat, vv, sh, y, s_new, y_new, U, lam,
                        refine ? rscratch : nullptr, Uprev, stats, s);
@@ -754,7 +759,9 @@ bool launch_dk_classes(cosmo_plan *pl, const T *U, const T *lam, const T *g, T *
   bool ok = true;
   fork_classes(pl, st, [&](int c, hipStream_t s) {
     const int n = pl->psd_cls_begin[c + 1] - pl->psd_cls_begin[c];
-    ok = launch_psd_vjp<T>(pl->d_psd + pl->psd_cls_begin[c], n, pl->psd_cls_maxp[c], U, lam, g, out, scratch, s) && ok;
+    ok = launch_psd_vjp<T>(pl->d_psd + pl->psd_cls_begin[c], n, pl->psd_cls_maxp[c], U, lam, g, out, scratch, s, 0,
+                           0.0, pl->vjp_threads) &&
+         ok;
   });
   return ok;
 }
@@ -1514,6 +1521,91 @@ cosmo_status cosmo_plan_get_pcg_form(const cosmo_plan *plan, int32_t *form) {
   return COSMO_OK;
 }
 
+cosmo_status cosmo_plan_set_psd_schedule(cosmo_plan *plan, const int32_t *eig_threads, int32_t vjp_threads) {
+  cosmo_status s = check_plan(plan);
+  if (s != COSMO_OK) return s;
+  if (!eig_threads) FAIL(COSMO_EINVAL, "eig_threads is NULL");
+  for (int c = 0; c < 4; ++c)
+    if (eig_threads[c] != kEigThreads[c] && eig_threads[c] != kEigThreadsAlt[c])
+      FAIL(COSMO_EINVAL, "eig_threads[" + std::to_string(c) + "] must be " + std::to_string(kEigThreads[c]) +
+                             (kEigThreadsAlt[c] != kEigThreads[c] ? " or " + std::to_string(kEigThreadsAlt[c]) : ""));
+  if (vjp_threads != kVjpThreads && vjp_threads != kVjpThreadsAlt) FAIL(COSMO_EINVAL, "vjp_threads must be 512 or 1024");
+  plan->drop_graphs();   // recorded sequences hold the previous launch shapes
+  for (int c = 0; c < 4; ++c) plan->eig_threads[c] = eig_threads[c];
+  plan->vjp_threads = vjp_threads;
+  return COSMO_OK;
+}
+
+cosmo_status cosmo_plan_get_psd_schedule(const cosmo_plan *plan, int32_t *eig_threads, int32_t *vjp_threads) {
+  cosmo_status s = check_plan(plan);
+  if (s != COSMO_OK) return s;
+  if (!eig_threads || !vjp_threads) FAIL(COSMO_EINVAL, "eig_threads and vjp_threads are required");
+  for (int c = 0; c < 4; ++c) eig_threads[c] = plan->eig_threads[c];
+  *vjp_threads = plan->vjp_threads;
+  return COSMO_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Second phase of the autotuner: the PSD launch shapes, with the CG schedule
+// already fixed.  Each order class's eigensolve is timed alone by the plan's
+// per-class events over a forward run under the class defaults and one under
+// the alternatives (the first run of each warms code objects and caches); a
+// class keeps the shape that ran faster.  The DK VJP is then timed under both
+// thread counts on the eigenpairs the last forward step left in the workspace
+// (its cost does not depend on the values), with a scratch cotangent.
+template <typename T>
+cosmo_status tune_psd(cosmo_plan *pl, const void *rho, const void *alpha, void *ws, hipStream_t st, void *xK, void *sK,
+                      void *yK, hipEvent_t e0, hipEvent_t e1) {
+  cosmo_status s = COSMO_OK;
+  bool has[4];
+  for (int c = 0; c < 4; ++c) has[c] = pl->psd_cls_begin[c + 1] > pl->psd_cls_begin[c];
+  for (int a = 0; a < 2 && s == COSMO_OK; ++a) {
+    for (int c = 0; c < 4; ++c) pl->eig_threads[c] = a ? kEigThreadsAlt[c] : kEigThreads[c];
+    for (int rep = 0; rep < 2 && s == COSMO_OK; ++rep) {
+      pl->profiling = true;
+      for (auto &sl : pl->prof) sl.used = 0;
+      s = cosmo_unroll_forward(pl, rho, alpha, nullptr, nullptr, nullptr, xK, sK, yK, nullptr, ws, nullptr, st);
+    }
+    for (int c = 0; c < 4 && s == COSMO_OK; ++c)
+      if (has[c]) s = cosmo_plan_profile_read(pl, 4 + c, nullptr, &pl->psd_tune_ms[a][c]);
+  }
+  pl->profiling = false;
+  for (auto &sl : pl->prof) sl.used = 0;
+  for (int c = 0; c < 4; ++c)
+    pl->eig_threads[c] = (s == COSMO_OK && has[c] && kEigThreadsAlt[c] != kEigThreads[c] &&
+                          pl->psd_tune_ms[1][c] < pl->psd_tune_ms[0][c])
+                             ? kEigThreadsAlt[c]
+                             : kEigThreads[c];
+  if (s != COSMO_OK) return s;
+  DevBuf scr;
+  HIPCHK(hipMalloc(&scr.ptr, (size_t)std::max<int64_t>(pl->sum_p2_large, 1) * sizeof(T)));
+  T *w = static_cast<T *>(ws);
+  for (int a = 0; a < 2; ++a) {
+    pl->vjp_threads = a ? kVjpThreadsAlt : kVjpThreads;
+    for (int rep = 0; rep < 2; ++rep) {
+      (void)hipEventRecord(e0, st);
+      if (!launch_dk_classes<T>(pl, w + pl->fw.U, w + pl->fw.lam, static_cast<const T *>(yK), static_cast<T *>(sK),
+                                static_cast<T *>(scr.ptr), st))
+        FAIL(COSMO_EUNSUPPORTED, "a PSD block is too large for the VJP's LDS layout");
+      (void)hipEventRecord(e1, st);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    pl->psd_tune_ms[a][4] = ms;
+  }
+  pl->vjp_threads = pl->psd_tune_ms[1][4] < pl->psd_tune_ms[0][4] ? kVjpThreadsAlt : kVjpThreads;
+  return COSMO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 cosmo_status cosmo_plan_autotune(cosmo_plan *plan, const void *rho, const void *alpha, void *ws, void *stream,
                                  double *ms_out) {
   cosmo_status s = check_plan(plan);
@@ -1563,14 +1655,31 @@ cosmo_status cosmo_plan_autotune(cosmo_plan *plan, const void *rho, const void *
       best_c = c;
     }
   }
+  plan->pcg_form = (s == COSMO_OK && best_c >= 0) ? cand_form[best_c] : keep_form;
+  plan->graph = (s == COSMO_OK && best_c >= 0) ? cand_graph[best_c] : keep_graph;
+  for (auto &row : plan->psd_tune_ms)
+    for (double &t : row) t = -1.0;
+  if (s == COSMO_OK && plan->n_psd > 0) {
+    plan->drop_graphs();
+    s = plan->opt.dtype == COSMO_F32 ? tune_psd<float>(plan, rho, alpha, ws, st, xK, sK, yK, e0, e1)
+                                     : tune_psd<double>(plan, rho, alpha, ws, st, xK, sK, yK, e0, e1);
+  }
   (void)hipStreamSynchronize(st);   // nothing in flight reads the scratch outputs when they are freed
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   plan->drop_graphs();   // the recorded sequences point at the scratch outputs
   plan->profiling = keep_prof;
-  plan->pcg_form = (s == COSMO_OK && best_c >= 0) ? cand_form[best_c] : keep_form;
-  plan->graph = (s == COSMO_OK && best_c >= 0) ? cand_graph[best_c] : keep_graph;
+  for (auto &sl : plan->prof) sl.used = 0;
   return s;
+}
+
+cosmo_status cosmo_plan_psd_tune_ms(const cosmo_plan *plan, double *ms) {
+  cosmo_status s = check_plan(plan);
+  if (s != COSMO_OK) return s;
+  if (!ms) FAIL(COSMO_EINVAL, "ms is NULL");
+  for (int a = 0; a < 2; ++a)
+    for (int c = 0; c < 5; ++c) ms[5 * a + c] = plan->psd_tune_ms[a][c];
+  return COSMO_OK;
 }
 
 // ---- profiling (not part of the hot path) -------------------------------------

@@ -33,13 +33,16 @@ def _hyper(insts, K, seed, spread=0.5, dtype=np.float32):
 
 
 def _run_and_check(insts, K, rhos, alphas, check_idx, tol_it, tol_g, dtype=torch.float32, form=None,
-                   autotune=False, **kw):
+                   autotune=False, schedule=None, **kw):
     from paper_2606_13825_amd import CosmoBatch
     batch = CosmoBatch(insts, K=K, dtype=dtype, device=DEV, **kw)
     rho = torch.from_numpy(np.concatenate(rhos, axis=1)).to(DEV)
     alpha = torch.from_numpy(np.stack(alphas, axis=1)).to(DEV)
     if form is not None:
         batch.set_pcg_form(form)
+    if schedule is not None:
+        batch.set_psd_schedule(*schedule)
+        assert batch.psd_schedule() == (list(schedule[0]), schedule[1])
     if autotune:
         chosen, ms = batch.autotune(rho, alpha)
         graphed = batch.graph()
@@ -185,3 +188,72 @@ def test_covsteer_autotuned_schedule():
     K = 6
     rhos, alphas = _hyper(insts, K, 54)
     _run_and_check(insts, K, rhos, alphas, range(4), 1e-5, 1e-4, autotune=True, cg_tol=1e-7, cg_max_iter=2000)
+
+
+# PSD launch shapes: eigensolve threads per order class (p <= 32, <= 64,
+# <= 128, larger) and DK VJP threads, the defaults and the alternatives.
+EIG_DEFAULT, EIG_ALT = [64, 256, 512, 1024], [128, 512, 1024, 1024]
+
+
+def _maxcut_classes(orders, seed, dtype):
+    rng = np.random.default_rng(seed)
+    return [synth.maxcut_sdp(p, synth.erdos_renyi(p, 0.3, rng)).astype(dtype) for p in orders]
+
+
+@pytest.mark.parametrize("dtype,orders,tol_it,tol_g", [(torch.float64, (20, 50, 100, 140), 1e-10, 1e-8),
+                                                       (torch.float32, (20, 50, 100, 180), 1e-5, 1e-4)])
+def test_alternative_psd_shapes_match_oracle(dtype, orders, tol_it, tol_g):
+    """Every order class under its alternative eigensolve shape and the DK VJP
+    with 8 waves: iterates and gradients at the oracle's, at the bars of the
+    default shapes."""
+    ensure_lib()
+    npd = np.float64 if dtype == torch.float64 else np.float32
+    insts = _maxcut_classes(orders, 61, npd)
+    K = 10
+    rhos, alphas = _hyper(insts, K, 62, dtype=npd)
+    say(f"maxcut orders {orders} {dtype} K={K} under eigensolve threads {EIG_ALT}, VJP 512")
+    _run_and_check(insts, K, rhos, alphas, range(len(insts)), tol_it, tol_g, dtype=dtype, schedule=(EIG_ALT, 512))
+
+
+def test_vjp_shapes_bitwise_equal():
+    """The DK VJP with 8 and with 16 waves per workgroup gives bitwise the
+    same reverse pass (each output tile is formed by one wave alike)."""
+    ensure_lib()
+    from paper_2606_13825_amd import CosmoBatch
+    insts = _maxcut_classes((20, 50, 100, 180), 63, np.float32)
+    K = 6
+    rhos, alphas = _hyper(insts, K, 64)
+    batch = CosmoBatch(insts, K=K, dtype=torch.float32, device=DEV)
+    rho = torch.from_numpy(np.concatenate(rhos, axis=1)).to(DEV)
+    alpha = torch.from_numpy(np.stack(alphas, axis=1)).to(DEV)
+    fw = batch.forward(rho, alpha)
+    _, g = batch.residual_loss(fw.x, fw.s, fw.y)
+    out = []
+    for vjp in (1024, 512):
+        batch.set_psd_schedule(EIG_DEFAULT, vjp)
+        bw = batch.backward(rho, alpha, fw.tape, *g)
+        torch.cuda.synchronize()
+        out.append([t.clone() for t in (bw.grho, bw.galpha)])
+    say(f"  max |grho| {out[0][0].abs().max().item():.3e}")
+    assert torch.isfinite(out[0][0]).all()
+    for a, b in zip(out[0], out[1]):
+        assert torch.equal(a, b)
+
+
+def test_autotuned_psd_shapes():
+    """The autotuner's PSD phase keeps, per order class and for the VJP, the
+    shape it timed faster, and the run that follows stays at the oracle."""
+    ensure_lib()
+    insts = _maxcut_classes((20, 50, 100, 180), 65, np.float32)
+    K = 6
+    rhos, alphas = _hyper(insts, K, 66)
+    batch = _run_and_check(insts, K, rhos, alphas, range(len(insts)), 1e-5, 1e-4, autotune=True)
+    eig, vjp = batch.psd_schedule()
+    tm = batch.psd_tune_ms()
+    say(f"  PSD shapes {eig} VJP {vjp}; timings {tm}")
+    for c in range(4):
+        assert tm["default"][c] > 0 and tm["alt"][c] > 0
+        faster_alt = tm["alt"][c] < tm["default"][c] and EIG_ALT[c] != EIG_DEFAULT[c]
+        assert eig[c] == (EIG_ALT[c] if faster_alt else EIG_DEFAULT[c])
+    assert tm["default"][4] > 0 and tm["alt"][4] > 0
+    assert vjp == (512 if tm["alt"][4] < tm["default"][4] else 1024)
