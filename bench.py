@@ -826,6 +826,9 @@ def main():
                     help="instances timed in the plain (unbatched forward-only) comparison")
     ap.add_argument("--schedule", default="auto", choices=["auto", "eager0"],
                     help="auto: the autotuner's choice; eager0: CG form 0, eager launches")
+    ap.add_argument("--psd-threads", default=None,
+                    help="with --schedule eager0: eigensolve threads per order class and DK VJP threads, "
+                         "five comma-separated numbers (e.g. 128,512,1024,1024,1024); default: the class defaults")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-floor", action="store_true",
                     help="skip the float32 floor of the error sample (the oracle's rounding model)")
@@ -969,6 +972,14 @@ def main():
         batch.set_graph(False)
         batch.set_pcg_form(0)
         sched = {"pcg_form": 0, "graph": False, "autotune_forward_ms": None}
+        if args.psd_threads:
+            t = [int(v) for v in args.psd_threads.split(",")]
+            if len(t) != 5:
+                raise SystemExit("--psd-threads takes five numbers: four order classes and the VJP")
+            batch.set_psd_schedule(t[:4], t[4])
+        if any(c.kind == "psd" for inst in insts for c in inst.cones):
+            eig, vjp = batch.psd_schedule()
+            sched.update({"eig_threads_per_class": eig, "vjp_threads": vjp})
     print(f"[bench] autotune: {sched}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
