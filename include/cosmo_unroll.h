@@ -491,6 +491,51 @@ cosmo_status cosmo_plan_get_psd_schedule(const cosmo_plan *plan, int32_t *eig_th
  * classes, plans without PSD blocks, before the first autotune). */
 cosmo_status cosmo_plan_psd_tune_ms(const cosmo_plan *plan, double *ms);
 
+/* A plan's whole launch schedule (the choices cosmo_plan_autotune makes). */
+typedef struct {
+  int32_t pcg_form;            /* CG form, 0..4 (cosmo_plan_set_pcg_form)              */
+  int32_t graph;               /* graph mode, 0 or 1 (cosmo_plan_set_graph)             */
+  int32_t eig_threads[4];      /* eigensolve threads per order class                    */
+  int32_t vjp_threads;         /* DK VJP threads, 1024 or 512                            */
+} cosmo_schedule;
+
+/* get: the plan's current schedule.  set: applies all of it or nothing (each
+ * field is checked as by the single setters; on an error the plan keeps its
+ * CG form and graph mode and the error names the field).  Set-up calls. */
+cosmo_status cosmo_plan_get_schedule(const cosmo_plan *plan, cosmo_schedule *sched);
+cosmo_status cosmo_plan_set_schedule(cosmo_plan *plan, const cosmo_schedule *sched);
+
+/* Problem signature of a plan, the key of the schedule cache: the device's
+ * target name (e.g. gfx950) and compute-unit count, dtype, K, B, n_tot,
+ * m_tot, and a 64-bit FNV-1a hash of the options, the per-instance offsets,
+ * the nonzero counts of A and P, the cone structure (SOC count, PSD order
+ * classes with their sizes and largest orders) and the dense blocks' shapes.
+ * The values of the problem data are not part of it.  buf (host) receives a
+ * NUL-terminated string of printable characters; len < its length + 1 is
+ * COSMO_EINVAL (256 bytes always suffice). */
+cosmo_status cosmo_plan_signature(const cosmo_plan *plan, char *buf, int64_t len);
+
+/* Schedule cache: a text file of JSON objects, one per line,
+ *   {"key": "<signature>", "pcg_form": f, "graph": g,
+ *    "eig_threads": [a, b, c, d], "vjp_threads": v}
+ * load: *found = 1 and *sched set from the last line with that key, else
+ * *found = 0 (a missing file is a miss).  Lines this library did not write
+ * are skipped.  store: rewrites the file (through `path`.tmp, then rename)
+ * with every other key's lines kept and this key's line replaced or added;
+ * an unwritable path is COSMO_EINVAL.  Keys are 1..255 printable characters
+ * without quotes or backslashes (COSMO_EINVAL otherwise).  Host-only calls;
+ * concurrent stores to one file from several processes may lose entries. */
+cosmo_status cosmo_schedule_cache_load(const char *path, const char *key, cosmo_schedule *sched, int32_t *found);
+cosmo_status cosmo_schedule_cache_store(const char *path, const char *key, const cosmo_schedule *sched);
+
+/* Autotuner with the cache: looks up the plan's signature in the file at
+ * `path`; on a hit (*hit = 1) applies that schedule without timing anything;
+ * otherwise (*hit = 0) runs cosmo_plan_autotune on rho, alpha and ws and
+ * stores the chosen schedule under the signature.  An entry the plan
+ * rejects is treated as a miss and replaced. */
+cosmo_status cosmo_plan_autotune_cached(cosmo_plan *plan, const void *rho, const void *alpha, void *ws, void *stream,
+                                        const char *path, int32_t *hit);
+
 /* Per-step taps for the PSD-backward comparison study (Fig. 3 of the paper:
  * each backward rule applied to the matrix the solver actually projects and
  * to the cotangent the reverse pass actually delivers).  tap (d): [K][2][m_tot]

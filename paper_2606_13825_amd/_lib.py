@@ -25,6 +25,8 @@ EXPORTED = [
     "cosmo_plan_set_pcg_form", "cosmo_plan_get_pcg_form", "cosmo_plan_autotune",
     "cosmo_plan_set_graph", "cosmo_plan_get_graph",
     "cosmo_plan_set_psd_schedule", "cosmo_plan_get_psd_schedule", "cosmo_plan_psd_tune_ms",
+    "cosmo_plan_get_schedule", "cosmo_plan_set_schedule", "cosmo_plan_signature",
+    "cosmo_schedule_cache_load", "cosmo_schedule_cache_store", "cosmo_plan_autotune_cached",
     "psd_proj_vjp_rule", "psd_ns_tape_size", "psd_proj_ns", "psd_proj_ns_vjp",
     "cosmo_policy_sizes", "cosmo_policy_forward", "cosmo_policy_backward",
     "cosmo_solve_size", "cosmo_solve",
@@ -114,6 +116,15 @@ class CosmoStats(ctypes.Structure):
                 ("nonfinite", ctypes.c_int32), ("eig_sweeps_total", ctypes.c_int32),
                 ("eig_solves", ctypes.c_int32), ("cg_iters_total", ctypes.c_int32),
                 ("cg_passes_total", ctypes.c_int32), ("eig_refine_steps_total", ctypes.c_int32)]
+
+
+class CosmoSchedule(ctypes.Structure):
+    _fields_ = [("pcg_form", ctypes.c_int32), ("graph", ctypes.c_int32), ("eig_threads", ctypes.c_int32 * 4),
+                ("vjp_threads", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"pcg_form": self.pcg_form, "graph": bool(self.graph), "eig_threads": list(self.eig_threads),
+                "vjp_threads": self.vjp_threads}
 
 
 STATS_FIELDS = ["cg_iters_max", "cg_not_converged", "eig_sweeps_max", "eig_not_converged", "nonfinite",
@@ -206,6 +217,19 @@ def _sig(lib):
     lib.cosmo_plan_get_psd_schedule.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.cosmo_plan_psd_tune_ms.restype = ctypes.c_int
     lib.cosmo_plan_psd_tune_ms.argtypes = [vp, ctypes.POINTER(dbl)]
+    sp = ctypes.POINTER(CosmoSchedule)
+    lib.cosmo_plan_get_schedule.restype = ctypes.c_int
+    lib.cosmo_plan_get_schedule.argtypes = [vp, sp]
+    lib.cosmo_plan_set_schedule.restype = ctypes.c_int
+    lib.cosmo_plan_set_schedule.argtypes = [vp, sp]
+    lib.cosmo_plan_signature.restype = ctypes.c_int
+    lib.cosmo_plan_signature.argtypes = [vp, ctypes.c_char_p, ctypes.c_int64]
+    lib.cosmo_schedule_cache_load.restype = ctypes.c_int
+    lib.cosmo_schedule_cache_load.argtypes = [ctypes.c_char_p, ctypes.c_char_p, sp, ctypes.POINTER(i32)]
+    lib.cosmo_schedule_cache_store.restype = ctypes.c_int
+    lib.cosmo_schedule_cache_store.argtypes = [ctypes.c_char_p, ctypes.c_char_p, sp]
+    lib.cosmo_plan_autotune_cached.restype = ctypes.c_int
+    lib.cosmo_plan_autotune_cached.argtypes = [vp, vp, vp, vp, vp, ctypes.c_char_p, ctypes.POINTER(i32)]
 
 
 def lib():

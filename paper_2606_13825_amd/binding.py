@@ -15,6 +15,7 @@ and A without those entries as CSR.
 from __future__ import annotations
 
 import ctypes
+import os
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
@@ -496,6 +497,35 @@ class CosmoBatch:
         ms = (ctypes.c_double * 10)()
         L.check(L.lib().cosmo_plan_psd_tune_ms(self._plan, ms), "cosmo_plan_psd_tune_ms")
         return {"default": [float(x) for x in ms[:5]], "alt": [float(x) for x in ms[5:]]}
+
+    def schedule(self) -> dict:
+        """The plan's whole launch schedule (CG form, graph mode, PSD shapes)."""
+        sc = L.CosmoSchedule()
+        L.check(L.lib().cosmo_plan_get_schedule(self._plan, ctypes.byref(sc)), "cosmo_plan_get_schedule")
+        return sc.as_dict()
+
+    def set_schedule(self, pcg_form: int, graph: bool, eig_threads, vjp_threads: int):
+        sc = L.CosmoSchedule(int(pcg_form), int(bool(graph)), (ctypes.c_int32 * 4)(*[int(t) for t in eig_threads]),
+                             int(vjp_threads))
+        L.check(L.lib().cosmo_plan_set_schedule(self._plan, ctypes.byref(sc)), "cosmo_plan_set_schedule")
+
+    def signature(self) -> str:
+        """Key of this plan's entry in a schedule cache."""
+        buf = ctypes.create_string_buffer(256)
+        L.check(L.lib().cosmo_plan_signature(self._plan, buf, 256), "cosmo_plan_signature")
+        return buf.value.decode()
+
+    def autotune_cached(self, rho: torch.Tensor, alpha: torch.Tensor, path: str,
+                        ws: Optional[torch.Tensor] = None) -> bool:
+        """Schedule from the cache file at `path` when it holds this plan's
+        signature (returns True), else autotune and record it (False)."""
+        rho = self._check_vec(rho.contiguous(), self.K * self.m_tot, "rho")
+        alpha = self._check_vec(alpha.contiguous(), self.K * self.B, "alpha")
+        ws = ws if ws is not None else self.new_fwd_ws()
+        hit = ctypes.c_int32()
+        L.check(L.lib().cosmo_plan_autotune_cached(self._plan, _ptr(rho), _ptr(alpha), _ptr(ws), _stream(self.device),
+                                                    os.fsencode(path), ctypes.byref(hit)), "cosmo_plan_autotune_cached")
+        return bool(hit.value)
 
     def autotune(self, rho: torch.Tensor, alpha: torch.Tensor, ws: Optional[torch.Tensor] = None):
         """Time the schedules (CG forms 0, 2, 4 eager; form 0 from a graph) on

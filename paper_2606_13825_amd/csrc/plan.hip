@@ -6,6 +6,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -1680,6 +1682,209 @@ cosmo_status cosmo_plan_psd_tune_ms(const cosmo_plan *plan, double *ms) {
   for (int a = 0; a < 2; ++a)
     for (int c = 0; c < 5; ++c) ms[5 * a + c] = plan->psd_tune_ms[a][c];
   return COSMO_OK;
+}
+
+// ---- schedule cache ----------------------------------------------------------------
+
+}  // extern "C"
+
+namespace {
+
+// FNV-1a (64 bit) over the bytes of plain values.
+struct Fnv {
+  uint64_t h = 1469598103934665603ull;
+  template <typename V> void add(const V &v) {
+    const unsigned char *b = reinterpret_cast<const unsigned char *>(&v);
+    for (size_t i = 0; i < sizeof(V); ++i) h = (h ^ b[i]) * 1099511628211ull;
+  }
+};
+
+std::string schedule_line(const char *key, const cosmo_schedule &sc) {
+  char buf[512];
+  std::snprintf(buf, sizeof buf,
+                "{\"key\": \"%s\", \"pcg_form\": %d, \"graph\": %d, \"eig_threads\": [%d, %d, %d, %d], "
+                "\"vjp_threads\": %d}",
+                key, sc.pcg_form, sc.graph, sc.eig_threads[0], sc.eig_threads[1], sc.eig_threads[2],
+                sc.eig_threads[3], sc.vjp_threads);
+  return buf;
+}
+
+// The key of a cache line, or "" when the line is not one this library wrote.
+std::string line_key(const std::string &ln) {
+  const std::string pre = "{\"key\": \"";
+  if (ln.compare(0, pre.size(), pre) != 0) return "";
+  const size_t e = ln.find('"', pre.size());
+  return e == std::string::npos ? "" : ln.substr(pre.size(), e - pre.size());
+}
+
+bool parse_schedule(const std::string &ln, cosmo_schedule &sc) {
+  const size_t at = ln.find("\", \"pcg_form\": ");
+  if (at == std::string::npos) return false;
+  cosmo_schedule t{};
+  const int n = std::sscanf(ln.c_str() + at,
+                            "\", \"pcg_form\": %d, \"graph\": %d, \"eig_threads\": [%d, %d, %d, %d], "
+                            "\"vjp_threads\": %d}",
+                            &t.pcg_form, &t.graph, &t.eig_threads[0], &t.eig_threads[1], &t.eig_threads[2],
+                            &t.eig_threads[3], &t.vjp_threads);
+  if (n != 7) return false;
+  sc = t;
+  return true;
+}
+
+bool key_ok(const char *key) {
+  if (!key || !*key) return false;
+  for (const char *c = key; *c; ++c)
+    if (*c == '"' || *c == '\\' || *c == '\n' || *c == '\r' || (unsigned char)*c < 0x20) return false;
+  return std::strlen(key) < 256;
+}
+
+}  // namespace
+
+extern "C" {
+
+cosmo_status cosmo_plan_signature(const cosmo_plan *plan, char *buf, int64_t len) {
+  cosmo_status s = check_plan(plan);
+  if (s != COSMO_OK) return s;
+  if (!buf || len < 1) FAIL(COSMO_EINVAL, "buf is NULL or len < 1");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  hipDeviceProp_t prop{};
+  HIPCHK(hipGetDeviceProperties(&prop, dev));
+  std::string arch = prop.gcnArchName;
+  arch = arch.substr(0, arch.find(':'));   // the target, without feature flags
+  Fnv f;
+  const cosmo_options &o = plan->opt;
+  f.add((int32_t)o.dtype);
+  f.add(o.K);
+  f.add(o.sigma);
+  f.add(o.cg_tol);
+  f.add(o.cg_max_iter);
+  f.add(o.eig_max_sweeps);
+  f.add(o.eig_tol);
+  f.add(o.eig_refine);
+  f.add(o.eig_warm_start);
+  f.add(plan->B);
+  for (int64_t v : plan->n_off) f.add(v);
+  for (int64_t v : plan->m_off) f.add(v);
+  f.add(plan->A_nnz);
+  f.add(plan->P_nnz);
+  f.add(plan->n_soc);
+  f.add(plan->n_psd);
+  for (int c = 0; c < 5; ++c) f.add(plan->psd_cls_begin[c]);
+  for (int c = 0; c < 4; ++c) f.add(plan->psd_cls_maxp[c]);
+  f.add(plan->sum_p);
+  f.add(plan->sum_p2);
+  f.add(plan->n_dense);
+  f.add(plan->dense_maxcols);
+  f.add(plan->dense_rows_tot);
+  f.add(plan->dense_cols_tot);
+  f.add(plan->dense_g32);
+  f.add(plan->diag_M);
+  char tail[160];
+  std::snprintf(tail, sizeof tail, "/cu%d/%s/K%d/B%d/n%lld/m%lld/%016llx", prop.multiProcessorCount,
+                o.dtype == COSMO_F32 ? "f32" : "f64", o.K, plan->B, (long long)plan->n_tot, (long long)plan->m_tot,
+                (unsigned long long)f.h);
+  const std::string key = arch + tail;
+  if ((int64_t)key.size() + 1 > len) FAIL(COSMO_EINVAL, "buf holds fewer than " + std::to_string(key.size() + 1) + " bytes");
+  std::memcpy(buf, key.c_str(), key.size() + 1);
+  return COSMO_OK;
+}
+
+cosmo_status cosmo_plan_get_schedule(const cosmo_plan *plan, cosmo_schedule *sched) {
+  cosmo_status s = check_plan(plan);
+  if (s != COSMO_OK) return s;
+  if (!sched) FAIL(COSMO_EINVAL, "sched is NULL");
+  sched->pcg_form = plan->pcg_form;
+  sched->graph = plan->graph ? 1 : 0;
+  for (int c = 0; c < 4; ++c) sched->eig_threads[c] = plan->eig_threads[c];
+  sched->vjp_threads = plan->vjp_threads;
+  return COSMO_OK;
+}
+
+cosmo_status cosmo_plan_set_schedule(cosmo_plan *plan, const cosmo_schedule *sched) {
+  cosmo_status s = check_plan(plan);
+  if (s != COSMO_OK) return s;
+  if (!sched) FAIL(COSMO_EINVAL, "sched is NULL");
+  if (sched->graph != 0 && sched->graph != 1) FAIL(COSMO_EINVAL, "graph must be 0 or 1");
+  // validate everything before changing anything
+  const int32_t keep_form = plan->pcg_form;
+  const bool keep_graph = plan->graph;
+  plan->graph = false;
+  s = cosmo_plan_set_pcg_form(plan, sched->pcg_form);
+  if (s == COSMO_OK) s = cosmo_plan_set_graph(plan, sched->graph);
+  if (s == COSMO_OK) s = cosmo_plan_set_psd_schedule(plan, sched->eig_threads, sched->vjp_threads);
+  if (s != COSMO_OK) {
+    const std::string msg = g_last_error;
+    plan->pcg_form = keep_form;
+    plan->drop_graphs();
+    plan->graph = keep_graph;
+    FAIL(s, msg);
+  }
+  return COSMO_OK;
+}
+
+cosmo_status cosmo_schedule_cache_load(const char *path, const char *key, cosmo_schedule *sched, int32_t *found) {
+  if (!path || !sched || !found) FAIL(COSMO_EINVAL, "path, sched and found are required");
+  if (!key_ok(key)) FAIL(COSMO_EINVAL, "key must be 1..255 printable characters without quotes or backslashes");
+  *found = 0;
+  std::ifstream in(path);
+  if (!in) return COSMO_OK;   // no cache yet: a miss
+  std::string ln;
+  cosmo_schedule sc{};
+  while (std::getline(in, ln))   // the last line with the key wins
+    if (line_key(ln) == key && parse_schedule(ln, sc)) {
+      *sched = sc;
+      *found = 1;
+    }
+  return COSMO_OK;
+}
+
+cosmo_status cosmo_schedule_cache_store(const char *path, const char *key, const cosmo_schedule *sched) {
+  if (!path || !sched) FAIL(COSMO_EINVAL, "path and sched are required");
+  if (!key_ok(key)) FAIL(COSMO_EINVAL, "key must be 1..255 printable characters without quotes or backslashes");
+  std::vector<std::string> keep;
+  {
+    std::ifstream in(path);
+    std::string ln;
+    while (in && std::getline(in, ln))
+      if (!ln.empty() && line_key(ln) != key) keep.push_back(ln);
+  }
+  keep.push_back(schedule_line(key, *sched));
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream out(tmp, std::ios::trunc);
+    if (!out) FAIL(COSMO_EINVAL, std::string("cannot write ") + tmp);
+    for (const auto &ln : keep) out << ln << '\n';
+    out.flush();
+    if (!out) FAIL(COSMO_EINVAL, std::string("cannot write ") + tmp);
+  }
+  if (std::rename(tmp.c_str(), path) != 0) FAIL(COSMO_EINVAL, std::string("cannot replace ") + path);
+  return COSMO_OK;
+}
+
+cosmo_status cosmo_plan_autotune_cached(cosmo_plan *plan, const void *rho, const void *alpha, void *ws, void *stream,
+                                        const char *path, int32_t *hit) {
+  cosmo_status s = check_plan(plan);
+  if (s != COSMO_OK) return s;
+  if (!path || !hit) FAIL(COSMO_EINVAL, "path and hit are required");
+  *hit = 0;
+  char key[256];
+  s = cosmo_plan_signature(plan, key, sizeof key);
+  if (s != COSMO_OK) return s;
+  cosmo_schedule sc{};
+  int32_t found = 0;
+  s = cosmo_schedule_cache_load(path, key, &sc, &found);
+  if (s != COSMO_OK) return s;
+  if (found && cosmo_plan_set_schedule(plan, &sc) == COSMO_OK) {
+    *hit = 1;
+    return COSMO_OK;
+  }
+  // a miss, or an entry this plan rejects: time the schedules and record them
+  s = cosmo_plan_autotune(plan, rho, alpha, ws, stream, nullptr);
+  if (s != COSMO_OK) return s;
+  s = cosmo_plan_get_schedule(plan, &sc);
+  if (s != COSMO_OK) return s;
+  return cosmo_schedule_cache_store(path, key, &sc);
 }
 
 // ---- profiling (not part of the hot path) -------------------------------------

@@ -306,3 +306,46 @@ def test_host_code_clean_under_asan_and_ubsan():
     assert r.returncode == 0, out[-4000:]
     assert "runtime error" not in out and "AddressSanitizer" not in out, out[-4000:]
     assert " passed" in r.stdout and " skipped" in r.stdout   # this test skipped itself there
+
+
+def _sched(L, form, graph, eig, vjp):
+    return L.CosmoSchedule(form, graph, (ctypes.c_int32 * 4)(*eig), vjp)
+
+
+def test_schedule_cache_round_trip(L, tmp_path):
+    """The schedule cache (host only): a missing file is a miss; stores add or
+    replace one key's line and keep the others; every line is a JSON object;
+    lines the library did not write are skipped; malformed keys and
+    unwritable paths are rejected."""
+    import json
+    lib = L.lib()
+    path = str(tmp_path / "sched.jsonl").encode()
+    out, found = L.CosmoSchedule(), ctypes.c_int32(7)
+    assert lib.cosmo_schedule_cache_load(path, b"gfx950/a", ctypes.byref(out), ctypes.byref(found)) == 0
+    assert found.value == 0
+    a = _sched(L, 2, 0, [128, 256, 1024, 1024], 512)
+    b = _sched(L, 0, 1, [64, 512, 512, 1024], 1024)
+    assert lib.cosmo_schedule_cache_store(path, b"gfx950/a", ctypes.byref(a)) == 0
+    assert lib.cosmo_schedule_cache_store(path, b"gfx950/b", ctypes.byref(b)) == 0
+    with open(path, "a") as f:
+        f.write("not a line of the cache\n{\"key\": \"gfx950/c\", \"pcg_form\": oops}\n")
+    for key, want in ((b"gfx950/a", a), (b"gfx950/b", b)):
+        assert lib.cosmo_schedule_cache_load(path, key, ctypes.byref(out), ctypes.byref(found)) == 0
+        assert found.value == 1 and out.as_dict() == want.as_dict()
+    assert lib.cosmo_schedule_cache_load(path, b"gfx950/c", ctypes.byref(out), ctypes.byref(found)) == 0
+    assert found.value == 0
+    a2 = _sched(L, 4, 0, [64, 256, 512, 1024], 1024)
+    assert lib.cosmo_schedule_cache_store(path, b"gfx950/a", ctypes.byref(a2)) == 0
+    assert lib.cosmo_schedule_cache_load(path, b"gfx950/a", ctypes.byref(out), ctypes.byref(found)) == 0
+    assert found.value == 1 and out.as_dict() == a2.as_dict()
+    lines = [ln for ln in open(path).read().splitlines() if ln.startswith("{\"key\": \"gfx950/")]
+    objs = [json.loads(ln) for ln in lines if "oops" not in ln]
+    assert [o["key"] for o in objs] == ["gfx950/b", "gfx950/a"]
+    assert objs[1] == {"key": "gfx950/a", "pcg_form": 4, "graph": 0, "eig_threads": [64, 256, 512, 1024],
+                       "vjp_threads": 1024}
+    for bad in (b"", b"has\"quote", b"back\\slash", b"new\nline", b"x" * 256):
+        assert lib.cosmo_schedule_cache_store(path, bad, ctypes.byref(a)) == L.COSMO_EINVAL
+        assert lib.cosmo_schedule_cache_load(path, bad, ctypes.byref(out), ctypes.byref(found)) == L.COSMO_EINVAL
+    nodir = str(tmp_path / "no" / "such" / "dir" / "c.jsonl").encode()
+    assert lib.cosmo_schedule_cache_store(nodir, b"k", ctypes.byref(a)) == L.COSMO_EINVAL
+    assert lib.cosmo_schedule_cache_load(None, b"k", ctypes.byref(out), ctypes.byref(found)) == L.COSMO_EINVAL

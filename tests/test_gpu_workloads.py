@@ -257,3 +257,43 @@ def test_autotuned_psd_shapes():
         assert eig[c] == (EIG_ALT[c] if faster_alt else EIG_DEFAULT[c])
     assert tm["default"][4] > 0 and tm["alt"][4] > 0
     assert vjp == (512 if tm["alt"][4] < tm["default"][4] else 1024)
+
+
+def test_schedule_cache(tmp_path):
+    """cosmo_plan_autotune_cached: the first plan misses, times the schedules
+    and records them under its signature; a second plan of the same problem
+    hits, takes the recorded schedule without timing, and runs bitwise like
+    the first; another problem has another signature; a rejected schedule
+    leaves the plan's schedule as it was."""
+    ensure_lib()
+    from paper_2606_13825_amd import CosmoBatch, CosmoError
+    insts = _maxcut_classes((20, 50, 100), 67, np.float32)
+    K = 4
+    rhos, alphas = _hyper(insts, K, 68)
+    rho = torch.from_numpy(np.concatenate(rhos, axis=1)).to(DEV)
+    alpha = torch.from_numpy(np.stack(alphas, axis=1)).to(DEV)
+    path = str(tmp_path / "schedules.jsonl")
+    runs = []
+    for expect_hit in (False, True):
+        batch = CosmoBatch(insts, K=K, dtype=torch.float32, device=DEV)
+        assert batch.autotune_cached(rho, alpha, path) == expect_hit
+        sig, sched = batch.signature(), batch.schedule()
+        say(f"  hit={expect_hit} signature {sig} schedule {sched}")
+        assert sig.startswith("gfx")
+        fw = batch.forward(rho, alpha)
+        _, g = batch.residual_loss(fw.x, fw.s, fw.y)
+        bw = batch.backward(rho, alpha, fw.tape, *g)
+        torch.cuda.synchronize()
+        runs.append((sig, sched, [t.clone() for t in (fw.x, fw.s, fw.y, bw.grho, bw.galpha)]))
+        if expect_hit:
+            with pytest.raises(CosmoError):
+                batch.set_schedule(sched["pcg_form"], sched["graph"], [64, 256, 512, 512], 1024)
+            assert batch.schedule() == sched
+        batch.close()
+    assert runs[0][0] == runs[1][0] and runs[0][1] == runs[1][1]
+    for a, b in zip(runs[0][2], runs[1][2]):
+        assert torch.equal(a, b)
+    other = CosmoBatch(insts[:2], K=K, dtype=torch.float32, device=DEV)
+    assert other.signature() != runs[0][0]
+    other.close()
+    assert len(open(path).read().splitlines()) == 1

@@ -232,3 +232,27 @@ def test_scp_expected_cost_recursion_matches_the_oracle_rollout():
     a = expected_cost(sc, A, B, mu, v, K)
     b = oracle.scp.expected_cost(sc, A, B, mu, v, K)
     assert abs(a - b) <= 1e-12 * abs(b)
+
+
+def test_lovasz_reduced_matrix_has_three_jacobi_eigenvalues():
+    """On a Lovasz theta SDP, A has one trace row plus rows with a single
+    entry (edge equalities, the PSD block's -I), and rectification makes the
+    penalty uniform within each cone block.  So diag(M)^-1/2 M diag(M)^-1/2
+    is the identity off the svec diagonal positions, and on the p diagonal
+    positions a multiple of the identity plus a rank-one term along the
+    trace row: three distinct eigenvalues (one small of multiplicity p - 1,
+    1, one large), so Jacobi-PCG ends in at most three iterations in exact
+    arithmetic, while the condition number is large."""
+    from oracle.cones import rectify
+    from oracle.cosmo import reduced_matrix
+    inst = synth.c3_batch(B=1, n_lo=24, n_hi=24, seed=3)[0]
+    rho, _ = synth.perturbed_hyper(inst, 1, np.random.default_rng(0), spread=0.5)
+    M = reduced_matrix(inst, rectify(rho[0], inst.cones), 1e-6).toarray()
+    dm = 1.0 / np.sqrt(np.diag(M))
+    ev = np.linalg.eigvalsh(dm[:, None] * M * dm[None, :])
+    groups = np.split(ev, np.where(np.diff(ev) > 1e-8 * ev[-1])[0] + 1)
+    assert len(groups) == 3
+    p = inst.meta["order"]
+    # the diagonal positions: p - 1 directions orthogonal to the trace row, and the trace direction
+    assert np.isclose(groups[1][0], 1.0) and groups[0].size == p - 1 and groups[2].size == 1
+    assert ev[-1] / ev[0] > 1e3   # the trace row: ill-conditioned although only three eigenvalues
