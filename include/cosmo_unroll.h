@@ -464,8 +464,10 @@ cosmo_status cosmo_plan_get_graph(const cosmo_plan *plan, int32_t *enabled);
  * cosmo_plan_set_psd_schedule): each order class's eigensolve is timed alone
  * over forward runs under the class defaults and under the alternatives, and
  * the DK VJP on the last step's eigenpairs under both thread counts; each
- * keeps the faster.  A setup call, not for the hot path: it allocates scratch
- * buffers and waits for the stream.  ms (host, nullable) [4] receives the CG
+ * keeps the faster (an error in that phase leaves the PSD shapes the plan
+ * had).  A setup call, not for the hot path: it allocates scratch buffers
+ * and waits for the stream, and it discards the plan's profiling records
+ * (cosmo_plan_profile_read counts from zero afterwards).  ms (host, nullable) [4] receives the CG
  * timings in that order (-1 for schedules not run: problems whose reduced
  * matrix is diagonal have no CG, and only the eager and graph runs of form
  * 0 are timed for them); cosmo_plan_psd_tune_ms returns the PSD timings. */

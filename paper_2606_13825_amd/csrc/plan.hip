@@ -1662,9 +1662,16 @@ cosmo_status cosmo_plan_autotune(cosmo_plan *plan, const void *rho, const void *
   for (auto &row : plan->psd_tune_ms)
     for (double &t : row) t = -1.0;
   if (s == COSMO_OK && plan->n_psd > 0) {
+    int32_t keep_eig[4];
+    for (int c = 0; c < 4; ++c) keep_eig[c] = plan->eig_threads[c];
+    const int32_t keep_vjp = plan->vjp_threads;
     plan->drop_graphs();
     s = plan->opt.dtype == COSMO_F32 ? tune_psd<float>(plan, rho, alpha, ws, st, xK, sK, yK, e0, e1)
                                      : tune_psd<double>(plan, rho, alpha, ws, st, xK, sK, yK, e0, e1);
+    if (s != COSMO_OK) {   // a failed PSD phase leaves the shapes the plan had
+      for (int c = 0; c < 4; ++c) plan->eig_threads[c] = keep_eig[c];
+      plan->vjp_threads = keep_vjp;
+    }
   }
   (void)hipStreamSynchronize(st);   // nothing in flight reads the scratch outputs when they are freed
   (void)hipEventDestroy(e0);
